@@ -1,0 +1,255 @@
+"""Pins of the CPU oracle against facts fixed by the paper and by mathematics.
+
+Each test checks the oracle against something other than itself: the problem
+definition evaluated by brute force in numpy on tiny inputs, the worked example
+of Sec. III, the BITS counting identity (Sec. II) via ``numpy.searchsorted``,
+the closed-form expected pair count for uniformly placed boxes, a second exact
+algorithm (sort-based matching, Sec. III-D), structural invariants, and the
+O(min{n, (k+1) log n}) query cost of Algorithm 3 (Sec. IV).
+"""
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_1309_3458_amd import workloads as W
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def definition_pairs(s_lo, s_hi, u_lo, u_hi):
+    """Problem statement of Sec. III with closed segments, by exhaustion."""
+    d = s_lo.shape[0]
+    ok = np.ones((u_lo.shape[1], s_lo.shape[1]), dtype=bool)
+    for k in range(d):
+        ok &= (s_lo[k][None, :] <= u_hi[k][:, None]) & (u_lo[k][:, None] <= s_hi[k][None, :])
+    j, i = np.nonzero(ok)
+    return (j.astype(np.uint64) << np.uint64(32)) | i.astype(np.uint64)
+
+
+@pytest.mark.parametrize("d", [1, 2, 3])
+@pytest.mark.parametrize("seed", range(6))
+def test_itm_equals_definition_adversarial(d, seed):
+    rng = np.random.default_rng(1000 + seed)
+    n = int(rng.integers(0, 300))
+    m = int(rng.integers(0, 300))
+    inst = W.tiny_adversarial(seed, n, m, d)
+    want = definition_pairs(inst.s_lo, inst.s_hi, inst.u_lo, inst.u_hi)
+    got = oracle.itm(inst.s_lo, inst.s_hi, inst.u_lo, inst.u_hi)
+    np.testing.assert_array_equal(got, want)
+    got_par = oracle.itm(inst.s_lo, inst.s_hi, inst.u_lo, inst.u_hi, threads=4)
+    np.testing.assert_array_equal(got_par, want)
+    np.testing.assert_array_equal(oracle.brute(inst.s_lo, inst.s_hi, inst.u_lo, inst.u_hi), want)
+
+
+@pytest.mark.parametrize("d", [1, 2])
+def test_itm_equals_definition_variable_lengths(d):
+    inst = W.random_lengths(7 + d, 1500, 1200, d)
+    want = definition_pairs(inst.s_lo, inst.s_hi, inst.u_lo, inst.u_hi)
+    np.testing.assert_array_equal(oracle.itm(inst.s_lo, inst.s_hi, inst.u_lo, inst.u_hi), want)
+
+
+def test_closed_semantics_pin():
+    """Touching segments: S_a=[5,7], S_b=[5,9], q=[0,5].
+
+    Closed segments (the text's [low, high]) meet at 5, so both pairs exist.
+    Algorithm 1 as printed is strict and reports neither; with the strict
+    right-descent condition of Algorithm 3 S_b (right child of S_a in the
+    (lower, upper) order) would not even be visited.
+    """
+    s_lo = np.array([[5, 5]], np.float32)
+    s_hi = np.array([[7, 9]], np.float32)
+    u_lo = np.array([[0]], np.float32)
+    u_hi = np.array([[5]], np.float32)
+    got = oracle.itm(s_lo, s_hi, u_lo, u_hi)
+    assert got.tolist() == [0, 1]
+    assert oracle.itm(s_lo, s_hi, u_lo, u_hi, strict=True).tolist() == []
+    assert oracle.brute(s_lo, s_hi, u_lo, u_hi, strict=True).tolist() == []
+
+
+def test_point_and_signed_zero():
+    s_lo = np.array([[-0.0, 0.0, 1.0]], np.float32)
+    s_hi = np.array([[-0.0, 0.0, 1.0]], np.float32)
+    u_lo = np.array([[0.0, -0.0, 0.5]], np.float32)
+    u_hi = np.array([[0.0, -0.0, 0.5]], np.float32)
+    got = oracle.itm(s_lo, s_hi, u_lo, u_hi)
+    # +0.0 == -0.0: both zero-points meet both zero-queries; 0.5 meets none
+    assert got.tolist() == [0, 1, (1 << 32) | 0, (1 << 32) | 1]
+
+
+def load_fig1():
+    S, U, M = {}, {}, []
+    with open(os.path.join(GOLDEN, "fig1_example.txt")) as f:
+        for line in f:
+            line = line.strip()
+            if not line or line.startswith("#"):
+                continue
+            t = line.split()
+            if t[0] in "SU":
+                (S if t[0] == "S" else U)[int(t[1])] = [float(x) for x in t[2:]]
+            elif t[0] == "M":
+                M.append([int(x) for x in t[1:]])
+
+    def arr(D):
+        rows = [D[i] for i in sorted(D)]
+        lo = np.array([[r[0] for r in rows], [r[2] for r in rows]], np.float32)
+        hi = np.array([[r[1] for r in rows], [r[3] for r in rows]], np.float32)
+        return lo, hi
+
+    return arr(S), arr(U), np.array(M)
+
+
+def test_fig1_worked_example():
+    (s_lo, s_hi), (u_lo, u_hi), M = load_fig1()
+    keys = oracle.itm(s_lo, s_hi, u_lo, u_hi)
+    got = np.zeros_like(M)
+    for k in keys.tolist():
+        got[k & 0xFFFFFFFF, k >> 32] = 1
+    np.testing.assert_array_equal(got, M)
+    # S1 and U2 overlap along dimension 1 only (Sec. III-A)
+    assert oracle.itm(s_lo[:1, :1], s_hi[:1, :1], u_lo[:1, 1:], u_hi[:1, 1:]).size == 1
+    assert oracle.itm(s_lo[1:, :1], s_hi[1:, :1], u_lo[1:, 1:], u_hi[1:, 1:]).size == 0
+
+
+def test_bits_identity_1d():
+    """Sec. II (BITS): the number of intervals meeting q is |B| minus those
+    ending before q.low minus those starting after q.high; with sorted
+    starts/ends that is two binary searches (closed segments)."""
+    inst = W.small_1d(0)
+    keys = oracle.itm(inst.s_lo, inst.s_hi, inst.u_lo, inst.u_hi)
+    cnt = oracle.counts_per_update(keys, inst.m)
+    starts = np.sort(inst.s_lo[0])
+    ends = np.sort(inst.s_hi[0])
+    c = (np.searchsorted(starts, inst.u_hi[0], side="right")
+         - np.searchsorted(ends, inst.u_lo[0], side="left"))
+    np.testing.assert_array_equal(cnt, c)
+
+
+def test_bits_upper_bound_2d():
+    inst = W.uniform_instance(11, 20000, 20000, 2, 2000.0)
+    keys = oracle.itm(inst.s_lo, inst.s_hi, inst.u_lo, inst.u_hi, threads=4)
+    cnt = oracle.counts_per_update(keys, inst.m)
+    for k in range(2):
+        c = (np.searchsorted(np.sort(inst.s_lo[k]), inst.u_hi[k], side="right")
+             - np.searchsorted(np.sort(inst.s_hi[k]), inst.u_lo[k], side="left"))
+        assert (cnt <= c).all()
+    # and the 1-D instance per dimension reproduces c exactly
+    k1 = oracle.itm(inst.s_lo[:1], inst.s_hi[:1], inst.u_lo[:1], inst.u_hi[:1], threads=4)
+    c0 = (np.searchsorted(np.sort(inst.s_lo[0]), inst.u_hi[0], side="right")
+          - np.searchsorted(np.sort(inst.s_hi[0]), inst.u_lo[0], side="left"))
+    np.testing.assert_array_equal(oracle.counts_per_update(k1, inst.m), c0)
+
+
+def _sd_check(K, EK, nsd=6.0):
+    assert abs(K - EK) <= nsd * np.sqrt(EK), (K, EK)
+
+
+def test_closed_form_count_small_1d():
+    inst = W.small_1d(0)
+    EK = oracle.expected_pairs_uniform(inst.n, inst.m, [100.0], W.L_SPACE)
+    assert abs(EK - 4999.75) < 1e-9
+    _sd_check(len(oracle.itm(inst.s_lo, inst.s_hi, inst.u_lo, inst.u_hi)), EK)
+
+
+def test_closed_form_count_many_seeds():
+    Ks = []
+    for seed in range(100, 120):
+        inst = W.small_1d(seed)
+        Ks.append(len(oracle.itm(inst.s_lo, inst.s_hi, inst.u_lo, inst.u_hi)))
+    EK = oracle.expected_pairs_uniform(5000, 5000, [100.0], W.L_SPACE)
+    # mean of 20 draws: sd of the mean ~ sqrt(EK / 20)
+    assert abs(np.mean(Ks) - EK) <= 5.0 * np.sqrt(EK / 20.0)
+    for K in Ks:
+        _sd_check(K, EK)
+
+
+def test_closed_form_count_2d():
+    N = 100_000
+    side = W.side_for_alpha(1.0, N, 2)
+    inst = W.uniform_instance(5, N // 2, N // 2, 2, side)
+    EK = oracle.expected_pairs_uniform(inst.n, inst.m, [side, side], W.L_SPACE)
+    _sd_check(len(oracle.itm(inst.s_lo, inst.s_hi, inst.u_lo, inst.u_hi, threads=4)), EK)
+
+
+def test_closed_form_count_3d():
+    N = 60_000
+    side = W.side_for_alpha(10.0, N, 3)
+    inst = W.uniform_instance(6, N // 2, N // 2, 3, side)
+    EK = oracle.expected_pairs_uniform(inst.n, inst.m, [side] * 3, W.L_SPACE)
+    _sd_check(len(oracle.itm(inst.s_lo, inst.s_hi, inst.u_lo, inst.u_hi, threads=4)), EK)
+
+
+@pytest.mark.parametrize("seed,length", [(21, 2.0), (22, 200.0), (23, 20000.0)])
+def test_sort_based_matching_agrees(seed, length):
+    inst = W.uniform_instance(seed, 30000, 25000, 1, length)
+    a = oracle.itm(inst.s_lo, inst.s_hi, inst.u_lo, inst.u_hi, threads=4)
+    b = oracle.sbm_1d(inst.s_lo, inst.s_hi, inst.u_lo, inst.u_hi)
+    np.testing.assert_array_equal(a, b)
+
+
+def test_invariants_and_sampled_pairs():
+    inst = W.uniform_instance(31, 40000, 40000, 2, 4000.0)
+    keys = oracle.itm(inst.s_lo, inst.s_hi, inst.u_lo, inst.u_hi, threads=4)
+    assert (np.diff(keys.astype(np.int64)) > 0).all()   # strictly increasing, no dups
+    assert oracle.counts_per_update(keys, inst.m).sum() == len(keys)
+    rng = np.random.default_rng(0)
+    pick = keys[rng.integers(0, len(keys), 500)]
+    j = (pick >> np.uint64(32)).astype(np.int64)
+    i = (pick & np.uint64(0xFFFFFFFF)).astype(np.int64)
+    for k in range(2):
+        assert ((inst.s_lo[k, i] <= inst.u_hi[k, j]) & (inst.u_lo[k, j] <= inst.s_hi[k, i])).all()
+    # random non-emitted pairs fail the predicate in some dimension
+    jj = rng.integers(0, inst.m, 5000)
+    ii = rng.integers(0, inst.n, 5000)
+    cand = (jj.astype(np.uint64) << np.uint64(32)) | ii.astype(np.uint64)
+    absent = ~np.isin(cand, keys)
+    ok = np.ones(absent.sum(), bool)
+    for k in range(2):
+        ok &= (inst.s_lo[k, ii[absent]] <= inst.u_hi[k, jj[absent]]) & \
+              (inst.u_lo[k, jj[absent]] <= inst.s_hi[k, ii[absent]])
+    assert not ok.any()
+
+
+def test_result_independent_of_order():
+    """Sec. IV leaves the order among equal intervals open: permuting the
+    subscriptions (relabelling ids back) and the updates changes nothing."""
+    inst = W.tiny_adversarial(3, 400, 300, 2)
+    base = oracle.itm(inst.s_lo, inst.s_hi, inst.u_lo, inst.u_hi)
+    rng = np.random.default_rng(5)
+    ps = rng.permutation(inst.n)
+    pu = rng.permutation(inst.m)
+    got = oracle.itm(inst.s_lo[:, ps], inst.s_hi[:, ps], inst.u_lo[:, pu], inst.u_hi[:, pu])
+    j = pu[(got >> np.uint64(32)).astype(np.int64)].astype(np.uint64)
+    i = ps[(got & np.uint64(0xFFFFFFFF)).astype(np.int64)].astype(np.uint64)
+    np.testing.assert_array_equal(np.sort((j << np.uint64(32)) | i), base)
+
+
+def test_query_cost_bound():
+    """Algorithm 3 enters at most min(n, 2 (k+1) H + 1) nodes for a query with
+    k hits in a tree of height H: a node that is not pruned is an ancestor of
+    a hit or straddles the boundary lower <= q.upper < lower (at most H such
+    nodes); every entered node is the root or a child of a non-pruned one."""
+    inst = W.random_lengths(41, 1 << 14, 3000, 1, L=1e5, max_len=300.0)
+    visits, hits, H = oracle.itm_1d_visits(inst.s_lo, inst.s_hi, inst.u_lo, inst.u_hi)
+    assert H == 15                       # perfectly balanced: ceil(log2(n + 1))
+    bound = np.minimum(inst.n, 2 * (hits.astype(np.int64) + 1) * H + 1)
+    assert (visits.astype(np.int64) <= bound).all()
+    assert (visits < inst.n // 4).all()  # pruning really happens
+
+
+def test_empty_sets():
+    z = np.zeros((2, 0), np.float32)
+    one = np.ones((2, 3), np.float32)
+    assert oracle.itm(z, z, one, one).size == 0
+    assert oracle.itm(one, one, z, z).size == 0
+
+
+def test_invalid_input_rejected():
+    s = np.array([[1.0, 2.0]], np.float32)
+    bad_hi = np.array([[0.5, 3.0]], np.float32)   # lo > hi
+    with pytest.raises(oracle.OracleError):
+        oracle.itm(s, bad_hi, s, s)
+    nan = np.array([[np.nan, 3.0]], np.float32)
+    with pytest.raises(oracle.OracleError):
+        oracle.itm(s, s, nan, s)
