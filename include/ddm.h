@@ -1,0 +1,204 @@
+/*
+ * ddm.h -- C ABI of libddm, an MI355X (gfx950) implementation of Interval
+ * Tree Matching for Data Distribution Management.
+ *
+ * Method: Marzolla, D'Angelo, Mandrioli, "A Parallel Data Distribution
+ * Management Algorithm", DS-RT 2013.  Given subscription extents S and
+ * update extents U (d-dimensional boxes), the library returns the exact set
+ * of intersecting (update, subscription) pairs (Sec. III, problem
+ * statement), computed the way the paper's ITM does it: one interval tree per
+ * dimension built over S (Sec. IV), every update queried against it in
+ * parallel (Algorithm 3 / Algorithm 4, "Parallelizing ITM"), and the
+ * per-dimension overlaps combined into d-rectangle overlaps (Sec. III-A).
+ *
+ * Conventions for every entry point
+ * ---------------------------------
+ *  - Coordinates are float32, dimension-major (structure of arrays):
+ *    lo[k * count + i], hi[k * count + i] for dimension k < d, element i.
+ *  - Segments are CLOSED: [lo, hi] and [lo', hi'] meet iff lo <= hi' and
+ *    lo' <= hi (the text's [low, high] segments; Algorithm 1 prints the strict
+ *    form).  Two boxes meet iff they meet in every dimension.  -0.0 == +0.0.
+ *  - Ids are the 0-based array index (the paper counts from 1).
+ *  - A result pair is the 64-bit key (update_id << 32) | subscription_id.
+ *    Results are returned sorted ascending, i.e. (update, subscription)
+ *    lexicographic: the nonzeros of the paper's n x m intersection matrix M,
+ *    column by column.
+ *  - "device pointer" means memory allocated on the GPU the stream belongs to
+ *    (for instance a torch tensor's data_ptr()).  "host pointer" means
+ *    ordinary CPU memory.
+ *  - `stream` is a hipStream_t passed as void* (NULL = the default stream).
+ *    Work is enqueued on it in stream order; an entry point returns before
+ *    the enqueued work finishes unless stated otherwise.
+ *  - Invalid input (NaN or +-inf anywhere, or lo > hi) makes the call that
+ *    detects it return DDM_E_INVALID_INPUT.  Points (lo == hi) are valid.
+ *  - No C++ exception crosses this boundary.  On error, a thread-local detail
+ *    message is available from ddm_last_error_detail().
+ *  - Ownership: the caller owns all inputs and outputs; the library owns the
+ *    trees and predictors it creates and frees them in the matching *_free.
+ */
+#ifndef DDM_H_
+#define DDM_H_
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define DDM_MAX_D 4
+
+typedef enum {
+  DDM_OK = 0,
+  DDM_E_INVALID_ARG = -1,   /* bad pointer, size, dimension or option      */
+  DDM_E_INVALID_INPUT = -2, /* NaN/inf coordinate or lo > hi                */
+  DDM_E_CAPACITY = -3,      /* result does not fit the caller's buffer      */
+  DDM_E_NOMEM = -4,         /* device or pinned host allocation failed      */
+  DDM_E_DEVICE = -5         /* HIP runtime error                            */
+} ddm_status;
+
+typedef struct ddm_tree ddm_tree;
+
+/* ddm_build -- interval trees over the subscription set (Sec. IV,
+ * Interval-Tree-Create in Algorithm 4; Sec. III-A for one tree per dimension).
+ *
+ *  sub_lo, sub_hi  device pointers, d*n float32 each, dimension-major.
+ *  n               number of subscriptions; 0 is valid (every match is empty).
+ *  d               dimensions, 1..DDM_MAX_D.
+ *  stream          HIP stream the build is enqueued on.
+ *  out_tree        host pointer; receives an opaque handle.
+ *
+ * The trees are flat, implicit and balanced: subscriptions sorted by lower
+ * bound (a device radix sort; equal lower bounds keep id order) form the
+ * in-order sequence of a complete binary tree, and each position stores the
+ * maximum upper bound of its subtree (the paper's maxupper; minlower is the
+ * leftmost lower bound of the subtree and needs no storage).  The tree owns
+ * its device memory.  The inputs may be freed or overwritten once the stream
+ * has passed this call.  Validation of the coordinates runs on the device;
+ * its outcome is reported by the first ddm_match on the tree (or by
+ * ddm_tree_check), not by ddm_build.
+ */
+ddm_status ddm_build(const float* sub_lo, const float* sub_hi, uint32_t n, uint32_t d,
+                     void* stream, ddm_tree** out_tree);
+
+/* ddm_match -- all (update, subscription) pairs that intersect
+ * (Algorithm 4: one Interval-Query, Algorithm 3, per update, run in
+ * parallel; Sec. III-A: overlap in every dimension).
+ *
+ *  t              tree from ddm_build (read only; may be matched concurrently
+ *                 on several streams).
+ *  upd_lo/upd_hi  device pointers, d*m float32 each, dimension-major, d = the
+ *                 tree's d.
+ *  m              number of updates; 0 is valid.
+ *  out_pairs      device pointer to `capacity` uint64 slots; may be NULL when
+ *                 capacity is 0.
+ *  out_count      host pointer; ALWAYS receives the exact pair count K when
+ *                 the call returns DDM_OK or DDM_E_CAPACITY.
+ *
+ * Synchronizes the stream once (to read K).  If K > capacity the call returns
+ * DDM_E_CAPACITY and writes no pair; call again with capacity >= K.  On
+ * DDM_OK the first K slots receive the sorted keys when the stream reaches
+ * the end of the enqueued work.
+ */
+ddm_status ddm_match(const ddm_tree* t, const float* upd_lo, const float* upd_hi, uint32_t m,
+                     uint64_t* out_pairs, uint64_t capacity, uint64_t* out_count,
+                     void* stream);
+
+/* Traversal kernels selectable through ddm_match_ex (results never differ):
+ *  DDM_TRAVERSE_LANE  one GPU lane per update, stackless form of Algorithm 3
+ *                     on the implicit tree.
+ *  DDM_TRAVERSE_TILE  one wavefront per 64 updates sorted by lower bound:
+ *                     Algorithm 3 runs once on the tile's enclosing interval,
+ *                     candidates are compacted into LDS with wavefront
+ *                     ballots and tested against all 64 updates.
+ *  DDM_TRAVERSE_AUTO  library default (currently TILE).                     */
+#define DDM_TRAVERSE_AUTO 0u
+#define DDM_TRAVERSE_LANE 1u
+#define DDM_TRAVERSE_TILE 2u
+
+typedef struct {
+  uint32_t traversal;   /* DDM_TRAVERSE_*                                     */
+  uint32_t block;       /* threads per workgroup of the traversal kernels:
+                           64, 128, 256, 512 or 1024; 0 = default (256)       */
+  uint32_t reserved[6]; /* must be zero                                       */
+} ddm_match_opts;
+
+/* ddm_match with explicit kernel options (opts may be NULL = defaults). */
+ddm_status ddm_match_ex(const ddm_tree* t, const float* upd_lo, const float* upd_hi,
+                        uint32_t m, uint64_t* out_pairs, uint64_t capacity,
+                        uint64_t* out_count, void* stream, const ddm_match_opts* opts);
+
+/* Two-step form of ddm_match_ex for callers that size the output from K.
+ *
+ * ddm_match_begin runs everything up to the pair count (validation, probe
+ * dimension, counts per update, offsets), synchronizes the stream once, and
+ * returns K through out_count (host pointer) plus a pending handle (host
+ * pointer receives it; NULL when m == 0 or n == 0, and ddm_match_finish
+ * accepts NULL).  A non-NULL handle must be passed to ddm_match_finish or
+ * ddm_match_abort exactly once.  It keeps the device state of the count; the
+ * update coordinates must stay valid until ddm_match_finish.
+ *
+ * ddm_match_finish writes the K sorted pairs into out_pairs (device, capacity
+ * slots) on the stream given to ddm_match_begin, and releases the handle in
+ * every case (also on error).  Returns DDM_E_CAPACITY, writing nothing, if
+ * capacity < K.  ddm_match_abort releases a handle without writing.       */
+typedef struct ddm_pending ddm_pending;
+ddm_status ddm_match_begin(const ddm_tree* t, const float* upd_lo, const float* upd_hi,
+                           uint32_t m, uint64_t* out_count, void* stream,
+                           const ddm_match_opts* opts, ddm_pending** out_pending);
+ddm_status ddm_match_finish(ddm_pending* pending, uint64_t* out_pairs, uint64_t capacity);
+void ddm_match_abort(ddm_pending* pending);
+
+/* ddm_count -- exact number of subscriptions each update meets (the length
+ * of column j of M), without producing the pairs.
+ *  counts     device pointer to m uint32 (caller owned).
+ *  out_total  host pointer, receives K = sum of counts (may be NULL).
+ * Synchronizes the stream once.                                             */
+ddm_status ddm_count(const ddm_tree* t, const float* upd_lo, const float* upd_hi, uint32_t m,
+                     uint32_t* counts, uint64_t* out_total, void* stream,
+                     const ddm_match_opts* opts);
+
+/* ddm_tree_check -- waits for the build to finish and reports whether the
+ * subscription coordinates were valid (DDM_OK or DDM_E_INVALID_INPUT).      */
+ddm_status ddm_tree_check(const ddm_tree* t);
+
+/* ddm_tree_info -- host pointers receive n, d and the tree height H (the
+ * implicit tree has 2^H - 1 positions, H = 0 for n = 0). Any may be NULL.   */
+ddm_status ddm_tree_info(const ddm_tree* t, uint32_t* n, uint32_t* d, uint32_t* height);
+
+/* ddm_tree_export -- copies dimension k's tree to host memory (synchronous),
+ * for inspection and tests.  Host pointers, each may be NULL:
+ *  lo, hi   n floats: the in-order (sorted by lower bound) segments;
+ *  ids      n uint32: subscription id at each in-order position;
+ *  maxhi    2^H - 1 floats: maxupper of the subtree rooted at each position
+ *           (positions beyond n belong to no subscription).                 */
+ddm_status ddm_tree_export(const ddm_tree* t, uint32_t k, float* lo, float* hi,
+                           uint32_t* ids, float* maxhi);
+
+/* ddm_tree_free -- releases the tree's device memory, ordered on the stream
+ * the tree was built on.  The caller must make sure that work on other
+ * streams that reads the tree has finished.  NULL is ignored.               */
+void ddm_tree_free(ddm_tree* t);
+
+/* Static message for a status code.                                          */
+const char* ddm_strerror(ddm_status s);
+
+/* Thread-local detail of the last error returned on this thread ("" if none).*/
+const char* ddm_last_error_detail(void);
+
+/* Kernel timing with HIP events recorded on the launching stream.
+ * ddm_prof_enable(1) starts recording every kernel launch of this thread;
+ * ddm_prof_read() waits for the recorded events and writes a JSON object
+ * {"kernel": [total_ms, launches], ...} into buf (host, size bytes), then
+ * clears the records.  Returns the number of bytes needed (excluding NUL). */
+void ddm_prof_enable(int on);
+uint64_t ddm_prof_read(char* buf, uint64_t size);
+
+/* Restricts recording to launches of the kernel `name` (a key of the JSON
+ * report, host string); NULL or "" records every kernel again.              */
+void ddm_prof_focus(const char* name);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* DDM_H_ */

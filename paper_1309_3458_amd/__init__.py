@@ -1,0 +1,187 @@
+"""Interval Tree Matching for DDM on MI355X (gfx950).
+
+Python face of libddm.  Tensors are torch CUDA tensors used as device memory;
+all work runs in the library's HIP kernels on the current torch stream.
+
+    tree = build(s_lo, s_hi)          # float32 [d, n] each, on the GPU
+    keys = match(tree, u_lo, u_hi)    # int64 [K]: (update << 32) | subscription
+"""
+from __future__ import annotations
+
+import ctypes
+import json
+
+from ._native import (DDMError, DDM_E_CAPACITY, TRAVERSE, check, header_functions, lib,
+                      opts as _opts)
+
+__all__ = ["build", "match", "count", "Tree", "DDMError", "prof_enable", "prof_read",
+           "TRAVERSE", "header_functions"]
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _stream_handle(stream):
+    torch = _torch()
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+def _coords(lo, hi, what):
+    torch = _torch()
+    if lo.dtype != torch.float32 or hi.dtype != torch.float32:
+        raise TypeError(f"{what}: coordinates must be float32")
+    if lo.dim() != 2 or lo.shape != hi.shape:
+        raise ValueError(f"{what}: expected lo, hi of equal shape [d, count]")
+    if not lo.is_cuda or not hi.is_cuda:
+        raise ValueError(f"{what}: tensors must be on the GPU")
+    return lo.contiguous(), hi.contiguous()
+
+
+class Tree:
+    """Handle of per-dimension interval trees built on the device."""
+
+    def __init__(self, handle: ctypes.c_void_p, n: int, d: int, keep):
+        self._h = handle
+        self.n = n
+        self.d = d
+        self._keep = keep  # inputs stay alive until the build has run
+
+    @property
+    def handle(self):
+        if self._h is None:
+            raise RuntimeError("tree already freed")
+        return self._h
+
+    def check(self):
+        check(lib().ddm_tree_check(self.handle), "ddm_tree_check")
+
+    def info(self):
+        n, d, h = ctypes.c_uint32(), ctypes.c_uint32(), ctypes.c_uint32()
+        check(lib().ddm_tree_info(self.handle, ctypes.byref(n), ctypes.byref(d),
+                                  ctypes.byref(h)), "ddm_tree_info")
+        return n.value, d.value, h.value
+
+    def export(self, k: int):
+        """(lo, hi, ids, maxhi) numpy arrays of dimension k's tree (in order)."""
+        import numpy as np
+        n, d, H = self.info()
+        lo = np.zeros(n, np.float32)
+        hi = np.zeros(n, np.float32)
+        ids = np.zeros(n, np.uint32)
+        mx = np.zeros((1 << H) - 1 if H else 0, np.float32)
+        check(lib().ddm_tree_export(self.handle, k, lo.ctypes.data, hi.ctypes.data,
+                                    ids.ctypes.data, mx.ctypes.data), "ddm_tree_export")
+        return lo, hi, ids, mx
+
+    def free(self):
+        if self._h is not None:
+            lib().ddm_tree_free(self._h)
+            self._h = None
+            self._keep = None
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
+
+
+def build(s_lo, s_hi, stream=None) -> Tree:
+    """Interval trees over subscriptions s_lo, s_hi (float32 [d, n] on the GPU)."""
+    s_lo, s_hi = _coords(s_lo, s_hi, "build")
+    d, n = int(s_lo.shape[0]), int(s_lo.shape[1])
+    h = ctypes.c_void_p()
+    check(lib().ddm_build(ctypes.c_void_p(s_lo.data_ptr()), ctypes.c_void_p(s_hi.data_ptr()),
+                          n, d, _stream_handle(stream), ctypes.byref(h)), "ddm_build")
+    return Tree(h, n, d, (s_lo, s_hi))
+
+
+def match(tree: Tree, u_lo, u_hi, traversal: str = "auto", block: int = 0, stream=None,
+          out=None):
+    """Sorted int64 keys (update << 32) | subscription of all intersecting pairs.
+
+    With ``out`` (int64 CUDA tensor) the keys are written into its first K
+    slots and a view of them is returned; otherwise a tensor of exactly K
+    elements is allocated on the current stream.
+    """
+    torch = _torch()
+    u_lo, u_hi = _coords(u_lo, u_hi, "match")
+    if u_lo.shape[0] != tree.d:
+        raise ValueError("match: update dimension differs from the tree's")
+    m = int(u_lo.shape[1])
+    o = _opts(traversal, block)
+    K = ctypes.c_uint64()
+    pend = ctypes.c_void_p()
+    sh = _stream_handle(stream)
+    check(lib().ddm_match_begin(tree.handle, ctypes.c_void_p(u_lo.data_ptr()),
+                                ctypes.c_void_p(u_hi.data_ptr()), m, ctypes.byref(K), sh,
+                                ctypes.byref(o), ctypes.byref(pend)), "ddm_match_begin")
+    k = int(K.value)
+    if out is None:
+        dev = u_lo.device
+        out = torch.empty(k, dtype=torch.int64, device=dev)
+    elif out.dtype != torch.int64 or not out.is_cuda:
+        lib().ddm_match_abort(pend)
+        raise TypeError("match: out must be an int64 CUDA tensor")
+    if out.numel() < k:
+        lib().ddm_match_abort(pend)
+        raise DDMError(DDM_E_CAPACITY, "match", f"K={k} > capacity {out.numel()}")
+    ptr = ctypes.c_void_p(out.data_ptr()) if out.numel() else ctypes.c_void_p()
+    check(lib().ddm_match_finish(pend, ptr, out.numel()), "ddm_match_finish")
+    return out[:k]
+
+
+def match_into(tree: Tree, u_lo, u_hi, out, traversal: str = "auto", block: int = 0,
+               stream=None) -> int:
+    """One-call form (ddm_match_ex): writes into ``out`` and returns K.
+
+    Raises DDMError(DDM_E_CAPACITY) with ``.detail`` holding K if out is too
+    small.
+    """
+    u_lo, u_hi = _coords(u_lo, u_hi, "match_into")
+    m = int(u_lo.shape[1])
+    o = _opts(traversal, block)
+    K = ctypes.c_uint64()
+    ptr = ctypes.c_void_p(out.data_ptr()) if out.numel() else ctypes.c_void_p()
+    rc = lib().ddm_match_ex(tree.handle, ctypes.c_void_p(u_lo.data_ptr()),
+                            ctypes.c_void_p(u_hi.data_ptr()), m, ptr, out.numel(),
+                            ctypes.byref(K), _stream_handle(stream), ctypes.byref(o))
+    if rc == DDM_E_CAPACITY:
+        raise DDMError(rc, "ddm_match_ex", str(int(K.value)))
+    check(rc, "ddm_match_ex")
+    return int(K.value)
+
+
+def count(tree: Tree, u_lo, u_hi, traversal: str = "auto", block: int = 0, stream=None):
+    """(counts int32 [m], K): subscriptions met by each update."""
+    torch = _torch()
+    u_lo, u_hi = _coords(u_lo, u_hi, "count")
+    m = int(u_lo.shape[1])
+    counts = torch.empty(m, dtype=torch.int32, device=u_lo.device)
+    o = _opts(traversal, block)
+    K = ctypes.c_uint64()
+    check(lib().ddm_count(tree.handle, ctypes.c_void_p(u_lo.data_ptr()),
+                          ctypes.c_void_p(u_hi.data_ptr()), m,
+                          ctypes.c_void_p(counts.data_ptr()) if m else ctypes.c_void_p(),
+                          ctypes.byref(K), _stream_handle(stream), ctypes.byref(o)),
+          "ddm_count")
+    return counts, int(K.value)
+
+
+def prof_enable(on: bool = True, only: str | None = None):
+    """Record HIP events around kernel launches (optionally one kernel only)."""
+    lib().ddm_prof_focus(only.encode() if only else None)
+    lib().ddm_prof_enable(1 if on else 0)
+
+
+def prof_read() -> dict:
+    """{kernel: (total_ms, launches)} since the last read (waits for events)."""
+    buf = ctypes.create_string_buffer(1 << 16)
+    need = lib().ddm_prof_read(buf, len(buf))
+    if need >= len(buf):
+        raise RuntimeError("kernel timing report truncated")
+    return {k: tuple(v) for k, v in json.loads(buf.value.decode()).items()}

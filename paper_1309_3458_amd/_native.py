@@ -1,0 +1,110 @@
+"""ctypes binding of libddm.so (argument marshalling only).
+
+Every computation happens in the library's HIP kernels.  If the library has
+not been built this module raises instead of falling back to anything else.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import re
+
+PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(PKG, "_build", "libddm.so")
+HEADER = os.path.join(os.path.dirname(PKG), "include", "ddm.h")
+
+DDM_OK = 0
+DDM_E_INVALID_ARG = -1
+DDM_E_INVALID_INPUT = -2
+DDM_E_CAPACITY = -3
+DDM_E_NOMEM = -4
+DDM_E_DEVICE = -5
+
+TRAVERSE = {"auto": 0, "lane": 1, "tile": 2}
+
+
+class DDMError(RuntimeError):
+    def __init__(self, code: int, where: str, detail: str = ""):
+        self.code = code
+        self.detail = detail
+        msg = f"{where}: {strerror(code)}"
+        if detail:
+            msg += f" ({detail})"
+        super().__init__(msg)
+
+
+class MatchOpts(ctypes.Structure):
+    _fields_ = [("traversal", ctypes.c_uint32), ("block", ctypes.c_uint32),
+                ("reserved", ctypes.c_uint32 * 6)]
+
+
+_lib = None
+
+vp = ctypes.c_void_p
+u32 = ctypes.c_uint32
+u64 = ctypes.c_uint64
+i32 = ctypes.c_int
+
+
+def _sig(L, name, restype, *argtypes):
+    f = getattr(L, name)
+    f.restype = restype
+    f.argtypes = list(argtypes)
+
+
+def lib():
+    """The loaded libddm (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(
+            f"libddm.so is not built ({LIB_PATH}); run "
+            "`python -m paper_1309_3458_amd.build_lib` (or __graft_entry__.build())")
+    L = ctypes.CDLL(LIB_PATH)
+    P = ctypes.POINTER
+    _sig(L, "ddm_build", i32, vp, vp, u32, u32, vp, P(vp))
+    _sig(L, "ddm_match", i32, vp, vp, vp, u32, vp, u64, P(u64), vp)
+    _sig(L, "ddm_match_ex", i32, vp, vp, vp, u32, vp, u64, P(u64), vp, P(MatchOpts))
+    _sig(L, "ddm_match_begin", i32, vp, vp, vp, u32, P(u64), vp, P(MatchOpts), P(vp))
+    _sig(L, "ddm_match_finish", i32, vp, vp, u64)
+    _sig(L, "ddm_match_abort", None, vp)
+    _sig(L, "ddm_count", i32, vp, vp, vp, u32, vp, P(u64), vp, P(MatchOpts))
+    _sig(L, "ddm_tree_check", i32, vp)
+    _sig(L, "ddm_tree_info", i32, vp, P(u32), P(u32), P(u32))
+    _sig(L, "ddm_tree_export", i32, vp, u32, vp, vp, vp, vp)
+    _sig(L, "ddm_tree_free", None, vp)
+    _sig(L, "ddm_strerror", ctypes.c_char_p, i32)
+    _sig(L, "ddm_last_error_detail", ctypes.c_char_p)
+    _sig(L, "ddm_prof_enable", None, i32)
+    _sig(L, "ddm_prof_read", u64, ctypes.c_char_p, u64)
+    _sig(L, "ddm_prof_focus", None, ctypes.c_char_p)
+    _lib = L
+    return L
+
+
+def strerror(code: int) -> str:
+    try:
+        return lib().ddm_strerror(code).decode()
+    except Exception:  # pragma: no cover - only when the library is missing
+        return f"status {code}"
+
+
+def check(code: int, where: str):
+    if code != DDM_OK:
+        raise DDMError(code, where, lib().ddm_last_error_detail().decode())
+
+
+def header_functions() -> list[str]:
+    """Names of every function the public header declares."""
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    names = re.findall(r"\b(ddm_[a-z_0-9]+)\s*\(", src)
+    return sorted(set(names))
+
+
+def opts(traversal: str = "auto", block: int = 0) -> MatchOpts:
+    o = MatchOpts()
+    o.traversal = TRAVERSE[traversal]
+    o.block = block
+    return o

@@ -1,0 +1,196 @@
+// Internal declarations shared by the libddm translation units (gfx950, wave64).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <string>
+
+#include "ddm.h"
+
+namespace ddm {
+
+constexpr int kWave = 64;
+
+// ---------------------------------------------------------------------------
+// error plumbing
+// ---------------------------------------------------------------------------
+void set_detail(const std::string& s);
+ddm_status hip_fail(hipError_t e, const char* what, const char* file, int line);
+
+#define DDM_HIP(call)                                                        \
+  do {                                                                       \
+    hipError_t _e = (call);                                                  \
+    if (_e != hipSuccess) return ::ddm::hip_fail(_e, #call, __FILE__, __LINE__); \
+  } while (0)
+
+#define DDM_LAUNCHED(name)                                                   \
+  do {                                                                       \
+    hipError_t _e = hipGetLastError();                                       \
+    if (_e != hipSuccess) return ::ddm::hip_fail(_e, name, __FILE__, __LINE__); \
+  } while (0)
+
+// ---------------------------------------------------------------------------
+// kernel timing (HIP events on the launching stream)
+// ---------------------------------------------------------------------------
+struct ProfScope {
+  ProfScope(const char* name, hipStream_t s);
+  ~ProfScope();
+  const char* name_;
+  hipStream_t s_;
+  void* ev_[2];
+};
+
+// ---------------------------------------------------------------------------
+// stream-ordered scratch
+// ---------------------------------------------------------------------------
+struct Scratch {
+  explicit Scratch(hipStream_t s) : s_(s) {}
+  ~Scratch();
+  // returns nullptr on failure (detail set); 256-byte aligned sub-allocations
+  // are carved from one hipMallocAsync block by reserve()/take().
+  void reserve(size_t bytes) { want_ += (bytes + 255) & ~size_t(255); }
+  bool commit();
+  template <class T>
+  T* take(size_t count) {
+    size_t b = (count * sizeof(T) + 255) & ~size_t(255);
+    char* p = base_ + used_;
+    used_ += b;
+    return reinterpret_cast<T*>(p);
+  }
+  hipStream_t s_;
+  char* base_ = nullptr;
+  size_t want_ = 0, used_ = 0;
+};
+
+void ensure_pool(int device);
+
+// ---------------------------------------------------------------------------
+// device-side data layout
+// ---------------------------------------------------------------------------
+// One radix-sort array (ping-pong buffers; v may be null for keys only).
+struct SortArr {
+  uint32_t* k[2];
+  uint32_t* v[2];
+  uint32_t n;
+  uint32_t tile0;  // first tile of this array in the launch
+};
+
+constexpr int kSortThreads = 256;
+constexpr int kSortItems = 16;
+constexpr int kSortTile = kSortThreads * kSortItems;  // 4096 keys per tile
+
+// Per-dimension flat interval tree (positions 1..P, P = 2^H - 1 >= n).
+//   rec[k]    (n+1) records of 2d floats; record p (1 <= p <= n) holds the
+//             p-th segment in lower-bound order: lo_k, hi_k, then lo, hi of
+//             every other dimension in increasing order.
+//   maxhi[k]  P+1 floats, maxhi[k][p] = max upper bound in subtree(p).
+//   id[k]     n+1 uint32, subscription id at position p.
+//   skey_lo[k], skey_hi[k]: n sorted order-preserving keys of lo_k / hi_k.
+struct TreeDev {
+  const float* rec[DDM_MAX_D];
+  const float* maxhi[DDM_MAX_D];
+  const uint32_t* id[DDM_MAX_D];
+  const uint32_t* skey_lo[DDM_MAX_D];
+  const uint32_t* skey_hi[DDM_MAX_D];
+  uint32_t n, d, H;
+};
+
+// ---------------------------------------------------------------------------
+// device helpers
+// ---------------------------------------------------------------------------
+// Order-preserving map float32 -> uint32 (-0.0 is folded onto +0.0 so that
+// key order equals float order, equalities included).
+__device__ __forceinline__ uint32_t f2key(float f) {
+  uint32_t b = __float_as_uint(f);
+  if ((b & 0x7fffffffu) == 0u) b = 0u;
+  return (b & 0x80000000u) ? ~b : (b | 0x80000000u);
+}
+
+__device__ __forceinline__ bool valid_extent(float lo, float hi) {
+  return isfinite(lo) && isfinite(hi) && lo <= hi;
+}
+
+__device__ __forceinline__ uint32_t lane_id() {
+  return __builtin_amdgcn_mbcnt_hi(~0u, __builtin_amdgcn_mbcnt_lo(~0u, 0u));
+}
+
+// number of set bits of `mask` below this lane
+__device__ __forceinline__ uint32_t mask_rank(uint64_t mask) {
+  return __builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32),
+                                   __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
+}
+
+__device__ __forceinline__ uint64_t ballot(bool p) { return __ballot(p); }
+
+// lanes of the wave whose 8-bit digit equals this lane's (restricted to `active`)
+__device__ __forceinline__ uint64_t match_digit8(uint32_t dig, uint64_t active) {
+  uint64_t peers = active;
+#pragma unroll
+  for (int b = 0; b < 8; ++b) {
+    bool bit = (dig >> b) & 1u;
+    uint64_t m = ballot(bit);
+    peers &= bit ? m : ~m;
+  }
+  return peers;
+}
+
+__device__ __forceinline__ int uniform_int(int v) { return __builtin_amdgcn_readfirstlane(v); }
+__device__ __forceinline__ uint32_t uniform_u32(uint32_t v) {
+  return (uint32_t)__builtin_amdgcn_readfirstlane((int)v);
+}
+__device__ __forceinline__ float uniform_f32(float v) {
+  return __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(v)));
+}
+
+// first index in sorted keys[0..n) with keys[i] >= x
+__device__ __forceinline__ uint32_t lower_bound_u32(const uint32_t* __restrict__ keys, uint32_t n,
+                                                    uint32_t x) {
+  uint32_t lo = 0, len = n;
+  while (len > 0) {
+    uint32_t half = len >> 1;
+    if (keys[lo + half] < x) {
+      lo += half + 1;
+      len -= half + 1;
+    } else {
+      len = half;
+    }
+  }
+  return lo;
+}
+
+// first index in sorted keys[0..n) with keys[i] > x
+__device__ __forceinline__ uint32_t upper_bound_u32(const uint32_t* __restrict__ keys, uint32_t n,
+                                                    uint32_t x) {
+  uint32_t lo = 0, len = n;
+  while (len > 0) {
+    uint32_t half = len >> 1;
+    if (keys[lo + half] <= x) {
+      lo += half + 1;
+      len -= half + 1;
+    } else {
+      len = half;
+    }
+  }
+  return lo;
+}
+
+// ---------------------------------------------------------------------------
+// launchers implemented in the .hip files (all enqueue on `s`)
+// ---------------------------------------------------------------------------
+// radix sort of `narr` arrays described by device descriptors; 4 passes of 8
+// bits; results end in k[0]/v[0].  hist: ntiles*256 uint32 scratch.
+ddm_status radix_sort_batch(const SortArr* arrs_dev, uint32_t narr, const uint32_t* tile_map,
+                            uint32_t ntiles, uint32_t* hist, int first_pass, int npasses,
+                            hipStream_t s);
+// fills descriptors + tile map on the device from host values (<= 8 arrays)
+ddm_status sort_setup_small(const SortArr* host_arrs, uint32_t narr, SortArr* arrs_dev,
+                            uint32_t* tile_map, uint32_t ntiles, hipStream_t s);
+
+// exclusive scan of u32 counts into u64 offsets out[0..m], out[m] = total.
+// tmp: scan_tmp_words(m) uint64 scratch.
+size_t scan_tmp_words(uint32_t m);
+ddm_status scan_u32_u64(const uint32_t* in, uint64_t* out, uint32_t m, uint64_t* tmp,
+                        hipStream_t s);
+
+}  // namespace ddm

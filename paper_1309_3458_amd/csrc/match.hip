@@ -1,0 +1,1000 @@
+// Matching on the device: Algorithm 4 (IntTree-Matching) with Algorithm 3
+// (Interval-Query) for every update in parallel, Sec. IV "Parallelizing ITM",
+// and the d-dimensional combine of Sec. III-A.
+//
+// Sequence for m updates against a tree set of d dimensions:
+//   1. bits_kernel: per update and dimension k, the exact number of
+//      subscriptions meeting it in dimension k, from two binary searches on
+//      sorted lower and upper bounds (the BITS identity recalled in Sec. II,
+//      closed form).  The smallest count picks the probe dimension k*; for
+//      d = 1 the count is already the final count.
+//   2. updates sorted by (k*, lower bound in k*) so that neighbouring lanes
+//      walk neighbouring parts of the same tree.
+//   3. count traversal (d > 1): Algorithm 3 on tree k*, every candidate also
+//      tested in the other dimensions (membership in every per-dimension
+//      overlap set is decided by that dimension's own predicate, so the
+//      intersection of Sec. III-A is formed without listing the per-dimension
+//      sets).
+//   4. exclusive scan of the counts -> segment offsets, total K.
+//   5. fill traversal: the same walk writes (update << 32) | subscription
+//      into the update's own segment (each query owns its column of M, so
+//      lanes never conflict).
+//   6. per-segment sort by subscription id.
+#include "ddm_internal.h"
+
+#include <algorithm>
+#include <new>
+
+namespace ddm {
+
+TreeDev tree_dev(const ddm_tree* t);
+const int32_t* tree_flag(const ddm_tree* t);
+uint32_t tree_n(const ddm_tree* t);
+uint32_t tree_d(const ddm_tree* t);
+int tree_device(const ddm_tree* t);
+
+// --------------------------------------------------------------------------
+// helpers
+// --------------------------------------------------------------------------
+template <int D>
+__device__ __forceinline__ void load_rec(const float* __restrict__ p, float (&v)[2 * D]) {
+  if constexpr (D == 1) {
+    const float2 a = *reinterpret_cast<const float2*>(p);
+    v[0] = a.x; v[1] = a.y;
+  } else if constexpr (D == 2) {
+    const float4 a = *reinterpret_cast<const float4*>(p);
+    v[0] = a.x; v[1] = a.y; v[2] = a.z; v[3] = a.w;
+  } else if constexpr (D == 3) {
+    const float2 a = reinterpret_cast<const float2*>(p)[0];
+    const float2 b = reinterpret_cast<const float2*>(p)[1];
+    const float2 c = reinterpret_cast<const float2*>(p)[2];
+    v[0] = a.x; v[1] = a.y; v[2] = b.x; v[3] = b.y; v[4] = c.x; v[5] = c.y;
+  } else {
+    const float4 a = reinterpret_cast<const float4*>(p)[0];
+    const float4 b = reinterpret_cast<const float4*>(p)[1];
+    v[0] = a.x; v[1] = a.y; v[2] = a.z; v[3] = a.w;
+    v[4] = b.x; v[5] = b.y; v[6] = b.z; v[7] = b.w;
+  }
+}
+
+// Query j's bounds in record order: probe dimension k first, then the other
+// dimensions ascending (slot s >= 1 holds dimension s-1 or s).
+template <int D>
+__device__ __forceinline__ void load_query(const float* __restrict__ ulo,
+                                           const float* __restrict__ uhi, uint32_t m,
+                                           uint32_t j, uint32_t k, float (&ql)[D],
+                                           float (&qh)[D]) {
+  ql[0] = ulo[(size_t)k * m + j];
+  qh[0] = uhi[(size_t)k * m + j];
+#pragma unroll
+  for (int s = 1; s < D; ++s) {
+    const uint32_t kk = (uint32_t)(s - 1) + (((uint32_t)(s - 1) >= k) ? 1u : 0u);
+    ql[s] = ulo[(size_t)kk * m + j];
+    qh[s] = uhi[(size_t)kk * m + j];
+  }
+}
+
+// closed overlap of a record (2D floats) with query bounds, all dimensions
+template <int D>
+__device__ __forceinline__ bool overlaps(const float (&v)[2 * D], const float (&ql)[D],
+                                         const float (&qh)[D]) {
+  bool ok = true;
+#pragma unroll
+  for (int s = 0; s < D; ++s) ok = ok && (v[2 * s] <= qh[s]) && (ql[s] <= v[2 * s + 1]);
+  return ok;
+}
+
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+__device__ __forceinline__ float wave_min(float v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v = fminf(v, __shfl_xor(v, o, kWave));
+  return uniform_f32(v);
+}
+
+__device__ __forceinline__ float wave_max(float v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v = fmaxf(v, __shfl_xor(v, o, kWave));
+  return uniform_f32(v);
+}
+
+__device__ __forceinline__ uint64_t readlane_u64(uint64_t v, uint32_t lane) {
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)v, (int)lane);
+  const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(v >> 32), (int)lane);
+  return ((uint64_t)hi << 32) | lo;
+}
+
+// --------------------------------------------------------------------------
+// 1. BITS counts, probe dimension, sort keys
+// --------------------------------------------------------------------------
+template <int D>
+__global__ __launch_bounds__(256) void bits_kernel(TreeDev T, const float* __restrict__ ulo,
+                                                   const float* __restrict__ uhi, uint32_t m,
+                                                   uint32_t* __restrict__ cmin,
+                                                   uint8_t* __restrict__ kstar,
+                                                   uint32_t* __restrict__ qkey,
+                                                   uint32_t* __restrict__ qval,
+                                                   uint32_t* __restrict__ gcount,
+                                                   int32_t* __restrict__ flag) {
+  const uint32_t j = blockIdx.x * blockDim.x + threadIdx.x;
+  const bool act = j < m;
+  bool bad = false;
+  uint32_t best = 0xffffffffu, bk = 0;
+  if (act) {
+#pragma unroll
+    for (int k = 0; k < D; ++k) {
+      const float a = ulo[(size_t)k * m + j], b = uhi[(size_t)k * m + j];
+      bad = bad || !valid_extent(a, b);
+      const uint32_t c = upper_bound_u32(T.skey_lo[k], T.n, f2key(b)) -
+                         lower_bound_u32(T.skey_hi[k], T.n, f2key(a));
+      if (c < best) {
+        best = c;
+        bk = (uint32_t)k;
+      }
+    }
+    if (bad) {
+      best = 0;
+      bk = 0;
+    }
+    cmin[j] = best;
+    kstar[j] = (uint8_t)bk;
+    qkey[j] = (bk << 30) | (f2key(ulo[(size_t)bk * m + j]) >> 2);
+    qval[j] = j;
+  }
+  if (ballot(bad) != 0 && lane_id() == 0) atomicOr(flag, 2);
+#pragma unroll
+  for (int k = 0; k < D; ++k) {
+    const uint64_t b = ballot(act && bk == (uint32_t)k);
+    if (b != 0 && lane_id() == 0) atomicAdd(&gcount[k], (uint32_t)__popcll(b));
+  }
+}
+
+// --------------------------------------------------------------------------
+// 3/5a. one lane per update: Algorithm 3 without a stack.
+//
+// On the implicit in-order tree the recursion of Algorithm 3 becomes a walk
+// over positions in increasing order with two states:
+//   ENTER x  (call on subtree x of height h, span [a, x + 2^h - 1]):
+//            a > n (all padding)            -> stop (so is everything after);
+//            minlower = lo[a] > q.upper     -> stop (every later lower bound
+//                                              is at least as large);
+//            maxupper[x] < q.lower          -> skip the subtree, VISIT x + 2^h;
+//            else descend to the left child, or VISIT x at a leaf.
+//   VISIT x  (left subtree of x done): x > n or lo[x] > q.upper -> stop;
+//            test x (Algorithm 1, closed, all dimensions); then ENTER the
+//            right child, or VISIT x + 1 at a leaf.
+// Positions after the end of a subtree are exactly the next in-order node
+// whose left subtree is complete, so no stack is needed.  The nodes tested
+// are those Algorithm 3 tests, in the same (in-order) order, except that the
+// walk stops at the first lower bound beyond q.upper instead of returning
+// through ancestors that would all fail the same test.
+// --------------------------------------------------------------------------
+template <int D, bool FILL>
+__global__ __launch_bounds__(1024) void lane_kernel(TreeDev T, const float* __restrict__ ulo,
+                                                   const float* __restrict__ uhi, uint32_t m,
+                                                   const uint32_t* __restrict__ perm,
+                                                   const uint8_t* __restrict__ kstar,
+                                                   uint32_t* __restrict__ cnt,
+                                                   const uint64_t* __restrict__ off,
+                                                   uint64_t* __restrict__ out) {
+  constexpr int R = 2 * D;
+  const uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= m) return;
+  const uint32_t j = perm[t];
+  const uint32_t k = kstar[j];
+  float ql[D], qh[D];
+  load_query<D>(ulo, uhi, m, j, k, ql, qh);
+  const float* __restrict__ rec = T.rec[k];
+  const float* __restrict__ mx = T.maxhi[k];
+  const uint32_t* __restrict__ ids = T.id[k];
+  const uint32_t n = T.n;
+  uint32_t x = 1u << (T.H - 1);
+  bool enter = true;
+  uint32_t c = 0;
+  const uint64_t base = FILL ? off[j] : 0;
+  const uint64_t lim = FILL ? off[j + 1] - base : 0;  // segment length (write guard)
+  const uint64_t jhi = (uint64_t)j << 32;
+  while (true) {
+    if (enter) {
+      const uint32_t h = (uint32_t)__builtin_ctz(x);
+      const uint32_t a = x - (1u << h) + 1u;
+      if (a > n) break;
+      if (rec[(size_t)a * R] > qh[0]) break;
+      if (mx[x] < ql[0]) {
+        x += 1u << h;
+        enter = false;
+      } else if (h == 0) {
+        enter = false;
+      } else {
+        x -= 1u << (h - 1);
+      }
+    } else {
+      if (x > n) break;
+      float v[R];
+      load_rec<D>(rec + (size_t)x * R, v);
+      if (v[0] > qh[0]) break;
+      if (overlaps<D>(v, ql, qh)) {
+        if (FILL && c < lim) out[base + c] = jhi | ids[x];
+        ++c;
+      }
+      const uint32_t h = (uint32_t)__builtin_ctz(x);
+      if (h == 0) {
+        x += 1u;
+      } else {
+        x += 1u << (h - 1);
+        enter = true;
+      }
+    }
+  }
+  if (!FILL) cnt[j] = c;
+}
+
+// --------------------------------------------------------------------------
+// 3/5b. one wavefront per tile of 64 updates (sorted by lower bound in the
+// probe dimension k of their group).
+//
+// The wave runs the same walk once, with uniform control flow, for the
+// tile's enclosing box E (per dimension: min of lower bounds, max of upper
+// bounds).  Every subscription meeting an update of the tile meets E, so the
+// walk's candidates contain every answer.  Subtrees of height <= 5 (at most
+// 63 positions) are loaded whole, one position per lane; candidates meeting
+// E in every dimension are compacted into an LDS ring with a wavefront
+// ballot and a prefix popcount.  Each time 64 candidates are pending, lane l
+// takes candidate l and the wave tests all updates of the tile against the
+// 64 candidates: one ballot per update gives its hits, and a prefix popcount
+// places them contiguously in the update's segment.
+// --------------------------------------------------------------------------
+constexpr int kTileWaves = 4;
+constexpr int kRing = 128;
+
+template <int D, bool FILL>
+__global__ __launch_bounds__(kTileWaves * kWave) void tile_kernel(
+    TreeDev T, const float* __restrict__ ulo, const float* __restrict__ uhi, uint32_t m,
+    const uint32_t* __restrict__ perm, const uint32_t* __restrict__ gcount,
+    uint32_t* __restrict__ cnt, const uint64_t* __restrict__ off, uint64_t* __restrict__ out) {
+  constexpr int R = 2 * D;
+  __shared__ float s_cand[kTileWaves][R][kRing];
+  __shared__ uint32_t s_cid[kTileWaves][kRing];
+  __shared__ float s_q[kTileWaves][kWave][R];
+  const uint32_t wave = threadIdx.x / kWave;
+  const uint32_t lane = lane_id();
+  const uint32_t tile = blockIdx.x * kTileWaves + wave;
+
+  // locate the tile inside its probe-dimension group
+  uint32_t qbeg = 0, tacc = 0, nq = 0, k = 0;
+  bool found = false;
+#pragma unroll
+  for (int g = 0; g < D; ++g) {
+    const uint32_t gs = uniform_u32(gcount[g]);
+    const uint32_t nt = (gs + kWave - 1) / kWave;
+    if (!found) {
+      if (tile < tacc + nt) {
+        found = true;
+        k = (uint32_t)g;
+        const uint32_t lt = tile - tacc;
+        qbeg += lt * kWave;
+        nq = min((uint32_t)kWave, gs - lt * kWave);
+      } else {
+        tacc += nt;
+        qbeg += gs;
+      }
+    }
+  }
+  if (!found) return;
+  k = uniform_u32(k);
+  nq = uniform_u32(nq);
+  qbeg = uniform_u32(qbeg);
+
+  const bool qv = lane < nq;
+  const uint32_t j = qv ? perm[qbeg + lane] : 0u;
+  float ql[D], qh[D];
+  if (qv) {
+    load_query<D>(ulo, uhi, m, j, k, ql, qh);
+  } else {
+#pragma unroll
+    for (int s = 0; s < D; ++s) {
+      ql[s] = INFINITY;
+      qh[s] = -INFINITY;
+    }
+  }
+  float elo[D], ehi[D];
+#pragma unroll
+  for (int s = 0; s < D; ++s) {
+    elo[s] = wave_min(ql[s]);
+    ehi[s] = wave_max(qh[s]);
+    s_q[wave][lane][2 * s] = ql[s];
+    s_q[wave][lane][2 * s + 1] = qh[s];
+  }
+  uint32_t mycnt = 0;
+  uint64_t mybase = (FILL && qv) ? off[j] : 0;
+  const uint64_t myend = (FILL && qv) ? off[j + 1] : 0;  // segment end (write guard)
+  const uint64_t jhi = (uint64_t)j << 32;
+  wave_sync();
+
+  const float* __restrict__ rec = T.rec[k];
+  const float* __restrict__ mx = T.maxhi[k];
+  const uint32_t* __restrict__ ids = T.id[k];
+  const uint32_t n = T.n;
+
+  uint32_t head = 0, tail = 0;
+
+  auto flush = [&](uint32_t c) {
+    wave_sync();
+    const bool cv = lane < c;
+    const uint32_t slot = (head + lane) & (kRing - 1);
+    float v[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) v[r] = s_cand[wave][r][slot];
+    const uint32_t sid = s_cid[wave][slot];
+    for (uint32_t qi = 0; qi < nq; ++qi) {
+      float q[R];
+#pragma unroll
+      for (int r = 0; r < R; ++r) q[r] = s_q[wave][qi][r];
+      bool hit = cv;
+#pragma unroll
+      for (int s = 0; s < D; ++s) hit = hit && (v[2 * s] <= q[2 * s + 1]) && (q[2 * s] <= v[2 * s + 1]);
+      const uint64_t hm = ballot(hit);
+      if (hm != 0) {
+        const uint32_t pc = (uint32_t)__popcll(hm);
+        if (FILL) {
+          const uint64_t b = readlane_u64(mybase, qi);
+          const uint64_t e = readlane_u64(myend, qi);
+          const uint64_t jq = readlane_u64(jhi, qi);
+          const uint64_t dst = b + mask_rank(hm);
+          if (hit && dst < e) out[dst] = jq | sid;
+          if (lane == qi) mybase += pc;
+        } else {
+          if (lane == qi) mycnt += pc;
+        }
+      }
+    }
+    head += c;
+    wave_sync();
+  };
+
+  auto push_block = [&](uint32_t a, uint32_t b) {
+    // positions a..b (b - a < 64), one per lane
+    const uint32_t p = a + lane;
+    bool cnd = false;
+    float v[R];
+    if (p <= b) {
+      load_rec<D>(rec + (size_t)p * R, v);
+      cnd = true;
+#pragma unroll
+      for (int s = 0; s < D; ++s) cnd = cnd && (v[2 * s] <= ehi[s]) && (elo[s] <= v[2 * s + 1]);
+    }
+    const uint64_t bm = ballot(cnd);
+    if (cnd) {
+      const uint32_t slot = (tail + mask_rank(bm)) & (kRing - 1);
+#pragma unroll
+      for (int r = 0; r < R; ++r) s_cand[wave][r][slot] = v[r];
+      s_cid[wave][slot] = ids[p];
+    }
+    tail += (uint32_t)__popcll(bm);
+  };
+
+  uint32_t x = 1u << (T.H - 1);
+  bool enter = true;
+  while (true) {
+    if (enter) {
+      const uint32_t h = (uint32_t)__builtin_ctz(x);
+      const uint32_t a = x - (1u << h) + 1u;
+      if (a > n) break;
+      if (uniform_f32(rec[(size_t)a * R]) > ehi[0]) break;
+      if (uniform_f32(mx[x]) < elo[0]) {
+        x += 1u << h;
+        enter = false;
+      } else if (h <= 5) {
+        push_block(a, min(x + (1u << h) - 1u, n));
+        x += 1u << h;
+        enter = false;
+        while (tail - head >= (uint32_t)kWave) flush(kWave);
+      } else {
+        x -= 1u << (h - 1);
+      }
+    } else {
+      if (x > n) break;
+      if (uniform_f32(rec[(size_t)x * R]) > ehi[0]) break;
+      push_block(x, x);
+      while (tail - head >= (uint32_t)kWave) flush(kWave);
+      const uint32_t h = (uint32_t)__builtin_ctz(x);
+      if (h == 0) {
+        x += 1u;
+      } else {
+        x += 1u << (h - 1);
+        enter = true;
+      }
+    }
+  }
+  if (tail != head) flush(tail - head);
+  if (!FILL && qv) cnt[j] = mycnt;
+}
+
+// --------------------------------------------------------------------------
+// 6. per-segment sort by subscription id
+// --------------------------------------------------------------------------
+template <int N>
+__device__ __forceinline__ void bitonic_regs(uint64_t (&v)[N]) {
+#pragma unroll
+  for (int k = 2; k <= N; k <<= 1) {
+#pragma unroll
+    for (int jj = k >> 1; jj > 0; jj >>= 1) {
+#pragma unroll
+      for (int i = 0; i < N; ++i) {
+        const int l = i ^ jj;
+        if (l > i) {
+          const bool up = (i & k) == 0;
+          const uint64_t a = v[i], b = v[l];
+          const bool sw = up ? (a > b) : (a < b);
+          v[i] = sw ? b : a;
+          v[l] = sw ? a : b;
+        }
+      }
+    }
+  }
+}
+
+template <int N>
+__device__ __forceinline__ void sort_small_segment(uint64_t* __restrict__ p, uint32_t len) {
+  uint64_t v[N];
+#pragma unroll
+  for (int i = 0; i < N; ++i) v[i] = ((uint32_t)i < len) ? p[i] : ~0ull;
+  bitonic_regs<N>(v);
+#pragma unroll
+  for (int i = 0; i < N; ++i)
+    if ((uint32_t)i < len) p[i] = v[i];
+}
+
+constexpr uint32_t kSegMid = 4096;  // longest segment sorted in LDS by bitonic
+
+__global__ __launch_bounds__(256) void segsort_small_kernel(const uint64_t* __restrict__ off,
+                                                            uint32_t m, uint64_t* __restrict__ out,
+                                                            uint32_t* __restrict__ lists,
+                                                            uint32_t* __restrict__ list_count) {
+  const uint32_t j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= m) return;
+  const uint64_t b = off[j];
+  const uint64_t len64 = off[j + 1] - b;
+  if (len64 <= 1) return;
+  const uint32_t len = len64 > 0xffffffffull ? 0xffffffffu : (uint32_t)len64;
+  if (len <= 4) {
+    sort_small_segment<4>(out + b, len);
+  } else if (len <= 8) {
+    sort_small_segment<8>(out + b, len);
+  } else if (len <= 16) {
+    sort_small_segment<16>(out + b, len);
+  } else if (len <= kSegMid) {
+    lists[atomicAdd(&list_count[0], 1u)] = j;
+  } else {
+    lists[m + atomicAdd(&list_count[1], 1u)] = j;
+  }
+}
+
+// one workgroup per listed segment (17..4096 keys): ids bitonic-sorted in LDS
+__global__ __launch_bounds__(256) void segsort_mid_kernel(const uint64_t* __restrict__ off,
+                                                          uint64_t* __restrict__ out,
+                                                          const uint32_t* __restrict__ lists,
+                                                          const uint32_t* __restrict__ list_count) {
+  __shared__ uint32_t s[kSegMid];
+  const uint32_t cntl = list_count[0];
+  for (uint32_t li = blockIdx.x; li < cntl; li += gridDim.x) {
+    const uint32_t j = lists[li];
+    const uint64_t b = off[j];
+    const uint32_t len = (uint32_t)(off[j + 1] - b);
+    uint32_t P2 = 32;
+    while (P2 < len) P2 <<= 1;
+    for (uint32_t i = threadIdx.x; i < P2; i += 256)
+      s[i] = (i < len) ? (uint32_t)out[b + i] : 0xffffffffu;
+    __syncthreads();
+    for (uint32_t k = 2; k <= P2; k <<= 1) {
+      for (uint32_t jj = k >> 1; jj > 0; jj >>= 1) {
+        for (uint32_t i = threadIdx.x; i < P2; i += 256) {
+          const uint32_t l = i ^ jj;
+          if (l > i) {
+            const uint32_t a = s[i], c = s[l];
+            const bool up = (i & k) == 0;
+            if (up ? (a > c) : (a < c)) {
+              s[i] = c;
+              s[l] = a;
+            }
+          }
+        }
+        __syncthreads();
+      }
+    }
+    const uint64_t jhi = (uint64_t)j << 32;
+    for (uint32_t i = threadIdx.x; i < len; i += 256) out[b + i] = jhi | s[i];
+    __syncthreads();
+  }
+}
+
+// One workgroup per long segment: mark ids in an LDS bitmap covering a
+// window of 2^20 ids, then emit them in increasing order.  Segments whose
+// ids do not fit one window read them from `src` (a copy), window by window.
+constexpr uint32_t kBitWords = 1u << 15;  // 2^20 bits = 128 KiB
+constexpr int kBigThreads = 1024;
+
+__global__ __launch_bounds__(kBigThreads) void segsort_big_kernel(
+    const uint64_t* __restrict__ off, uint32_t m, uint64_t* __restrict__ out,
+    const uint32_t* __restrict__ lists, const uint32_t* __restrict__ list_count,
+    const uint32_t* __restrict__ src, uint32_t n) {
+  __shared__ uint32_t bits[kBitWords];
+  __shared__ uint32_t wsum[kBigThreads / kWave];
+  const uint32_t cntl = list_count[1];
+  const uint32_t tid = threadIdx.x;
+  const uint32_t lane = lane_id();
+  const uint32_t wave = tid / kWave;
+  const uint32_t nwin = (n + (kBitWords * 32) - 1) / (kBitWords * 32);
+  for (uint32_t li = blockIdx.x; li < cntl; li += gridDim.x) {
+    const uint32_t j = lists[m + li];
+    const uint64_t b = off[j];
+    const uint64_t len = off[j + 1] - b;
+    const uint64_t jhi = (uint64_t)j << 32;
+    uint64_t written = 0;
+    for (uint32_t w = 0; w < nwin; ++w) {
+      const uint32_t w0 = w * kBitWords * 32;
+      const uint32_t words = min(kBitWords, (n - w0 + 31) / 32);
+      for (uint32_t i = tid; i < words; i += kBigThreads) bits[i] = 0;
+      __syncthreads();
+      for (uint64_t i = tid; i < len; i += kBigThreads) {
+        const uint32_t id = (nwin == 1) ? (uint32_t)out[b + i] : src[b + i];
+        if (id >= w0 && id - w0 < kBitWords * 32) {
+          const uint32_t r = id - w0;
+          atomicOr(&bits[r >> 5], 1u << (r & 31));
+        }
+      }
+      __syncthreads();
+      // each thread owns a contiguous run of words
+      const uint32_t per = (words + kBigThreads - 1) / kBigThreads;
+      const uint32_t w_beg = min(words, tid * per), w_end = min(words, w_beg + per);
+      uint32_t mine = 0;
+      for (uint32_t q = w_beg; q < w_end; ++q) mine += __popc(bits[q]);
+      // block exclusive scan of `mine`
+      uint32_t inc = mine;
+#pragma unroll
+      for (int o = 1; o < kWave; o <<= 1) {
+        const uint32_t t2 = __shfl_up(inc, o, kWave);
+        if (lane >= (uint32_t)o) inc += t2;
+      }
+      if (lane == kWave - 1) wsum[wave] = inc;
+      __syncthreads();
+      uint32_t before = 0, total = 0;
+      for (uint32_t q = 0; q < kBigThreads / kWave; ++q) {
+        if (q < wave) before += wsum[q];
+        total += wsum[q];
+      }
+      uint64_t pos = written + before + inc - mine;
+      for (uint32_t q = w_beg; q < w_end; ++q) {
+        uint32_t word = bits[q];
+        while (word) {
+          const uint32_t bit = (uint32_t)__builtin_ctz(word);
+          word &= word - 1;
+          out[b + pos++] = jhi | (w0 + q * 32 + bit);
+        }
+      }
+      written += total;
+      __syncthreads();
+    }
+  }
+}
+
+__global__ void copy_ids_kernel(const uint64_t* __restrict__ in, uint32_t* __restrict__ outp,
+                                uint64_t K) {
+  const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < K) outp[i] = (uint32_t)in[i];
+}
+
+__global__ void zero_u32_kernel(uint32_t* __restrict__ p, uint32_t count) {
+  const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < count) p[i] = 0;
+}
+
+__global__ void copy_counts_kernel(const uint32_t* __restrict__ in, uint32_t* __restrict__ o,
+                                   uint32_t m) {
+  const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < m) o[i] = in[i];
+}
+
+// --------------------------------------------------------------------------
+// host side
+// --------------------------------------------------------------------------
+struct MatchPlan {
+  uint32_t traversal;
+  uint32_t block;
+};
+
+static ddm_status parse_opts(const ddm_match_opts* o, MatchPlan* p) {
+  p->traversal = DDM_TRAVERSE_TILE;
+  p->block = 256;
+  if (!o) return DDM_OK;
+  for (int i = 0; i < 6; ++i)
+    if (o->reserved[i]) {
+      set_detail("ddm_match_opts: reserved fields must be zero");
+      return DDM_E_INVALID_ARG;
+    }
+  if (o->traversal > DDM_TRAVERSE_TILE) {
+    set_detail("ddm_match_opts: unknown traversal");
+    return DDM_E_INVALID_ARG;
+  }
+  if (o->traversal != DDM_TRAVERSE_AUTO) p->traversal = o->traversal;
+  if (o->block) {
+    if (o->block != 64 && o->block != 128 && o->block != 256 && o->block != 512 &&
+        o->block != 1024) {
+      set_detail("ddm_match_opts: block must be 64..1024, a power of two");
+      return DDM_E_INVALID_ARG;
+    }
+    p->block = o->block;
+  }
+  return DDM_OK;
+}
+
+template <int D>
+static ddm_status launch_bits(const TreeDev& T, const float* ulo, const float* uhi, uint32_t m,
+                              uint32_t* cmin, uint8_t* kstar, uint32_t* qkey, uint32_t* qval,
+                              uint32_t* gcount, int32_t* flag, hipStream_t s) {
+  ProfScope ps("bits", s);
+  bits_kernel<D><<<(m + 255) / 256, 256, 0, s>>>(T, ulo, uhi, m, cmin, kstar, qkey, qval, gcount,
+                                                   flag);
+  DDM_LAUNCHED("bits_kernel");
+  return DDM_OK;
+}
+
+template <int D, bool FILL>
+static ddm_status launch_traverse(const MatchPlan& P, const TreeDev& T, const float* ulo,
+                                  const float* uhi, uint32_t m, const uint32_t* perm,
+                                  const uint8_t* kstar, const uint32_t* gcount, uint32_t* cnt,
+                                  const uint64_t* off, uint64_t* out, hipStream_t s) {
+  if (P.traversal == DDM_TRAVERSE_LANE) {
+    ProfScope ps(FILL ? "traverse_lane_fill" : "traverse_lane_count", s);
+    const uint32_t bs = P.block;
+    lane_kernel<D, FILL><<<(m + bs - 1) / bs, bs, 0, s>>>(T, ulo, uhi, m, perm, kstar, cnt, off,
+                                                          out);
+    DDM_LAUNCHED("lane_kernel");
+  } else {
+    ProfScope ps(FILL ? "traverse_tile_fill" : "traverse_tile_count", s);
+    const uint32_t tiles = (m + kWave - 1) / kWave + D;
+    tile_kernel<D, FILL><<<(tiles + kTileWaves - 1) / kTileWaves, kTileWaves * kWave, 0, s>>>(
+        T, ulo, uhi, m, perm, gcount, cnt, off, out);
+    DDM_LAUNCHED("tile_kernel");
+  }
+  return DDM_OK;
+}
+
+template <bool FILL>
+static ddm_status traverse_any(uint32_t d, const MatchPlan& P, const TreeDev& T,
+                               const float* ulo, const float* uhi, uint32_t m,
+                               const uint32_t* perm, const uint8_t* kstar,
+                               const uint32_t* gcount, uint32_t* cnt, const uint64_t* off,
+                               uint64_t* out, hipStream_t s) {
+  switch (d) {
+    case 1: return launch_traverse<1, FILL>(P, T, ulo, uhi, m, perm, kstar, gcount, cnt, off, out, s);
+    case 2: return launch_traverse<2, FILL>(P, T, ulo, uhi, m, perm, kstar, gcount, cnt, off, out, s);
+    case 3: return launch_traverse<3, FILL>(P, T, ulo, uhi, m, perm, kstar, gcount, cnt, off, out, s);
+    default: return launch_traverse<4, FILL>(P, T, ulo, uhi, m, perm, kstar, gcount, cnt, off, out, s);
+  }
+}
+
+// pinned host words for the single device->host read of a match
+// (one small block per host thread, kept for the life of the process)
+struct HostWords {
+  uint64_t* p = nullptr;
+};
+static thread_local HostWords g_host;
+
+static ddm_status host_words(uint64_t** out) {
+  if (!g_host.p) {
+    hipError_t e = hipHostMalloc((void**)&g_host.p, 64, hipHostMallocDefault);
+    if (e != hipSuccess) {
+      g_host.p = nullptr;
+      (void)hipGetLastError();
+      set_detail("pinned host allocation failed");
+      return DDM_E_NOMEM;
+    }
+  }
+  *out = g_host.p;
+  return DDM_OK;
+}
+
+// Common front half: validation/BITS, query order, counts, scan, K readback.
+struct MatchState {
+  Scratch sc;
+  uint32_t* cmin = nullptr;
+  uint8_t* kstar = nullptr;
+  uint32_t* qkey = nullptr;
+  uint32_t* qval = nullptr;
+  uint32_t* gcount = nullptr;
+  int32_t* flag = nullptr;
+  uint32_t* cnt = nullptr;
+  uint64_t* off = nullptr;
+  uint64_t K = 0;
+  explicit MatchState(hipStream_t s) : sc(s) {}
+};
+
+__global__ void match_init_kernel(uint32_t* __restrict__ gcount, int32_t* __restrict__ flag,
+                                  uint32_t* __restrict__ lists_count) {
+  if (threadIdx.x < DDM_MAX_D) gcount[threadIdx.x] = 0;
+  if (threadIdx.x == 0) *flag = 0;
+  if (threadIdx.x < 2) lists_count[threadIdx.x] = 0;
+}
+
+__global__ void gather_flags_kernel(const int32_t* __restrict__ tflag,
+                                    const int32_t* __restrict__ uflag,
+                                    const uint64_t* __restrict__ off, uint32_t m,
+                                    uint64_t* __restrict__ dst) {
+  if (threadIdx.x == 0) {
+    dst[0] = off[m];
+    dst[1] = (uint64_t)(uint32_t)(*tflag) | ((uint64_t)(uint32_t)(*uflag) << 32);
+  }
+}
+
+static ddm_status front_half(const ddm_tree* t, const float* ulo, const float* uhi, uint32_t m,
+                             const MatchPlan& P, MatchState& st, uint32_t* counts_out,
+                             uint32_t** lists, uint32_t** lists_count, hipStream_t s) {
+  const uint32_t d = tree_d(t);
+  const TreeDev T = tree_dev(t);
+  const uint32_t tiles = (m + kSortTile - 1) / kSortTile;
+  Scratch& sc = st.sc;
+  sc.reserve(sizeof(uint32_t) * m);          // cmin
+  sc.reserve(m);                             // kstar
+  sc.reserve(sizeof(uint32_t) * m * 4);      // qkey, qval + ping-pong
+  sc.reserve(sizeof(uint32_t) * DDM_MAX_D);  // gcount
+  sc.reserve(sizeof(int32_t));               // flag
+  sc.reserve(sizeof(uint32_t) * m);          // cnt
+  sc.reserve(sizeof(uint64_t) * (m + 1));    // off
+  sc.reserve(sizeof(uint64_t) * scan_tmp_words(m));
+  sc.reserve(sizeof(SortArr));
+  sc.reserve(sizeof(uint32_t) * tiles);
+  sc.reserve(sizeof(uint32_t) * 256 * (size_t)tiles);
+  sc.reserve(sizeof(uint32_t) * (2 * (size_t)m + 2));  // segment lists + counts
+  sc.reserve(sizeof(uint64_t) * 4);                    // device words for readback
+  if (!sc.commit()) return DDM_E_NOMEM;
+  st.cmin = sc.take<uint32_t>(m);
+  st.kstar = sc.take<uint8_t>(m);
+  st.qkey = sc.take<uint32_t>(m);
+  st.qval = sc.take<uint32_t>(m);
+  uint32_t* qkey2 = sc.take<uint32_t>(m);
+  uint32_t* qval2 = sc.take<uint32_t>(m);
+  st.gcount = sc.take<uint32_t>(DDM_MAX_D);
+  st.flag = sc.take<int32_t>(1);
+  st.cnt = sc.take<uint32_t>(m);
+  st.off = sc.take<uint64_t>(m + 1);
+  uint64_t* stmp = sc.take<uint64_t>(scan_tmp_words(m));
+  SortArr* arr = sc.take<SortArr>(1);
+  uint32_t* tile_map = sc.take<uint32_t>(tiles);
+  uint32_t* hist = sc.take<uint32_t>(256 * (size_t)tiles);
+  *lists = sc.take<uint32_t>(2 * (size_t)m);
+  *lists_count = sc.take<uint32_t>(2);
+  uint64_t* dwords = sc.take<uint64_t>(4);
+
+  match_init_kernel<<<1, 64, 0, s>>>(st.gcount, st.flag, *lists_count);
+  DDM_LAUNCHED("match_init_kernel");
+  ddm_status r;
+  switch (d) {
+    case 1: r = launch_bits<1>(T, ulo, uhi, m, st.cmin, st.kstar, st.qkey, st.qval, st.gcount, st.flag, s); break;
+    case 2: r = launch_bits<2>(T, ulo, uhi, m, st.cmin, st.kstar, st.qkey, st.qval, st.gcount, st.flag, s); break;
+    case 3: r = launch_bits<3>(T, ulo, uhi, m, st.cmin, st.kstar, st.qkey, st.qval, st.gcount, st.flag, s); break;
+    default: r = launch_bits<4>(T, ulo, uhi, m, st.cmin, st.kstar, st.qkey, st.qval, st.gcount, st.flag, s); break;
+  }
+  if (r != DDM_OK) return r;
+  // update order for the traversal (payload = update id)
+  SortArr a{};
+  a.k[0] = st.qkey;
+  a.k[1] = qkey2;
+  a.v[0] = st.qval;
+  a.v[1] = qval2;
+  a.n = m;
+  a.tile0 = 0;
+  r = sort_setup_small(&a, 1, arr, tile_map, tiles, s);
+  if (r != DDM_OK) return r;
+  r = radix_sort_batch(arr, 1, tile_map, tiles, hist, 0, 4, s);
+  if (r != DDM_OK) return r;
+  // per-update counts
+  const uint32_t* counts = st.cmin;
+  if (d > 1) {
+    r = traverse_any<false>(d, P, T, ulo, uhi, m, st.qval, st.kstar, st.gcount, st.cnt, nullptr,
+                            nullptr, s);
+    if (r != DDM_OK) return r;
+    counts = st.cnt;
+  }
+  if (counts_out) {
+    copy_counts_kernel<<<(m + 255) / 256, 256, 0, s>>>(counts, counts_out, m);
+    DDM_LAUNCHED("copy_counts_kernel");
+  }
+  r = scan_u32_u64(counts, st.off, m, stmp, s);
+  if (r != DDM_OK) return r;
+  gather_flags_kernel<<<1, 64, 0, s>>>(tree_flag(t), st.flag, st.off, m, dwords);
+  DDM_LAUNCHED("gather_flags_kernel");
+  uint64_t* hw = nullptr;
+  r = host_words(&hw);
+  if (r != DDM_OK) return r;
+  DDM_HIP(hipMemcpyAsync(hw, dwords, 2 * sizeof(uint64_t), hipMemcpyDeviceToHost, s));
+  DDM_HIP(hipStreamSynchronize(s));
+  const uint64_t flags = hw[1];
+  st.K = hw[0];
+  if (flags & 0xffffffffull) {
+    set_detail("subscription coordinates: NaN/inf or lo > hi");
+    return DDM_E_INVALID_INPUT;
+  }
+  if (flags >> 32) {
+    set_detail("update coordinates: NaN/inf or lo > hi");
+    return DDM_E_INVALID_INPUT;
+  }
+  return DDM_OK;
+}
+
+static ddm_status check_common(const ddm_tree* t, const float* ulo, const float* uhi,
+                               uint32_t m) {
+  if (!t) {
+    set_detail("tree is NULL");
+    return DDM_E_INVALID_ARG;
+  }
+  if (m > 0 && (!ulo || !uhi)) {
+    set_detail("NULL update coordinate pointer");
+    return DDM_E_INVALID_ARG;
+  }
+  if (m >= 0x80000000u) {
+    set_detail("m must be below 2^31");
+    return DDM_E_INVALID_ARG;
+  }
+  int cur = -1;
+  DDM_HIP(hipGetDevice(&cur));
+  if (cur != tree_device(t)) {
+    set_detail("the current device is not the tree's device");
+    return DDM_E_INVALID_ARG;
+  }
+  return DDM_OK;
+}
+
+ddm_status sort_segments(const uint64_t* off, uint32_t m, uint64_t* out, uint64_t K, uint32_t n,
+                         uint32_t* lists, uint32_t* lists_count, hipStream_t s) {
+  ProfScope ps("segsort", s);
+  segsort_small_kernel<<<(m + 255) / 256, 256, 0, s>>>(off, m, out, lists, lists_count);
+  DDM_LAUNCHED("segsort_small_kernel");
+  segsort_mid_kernel<<<1024, 256, 0, s>>>(off, out, lists, lists_count);
+  DDM_LAUNCHED("segsort_mid_kernel");
+  uint32_t* src = nullptr;
+  Scratch sc(s);
+  if (n > kBitWords * 32) {
+    sc.reserve(sizeof(uint32_t) * K);
+    if (!sc.commit()) return DDM_E_NOMEM;
+    src = sc.take<uint32_t>(K);
+    copy_ids_kernel<<<(unsigned)((K + 255) / 256), 256, 0, s>>>(out, src, K);
+    DDM_LAUNCHED("copy_ids_kernel");
+  }
+  segsort_big_kernel<<<256, kBigThreads, 0, s>>>(off, m, out, lists, lists_count, src, n);
+  DDM_LAUNCHED("segsort_big_kernel");
+  return DDM_OK;
+}
+
+}  // namespace ddm
+
+using namespace ddm;
+
+struct ddm_pending {
+  ddm::MatchState st;
+  ddm::MatchPlan plan;
+  const ddm_tree* t;
+  const float* ulo;
+  const float* uhi;
+  uint32_t m;
+  uint32_t* lists = nullptr;
+  uint32_t* lists_count = nullptr;
+  hipStream_t s;
+  explicit ddm_pending(hipStream_t st_) : st(st_), s(st_) {}
+};
+
+extern "C" ddm_status ddm_match_begin(const ddm_tree* t, const float* upd_lo,
+                                      const float* upd_hi, uint32_t m, uint64_t* out_count,
+                                      void* stream, const ddm_match_opts* opts,
+                                      ddm_pending** out_pending) {
+  set_detail("");
+  if (!out_count || !out_pending) {
+    set_detail("out_count / out_pending is NULL");
+    return DDM_E_INVALID_ARG;
+  }
+  *out_count = 0;
+  *out_pending = nullptr;
+  ddm_status r = check_common(t, upd_lo, upd_hi, m);
+  if (r != DDM_OK) return r;
+  MatchPlan P;
+  r = parse_opts(opts, &P);
+  if (r != DDM_OK) return r;
+  hipStream_t s = (hipStream_t)stream;
+  if (m == 0 || tree_n(t) == 0) {
+    if (tree_n(t) != 0) return ddm_tree_check(t);
+    return DDM_OK;
+  }
+  ddm_pending* pd = new (std::nothrow) ddm_pending(s);
+  if (!pd) return DDM_E_NOMEM;
+  pd->plan = P;
+  pd->t = t;
+  pd->ulo = upd_lo;
+  pd->uhi = upd_hi;
+  pd->m = m;
+  r = front_half(t, upd_lo, upd_hi, m, P, pd->st, nullptr, &pd->lists, &pd->lists_count, s);
+  if (r != DDM_OK) {
+    delete pd;
+    return r;
+  }
+  *out_count = pd->st.K;
+  *out_pending = pd;
+  return DDM_OK;
+}
+
+extern "C" ddm_status ddm_match_finish(ddm_pending* pd, uint64_t* out_pairs, uint64_t capacity) {
+  set_detail("");
+  if (!pd) return DDM_OK;  // empty match: nothing to do
+  ddm_status r = DDM_OK;
+  if (pd->st.K > capacity) {
+    set_detail("result larger than capacity");
+    r = DDM_E_CAPACITY;
+  } else if (pd->st.K > 0 && !out_pairs) {
+    set_detail("out_pairs is NULL");
+    r = DDM_E_INVALID_ARG;
+  } else if (pd->st.K > 0) {
+    const TreeDev T = tree_dev(pd->t);
+    r = traverse_any<true>(tree_d(pd->t), pd->plan, T, pd->ulo, pd->uhi, pd->m, pd->st.qval,
+                           pd->st.kstar, pd->st.gcount, nullptr, pd->st.off, out_pairs, pd->s);
+    if (r == DDM_OK)
+      r = sort_segments(pd->st.off, pd->m, out_pairs, pd->st.K, tree_n(pd->t), pd->lists,
+                        pd->lists_count, pd->s);
+  }
+  delete pd;
+  return r;
+}
+
+extern "C" void ddm_match_abort(ddm_pending* pd) { delete pd; }
+
+extern "C" ddm_status ddm_match_ex(const ddm_tree* t, const float* upd_lo, const float* upd_hi,
+                                   uint32_t m, uint64_t* out_pairs, uint64_t capacity,
+                                   uint64_t* out_count, void* stream,
+                                   const ddm_match_opts* opts) {
+  ddm_pending* pd = nullptr;
+  ddm_status r = ddm_match_begin(t, upd_lo, upd_hi, m, out_count, stream, opts, &pd);
+  if (r != DDM_OK) return r;
+  if (*out_count > capacity) {
+    ddm_match_abort(pd);
+    set_detail("result larger than capacity");
+    return DDM_E_CAPACITY;
+  }
+  return ddm_match_finish(pd, out_pairs, capacity);
+}
+
+extern "C" ddm_status ddm_match(const ddm_tree* t, const float* upd_lo, const float* upd_hi,
+                                uint32_t m, uint64_t* out_pairs, uint64_t capacity,
+                                uint64_t* out_count, void* stream) {
+  return ddm_match_ex(t, upd_lo, upd_hi, m, out_pairs, capacity, out_count, stream, nullptr);
+}
+
+extern "C" ddm_status ddm_count(const ddm_tree* t, const float* upd_lo, const float* upd_hi,
+                                uint32_t m, uint32_t* counts, uint64_t* out_total, void* stream,
+                                const ddm_match_opts* opts) {
+  set_detail("");
+  if (out_total) *out_total = 0;
+  ddm_status r = check_common(t, upd_lo, upd_hi, m);
+  if (r != DDM_OK) return r;
+  if (m > 0 && !counts) {
+    set_detail("counts is NULL");
+    return DDM_E_INVALID_ARG;
+  }
+  MatchPlan P;
+  r = parse_opts(opts, &P);
+  if (r != DDM_OK) return r;
+  hipStream_t s = (hipStream_t)stream;
+  if (m == 0) return tree_n(t) ? ddm_tree_check(t) : DDM_OK;
+  if (tree_n(t) == 0) {
+    zero_u32_kernel<<<(m + 255) / 256, 256, 0, s>>>(counts, m);
+    DDM_LAUNCHED("zero_u32_kernel");
+    return DDM_OK;
+  }
+  MatchState st(s);
+  uint32_t *lists = nullptr, *lists_count = nullptr;
+  r = front_half(t, upd_lo, upd_hi, m, P, st, counts, &lists, &lists_count, s);
+  if (r != DDM_OK) return r;
+  if (out_total) *out_total = st.K;
+  return DDM_OK;
+}

@@ -1,0 +1,396 @@
+// Interval tree construction on the device (Sec. IV, Interval-Tree-Create).
+//
+// The paper builds an augmented AVL tree by insertion.  Here the tree over a
+// static subscription set is flat and implicit: segments sorted by lower
+// bound occupy in-order positions 1..n of a complete binary tree with
+// P = 2^H - 1 >= n positions, where position p has height ctz(p), children
+// p -/+ 2^(h-1) and subtree span [p - 2^h + 1, p + 2^h - 1].  The order is
+// the paper's (lower bound first); equal lower bounds keep subscription id
+// order (stable sort) instead of the upper-bound tie-break, which changes
+// no query result.  Each position stores maxupper of its subtree, computed
+// bottom-up; minlower is the lower bound at the leftmost position of the
+// subtree and needs no storage.  Positions beyond n are padding, recognised
+// by index only.
+#include "ddm_internal.h"
+
+#include <new>
+
+struct ddm_tree {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  uint32_t n = 0, d = 0, H = 0, P = 0;
+  char* block = nullptr;  // one device allocation for everything below
+  float* rec[DDM_MAX_D] = {};
+  float* maxhi[DDM_MAX_D] = {};
+  uint32_t* id[DDM_MAX_D] = {};
+  uint32_t* skey_lo[DDM_MAX_D] = {};
+  uint32_t* skey_hi[DDM_MAX_D] = {};
+  int32_t* flag = nullptr;  // device: nonzero if a coordinate was invalid
+};
+
+namespace ddm {
+
+const TreeDev tree_dev(const ddm_tree* t) {
+  TreeDev T{};
+  for (uint32_t k = 0; k < t->d; ++k) {
+    T.rec[k] = t->rec[k];
+    T.maxhi[k] = t->maxhi[k];
+    T.id[k] = t->id[k];
+    T.skey_lo[k] = t->skey_lo[k];
+    T.skey_hi[k] = t->skey_hi[k];
+  }
+  T.n = t->n;
+  T.d = t->d;
+  T.H = t->H;
+  return T;
+}
+
+const int32_t* tree_flag(const ddm_tree* t) { return t->flag; }
+uint32_t tree_n(const ddm_tree* t) { return t->n; }
+uint32_t tree_d(const ddm_tree* t) { return t->d; }
+int tree_device(const ddm_tree* t) { return t->device; }
+
+// validate, order-preserving keys, identity payload (id arrays shifted by one
+// so that the sorted payload lands directly at positions 1..n)
+__global__ void build_keys_kernel(const float* __restrict__ lo, const float* __restrict__ hi,
+                                  uint32_t n, uint32_t d, uint32_t* __restrict__ klo,
+                                  uint32_t* __restrict__ khi, uint32_t* __restrict__ id_base,
+                                  int32_t* __restrict__ flag) {
+  const uint64_t idx = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const uint64_t total = (uint64_t)n * d;
+  bool bad = false;
+  if (idx < total) {
+    const uint32_t k = (uint32_t)(idx / n);
+    const uint32_t i = (uint32_t)(idx - (uint64_t)k * n);
+    const float a = lo[idx], b = hi[idx];
+    bad = !valid_extent(a, b);
+    klo[idx] = f2key(a);
+    khi[idx] = f2key(b);
+    id_base[(size_t)k * (n + 1) + 1 + i] = i;
+  }
+  if (ballot(bad) != 0 && lane_id() == 0) atomicOr(flag, 1);
+}
+
+constexpr int kChunk = 2048;        // positions per workgroup in a maxhi pass
+constexpr int kChunkLog = 11;
+constexpr int kTreeThreads = 1024;  // two positions per thread
+
+struct TreeBuildArgs {
+  const float* s_lo;
+  const float* s_hi;
+  float* rec[DDM_MAX_D];
+  float* maxhi[DDM_MAX_D];
+  const uint32_t* id[DDM_MAX_D];
+  uint32_t n, d, H, P;
+};
+
+// Pass 0: gather the records of every position in the chunk (one chunk of
+// 2048 consecutive positions per workgroup, dimension blockIdx.y) and compute
+// maxhi for heights 0..10 in LDS.
+__global__ __launch_bounds__(kTreeThreads) void tree_low_kernel(TreeBuildArgs A) {
+  __shared__ float mx[kChunk];
+  const uint32_t k = blockIdx.y;
+  const uint32_t c = blockIdx.x;
+  const uint32_t D = A.d;
+  float* __restrict__ rec = A.rec[k];
+  const uint32_t* __restrict__ ids = A.id[k];
+  for (uint32_t r = threadIdx.x; r < kChunk; r += kTreeThreads) {
+    const uint32_t p = c * kChunk + r;
+    float h = -INFINITY;
+    if (p >= 1 && p <= A.n) {
+      const uint32_t i = ids[p];
+      float* dst = rec + (size_t)p * 2 * D;
+      dst[0] = A.s_lo[(size_t)k * A.n + i];
+      h = A.s_hi[(size_t)k * A.n + i];
+      dst[1] = h;
+      uint32_t slot = 1;
+      for (uint32_t kk = 0; kk < D; ++kk) {
+        if (kk == k) continue;
+        dst[2 * slot] = A.s_lo[(size_t)kk * A.n + i];
+        dst[2 * slot + 1] = A.s_hi[(size_t)kk * A.n + i];
+        ++slot;
+      }
+    }
+    mx[r] = h;
+  }
+  for (int h = 1; h < kChunkLog; ++h) {
+    __syncthreads();
+    for (uint32_t r = threadIdx.x; r < kChunk; r += kTreeThreads) {
+      if (r != 0 && (uint32_t)__builtin_ctz(r) == (uint32_t)h) {
+        const uint32_t half = 1u << (h - 1);
+        mx[r] = fmaxf(mx[r], fmaxf(mx[r - half], mx[r + half]));
+      }
+    }
+  }
+  __syncthreads();
+  for (uint32_t r = threadIdx.x; r < kChunk; r += kTreeThreads) {
+    const uint32_t p = c * kChunk + r;
+    if (r != 0 && p <= A.P) A.maxhi[k][p] = mx[r];
+  }
+}
+
+// Pass s >= 1: positions p = q << S (S = 11 s) with q in this chunk; real
+// heights S .. S+10.  Leaves (odd q) combine the two children of height S-1
+// computed by the previous pass.
+__global__ __launch_bounds__(kTreeThreads) void tree_high_kernel(TreeBuildArgs A, uint32_t S) {
+  __shared__ float mx[kChunk];
+  const uint32_t k = blockIdx.y;
+  const uint32_t c = blockIdx.x;
+  const uint32_t D = A.d;
+  const uint32_t qmax = A.P >> S;
+  const float* __restrict__ rec = A.rec[k];
+  float* __restrict__ maxhi = A.maxhi[k];
+  for (uint32_t r = threadIdx.x; r < kChunk; r += kTreeThreads) {
+    const uint32_t q = c * kChunk + r;
+    float h = -INFINITY;
+    if (r != 0 && q <= qmax) {
+      const uint32_t p = q << S;
+      if (p <= A.n) h = rec[(size_t)p * 2 * D + 1];
+      if (q & 1u) {
+        const uint32_t half = 1u << (S - 1);
+        h = fmaxf(h, fmaxf(maxhi[p - half], maxhi[p + half]));
+      }
+    }
+    mx[r] = h;
+  }
+  for (int h = 1; h < kChunkLog; ++h) {
+    __syncthreads();
+    for (uint32_t r = threadIdx.x; r < kChunk; r += kTreeThreads) {
+      if (r != 0 && (uint32_t)__builtin_ctz(r) == (uint32_t)h) {
+        const uint32_t half = 1u << (h - 1);
+        mx[r] = fmaxf(mx[r], fmaxf(mx[r - half], mx[r + half]));
+      }
+    }
+  }
+  __syncthreads();
+  for (uint32_t r = threadIdx.x; r < kChunk; r += kTreeThreads) {
+    const uint32_t q = c * kChunk + r;
+    if (r != 0 && q <= qmax) maxhi[q << S] = mx[r];
+  }
+}
+
+static size_t al(size_t b) { return (b + 255) & ~size_t(255); }
+
+ddm_status enqueue_tree_build(ddm_tree* t, const float* lo, const float* hi, hipStream_t s) {
+  const uint32_t n = t->n, d = t->d;
+  // scratch: ping-pong key buffers (lo and hi), payload ping-pong, sort tables
+  const uint32_t tiles_per = (n + kSortTile - 1) / kSortTile;
+  const uint32_t narr = 2 * d;
+  const uint32_t ntiles = tiles_per * narr;
+  Scratch sc(s);
+  sc.reserve(sizeof(uint32_t) * (size_t)n * d);  // lo keys tmp
+  sc.reserve(sizeof(uint32_t) * (size_t)n * d);  // hi keys tmp
+  sc.reserve(sizeof(uint32_t) * (size_t)n * d);  // payload tmp
+  sc.reserve(sizeof(SortArr) * narr);
+  sc.reserve(sizeof(uint32_t) * ntiles);
+  sc.reserve(sizeof(uint32_t) * 256 * (size_t)ntiles);
+  if (!sc.commit()) return DDM_E_NOMEM;
+  uint32_t* klo_tmp = sc.take<uint32_t>((size_t)n * d);
+  uint32_t* khi_tmp = sc.take<uint32_t>((size_t)n * d);
+  uint32_t* val_tmp = sc.take<uint32_t>((size_t)n * d);
+  SortArr* arrs = sc.take<SortArr>(narr);
+  uint32_t* tile_map = sc.take<uint32_t>(ntiles);
+  uint32_t* hist = sc.take<uint32_t>(256 * (size_t)ntiles);
+
+  {
+    ProfScope ps("build_keys", s);
+    const uint64_t total = (uint64_t)n * d;
+    build_keys_kernel<<<(unsigned)((total + 255) / 256), 256, 0, s>>>(
+        lo, hi, n, d, t->skey_lo[0], t->skey_hi[0], t->id[0], t->flag);
+    DDM_LAUNCHED("build_keys_kernel");
+  }
+  SortArr host[2 * DDM_MAX_D];
+  for (uint32_t k = 0; k < d; ++k) {
+    SortArr& a = host[2 * k];
+    a.k[0] = t->skey_lo[k];
+    a.k[1] = klo_tmp + (size_t)k * n;
+    a.v[0] = t->id[k] + 1;
+    a.v[1] = val_tmp + (size_t)k * n;
+    a.n = n;
+    a.tile0 = (2 * k) * tiles_per;
+    SortArr& b = host[2 * k + 1];
+    b.k[0] = t->skey_hi[k];
+    b.k[1] = khi_tmp + (size_t)k * n;
+    b.v[0] = nullptr;
+    b.v[1] = nullptr;
+    b.n = n;
+    b.tile0 = (2 * k + 1) * tiles_per;
+  }
+  ddm_status st = sort_setup_small(host, narr, arrs, tile_map, ntiles, s);
+  if (st != DDM_OK) return st;
+  st = radix_sort_batch(arrs, narr, tile_map, ntiles, hist, 0, 4, s);
+  if (st != DDM_OK) return st;
+
+  TreeBuildArgs A{};
+  A.s_lo = lo;
+  A.s_hi = hi;
+  for (uint32_t k = 0; k < d; ++k) {
+    A.rec[k] = t->rec[k];
+    A.maxhi[k] = t->maxhi[k];
+    A.id[k] = t->id[k];
+  }
+  A.n = n;
+  A.d = d;
+  A.H = t->H;
+  A.P = t->P;
+  {
+    ProfScope ps("tree_build", s);
+    dim3 g((t->P + 1 + kChunk - 1) / kChunk, d);
+    tree_low_kernel<<<g, kTreeThreads, 0, s>>>(A);
+    DDM_LAUNCHED("tree_low_kernel");
+    for (uint32_t S = kChunkLog; S < t->H; S += kChunkLog) {
+      const uint32_t q_end = (t->P >> S) + 1;
+      dim3 g2((q_end + kChunk - 1) / kChunk, d);
+      tree_high_kernel<<<g2, kTreeThreads, 0, s>>>(A, S);
+      DDM_LAUNCHED("tree_high_kernel");
+    }
+  }
+  return DDM_OK;
+}
+
+}  // namespace ddm
+
+using namespace ddm;
+
+extern "C" ddm_status ddm_build(const float* sub_lo, const float* sub_hi, uint32_t n, uint32_t d,
+                                void* stream, ddm_tree** out_tree) {
+  set_detail("");
+  if (!out_tree) {
+    set_detail("ddm_build: out_tree is NULL");
+    return DDM_E_INVALID_ARG;
+  }
+  *out_tree = nullptr;
+  if (d < 1 || d > DDM_MAX_D) {
+    set_detail("ddm_build: d must be in [1, DDM_MAX_D]");
+    return DDM_E_INVALID_ARG;
+  }
+  if (n > 0 && (!sub_lo || !sub_hi)) {
+    set_detail("ddm_build: NULL coordinate pointer");
+    return DDM_E_INVALID_ARG;
+  }
+  if (n >= 0x80000000u) {
+    set_detail("ddm_build: n must be below 2^31");
+    return DDM_E_INVALID_ARG;
+  }
+  hipStream_t s = (hipStream_t)stream;
+  ddm_tree* t = new (std::nothrow) ddm_tree();
+  if (!t) return DDM_E_NOMEM;
+  DDM_HIP(hipGetDevice(&t->device));
+  ensure_pool(t->device);
+  t->stream = s;
+  t->n = n;
+  t->d = d;
+  if (n == 0) {
+    *out_tree = t;
+    return DDM_OK;
+  }
+  uint32_t H = 0;
+  while (H < 32 && ((1ull << H) - 1) < n) ++H;
+  t->H = H;
+  t->P = (uint32_t)((1ull << H) - 1);
+  const size_t rec_b = al(sizeof(float) * (size_t)(n + 1) * 2 * d);
+  const size_t mx_b = al(sizeof(float) * ((size_t)t->P + 1));
+  const size_t id_b = al(sizeof(uint32_t) * (size_t)(n + 1) * d);
+  const size_t key_b = al(sizeof(uint32_t) * (size_t)n * d);
+  const size_t total = rec_b * d + mx_b * d + id_b + 2 * key_b + 256;
+  void* blk = nullptr;
+  hipError_t e = hipMallocAsync(&blk, total, s);
+  if (e != hipSuccess || !blk) {
+    (void)hipGetLastError();
+    delete t;
+    set_detail("ddm_build: device allocation failed");
+    return DDM_E_NOMEM;
+  }
+  t->block = (char*)blk;
+  char* p = t->block;
+  for (uint32_t k = 0; k < d; ++k) { t->rec[k] = (float*)p; p += rec_b; }
+  for (uint32_t k = 0; k < d; ++k) { t->maxhi[k] = (float*)p; p += mx_b; }
+  uint32_t* idb = (uint32_t*)p;
+  p += id_b;
+  for (uint32_t k = 0; k < d; ++k) t->id[k] = idb + (size_t)k * (n + 1);
+  uint32_t* klo = (uint32_t*)p;
+  p += key_b;
+  uint32_t* khi = (uint32_t*)p;
+  p += key_b;
+  for (uint32_t k = 0; k < d; ++k) {
+    t->skey_lo[k] = klo + (size_t)k * n;
+    t->skey_hi[k] = khi + (size_t)k * n;
+  }
+  t->flag = (int32_t*)p;
+  e = hipMemsetAsync(t->flag, 0, sizeof(int32_t), s);
+  if (e != hipSuccess) {
+    (void)hipFreeAsync(t->block, s);
+    delete t;
+    return hip_fail(e, "hipMemsetAsync", __FILE__, __LINE__);
+  }
+  ddm_status st = enqueue_tree_build(t, sub_lo, sub_hi, s);
+  if (st != DDM_OK) {
+    (void)hipFreeAsync(t->block, s);
+    delete t;
+    return st;
+  }
+  *out_tree = t;
+  return DDM_OK;
+}
+
+extern "C" void ddm_tree_free(ddm_tree* t) {
+  if (!t) return;
+  if (t->block) {
+    int cur = 0;
+    (void)hipGetDevice(&cur);
+    if (cur != t->device) (void)hipSetDevice(t->device);
+    (void)hipFreeAsync(t->block, t->stream);
+    if (cur != t->device) (void)hipSetDevice(cur);
+  }
+  delete t;
+}
+
+extern "C" ddm_status ddm_tree_check(const ddm_tree* t) {
+  set_detail("");
+  if (!t) return DDM_E_INVALID_ARG;
+  if (t->n == 0) return DDM_OK;
+  int32_t f = 0;
+  DDM_HIP(hipStreamSynchronize(t->stream));
+  DDM_HIP(hipMemcpy(&f, t->flag, sizeof(f), hipMemcpyDeviceToHost));
+  if (f) {
+    set_detail("subscription coordinates: NaN/inf or lo > hi");
+    return DDM_E_INVALID_INPUT;
+  }
+  return DDM_OK;
+}
+
+extern "C" ddm_status ddm_tree_info(const ddm_tree* t, uint32_t* n, uint32_t* d, uint32_t* height) {
+  if (!t) return DDM_E_INVALID_ARG;
+  if (n) *n = t->n;
+  if (d) *d = t->d;
+  if (height) *height = t->H;
+  return DDM_OK;
+}
+
+extern "C" ddm_status ddm_tree_export(const ddm_tree* t, uint32_t k, float* lo, float* hi,
+                                      uint32_t* ids, float* maxhi) {
+  set_detail("");
+  if (!t || k >= t->d) return DDM_E_INVALID_ARG;
+  if (t->n == 0) return DDM_OK;
+  DDM_HIP(hipStreamSynchronize(t->stream));
+  const uint32_t n = t->n, D = t->d;
+  if (lo || hi) {
+    float* recs = (float*)malloc(sizeof(float) * (size_t)(n + 1) * 2 * D);
+    if (!recs) return DDM_E_NOMEM;
+    hipError_t e = hipMemcpy(recs, t->rec[k], sizeof(float) * (size_t)(n + 1) * 2 * D,
+                             hipMemcpyDeviceToHost);
+    if (e != hipSuccess) {
+      free(recs);
+      return hip_fail(e, "hipMemcpy", __FILE__, __LINE__);
+    }
+    for (uint32_t p = 1; p <= n; ++p) {
+      if (lo) lo[p - 1] = recs[(size_t)p * 2 * D];
+      if (hi) hi[p - 1] = recs[(size_t)p * 2 * D + 1];
+    }
+    free(recs);
+  }
+  if (ids) DDM_HIP(hipMemcpy(ids, t->id[k] + 1, sizeof(uint32_t) * n, hipMemcpyDeviceToHost));
+  if (maxhi)
+    DDM_HIP(hipMemcpy(maxhi, t->maxhi[k] + 1, sizeof(float) * t->P, hipMemcpyDeviceToHost));
+  return DDM_OK;
+}
