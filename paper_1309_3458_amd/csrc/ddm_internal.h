@@ -87,14 +87,30 @@ constexpr int kSortTile = kSortThreads * kSortItems;  // 4096 keys per tile
 //   maxhi[k]  P+1 floats, maxhi[k][p] = max upper bound in subtree(p).
 //   id[k]     n+1 uint32, subscription id at position p.
 //   skey_lo[k], skey_hi[k]: n sorted order-preserving keys of lo_k / hi_k.
+//   bmax[k]   C = max(1, (P+1)/64) floats: bmax[k][c] = max upper bound over
+//             positions 64c .. 64c+63 (position 64c and the height-5 subtree
+//             rooted at 64c+32), the tree's augmentation cut at height 5.
+//   maxlen[k] one float >= every (hi - lo) in dimension k.
 struct TreeDev {
   const float* rec[DDM_MAX_D];
   const float* maxhi[DDM_MAX_D];
   const uint32_t* id[DDM_MAX_D];
   const uint32_t* skey_lo[DDM_MAX_D];
   const uint32_t* skey_hi[DDM_MAX_D];
-  uint32_t n, d, H;
+  const float* bmax[DDM_MAX_D];
+  const float* maxlen;
+  // every 64th sorted key: sidx_lo[k][c] = skey_lo[k][64c], c < ns
+  const uint32_t* sidx_lo[DDM_MAX_D];
+  const uint32_t* sidx_hi[DDM_MAX_D];  // d == 1 only (upper bounds sorted)
+  // kQuant quantiles of the sorted lower-bound keys: quant[k][i] =
+  // skey_lo[k][floor(i n / kQuant)]
+  const uint32_t* quant[DDM_MAX_D];
+  uint32_t n, d, H, ns;
 };
+
+constexpr uint32_t kQuant = 4096;
+
+constexpr uint32_t kBlockLog = 6;  // 64 positions per block of bmax
 
 // ---------------------------------------------------------------------------
 // device helpers
@@ -173,6 +189,77 @@ __device__ __forceinline__ uint32_t upper_bound_u32(const uint32_t* __restrict__
     }
   }
   return lo;
+}
+
+// Two-level searches over sorted keys[0..n) with samples idx[c] = keys[64c]
+// (c < ns = ceil(n/64)): a binary search over the samples (small, cache
+// resident) picks one 64-key window, a second one finishes inside it.
+// number of keys <= x
+__device__ __forceinline__ uint32_t upper_bound_2l(const uint32_t* __restrict__ keys,
+                                                   const uint32_t* __restrict__ idx, uint32_t n,
+                                                   uint32_t ns, uint32_t x) {
+  const uint32_t g = upper_bound_u32(idx, ns, x);
+  if (g == 0) return 0;
+  const uint32_t lo = (g - 1) << 6;
+  const uint32_t hi = min(g << 6, n);
+  return lo + 1 + upper_bound_u32(keys + lo + 1, hi - lo - 1, x);
+}
+// number of keys < x
+__device__ __forceinline__ uint32_t lower_bound_2l(const uint32_t* __restrict__ keys,
+                                                   const uint32_t* __restrict__ idx, uint32_t n,
+                                                   uint32_t ns, uint32_t x) {
+  const uint32_t g = lower_bound_u32(idx, ns, x);
+  if (g == 0) return 0;
+  const uint32_t lo = (g - 1) << 6;
+  const uint32_t hi = min(g << 6, n);
+  return lo + 1 + lower_bound_u32(keys + lo + 1, hi - lo - 1, x);
+}
+
+// NS independent two-level counts run in lockstep, so that the loads of the
+// different searches overlap: res[i] = #{keys_i < x_i} (upper[i] false) or
+// #{keys_i <= x_i} (upper[i] true).  Binary lifting with a trip count fixed
+// by ns keeps all searches on the same step.
+template <int NS>
+__device__ __forceinline__ void count_2l(const uint32_t* const (&keys)[NS],
+                                         const uint32_t* const (&idx)[NS],
+                                         const uint32_t (&x)[NS], const bool (&upper)[NS],
+                                         uint32_t n, uint32_t ns, uint32_t (&res)[NS]) {
+  uint32_t g[NS];
+#pragma unroll
+  for (int i = 0; i < NS; ++i) g[i] = 0;
+  uint32_t top = 1;
+  while ((top << 1) <= ns) top <<= 1;
+  for (uint32_t step = top; step > 0; step >>= 1) {
+#pragma unroll
+    for (int i = 0; i < NS; ++i) {
+      const uint32_t c = g[i] + step;
+      if (c <= ns) {
+        const uint32_t v = idx[i][c - 1];
+        if (upper[i] ? (v <= x[i]) : (v < x[i])) g[i] = c;
+      }
+    }
+  }
+  uint32_t lo[NS], w[NS], pos[NS];
+#pragma unroll
+  for (int i = 0; i < NS; ++i) {
+    lo[i] = g[i] ? ((g[i] - 1) << 6) : 0u;
+    const uint32_t hi = g[i] ? min(g[i] << 6, n) : 0u;
+    w[i] = g[i] ? hi - lo[i] - 1 : 0u;
+    pos[i] = 0;
+  }
+#pragma unroll
+  for (uint32_t step = 32; step > 0; step >>= 1) {
+#pragma unroll
+    for (int i = 0; i < NS; ++i) {
+      const uint32_t c = pos[i] + step;
+      if (c <= w[i]) {
+        const uint32_t v = keys[i][lo[i] + c];
+        if (upper[i] ? (v <= x[i]) : (v < x[i])) pos[i] = c;
+      }
+    }
+  }
+#pragma unroll
+  for (int i = 0; i < NS; ++i) res[i] = g[i] ? lo[i] + 1 + pos[i] : 0u;
 }
 
 // ---------------------------------------------------------------------------

@@ -109,48 +109,181 @@ __device__ __forceinline__ uint64_t readlane_u64(uint64_t v, uint32_t lane) {
 }
 
 // --------------------------------------------------------------------------
-// 1. BITS counts, probe dimension, sort keys
+// 1. Probe dimension and update order.
+//
+// d = 1 (bits1_kernel): the BITS identity recalled in Sec. II gives the exact
+// number of closed segments meeting q: c = #{lo <= q.hi} - #{hi < q.lo}
+// (lo <= hi holds for every subscription), which is already the final count.
+//
+// d > 1 (probe_kernel): the probe dimension k* minimises the number of tree
+// positions that can hold a candidate, i.e. positions p with
+// t <= lo_p <= q.hi where t <= q.lo - maxlen (rounded down): a segment that
+// meets q has hi >= q.lo and lo >= hi - maxlen >= t.  The count is estimated
+// from kQuant quantiles of the sorted lower bounds held in LDS; any choice of
+// k* gives the same pairs, only the work differs.
+//
+// Both kernels bucket the update by (k*, position of q.hi in tree k*) and
+// take its rank inside the bucket from the histogram atomic, so the order is
+// a counting sort without a second pass of atomics.
 // --------------------------------------------------------------------------
-template <int D>
-__global__ __launch_bounds__(256) void bits_kernel(TreeDev T, const float* __restrict__ ulo,
-                                                   const float* __restrict__ uhi, uint32_t m,
-                                                   uint32_t* __restrict__ cmin,
-                                                   uint8_t* __restrict__ kstar,
-                                                   uint32_t* __restrict__ qkey,
-                                                   uint32_t* __restrict__ qval,
-                                                   uint32_t* __restrict__ gcount,
-                                                   int32_t* __restrict__ flag) {
+constexpr uint32_t kBucketsPerDim = 8192;
+constexpr uint32_t kBuckets = kBucketsPerDim * DDM_MAX_D;
+
+__global__ __launch_bounds__(256) void bits1_kernel(TreeDev T, const float* __restrict__ ulo,
+                                                    const float* __restrict__ uhi, uint32_t m,
+                                                    uint32_t* __restrict__ cmin,
+                                                    uint8_t* __restrict__ kstar,
+                                                    uint32_t* __restrict__ bucket,
+                                                    uint32_t* __restrict__ rank,
+                                                    uint32_t* __restrict__ bhist,
+                                                    int32_t* __restrict__ flag) {
   const uint32_t j = blockIdx.x * blockDim.x + threadIdx.x;
   const bool act = j < m;
   bool bad = false;
-  uint32_t best = 0xffffffffu, bk = 0;
   if (act) {
+    const float a = ulo[j], b = uhi[j];
+    bad = !valid_extent(a, b);
+    const uint32_t* keys[2] = {T.skey_lo[0], T.skey_hi[0]};
+    const uint32_t* idx[2] = {T.sidx_lo[0], T.sidx_hi[0]};
+    const uint32_t x[2] = {f2key(b), f2key(a)};
+    const bool up[2] = {true, false};
+    uint32_t res[2];
+    count_2l<2>(keys, idx, x, up, T.n, T.ns, res);
+    const uint32_t c = bad ? 0u : res[0] - res[1];
+    const uint32_t ph = bad ? 0u : res[0];
+    cmin[j] = c;
+    kstar[j] = 0;
+    const uint32_t bu = min((uint32_t)(((uint64_t)ph * kBucketsPerDim) / ((uint64_t)T.n + 1)),
+                            kBucketsPerDim - 1u);
+    bucket[j] = bu;
+    rank[j] = atomicAdd(&bhist[bu], 1u);
+  }
+  if (ballot(bad) != 0 && lane_id() == 0) atomicOr(flag, 2);
+}
+
+// number of quantiles <= x (upper) or < x, LDS binary lifting
+__device__ __forceinline__ uint32_t quant_count(const uint32_t* __restrict__ q, uint32_t x,
+                                                bool upper) {
+  uint32_t pos = 0;
+#pragma unroll
+  for (uint32_t step = kQuant; step > 0; step >>= 1) {
+    const uint32_t c = pos + step;
+    if (c <= kQuant) {
+      const uint32_t v = q[c - 1];
+      if (upper ? (v <= x) : (v < x)) pos = c;
+    }
+  }
+  return pos;
+}
+
+template <int D>
+__global__ __launch_bounds__(1024) void probe_kernel(TreeDev T, const float* __restrict__ ulo,
+                                                     const float* __restrict__ uhi, uint32_t m,
+                                                     uint8_t* __restrict__ kstar,
+                                                     uint32_t* __restrict__ bucket,
+                                                     uint32_t* __restrict__ rank,
+                                                     uint32_t* __restrict__ bhist,
+                                                     int32_t* __restrict__ flag) {
+  __shared__ uint32_t sq[D][kQuant];
+#pragma unroll
+  for (int k = 0; k < D; ++k)
+    for (uint32_t i = threadIdx.x; i < kQuant; i += blockDim.x) sq[k][i] = T.quant[k][i];
+  __syncthreads();
+  const uint32_t j = blockIdx.x * blockDim.x + threadIdx.x;
+  const bool act = j < m;
+  bool bad = false;
+  if (act) {
+    uint32_t best = 0xffffffffu, bk = 0, bqa = 0, bx = 0;
 #pragma unroll
     for (int k = 0; k < D; ++k) {
       const float a = ulo[(size_t)k * m + j], b = uhi[(size_t)k * m + j];
       bad = bad || !valid_extent(a, b);
-      const uint32_t c = upper_bound_u32(T.skey_lo[k], T.n, f2key(b)) -
-                         lower_bound_u32(T.skey_hi[k], T.n, f2key(a));
-      if (c < best) {
-        best = c;
+      const uint32_t xh = f2key(b);
+      const uint32_t qa = quant_count(sq[k], xh, true);
+      const uint32_t qb = quant_count(sq[k], f2key(nextafterf(a - T.maxlen[k], -INFINITY)), false);
+      const uint32_t est = qa - min(qa, qb);
+      if (est < best) {
+        best = est;
         bk = (uint32_t)k;
+        bqa = qa;
+        bx = xh;
       }
     }
-    if (bad) {
-      best = 0;
-      bk = 0;
+    // position of q.hi in tree k*, interpolated between its two quantiles
+    float fine;
+    if (bqa == 0) {
+      fine = 0.f;
+    } else if (bqa >= kQuant) {
+      fine = (float)kQuant - 0.5f;
+    } else {
+      uint32_t kl = 0, ku = 0;
+#pragma unroll
+      for (int k = 0; k < D; ++k)
+        if ((uint32_t)k == bk) {
+          kl = sq[k][bqa - 1];
+          ku = sq[k][bqa];
+        }
+      const float fr = ku > kl ? (float)(bx - kl) / (float)(ku - kl) : 0.f;
+      fine = (float)(bqa - 1) + fminf(fr, 0.999f);
     }
-    cmin[j] = best;
+    if (bad) {
+      bk = 0;
+      fine = 0.f;
+    }
     kstar[j] = (uint8_t)bk;
-    qkey[j] = (bk << 30) | (f2key(ulo[(size_t)bk * m + j]) >> 2);
-    qval[j] = j;
+    const uint32_t sub = min((uint32_t)(fine * (float)(kBucketsPerDim / kQuant)),
+                             kBucketsPerDim - 1u);
+    const uint32_t bu = bk * kBucketsPerDim + sub;
+    bucket[j] = bu;
+    rank[j] = atomicAdd(&bhist[bu], 1u);
   }
   if (ballot(bad) != 0 && lane_id() == 0) atomicOr(flag, 2);
+}
+
+// exclusive scan of the bucket counts (one workgroup, through LDS); the
+// number of updates of each probe dimension falls out of group boundaries
+__global__ __launch_bounds__(1024) void bucket_scan_kernel(uint32_t* __restrict__ bhist,
+                                                           uint32_t m,
+                                                           uint32_t* __restrict__ gcount) {
+  constexpr uint32_t per = kBuckets / 1024;
+  __shared__ uint32_t sb[kBuckets];
+  __shared__ uint32_t wsum[1024 / kWave];
+  __shared__ uint32_t gstart[DDM_MAX_D + 1];
+  const uint32_t tid = threadIdx.x, lane = lane_id(), wave = tid / kWave;
+  for (uint32_t i = tid; i < kBuckets; i += 1024) sb[i] = bhist[i];
+  __syncthreads();
+  uint32_t sum = 0;
+  for (uint32_t i = 0; i < per; ++i) sum += sb[tid * per + i];
+  uint32_t inc = sum;
 #pragma unroll
-  for (int k = 0; k < D; ++k) {
-    const uint64_t b = ballot(act && bk == (uint32_t)k);
-    if (b != 0 && lane_id() == 0) atomicAdd(&gcount[k], (uint32_t)__popcll(b));
+  for (int o = 1; o < kWave; o <<= 1) {
+    const uint32_t t2 = __shfl_up(inc, o, kWave);
+    if (lane >= (uint32_t)o) inc += t2;
   }
+  if (lane == kWave - 1) wsum[wave] = inc;
+  __syncthreads();
+  uint32_t before = 0;
+  for (uint32_t w = 0; w < wave; ++w) before += wsum[w];
+  uint32_t run = before + inc - sum;
+  if ((tid * per) % kBucketsPerDim == 0) gstart[(tid * per) / kBucketsPerDim] = run;
+  if (tid == 0) gstart[DDM_MAX_D] = m;
+  for (uint32_t i = 0; i < per; ++i) {
+    const uint32_t v = sb[tid * per + i];
+    sb[tid * per + i] = run;
+    run += v;
+  }
+  __syncthreads();
+  for (uint32_t i = tid; i < kBuckets; i += 1024) bhist[i] = sb[i];
+  if (tid < DDM_MAX_D) gcount[tid] = gstart[tid + 1] - gstart[tid];
+}
+
+__global__ __launch_bounds__(256) void bucket_scatter_kernel(const uint32_t* __restrict__ bucket,
+                                                             const uint32_t* __restrict__ rank,
+                                                             uint32_t m,
+                                                             const uint32_t* __restrict__ bhist,
+                                                             uint32_t* __restrict__ perm) {
+  const uint32_t j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j < m) perm[bhist[bucket[j]] + rank[j]] = j;
 }
 
 // --------------------------------------------------------------------------
@@ -234,22 +367,37 @@ __global__ __launch_bounds__(1024) void lane_kernel(TreeDev T, const float* __re
 }
 
 // --------------------------------------------------------------------------
-// 3/5b. one wavefront per tile of 64 updates (sorted by lower bound in the
-// probe dimension k of their group).
+// 3/5b. one wavefront per tile of 64 updates (same probe dimension k, ordered
+// by bucket).
 //
-// The wave runs the same walk once, with uniform control flow, for the
-// tile's enclosing box E (per dimension: min of lower bounds, max of upper
-// bounds).  Every subscription meeting an update of the tile meets E, so the
-// walk's candidates contain every answer.  Subtrees of height <= 5 (at most
-// 63 positions) are loaded whole, one position per lane; candidates meeting
-// E in every dimension are compacted into an LDS ring with a wavefront
-// ballot and a prefix popcount.  Each time 64 candidates are pending, lane l
-// takes candidate l and the wave tests all updates of the tile against the
-// 64 candidates: one ballot per update gives its hits, and a prefix popcount
-// places them contiguously in the update's segment.
+// The tile's candidates in tree k are confined to positions
+// [Pbeg, Pend] = [min plo, max phi] of its updates.  The wave walks that
+// range block by block (64 positions; the tree's maxupper of position 64c and
+// of the height-5 subtree at 64c+32, i.e. Algorithm 3's pruning test cut at
+// height 5): 64 lanes read 64 block maxima at once and a ballot keeps the
+// blocks whose maxupper reaches the tile's smallest q.lower.  A kept block is
+// read one position per lane; positions meeting the tile's enclosing box in
+// every dimension are compacted into an LDS ring with a ballot and a prefix
+// popcount.  Each time 64 candidates are pending, lane l takes candidate l
+// and the wave tests the tile's updates one after the other against the 64
+// candidates (Algorithm 1, closed, every dimension): the ballot of the test
+// is the update's hits among them, and a prefix popcount places the hits
+// contiguously in the update's own segment.
 // --------------------------------------------------------------------------
 constexpr int kTileWaves = 4;
 constexpr int kRing = 128;
+
+__device__ __forceinline__ uint32_t wave_min_u32(uint32_t v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v = min(v, (uint32_t)__shfl_xor((int)v, o, kWave));
+  return uniform_u32(v);
+}
+
+__device__ __forceinline__ uint32_t wave_max_u32(uint32_t v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v = max(v, (uint32_t)__shfl_xor((int)v, o, kWave));
+  return uniform_u32(v);
+}
 
 template <int D, bool FILL>
 __global__ __launch_bounds__(kTileWaves * kWave) void tile_kernel(
@@ -257,9 +405,10 @@ __global__ __launch_bounds__(kTileWaves * kWave) void tile_kernel(
     const uint32_t* __restrict__ perm, const uint32_t* __restrict__ gcount,
     uint32_t* __restrict__ cnt, const uint64_t* __restrict__ off, uint64_t* __restrict__ out) {
   constexpr int R = 2 * D;
+  constexpr int RV = (R + 3) / 4;
   __shared__ float s_cand[kTileWaves][R][kRing];
   __shared__ uint32_t s_cid[kTileWaves][kRing];
-  __shared__ float s_q[kTileWaves][kWave][R];
+  __shared__ float4 s_q[kTileWaves][kWave][RV];
   const uint32_t wave = threadIdx.x / kWave;
   const uint32_t lane = lane_id();
   const uint32_t tile = blockIdx.x * kTileWaves + wave;
@@ -301,54 +450,96 @@ __global__ __launch_bounds__(kTileWaves * kWave) void tile_kernel(
       qh[s] = -INFINITY;
     }
   }
+  {
+    float qr[4 * RV];
+#pragma unroll
+    for (int s = 0; s < D; ++s) {
+      qr[2 * s] = ql[s];
+      qr[2 * s + 1] = qh[s];
+    }
+#pragma unroll
+    for (int r = R; r < 4 * RV; ++r) qr[r] = 0.f;
+#pragma unroll
+    for (int vv = 0; vv < RV; ++vv)
+      s_q[wave][lane][vv] = make_float4(qr[4 * vv], qr[4 * vv + 1], qr[4 * vv + 2], qr[4 * vv + 3]);
+  }
   float elo[D], ehi[D];
 #pragma unroll
   for (int s = 0; s < D; ++s) {
     elo[s] = wave_min(ql[s]);
     ehi[s] = wave_max(qh[s]);
-    s_q[wave][lane][2 * s] = ql[s];
-    s_q[wave][lane][2 * s + 1] = qh[s];
+  }
+  // candidate positions of the tile in tree k: lower bound in
+  // [t, Ehi] with t <= Elo - maxlen (see the probe kernels)
+  uint32_t Pbeg, Pend;
+  {
+    const uint32_t* keys[2] = {T.skey_lo[k], T.skey_lo[k]};
+    const uint32_t* idx[2] = {T.sidx_lo[k], T.sidx_lo[k]};
+    const uint32_t x[2] = {f2key(ehi[0]), f2key(nextafterf(elo[0] - T.maxlen[k], -INFINITY))};
+    const bool up[2] = {true, false};
+    uint32_t res[2];
+    count_2l<2>(keys, idx, x, up, T.n, T.ns, res);
+    Pend = uniform_u32(res[0]);
+    Pbeg = uniform_u32(res[1] + 1u);
   }
   uint32_t mycnt = 0;
   uint64_t mybase = (FILL && qv) ? off[j] : 0;
   const uint64_t myend = (FILL && qv) ? off[j + 1] : 0;  // segment end (write guard)
   const uint64_t jhi = (uint64_t)j << 32;
+  const uint32_t nq4 = (nq + 3u) & ~3u;
   wave_sync();
 
   const float* __restrict__ rec = T.rec[k];
-  const float* __restrict__ mx = T.maxhi[k];
+  const float* __restrict__ bmx = T.bmax[k];
   const uint32_t* __restrict__ ids = T.id[k];
-  const uint32_t n = T.n;
-
   uint32_t head = 0, tail = 0;
 
   auto flush = [&](uint32_t c) {
     wave_sync();
-    const bool cv = lane < c;
+    const uint64_t cvm = (c >= (uint32_t)kWave) ? ~0ull : ((1ull << c) - 1ull);
     const uint32_t slot = (head + lane) & (kRing - 1);
     float v[R];
 #pragma unroll
     for (int r = 0; r < R; ++r) v[r] = s_cand[wave][r][slot];
     const uint32_t sid = s_cid[wave][slot];
-    for (uint32_t qi = 0; qi < nq; ++qi) {
-      float q[R];
+    for (uint32_t qi = 0; qi < nq4; qi += 4) {
+      uint64_t hm[4];
 #pragma unroll
-      for (int r = 0; r < R; ++r) q[r] = s_q[wave][qi][r];
-      bool hit = cv;
+      for (uint32_t u = 0; u < 4; ++u) {
+        float q[4 * RV];
 #pragma unroll
-      for (int s = 0; s < D; ++s) hit = hit && (v[2 * s] <= q[2 * s + 1]) && (q[2 * s] <= v[2 * s + 1]);
-      const uint64_t hm = ballot(hit);
-      if (hm != 0) {
-        const uint32_t pc = (uint32_t)__popcll(hm);
-        if (FILL) {
-          const uint64_t b = readlane_u64(mybase, qi);
-          const uint64_t e = readlane_u64(myend, qi);
-          const uint64_t jq = readlane_u64(jhi, qi);
-          const uint64_t dst = b + mask_rank(hm);
-          if (hit && dst < e) out[dst] = jq | sid;
-          if (lane == qi) mybase += pc;
-        } else {
-          if (lane == qi) mycnt += pc;
+        for (int vv = 0; vv < RV; ++vv) {
+          const float4 t4 = s_q[wave][qi + u][vv];
+          q[4 * vv] = t4.x;
+          q[4 * vv + 1] = t4.y;
+          q[4 * vv + 2] = t4.z;
+          q[4 * vv + 3] = t4.w;
+        }
+        // one compare per lane mask, combined with scalar ANDs
+        uint64_t h = cvm;
+#pragma unroll
+        for (int s = 0; s < D; ++s) {
+          h &= ballot(v[2 * s] <= q[2 * s + 1]);
+          h &= ballot(q[2 * s] <= v[2 * s + 1]);
+        }
+        hm[u] = h;
+      }
+      if ((hm[0] | hm[1] | hm[2] | hm[3]) != 0) {
+#pragma unroll
+        for (uint32_t u = 0; u < 4; ++u) {
+          if (hm[u] == 0) continue;
+          const uint32_t qq = qi + u;
+          const uint32_t pc = (uint32_t)__popcll(hm[u]);
+          if (FILL) {
+            const uint64_t b = readlane_u64(mybase, qq);
+            const uint64_t e = readlane_u64(myend, qq);
+            const uint64_t jq = readlane_u64(jhi, qq);
+            const uint64_t dst = b + mask_rank(hm[u]);
+            if (((hm[u] >> lane) & 1ull) && dst < e) out[dst] = jq | sid;
+            if (lane == qq) mybase += pc;
+          } else {
+            if (lane == qq) mycnt += pc;
+          }
         }
       }
     }
@@ -356,61 +547,42 @@ __global__ __launch_bounds__(kTileWaves * kWave) void tile_kernel(
     wave_sync();
   };
 
-  auto push_block = [&](uint32_t a, uint32_t b) {
-    // positions a..b (b - a < 64), one per lane
-    const uint32_t p = a + lane;
-    bool cnd = false;
-    float v[R];
-    if (p <= b) {
-      load_rec<D>(rec + (size_t)p * R, v);
-      cnd = true;
+  if (Pbeg <= Pend) {
+    const uint32_t c0 = Pbeg >> kBlockLog, c1 = Pend >> kBlockLog;
+    for (uint32_t cb = c0; cb <= c1; cb += kWave) {
+      const uint32_t c = cb + lane;
+      const bool keep = (c <= c1) && (bmx[c] >= elo[0]);
+      uint64_t bm = ballot(keep);
+      while (bm != 0) {
+        const uint32_t b = (uint32_t)__builtin_ctzll(bm);
+        bm &= bm - 1;
+        const uint32_t blk = cb + b;
+        const uint32_t a = max(blk << kBlockLog, Pbeg);
+        const uint32_t e = min((blk << kBlockLog) + (1u << kBlockLog) - 1u, Pend);
+        // positions a..e, one per lane
+        const uint32_t p = a + lane;
+        bool cnd = false;
+        float v[R];
+        if (p <= e) {
+          load_rec<D>(rec + (size_t)p * R, v);
+          cnd = true;
 #pragma unroll
-      for (int s = 0; s < D; ++s) cnd = cnd && (v[2 * s] <= ehi[s]) && (elo[s] <= v[2 * s + 1]);
-    }
-    const uint64_t bm = ballot(cnd);
-    if (cnd) {
-      const uint32_t slot = (tail + mask_rank(bm)) & (kRing - 1);
+          for (int s = 0; s < D; ++s)
+            cnd = cnd & (v[2 * s] <= ehi[s]) & (elo[s] <= v[2 * s + 1]);
+        }
+        const uint64_t cm = ballot(cnd);
+        if (cnd) {
+          const uint32_t slot = (tail + mask_rank(cm)) & (kRing - 1);
 #pragma unroll
-      for (int r = 0; r < R; ++r) s_cand[wave][r][slot] = v[r];
-      s_cid[wave][slot] = ids[p];
-    }
-    tail += (uint32_t)__popcll(bm);
-  };
-
-  uint32_t x = 1u << (T.H - 1);
-  bool enter = true;
-  while (true) {
-    if (enter) {
-      const uint32_t h = (uint32_t)__builtin_ctz(x);
-      const uint32_t a = x - (1u << h) + 1u;
-      if (a > n) break;
-      if (uniform_f32(rec[(size_t)a * R]) > ehi[0]) break;
-      if (uniform_f32(mx[x]) < elo[0]) {
-        x += 1u << h;
-        enter = false;
-      } else if (h <= 5) {
-        push_block(a, min(x + (1u << h) - 1u, n));
-        x += 1u << h;
-        enter = false;
-        while (tail - head >= (uint32_t)kWave) flush(kWave);
-      } else {
-        x -= 1u << (h - 1);
-      }
-    } else {
-      if (x > n) break;
-      if (uniform_f32(rec[(size_t)x * R]) > ehi[0]) break;
-      push_block(x, x);
-      while (tail - head >= (uint32_t)kWave) flush(kWave);
-      const uint32_t h = (uint32_t)__builtin_ctz(x);
-      if (h == 0) {
-        x += 1u;
-      } else {
-        x += 1u << (h - 1);
-        enter = true;
+          for (int r = 0; r < R; ++r) s_cand[wave][r][slot] = v[r];
+          s_cid[wave][slot] = ids[p];
+        }
+        tail += (uint32_t)__popcll(cm);
+        if (tail - head >= (uint32_t)kWave) flush(kWave);
       }
     }
+    if (tail != head) flush(tail - head);
   }
-  if (tail != head) flush(tail - head);
   if (!FILL && qv) cnt[j] = mycnt;
 }
 
@@ -632,16 +804,6 @@ static ddm_status parse_opts(const ddm_match_opts* o, MatchPlan* p) {
   return DDM_OK;
 }
 
-template <int D>
-static ddm_status launch_bits(const TreeDev& T, const float* ulo, const float* uhi, uint32_t m,
-                              uint32_t* cmin, uint8_t* kstar, uint32_t* qkey, uint32_t* qval,
-                              uint32_t* gcount, int32_t* flag, hipStream_t s) {
-  ProfScope ps("bits", s);
-  bits_kernel<D><<<(m + 255) / 256, 256, 0, s>>>(T, ulo, uhi, m, cmin, kstar, qkey, qval, gcount,
-                                                   flag);
-  DDM_LAUNCHED("bits_kernel");
-  return DDM_OK;
-}
 
 template <int D, bool FILL>
 static ddm_status launch_traverse(const MatchPlan& P, const TreeDev& T, const float* ulo,
@@ -664,19 +826,13 @@ static ddm_status launch_traverse(const MatchPlan& P, const TreeDev& T, const fl
   return DDM_OK;
 }
 
+struct MatchState;
+
 template <bool FILL>
 static ddm_status traverse_any(uint32_t d, const MatchPlan& P, const TreeDev& T,
                                const float* ulo, const float* uhi, uint32_t m,
-                               const uint32_t* perm, const uint8_t* kstar,
-                               const uint32_t* gcount, uint32_t* cnt, const uint64_t* off,
-                               uint64_t* out, hipStream_t s) {
-  switch (d) {
-    case 1: return launch_traverse<1, FILL>(P, T, ulo, uhi, m, perm, kstar, gcount, cnt, off, out, s);
-    case 2: return launch_traverse<2, FILL>(P, T, ulo, uhi, m, perm, kstar, gcount, cnt, off, out, s);
-    case 3: return launch_traverse<3, FILL>(P, T, ulo, uhi, m, perm, kstar, gcount, cnt, off, out, s);
-    default: return launch_traverse<4, FILL>(P, T, ulo, uhi, m, perm, kstar, gcount, cnt, off, out, s);
-  }
-}
+                               const MatchState& st, uint32_t* cnt, const uint64_t* off,
+                               uint64_t* out, hipStream_t s);
 
 // pinned host words for the single device->host read of a match
 // (one small block per host thread, kept for the life of the process)
@@ -699,13 +855,15 @@ static ddm_status host_words(uint64_t** out) {
   return DDM_OK;
 }
 
-// Common front half: validation/BITS, query order, counts, scan, K readback.
+// Common front half: validation/BITS, update order, counts, scan, K readback.
 struct MatchState {
   Scratch sc;
   uint32_t* cmin = nullptr;
   uint8_t* kstar = nullptr;
-  uint32_t* qkey = nullptr;
-  uint32_t* qval = nullptr;
+  uint32_t* rank = nullptr;
+  uint32_t* bucket = nullptr;
+  uint32_t* bhist = nullptr;
+  uint32_t* perm = nullptr;
   uint32_t* gcount = nullptr;
   int32_t* flag = nullptr;
   uint32_t* cnt = nullptr;
@@ -714,11 +872,30 @@ struct MatchState {
   explicit MatchState(hipStream_t s) : sc(s) {}
 };
 
+template <bool FILL>
+static ddm_status traverse_any(uint32_t d, const MatchPlan& P, const TreeDev& T,
+                               const float* ulo, const float* uhi, uint32_t m,
+                               const MatchState& st, uint32_t* cnt, const uint64_t* off,
+                               uint64_t* out, hipStream_t s) {
+#define DDM_TRAV(DD) \
+  launch_traverse<DD, FILL>(P, T, ulo, uhi, m, st.perm, st.kstar, st.gcount, cnt, off, out, s)
+  switch (d) {
+    case 1: return DDM_TRAV(1);
+    case 2: return DDM_TRAV(2);
+    case 3: return DDM_TRAV(3);
+    default: return DDM_TRAV(4);
+  }
+#undef DDM_TRAV
+}
+
 __global__ void match_init_kernel(uint32_t* __restrict__ gcount, int32_t* __restrict__ flag,
-                                  uint32_t* __restrict__ lists_count) {
-  if (threadIdx.x < DDM_MAX_D) gcount[threadIdx.x] = 0;
-  if (threadIdx.x == 0) *flag = 0;
-  if (threadIdx.x < 2) lists_count[threadIdx.x] = 0;
+                                  uint32_t* __restrict__ lists_count,
+                                  uint32_t* __restrict__ bhist) {
+  const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < kBuckets) bhist[i] = 0;
+  if (i < DDM_MAX_D) gcount[i] = 0;
+  if (i == 0) *flag = 0;
+  if (i < 2) lists_count[i] = 0;
 }
 
 __global__ void gather_flags_kernel(const int32_t* __restrict__ tflag,
@@ -731,72 +908,78 @@ __global__ void gather_flags_kernel(const int32_t* __restrict__ tflag,
   }
 }
 
+template <int D>
+static ddm_status launch_probe(const TreeDev& T, const float* ulo, const float* uhi, uint32_t m,
+                               MatchState& st, hipStream_t s) {
+  if (D == 1) {
+    ProfScope ps("bits", s);
+    bits1_kernel<<<(m + 255) / 256, 256, 0, s>>>(T, ulo, uhi, m, st.cmin, st.kstar, st.bucket,
+                                                 st.rank, st.bhist, st.flag);
+    DDM_LAUNCHED("bits1_kernel");
+  } else {
+    ProfScope ps("probe", s);
+    probe_kernel<D><<<(m + 1023) / 1024, 1024, 0, s>>>(T, ulo, uhi, m, st.kstar, st.bucket,
+                                                       st.rank, st.bhist, st.flag);
+    DDM_LAUNCHED("probe_kernel");
+  }
+  return DDM_OK;
+}
+
 static ddm_status front_half(const ddm_tree* t, const float* ulo, const float* uhi, uint32_t m,
                              const MatchPlan& P, MatchState& st, uint32_t* counts_out,
                              uint32_t** lists, uint32_t** lists_count, hipStream_t s) {
   const uint32_t d = tree_d(t);
   const TreeDev T = tree_dev(t);
-  const uint32_t tiles = (m + kSortTile - 1) / kSortTile;
   Scratch& sc = st.sc;
   sc.reserve(sizeof(uint32_t) * m);          // cmin
   sc.reserve(m);                             // kstar
-  sc.reserve(sizeof(uint32_t) * m * 4);      // qkey, qval + ping-pong
+  sc.reserve(sizeof(uint32_t) * m * 3);      // rank, bucket, perm
+  sc.reserve(sizeof(uint32_t) * kBuckets);   // bucket histogram / offsets
   sc.reserve(sizeof(uint32_t) * DDM_MAX_D);  // gcount
   sc.reserve(sizeof(int32_t));               // flag
   sc.reserve(sizeof(uint32_t) * m);          // cnt
   sc.reserve(sizeof(uint64_t) * (m + 1));    // off
   sc.reserve(sizeof(uint64_t) * scan_tmp_words(m));
-  sc.reserve(sizeof(SortArr));
-  sc.reserve(sizeof(uint32_t) * tiles);
-  sc.reserve(sizeof(uint32_t) * 256 * (size_t)tiles);
   sc.reserve(sizeof(uint32_t) * (2 * (size_t)m + 2));  // segment lists + counts
   sc.reserve(sizeof(uint64_t) * 4);                    // device words for readback
   if (!sc.commit()) return DDM_E_NOMEM;
   st.cmin = sc.take<uint32_t>(m);
   st.kstar = sc.take<uint8_t>(m);
-  st.qkey = sc.take<uint32_t>(m);
-  st.qval = sc.take<uint32_t>(m);
-  uint32_t* qkey2 = sc.take<uint32_t>(m);
-  uint32_t* qval2 = sc.take<uint32_t>(m);
+  st.rank = sc.take<uint32_t>(m);
+  st.bucket = sc.take<uint32_t>(m);
+  st.perm = sc.take<uint32_t>(m);
+  st.bhist = sc.take<uint32_t>(kBuckets);
   st.gcount = sc.take<uint32_t>(DDM_MAX_D);
   st.flag = sc.take<int32_t>(1);
   st.cnt = sc.take<uint32_t>(m);
   st.off = sc.take<uint64_t>(m + 1);
   uint64_t* stmp = sc.take<uint64_t>(scan_tmp_words(m));
-  SortArr* arr = sc.take<SortArr>(1);
-  uint32_t* tile_map = sc.take<uint32_t>(tiles);
-  uint32_t* hist = sc.take<uint32_t>(256 * (size_t)tiles);
   *lists = sc.take<uint32_t>(2 * (size_t)m);
   *lists_count = sc.take<uint32_t>(2);
   uint64_t* dwords = sc.take<uint64_t>(4);
 
-  match_init_kernel<<<1, 64, 0, s>>>(st.gcount, st.flag, *lists_count);
+  match_init_kernel<<<kBuckets / 256, 256, 0, s>>>(st.gcount, st.flag, *lists_count, st.bhist);
   DDM_LAUNCHED("match_init_kernel");
   ddm_status r;
   switch (d) {
-    case 1: r = launch_bits<1>(T, ulo, uhi, m, st.cmin, st.kstar, st.qkey, st.qval, st.gcount, st.flag, s); break;
-    case 2: r = launch_bits<2>(T, ulo, uhi, m, st.cmin, st.kstar, st.qkey, st.qval, st.gcount, st.flag, s); break;
-    case 3: r = launch_bits<3>(T, ulo, uhi, m, st.cmin, st.kstar, st.qkey, st.qval, st.gcount, st.flag, s); break;
-    default: r = launch_bits<4>(T, ulo, uhi, m, st.cmin, st.kstar, st.qkey, st.qval, st.gcount, st.flag, s); break;
+    case 1: r = launch_probe<1>(T, ulo, uhi, m, st, s); break;
+    case 2: r = launch_probe<2>(T, ulo, uhi, m, st, s); break;
+    case 3: r = launch_probe<3>(T, ulo, uhi, m, st, s); break;
+    default: r = launch_probe<4>(T, ulo, uhi, m, st, s); break;
   }
   if (r != DDM_OK) return r;
-  // update order for the traversal (payload = update id)
-  SortArr a{};
-  a.k[0] = st.qkey;
-  a.k[1] = qkey2;
-  a.v[0] = st.qval;
-  a.v[1] = qval2;
-  a.n = m;
-  a.tile0 = 0;
-  r = sort_setup_small(&a, 1, arr, tile_map, tiles, s);
-  if (r != DDM_OK) return r;
-  r = radix_sort_batch(arr, 1, tile_map, tiles, hist, 0, 4, s);
-  if (r != DDM_OK) return r;
+  {
+    ProfScope ps("order", s);
+    bucket_scan_kernel<<<1, 1024, 0, s>>>(st.bhist, m, st.gcount);
+    DDM_LAUNCHED("bucket_scan_kernel");
+    bucket_scatter_kernel<<<(m + 255) / 256, 256, 0, s>>>(st.bucket, st.rank, m, st.bhist,
+                                                          st.perm);
+    DDM_LAUNCHED("bucket_scatter_kernel");
+  }
   // per-update counts
   const uint32_t* counts = st.cmin;
   if (d > 1) {
-    r = traverse_any<false>(d, P, T, ulo, uhi, m, st.qval, st.kstar, st.gcount, st.cnt, nullptr,
-                            nullptr, s);
+    r = traverse_any<false>(d, P, T, ulo, uhi, m, st, st.cnt, nullptr, nullptr, s);
     if (r != DDM_OK) return r;
     counts = st.cnt;
   }
@@ -937,8 +1120,8 @@ extern "C" ddm_status ddm_match_finish(ddm_pending* pd, uint64_t* out_pairs, uin
     r = DDM_E_INVALID_ARG;
   } else if (pd->st.K > 0) {
     const TreeDev T = tree_dev(pd->t);
-    r = traverse_any<true>(tree_d(pd->t), pd->plan, T, pd->ulo, pd->uhi, pd->m, pd->st.qval,
-                           pd->st.kstar, pd->st.gcount, nullptr, pd->st.off, out_pairs, pd->s);
+    r = traverse_any<true>(tree_d(pd->t), pd->plan, T, pd->ulo, pd->uhi, pd->m, pd->st,
+                           nullptr, pd->st.off, out_pairs, pd->s);
     if (r == DDM_OK)
       r = sort_segments(pd->st.off, pd->m, out_pairs, pd->st.K, tree_n(pd->t), pd->lists,
                         pd->lists_count, pd->s);

@@ -40,31 +40,56 @@ __global__ __launch_bounds__(kSortThreads) void rs_hist_kernel(const SortArr* __
 }
 
 // One workgroup per array: exclusive offsets of digit b in tile lt equal
-// (all keys of smaller digits) + (keys of digit b in earlier tiles).
-__global__ __launch_bounds__(256) void rs_scan_kernel(const SortArr* __restrict__ arrs,
-                                                      uint32_t* __restrict__ hist) {
-  __shared__ uint32_t tot[256];
+// (all keys of smaller digits) + (keys of digit b in earlier tiles).  The
+// 1024 threads are 256 digits x 4 quarters of the array's tiles.
+constexpr int kScanQ = 4;
+
+__global__ __launch_bounds__(256 * kScanQ) void rs_scan_kernel(const SortArr* __restrict__ arrs,
+                                                               uint32_t* __restrict__ hist) {
+  __shared__ uint32_t part[kScanQ][256];
+  __shared__ uint32_t base[256];
+  __shared__ uint32_t wtot[256 / kWave];
   const SortArr A = arrs[blockIdx.x];
-  const uint32_t b = threadIdx.x;
+  const uint32_t tid = threadIdx.x;
+  const uint32_t b = tid & 255u, q = tid >> 8;
   const uint32_t T = (A.n + kSortTile - 1) / kSortTile;
-  uint32_t run = 0;
-  for (uint32_t lt = 0; lt < T; ++lt) {
-    const size_t idx = (size_t)(A.tile0 + lt) * 256 + b;
-    const uint32_t v = hist[idx];
-    hist[idx] = run;
+  const uint32_t lt0 = (uint32_t)(((uint64_t)T * q) / kScanQ);
+  const uint32_t lt1 = (uint32_t)(((uint64_t)T * (q + 1)) / kScanQ);
+  uint32_t* __restrict__ h = hist + (size_t)A.tile0 * 256 + b;
+  uint32_t sum = 0;
+#pragma unroll 8
+  for (uint32_t lt = lt0; lt < lt1; ++lt) sum += h[(size_t)lt * 256];
+  part[q][b] = sum;
+  __syncthreads();
+  uint32_t excl = 0;
+  if (q == 0) {
+    uint32_t tot = 0;
+#pragma unroll
+    for (int qq = 0; qq < kScanQ; ++qq) tot += part[qq][b];
+    const uint32_t lane = lane_id();
+    uint32_t inc = tot;
+#pragma unroll
+    for (int o = 1; o < kWave; o <<= 1) {
+      const uint32_t t2 = __shfl_up(inc, o, kWave);
+      if (lane >= (uint32_t)o) inc += t2;
+    }
+    if (lane == kWave - 1) wtot[b / kWave] = inc;
+    excl = inc - tot;
+  }
+  __syncthreads();
+  if (q == 0) {
+    for (uint32_t w = 0; w < b / kWave; ++w) excl += wtot[w];
+    base[b] = excl;
+  }
+  __syncthreads();
+  uint32_t run = base[b];
+  for (uint32_t qq = 0; qq < q; ++qq) run += part[qq][b];
+#pragma unroll 8
+  for (uint32_t lt = lt0; lt < lt1; ++lt) {
+    const uint32_t v = h[(size_t)lt * 256];
+    h[(size_t)lt * 256] = run;
     run += v;
   }
-  tot[b] = run;
-  __syncthreads();
-  // exclusive scan of 256 totals (Hillis-Steele in LDS)
-  for (uint32_t off = 1; off < 256; off <<= 1) {
-    uint32_t v = (b >= off) ? tot[b - off] : 0u;
-    __syncthreads();
-    tot[b] += v;
-    __syncthreads();
-  }
-  const uint32_t excl = tot[b] - run;
-  for (uint32_t lt = 0; lt < T; ++lt) hist[(size_t)(A.tile0 + lt) * 256 + b] += excl;
 }
 
 __global__ __launch_bounds__(kSortThreads) void rs_scatter_kernel(const SortArr* __restrict__ arrs,
@@ -127,7 +152,7 @@ ddm_status radix_sort_batch(const SortArr* arrs_dev, uint32_t narr, const uint32
     }
     {
       ProfScope ps("radix_scan", s);
-      rs_scan_kernel<<<narr, 256, 0, s>>>(arrs_dev, hist);
+      rs_scan_kernel<<<narr, 256 * kScanQ, 0, s>>>(arrs_dev, hist);
       DDM_LAUNCHED("rs_scan_kernel");
     }
     {

@@ -13,6 +13,7 @@
 // by index only.
 #include "ddm_internal.h"
 
+#include <algorithm>
 #include <new>
 
 struct ddm_tree {
@@ -25,12 +26,19 @@ struct ddm_tree {
   uint32_t* id[DDM_MAX_D] = {};
   uint32_t* skey_lo[DDM_MAX_D] = {};
   uint32_t* skey_hi[DDM_MAX_D] = {};
+  float* bmax[DDM_MAX_D] = {};
+  uint32_t* sidx_lo[DDM_MAX_D] = {};
+  uint32_t* sidx_hi[DDM_MAX_D] = {};
+  uint32_t* quant[DDM_MAX_D] = {};
+  uint32_t ns = 0;              // ceil(n / 64) search samples
+  uint32_t C = 0;               // blocks of 64 positions
+  float* maxlen = nullptr;      // d floats (device)
   int32_t* flag = nullptr;  // device: nonzero if a coordinate was invalid
 };
 
 namespace ddm {
 
-const TreeDev tree_dev(const ddm_tree* t) {
+TreeDev tree_dev(const ddm_tree* t) {
   TreeDev T{};
   for (uint32_t k = 0; k < t->d; ++k) {
     T.rec[k] = t->rec[k];
@@ -38,7 +46,13 @@ const TreeDev tree_dev(const ddm_tree* t) {
     T.id[k] = t->id[k];
     T.skey_lo[k] = t->skey_lo[k];
     T.skey_hi[k] = t->skey_hi[k];
+    T.bmax[k] = t->bmax[k];
+    T.sidx_lo[k] = t->sidx_lo[k];
+    T.sidx_hi[k] = t->sidx_hi[k];
+    T.quant[k] = t->quant[k];
   }
+  T.ns = t->ns;
+  T.maxlen = t->maxlen;
   T.n = t->n;
   T.d = t->d;
   T.H = t->H;
@@ -65,10 +79,31 @@ __global__ void build_keys_kernel(const float* __restrict__ lo, const float* __r
     const float a = lo[idx], b = hi[idx];
     bad = !valid_extent(a, b);
     klo[idx] = f2key(a);
-    khi[idx] = f2key(b);
+    if (khi) khi[idx] = f2key(b);
     id_base[(size_t)k * (n + 1) + 1 + i] = i;
   }
   if (ballot(bad) != 0 && lane_id() == 0) atomicOr(flag, 1);
+}
+
+// samples of the sorted keys for two-level searches, and quantiles
+__global__ void build_index_kernel(const uint32_t* __restrict__ klo,
+                                   const uint32_t* __restrict__ khi, uint32_t n, uint32_t ns,
+                                   uint32_t d, uint32_t* __restrict__ ilo,
+                                   uint32_t* __restrict__ ihi, uint32_t* __restrict__ quant) {
+  const uint32_t c = blockIdx.x * blockDim.x + threadIdx.x;
+  const uint32_t k = blockIdx.y;
+  if (c < ns) {
+    ilo[(size_t)k * ns + c] = klo[(size_t)k * n + ((size_t)c << 6)];
+    if (khi) ihi[(size_t)k * ns + c] = khi[(size_t)k * n + ((size_t)c << 6)];
+  }
+  if (c < kQuant)
+    quant[(size_t)k * kQuant + c] = klo[(size_t)k * n + (uint32_t)(((uint64_t)c * n) / kQuant)];
+}
+
+__global__ void tree_init_kernel(int32_t* __restrict__ flag, uint32_t* __restrict__ maxlen_bits,
+                                 uint32_t d) {
+  if (threadIdx.x == 0) *flag = 0;
+  if (threadIdx.x < d) maxlen_bits[threadIdx.x] = 0;
 }
 
 constexpr int kChunk = 2048;        // positions per workgroup in a maxhi pass
@@ -80,6 +115,9 @@ struct TreeBuildArgs {
   const float* s_hi;
   float* rec[DDM_MAX_D];
   float* maxhi[DDM_MAX_D];
+  float* bmax[DDM_MAX_D];
+  uint32_t* maxlen_bits;
+  uint32_t C;
   const uint32_t* id[DDM_MAX_D];
   uint32_t n, d, H, P;
 };
@@ -89,20 +127,27 @@ struct TreeBuildArgs {
 // maxhi for heights 0..10 in LDS.
 __global__ __launch_bounds__(kTreeThreads) void tree_low_kernel(TreeBuildArgs A) {
   __shared__ float mx[kChunk];
+  __shared__ uint32_t wlen[kTreeThreads / kWave];
   const uint32_t k = blockIdx.y;
   const uint32_t c = blockIdx.x;
   const uint32_t D = A.d;
   float* __restrict__ rec = A.rec[k];
   const uint32_t* __restrict__ ids = A.id[k];
+  // bound of the segment lengths in dimension k: the float difference rounded
+  // to nearest, moved one float up, is >= the exact difference; lengths are
+  // >= 0, so their float bits order like unsigned integers
+  uint32_t lenb = 0;
   for (uint32_t r = threadIdx.x; r < kChunk; r += kTreeThreads) {
     const uint32_t p = c * kChunk + r;
     float h = -INFINITY;
     if (p >= 1 && p <= A.n) {
       const uint32_t i = ids[p];
       float* dst = rec + (size_t)p * 2 * D;
-      dst[0] = A.s_lo[(size_t)k * A.n + i];
+      const float l0 = A.s_lo[(size_t)k * A.n + i];
+      dst[0] = l0;
       h = A.s_hi[(size_t)k * A.n + i];
       dst[1] = h;
+      if (valid_extent(l0, h)) lenb = max(lenb, __float_as_uint(nextafterf(h - l0, INFINITY)));
       uint32_t slot = 1;
       for (uint32_t kk = 0; kk < D; ++kk) {
         if (kk == k) continue;
@@ -113,8 +158,26 @@ __global__ __launch_bounds__(kTreeThreads) void tree_low_kernel(TreeBuildArgs A)
     }
     mx[r] = h;
   }
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) lenb = max(lenb, (uint32_t)__shfl_xor((int)lenb, o, kWave));
+  if (lane_id() == 0) wlen[threadIdx.x / kWave] = lenb;
   for (int h = 1; h < kChunkLog; ++h) {
     __syncthreads();
+    if (h == 1 && threadIdx.x == 0) {
+      uint32_t v = 0;
+      for (int w = 0; w < kTreeThreads / kWave; ++w) v = max(v, wlen[w]);
+      if (v) atomicMax(&A.maxlen_bits[k], v);
+    }
+    if (h == (int)kBlockLog) {
+      // heights < 6 are final and heights >= 6 still hold their own upper
+      // bound: block b of the chunk is position 64b plus subtree(64b + 32)
+      if (threadIdx.x < kChunk / 64) {
+        const uint32_t b = threadIdx.x;
+        const uint32_t blk = c * (kChunk / 64) + b;
+        if (blk < A.C) A.bmax[k][blk] = fmaxf(mx[64 * b], mx[64 * b + 32]);
+      }
+      __syncthreads();
+    }
     for (uint32_t r = threadIdx.x; r < kChunk; r += kTreeThreads) {
       if (r != 0 && (uint32_t)__builtin_ctz(r) == (uint32_t)h) {
         const uint32_t half = 1u << (h - 1);
@@ -174,8 +237,11 @@ static size_t al(size_t b) { return (b + 255) & ~size_t(255); }
 ddm_status enqueue_tree_build(ddm_tree* t, const float* lo, const float* hi, hipStream_t s) {
   const uint32_t n = t->n, d = t->d;
   // scratch: ping-pong key buffers (lo and hi), payload ping-pong, sort tables
+  // upper bounds are sorted only for d == 1, where the BITS counts are the
+  // final counts; for d > 1 the probe dimension comes from lower bounds only
+  const bool sort_hi = d == 1;
   const uint32_t tiles_per = (n + kSortTile - 1) / kSortTile;
-  const uint32_t narr = 2 * d;
+  const uint32_t narr = sort_hi ? 2 * d : d;
   const uint32_t ntiles = tiles_per * narr;
   Scratch sc(s);
   sc.reserve(sizeof(uint32_t) * (size_t)n * d);  // lo keys tmp
@@ -196,30 +262,40 @@ ddm_status enqueue_tree_build(ddm_tree* t, const float* lo, const float* hi, hip
     ProfScope ps("build_keys", s);
     const uint64_t total = (uint64_t)n * d;
     build_keys_kernel<<<(unsigned)((total + 255) / 256), 256, 0, s>>>(
-        lo, hi, n, d, t->skey_lo[0], t->skey_hi[0], t->id[0], t->flag);
+        lo, hi, n, d, t->skey_lo[0], sort_hi ? t->skey_hi[0] : nullptr, t->id[0], t->flag);
     DDM_LAUNCHED("build_keys_kernel");
   }
   SortArr host[2 * DDM_MAX_D];
+  uint32_t na = 0;
   for (uint32_t k = 0; k < d; ++k) {
-    SortArr& a = host[2 * k];
+    SortArr& a = host[na];
     a.k[0] = t->skey_lo[k];
     a.k[1] = klo_tmp + (size_t)k * n;
     a.v[0] = t->id[k] + 1;
     a.v[1] = val_tmp + (size_t)k * n;
     a.n = n;
-    a.tile0 = (2 * k) * tiles_per;
-    SortArr& b = host[2 * k + 1];
+    a.tile0 = na * tiles_per;
+    ++na;
+    if (!sort_hi) continue;
+    SortArr& b = host[na];
     b.k[0] = t->skey_hi[k];
     b.k[1] = khi_tmp + (size_t)k * n;
     b.v[0] = nullptr;
     b.v[1] = nullptr;
     b.n = n;
-    b.tile0 = (2 * k + 1) * tiles_per;
+    b.tile0 = na * tiles_per;
+    ++na;
   }
   ddm_status st = sort_setup_small(host, narr, arrs, tile_map, ntiles, s);
   if (st != DDM_OK) return st;
   st = radix_sort_batch(arrs, narr, tile_map, ntiles, hist, 0, 4, s);
   if (st != DDM_OK) return st;
+  {
+    dim3 g((std::max(t->ns, kQuant) + 255) / 256, d);
+    build_index_kernel<<<g, 256, 0, s>>>(t->skey_lo[0], sort_hi ? t->skey_hi[0] : nullptr, n,
+                                         t->ns, d, t->sidx_lo[0], t->sidx_hi[0], t->quant[0]);
+    DDM_LAUNCHED("build_index_kernel");
+  }
 
   TreeBuildArgs A{};
   A.s_lo = lo;
@@ -228,7 +304,10 @@ ddm_status enqueue_tree_build(ddm_tree* t, const float* lo, const float* hi, hip
     A.rec[k] = t->rec[k];
     A.maxhi[k] = t->maxhi[k];
     A.id[k] = t->id[k];
+    A.bmax[k] = t->bmax[k];
   }
+  A.C = t->C;
+  A.maxlen_bits = (uint32_t*)t->maxlen;
   A.n = n;
   A.d = d;
   A.H = t->H;
@@ -268,8 +347,8 @@ extern "C" ddm_status ddm_build(const float* sub_lo, const float* sub_hi, uint32
     set_detail("ddm_build: NULL coordinate pointer");
     return DDM_E_INVALID_ARG;
   }
-  if (n >= 0x80000000u) {
-    set_detail("ddm_build: n must be below 2^31");
+  if (n >= 0x40000000u) {
+    set_detail("ddm_build: n must be below 2^30");
     return DDM_E_INVALID_ARG;
   }
   hipStream_t s = (hipStream_t)stream;
@@ -292,7 +371,13 @@ extern "C" ddm_status ddm_build(const float* sub_lo, const float* sub_hi, uint32
   const size_t mx_b = al(sizeof(float) * ((size_t)t->P + 1));
   const size_t id_b = al(sizeof(uint32_t) * (size_t)(n + 1) * d);
   const size_t key_b = al(sizeof(uint32_t) * (size_t)n * d);
-  const size_t total = rec_b * d + mx_b * d + id_b + 2 * key_b + 256;
+  t->C = std::max<uint32_t>(1u, (uint32_t)(((uint64_t)t->P + 1) >> kBlockLog));
+  const size_t bm_b = al(sizeof(float) * t->C);
+  t->ns = (n + 63) / 64;
+  const size_t si_b = al(sizeof(uint32_t) * (size_t)t->ns * d);
+  const size_t qu_b = al(sizeof(uint32_t) * kQuant * d);
+  const size_t total =
+      rec_b * d + mx_b * d + id_b + 2 * key_b + bm_b * d + 2 * si_b + qu_b + 256 + 256;
   void* blk = nullptr;
   hipError_t e = hipMallocAsync(&blk, total, s);
   if (e != hipSuccess || !blk) {
@@ -316,12 +401,29 @@ extern "C" ddm_status ddm_build(const float* sub_lo, const float* sub_hi, uint32
     t->skey_lo[k] = klo + (size_t)k * n;
     t->skey_hi[k] = khi + (size_t)k * n;
   }
+  for (uint32_t k = 0; k < d; ++k) { t->bmax[k] = (float*)p; p += bm_b; }
+  {
+    uint32_t* ilo = (uint32_t*)p;
+    p += si_b;
+    uint32_t* ihi = (uint32_t*)p;
+    p += si_b;
+    for (uint32_t k = 0; k < d; ++k) {
+      t->sidx_lo[k] = ilo + (size_t)k * t->ns;
+      t->sidx_hi[k] = ihi + (size_t)k * t->ns;
+    }
+    uint32_t* qu = (uint32_t*)p;
+    p += qu_b;
+    for (uint32_t k = 0; k < d; ++k) t->quant[k] = qu + (size_t)k * kQuant;
+  }
+  t->maxlen = (float*)p;
+  p += 256;
   t->flag = (int32_t*)p;
-  e = hipMemsetAsync(t->flag, 0, sizeof(int32_t), s);
+  tree_init_kernel<<<1, 64, 0, s>>>(t->flag, (uint32_t*)t->maxlen, d);
+  e = hipGetLastError();
   if (e != hipSuccess) {
     (void)hipFreeAsync(t->block, s);
     delete t;
-    return hip_fail(e, "hipMemsetAsync", __FILE__, __LINE__);
+    return hip_fail(e, "tree_init_kernel", __FILE__, __LINE__);
   }
   ddm_status st = enqueue_tree_build(t, sub_lo, sub_hi, s);
   if (st != DDM_OK) {
