@@ -77,8 +77,8 @@ struct SortArr {
 };
 
 constexpr int kSortThreads = 256;
-constexpr int kSortItems = 16;
-constexpr int kSortTile = kSortThreads * kSortItems;  // 4096 keys per tile
+constexpr int kSortItems = 8;
+constexpr int kSortTile = kSortThreads * kSortItems;  // 2048 keys per tile
 
 // Per-dimension flat interval tree (positions 1..P, P = 2^H - 1 >= n).
 //   rec[k]    (n+1) records of 2d floats; record p (1 <= p <= n) holds the

@@ -20,18 +20,25 @@ __global__ __launch_bounds__(kSortThreads) void rs_hist_kernel(const SortArr* __
   const uint32_t t = blockIdx.x;
   const uint32_t tid = threadIdx.x;
   h[tid] = 0;
-  __syncthreads();
   const SortArr A = arrs[tile_map[t]];
   const uint32_t lt = t - A.tile0;
   const uint32_t* __restrict__ src = A.k[pass & 1];
   const uint32_t base = lt * kSortTile;
   const uint32_t end = min(A.n, base + kSortTile);
   const int shift = pass * 8;
-  for (uint32_t r = 0; r < kSortItems; ++r) {
+  // all loads first, so the tile costs one memory latency
+  uint32_t key[kSortItems];
+#pragma unroll
+  for (int r = 0; r < kSortItems; ++r) {
     const uint32_t i = base + r * kSortThreads + tid;
-    if (base + r * kSortThreads >= end) break;
+    key[r] = (i < end) ? src[i] : 0u;
+  }
+  __syncthreads();
+#pragma unroll
+  for (int r = 0; r < kSortItems; ++r) {
+    const uint32_t i = base + r * kSortThreads + tid;
     const bool valid = i < end;
-    const uint32_t dig = valid ? (src[i] >> shift) & 255u : 0u;
+    const uint32_t dig = (key[r] >> shift) & 255u;
     const uint64_t peers = match_digit8(dig, ballot(valid));
     if (valid && mask_rank(peers) == 0) atomicAdd(&h[dig], (uint32_t)__popcll(peers));
   }
@@ -111,13 +118,20 @@ __global__ __launch_bounds__(kSortThreads) void rs_scatter_kernel(const SortArr*
   const uint32_t end = min(A.n, base + kSortTile);
   const int shift = pass * 8;
   doff[tid] = hist[(size_t)t * 256 + tid];
-  for (uint32_t r = 0; r < kSortItems; ++r) {
+  uint32_t key[kSortItems], val[kSortItems];
+#pragma unroll
+  for (int r = 0; r < kSortItems; ++r) {
+    const uint32_t i = base + r * kSortThreads + tid;
+    const bool valid = i < end;
+    key[r] = valid ? ks[i] : 0u;
+    val[r] = (valid && vs) ? vs[i] : 0u;
+  }
+#pragma unroll
+  for (int r = 0; r < kSortItems; ++r) {
     if (base + r * kSortThreads >= end) break;
     const uint32_t i = base + r * kSortThreads + tid;
     const bool valid = i < end;
-    const uint32_t key = valid ? ks[i] : 0u;
-    const uint32_t val = (valid && vs) ? vs[i] : 0u;
-    const uint32_t dig = (key >> shift) & 255u;
+    const uint32_t dig = (key[r] >> shift) & 255u;
 #pragma unroll
     for (int w = 0; w < kSortThreads / kWave; ++w) wc[w][tid] = 0;
     __syncthreads();
@@ -128,15 +142,14 @@ __global__ __launch_bounds__(kSortThreads) void rs_scatter_kernel(const SortArr*
     if (valid) {
       uint32_t pos = doff[dig] + rank;
       for (uint32_t w = 0; w < wave; ++w) pos += wc[w][dig];
-      kd[pos] = key;
-      if (vd) vd[pos] = val;
+      kd[pos] = key[r];
+      if (vd) vd[pos] = val[r];
     }
     __syncthreads();
     uint32_t add = 0;
 #pragma unroll
     for (int w = 0; w < kSortThreads / kWave; ++w) add += wc[w][tid];
     doff[tid] += add;
-    __syncthreads();
   }
 }
 
