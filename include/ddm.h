@@ -148,6 +148,97 @@ ddm_status ddm_match_begin(const ddm_tree* t, const float* upd_lo, const float* 
 ddm_status ddm_match_finish(ddm_pending* pending, uint64_t* out_pairs, uint64_t capacity);
 void ddm_match_abort(ddm_pending* pending);
 
+/* ------------------------------------------------------------------------
+ * Learned output sizing (an addition to the paper's method).
+ *
+ * A small MLP (DDM_FEATURES = 18 inputs -> 64 -> 64 -> 1, ReLU, FP32)
+ * predicts y = log1p(number of subscriptions an update meets).  The single-
+ * pass matcher gives update j ceil(expm1(yhat_j + delta)) output slots, runs
+ * ONE traversal that writes hits into the slots while counting every hit
+ * exactly, and sends the updates whose hits exceeded their slots through the
+ * plain fill afterwards.  The pairs are exactly those of ddm_match, byte for
+ * byte, whatever the network predicts; only the work changes.
+ *
+ * Parameter layout (DDM_PREDICTOR_PARAMS = 5441 floats, row-major W[out][in]):
+ *   W1[64][18], b1[64], W2[64][64], b2[64], w3[64], b3.
+ *
+ * Features of update j (dimension k < 3, zero for k >= d), with mn_k, W_k
+ * the smallest lower bound and the width (largest upper - smallest lower) of
+ * the subscriptions in dimension k, and c_k an estimate of how many
+ * subscriptions meet j in dimension k from 64-bin prefix histograms of the
+ * subscription lower and upper bounds (linear inside a bin):
+ *   x[5k+0] = (hi - lo) / W_k          x[5k+1] = ((lo + hi)/2 - mn_k) / W_k
+ *   x[5k+2] = c_k / n                  x[5k+3] = log1p(c_k) / 16
+ *   x[5k+4] = mean subscription length in k / W_k
+ *   x[15] = log2(n) / 20   x[16] = d / 3   x[17] = log1p(e) / 16,
+ * where e estimates how many subscriptions have their lower corner in the
+ * box prod_k [lo_k - l_k, hi_k] (l_k = mean subscription length in k), from
+ * a grid over the subscriptions' bounding box (256, 64x64 or 16x16x16 cells
+ * for d = 1, 2, 3) that counts lower corners per cell, corners taken as
+ * spread evenly inside a cell.
+ * ---------------------------------------------------------------------- */
+#define DDM_FEATURES 18
+#define DDM_PREDICTOR_PARAMS 5441
+
+typedef struct ddm_predictor ddm_predictor;
+
+/* New predictor on the current device; weights and biases of each layer
+ * drawn uniformly in +-1/sqrt(fan_in) from a counter-based generator seeded
+ * by `seed`; Adam state zero; delta = 0.  Synchronizes the device.          */
+ddm_status ddm_predictor_create(uint64_t seed, ddm_predictor** out);
+void ddm_predictor_free(ddm_predictor* p);
+
+/* Copy parameters to / from host memory (count must be 0 or
+ * DDM_PREDICTOR_PARAMS; 0 only reads/writes delta).  delta (host pointer for
+ * get, value for set) is the margin added to the prediction before sizing. */
+ddm_status ddm_predictor_get_params(const ddm_predictor* p, float* host, uint32_t count,
+                                    float* delta);
+ddm_status ddm_predictor_set_params(ddm_predictor* p, const float* host, uint32_t count,
+                                    float delta);
+
+/* Features of m updates against tree t (d <= 3, n > 0): X is a device
+ * pointer to m*DDM_FEATURES floats, row j = update j.                        */
+ddm_status ddm_features(const ddm_tree* t, const float* upd_lo, const float* upd_hi, uint32_t m,
+                        float* X, void* stream);
+
+/* yhat[s] (device, N floats) = network output for row s of X (device).      */
+ddm_status ddm_predictor_forward(const ddm_predictor* p, const float* X, uint32_t N, float* yhat,
+                                 void* stream);
+
+/* Gradient of the mean squared error (1/N) sum_s (yhat_s - Y_s)^2 with
+ * respect to the parameters: grad (device, DDM_PREDICTOR_PARAMS floats),
+ * loss (device, one float, may be NULL).  Partial sums are reduced in a fixed
+ * order, so the result is deterministic.                                    */
+ddm_status ddm_predictor_grad(const ddm_predictor* p, const float* X, const float* Y, uint32_t N,
+                              float* grad, float* loss, void* stream);
+
+/* One Adam step (beta1 0.9, beta2 0.999, eps 1e-8, bias-corrected) with the
+ * device gradient `grad` and learning rate lr.                              */
+ddm_status ddm_predictor_adam(ddm_predictor* p, const float* grad, float lr, void* stream);
+
+/* `epochs` passes of minibatch Adam over (X, Y) (device, N rows), batches of
+ * `batch` consecutive rows.  epoch_loss (host, epochs floats, may be NULL)
+ * receives the mean batch loss of each epoch; it synchronizes the stream.   */
+ddm_status ddm_predictor_train(ddm_predictor* p, const float* X, const float* Y, uint32_t N,
+                               uint32_t batch, uint32_t epochs, float lr, void* stream,
+                               float* epoch_loss);
+
+/* Single-pass form of ddm_match_begin (d <= 3; for d = 1 the counts are exact
+ * without any traversal, so it is the plain path).  slot_budget > 0 fixes
+ * the slot arena (updates whose slots fall beyond it are treated as
+ * overflowed); 0 sizes the arena to the predicted total, at the cost of one
+ * more stream synchronization.  Finish with ddm_match_finish.               */
+ddm_status ddm_match_learned_begin(const ddm_tree* t, const float* upd_lo, const float* upd_hi,
+                                   uint32_t m, const ddm_predictor* pred, uint64_t slot_budget,
+                                   uint64_t* out_count, void* stream, const ddm_match_opts* opts,
+                                   ddm_pending** out_pending);
+
+/* Sizing outcome of a pending single-pass match (host pointers, may be
+ * NULL): slots reserved by the predictions, the arena size, and the number
+ * of updates that overflowed their slots (0 for a plain pending match).     */
+ddm_status ddm_pending_info(const ddm_pending* pending, uint64_t* slots, uint64_t* budget,
+                            uint32_t* overflowed);
+
 /* ddm_count -- exact number of subscriptions each update meets (the length
  * of column j of M), without producing the pairs.
  *  counts     device pointer to m uint32 (caller owned).

@@ -11,11 +11,11 @@ from __future__ import annotations
 import ctypes
 import json
 
-from ._native import (DDMError, DDM_E_CAPACITY, TRAVERSE, check, header_functions, lib,
-                      opts as _opts)
+from ._native import (DDMError, DDM_E_CAPACITY, FEATURES, PREDICTOR_PARAMS, TRAVERSE, check,
+                      header_functions, lib, opts as _opts)
 
 __all__ = ["build", "match", "count", "Tree", "DDMError", "prof_enable", "prof_read",
-           "TRAVERSE", "header_functions"]
+           "TRAVERSE", "header_functions", "Predictor", "features", "match_learned"]
 
 
 def _torch():
@@ -185,3 +185,141 @@ def prof_read() -> dict:
     if need >= len(buf):
         raise RuntimeError("kernel timing report truncated")
     return {k: tuple(v) for k, v in json.loads(buf.value.decode()).items()}
+
+
+# ---------------------------------------------------------------------------
+# learned output sizing
+# ---------------------------------------------------------------------------
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None and t.numel() else ctypes.c_void_p()
+
+
+class Predictor:
+    """Hit-count predictor (MLP 18 -> 64 -> 64 -> 1, FP32) living on the GPU."""
+
+    def __init__(self, seed: int = 0):
+        h = ctypes.c_void_p()
+        check(lib().ddm_predictor_create(seed, ctypes.byref(h)), "ddm_predictor_create")
+        self._h = h
+
+    @property
+    def handle(self):
+        return self._h
+
+    def params(self):
+        import numpy as np
+        a = np.zeros(PREDICTOR_PARAMS, np.float32)
+        d = ctypes.c_float()
+        check(lib().ddm_predictor_get_params(self._h, a.ctypes.data, PREDICTOR_PARAMS,
+                                             ctypes.byref(d)), "ddm_predictor_get_params")
+        return a, float(d.value)
+
+    def set_params(self, params=None, delta: float | None = None):
+        import numpy as np
+        if delta is None:
+            delta = self.params()[1]
+        if params is None:
+            check(lib().ddm_predictor_set_params(self._h, None, 0, float(delta)),
+                  "ddm_predictor_set_params")
+            return
+        a = np.ascontiguousarray(params, dtype=np.float32)
+        assert a.size == PREDICTOR_PARAMS
+        check(lib().ddm_predictor_set_params(self._h, a.ctypes.data, PREDICTOR_PARAMS,
+                                             float(delta)), "ddm_predictor_set_params")
+
+    @property
+    def delta(self) -> float:
+        return self.params()[1]
+
+    def forward(self, X, stream=None):
+        torch = _torch()
+        X = X.contiguous()
+        y = torch.empty(X.shape[0], dtype=torch.float32, device=X.device)
+        check(lib().ddm_predictor_forward(self._h, _ptr(X), X.shape[0], _ptr(y),
+                                          _stream_handle(stream)), "ddm_predictor_forward")
+        return y
+
+    def grad(self, X, Y, stream=None):
+        torch = _torch()
+        X, Y = X.contiguous(), Y.contiguous()
+        g = torch.empty(PREDICTOR_PARAMS, dtype=torch.float32, device=X.device)
+        loss = torch.empty(1, dtype=torch.float32, device=X.device)
+        check(lib().ddm_predictor_grad(self._h, _ptr(X), _ptr(Y), X.shape[0], _ptr(g), _ptr(loss),
+                                       _stream_handle(stream)), "ddm_predictor_grad")
+        return g, loss
+
+    def adam(self, grad, lr: float, stream=None):
+        check(lib().ddm_predictor_adam(self._h, _ptr(grad), float(lr), _stream_handle(stream)),
+              "ddm_predictor_adam")
+
+    def train(self, X, Y, batch: int = 4096, epochs: int = 10, lr: float = 1e-3, stream=None):
+        import numpy as np
+        X, Y = X.contiguous(), Y.contiguous()
+        losses = np.zeros(epochs, np.float32)
+        check(lib().ddm_predictor_train(self._h, _ptr(X), _ptr(Y), X.shape[0], batch, epochs,
+                                        float(lr), _stream_handle(stream), losses.ctypes.data),
+              "ddm_predictor_train")
+        return losses
+
+    def save(self, path: str):
+        import numpy as np
+        a, d = self.params()
+        np.savez(path, params=a, delta=np.float32(d))
+
+    @classmethod
+    def load(cls, path: str):
+        import numpy as np
+        z = np.load(path, allow_pickle=False)
+        p = cls(0)
+        p.set_params(z["params"], float(z["delta"]))
+        return p
+
+    def free(self):
+        if self._h is not None:
+            lib().ddm_predictor_free(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
+
+
+def features(tree: Tree, u_lo, u_hi, stream=None):
+    """float32 [m, 18] features of the updates against the tree (d <= 3)."""
+    torch = _torch()
+    u_lo, u_hi = _coords(u_lo, u_hi, "features")
+    m = int(u_lo.shape[1])
+    X = torch.empty((m, FEATURES), dtype=torch.float32, device=u_lo.device)
+    check(lib().ddm_features(tree.handle, _ptr(u_lo), _ptr(u_hi), m, _ptr(X),
+                             _stream_handle(stream)), "ddm_features")
+    return X
+
+
+def match_learned(tree: Tree, u_lo, u_hi, predictor: Predictor, slot_budget: int = 0,
+                  traversal: str = "auto", block: int = 0, stream=None, out=None,
+                  info: dict | None = None):
+    """Single-pass match sized by the predictor; same keys as match()."""
+    torch = _torch()
+    u_lo, u_hi = _coords(u_lo, u_hi, "match_learned")
+    m = int(u_lo.shape[1])
+    o = _opts(traversal, block)
+    K = ctypes.c_uint64()
+    pend = ctypes.c_void_p()
+    check(lib().ddm_match_learned_begin(tree.handle, _ptr(u_lo), _ptr(u_hi), m, predictor.handle,
+                                        int(slot_budget), ctypes.byref(K),
+                                        _stream_handle(stream), ctypes.byref(o),
+                                        ctypes.byref(pend)), "ddm_match_learned_begin")
+    if info is not None and pend:
+        sl, bu, ov = ctypes.c_uint64(), ctypes.c_uint64(), ctypes.c_uint32()
+        lib().ddm_pending_info(pend, ctypes.byref(sl), ctypes.byref(bu), ctypes.byref(ov))
+        info.update(slots=int(sl.value), budget=int(bu.value), overflowed=int(ov.value))
+    k = int(K.value)
+    if out is None:
+        out = torch.empty(k, dtype=torch.int64, device=u_lo.device)
+    if out.numel() < k:
+        lib().ddm_match_abort(pend)
+        raise DDMError(DDM_E_CAPACITY, "match_learned", f"K={k} > capacity {out.numel()}")
+    check(lib().ddm_match_finish(pend, _ptr(out), out.numel()), "ddm_match_finish")
+    return out[:k]

@@ -21,6 +21,8 @@ DDM_E_NOMEM = -4
 DDM_E_DEVICE = -5
 
 TRAVERSE = {"auto": 0, "lane": 1, "tile": 2}
+FEATURES = 18
+PREDICTOR_PARAMS = 5441
 
 
 class DDMError(RuntimeError):
@@ -61,6 +63,10 @@ def lib():
         raise RuntimeError(
             f"libddm.so is not built ({LIB_PATH}); run "
             "`python -m paper_1309_3458_amd.build_lib` (or __graft_entry__.build())")
+    # torch ships its own HIP runtime under the same soname as the system one;
+    # loading torch first makes libddm bind to that runtime, so that the
+    # library and torch's tensors and streams share one HIP runtime.
+    import torch  # noqa: F401
     L = ctypes.CDLL(LIB_PATH)
     P = ctypes.POINTER
     _sig(L, "ddm_build", i32, vp, vp, u32, u32, vp, P(vp))
@@ -79,6 +85,19 @@ def lib():
     _sig(L, "ddm_prof_enable", None, i32)
     _sig(L, "ddm_prof_read", u64, ctypes.c_char_p, u64)
     _sig(L, "ddm_prof_focus", None, ctypes.c_char_p)
+    f32p = ctypes.POINTER(ctypes.c_float)
+    _sig(L, "ddm_predictor_create", i32, u64, P(vp))
+    _sig(L, "ddm_predictor_free", None, vp)
+    _sig(L, "ddm_predictor_get_params", i32, vp, vp, u32, f32p)
+    _sig(L, "ddm_predictor_set_params", i32, vp, vp, u32, ctypes.c_float)
+    _sig(L, "ddm_features", i32, vp, vp, vp, u32, vp, vp)
+    _sig(L, "ddm_predictor_forward", i32, vp, vp, u32, vp, vp)
+    _sig(L, "ddm_predictor_grad", i32, vp, vp, vp, u32, vp, vp, vp)
+    _sig(L, "ddm_predictor_adam", i32, vp, vp, ctypes.c_float, vp)
+    _sig(L, "ddm_predictor_train", i32, vp, vp, vp, u32, u32, u32, ctypes.c_float, vp, vp)
+    _sig(L, "ddm_match_learned_begin", i32, vp, vp, vp, u32, vp, u64, P(u64), vp,
+         P(MatchOpts), P(vp))
+    _sig(L, "ddm_pending_info", i32, vp, P(u64), P(u64), P(u32))
     _lib = L
     return L
 

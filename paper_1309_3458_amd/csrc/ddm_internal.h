@@ -263,6 +263,44 @@ __device__ __forceinline__ void count_2l(const uint32_t* const (&keys)[NS],
 }
 
 // ---------------------------------------------------------------------------
+// learned sizing (learn.hip)
+// ---------------------------------------------------------------------------
+constexpr int kFeatures = 18;
+constexpr int kFeatBins = 64;
+constexpr int kParams = 5441;  // 18*64 + 64 + 64*64 + 64 + 64 + 1
+
+// inputs of the per-tree feature statistics
+struct FeatArgs {
+  const float* rec[DDM_MAX_D];
+  const float* maxhi[DDM_MAX_D];
+  const uint32_t* skey_lo[DDM_MAX_D];
+  const uint32_t* sidx_lo[DDM_MAX_D];
+  uint32_t n, d, ns, root;
+  float* fstat;    // [DDM_MAX_D][4]: min lower bound, width, mean length, 0
+  uint32_t* fcum;  // [DDM_MAX_D][2][kFeatBins + 1] prefix counts of lo / hi
+  uint32_t* sat;   // kSatWords: d-dimensional prefix counts of lower corners
+};
+struct FeatDev {
+  const float* fstat;
+  const uint32_t* fcum;
+  const uint32_t* sat;
+  uint32_t n, d;
+};
+// grid cells per dimension of the joint lower-corner histogram (d <= 3)
+__host__ __device__ constexpr uint32_t sat_grid(uint32_t d) {
+  return d == 1 ? 256u : (d == 2 ? 64u : 16u);
+}
+constexpr uint32_t kSatWords = 17u * 17u * 17u;  // max over d of (G+1)^d
+ddm_status enqueue_feature_stats(const FeatArgs& A, hipStream_t s);
+ddm_status launch_features(const FeatDev& F, uint32_t d, const float* ulo, const float* uhi,
+                           uint32_t m, float* X, hipStream_t s);
+ddm_status launch_mlp_forward(const float* params, const float* X, uint32_t N, int out_mode,
+                              float delta, uint32_t capmax, float* yhat, uint32_t* cap,
+                              hipStream_t s);
+ddm_status launch_mlp_grad(const float* params, const float* X, const float* Y, uint32_t N,
+                           float* grad, float* loss, hipStream_t s);
+
+// ---------------------------------------------------------------------------
 // launchers implemented in the .hip files (all enqueue on `s`)
 // ---------------------------------------------------------------------------
 // radix sort of `narr` arrays described by device descriptors; 4 passes of 8

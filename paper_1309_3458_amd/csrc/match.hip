@@ -28,6 +28,10 @@
 namespace ddm {
 
 TreeDev tree_dev(const ddm_tree* t);
+FeatDev tree_feat(const ddm_tree* t);
+const float* predictor_params(const ddm_predictor* p);
+float predictor_delta(const ddm_predictor* p);
+int predictor_device(const ddm_predictor* p);
 const int32_t* tree_flag(const ddm_tree* t);
 uint32_t tree_n(const ddm_tree* t);
 uint32_t tree_d(const ddm_tree* t);
@@ -244,6 +248,7 @@ __global__ __launch_bounds__(1024) void probe_kernel(TreeDev T, const float* __r
 // number of updates of each probe dimension falls out of group boundaries
 __global__ __launch_bounds__(1024) void bucket_scan_kernel(uint32_t* __restrict__ bhist,
                                                            uint32_t m,
+                                                           uint32_t* __restrict__ gstart_out,
                                                            uint32_t* __restrict__ gcount) {
   constexpr uint32_t per = kBuckets / 1024;
   __shared__ uint32_t sb[kBuckets];
@@ -274,7 +279,10 @@ __global__ __launch_bounds__(1024) void bucket_scan_kernel(uint32_t* __restrict_
   }
   __syncthreads();
   for (uint32_t i = tid; i < kBuckets; i += 1024) bhist[i] = sb[i];
-  if (tid < DDM_MAX_D) gcount[tid] = gstart[tid + 1] - gstart[tid];
+  if (tid < DDM_MAX_D) {
+    gcount[tid] = gstart[tid + 1] - gstart[tid];
+    gstart_out[tid] = gstart[tid];
+  }
 }
 
 __global__ __launch_bounds__(256) void bucket_scatter_kernel(const uint32_t* __restrict__ bucket,
@@ -284,6 +292,54 @@ __global__ __launch_bounds__(256) void bucket_scatter_kernel(const uint32_t* __r
                                                              uint32_t* __restrict__ perm) {
   const uint32_t j = blockIdx.x * blockDim.x + threadIdx.x;
   if (j < m) perm[bhist[bucket[j]] + rank[j]] = j;
+}
+
+// Which updates a traversal processes: group g (probe dimension g) holds
+// gcount[g] updates at perm[gstart[g] ...].
+struct UpdSet {
+  const uint32_t* perm;
+  const uint32_t* gstart;
+  const uint32_t* gcount;
+  uint32_t total;  // upper bound of sum(gcount), for the launch size
+};
+
+// Where a traversal writes.  COUNT (fill == false): cnt[j] = hits of j.
+// FILL: hit r of update j goes to out[base[j] + r] if that is below the
+// segment end: base[j+1] (final offsets, cap == nullptr) or
+// min(base[j] + cap[j], limit) (slots of the single-pass form); with cnt
+// non-null the total number of hits (written or not) is stored in cnt[j].
+struct SegOut {
+  const uint64_t* base;
+  const uint32_t* cap;
+  uint64_t limit;
+  uint32_t* cnt;
+  uint64_t* out;
+};
+
+__device__ __forceinline__ bool upd_index(const UpdSet& U, uint32_t t, uint32_t d,
+                                          uint32_t* idx, uint32_t* grp = nullptr) {
+  uint32_t acc = 0;
+  for (uint32_t g = 0; g < d; ++g) {
+    const uint32_t c = U.gcount[g];
+    if (t < acc + c) {
+      *idx = U.gstart[g] + (t - acc);
+      if (grp) *grp = g;
+      return true;
+    }
+    acc += c;
+  }
+  return false;
+}
+
+__device__ __forceinline__ void seg_bounds(const SegOut& O, uint32_t j, uint64_t* b,
+                                           uint64_t* e) {
+  *b = O.base[j];
+  if (O.cap) {
+    const uint64_t e0 = *b + O.cap[j];
+    *e = e0 < O.limit ? e0 : (O.limit > *b ? O.limit : *b);
+  } else {
+    *e = O.base[j + 1];
+  }
 }
 
 // --------------------------------------------------------------------------
@@ -309,15 +365,13 @@ __global__ __launch_bounds__(256) void bucket_scatter_kernel(const uint32_t* __r
 template <int D, bool FILL>
 __global__ __launch_bounds__(1024) void lane_kernel(TreeDev T, const float* __restrict__ ulo,
                                                    const float* __restrict__ uhi, uint32_t m,
-                                                   const uint32_t* __restrict__ perm,
-                                                   const uint8_t* __restrict__ kstar,
-                                                   uint32_t* __restrict__ cnt,
-                                                   const uint64_t* __restrict__ off,
-                                                   uint64_t* __restrict__ out) {
+                                                   UpdSet US, const uint8_t* __restrict__ kstar,
+                                                   SegOut O) {
   constexpr int R = 2 * D;
   const uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= m) return;
-  const uint32_t j = perm[t];
+  uint32_t pi;
+  if (!upd_index(US, t, D, &pi)) return;
+  const uint32_t j = US.perm[pi];
   const uint32_t k = kstar[j];
   float ql[D], qh[D];
   load_query<D>(ulo, uhi, m, j, k, ql, qh);
@@ -328,8 +382,10 @@ __global__ __launch_bounds__(1024) void lane_kernel(TreeDev T, const float* __re
   uint32_t x = 1u << (T.H - 1);
   bool enter = true;
   uint32_t c = 0;
-  const uint64_t base = FILL ? off[j] : 0;
-  const uint64_t lim = FILL ? off[j + 1] - base : 0;  // segment length (write guard)
+  uint64_t base = 0, segend = 0;
+  if (FILL) seg_bounds(O, j, &base, &segend);
+  const uint64_t lim = segend - base;  // writable slots (write guard)
+  uint64_t* __restrict__ out = O.out;
   const uint64_t jhi = (uint64_t)j << 32;
   while (true) {
     if (enter) {
@@ -363,7 +419,7 @@ __global__ __launch_bounds__(1024) void lane_kernel(TreeDev T, const float* __re
       }
     }
   }
-  if (!FILL) cnt[j] = c;
+  if (!FILL || O.cnt) O.cnt[j] = c;
 }
 
 // --------------------------------------------------------------------------
@@ -402,8 +458,7 @@ __device__ __forceinline__ uint32_t wave_max_u32(uint32_t v) {
 template <int D, bool FILL>
 __global__ __launch_bounds__(kTileWaves * kWave) void tile_kernel(
     TreeDev T, const float* __restrict__ ulo, const float* __restrict__ uhi, uint32_t m,
-    const uint32_t* __restrict__ perm, const uint32_t* __restrict__ gcount,
-    uint32_t* __restrict__ cnt, const uint64_t* __restrict__ off, uint64_t* __restrict__ out) {
+    UpdSet US, SegOut O) {
   constexpr int R = 2 * D;
   constexpr int RV = (R + 3) / 4;
   __shared__ float s_cand[kTileWaves][R][kRing];
@@ -418,18 +473,17 @@ __global__ __launch_bounds__(kTileWaves * kWave) void tile_kernel(
   bool found = false;
 #pragma unroll
   for (int g = 0; g < D; ++g) {
-    const uint32_t gs = uniform_u32(gcount[g]);
+    const uint32_t gs = uniform_u32(US.gcount[g]);
     const uint32_t nt = (gs + kWave - 1) / kWave;
     if (!found) {
       if (tile < tacc + nt) {
         found = true;
         k = (uint32_t)g;
         const uint32_t lt = tile - tacc;
-        qbeg += lt * kWave;
+        qbeg = uniform_u32(US.gstart[g]) + lt * kWave;
         nq = min((uint32_t)kWave, gs - lt * kWave);
       } else {
         tacc += nt;
-        qbeg += gs;
       }
     }
   }
@@ -439,7 +493,7 @@ __global__ __launch_bounds__(kTileWaves * kWave) void tile_kernel(
   qbeg = uniform_u32(qbeg);
 
   const bool qv = lane < nq;
-  const uint32_t j = qv ? perm[qbeg + lane] : 0u;
+  const uint32_t j = qv ? US.perm[qbeg + lane] : 0u;
   float ql[D], qh[D];
   if (qv) {
     load_query<D>(ulo, uhi, m, j, k, ql, qh);
@@ -483,8 +537,10 @@ __global__ __launch_bounds__(kTileWaves * kWave) void tile_kernel(
     Pbeg = uniform_u32(res[1] + 1u);
   }
   uint32_t mycnt = 0;
-  uint64_t mybase = (FILL && qv) ? off[j] : 0;
-  const uint64_t myend = (FILL && qv) ? off[j + 1] : 0;  // segment end (write guard)
+  uint64_t mybase = 0, myend = 0;  // myend: segment end (write guard)
+  if (FILL && qv) seg_bounds(O, j, &mybase, &myend);
+  const uint64_t mystart = mybase;
+  uint64_t* __restrict__ out = O.out;
   const uint64_t jhi = (uint64_t)j << 32;
   const uint32_t nq4 = (nq + 3u) & ~3u;
   wave_sync();
@@ -583,7 +639,10 @@ __global__ __launch_bounds__(kTileWaves * kWave) void tile_kernel(
     }
     if (tail != head) flush(tail - head);
   }
-  if (!FILL && qv) cnt[j] = mycnt;
+  if (qv) {
+    if (!FILL) O.cnt[j] = mycnt;
+    else if (O.cnt) O.cnt[j] = (uint32_t)(mybase - mystart);
+  }
 }
 
 // --------------------------------------------------------------------------
@@ -807,32 +866,35 @@ static ddm_status parse_opts(const ddm_match_opts* o, MatchPlan* p) {
 
 template <int D, bool FILL>
 static ddm_status launch_traverse(const MatchPlan& P, const TreeDev& T, const float* ulo,
-                                  const float* uhi, uint32_t m, const uint32_t* perm,
-                                  const uint8_t* kstar, const uint32_t* gcount, uint32_t* cnt,
-                                  const uint64_t* off, uint64_t* out, hipStream_t s) {
+                                  const float* uhi, uint32_t m, const UpdSet& US,
+                                  const uint8_t* kstar, const SegOut& O, hipStream_t s) {
+  if (US.total == 0) return DDM_OK;
   if (P.traversal == DDM_TRAVERSE_LANE) {
     ProfScope ps(FILL ? "traverse_lane_fill" : "traverse_lane_count", s);
     const uint32_t bs = P.block;
-    lane_kernel<D, FILL><<<(m + bs - 1) / bs, bs, 0, s>>>(T, ulo, uhi, m, perm, kstar, cnt, off,
-                                                          out);
+    lane_kernel<D, FILL><<<(US.total + bs - 1) / bs, bs, 0, s>>>(T, ulo, uhi, m, US, kstar, O);
     DDM_LAUNCHED("lane_kernel");
   } else {
     ProfScope ps(FILL ? "traverse_tile_fill" : "traverse_tile_count", s);
-    const uint32_t tiles = (m + kWave - 1) / kWave + D;
+    const uint32_t tiles = (US.total + kWave - 1) / kWave + D;
     tile_kernel<D, FILL><<<(tiles + kTileWaves - 1) / kTileWaves, kTileWaves * kWave, 0, s>>>(
-        T, ulo, uhi, m, perm, gcount, cnt, off, out);
+        T, ulo, uhi, m, US, O);
     DDM_LAUNCHED("tile_kernel");
   }
   return DDM_OK;
 }
 
-struct MatchState;
-
 template <bool FILL>
 static ddm_status traverse_any(uint32_t d, const MatchPlan& P, const TreeDev& T,
-                               const float* ulo, const float* uhi, uint32_t m,
-                               const MatchState& st, uint32_t* cnt, const uint64_t* off,
-                               uint64_t* out, hipStream_t s);
+                               const float* ulo, const float* uhi, uint32_t m, const UpdSet& US,
+                               const uint8_t* kstar, const SegOut& O, hipStream_t s) {
+  switch (d) {
+    case 1: return launch_traverse<1, FILL>(P, T, ulo, uhi, m, US, kstar, O, s);
+    case 2: return launch_traverse<2, FILL>(P, T, ulo, uhi, m, US, kstar, O, s);
+    case 3: return launch_traverse<3, FILL>(P, T, ulo, uhi, m, US, kstar, O, s);
+    default: return launch_traverse<4, FILL>(P, T, ulo, uhi, m, US, kstar, O, s);
+  }
+}
 
 // pinned host words for the single device->host read of a match
 // (one small block per host thread, kept for the life of the process)
@@ -864,29 +926,28 @@ struct MatchState {
   uint32_t* bucket = nullptr;
   uint32_t* bhist = nullptr;
   uint32_t* perm = nullptr;
+  uint32_t* gstart = nullptr;
   uint32_t* gcount = nullptr;
   int32_t* flag = nullptr;
   uint32_t* cnt = nullptr;
   uint64_t* off = nullptr;
   uint64_t K = 0;
-  explicit MatchState(hipStream_t s) : sc(s) {}
+  uint32_t m = 0;
+  // single-pass (learned sizing) state
+  bool learned = false;
+  Scratch slots_sc;
+  float* X = nullptr;
+  uint32_t* cap = nullptr;
+  uint64_t* soff = nullptr;
+  uint64_t* slots = nullptr;
+  uint64_t budget = 0;
+  uint64_t slots_total = 0;
+  uint32_t* perm_ovf = nullptr;
+  uint32_t* govf = nullptr;
+  uint32_t novf = 0;
+  explicit MatchState(hipStream_t s) : sc(s), slots_sc(s) {}
+  UpdSet all() const { return UpdSet{perm, gstart, gcount, m}; }
 };
-
-template <bool FILL>
-static ddm_status traverse_any(uint32_t d, const MatchPlan& P, const TreeDev& T,
-                               const float* ulo, const float* uhi, uint32_t m,
-                               const MatchState& st, uint32_t* cnt, const uint64_t* off,
-                               uint64_t* out, hipStream_t s) {
-#define DDM_TRAV(DD) \
-  launch_traverse<DD, FILL>(P, T, ulo, uhi, m, st.perm, st.kstar, st.gcount, cnt, off, out, s)
-  switch (d) {
-    case 1: return DDM_TRAV(1);
-    case 2: return DDM_TRAV(2);
-    case 3: return DDM_TRAV(3);
-    default: return DDM_TRAV(4);
-  }
-#undef DDM_TRAV
-}
 
 __global__ void match_init_kernel(uint32_t* __restrict__ gcount, int32_t* __restrict__ flag,
                                   uint32_t* __restrict__ lists_count,
@@ -925,17 +986,86 @@ static ddm_status launch_probe(const TreeDev& T, const float* ulo, const float* 
   return DDM_OK;
 }
 
+// updates whose hits exceeded their slots, kept in their probe group
+__global__ __launch_bounds__(256) void overflow_kernel(UpdSet US, uint32_t d, SegOut O,
+                                                       const uint32_t* __restrict__ cnt,
+                                                       uint32_t* __restrict__ perm_ovf,
+                                                       uint32_t* __restrict__ govf) {
+  const uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;
+  uint32_t pi, g;
+  if (!upd_index(US, t, d, &pi, &g)) return;
+  const uint32_t j = US.perm[pi];
+  uint64_t b, e;
+  seg_bounds(O, j, &b, &e);
+  if ((uint64_t)cnt[j] > e - b) perm_ovf[US.gstart[g] + atomicAdd(&govf[g], 1u)] = j;
+}
+
+// copy the slots of every update that fitted into its final segment; lane l
+// of a wave reads the bounds of update 64w + l, then the wave copies the 64
+// segments one after the other
+__global__ __launch_bounds__(256) void compact_kernel(uint32_t m, SegOut O,
+                                                      const uint32_t* __restrict__ cnt,
+                                                      const uint64_t* __restrict__ off,
+                                                      const uint64_t* __restrict__ slots,
+                                                      uint64_t* __restrict__ out) {
+  const uint32_t lane = lane_id();
+  const uint32_t w0 = (blockIdx.x * blockDim.x + threadIdx.x) - lane;
+  const uint32_t j = w0 + lane;
+  uint64_t b = 0, e = 0, dst = 0;
+  uint32_t c = 0;
+  if (j < m) {
+    seg_bounds(O, j, &b, &e);
+    c = cnt[j];
+    if ((uint64_t)c > e - b) c = 0;  // overflowed: filled by the fallback
+    dst = off[j];
+  }
+  uint64_t todo = ballot(c != 0);
+  while (todo) {
+    const uint32_t l = (uint32_t)__builtin_ctzll(todo);
+    todo &= todo - 1;
+    const uint32_t cl = (uint32_t)__builtin_amdgcn_readlane((int)c, (int)l);
+    const uint64_t bl = readlane_u64(b, l);
+    const uint64_t dl = readlane_u64(dst, l);
+    for (uint32_t r = lane; r < cl; r += kWave) out[dl + r] = slots[bl + r];
+  }
+}
+
+__global__ void learned_init_kernel(uint32_t* __restrict__ govf) {
+  if (threadIdx.x < DDM_MAX_D) govf[threadIdx.x] = 0;
+}
+
+__global__ void learned_words_kernel(const uint32_t* __restrict__ govf,
+                                     const uint64_t* __restrict__ soff, uint32_t m,
+                                     uint64_t* __restrict__ dst) {
+  if (threadIdx.x == 0) {
+    uint64_t t = 0;
+    for (int g = 0; g < DDM_MAX_D; ++g) t += govf[g];
+    dst[2] = t;
+    dst[3] = soff[m];
+  }
+}
+
 static ddm_status front_half(const ddm_tree* t, const float* ulo, const float* uhi, uint32_t m,
                              const MatchPlan& P, MatchState& st, uint32_t* counts_out,
-                             uint32_t** lists, uint32_t** lists_count, hipStream_t s) {
+                             uint32_t** lists, uint32_t** lists_count, hipStream_t s,
+                             const ddm_predictor* pred = nullptr, uint64_t budget = 0) {
   const uint32_t d = tree_d(t);
   const TreeDev T = tree_dev(t);
   Scratch& sc = st.sc;
+  // the single pass replaces the count traversal, which only exists for d > 1
+  st.learned = pred != nullptr && d > 1;
+  if (st.learned) {
+    sc.reserve(sizeof(float) * (size_t)m * kFeatures);  // X
+    sc.reserve(sizeof(uint32_t) * m);                   // cap
+    sc.reserve(sizeof(uint64_t) * (m + 1));             // soff
+    sc.reserve(sizeof(uint32_t) * m);                   // perm_ovf
+    sc.reserve(sizeof(uint32_t) * DDM_MAX_D);           // govf
+  }
   sc.reserve(sizeof(uint32_t) * m);          // cmin
   sc.reserve(m);                             // kstar
   sc.reserve(sizeof(uint32_t) * m * 3);      // rank, bucket, perm
   sc.reserve(sizeof(uint32_t) * kBuckets);   // bucket histogram / offsets
-  sc.reserve(sizeof(uint32_t) * DDM_MAX_D);  // gcount
+  sc.reserve(sizeof(uint32_t) * 2 * DDM_MAX_D);  // gstart, gcount
   sc.reserve(sizeof(int32_t));               // flag
   sc.reserve(sizeof(uint32_t) * m);          // cnt
   sc.reserve(sizeof(uint64_t) * (m + 1));    // off
@@ -949,7 +1079,9 @@ static ddm_status front_half(const ddm_tree* t, const float* ulo, const float* u
   st.bucket = sc.take<uint32_t>(m);
   st.perm = sc.take<uint32_t>(m);
   st.bhist = sc.take<uint32_t>(kBuckets);
+  st.gstart = sc.take<uint32_t>(DDM_MAX_D);
   st.gcount = sc.take<uint32_t>(DDM_MAX_D);
+  st.m = m;
   st.flag = sc.take<int32_t>(1);
   st.cnt = sc.take<uint32_t>(m);
   st.off = sc.take<uint64_t>(m + 1);
@@ -957,6 +1089,15 @@ static ddm_status front_half(const ddm_tree* t, const float* ulo, const float* u
   *lists = sc.take<uint32_t>(2 * (size_t)m);
   *lists_count = sc.take<uint32_t>(2);
   uint64_t* dwords = sc.take<uint64_t>(4);
+  if (st.learned) {
+    st.X = sc.take<float>((size_t)m * kFeatures);
+    st.cap = sc.take<uint32_t>(m);
+    st.soff = sc.take<uint64_t>(m + 1);
+    st.perm_ovf = sc.take<uint32_t>(m);
+    st.govf = sc.take<uint32_t>(DDM_MAX_D);
+    learned_init_kernel<<<1, 64, 0, s>>>(st.govf);
+    DDM_LAUNCHED("learned_init_kernel");
+  }
 
   match_init_kernel<<<kBuckets / 256, 256, 0, s>>>(st.gcount, st.flag, *lists_count, st.bhist);
   DDM_LAUNCHED("match_init_kernel");
@@ -970,7 +1111,7 @@ static ddm_status front_half(const ddm_tree* t, const float* ulo, const float* u
   if (r != DDM_OK) return r;
   {
     ProfScope ps("order", s);
-    bucket_scan_kernel<<<1, 1024, 0, s>>>(st.bhist, m, st.gcount);
+    bucket_scan_kernel<<<1, 1024, 0, s>>>(st.bhist, m, st.gstart, st.gcount);
     DDM_LAUNCHED("bucket_scan_kernel");
     bucket_scatter_kernel<<<(m + 255) / 256, 256, 0, s>>>(st.bucket, st.rank, m, st.bhist,
                                                           st.perm);
@@ -978,8 +1119,42 @@ static ddm_status front_half(const ddm_tree* t, const float* ulo, const float* u
   }
   // per-update counts
   const uint32_t* counts = st.cmin;
-  if (d > 1) {
-    r = traverse_any<false>(d, P, T, ulo, uhi, m, st, st.cnt, nullptr, nullptr, s);
+  SegOut SO{};
+  if (st.learned) {
+    // predicted capacities -> slot offsets; one traversal writes hits into
+    // the slots and counts every hit exactly
+    r = launch_features(tree_feat(t), d, ulo, uhi, m, st.X, s);
+    if (r != DDM_OK) return r;
+    r = launch_mlp_forward(predictor_params(pred), st.X, m, 1, predictor_delta(pred), 1u << 30,
+                           nullptr, st.cap, s);
+    if (r != DDM_OK) return r;
+    r = scan_u32_u64(st.cap, st.soff, m, stmp, s);
+    if (r != DDM_OK) return r;
+    if (budget == 0) {
+      // arena sized to the predicted total (one extra stream synchronization)
+      uint64_t* hw0 = nullptr;
+      r = host_words(&hw0);
+      if (r != DDM_OK) return r;
+      DDM_HIP(hipMemcpyAsync(hw0 + 4, st.soff + m, sizeof(uint64_t), hipMemcpyDeviceToHost, s));
+      DDM_HIP(hipStreamSynchronize(s));
+      budget = hw0[4];
+    }
+    st.budget = budget;
+    st.slots_sc.reserve(sizeof(uint64_t) * (budget ? budget : 1));
+    if (!st.slots_sc.commit()) return DDM_E_NOMEM;
+    st.slots = st.slots_sc.take<uint64_t>(budget ? budget : 1);
+    SO.base = st.soff;
+    SO.cap = st.cap;
+    SO.limit = budget;
+    SO.cnt = st.cnt;
+    SO.out = st.slots;
+    r = traverse_any<true>(d, P, T, ulo, uhi, m, st.all(), st.kstar, SO, s);
+    if (r != DDM_OK) return r;
+    counts = st.cnt;
+  } else if (d > 1) {
+    SegOut O{};
+    O.cnt = st.cnt;
+    r = traverse_any<false>(d, P, T, ulo, uhi, m, st.all(), st.kstar, O, s);
     if (r != DDM_OK) return r;
     counts = st.cnt;
   }
@@ -991,13 +1166,24 @@ static ddm_status front_half(const ddm_tree* t, const float* ulo, const float* u
   if (r != DDM_OK) return r;
   gather_flags_kernel<<<1, 64, 0, s>>>(tree_flag(t), st.flag, st.off, m, dwords);
   DDM_LAUNCHED("gather_flags_kernel");
+  if (st.learned) {
+    overflow_kernel<<<(m + 255) / 256, 256, 0, s>>>(st.all(), d, SO, st.cnt, st.perm_ovf,
+                                                    st.govf);
+    DDM_LAUNCHED("overflow_kernel");
+    learned_words_kernel<<<1, 64, 0, s>>>(st.govf, st.soff, m, dwords);
+    DDM_LAUNCHED("learned_words_kernel");
+  }
   uint64_t* hw = nullptr;
   r = host_words(&hw);
   if (r != DDM_OK) return r;
-  DDM_HIP(hipMemcpyAsync(hw, dwords, 2 * sizeof(uint64_t), hipMemcpyDeviceToHost, s));
+  DDM_HIP(hipMemcpyAsync(hw, dwords, 4 * sizeof(uint64_t), hipMemcpyDeviceToHost, s));
   DDM_HIP(hipStreamSynchronize(s));
   const uint64_t flags = hw[1];
   st.K = hw[0];
+  if (st.learned) {
+    st.novf = (uint32_t)hw[2];
+    st.slots_total = hw[3];
+  }
   if (flags & 0xffffffffull) {
     set_detail("subscription coordinates: NaN/inf or lo > hi");
     return DDM_E_INVALID_INPUT;
@@ -1108,6 +1294,81 @@ extern "C" ddm_status ddm_match_begin(const ddm_tree* t, const float* upd_lo,
   return DDM_OK;
 }
 
+extern "C" ddm_status ddm_match_learned_begin(const ddm_tree* t, const float* upd_lo,
+                                              const float* upd_hi, uint32_t m,
+                                              const ddm_predictor* pred, uint64_t slot_budget,
+                                              uint64_t* out_count, void* stream,
+                                              const ddm_match_opts* opts,
+                                              ddm_pending** out_pending) {
+  set_detail("");
+  if (!out_count || !out_pending || !pred) {
+    set_detail("out_count / out_pending / predictor is NULL");
+    return DDM_E_INVALID_ARG;
+  }
+  *out_count = 0;
+  *out_pending = nullptr;
+  ddm_status r = check_common(t, upd_lo, upd_hi, m);
+  if (r != DDM_OK) return r;
+  if (tree_d(t) > 3) {
+    set_detail("learned sizing supports d <= 3");
+    return DDM_E_INVALID_ARG;
+  }
+  if (predictor_device(pred) != tree_device(t)) {
+    set_detail("predictor and tree live on different devices");
+    return DDM_E_INVALID_ARG;
+  }
+  MatchPlan P;
+  r = parse_opts(opts, &P);
+  if (r != DDM_OK) return r;
+  hipStream_t s = (hipStream_t)stream;
+  if (m == 0 || tree_n(t) == 0) {
+    if (tree_n(t) != 0) return ddm_tree_check(t);
+    return DDM_OK;
+  }
+  ddm_pending* pd = new (std::nothrow) ddm_pending(s);
+  if (!pd) return DDM_E_NOMEM;
+  pd->plan = P;
+  pd->t = t;
+  pd->ulo = upd_lo;
+  pd->uhi = upd_hi;
+  pd->m = m;
+  r = front_half(t, upd_lo, upd_hi, m, P, pd->st, nullptr, &pd->lists, &pd->lists_count, s, pred,
+                 slot_budget);
+  if (r != DDM_OK) {
+    delete pd;
+    return r;
+  }
+  *out_count = pd->st.K;
+  *out_pending = pd;
+  return DDM_OK;
+}
+
+extern "C" ddm_status ddm_pending_info(const ddm_pending* pd, uint64_t* slots, uint64_t* budget,
+                                       uint32_t* overflowed) {
+  if (!pd) return DDM_E_INVALID_ARG;
+  if (slots) *slots = pd->st.slots_total;
+  if (budget) *budget = pd->st.budget;
+  if (overflowed) *overflowed = pd->st.novf;
+  return DDM_OK;
+}
+
+extern "C" ddm_status ddm_features(const ddm_tree* t, const float* upd_lo, const float* upd_hi,
+                                   uint32_t m, float* X, void* stream) {
+  set_detail("");
+  ddm_status r = check_common(t, upd_lo, upd_hi, m);
+  if (r != DDM_OK) return r;
+  if (m > 0 && !X) return DDM_E_INVALID_ARG;
+  if (tree_d(t) > 3) {
+    set_detail("features are defined for d <= 3");
+    return DDM_E_INVALID_ARG;
+  }
+  if (tree_n(t) == 0) {
+    set_detail("features need a non-empty subscription set");
+    return DDM_E_INVALID_ARG;
+  }
+  return launch_features(tree_feat(t), tree_d(t), upd_lo, upd_hi, m, X, (hipStream_t)stream);
+}
+
 extern "C" ddm_status ddm_match_finish(ddm_pending* pd, uint64_t* out_pairs, uint64_t capacity) {
   set_detail("");
   if (!pd) return DDM_OK;  // empty match: nothing to do
@@ -1120,8 +1381,30 @@ extern "C" ddm_status ddm_match_finish(ddm_pending* pd, uint64_t* out_pairs, uin
     r = DDM_E_INVALID_ARG;
   } else if (pd->st.K > 0) {
     const TreeDev T = tree_dev(pd->t);
-    r = traverse_any<true>(tree_d(pd->t), pd->plan, T, pd->ulo, pd->uhi, pd->m, pd->st,
-                           nullptr, pd->st.off, out_pairs, pd->s);
+    MatchState& st = pd->st;
+    SegOut O{};
+    O.base = st.off;
+    O.out = out_pairs;
+    if (st.learned) {
+      SegOut SO{};
+      SO.base = st.soff;
+      SO.cap = st.cap;
+      SO.limit = st.budget;
+      {
+        ProfScope ps("compact", pd->s);
+        compact_kernel<<<(pd->m + 255) / 256, 256, 0, pd->s>>>(pd->m, SO, st.cnt, st.off,
+                                                                st.slots, out_pairs);
+        r = hipGetLastError() == hipSuccess ? DDM_OK : DDM_E_DEVICE;
+      }
+      if (r == DDM_OK && st.novf > 0) {
+        UpdSet OV{st.perm_ovf, st.gstart, st.govf, st.novf};
+        r = traverse_any<true>(tree_d(pd->t), pd->plan, T, pd->ulo, pd->uhi, pd->m, OV, st.kstar,
+                               O, pd->s);
+      }
+    } else {
+      r = traverse_any<true>(tree_d(pd->t), pd->plan, T, pd->ulo, pd->uhi, pd->m, st.all(),
+                             st.kstar, O, pd->s);
+    }
     if (r == DDM_OK)
       r = sort_segments(pd->st.off, pd->m, out_pairs, pd->st.K, tree_n(pd->t), pd->lists,
                         pd->lists_count, pd->s);

@@ -33,6 +33,9 @@ struct ddm_tree {
   uint32_t ns = 0;              // ceil(n / 64) search samples
   uint32_t C = 0;               // blocks of 64 positions
   float* maxlen = nullptr;      // d floats (device)
+  float* fstat = nullptr;       // feature statistics (learned sizing)
+  uint32_t* fcum = nullptr;
+  uint32_t* sat = nullptr;
   int32_t* flag = nullptr;  // device: nonzero if a coordinate was invalid
 };
 
@@ -59,6 +62,7 @@ TreeDev tree_dev(const ddm_tree* t) {
   return T;
 }
 
+FeatDev tree_feat(const ddm_tree* t) { return FeatDev{t->fstat, t->fcum, t->sat, t->n, t->d}; }
 const int32_t* tree_flag(const ddm_tree* t) { return t->flag; }
 uint32_t tree_n(const ddm_tree* t) { return t->n; }
 uint32_t tree_d(const ddm_tree* t) { return t->d; }
@@ -324,6 +328,25 @@ ddm_status enqueue_tree_build(ddm_tree* t, const float* lo, const float* hi, hip
       DDM_LAUNCHED("tree_high_kernel");
     }
   }
+  {
+    ProfScope ps("feature_stats", s);
+    FeatArgs F{};
+    for (uint32_t k = 0; k < d; ++k) {
+      F.rec[k] = t->rec[k];
+      F.maxhi[k] = t->maxhi[k];
+      F.skey_lo[k] = t->skey_lo[k];
+      F.sidx_lo[k] = t->sidx_lo[k];
+    }
+    F.n = n;
+    F.d = d;
+    F.ns = t->ns;
+    F.root = 1u << (t->H - 1);
+    F.fstat = t->fstat;
+    F.fcum = t->fcum;
+    F.sat = t->sat;
+    st = enqueue_feature_stats(F, s);
+    if (st != DDM_OK) return st;
+  }
   return DDM_OK;
 }
 
@@ -377,7 +400,9 @@ extern "C" ddm_status ddm_build(const float* sub_lo, const float* sub_hi, uint32
   const size_t si_b = al(sizeof(uint32_t) * (size_t)t->ns * d);
   const size_t qu_b = al(sizeof(uint32_t) * kQuant * d);
   const size_t total =
-      rec_b * d + mx_b * d + id_b + 2 * key_b + bm_b * d + 2 * si_b + qu_b + 256 + 256;
+      rec_b * d + mx_b * d + id_b + 2 * key_b + bm_b * d + 2 * si_b + qu_b + 256 + 256 +
+      al(sizeof(float) * 4 * DDM_MAX_D) + al(sizeof(uint32_t) * DDM_MAX_D * 2 * (kFeatBins + 1)) +
+      al(sizeof(uint32_t) * kSatWords);
   void* blk = nullptr;
   hipError_t e = hipMallocAsync(&blk, total, s);
   if (e != hipSuccess || !blk) {
@@ -417,6 +442,12 @@ extern "C" ddm_status ddm_build(const float* sub_lo, const float* sub_hi, uint32
   }
   t->maxlen = (float*)p;
   p += 256;
+  t->fstat = (float*)p;
+  p += al(sizeof(float) * 4 * DDM_MAX_D);
+  t->fcum = (uint32_t*)p;
+  p += al(sizeof(uint32_t) * DDM_MAX_D * 2 * (kFeatBins + 1));
+  t->sat = (uint32_t*)p;
+  p += al(sizeof(uint32_t) * kSatWords);
   t->flag = (int32_t*)p;
   tree_init_kernel<<<1, 64, 0, s>>>(t->flag, (uint32_t*)t->maxlen, d);
   e = hipGetLastError();

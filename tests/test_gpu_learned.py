@@ -1,0 +1,182 @@
+"""Learned output sizing on the GPU, through the C ABI.
+
+* the network's forward pass, gradient and Adam step against the float64
+  reference (gradient within relative 1e-4);
+* the per-update features against their float64 restatement;
+* the single-pass matcher returns exactly the bytes of the plain matcher for
+  trained, untrained, forced-zero-capacity and tiny-arena predictors, with
+  both traversal kernels;
+* training lowers the loss, and the trained network overflows far fewer
+  updates than an untrained one on a shifted (hotspot) distribution.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from oracle import mlp_ref
+from paper_1309_3458_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+def _torch():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch
+
+
+def dev(a):
+    torch = _torch()
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+@pytest.fixture(scope="module")
+def trained():
+    _torch()
+    from paper_1309_3458_amd import learn
+    p, rep = learn.train_predictor(n_inst=16, per_instance=8000, epochs=12)
+    return p, rep
+
+
+def test_forward_matches_reference():
+    import paper_1309_3458_amd as P
+    rng = np.random.default_rng(1)
+    params = rng.normal(0, 0.25, mlp_ref.N_PARAMS).astype(np.float32)
+    X = rng.normal(0, 1, (3001, 18)).astype(np.float32)
+    p = P.Predictor(3)
+    p.set_params(params, 0.0)
+    got = p.forward(dev(X)).cpu().numpy()
+    want = mlp_ref.forward(params.astype(np.float64), X.astype(np.float64))
+    assert np.max(np.abs(got - want)) <= 1e-4 * max(1.0, np.max(np.abs(want)))
+
+
+@pytest.mark.parametrize("N", [1, 127, 128, 1000, 4097])
+def test_gradient_matches_reference(N):
+    import paper_1309_3458_amd as P
+    rng = np.random.default_rng(N)
+    params = rng.normal(0, 0.25, mlp_ref.N_PARAMS).astype(np.float32)
+    X = rng.normal(0, 1, (N, 18)).astype(np.float32)
+    Y = rng.normal(0, 1, N).astype(np.float32)
+    p = P.Predictor(0)
+    p.set_params(params, 0.0)
+    g, loss = p.grad(dev(X), dev(Y))
+    g = g.cpu().numpy().astype(np.float64)
+    L, gref = mlp_ref.loss_grad(params.astype(np.float64), X.astype(np.float64),
+                                Y.astype(np.float64))
+    scale = np.max(np.abs(gref))
+    err = np.abs(g - gref)
+    assert np.all(err <= 1e-4 * np.abs(gref) + 1e-6 * scale), np.max(err / (np.abs(gref) + 1e-30))
+    assert abs(float(loss.cpu()[0]) - L) <= 1e-4 * L
+
+
+def test_adam_step_matches_reference():
+    import paper_1309_3458_amd as P
+    rng = np.random.default_rng(5)
+    params = rng.normal(0, 0.25, mlp_ref.N_PARAMS).astype(np.float32)
+    grads = [rng.normal(0, 0.1, mlp_ref.N_PARAMS).astype(np.float32) for _ in range(3)]
+    p = P.Predictor(0)
+    p.set_params(params, 0.0)
+    m1 = np.zeros(mlp_ref.N_PARAMS)
+    m2 = np.zeros(mlp_ref.N_PARAMS)
+    th = params.astype(np.float64)
+    lr, b1, b2, eps = 1e-2, 0.9, 0.999, 1e-8
+    for t, g in enumerate(grads, 1):
+        p.adam(dev(g), lr)
+        m1 = b1 * m1 + (1 - b1) * g
+        m2 = b2 * m2 + (1 - b2) * g.astype(np.float64) ** 2
+        th = th - lr * (m1 / (1 - b1 ** t)) / (np.sqrt(m2 / (1 - b2 ** t)) + eps)
+    got, _ = p.params()
+    np.testing.assert_allclose(got, th, rtol=1e-5, atol=1e-6)
+
+
+@pytest.mark.parametrize("d", [1, 2, 3])
+def test_features_match_reference(d):
+    import paper_1309_3458_amd as P
+    inst = W.random_lengths(200 + d, 30000, 5000, d, L=1e5, max_len=800.0)
+    t = P.build(dev(inst.s_lo), dev(inst.s_hi))
+    X = P.features(t, dev(inst.u_lo), dev(inst.u_hi)).cpu().numpy()
+    ref = mlp_ref.features(inst.s_lo, inst.s_hi, inst.u_lo, inst.u_hi)
+    assert X.shape == ref.shape
+    np.testing.assert_allclose(X, ref, rtol=1e-3, atol=2e-4)
+
+
+def _plain(inst, traversal="auto"):
+    import paper_1309_3458_amd as P
+    t = P.build(dev(inst.s_lo), dev(inst.s_hi))
+    return t, P.match(t, dev(inst.u_lo), dev(inst.u_hi), traversal=traversal).cpu().numpy()
+
+
+CASES = [
+    W.uniform_instance(300, 60000, 50000, 2, 3000.0),
+    W.uniform_instance(301, 30000, 40000, 3, 20000.0),
+    W.hotspot_2d(302, n=40000, m=30000),
+    W.random_lengths(303, 20000, 20000, 2, L=2e4, max_len=400.0),
+]
+
+
+@pytest.mark.parametrize("case", range(len(CASES)))
+@pytest.mark.parametrize("traversal", ["tile", "lane"])
+def test_learned_equals_plain(trained, case, traversal):
+    import paper_1309_3458_amd as P
+    p, _ = trained
+    inst = CASES[case]
+    t, want = _plain(inst, traversal)
+    info = {}
+    got = P.match_learned(t, dev(inst.u_lo), dev(inst.u_hi), p, traversal=traversal,
+                          info=info).cpu().numpy()
+    assert np.array_equal(got, want)
+    assert info["overflowed"] <= inst.m
+    # a tiny fixed arena: most updates overflow by arena, same bytes
+    info = {}
+    got = P.match_learned(t, dev(inst.u_lo), dev(inst.u_hi), p, slot_budget=1000,
+                          traversal=traversal, info=info).cpu().numpy()
+    assert np.array_equal(got, want)
+    assert info["budget"] == 1000
+
+
+def test_forced_under_prediction_falls_back(trained):
+    """Capacities forced to 0 (delta = -30): every update with a hit takes the
+    plain fill, and the bytes are unchanged."""
+    import paper_1309_3458_amd as P
+    p, _ = trained
+    params, delta = p.params()
+    q = P.Predictor(0)
+    q.set_params(params, -30.0)
+    inst = CASES[0]
+    t, want = _plain(inst)
+    info = {}
+    got = P.match_learned(t, dev(inst.u_lo), dev(inst.u_hi), q, info=info).cpu().numpy()
+    assert np.array_equal(got, want)
+    K = oracle.counts_per_update(want.view(np.uint64) if want.dtype != np.uint64 else want,
+                                 inst.m)
+    assert info["slots"] == 0 and info["overflowed"] == int((K > 0).sum())
+
+
+def test_oracle_parity_of_learned_path(trained):
+    import paper_1309_3458_amd as P
+    p, _ = trained
+    inst = W.uniform_instance(310, 8000, 7000, 3, 30000.0)
+    want = oracle.itm(inst.s_lo, inst.s_hi, inst.u_lo, inst.u_hi, threads=8)
+    t = P.build(dev(inst.s_lo), dev(inst.s_hi))
+    got = P.match_learned(t, dev(inst.u_lo), dev(inst.u_hi), p).cpu().numpy().view(np.uint64)
+    assert np.array_equal(got, want)
+
+
+def test_training_gain_over_untrained(trained):
+    """What the trained network buys: on hotspot data (a shifted distribution)
+    it overflows far fewer updates than the untrained network, whose slots
+    are essentially arbitrary."""
+    import paper_1309_3458_amd as P
+    p, rep = trained
+    assert rep["loss_last"] < 0.5 * rep["loss_first"]
+    assert rep["val_under_rate"] <= 0.02
+    inst = W.hotspot_2d(320, n=50000, m=50000)
+    t = P.build(dev(inst.s_lo), dev(inst.s_hi))
+    raw = P.Predictor(77)
+    i_raw, i_tr = {}, {}
+    a = P.match_learned(t, dev(inst.u_lo), dev(inst.u_hi), raw, info=i_raw).cpu().numpy()
+    b = P.match_learned(t, dev(inst.u_lo), dev(inst.u_hi), p, info=i_tr).cpu().numpy()
+    assert np.array_equal(a, b)
+    assert i_tr["overflowed"] < 0.25 * max(1, i_raw["overflowed"])
+    assert i_tr["overflowed"] < 0.2 * inst.m
