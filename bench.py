@@ -42,6 +42,11 @@ def parse():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--traversal", default="auto", choices=["auto", "lane", "tile"])
+    ap.add_argument("--workload", default="d2_uniform", choices=["d2_uniform", "d2_hotspot"])
+    ap.add_argument("--path", default="both", choices=["plain", "learned", "both"],
+                    help="plain two-pass, learned single-pass, or both (value = faster)")
+    ap.add_argument("--predictor", default="",
+                    help="saved predictor (.npz); default: train one before timing")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample", type=int, default=0,
                     help="updates in the oracle's timed sample (0 = auto)")
@@ -63,56 +68,95 @@ def main():
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     torch.cuda.set_device(0)
-    stream = torch.cuda.current_stream()
 
     t0 = time.time()
-    inst = W.uniform_2d_1m(1)
-    log(f"workload generated in {time.time() - t0:.2f}s: d={inst.d} n={inst.n} m={inst.m}")
+    if args.workload == "d2_uniform":
+        inst = W.uniform_2d_1m(1)
+        wname, seed = "d2_N1e6_alpha1_uniform", 1
+    else:
+        inst = W.hotspot_2d(2)
+        wname, seed = "d2_N1e6_hotspots_alpha100", 2
+    log(f"workload {wname} generated in {time.time() - t0:.2f}s: d={inst.d} n={inst.n} "
+        f"m={inst.m}")
     dev = lambda a: torch.from_numpy(a).cuda()
     s_lo, s_hi, u_lo, u_hi = dev(inst.s_lo), dev(inst.s_hi), dev(inst.u_lo), dev(inst.u_hi)
-    EK = inst.n * inst.m * ((2 * inst.side / W.L_SPACE - (inst.side / W.L_SPACE) ** 2) ** 2)
-    out = torch.empty(int(EK * 1.5) + 65536, dtype=torch.int64, device="cuda")
 
-    def step():
+    pred, train_rep = None, None
+    if args.path in ("learned", "both"):
+        if args.predictor:
+            pred = P.Predictor.load(args.predictor)
+        else:
+            from paper_1309_3458_amd import learn
+            pred, train_rep = learn.train_predictor(n_inst=32, per_instance=16000, epochs=20)
+            log(f"predictor trained: {train_rep}")
+
+    # size the output once (untimed), then reuse it
+    t = P.build(s_lo, s_hi)
+    K0 = int(P.match(t, u_lo, u_hi, traversal=args.traversal).numel())
+    t.free()
+    out = torch.empty(K0 + 1, dtype=torch.int64, device="cuda")
+    log(f"K = {K0}")
+
+    def step_plain():
         t = P.build(s_lo, s_hi)
         keys = P.match(t, u_lo, u_hi, traversal=args.traversal, out=out)
         t.free()
         return keys.numel()
 
-    for i in range(args.warmup):
-        K = step()
-    torch.cuda.synchronize()
-    log(f"warmup done, K={K}")
+    info = {}
 
-    # which kernel dominates: one profiled step with every launch evented
-    P.prof_enable(True)
-    step()
-    torch.cuda.synchronize()
-    prof = P.prof_read()
-    P.prof_enable(False)
-    dom = max((k for k in prof if k.startswith("traverse")), key=lambda k: prof[k][0])
-    log("per-kernel ms (one step): " + json.dumps({k: round(v[0], 4) for k, v in prof.items()}))
+    def step_learned():
+        t = P.build(s_lo, s_hi)
+        keys = P.match_learned(t, u_lo, u_hi, pred, traversal=args.traversal, out=out, info=info)
+        t.free()
+        return keys.numel()
 
-    # timed region: events only around the dominant kernel's launches
-    P.prof_enable(True, only=dom)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for i in range(args.steps):
-        K = step()
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    dprof = P.prof_read()
-    P.prof_enable(False)
-    ms_step = (t1 - t0) * 1e3 / args.steps
-    pairs_s = K / (ms_step / 1e3)
+    def timed(step, name):
+        for i in range(args.warmup):
+            K = step()
+        torch.cuda.synchronize()
+        # which traversal kernel dominates: one step with every launch evented
+        P.prof_enable(True)
+        step()
+        torch.cuda.synchronize()
+        prof = P.prof_read()
+        P.prof_enable(False)
+        dom = max((k for k in prof if k.startswith("traverse")), key=lambda k: prof[k][0])
+        log(f"[{name}] per-kernel ms (one step): "
+            + json.dumps({k: round(v[0], 4) for k, v in sorted(prof.items())}))
+        # timed region: HIP events only around the dominant kernel's launches
+        P.prof_enable(True, only=dom)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for i in range(args.steps):
+            K = step()
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        dprof = P.prof_read()
+        P.prof_enable(False)
+        assert K == K0
+        dms, dn = dprof[dom]
+        return {"ms_per_step": (t1 - t0) * 1e3 / args.steps, "dominant": dom,
+                "dominant_avg_ms": dms / dn, "per_kernel_ms": prof}
+
+    res = {}
+    if args.path in ("plain", "both"):
+        res["plain"] = timed(step_plain, "plain")
+    if args.path in ("learned", "both"):
+        res["learned"] = timed(step_learned, "learned")
+        res["learned"]["overflowed"] = info.get("overflowed")
+        res["learned"]["slots"] = info.get("slots")
+    best = min(res, key=lambda k: res[k]["ms_per_step"])
+    ms_step = res[best]["ms_per_step"]
+    pairs_s = K0 / (ms_step / 1e3)
     regions_s = (inst.n + inst.m) / (ms_step / 1e3)
-    dom_ms, dom_launches = dprof[dom]
-    dom_avg_ms = dom_ms / dom_launches
+    dom, dom_avg_ms = res[best]["dominant"], res[best]["dominant_avg_ms"]
 
-    # dominant kernel: one traversal pass.  Its work unit is a per-dimension
-    # candidate test of Algorithm 3 (update j against subscription i in the
-    # probe dimension), 2*d float compares each; the number of candidates
-    # per pass is sum_j c_{j,k*} (exact BITS counts, recomputed here).
+    # Dominant kernel: one traversal pass.  Its unit of work is the per-
+    # dimension candidate test of Algorithm 3 (an update against a
+    # subscription that meets it in the probe dimension), 2*d float compares
+    # each.  Candidates per pass = sum_j min_k c_{j,k} (exact BITS counts,
+    # recomputed here on the host).
     ks = [np.sort(inst.s_lo[k]) for k in range(inst.d)]
     he = [np.sort(inst.s_hi[k]) for k in range(inst.d)]
     c = np.stack([np.searchsorted(ks[k], inst.u_hi[k], side="right")
@@ -129,7 +173,7 @@ def main():
     if not args.no_cpu_baseline:
         import oracle
         cores = min(os.cpu_count() or 1, 16)
-        sample = args.cpu_sample or inst.m
+        sample = args.cpu_sample or (inst.m if args.workload == "d2_uniform" else 2000)
         t0 = time.perf_counter()
         ok = oracle.itm(inst.s_lo, inst.s_hi, inst.u_lo[:, :sample], inst.u_hi[:, :sample],
                         threads=cores)
@@ -139,6 +183,14 @@ def main():
                "sample": f"all {inst.n} subscriptions x first {sample} updates, tree build "
                          f"included, {dt:.2f}s, {len(ok)} pairs"}
 
+    paths = {k: {"ms_per_step": round(v["ms_per_step"], 4),
+                 "pairs_per_s": round(K0 / (v["ms_per_step"] / 1e3), 1),
+                 **({"overflowed": v.get("overflowed"), "slots": v.get("slots")}
+                    if k == "learned" else {})}
+             for k, v in res.items()}
+    if "plain" in res and "learned" in res:
+        paths["learned_speedup_vs_plain"] = round(
+            res["plain"]["ms_per_step"] / res["learned"]["ms_per_step"], 4)
     rec = {
         "metric": "matched pairs/sec + regions/sec at d=2 N=1M alpha=1; p99 latency (serving)",
         "value": round(pairs_s, 1),
@@ -153,8 +205,13 @@ def main():
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": "d2_N1e6_alpha1_uniform", "d": inst.d, "n": inst.n, "m": inst.m,
-                   "side": inst.side, "seed": 1, "K": int(K), "traversal": args.traversal},
+        "config": {"workload": wname, "d": inst.d, "n": inst.n, "m": inst.m,
+                   "seed": seed, "K": int(K0), "traversal": args.traversal, "path": best},
+        "paths": paths,
+        "predictor": ({"val_under_rate": train_rep["val_under_rate"],
+                       "val_mae_log1p": round(train_rep["val_mae_log1p"], 4),
+                       "delta": round(train_rep["delta"], 4), "train_s": train_rep["train_s"]}
+                      if train_rep else None),
         "roofline": roofline,
         "cpu_baseline": cpu,
     }

@@ -5,6 +5,7 @@
 #include <cstdio>
 #include <cstring>
 #include <map>
+#include <unordered_map>
 #include <mutex>
 #include <set>
 #include <string>
@@ -24,38 +25,150 @@ ddm_status hip_fail(hipError_t e, const char* what, const char* file, int line) 
   return DDM_E_DEVICE;
 }
 
-// Keep memory released by hipFreeAsync in the device's default pool instead
-// of returning it to the driver, so repeated builds and matches reuse it.
-void ensure_pool(int device) {
-  static std::mutex mu;
-  static std::set<int> done;
-  std::lock_guard<std::mutex> lk(mu);
-  if (done.count(device)) return;
-  hipMemPool_t pool = nullptr;
-  if (hipDeviceGetDefaultMemPool(&pool, device) == hipSuccess && pool) {
-    uint64_t thr = ~0ull;
-    (void)hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &thr);
+// ---------------------------------------------------------------------------
+// device memory cache
+//
+// Blocks come from hipMalloc and are kept for the life of the process.  A
+// freed block remembers the stream that freed it and an event recorded on
+// that stream at the free: the same stream may reuse the block at once
+// (stream order), another stream only once the event has completed.  Reuse
+// is best fit among cached blocks at most 25% (+1 MiB) larger than asked.
+// ---------------------------------------------------------------------------
+struct CachedBlock {
+  char* p;
+  size_t size;
+  hipStream_t s;
+  hipEvent_t ev;
+  int dev;
+};
+
+static std::mutex g_mem_mu;
+static std::multimap<size_t, CachedBlock>* g_free = new std::multimap<size_t, CachedBlock>();
+static std::map<char*, std::pair<size_t, int>>* g_live = new std::map<char*, std::pair<size_t, int>>();
+static std::vector<hipEvent_t>* g_events = new std::vector<hipEvent_t>();
+
+// events without timing, from a pool (creating one per use is slow)
+hipEvent_t pooled_event() {
+  {
+    std::lock_guard<std::mutex> lk(g_mem_mu);
+    if (!g_events->empty()) {
+      hipEvent_t e = g_events->back();
+      g_events->pop_back();
+      return e;
+    }
   }
-  (void)hipGetLastError();
-  done.insert(device);
+  hipEvent_t e = nullptr;
+  if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) {
+    (void)hipGetLastError();
+    return nullptr;
+  }
+  return e;
+}
+
+void release_event(hipEvent_t e) {
+  if (!e) return;
+  std::lock_guard<std::mutex> lk(g_mem_mu);
+  g_events->push_back(e);
+}
+
+static size_t round_bytes(size_t b) {
+  if (b <= (1u << 20)) return (b + 255) & ~size_t(255);
+  return (b + (1u << 20) - 1) & ~size_t((1u << 20) - 1);
+}
+
+char* dev_alloc(size_t bytes, hipStream_t s) {
+  if (bytes == 0) bytes = 256;
+  bytes = round_bytes(bytes);
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) {
+    (void)hipGetLastError();
+    return nullptr;
+  }
+  {
+    std::lock_guard<std::mutex> lk(g_mem_mu);
+    const size_t cap = bytes + bytes / 4 + (1u << 20);
+    for (auto it = g_free->lower_bound(bytes); it != g_free->end() && it->first <= cap; ++it) {
+      CachedBlock& b = it->second;
+      if (b.dev != dev) continue;
+      bool ok = b.s == s;
+      if (!ok && b.ev) {
+        const hipError_t q = hipEventQuery(b.ev);
+        ok = q == hipSuccess;
+        if (q != hipSuccess && q != hipErrorNotReady) (void)hipGetLastError();
+      }
+      if (!ok) continue;
+      char* p = b.p;
+      const size_t sz = b.size;
+      if (b.ev) g_events->push_back(b.ev);
+      g_free->erase(it);
+      (*g_live)[p] = {sz, dev};
+      return p;
+    }
+  }
+  void* p = nullptr;
+  hipError_t e = hipMalloc(&p, bytes);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    // give the cached blocks of this device back to the driver and retry
+    std::vector<CachedBlock> drop;
+    {
+      std::lock_guard<std::mutex> lk(g_mem_mu);
+      for (auto it = g_free->begin(); it != g_free->end();) {
+        if (it->second.dev == dev) {
+          drop.push_back(it->second);
+          it = g_free->erase(it);
+        } else {
+          ++it;
+        }
+      }
+    }
+    (void)hipDeviceSynchronize();
+    for (auto& b : drop) {
+      (void)hipFree(b.p);
+      release_event(b.ev);
+    }
+    (void)hipGetLastError();
+    e = hipMalloc(&p, bytes);
+    if (e != hipSuccess) {
+      (void)hipGetLastError();
+      return nullptr;
+    }
+  }
+  std::lock_guard<std::mutex> lk(g_mem_mu);
+  (*g_live)[(char*)p] = {bytes, dev};
+  return (char*)p;
+}
+
+void dev_free(char* p, hipStream_t s) {
+  if (!p) return;
+  size_t sz = 0;
+  int dev = 0;
+  {
+    std::lock_guard<std::mutex> lk(g_mem_mu);
+    auto it = g_live->find(p);
+    if (it == g_live->end()) return;
+    sz = it->second.first;
+    dev = it->second.second;
+    g_live->erase(it);
+  }
+  hipEvent_t ev = pooled_event();
+  if (ev) (void)hipEventRecord(ev, s);
+  // without an event only the freeing stream may reuse the block
+  std::lock_guard<std::mutex> lk(g_mem_mu);
+  g_free->insert({sz, CachedBlock{p, sz, s, ev, dev}});
 }
 
 Scratch::~Scratch() {
-  if (base_) (void)hipFreeAsync(base_, s_);
+  if (base_) dev_free(base_, s_);
 }
 
 bool Scratch::commit() {
   if (want_ == 0) want_ = 256;
-  int dev = 0;
-  if (hipGetDevice(&dev) == hipSuccess) ensure_pool(dev);
-  void* p = nullptr;
-  hipError_t e = hipMallocAsync(&p, want_, s_);
-  if (e != hipSuccess || !p) {
-    (void)hipGetLastError();
+  base_ = dev_alloc(want_, s_);
+  if (!base_) {
     set_detail("device scratch allocation failed");
     return false;
   }
-  base_ = (char*)p;
   used_ = 0;
   return true;
 }

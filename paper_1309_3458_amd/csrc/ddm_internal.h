@@ -47,8 +47,9 @@ struct ProfScope {
 struct Scratch {
   explicit Scratch(hipStream_t s) : s_(s) {}
   ~Scratch();
-  // returns nullptr on failure (detail set); 256-byte aligned sub-allocations
-  // are carved from one hipMallocAsync block by reserve()/take().
+  // commit() returns false on failure (detail set); 256-byte aligned
+  // sub-allocations are carved from one cached block by reserve()/take();
+  // the block returns to the cache, ordered on the stream, at destruction.
   void reserve(size_t bytes) { want_ += (bytes + 255) & ~size_t(255); }
   bool commit();
   template <class T>
@@ -63,7 +64,11 @@ struct Scratch {
   size_t want_ = 0, used_ = 0;
 };
 
-void ensure_pool(int device);
+// stream-aware device memory cache and event pool (api.hip)
+char* dev_alloc(size_t bytes, hipStream_t s);
+void dev_free(char* p, hipStream_t s);
+hipEvent_t pooled_event();
+void release_event(hipEvent_t e);
 
 // ---------------------------------------------------------------------------
 // device-side data layout

@@ -116,11 +116,17 @@ __global__ void feat_zero_kernel(uint32_t* __restrict__ fcum, uint32_t count,
 // joint histogram of the subscriptions' lower corners on a G^d grid over the
 // bounding box; entry (i0+1, i1+1, ...) of the (G+1)^d array counts the
 // corners of cell (i0, i1, ...).  Corners are read from tree 0's records
-// (lower bound of dimension 0, then those of the other dimensions).
+// (lower bound of dimension 0, then those of the other dimensions).  Each
+// workgroup counts into LDS and adds its nonzero cells to the global array.
 __global__ __launch_bounds__(256) void sat_hist_kernel(FeatArgs A) {
+  __shared__ uint32_t h[kSatWords];
   const uint32_t D = A.d;
   if (D > 3) return;
   const uint32_t G = sat_grid(D);
+  uint32_t cells = 1;
+  for (uint32_t k = 0; k < D; ++k) cells *= G + 1;
+  for (uint32_t i = threadIdx.x; i < cells; i += 256) h[i] = 0;
+  __syncthreads();
   for (uint32_t p = 1 + blockIdx.x * 256 + threadIdx.x; p <= A.n; p += gridDim.x * 256) {
     uint32_t idx = 0, stride = 1;
     for (uint32_t k = 0; k < D; ++k) {
@@ -130,17 +136,24 @@ __global__ __launch_bounds__(256) void sat_hist_kernel(FeatArgs A) {
       idx += (c + 1) * stride;
       stride *= G + 1;
     }
-    atomicAdd(&A.sat[idx], 1u);
+    atomicAdd(&h[idx], 1u);
   }
+  __syncthreads();
+  for (uint32_t i = threadIdx.x; i < cells; i += 256)
+    if (h[i]) atomicAdd(&A.sat[i], h[i]);
 }
 
-// prefix sums along every axis: sat[i...] = corners in cells with index < i
+// prefix sums along every axis in LDS: sat[i...] = corners in cells < i
 __global__ __launch_bounds__(1024) void sat_prefix_kernel(FeatArgs A) {
+  __shared__ uint32_t h[kSatWords];
   const uint32_t D = A.d;
   if (D > 3) return;
   const uint32_t G1 = sat_grid(D) + 1;
-  uint32_t lines = 1;
-  for (uint32_t k = 1; k < D; ++k) lines *= G1;
+  uint32_t cells = 1;
+  for (uint32_t k = 0; k < D; ++k) cells *= G1;
+  for (uint32_t i = threadIdx.x; i < cells; i += blockDim.x) h[i] = A.sat[i];
+  __syncthreads();
+  const uint32_t lines = cells / G1;
   uint32_t stride = 1;
   for (uint32_t ax = 0; ax < D; ++ax) {
     for (uint32_t l = threadIdx.x; l < lines; l += blockDim.x) {
@@ -155,13 +168,14 @@ __global__ __launch_bounds__(1024) void sat_prefix_kernel(FeatArgs A) {
       }
       uint32_t run = 0;
       for (uint32_t i = 0; i < G1; ++i) {
-        run += A.sat[base + i * stride];
-        A.sat[base + i * stride] = run;
+        run += h[base + i * stride];
+        h[base + i * stride] = run;
       }
     }
     stride *= G1;
     __syncthreads();
   }
+  for (uint32_t i = threadIdx.x; i < cells; i += blockDim.x) A.sat[i] = h[i];
 }
 
 ddm_status enqueue_feature_stats(const FeatArgs& A, hipStream_t s) {

@@ -29,6 +29,7 @@ namespace ddm {
 
 TreeDev tree_dev(const ddm_tree* t);
 FeatDev tree_feat(const ddm_tree* t);
+ddm_status tree_ensure_features(const ddm_tree* t, hipStream_t s);
 const float* predictor_params(const ddm_predictor* p);
 float predictor_delta(const ddm_predictor* p);
 int predictor_device(const ddm_predictor* p);
@@ -300,7 +301,8 @@ struct UpdSet {
   const uint32_t* perm;
   const uint32_t* gstart;
   const uint32_t* gcount;
-  uint32_t total;  // upper bound of sum(gcount), for the launch size
+  uint32_t total;     // upper bound of sum(gcount), for the launch size
+  uint32_t qpt = 64;  // updates per wavefront in the tile traversal (64 or 1)
 };
 
 // Where a traversal writes.  COUNT (fill == false): cnt[j] = hits of j.
@@ -471,17 +473,18 @@ __global__ __launch_bounds__(kTileWaves * kWave) void tile_kernel(
   // locate the tile inside its probe-dimension group
   uint32_t qbeg = 0, tacc = 0, nq = 0, k = 0;
   bool found = false;
+  const uint32_t qpt = US.qpt;
 #pragma unroll
   for (int g = 0; g < D; ++g) {
     const uint32_t gs = uniform_u32(US.gcount[g]);
-    const uint32_t nt = (gs + kWave - 1) / kWave;
+    const uint32_t nt = (gs + qpt - 1) / qpt;
     if (!found) {
       if (tile < tacc + nt) {
         found = true;
         k = (uint32_t)g;
         const uint32_t lt = tile - tacc;
-        qbeg = uniform_u32(US.gstart[g]) + lt * kWave;
-        nq = min((uint32_t)kWave, gs - lt * kWave);
+        qbeg = uniform_u32(US.gstart[g]) + lt * qpt;
+        nq = min(qpt, gs - lt * qpt);
       } else {
         tacc += nt;
       }
@@ -669,35 +672,67 @@ __device__ __forceinline__ void bitonic_regs(uint64_t (&v)[N]) {
   }
 }
 
+// Where segment j's unsorted keys are.  In the single-pass form the updates
+// that fitted their slots still sit in the slot arena; every other segment
+// is in place in the output.  The sorts below read a segment from its source
+// and write it sorted to its final position, so moving slots into place
+// costs no extra pass.
+struct SegSrc {
+  const uint64_t* slots;  // nullptr: every segment is in place
+  SegOut so;              // slot bounds (base = slot offsets, cap, limit)
+  const uint32_t* cnt;    // hits per update
+};
+
+__device__ __forceinline__ const uint64_t* seg_src(const SegSrc& S, uint32_t j,
+                                                   const uint64_t* out, uint64_t off_j,
+                                                   bool* in_place) {
+  if (S.slots) {
+    uint64_t b, e;
+    seg_bounds(S.so, j, &b, &e);
+    if ((uint64_t)S.cnt[j] <= e - b) {
+      *in_place = false;
+      return S.slots + b;
+    }
+  }
+  *in_place = true;
+  return out + off_j;
+}
+
 template <int N>
-__device__ __forceinline__ void sort_small_segment(uint64_t* __restrict__ p, uint32_t len) {
+__device__ __forceinline__ void sort_small_segment(const uint64_t* __restrict__ src,
+                                                   uint64_t* __restrict__ dst, uint32_t len) {
   uint64_t v[N];
 #pragma unroll
-  for (int i = 0; i < N; ++i) v[i] = ((uint32_t)i < len) ? p[i] : ~0ull;
+  for (int i = 0; i < N; ++i) v[i] = ((uint32_t)i < len) ? src[i] : ~0ull;
   bitonic_regs<N>(v);
 #pragma unroll
   for (int i = 0; i < N; ++i)
-    if ((uint32_t)i < len) p[i] = v[i];
+    if ((uint32_t)i < len) dst[i] = v[i];
 }
 
-constexpr uint32_t kSegMid = 4096;  // longest segment sorted in LDS by bitonic
+constexpr uint32_t kSegMid = 2048;  // longest segment sorted in LDS by bitonic
 
 __global__ __launch_bounds__(256) void segsort_small_kernel(const uint64_t* __restrict__ off,
                                                             uint32_t m, uint64_t* __restrict__ out,
+                                                            SegSrc S,
                                                             uint32_t* __restrict__ lists,
                                                             uint32_t* __restrict__ list_count) {
   const uint32_t j = blockIdx.x * blockDim.x + threadIdx.x;
   if (j >= m) return;
   const uint64_t b = off[j];
   const uint64_t len64 = off[j + 1] - b;
-  if (len64 <= 1) return;
+  if (len64 == 0) return;
+  bool in_place;
+  const uint64_t* src = seg_src(S, j, out, b, &in_place);
   const uint32_t len = len64 > 0xffffffffull ? 0xffffffffu : (uint32_t)len64;
-  if (len <= 4) {
-    sort_small_segment<4>(out + b, len);
+  if (len == 1) {
+    if (!in_place) out[b] = src[0];
+  } else if (len <= 4) {
+    sort_small_segment<4>(src, out + b, len);
   } else if (len <= 8) {
-    sort_small_segment<8>(out + b, len);
+    sort_small_segment<8>(src, out + b, len);
   } else if (len <= 16) {
-    sort_small_segment<16>(out + b, len);
+    sort_small_segment<16>(src, out + b, len);
   } else if (len <= kSegMid) {
     lists[atomicAdd(&list_count[0], 1u)] = j;
   } else {
@@ -705,32 +740,34 @@ __global__ __launch_bounds__(256) void segsort_small_kernel(const uint64_t* __re
   }
 }
 
-// one workgroup per listed segment (17..4096 keys): ids bitonic-sorted in LDS
+// one workgroup per listed segment (17..2048 keys): ids bitonic-sorted in LDS
 __global__ __launch_bounds__(256) void segsort_mid_kernel(const uint64_t* __restrict__ off,
-                                                          uint64_t* __restrict__ out,
+                                                          uint64_t* __restrict__ out, SegSrc S,
                                                           const uint32_t* __restrict__ lists,
                                                           const uint32_t* __restrict__ list_count) {
-  __shared__ uint32_t s[kSegMid];
+  __shared__ uint32_t sh[kSegMid];
   const uint32_t cntl = list_count[0];
   for (uint32_t li = blockIdx.x; li < cntl; li += gridDim.x) {
     const uint32_t j = lists[li];
     const uint64_t b = off[j];
     const uint32_t len = (uint32_t)(off[j + 1] - b);
+    bool in_place;
+    const uint64_t* src = seg_src(S, j, out, b, &in_place);
     uint32_t P2 = 32;
     while (P2 < len) P2 <<= 1;
     for (uint32_t i = threadIdx.x; i < P2; i += 256)
-      s[i] = (i < len) ? (uint32_t)out[b + i] : 0xffffffffu;
+      sh[i] = (i < len) ? (uint32_t)src[i] : 0xffffffffu;
     __syncthreads();
     for (uint32_t k = 2; k <= P2; k <<= 1) {
       for (uint32_t jj = k >> 1; jj > 0; jj >>= 1) {
         for (uint32_t i = threadIdx.x; i < P2; i += 256) {
           const uint32_t l = i ^ jj;
           if (l > i) {
-            const uint32_t a = s[i], c = s[l];
+            const uint32_t a = sh[i], c = sh[l];
             const bool up = (i & k) == 0;
             if (up ? (a > c) : (a < c)) {
-              s[i] = c;
-              s[l] = a;
+              sh[i] = c;
+              sh[l] = a;
             }
           }
         }
@@ -738,53 +775,56 @@ __global__ __launch_bounds__(256) void segsort_mid_kernel(const uint64_t* __rest
       }
     }
     const uint64_t jhi = (uint64_t)j << 32;
-    for (uint32_t i = threadIdx.x; i < len; i += 256) out[b + i] = jhi | s[i];
+    for (uint32_t i = threadIdx.x; i < len; i += 256) out[b + i] = jhi | sh[i];
     __syncthreads();
   }
 }
 
-// One workgroup per long segment: mark ids in an LDS bitmap covering a
-// window of 2^20 ids, then emit them in increasing order.  Segments whose
-// ids do not fit one window read them from `src` (a copy), window by window.
-constexpr uint32_t kBitWords = 1u << 15;  // 2^20 bits = 128 KiB
+// One workgroup per long segment: mark ids in an LDS bitmap (dynamic size:
+// `words` 32-bit words covering a window of ids), then emit them in
+// increasing order.  Ids span [0, n): with more than one window, in-place
+// segments read their ids from `tmp`, a copy taken before any write.
 constexpr int kBigThreads = 1024;
+constexpr uint32_t kMaxBitWords = 1u << 15;  // 128 KiB of LDS, 2^20 ids per window
 
 __global__ __launch_bounds__(kBigThreads) void segsort_big_kernel(
-    const uint64_t* __restrict__ off, uint32_t m, uint64_t* __restrict__ out,
+    const uint64_t* __restrict__ off, uint32_t m, uint64_t* __restrict__ out, SegSrc S,
     const uint32_t* __restrict__ lists, const uint32_t* __restrict__ list_count,
-    const uint32_t* __restrict__ src, uint32_t n) {
-  __shared__ uint32_t bits[kBitWords];
+    const uint32_t* __restrict__ tmp, uint32_t n, uint32_t words) {
+  extern __shared__ uint32_t bits[];
   __shared__ uint32_t wsum[kBigThreads / kWave];
   const uint32_t cntl = list_count[1];
   const uint32_t tid = threadIdx.x;
   const uint32_t lane = lane_id();
   const uint32_t wave = tid / kWave;
-  const uint32_t nwin = (n + (kBitWords * 32) - 1) / (kBitWords * 32);
+  const uint32_t span = words * 32;
+  const uint32_t nwin = (n + span - 1) / span;
   for (uint32_t li = blockIdx.x; li < cntl; li += gridDim.x) {
     const uint32_t j = lists[m + li];
     const uint64_t b = off[j];
     const uint64_t len = off[j + 1] - b;
+    bool in_place;
+    const uint64_t* src = seg_src(S, j, out, b, &in_place);
     const uint64_t jhi = (uint64_t)j << 32;
     uint64_t written = 0;
     for (uint32_t w = 0; w < nwin; ++w) {
-      const uint32_t w0 = w * kBitWords * 32;
-      const uint32_t words = min(kBitWords, (n - w0 + 31) / 32);
-      for (uint32_t i = tid; i < words; i += kBigThreads) bits[i] = 0;
+      const uint32_t w0 = w * span;
+      const uint32_t wwords = min(words, (n - w0 + 31) / 32);
+      for (uint32_t i = tid; i < wwords; i += kBigThreads) bits[i] = 0;
       __syncthreads();
       for (uint64_t i = tid; i < len; i += kBigThreads) {
-        const uint32_t id = (nwin == 1) ? (uint32_t)out[b + i] : src[b + i];
-        if (id >= w0 && id - w0 < kBitWords * 32) {
+        const uint32_t id = (nwin > 1 && in_place) ? tmp[b + i] : (uint32_t)src[i];
+        if (id >= w0 && id - w0 < span) {
           const uint32_t r = id - w0;
           atomicOr(&bits[r >> 5], 1u << (r & 31));
         }
       }
       __syncthreads();
       // each thread owns a contiguous run of words
-      const uint32_t per = (words + kBigThreads - 1) / kBigThreads;
-      const uint32_t w_beg = min(words, tid * per), w_end = min(words, w_beg + per);
+      const uint32_t per = (wwords + kBigThreads - 1) / kBigThreads;
+      const uint32_t w_beg = min(wwords, tid * per), w_end = min(wwords, w_beg + per);
       uint32_t mine = 0;
       for (uint32_t q = w_beg; q < w_end; ++q) mine += __popc(bits[q]);
-      // block exclusive scan of `mine`
       uint32_t inc = mine;
 #pragma unroll
       for (int o = 1; o < kWave; o <<= 1) {
@@ -875,8 +915,9 @@ static ddm_status launch_traverse(const MatchPlan& P, const TreeDev& T, const fl
     lane_kernel<D, FILL><<<(US.total + bs - 1) / bs, bs, 0, s>>>(T, ulo, uhi, m, US, kstar, O);
     DDM_LAUNCHED("lane_kernel");
   } else {
-    ProfScope ps(FILL ? "traverse_tile_fill" : "traverse_tile_count", s);
-    const uint32_t tiles = (US.total + kWave - 1) / kWave + D;
+    ProfScope ps(FILL ? (US.qpt == 1 ? "traverse_tile1_fill" : "traverse_tile_fill")
+                      : "traverse_tile_count", s);
+    const uint32_t tiles = (US.total + US.qpt - 1) / US.qpt + D;
     tile_kernel<D, FILL><<<(tiles + kTileWaves - 1) / kTileWaves, kTileWaves * kWave, 0, s>>>(
         T, ulo, uhi, m, US, O);
     DDM_LAUNCHED("tile_kernel");
@@ -946,7 +987,7 @@ struct MatchState {
   uint32_t* govf = nullptr;
   uint32_t novf = 0;
   explicit MatchState(hipStream_t s) : sc(s), slots_sc(s) {}
-  UpdSet all() const { return UpdSet{perm, gstart, gcount, m}; }
+  UpdSet all() const { return UpdSet{perm, gstart, gcount, m, 64}; }
 };
 
 __global__ void match_init_kernel(uint32_t* __restrict__ gcount, int32_t* __restrict__ flag,
@@ -998,36 +1039,6 @@ __global__ __launch_bounds__(256) void overflow_kernel(UpdSet US, uint32_t d, Se
   uint64_t b, e;
   seg_bounds(O, j, &b, &e);
   if ((uint64_t)cnt[j] > e - b) perm_ovf[US.gstart[g] + atomicAdd(&govf[g], 1u)] = j;
-}
-
-// copy the slots of every update that fitted into its final segment; lane l
-// of a wave reads the bounds of update 64w + l, then the wave copies the 64
-// segments one after the other
-__global__ __launch_bounds__(256) void compact_kernel(uint32_t m, SegOut O,
-                                                      const uint32_t* __restrict__ cnt,
-                                                      const uint64_t* __restrict__ off,
-                                                      const uint64_t* __restrict__ slots,
-                                                      uint64_t* __restrict__ out) {
-  const uint32_t lane = lane_id();
-  const uint32_t w0 = (blockIdx.x * blockDim.x + threadIdx.x) - lane;
-  const uint32_t j = w0 + lane;
-  uint64_t b = 0, e = 0, dst = 0;
-  uint32_t c = 0;
-  if (j < m) {
-    seg_bounds(O, j, &b, &e);
-    c = cnt[j];
-    if ((uint64_t)c > e - b) c = 0;  // overflowed: filled by the fallback
-    dst = off[j];
-  }
-  uint64_t todo = ballot(c != 0);
-  while (todo) {
-    const uint32_t l = (uint32_t)__builtin_ctzll(todo);
-    todo &= todo - 1;
-    const uint32_t cl = (uint32_t)__builtin_amdgcn_readlane((int)c, (int)l);
-    const uint64_t bl = readlane_u64(b, l);
-    const uint64_t dl = readlane_u64(dst, l);
-    for (uint32_t r = lane; r < cl; r += kWave) out[dl + r] = slots[bl + r];
-  }
 }
 
 __global__ void learned_init_kernel(uint32_t* __restrict__ govf) {
@@ -1123,6 +1134,8 @@ static ddm_status front_half(const ddm_tree* t, const float* ulo, const float* u
   if (st.learned) {
     // predicted capacities -> slot offsets; one traversal writes hits into
     // the slots and counts every hit exactly
+    r = tree_ensure_features(t, s);
+    if (r != DDM_OK) return r;
     r = launch_features(tree_feat(t), d, ulo, uhi, m, st.X, s);
     if (r != DDM_OK) return r;
     r = launch_mlp_forward(predictor_params(pred), st.X, m, 1, predictor_delta(pred), 1u << 30,
@@ -1219,22 +1232,33 @@ static ddm_status check_common(const ddm_tree* t, const float* ulo, const float*
 }
 
 ddm_status sort_segments(const uint64_t* off, uint32_t m, uint64_t* out, uint64_t K, uint32_t n,
-                         uint32_t* lists, uint32_t* lists_count, hipStream_t s) {
+                         uint32_t* lists, uint32_t* lists_count, hipStream_t s,
+                         const SegSrc& S) {
   ProfScope ps("segsort", s);
-  segsort_small_kernel<<<(m + 255) / 256, 256, 0, s>>>(off, m, out, lists, lists_count);
+  segsort_small_kernel<<<(m + 255) / 256, 256, 0, s>>>(off, m, out, S, lists, lists_count);
   DDM_LAUNCHED("segsort_small_kernel");
-  segsort_mid_kernel<<<1024, 256, 0, s>>>(off, out, lists, lists_count);
+  segsort_mid_kernel<<<8192, 256, 0, s>>>(off, out, S, lists, lists_count);
   DDM_LAUNCHED("segsort_mid_kernel");
-  uint32_t* src = nullptr;
+  const uint32_t words = std::min<uint32_t>(kMaxBitWords, (n + 31) / 32);
+  uint32_t* tmp = nullptr;
   Scratch sc(s);
-  if (n > kBitWords * 32) {
+  if (n > words * 32) {
+    // ids of in-place segments are read window by window from a copy
     sc.reserve(sizeof(uint32_t) * K);
     if (!sc.commit()) return DDM_E_NOMEM;
-    src = sc.take<uint32_t>(K);
-    copy_ids_kernel<<<(unsigned)((K + 255) / 256), 256, 0, s>>>(out, src, K);
+    tmp = sc.take<uint32_t>(K);
+    copy_ids_kernel<<<(unsigned)((K + 255) / 256), 256, 0, s>>>(out, tmp, K);
     DDM_LAUNCHED("copy_ids_kernel");
   }
-  segsort_big_kernel<<<256, kBigThreads, 0, s>>>(off, m, out, lists, lists_count, src, n);
+  static bool attr_set = false;
+  if (!attr_set) {
+    DDM_HIP(hipFuncSetAttribute((const void*)segsort_big_kernel,
+                                hipFuncAttributeMaxDynamicSharedMemorySize,
+                                (int)(kMaxBitWords * sizeof(uint32_t))));
+    attr_set = true;
+  }
+  segsort_big_kernel<<<512, kBigThreads, words * sizeof(uint32_t), s>>>(off, m, out, S, lists,
+                                                                        lists_count, tmp, n, words);
   DDM_LAUNCHED("segsort_big_kernel");
   return DDM_OK;
 }
@@ -1366,6 +1390,8 @@ extern "C" ddm_status ddm_features(const ddm_tree* t, const float* upd_lo, const
     set_detail("features need a non-empty subscription set");
     return DDM_E_INVALID_ARG;
   }
+  r = tree_ensure_features(t, (hipStream_t)stream);
+  if (r != DDM_OK) return r;
   return launch_features(tree_feat(t), tree_d(t), upd_lo, upd_hi, m, X, (hipStream_t)stream);
 }
 
@@ -1386,28 +1412,33 @@ extern "C" ddm_status ddm_match_finish(ddm_pending* pd, uint64_t* out_pairs, uin
     O.base = st.off;
     O.out = out_pairs;
     if (st.learned) {
-      SegOut SO{};
-      SO.base = st.soff;
-      SO.cap = st.cap;
-      SO.limit = st.budget;
-      {
-        ProfScope ps("compact", pd->s);
-        compact_kernel<<<(pd->m + 255) / 256, 256, 0, pd->s>>>(pd->m, SO, st.cnt, st.off,
-                                                                st.slots, out_pairs);
-        r = hipGetLastError() == hipSuccess ? DDM_OK : DDM_E_DEVICE;
-      }
-      if (r == DDM_OK && st.novf > 0) {
-        UpdSet OV{st.perm_ovf, st.gstart, st.govf, st.novf};
-        r = traverse_any<true>(tree_d(pd->t), pd->plan, T, pd->ulo, pd->uhi, pd->m, OV, st.kstar,
-                               O, pd->s);
+      // segments that fitted their slots are moved into place by the
+      // segment sort; overflowed ones are filled in place here
+      if (st.novf > 0) {
+        // overflowed updates are few and scattered, and each has many
+        // hits: one wavefront per update scans its candidate range
+        UpdSet OV{st.perm_ovf, st.gstart, st.govf, st.novf, 1};
+        MatchPlan TP = pd->plan;
+        TP.traversal = DDM_TRAVERSE_TILE;
+        r = traverse_any<true>(tree_d(pd->t), TP, T, pd->ulo, pd->uhi, pd->m, OV, st.kstar, O,
+                               pd->s);
       }
     } else {
       r = traverse_any<true>(tree_d(pd->t), pd->plan, T, pd->ulo, pd->uhi, pd->m, st.all(),
                              st.kstar, O, pd->s);
     }
-    if (r == DDM_OK)
-      r = sort_segments(pd->st.off, pd->m, out_pairs, pd->st.K, tree_n(pd->t), pd->lists,
-                        pd->lists_count, pd->s);
+    if (r == DDM_OK) {
+      SegSrc S{};
+      if (st.learned) {
+        S.slots = st.slots;
+        S.so.base = st.soff;
+        S.so.cap = st.cap;
+        S.so.limit = st.budget;
+        S.cnt = st.cnt;
+      }
+      r = sort_segments(st.off, pd->m, out_pairs, st.K, tree_n(pd->t), pd->lists,
+                        pd->lists_count, pd->s, S);
+    }
   }
   delete pd;
   return r;

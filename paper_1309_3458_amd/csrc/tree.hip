@@ -14,6 +14,7 @@
 #include "ddm_internal.h"
 
 #include <algorithm>
+#include <mutex>
 #include <new>
 
 struct ddm_tree {
@@ -37,6 +38,12 @@ struct ddm_tree {
   uint32_t* fcum = nullptr;
   uint32_t* sat = nullptr;
   int32_t* flag = nullptr;  // device: nonzero if a coordinate was invalid
+  // feature statistics are computed on the first learned match (they are
+  // not needed otherwise); `fstats_ready` marks them enqueued on the stream
+  // of that match, `fstats_event` lets other streams wait for them
+  std::mutex fmu;
+  bool fstats_ready = false;
+  hipEvent_t fstats_event = nullptr;
 };
 
 namespace ddm {
@@ -328,25 +335,42 @@ ddm_status enqueue_tree_build(ddm_tree* t, const float* lo, const float* hi, hip
       DDM_LAUNCHED("tree_high_kernel");
     }
   }
-  {
-    ProfScope ps("feature_stats", s);
-    FeatArgs F{};
-    for (uint32_t k = 0; k < d; ++k) {
-      F.rec[k] = t->rec[k];
-      F.maxhi[k] = t->maxhi[k];
-      F.skey_lo[k] = t->skey_lo[k];
-      F.sidx_lo[k] = t->sidx_lo[k];
-    }
-    F.n = n;
-    F.d = d;
-    F.ns = t->ns;
-    F.root = 1u << (t->H - 1);
-    F.fstat = t->fstat;
-    F.fcum = t->fcum;
-    F.sat = t->sat;
-    st = enqueue_feature_stats(F, s);
-    if (st != DDM_OK) return st;
+  return DDM_OK;
+}
+
+// Enqueue the feature statistics on stream s the first time a learned match
+// uses the tree; later users on other streams wait for the recorded event.
+ddm_status tree_ensure_features(const ddm_tree* tc, hipStream_t s) {
+  ddm_tree* t = const_cast<ddm_tree*>(tc);
+  std::lock_guard<std::mutex> lk(t->fmu);
+  if (t->fstats_ready) {
+    DDM_HIP(hipStreamWaitEvent(s, t->fstats_event, 0));
+    return DDM_OK;
   }
+  ProfScope ps("feature_stats", s);
+  FeatArgs F{};
+  for (uint32_t k = 0; k < t->d; ++k) {
+    F.rec[k] = t->rec[k];
+    F.maxhi[k] = t->maxhi[k];
+    F.skey_lo[k] = t->skey_lo[k];
+    F.sidx_lo[k] = t->sidx_lo[k];
+  }
+  F.n = t->n;
+  F.d = t->d;
+  F.ns = t->ns;
+  F.root = 1u << (t->H - 1);
+  F.fstat = t->fstat;
+  F.fcum = t->fcum;
+  F.sat = t->sat;
+  ddm_status st = enqueue_feature_stats(F, s);
+  if (st != DDM_OK) return st;
+  if (!t->fstats_event) t->fstats_event = pooled_event();
+  if (!t->fstats_event) {
+    set_detail("event creation failed");
+    return DDM_E_DEVICE;
+  }
+  DDM_HIP(hipEventRecord(t->fstats_event, s));
+  t->fstats_ready = true;
   return DDM_OK;
 }
 
@@ -378,7 +402,6 @@ extern "C" ddm_status ddm_build(const float* sub_lo, const float* sub_hi, uint32
   ddm_tree* t = new (std::nothrow) ddm_tree();
   if (!t) return DDM_E_NOMEM;
   DDM_HIP(hipGetDevice(&t->device));
-  ensure_pool(t->device);
   t->stream = s;
   t->n = n;
   t->d = d;
@@ -403,10 +426,9 @@ extern "C" ddm_status ddm_build(const float* sub_lo, const float* sub_hi, uint32
       rec_b * d + mx_b * d + id_b + 2 * key_b + bm_b * d + 2 * si_b + qu_b + 256 + 256 +
       al(sizeof(float) * 4 * DDM_MAX_D) + al(sizeof(uint32_t) * DDM_MAX_D * 2 * (kFeatBins + 1)) +
       al(sizeof(uint32_t) * kSatWords);
-  void* blk = nullptr;
-  hipError_t e = hipMallocAsync(&blk, total, s);
-  if (e != hipSuccess || !blk) {
-    (void)hipGetLastError();
+  void* blk = dev_alloc(total, s);
+  hipError_t e = hipSuccess;
+  if (!blk) {
     delete t;
     set_detail("ddm_build: device allocation failed");
     return DDM_E_NOMEM;
@@ -452,13 +474,13 @@ extern "C" ddm_status ddm_build(const float* sub_lo, const float* sub_hi, uint32
   tree_init_kernel<<<1, 64, 0, s>>>(t->flag, (uint32_t*)t->maxlen, d);
   e = hipGetLastError();
   if (e != hipSuccess) {
-    (void)hipFreeAsync(t->block, s);
+    dev_free(t->block, s);
     delete t;
     return hip_fail(e, "tree_init_kernel", __FILE__, __LINE__);
   }
   ddm_status st = enqueue_tree_build(t, sub_lo, sub_hi, s);
   if (st != DDM_OK) {
-    (void)hipFreeAsync(t->block, s);
+    dev_free(t->block, s);
     delete t;
     return st;
   }
@@ -468,11 +490,12 @@ extern "C" ddm_status ddm_build(const float* sub_lo, const float* sub_hi, uint32
 
 extern "C" void ddm_tree_free(ddm_tree* t) {
   if (!t) return;
+  release_event(t->fstats_event);
   if (t->block) {
     int cur = 0;
     (void)hipGetDevice(&cur);
     if (cur != t->device) (void)hipSetDevice(t->device);
-    (void)hipFreeAsync(t->block, t->stream);
+    dev_free(t->block, t->stream);
     if (cur != t->device) (void)hipSetDevice(cur);
   }
   delete t;
