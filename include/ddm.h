@@ -270,6 +270,77 @@ ddm_status ddm_tree_export(const ddm_tree* t, uint32_t k, float* lo, float* hi,
  * streams that reads the tree has finished.  NULL is ignored.               */
 void ddm_tree_free(ddm_tree* t);
 
+/* ---------------------------------------------------------------------------
+ * Batched matching (an addition to the paper; every instance is the
+ * problem of Sec. III, solved as in Algorithm 4 with the trees of Sec. IV).
+ *
+ * Many independent instances -- each its own subscription set, update set
+ * and dimension -- matched by one fixed sequence of kernels: one tree build
+ * over all subscription sets, one probe and ordering pass over all updates,
+ * a persistent count traversal and a persistent fill traversal whose
+ * wavefronts take (instance, probe dimension, tile of updates) items from an
+ * atomic ticket, one scan and one segment sort.  The sequence allocates
+ * nothing and never waits on the host, so it is captured once into a HIP
+ * graph and replayed by every ddm_batch_run (opts.use_graph).
+ *
+ * Output: out_pairs (device, capacity uint64) receives every instance's
+ * pairs, instance after instance; instance i owns
+ * out_pairs[ranges[i] .. ranges[i+1]) holding keys
+ * (update << 32) | subscription with both ids local to instance i, sorted
+ * ascending -- the bytes ddm_match returns for that instance alone.
+ * --------------------------------------------------------------------------*/
+#define DDM_BATCH_MAX_INSTANCES 16383
+
+typedef struct {
+  const float* sub_lo;  /* device, [d][n] dimension-major, like ddm_build  */
+  const float* sub_hi;
+  const float* upd_lo;  /* device, [d][m] dimension-major, like ddm_match  */
+  const float* upd_hi;
+  uint32_t n;           /* 0 < n < 2^20                                     */
+  uint32_t m;           /* m > 0                                            */
+  uint32_t d;           /* 1 <= d <= DDM_MAX_D                              */
+  uint32_t reserved;    /* must be 0                                        */
+} ddm_batch_instance;
+
+typedef struct {
+  uint32_t qpt;          /* updates per traversal work item: 16, 32 or 64
+                            (0 = 64)                                        */
+  uint32_t waves_per_cu; /* persistent traversal occupancy, 1..64 (0 = 16)  */
+  uint32_t use_graph;    /* nonzero: capture on the first run, then replay  */
+  uint32_t reserved[5];  /* must be 0                                       */
+} ddm_batch_opts;
+
+typedef struct ddm_batch ddm_batch;
+
+/* ddm_batch_create -- plans a batch on the current device: one device block
+ * holds every tree, every intermediate and the work tables (synchronous
+ * upload of the tables).  The coordinate arrays are read at every
+ * ddm_batch_run, so their contents may change between runs but their
+ * addresses and sizes may not.  out_pairs may be NULL when capacity is 0.
+ * Errors: DDM_E_INVALID_ARG (count 0 or above DDM_BATCH_MAX_INSTANCES, an
+ * instance out of range, bad opts),
+ * DDM_E_NOMEM, DDM_E_DEVICE.                                                */
+ddm_status ddm_batch_create(const ddm_batch_instance* inst, uint32_t count,
+                            uint64_t* out_pairs, uint64_t capacity,
+                            const ddm_batch_opts* opts, ddm_batch** out_batch);
+
+/* ddm_batch_run -- enqueues one whole pass on `stream` (graph replay or
+ * eager launches); returns without waiting.  Runs of one batch must not
+ * overlap in time.                                                           */
+ddm_status ddm_batch_run(ddm_batch* b, void* stream);
+
+/* ddm_batch_result -- waits for the last run and reports it: *total
+ * receives the number of pairs over all instances, ranges (host, count + 1
+ * uint64, may be NULL) the instance offsets -- both also when the result
+ * did not fit.  DDM_E_CAPACITY: total > capacity, nothing was written.
+ * DDM_E_INVALID_INPUT: an instance has a NaN/inf coordinate or lo > hi;
+ * nothing was written.                                                       */
+ddm_status ddm_batch_result(ddm_batch* b, uint64_t* total, uint64_t* ranges);
+
+/* ddm_batch_free -- waits for the batch's work and releases it; NULL is
+ * ignored.                                                                    */
+void ddm_batch_free(ddm_batch* b);
+
 /* Static message for a status code.                                          */
 const char* ddm_strerror(ddm_status s);
 

@@ -15,7 +15,7 @@ from ._native import (DDMError, DDM_E_CAPACITY, FEATURES, PREDICTOR_PARAMS, TRAV
                       header_functions, lib, opts as _opts)
 
 __all__ = ["build", "match", "count", "Tree", "DDMError", "prof_enable", "prof_read",
-           "TRAVERSE", "header_functions", "Predictor", "features", "match_learned"]
+           "TRAVERSE", "header_functions", "Predictor", "features", "match_learned", "Batch"]
 
 
 def _torch():
@@ -323,3 +323,82 @@ def match_learned(tree: Tree, u_lo, u_hi, predictor: Predictor, slot_budget: int
         raise DDMError(DDM_E_CAPACITY, "match_learned", f"K={k} > capacity {out.numel()}")
     check(lib().ddm_match_finish(pend, _ptr(out), out.numel()), "ddm_match_finish")
     return out[:k]
+
+
+class Batch:
+    """Many independent instances matched by one fixed kernel sequence.
+
+    instances: list of (s_lo, s_hi, u_lo, u_hi) float32 GPU tensors, [d, n]
+    and [d, m].  The output buffer (int64, `capacity` keys) is allocated
+    here; after run() + result(), pairs(i) is instance i's sorted keys (the
+    bytes match() returns for that instance alone).  The coordinate tensors
+    may be overwritten in place between runs (same shapes).
+    """
+
+    def __init__(self, instances, capacity: int, qpt: int = 64, waves_per_cu: int = 16,
+                 use_graph: bool = True, out=None):
+        from ._native import BatchInstance, BatchOpts
+        torch = _torch()
+        keep = []
+        arr = (BatchInstance * len(instances))()
+        for i, (s_lo, s_hi, u_lo, u_hi) in enumerate(instances):
+            s_lo, s_hi = _coords(s_lo, s_hi, "Batch subscriptions")
+            u_lo, u_hi = _coords(u_lo, u_hi, "Batch updates")
+            if s_lo.shape[0] != u_lo.shape[0]:
+                raise ValueError("Batch: subscriptions and updates differ in d")
+            keep += [s_lo, s_hi, u_lo, u_hi]
+            arr[i].sub_lo, arr[i].sub_hi = _ptr(s_lo), _ptr(s_hi)
+            arr[i].upd_lo, arr[i].upd_hi = _ptr(u_lo), _ptr(u_hi)
+            arr[i].n, arr[i].m, arr[i].d = int(s_lo.shape[1]), int(u_lo.shape[1]), int(s_lo.shape[0])
+        if out is None:
+            dev = keep[0].device if keep else "cuda"
+            out = torch.empty(max(1, int(capacity)), dtype=torch.int64, device=dev)
+        self.out = out
+        self.count = len(instances)
+        self._keep = keep
+        o = BatchOpts()
+        o.qpt, o.waves_per_cu, o.use_graph = int(qpt), int(waves_per_cu), int(bool(use_graph))
+        h = ctypes.c_void_p()
+        check(lib().ddm_batch_create(arr, len(instances), _ptr(out), int(capacity),
+                                     ctypes.byref(o), ctypes.byref(h)), "ddm_batch_create")
+        self._h = h
+        self._ranges = None
+
+    @property
+    def handle(self):
+        if self._h is None:
+            raise RuntimeError("batch already freed")
+        return self._h
+
+    def run(self, stream=None):
+        self._ranges = None
+        check(lib().ddm_batch_run(self.handle, _stream_handle(stream)), "ddm_batch_run")
+
+    def result(self):
+        """(total pairs, host list of count + 1 offsets); raises on overflow."""
+        import numpy as np
+        tot = ctypes.c_uint64()
+        rg = np.zeros(self.count + 1, dtype=np.uint64)
+        code = lib().ddm_batch_result(self.handle, ctypes.byref(tot),
+                                      rg.ctypes.data_as(ctypes.c_void_p))
+        self.total = int(tot.value)
+        self._ranges = rg
+        check(code, "ddm_batch_result")
+        return self.total, rg
+
+    def pairs(self, i: int):
+        if self._ranges is None:
+            self.result()
+        a, b = int(self._ranges[i]), int(self._ranges[i + 1])
+        return self.out[a:b]
+
+    def free(self):
+        if self._h is not None:
+            lib().ddm_batch_free(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass

@@ -40,6 +40,18 @@ class MatchOpts(ctypes.Structure):
                 ("reserved", ctypes.c_uint32 * 6)]
 
 
+class BatchInstance(ctypes.Structure):
+    _fields_ = [("sub_lo", ctypes.c_void_p), ("sub_hi", ctypes.c_void_p),
+                ("upd_lo", ctypes.c_void_p), ("upd_hi", ctypes.c_void_p),
+                ("n", ctypes.c_uint32), ("m", ctypes.c_uint32), ("d", ctypes.c_uint32),
+                ("reserved", ctypes.c_uint32)]
+
+
+class BatchOpts(ctypes.Structure):
+    _fields_ = [("qpt", ctypes.c_uint32), ("waves_per_cu", ctypes.c_uint32),
+                ("use_graph", ctypes.c_uint32), ("reserved", ctypes.c_uint32 * 5)]
+
+
 _lib = None
 
 vp = ctypes.c_void_p
@@ -98,6 +110,10 @@ def lib():
     _sig(L, "ddm_match_learned_begin", i32, vp, vp, vp, u32, vp, u64, P(u64), vp,
          P(MatchOpts), P(vp))
     _sig(L, "ddm_pending_info", i32, vp, P(u64), P(u64), P(u32))
+    _sig(L, "ddm_batch_create", i32, P(BatchInstance), u32, vp, u64, P(BatchOpts), P(vp))
+    _sig(L, "ddm_batch_run", i32, vp, vp)
+    _sig(L, "ddm_batch_result", i32, vp, P(u64), vp)
+    _sig(L, "ddm_batch_free", None, vp)
     _lib = L
     return L
 

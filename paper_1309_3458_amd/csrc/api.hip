@@ -204,6 +204,12 @@ ProfScope::ProfScope(const char* name, hipStream_t s) : name_(name), s_(s) {
   ev_[0] = ev_[1] = nullptr;
   if (!g_prof_on) return;
   if (!g_prof_focus.empty() && g_prof_focus != name) return;
+  // events recorded during graph capture would become graph nodes
+  hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+  if (hipStreamIsCapturing(s, &cs) != hipSuccess || cs != hipStreamCaptureStatusNone) {
+    (void)hipGetLastError();
+    return;
+  }
   hipEvent_t a = get_event();
   if (!a) return;
   ev_[0] = a;

@@ -317,6 +317,12 @@ ddm_status radix_sort_batch(const SortArr* arrs_dev, uint32_t narr, const uint32
 ddm_status sort_setup_small(const SortArr* host_arrs, uint32_t narr, SortArr* arrs_dev,
                             uint32_t* tile_map, uint32_t ntiles, hipStream_t s);
 
+// per-segment sort of the pairs in place (segments off[j] .. off[j+1]);
+// ids must be below 2^20.  lists: 2m+2 uint32 scratch (last two words are
+// counters, zeroed by the caller beforehand).
+ddm_status sort_segments_inplace(const uint64_t* off, uint32_t m, uint64_t* out, uint32_t n,
+                                 uint32_t* lists, uint32_t* lists_count, hipStream_t s);
+
 // exclusive scan of u32 counts into u64 offsets out[0..m], out[m] = total.
 // tmp: scan_tmp_words(m) uint64 scratch.
 size_t scan_tmp_words(uint32_t m);

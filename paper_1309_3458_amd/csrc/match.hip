@@ -21,8 +21,10 @@
 //      lanes never conflict).
 //   6. per-segment sort by subscription id.
 #include "ddm_internal.h"
+#include "traverse.h"
 
 #include <algorithm>
+#include <mutex>
 #include <new>
 
 namespace ddm {
@@ -37,81 +39,6 @@ const int32_t* tree_flag(const ddm_tree* t);
 uint32_t tree_n(const ddm_tree* t);
 uint32_t tree_d(const ddm_tree* t);
 int tree_device(const ddm_tree* t);
-
-// --------------------------------------------------------------------------
-// helpers
-// --------------------------------------------------------------------------
-template <int D>
-__device__ __forceinline__ void load_rec(const float* __restrict__ p, float (&v)[2 * D]) {
-  if constexpr (D == 1) {
-    const float2 a = *reinterpret_cast<const float2*>(p);
-    v[0] = a.x; v[1] = a.y;
-  } else if constexpr (D == 2) {
-    const float4 a = *reinterpret_cast<const float4*>(p);
-    v[0] = a.x; v[1] = a.y; v[2] = a.z; v[3] = a.w;
-  } else if constexpr (D == 3) {
-    const float2 a = reinterpret_cast<const float2*>(p)[0];
-    const float2 b = reinterpret_cast<const float2*>(p)[1];
-    const float2 c = reinterpret_cast<const float2*>(p)[2];
-    v[0] = a.x; v[1] = a.y; v[2] = b.x; v[3] = b.y; v[4] = c.x; v[5] = c.y;
-  } else {
-    const float4 a = reinterpret_cast<const float4*>(p)[0];
-    const float4 b = reinterpret_cast<const float4*>(p)[1];
-    v[0] = a.x; v[1] = a.y; v[2] = a.z; v[3] = a.w;
-    v[4] = b.x; v[5] = b.y; v[6] = b.z; v[7] = b.w;
-  }
-}
-
-// Query j's bounds in record order: probe dimension k first, then the other
-// dimensions ascending (slot s >= 1 holds dimension s-1 or s).
-template <int D>
-__device__ __forceinline__ void load_query(const float* __restrict__ ulo,
-                                           const float* __restrict__ uhi, uint32_t m,
-                                           uint32_t j, uint32_t k, float (&ql)[D],
-                                           float (&qh)[D]) {
-  ql[0] = ulo[(size_t)k * m + j];
-  qh[0] = uhi[(size_t)k * m + j];
-#pragma unroll
-  for (int s = 1; s < D; ++s) {
-    const uint32_t kk = (uint32_t)(s - 1) + (((uint32_t)(s - 1) >= k) ? 1u : 0u);
-    ql[s] = ulo[(size_t)kk * m + j];
-    qh[s] = uhi[(size_t)kk * m + j];
-  }
-}
-
-// closed overlap of a record (2D floats) with query bounds, all dimensions
-template <int D>
-__device__ __forceinline__ bool overlaps(const float (&v)[2 * D], const float (&ql)[D],
-                                         const float (&qh)[D]) {
-  bool ok = true;
-#pragma unroll
-  for (int s = 0; s < D; ++s) ok = ok && (v[2 * s] <= qh[s]) && (ql[s] <= v[2 * s + 1]);
-  return ok;
-}
-
-__device__ __forceinline__ void wave_sync() {
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-  __builtin_amdgcn_wave_barrier();
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-}
-
-__device__ __forceinline__ float wave_min(float v) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v = fminf(v, __shfl_xor(v, o, kWave));
-  return uniform_f32(v);
-}
-
-__device__ __forceinline__ float wave_max(float v) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v = fmaxf(v, __shfl_xor(v, o, kWave));
-  return uniform_f32(v);
-}
-
-__device__ __forceinline__ uint64_t readlane_u64(uint64_t v, uint32_t lane) {
-  const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)v, (int)lane);
-  const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(v >> 32), (int)lane);
-  return ((uint64_t)hi << 32) | lo;
-}
 
 // --------------------------------------------------------------------------
 // 1. Probe dimension and update order.
@@ -164,21 +91,6 @@ __global__ __launch_bounds__(256) void bits1_kernel(TreeDev T, const float* __re
     rank[j] = atomicAdd(&bhist[bu], 1u);
   }
   if (ballot(bad) != 0 && lane_id() == 0) atomicOr(flag, 2);
-}
-
-// number of quantiles <= x (upper) or < x, LDS binary lifting
-__device__ __forceinline__ uint32_t quant_count(const uint32_t* __restrict__ q, uint32_t x,
-                                                bool upper) {
-  uint32_t pos = 0;
-#pragma unroll
-  for (uint32_t step = kQuant; step > 0; step >>= 1) {
-    const uint32_t c = pos + step;
-    if (c <= kQuant) {
-      const uint32_t v = q[c - 1];
-      if (upper ? (v <= x) : (v < x)) pos = c;
-    }
-  }
-  return pos;
 }
 
 template <int D>
@@ -295,55 +207,6 @@ __global__ __launch_bounds__(256) void bucket_scatter_kernel(const uint32_t* __r
   if (j < m) perm[bhist[bucket[j]] + rank[j]] = j;
 }
 
-// Which updates a traversal processes: group g (probe dimension g) holds
-// gcount[g] updates at perm[gstart[g] ...].
-struct UpdSet {
-  const uint32_t* perm;
-  const uint32_t* gstart;
-  const uint32_t* gcount;
-  uint32_t total;     // upper bound of sum(gcount), for the launch size
-  uint32_t qpt = 64;  // updates per wavefront in the tile traversal (64 or 1)
-};
-
-// Where a traversal writes.  COUNT (fill == false): cnt[j] = hits of j.
-// FILL: hit r of update j goes to out[base[j] + r] if that is below the
-// segment end: base[j+1] (final offsets, cap == nullptr) or
-// min(base[j] + cap[j], limit) (slots of the single-pass form); with cnt
-// non-null the total number of hits (written or not) is stored in cnt[j].
-struct SegOut {
-  const uint64_t* base;
-  const uint32_t* cap;
-  uint64_t limit;
-  uint32_t* cnt;
-  uint64_t* out;
-};
-
-__device__ __forceinline__ bool upd_index(const UpdSet& U, uint32_t t, uint32_t d,
-                                          uint32_t* idx, uint32_t* grp = nullptr) {
-  uint32_t acc = 0;
-  for (uint32_t g = 0; g < d; ++g) {
-    const uint32_t c = U.gcount[g];
-    if (t < acc + c) {
-      *idx = U.gstart[g] + (t - acc);
-      if (grp) *grp = g;
-      return true;
-    }
-    acc += c;
-  }
-  return false;
-}
-
-__device__ __forceinline__ void seg_bounds(const SegOut& O, uint32_t j, uint64_t* b,
-                                           uint64_t* e) {
-  *b = O.base[j];
-  if (O.cap) {
-    const uint64_t e0 = *b + O.cap[j];
-    *e = e0 < O.limit ? e0 : (O.limit > *b ? O.limit : *b);
-  } else {
-    *e = O.base[j + 1];
-  }
-}
-
 // --------------------------------------------------------------------------
 // 3/5a. one lane per update: Algorithm 3 without a stack.
 //
@@ -425,38 +288,8 @@ __global__ __launch_bounds__(1024) void lane_kernel(TreeDev T, const float* __re
 }
 
 // --------------------------------------------------------------------------
-// 3/5b. one wavefront per tile of 64 updates (same probe dimension k, ordered
-// by bucket).
-//
-// The tile's candidates in tree k are confined to positions
-// [Pbeg, Pend] = [min plo, max phi] of its updates.  The wave walks that
-// range block by block (64 positions; the tree's maxupper of position 64c and
-// of the height-5 subtree at 64c+32, i.e. Algorithm 3's pruning test cut at
-// height 5): 64 lanes read 64 block maxima at once and a ballot keeps the
-// blocks whose maxupper reaches the tile's smallest q.lower.  A kept block is
-// read one position per lane; positions meeting the tile's enclosing box in
-// every dimension are compacted into an LDS ring with a ballot and a prefix
-// popcount.  Each time 64 candidates are pending, lane l takes candidate l
-// and the wave tests the tile's updates one after the other against the 64
-// candidates (Algorithm 1, closed, every dimension): the ballot of the test
-// is the update's hits among them, and a prefix popcount places the hits
-// contiguously in the update's own segment.
+// 3/5b. tile traversal for one instance (body in traverse.h)
 // --------------------------------------------------------------------------
-constexpr int kTileWaves = 4;
-constexpr int kRing = 128;
-
-__device__ __forceinline__ uint32_t wave_min_u32(uint32_t v) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v = min(v, (uint32_t)__shfl_xor((int)v, o, kWave));
-  return uniform_u32(v);
-}
-
-__device__ __forceinline__ uint32_t wave_max_u32(uint32_t v) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v = max(v, (uint32_t)__shfl_xor((int)v, o, kWave));
-  return uniform_u32(v);
-}
-
 template <int D, bool FILL>
 __global__ __launch_bounds__(kTileWaves * kWave) void tile_kernel(
     TreeDev T, const float* __restrict__ ulo, const float* __restrict__ uhi, uint32_t m,
@@ -495,157 +328,8 @@ __global__ __launch_bounds__(kTileWaves * kWave) void tile_kernel(
   nq = uniform_u32(nq);
   qbeg = uniform_u32(qbeg);
 
-  const bool qv = lane < nq;
-  const uint32_t j = qv ? US.perm[qbeg + lane] : 0u;
-  float ql[D], qh[D];
-  if (qv) {
-    load_query<D>(ulo, uhi, m, j, k, ql, qh);
-  } else {
-#pragma unroll
-    for (int s = 0; s < D; ++s) {
-      ql[s] = INFINITY;
-      qh[s] = -INFINITY;
-    }
-  }
-  {
-    float qr[4 * RV];
-#pragma unroll
-    for (int s = 0; s < D; ++s) {
-      qr[2 * s] = ql[s];
-      qr[2 * s + 1] = qh[s];
-    }
-#pragma unroll
-    for (int r = R; r < 4 * RV; ++r) qr[r] = 0.f;
-#pragma unroll
-    for (int vv = 0; vv < RV; ++vv)
-      s_q[wave][lane][vv] = make_float4(qr[4 * vv], qr[4 * vv + 1], qr[4 * vv + 2], qr[4 * vv + 3]);
-  }
-  float elo[D], ehi[D];
-#pragma unroll
-  for (int s = 0; s < D; ++s) {
-    elo[s] = wave_min(ql[s]);
-    ehi[s] = wave_max(qh[s]);
-  }
-  // candidate positions of the tile in tree k: lower bound in
-  // [t, Ehi] with t <= Elo - maxlen (see the probe kernels)
-  uint32_t Pbeg, Pend;
-  {
-    const uint32_t* keys[2] = {T.skey_lo[k], T.skey_lo[k]};
-    const uint32_t* idx[2] = {T.sidx_lo[k], T.sidx_lo[k]};
-    const uint32_t x[2] = {f2key(ehi[0]), f2key(nextafterf(elo[0] - T.maxlen[k], -INFINITY))};
-    const bool up[2] = {true, false};
-    uint32_t res[2];
-    count_2l<2>(keys, idx, x, up, T.n, T.ns, res);
-    Pend = uniform_u32(res[0]);
-    Pbeg = uniform_u32(res[1] + 1u);
-  }
-  uint32_t mycnt = 0;
-  uint64_t mybase = 0, myend = 0;  // myend: segment end (write guard)
-  if (FILL && qv) seg_bounds(O, j, &mybase, &myend);
-  const uint64_t mystart = mybase;
-  uint64_t* __restrict__ out = O.out;
-  const uint64_t jhi = (uint64_t)j << 32;
-  const uint32_t nq4 = (nq + 3u) & ~3u;
-  wave_sync();
-
-  const float* __restrict__ rec = T.rec[k];
-  const float* __restrict__ bmx = T.bmax[k];
-  const uint32_t* __restrict__ ids = T.id[k];
-  uint32_t head = 0, tail = 0;
-
-  auto flush = [&](uint32_t c) {
-    wave_sync();
-    const uint64_t cvm = (c >= (uint32_t)kWave) ? ~0ull : ((1ull << c) - 1ull);
-    const uint32_t slot = (head + lane) & (kRing - 1);
-    float v[R];
-#pragma unroll
-    for (int r = 0; r < R; ++r) v[r] = s_cand[wave][r][slot];
-    const uint32_t sid = s_cid[wave][slot];
-    for (uint32_t qi = 0; qi < nq4; qi += 4) {
-      uint64_t hm[4];
-#pragma unroll
-      for (uint32_t u = 0; u < 4; ++u) {
-        float q[4 * RV];
-#pragma unroll
-        for (int vv = 0; vv < RV; ++vv) {
-          const float4 t4 = s_q[wave][qi + u][vv];
-          q[4 * vv] = t4.x;
-          q[4 * vv + 1] = t4.y;
-          q[4 * vv + 2] = t4.z;
-          q[4 * vv + 3] = t4.w;
-        }
-        // one compare per lane mask, combined with scalar ANDs
-        uint64_t h = cvm;
-#pragma unroll
-        for (int s = 0; s < D; ++s) {
-          h &= ballot(v[2 * s] <= q[2 * s + 1]);
-          h &= ballot(q[2 * s] <= v[2 * s + 1]);
-        }
-        hm[u] = h;
-      }
-      if ((hm[0] | hm[1] | hm[2] | hm[3]) != 0) {
-#pragma unroll
-        for (uint32_t u = 0; u < 4; ++u) {
-          if (hm[u] == 0) continue;
-          const uint32_t qq = qi + u;
-          const uint32_t pc = (uint32_t)__popcll(hm[u]);
-          if (FILL) {
-            const uint64_t b = readlane_u64(mybase, qq);
-            const uint64_t e = readlane_u64(myend, qq);
-            const uint64_t jq = readlane_u64(jhi, qq);
-            const uint64_t dst = b + mask_rank(hm[u]);
-            if (((hm[u] >> lane) & 1ull) && dst < e) out[dst] = jq | sid;
-            if (lane == qq) mybase += pc;
-          } else {
-            if (lane == qq) mycnt += pc;
-          }
-        }
-      }
-    }
-    head += c;
-    wave_sync();
-  };
-
-  if (Pbeg <= Pend) {
-    const uint32_t c0 = Pbeg >> kBlockLog, c1 = Pend >> kBlockLog;
-    for (uint32_t cb = c0; cb <= c1; cb += kWave) {
-      const uint32_t c = cb + lane;
-      const bool keep = (c <= c1) && (bmx[c] >= elo[0]);
-      uint64_t bm = ballot(keep);
-      while (bm != 0) {
-        const uint32_t b = (uint32_t)__builtin_ctzll(bm);
-        bm &= bm - 1;
-        const uint32_t blk = cb + b;
-        const uint32_t a = max(blk << kBlockLog, Pbeg);
-        const uint32_t e = min((blk << kBlockLog) + (1u << kBlockLog) - 1u, Pend);
-        // positions a..e, one per lane
-        const uint32_t p = a + lane;
-        bool cnd = false;
-        float v[R];
-        if (p <= e) {
-          load_rec<D>(rec + (size_t)p * R, v);
-          cnd = true;
-#pragma unroll
-          for (int s = 0; s < D; ++s)
-            cnd = cnd & (v[2 * s] <= ehi[s]) & (elo[s] <= v[2 * s + 1]);
-        }
-        const uint64_t cm = ballot(cnd);
-        if (cnd) {
-          const uint32_t slot = (tail + mask_rank(cm)) & (kRing - 1);
-#pragma unroll
-          for (int r = 0; r < R; ++r) s_cand[wave][r][slot] = v[r];
-          s_cid[wave][slot] = ids[p];
-        }
-        tail += (uint32_t)__popcll(cm);
-        if (tail - head >= (uint32_t)kWave) flush(kWave);
-      }
-    }
-    if (tail != head) flush(tail - head);
-  }
-  if (qv) {
-    if (!FILL) O.cnt[j] = mycnt;
-    else if (O.cnt) O.cnt[j] = (uint32_t)(mybase - mystart);
-  }
+  tile_body<D, FILL>(T, ulo, uhi, m, US.perm, 0, k, qbeg, nq, O, &s_cand[wave][0][0],
+                     &s_cid[wave][0], &s_q[wave][0][0], lane);
 }
 
 // --------------------------------------------------------------------------
@@ -753,6 +437,8 @@ __global__ __launch_bounds__(256) void segsort_mid_kernel(const uint64_t* __rest
     const uint32_t len = (uint32_t)(off[j + 1] - b);
     bool in_place;
     const uint64_t* src = seg_src(S, j, out, b, &in_place);
+    // every key of the segment carries the same update id in its high word
+    const uint64_t jhi = src[0] & 0xffffffff00000000ull;
     uint32_t P2 = 32;
     while (P2 < len) P2 <<= 1;
     for (uint32_t i = threadIdx.x; i < P2; i += 256)
@@ -774,7 +460,6 @@ __global__ __launch_bounds__(256) void segsort_mid_kernel(const uint64_t* __rest
         __syncthreads();
       }
     }
-    const uint64_t jhi = (uint64_t)j << 32;
     for (uint32_t i = threadIdx.x; i < len; i += 256) out[b + i] = jhi | sh[i];
     __syncthreads();
   }
@@ -805,7 +490,9 @@ __global__ __launch_bounds__(kBigThreads) void segsort_big_kernel(
     const uint64_t len = off[j + 1] - b;
     bool in_place;
     const uint64_t* src = seg_src(S, j, out, b, &in_place);
-    const uint64_t jhi = (uint64_t)j << 32;
+    // every key of the segment carries the same update id in its high word
+    const uint64_t jhi = src[0] & 0xffffffff00000000ull;
+    __syncthreads();  // read before any in-place write of this segment
     uint64_t written = 0;
     for (uint32_t w = 0; w < nwin; ++w) {
       const uint32_t w0 = w * span;
@@ -1232,6 +919,32 @@ static ddm_status check_common(const ddm_tree* t, const float* ulo, const float*
 }
 
 ddm_status sort_segments(const uint64_t* off, uint32_t m, uint64_t* out, uint64_t K, uint32_t n,
+                         uint32_t* lists, uint32_t* lists_count, hipStream_t s, const SegSrc& S);
+
+// the big-segment kernel's LDS bitmap exceeds the default dynamic LDS limit
+ddm_status ensure_segsort_attr() {
+  static std::once_flag once;
+  static hipError_t err = hipSuccess;
+  std::call_once(once, [] {
+    err = hipFuncSetAttribute((const void*)segsort_big_kernel,
+                              hipFuncAttributeMaxDynamicSharedMemorySize,
+                              (int)(kMaxBitWords * sizeof(uint32_t)));
+  });
+  if (err != hipSuccess) return hip_fail(err, "hipFuncSetAttribute", __FILE__, __LINE__);
+  return DDM_OK;
+}
+
+ddm_status sort_segments_inplace(const uint64_t* off, uint32_t m, uint64_t* out, uint32_t n,
+                                 uint32_t* lists, uint32_t* lists_count, hipStream_t s) {
+  // ids of at most 2^20: one bitmap window, no id copy (K is not needed)
+  if (n > kMaxBitWords * 32) {
+    set_detail("segment sort without host sizing needs n <= 2^20");
+    return DDM_E_INVALID_ARG;
+  }
+  return sort_segments(off, m, out, 0, n, lists, lists_count, s, SegSrc{});
+}
+
+ddm_status sort_segments(const uint64_t* off, uint32_t m, uint64_t* out, uint64_t K, uint32_t n,
                          uint32_t* lists, uint32_t* lists_count, hipStream_t s,
                          const SegSrc& S) {
   ProfScope ps("segsort", s);
@@ -1250,13 +963,8 @@ ddm_status sort_segments(const uint64_t* off, uint32_t m, uint64_t* out, uint64_
     copy_ids_kernel<<<(unsigned)((K + 255) / 256), 256, 0, s>>>(out, tmp, K);
     DDM_LAUNCHED("copy_ids_kernel");
   }
-  static bool attr_set = false;
-  if (!attr_set) {
-    DDM_HIP(hipFuncSetAttribute((const void*)segsort_big_kernel,
-                                hipFuncAttributeMaxDynamicSharedMemorySize,
-                                (int)(kMaxBitWords * sizeof(uint32_t))));
-    attr_set = true;
-  }
+  ddm_status r = ensure_segsort_attr();
+  if (r != DDM_OK) return r;
   segsort_big_kernel<<<512, kBigThreads, words * sizeof(uint32_t), s>>>(off, m, out, S, lists,
                                                                         lists_count, tmp, n, words);
   DDM_LAUNCHED("segsort_big_kernel");

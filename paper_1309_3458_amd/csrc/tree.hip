@@ -12,6 +12,7 @@
 // subtree and needs no storage.  Positions beyond n are padding, recognised
 // by index only.
 #include "ddm_internal.h"
+#include "tree_dev.h"
 
 #include <algorithm>
 #include <mutex>
@@ -96,19 +97,14 @@ __global__ void build_keys_kernel(const float* __restrict__ lo, const float* __r
   if (ballot(bad) != 0 && lane_id() == 0) atomicOr(flag, 1);
 }
 
-// samples of the sorted keys for two-level searches, and quantiles
-__global__ void build_index_kernel(const uint32_t* __restrict__ klo,
-                                   const uint32_t* __restrict__ khi, uint32_t n, uint32_t ns,
-                                   uint32_t d, uint32_t* __restrict__ ilo,
-                                   uint32_t* __restrict__ ihi, uint32_t* __restrict__ quant) {
-  const uint32_t c = blockIdx.x * blockDim.x + threadIdx.x;
-  const uint32_t k = blockIdx.y;
-  if (c < ns) {
-    ilo[(size_t)k * ns + c] = klo[(size_t)k * n + ((size_t)c << 6)];
-    if (khi) ihi[(size_t)k * ns + c] = khi[(size_t)k * n + ((size_t)c << 6)];
-  }
-  if (c < kQuant)
-    quant[(size_t)k * kQuant + c] = klo[(size_t)k * n + (uint32_t)(((uint64_t)c * n) / kQuant)];
+// up to DDM_MAX_D tree jobs passed by value (one build)
+struct TreeJobs {
+  TreeJob j[DDM_MAX_D];
+};
+
+// samples and quantiles: job blockIdx.y, items blockIdx.x * 256 + tid
+__global__ void build_index_kernel(TreeJobs J) {
+  tree_index_item(J.j[blockIdx.y], blockIdx.x * blockDim.x + threadIdx.x);
 }
 
 __global__ void tree_init_kernel(int32_t* __restrict__ flag, uint32_t* __restrict__ maxlen_bits,
@@ -117,130 +113,13 @@ __global__ void tree_init_kernel(int32_t* __restrict__ flag, uint32_t* __restric
   if (threadIdx.x < d) maxlen_bits[threadIdx.x] = 0;
 }
 
-constexpr int kChunk = 2048;        // positions per workgroup in a maxhi pass
-constexpr int kChunkLog = 11;
-constexpr int kTreeThreads = 1024;  // two positions per thread
-
-struct TreeBuildArgs {
-  const float* s_lo;
-  const float* s_hi;
-  float* rec[DDM_MAX_D];
-  float* maxhi[DDM_MAX_D];
-  float* bmax[DDM_MAX_D];
-  uint32_t* maxlen_bits;
-  uint32_t C;
-  const uint32_t* id[DDM_MAX_D];
-  uint32_t n, d, H, P;
-};
-
-// Pass 0: gather the records of every position in the chunk (one chunk of
-// 2048 consecutive positions per workgroup, dimension blockIdx.y) and compute
-// maxhi for heights 0..10 in LDS.
-__global__ __launch_bounds__(kTreeThreads) void tree_low_kernel(TreeBuildArgs A) {
-  __shared__ float mx[kChunk];
-  __shared__ uint32_t wlen[kTreeThreads / kWave];
-  const uint32_t k = blockIdx.y;
-  const uint32_t c = blockIdx.x;
-  const uint32_t D = A.d;
-  float* __restrict__ rec = A.rec[k];
-  const uint32_t* __restrict__ ids = A.id[k];
-  // bound of the segment lengths in dimension k: the float difference rounded
-  // to nearest, moved one float up, is >= the exact difference; lengths are
-  // >= 0, so their float bits order like unsigned integers
-  uint32_t lenb = 0;
-  for (uint32_t r = threadIdx.x; r < kChunk; r += kTreeThreads) {
-    const uint32_t p = c * kChunk + r;
-    float h = -INFINITY;
-    if (p >= 1 && p <= A.n) {
-      const uint32_t i = ids[p];
-      float* dst = rec + (size_t)p * 2 * D;
-      const float l0 = A.s_lo[(size_t)k * A.n + i];
-      dst[0] = l0;
-      h = A.s_hi[(size_t)k * A.n + i];
-      dst[1] = h;
-      if (valid_extent(l0, h)) lenb = max(lenb, __float_as_uint(nextafterf(h - l0, INFINITY)));
-      uint32_t slot = 1;
-      for (uint32_t kk = 0; kk < D; ++kk) {
-        if (kk == k) continue;
-        dst[2 * slot] = A.s_lo[(size_t)kk * A.n + i];
-        dst[2 * slot + 1] = A.s_hi[(size_t)kk * A.n + i];
-        ++slot;
-      }
-    }
-    mx[r] = h;
-  }
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) lenb = max(lenb, (uint32_t)__shfl_xor((int)lenb, o, kWave));
-  if (lane_id() == 0) wlen[threadIdx.x / kWave] = lenb;
-  for (int h = 1; h < kChunkLog; ++h) {
-    __syncthreads();
-    if (h == 1 && threadIdx.x == 0) {
-      uint32_t v = 0;
-      for (int w = 0; w < kTreeThreads / kWave; ++w) v = max(v, wlen[w]);
-      if (v) atomicMax(&A.maxlen_bits[k], v);
-    }
-    if (h == (int)kBlockLog) {
-      // heights < 6 are final and heights >= 6 still hold their own upper
-      // bound: block b of the chunk is position 64b plus subtree(64b + 32)
-      if (threadIdx.x < kChunk / 64) {
-        const uint32_t b = threadIdx.x;
-        const uint32_t blk = c * (kChunk / 64) + b;
-        if (blk < A.C) A.bmax[k][blk] = fmaxf(mx[64 * b], mx[64 * b + 32]);
-      }
-      __syncthreads();
-    }
-    for (uint32_t r = threadIdx.x; r < kChunk; r += kTreeThreads) {
-      if (r != 0 && (uint32_t)__builtin_ctz(r) == (uint32_t)h) {
-        const uint32_t half = 1u << (h - 1);
-        mx[r] = fmaxf(mx[r], fmaxf(mx[r - half], mx[r + half]));
-      }
-    }
-  }
-  __syncthreads();
-  for (uint32_t r = threadIdx.x; r < kChunk; r += kTreeThreads) {
-    const uint32_t p = c * kChunk + r;
-    if (r != 0 && p <= A.P) A.maxhi[k][p] = mx[r];
-  }
+// job blockIdx.y, chunk blockIdx.x
+__global__ __launch_bounds__(kTreeThreads) void tree_low_kernel(TreeJobs J) {
+  tree_low_chunk(J.j[blockIdx.y], blockIdx.x);
 }
 
-// Pass s >= 1: positions p = q << S (S = 11 s) with q in this chunk; real
-// heights S .. S+10.  Leaves (odd q) combine the two children of height S-1
-// computed by the previous pass.
-__global__ __launch_bounds__(kTreeThreads) void tree_high_kernel(TreeBuildArgs A, uint32_t S) {
-  __shared__ float mx[kChunk];
-  const uint32_t k = blockIdx.y;
-  const uint32_t c = blockIdx.x;
-  const uint32_t D = A.d;
-  const uint32_t qmax = A.P >> S;
-  const float* __restrict__ rec = A.rec[k];
-  float* __restrict__ maxhi = A.maxhi[k];
-  for (uint32_t r = threadIdx.x; r < kChunk; r += kTreeThreads) {
-    const uint32_t q = c * kChunk + r;
-    float h = -INFINITY;
-    if (r != 0 && q <= qmax) {
-      const uint32_t p = q << S;
-      if (p <= A.n) h = rec[(size_t)p * 2 * D + 1];
-      if (q & 1u) {
-        const uint32_t half = 1u << (S - 1);
-        h = fmaxf(h, fmaxf(maxhi[p - half], maxhi[p + half]));
-      }
-    }
-    mx[r] = h;
-  }
-  for (int h = 1; h < kChunkLog; ++h) {
-    __syncthreads();
-    for (uint32_t r = threadIdx.x; r < kChunk; r += kTreeThreads) {
-      if (r != 0 && (uint32_t)__builtin_ctz(r) == (uint32_t)h) {
-        const uint32_t half = 1u << (h - 1);
-        mx[r] = fmaxf(mx[r], fmaxf(mx[r - half], mx[r + half]));
-      }
-    }
-  }
-  __syncthreads();
-  for (uint32_t r = threadIdx.x; r < kChunk; r += kTreeThreads) {
-    const uint32_t q = c * kChunk + r;
-    if (r != 0 && q <= qmax) maxhi[q << S] = mx[r];
-  }
+__global__ __launch_bounds__(kTreeThreads) void tree_high_kernel(TreeJobs J, uint32_t S) {
+  tree_high_chunk(J.j[blockIdx.y], blockIdx.x, S);
 }
 
 static size_t al(size_t b) { return (b + 255) & ~size_t(255); }
@@ -301,37 +180,43 @@ ddm_status enqueue_tree_build(ddm_tree* t, const float* lo, const float* hi, hip
   if (st != DDM_OK) return st;
   st = radix_sort_batch(arrs, narr, tile_map, ntiles, hist, 0, 4, s);
   if (st != DDM_OK) return st;
+  TreeJobs J{};
+  for (uint32_t k = 0; k < d; ++k) {
+    TreeJob& j = J.j[k];
+    j.s_lo = lo;
+    j.s_hi = hi;
+    j.rec = t->rec[k];
+    j.maxhi = t->maxhi[k];
+    j.bmax = t->bmax[k];
+    j.id = t->id[k];
+    j.skey_lo = t->skey_lo[k];
+    j.skey_hi = sort_hi ? t->skey_hi[k] : nullptr;
+    j.sidx_lo = t->sidx_lo[k];
+    j.sidx_hi = sort_hi ? t->sidx_hi[k] : nullptr;
+    j.quant = t->quant[k];
+    j.maxlen_bits = (uint32_t*)t->maxlen + k;
+    j.n = n;
+    j.d = d;
+    j.k = k;
+    j.P = t->P;
+    j.C = t->C;
+    j.H = t->H;
+    j.ns = t->ns;
+  }
   {
     dim3 g((std::max(t->ns, kQuant) + 255) / 256, d);
-    build_index_kernel<<<g, 256, 0, s>>>(t->skey_lo[0], sort_hi ? t->skey_hi[0] : nullptr, n,
-                                         t->ns, d, t->sidx_lo[0], t->sidx_hi[0], t->quant[0]);
+    build_index_kernel<<<g, 256, 0, s>>>(J);
     DDM_LAUNCHED("build_index_kernel");
   }
-
-  TreeBuildArgs A{};
-  A.s_lo = lo;
-  A.s_hi = hi;
-  for (uint32_t k = 0; k < d; ++k) {
-    A.rec[k] = t->rec[k];
-    A.maxhi[k] = t->maxhi[k];
-    A.id[k] = t->id[k];
-    A.bmax[k] = t->bmax[k];
-  }
-  A.C = t->C;
-  A.maxlen_bits = (uint32_t*)t->maxlen;
-  A.n = n;
-  A.d = d;
-  A.H = t->H;
-  A.P = t->P;
   {
     ProfScope ps("tree_build", s);
     dim3 g((t->P + 1 + kChunk - 1) / kChunk, d);
-    tree_low_kernel<<<g, kTreeThreads, 0, s>>>(A);
+    tree_low_kernel<<<g, kTreeThreads, 0, s>>>(J);
     DDM_LAUNCHED("tree_low_kernel");
     for (uint32_t S = kChunkLog; S < t->H; S += kChunkLog) {
       const uint32_t q_end = (t->P >> S) + 1;
       dim3 g2((q_end + kChunk - 1) / kChunk, d);
-      tree_high_kernel<<<g2, kTreeThreads, 0, s>>>(A, S);
+      tree_high_kernel<<<g2, kTreeThreads, 0, s>>>(J, S);
       DDM_LAUNCHED("tree_high_kernel");
     }
   }

@@ -1,0 +1,146 @@
+// Per-tree construction steps shared by the single-tree build (tree.hip) and
+// the batched build (batch.hip).  Each step works on one tree (one
+// dimension k of one subscription set) described by a TreeJob.
+#pragma once
+
+#include "ddm_internal.h"
+
+namespace ddm {
+
+struct TreeJob {
+  const float* s_lo;       // the set's lower bounds, dimension-major [d][n]
+  const float* s_hi;
+  float* rec;              // (n+1) records of 2d floats (tree k order)
+  float* maxhi;            // P+1
+  float* bmax;             // C
+  const uint32_t* id;      // n+1 (sorted payload at positions 1..n)
+  const uint32_t* skey_lo; // n sorted keys of lo_k
+  const uint32_t* skey_hi; // n sorted keys of hi_k, or null
+  uint32_t* sidx_lo;       // ns samples
+  uint32_t* sidx_hi;       // ns samples, or null
+  uint32_t* quant;         // kQuant quantiles
+  uint32_t* maxlen_bits;   // one word: bound of the lengths (float bits)
+  uint32_t n, d, k, P, C, H, ns;
+};
+
+constexpr int kChunk = 2048;        // positions per workgroup in a maxhi pass
+constexpr int kChunkLog = 11;
+constexpr int kTreeThreads = 1024;  // two positions per thread
+
+// samples of the sorted keys for two-level searches, and quantiles; index c
+__device__ __forceinline__ void tree_index_item(const TreeJob& J, uint32_t c) {
+  if (c < J.ns) {
+    J.sidx_lo[c] = J.skey_lo[(size_t)c << 6];
+    if (J.skey_hi) J.sidx_hi[c] = J.skey_hi[(size_t)c << 6];
+  }
+  if (c < kQuant) J.quant[c] = J.skey_lo[(uint32_t)(((uint64_t)c * J.n) / kQuant)];
+}
+
+// Pass 0 on chunk c (2048 consecutive positions): gather the records and
+// compute maxhi for heights 0..10 in LDS, the block maxima (height 5 plus
+// the position above) and the length bound.
+__device__ __forceinline__ void tree_low_chunk(const TreeJob& J, uint32_t c) {
+  __shared__ float mx[kChunk];
+  __shared__ uint32_t wlen[kTreeThreads / kWave];
+  const uint32_t k = J.k;
+  const uint32_t D = J.d;
+  float* __restrict__ rec = J.rec;
+  const uint32_t* __restrict__ ids = J.id;
+  // bound of the segment lengths in dimension k: the float difference rounded
+  // to nearest, moved one float up, is >= the exact difference; lengths are
+  // >= 0, so their float bits order like unsigned integers
+  uint32_t lenb = 0;
+  for (uint32_t r = threadIdx.x; r < kChunk; r += kTreeThreads) {
+    const uint32_t p = c * kChunk + r;
+    float h = -INFINITY;
+    if (p >= 1 && p <= J.n) {
+      const uint32_t i = ids[p];
+      float* dst = rec + (size_t)p * 2 * D;
+      const float l0 = J.s_lo[(size_t)k * J.n + i];
+      dst[0] = l0;
+      h = J.s_hi[(size_t)k * J.n + i];
+      dst[1] = h;
+      if (valid_extent(l0, h)) lenb = max(lenb, __float_as_uint(nextafterf(h - l0, INFINITY)));
+      uint32_t slot = 1;
+      for (uint32_t kk = 0; kk < D; ++kk) {
+        if (kk == k) continue;
+        dst[2 * slot] = J.s_lo[(size_t)kk * J.n + i];
+        dst[2 * slot + 1] = J.s_hi[(size_t)kk * J.n + i];
+        ++slot;
+      }
+    }
+    mx[r] = h;
+  }
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) lenb = max(lenb, (uint32_t)__shfl_xor((int)lenb, o, kWave));
+  if (lane_id() == 0) wlen[threadIdx.x / kWave] = lenb;
+  for (int h = 1; h < kChunkLog; ++h) {
+    __syncthreads();
+    if (h == 1 && threadIdx.x == 0) {
+      uint32_t v = 0;
+      for (int w = 0; w < kTreeThreads / kWave; ++w) v = max(v, wlen[w]);
+      if (v) atomicMax(J.maxlen_bits, v);
+    }
+    if (h == (int)kBlockLog) {
+      // heights < 6 are final and heights >= 6 still hold their own upper
+      // bound: block b of the chunk is position 64b plus subtree(64b + 32)
+      if (threadIdx.x < kChunk / 64) {
+        const uint32_t b = threadIdx.x;
+        const uint32_t blk = c * (kChunk / 64) + b;
+        if (blk < J.C) J.bmax[blk] = fmaxf(mx[64 * b], mx[64 * b + 32]);
+      }
+      __syncthreads();
+    }
+    for (uint32_t r = threadIdx.x; r < kChunk; r += kTreeThreads) {
+      if (r != 0 && (uint32_t)__builtin_ctz(r) == (uint32_t)h) {
+        const uint32_t half = 1u << (h - 1);
+        mx[r] = fmaxf(mx[r], fmaxf(mx[r - half], mx[r + half]));
+      }
+    }
+  }
+  __syncthreads();
+  for (uint32_t r = threadIdx.x; r < kChunk; r += kTreeThreads) {
+    const uint32_t p = c * kChunk + r;
+    if (r != 0 && p <= J.P) J.maxhi[p] = mx[r];
+  }
+}
+
+// Pass with shift S >= 11 on chunk c: positions p = q << S (q in the chunk),
+// real heights S .. S+10.  Leaves (odd q) combine the two children of height
+// S-1 computed by the previous pass.
+__device__ __forceinline__ void tree_high_chunk(const TreeJob& J, uint32_t c, uint32_t S) {
+  __shared__ float mx[kChunk];
+  const uint32_t D = J.d;
+  const uint32_t qmax = J.P >> S;
+  const float* __restrict__ rec = J.rec;
+  float* __restrict__ maxhi = J.maxhi;
+  for (uint32_t r = threadIdx.x; r < kChunk; r += kTreeThreads) {
+    const uint32_t q = c * kChunk + r;
+    float h = -INFINITY;
+    if (r != 0 && q <= qmax) {
+      const uint32_t p = q << S;
+      if (p <= J.n) h = rec[(size_t)p * 2 * D + 1];
+      if (q & 1u) {
+        const uint32_t half = 1u << (S - 1);
+        h = fmaxf(h, fmaxf(maxhi[p - half], maxhi[p + half]));
+      }
+    }
+    mx[r] = h;
+  }
+  for (int h = 1; h < kChunkLog; ++h) {
+    __syncthreads();
+    for (uint32_t r = threadIdx.x; r < kChunk; r += kTreeThreads) {
+      if (r != 0 && (uint32_t)__builtin_ctz(r) == (uint32_t)h) {
+        const uint32_t half = 1u << (h - 1);
+        mx[r] = fmaxf(mx[r], fmaxf(mx[r - half], mx[r + half]));
+      }
+    }
+  }
+  __syncthreads();
+  for (uint32_t r = threadIdx.x; r < kChunk; r += kTreeThreads) {
+    const uint32_t q = c * kChunk + r;
+    if (r != 0 && q <= qmax) maxhi[q << S] = mx[r];
+  }
+}
+
+}  // namespace ddm
