@@ -7,19 +7,28 @@ interval trees over the subscriptions (sort + tree + maxupper), match every
 update (BITS counts, update order, count traversal, scan, fill traversal,
 segment sort) into a preallocated output, and release the trees.  As in the
 paper's measurements, preprocessing (the tree build) is inside the timed
-step.
+step; the match alone on a resident tree is reported beside it.
 
-Prints ONE JSON line: pairs/s (value), regions/s, the roofline of the
-dominant kernel (its launch durations measured with HIP events on the
-stream it is launched on, during the timed steps) and the CPU oracle's rate
-on the host.
+Workloads:
+  d2_uniform (default)  d=2, 500,000 subscriptions + 500,000 updates, square
+                        side 1000 on [0, 1e6)^2 (alpha = 1), seed 1
+  d2_hotspot            d=2, 500,000 + 500,000 boxes around 16 Gaussian
+                        hotspots, log-normal sides (median 1e4), seed 2
+  batch256              256 independent instances (N log-uniform in
+                        [1e3, 2e5], d in {1,2,3}, alpha log-uniform in
+                        [0.01, 100], seed 3), one graph replay per step
+
+Prints ONE JSON line: pairs/s (value), regions/s, per-step statistics, the
+roofline of the dominant kernel (its launch durations measured with HIP
+events on the stream it is launched on) and the CPU oracle's rate on the
+host.
 """
 from __future__ import annotations
 
 import argparse
 import json
-import math
 import os
+import statistics
 import sys
 import time
 
@@ -30,6 +39,7 @@ sys.path.insert(0, ROOT)
 # 4 SIMDs x 16 lanes x 2.4 GHz lane-operations per second.
 HBM_PEAK_GBS = 8000.0
 ALU_PEAK_GOPS = 256 * 4 * 16 * 2.4
+METRIC = "matched pairs/sec + regions/sec at d=2 N=1M alpha=1; p99 latency (serving)"
 
 
 def log(msg):
@@ -39,35 +49,87 @@ def log(msg):
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--steps", type=int, default=30)
+    ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--traversal", default="auto", choices=["auto", "lane", "tile"])
-    ap.add_argument("--workload", default="d2_uniform", choices=["d2_uniform", "d2_hotspot"])
+    ap.add_argument("--workload", default="d2_uniform",
+                    choices=["d2_uniform", "d2_hotspot", "batch256"])
     ap.add_argument("--path", default="both", choices=["plain", "learned", "both"],
                     help="plain two-pass, learned single-pass, or both (value = faster)")
     ap.add_argument("--predictor", default="",
                     help="saved predictor (.npz); default: train one before timing")
+    ap.add_argument("--tuning", default="",
+                    help="batch256: tuning table (JSON); default: the packaged table")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample", type=int, default=0,
                     help="updates in the oracle's timed sample (0 = auto)")
     return ap.parse_args()
 
 
-def main():
-    args = parse()
-    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
-        print("bench.py measures one GPU only: every node here exposes a single MI355X and "
-              "the matcher has no multi-GPU path; run with --gpus 1.", file=sys.stderr)
-        sys.exit(2)
+def step_stats(ms):
+    return {"mean": round(statistics.fmean(ms), 4), "median": round(statistics.median(ms), 4),
+            "min": round(min(ms), 4)}
 
+
+def candidates(inst):
+    """Per-dimension candidate tests of one traversal pass: sum over updates
+    of the smallest exact per-dimension count (closed BITS identity)."""
     import numpy as np
+    c = None
+    for k in range(inst.d):
+        lo, hi = np.sort(inst.s_lo[k]), np.sort(inst.s_hi[k])
+        ck = np.searchsorted(lo, inst.u_hi[k], side="right") \
+            - np.searchsorted(hi, inst.u_lo[k], side="left")
+        c = ck if c is None else np.minimum(c, ck)
+    return float(c.sum())
+
+
+def roofline_alu(cand, ops, dom, dom_avg_ms):
+    # Unit of work of a traversal pass: the per-dimension candidate test of
+    # Algorithm 3 (an update against a subscription that meets it in the probe
+    # dimension), 2*d float compares each.
+    achieved = ops / (dom_avg_ms / 1e3) / 1e9
+    return {"bound": "alu", "achieved": round(achieved, 1), "peak": ALU_PEAK_GOPS,
+            "unit": "Gop/s", "frac": round(achieved / ALU_PEAK_GOPS, 4), "traffic": None,
+            "kernel": dom, "kernel_avg_ms": round(dom_avg_ms, 4),
+            "candidates_per_launch": int(cand)}
+
+
+def evented_steps(step, steps):
+    """Run `steps` steps with a HIP event between consecutive steps on the
+    current stream; returns (wall ms per step, per-step ms list, last K)."""
+    import torch
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(steps + 1)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ev[0].record()
+    K = None
+    for i in range(steps):
+        K = step()
+        ev[i + 1].record()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    per = [ev[i].elapsed_time(ev[i + 1]) for i in range(steps)]
+    return (t1 - t0) * 1e3 / steps, per, K
+
+
+def oracle_rate(inst, cores, sample, what):
+    import oracle
+    t0 = time.perf_counter()
+    ok = oracle.itm(inst.s_lo, inst.s_hi, inst.u_lo[:, :sample], inst.u_hi[:, :sample],
+                    threads=cores)
+    dt = time.perf_counter() - t0
+    return {"value": round(len(ok) / dt, 1), "unit": "pairs/s", "cores": cores,
+            "kind": "oracle",
+            "sample": f"{what}: all {inst.n} subscriptions x first {sample} updates, tree "
+                      f"build included, {dt:.2f}s, {len(ok)} pairs"}
+
+
+def bench_single(args):
     import torch
 
     import paper_1309_3458_amd as P
     from paper_1309_3458_amd import workloads as W
-
-    assert torch.cuda.is_available(), "bench.py needs a GPU"
-    torch.cuda.set_device(0)
 
     t0 = time.time()
     if args.workload == "d2_uniform":
@@ -93,9 +155,15 @@ def main():
     # size the output once (untimed), then reuse it
     t = P.build(s_lo, s_hi)
     K0 = int(P.match(t, u_lo, u_hi, traversal=args.traversal).numel())
-    t.free()
     out = torch.empty(K0 + 1, dtype=torch.int64, device="cuda")
     log(f"K = {K0}")
+
+    # the match alone on a resident tree (untimed region)
+    for _ in range(args.warmup):
+        P.match(t, u_lo, u_hi, traversal=args.traversal, out=out)
+    _, per_match, _ = evented_steps(
+        lambda: P.match(t, u_lo, u_hi, traversal=args.traversal, out=out).numel(), args.steps)
+    t.free()
 
     def step_plain():
         t = P.build(s_lo, s_hi)
@@ -113,7 +181,7 @@ def main():
 
     def timed(step, name):
         for i in range(args.warmup):
-            K = step()
+            step()
         torch.cuda.synchronize()
         # which traversal kernel dominates: one step with every launch evented
         P.prof_enable(True)
@@ -126,17 +194,12 @@ def main():
             + json.dumps({k: round(v[0], 4) for k, v in sorted(prof.items())}))
         # timed region: HIP events only around the dominant kernel's launches
         P.prof_enable(True, only=dom)
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        for i in range(args.steps):
-            K = step()
-        torch.cuda.synchronize()
-        t1 = time.perf_counter()
+        wall, per, K = evented_steps(step, args.steps)
         dprof = P.prof_read()
         P.prof_enable(False)
         assert K == K0
         dms, dn = dprof[dom]
-        return {"ms_per_step": (t1 - t0) * 1e3 / args.steps, "dominant": dom,
+        return {"ms_per_step": wall, "step_ms": step_stats(per), "dominant": dom,
                 "dominant_avg_ms": dms / dn, "per_kernel_ms": prof}
 
     res = {}
@@ -148,42 +211,20 @@ def main():
         res["learned"]["slots"] = info.get("slots")
     best = min(res, key=lambda k: res[k]["ms_per_step"])
     ms_step = res[best]["ms_per_step"]
-    pairs_s = K0 / (ms_step / 1e3)
-    regions_s = (inst.n + inst.m) / (ms_step / 1e3)
-    dom, dom_avg_ms = res[best]["dominant"], res[best]["dominant_avg_ms"]
-
-    # Dominant kernel: one traversal pass.  Its unit of work is the per-
-    # dimension candidate test of Algorithm 3 (an update against a
-    # subscription that meets it in the probe dimension), 2*d float compares
-    # each.  Candidates per pass = sum_j min_k c_{j,k} (exact BITS counts,
-    # recomputed here on the host).
-    ks = [np.sort(inst.s_lo[k]) for k in range(inst.d)]
-    he = [np.sort(inst.s_hi[k]) for k in range(inst.d)]
-    c = np.stack([np.searchsorted(ks[k], inst.u_hi[k], side="right")
-                  - np.searchsorted(he[k], inst.u_lo[k], side="left") for k in range(inst.d)])
-    cand = float(c.min(axis=0).sum())
-    ops = cand * 2 * inst.d
-    achieved = ops / (dom_avg_ms / 1e3) / 1e9
-    roofline = {"bound": "alu", "achieved": round(achieved, 1), "peak": ALU_PEAK_GOPS,
-                "unit": "Gop/s", "frac": round(achieved / ALU_PEAK_GOPS, 4), "traffic": None,
-                "kernel": dom, "kernel_avg_ms": round(dom_avg_ms, 4),
-                "candidates_per_launch": int(cand)}
+    cand = candidates(inst)
+    roofline = roofline_alu(cand, cand * 2 * inst.d, res[best]["dominant"],
+                            res[best]["dominant_avg_ms"])
 
     cpu = None
     if not args.no_cpu_baseline:
-        import oracle
         cores = min(os.cpu_count() or 1, 16)
         sample = args.cpu_sample or (inst.m if args.workload == "d2_uniform" else 2000)
-        t0 = time.perf_counter()
-        ok = oracle.itm(inst.s_lo, inst.s_hi, inst.u_lo[:, :sample], inst.u_hi[:, :sample],
-                        threads=cores)
-        dt = time.perf_counter() - t0
-        cpu = {"value": round(len(ok) / dt, 1), "unit": "pairs/s", "cores": cores,
-               "kind": "oracle",
-               "sample": f"all {inst.n} subscriptions x first {sample} updates, tree build "
-                         f"included, {dt:.2f}s, {len(ok)} pairs"}
+        cpu = oracle_rate(inst, cores, sample, wname)
+        # the plain sequential oracle on a tenth of the sample
+        one = oracle_rate(inst, 1, max(1, sample // 10), wname)
+        cpu["single_thread"] = {"value": one["value"], "sample": one["sample"]}
 
-    paths = {k: {"ms_per_step": round(v["ms_per_step"], 4),
+    paths = {k: {"ms_per_step": round(v["ms_per_step"], 4), "step_ms": v["step_ms"],
                  "pairs_per_s": round(K0 / (v["ms_per_step"] / 1e3), 1),
                  **({"overflowed": v.get("overflowed"), "slots": v.get("slots")}
                     if k == "learned" else {})}
@@ -191,20 +232,15 @@ def main():
     if "plain" in res and "learned" in res:
         paths["learned_speedup_vs_plain"] = round(
             res["plain"]["ms_per_step"] / res["learned"]["ms_per_step"], 4)
-    rec = {
-        "metric": "matched pairs/sec + regions/sec at d=2 N=1M alpha=1; p99 latency (serving)",
-        "value": round(pairs_s, 1),
+    return {
+        "metric": METRIC,
+        "value": round(K0 / (ms_step / 1e3), 1),
         "unit": "pairs/s",
-        "regions_per_s": round(regions_s, 1),
-        "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
+        "regions_per_s": round((inst.n + inst.m) / (ms_step / 1e3), 1),
         "ms_per_step": round(ms_step, 4),
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
+        "step_ms": res[best]["step_ms"],
+        "match_only_ms": step_stats(per_match),
         "dtype": "f32",
-        "data": "synthetic",
         "config": {"workload": wname, "d": inst.d, "n": inst.n, "m": inst.m,
                    "seed": seed, "K": int(K0), "traversal": args.traversal, "path": best},
         "paths": paths,
@@ -215,7 +251,123 @@ def main():
         "roofline": roofline,
         "cpu_baseline": cpu,
     }
-    print(json.dumps(rec), flush=True)
+
+
+def bench_batch(args):
+    import numpy as np
+    import torch
+
+    import paper_1309_3458_amd as P
+    from paper_1309_3458_amd import tune
+    from paper_1309_3458_amd import workloads as W
+
+    t0 = time.time()
+    specs = W.batch_specs(3, 256)
+    insts = [W.instance_from_spec(s) for s in specs]
+    log(f"batch256 generated in {time.time() - t0:.2f}s: "
+        f"sum n={sum(i.n for i in insts)} sum m={sum(i.m for i in insts)}")
+    dev = lambda a: torch.from_numpy(a).cuda()
+    tens = [(dev(i.s_lo), dev(i.s_hi), dev(i.u_lo), dev(i.u_hi)) for i in insts]
+    table = tune.Table.load(args.tuning or tune.DEFAULT_TABLE)
+    qpts, wpc = table.qpts(specs), table.waves_per_cu
+    K0 = tune.batch_total(tens, qpts)
+    out = torch.empty(K0, dtype=torch.int64, device="cuda")
+    log(f"K = {K0}; tuned classes {len(table.qpt_map)}, waves/CU {wpc}")
+    b = P.Batch(tens, K0, qpts=qpts, waves_per_cu=wpc, use_graph=True, out=out)
+
+    def step():
+        b.run()
+        return K0
+
+    for _ in range(args.warmup):
+        step()
+    wall, per, _ = evented_steps(step, args.steps)
+    tot, _ = b.result()
+    assert tot == K0
+    b.free()
+
+    # per-kernel durations: the same sequence launched eagerly, every launch
+    # evented once, then HIP events around the dominant traversal only
+    e = P.Batch(tens, K0, qpts=qpts, waves_per_cu=wpc, use_graph=False, out=out)
+    e.run()
+    torch.cuda.synchronize()
+    P.prof_enable(True)
+    e.run()
+    torch.cuda.synchronize()
+    prof = P.prof_read()
+    P.prof_enable(False)
+    dom = max((k for k in prof if k.startswith("batch_traverse")), key=lambda k: prof[k][0])
+    log("[batch] per-kernel ms (one eager step): "
+        + json.dumps({k: round(v[0], 4) for k, v in sorted(prof.items())}))
+    P.prof_enable(True, only=dom)
+    eager_wall, _, _ = evented_steps(lambda: e.run(), args.steps)
+    dprof = P.prof_read()
+    P.prof_enable(False)
+    e.result()
+    e.free()
+    dms, dn = dprof[dom]
+    cands = [candidates(i) for i in insts]
+    ops = sum(c * 2 * i.d for c, i in zip(cands, insts))
+    roofline = roofline_alu(sum(cands), ops, dom, dms / dn)
+    roofline["timing"] = "eager launches of the same sequence"
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        import oracle
+        cores = min(os.cpu_count() or 1, 16)
+        # a bounded sample: whole instances in a fixed shuffled order until
+        # ~10 s of oracle time
+        order = np.random.default_rng(11).permutation(len(insts))
+        pairs, dt, used = 0, 0.0, 0
+        for i in order:
+            inst = insts[i]
+            t1 = time.perf_counter()
+            pairs += len(oracle.itm(inst.s_lo, inst.s_hi, inst.u_lo, inst.u_hi, threads=cores))
+            dt += time.perf_counter() - t1
+            used += 1
+            if dt > 10.0:
+                break
+        cpu = {"value": round(pairs / dt, 1), "unit": "pairs/s", "cores": cores,
+               "kind": "oracle",
+               "sample": f"{used} whole instances of batch256 in a fixed shuffled order, "
+                         f"{dt:.2f}s, {pairs} pairs"}
+
+    n_tot = sum(i.n + i.m for i in insts)
+    return {
+        "metric": METRIC,
+        "value": round(K0 / (wall / 1e3), 1),
+        "unit": "pairs/s",
+        "regions_per_s": round(n_tot / (wall / 1e3), 1),
+        "ms_per_step": round(wall, 4),
+        "step_ms": step_stats(per),
+        "eager_ms_per_step": round(eager_wall, 4),
+        "dtype": "f32",
+        "config": {"workload": "batch256_N1e3-2e5_d1-3_alpha0.01-100", "instances": 256,
+                   "seed": 3, "K": int(K0), "regions": int(n_tot), "graph": True,
+                   "waves_per_cu": wpc,
+                   "qpt_hist": {str(q): qpts.count(q) for q in sorted(set(qpts))}},
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+    }
+
+
+def main():
+    args = parse()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print("bench.py measures one GPU only: every node here exposes a single MI355X and "
+              "the matcher has no multi-GPU path; run with --gpus 1.", file=sys.stderr)
+        sys.exit(2)
+    import torch
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    torch.cuda.set_device(0)
+    rec = bench_batch(args) if args.workload == "batch256" else bench_single(args)
+    head = {"metric": rec.pop("metric"), "value": rec.pop("value"), "unit": rec.pop("unit"),
+            "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+            "ms_per_step": rec.pop("ms_per_step"), "higher_is_better": True,
+            "scaling": "weak", "vs_baseline": None, "dtype": rec.pop("dtype"),
+            "data": "synthetic", "config": rec.pop("config")}
+    head.update(rec)
+    print(json.dumps(head), flush=True)
 
 
 if __name__ == "__main__":

@@ -299,12 +299,13 @@ typedef struct {
   uint32_t n;           /* 0 < n < 2^20                                     */
   uint32_t m;           /* m > 0                                            */
   uint32_t d;           /* 1 <= d <= DDM_MAX_D                              */
-  uint32_t reserved;    /* must be 0                                        */
+  uint32_t qpt;         /* updates per traversal work item of this instance:
+                           16, 32 or 64; 0 = the batch's opts.qpt          */
 } ddm_batch_instance;
 
 typedef struct {
-  uint32_t qpt;          /* updates per traversal work item: 16, 32 or 64
-                            (0 = 64)                                        */
+  uint32_t qpt;          /* default updates per traversal work item: 16, 32
+                            or 64 (0 = 64)                                  */
   uint32_t waves_per_cu; /* persistent traversal occupancy, 1..64 (0 = 16)  */
   uint32_t use_graph;    /* nonzero: capture on the first run, then replay  */
   uint32_t reserved[5];  /* must be 0                                       */

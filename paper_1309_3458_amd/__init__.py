@@ -331,12 +331,14 @@ class Batch:
     instances: list of (s_lo, s_hi, u_lo, u_hi) float32 GPU tensors, [d, n]
     and [d, m].  The output buffer (int64, `capacity` keys) is allocated
     here; after run() + result(), pairs(i) is instance i's sorted keys (the
-    bytes match() returns for that instance alone).  The coordinate tensors
+    bytes match() returns for that instance alone).  qpts optionally gives
+    each instance's work-item size (16, 32 or 64; see tune.py), qpt and
+    waves_per_cu the batch defaults.  The coordinate tensors
     may be overwritten in place between runs (same shapes).
     """
 
     def __init__(self, instances, capacity: int, qpt: int = 64, waves_per_cu: int = 16,
-                 use_graph: bool = True, out=None):
+                 use_graph: bool = True, out=None, qpts=None):
         from ._native import BatchInstance, BatchOpts
         torch = _torch()
         keep = []
@@ -350,6 +352,7 @@ class Batch:
             arr[i].sub_lo, arr[i].sub_hi = _ptr(s_lo), _ptr(s_hi)
             arr[i].upd_lo, arr[i].upd_hi = _ptr(u_lo), _ptr(u_hi)
             arr[i].n, arr[i].m, arr[i].d = int(s_lo.shape[1]), int(u_lo.shape[1]), int(s_lo.shape[0])
+            arr[i].qpt = int(qpts[i]) if qpts is not None else 0
         if out is None:
             dev = keep[0].device if keep else "cuda"
             out = torch.empty(max(1, int(capacity)), dtype=torch.int64, device=dev)

@@ -44,7 +44,7 @@ class BatchInstance(ctypes.Structure):
     _fields_ = [("sub_lo", ctypes.c_void_p), ("sub_hi", ctypes.c_void_p),
                 ("upd_lo", ctypes.c_void_p), ("upd_hi", ctypes.c_void_p),
                 ("n", ctypes.c_uint32), ("m", ctypes.c_uint32), ("d", ctypes.c_uint32),
-                ("reserved", ctypes.c_uint32)]
+                ("qpt", ctypes.c_uint32)]
 
 
 class BatchOpts(ctypes.Structure):

@@ -35,6 +35,7 @@ struct BInst {
   uint32_t qbase;  // first global update index
   uint32_t bbase;  // first bucket
   uint32_t nb;     // buckets per dimension
+  uint32_t qpt;    // updates per traversal work item
   uint64_t ebase;  // first element of the key kernel (d * n elements)
   int32_t* flag;   // nonzero: invalid coordinates
   uint32_t* klo;   // d * n lower keys (tree k: klo + k n)
@@ -184,7 +185,7 @@ __global__ __launch_bounds__(256) void b_scatter_kernel(const uint32_t* __restri
 // of their tiles for the count pass (d > 1 only) and the fill pass
 __global__ __launch_bounds__(1024) void b_groups_kernel(const BInst* __restrict__ I, uint32_t count,
                                                         const uint64_t* __restrict__ boff,
-                                                        uint32_t qpt, uint32_t* __restrict__ gstart,
+                                                        uint32_t* __restrict__ gstart,
                                                         uint32_t* __restrict__ gcount,
                                                         uint32_t* __restrict__ tpc,
                                                         uint32_t* __restrict__ tpf) {
@@ -208,7 +209,7 @@ __global__ __launch_bounds__(1024) void b_groups_kernel(const BInst* __restrict_
       }
       gstart[g] = st;
       gcount[g] = sz;
-      tf = (sz + qpt - 1) / qpt;
+      tf = (sz + b.qpt - 1) / b.qpt;
       tc = b.d > 1 ? tf : 0u;
     }
     uint32_t ic = tc, jf = tf;
@@ -257,7 +258,7 @@ template <bool FILL>
 __global__ __launch_bounds__(kTileWaves * kWave) void b_traverse_kernel(
     const BInst* __restrict__ I, uint32_t G, const uint32_t* __restrict__ tp,
     const uint32_t* __restrict__ gstart, const uint32_t* __restrict__ gcount,
-    const uint32_t* __restrict__ perm, uint32_t qpt, uint32_t* __restrict__ ticket,
+    const uint32_t* __restrict__ perm, uint32_t* __restrict__ ticket,
     const uint32_t* __restrict__ status, SegOut O) {
   __shared__ float s_cand[kTileWaves][2 * DDM_MAX_D * kRing];
   __shared__ uint32_t s_cid[kTileWaves][kRing];
@@ -280,11 +281,12 @@ __global__ __launch_bounds__(kTileWaves * kWave) void b_traverse_kernel(
     }
     const uint32_t g = uniform_u32(lo);
     const uint32_t inst = g / DDM_MAX_D, k = g % DDM_MAX_D;
+    const BInst& b = I[inst];
+    const uint32_t qpt = uniform_u32(b.qpt);
     const uint32_t lt = item - uniform_u32(tp[g]);
     const uint32_t gs = uniform_u32(gcount[g]);
     const uint32_t qbeg = uniform_u32(gstart[g]) + lt * qpt;
     const uint32_t nq = min(qpt, gs - lt * qpt);
-    const BInst& b = I[inst];
     switch (uniform_u32(b.d)) {
       case 1:
         tile_body<1, FILL>(b.T, b.u_lo, b.u_hi, b.m, perm, b.qbase, k, qbeg, nq, O,
@@ -420,15 +422,15 @@ static ddm_status batch_enqueue(ddm_batch* b, hipStream_t s) {
   if (r != DDM_OK) return r;
   b_scatter_kernel<<<(b->M + 255) / 256, 256, 0, s>>>(b->bucket, b->rank, b->M, b->boff, b->perm);
   DDM_LAUNCHED("b_scatter_kernel");
-  b_groups_kernel<<<1, 1024, 0, s>>>(b->inst, b->count, b->boff, b->opts.qpt, b->gstart,
-                                     b->gcount, b->tpc, b->tpf);
+  b_groups_kernel<<<1, 1024, 0, s>>>(b->inst, b->count, b->boff, b->gstart, b->gcount, b->tpc,
+                                     b->tpf);
   DDM_LAUNCHED("b_groups_kernel");
   {
     ProfScope ps("batch_traverse_count", s);
     SegOut O{};
     O.cnt = b->cnt;
     b_traverse_kernel<false><<<b->grid, kTileWaves * kWave, 0, s>>>(
-        b->inst, b->G, b->tpc, b->gstart, b->gcount, b->perm, b->opts.qpt, b->tickets,
+        b->inst, b->G, b->tpc, b->gstart, b->gcount, b->perm, b->tickets,
         b->status, O);
     DDM_LAUNCHED("b_traverse_kernel");
   }
@@ -448,7 +450,7 @@ static ddm_status batch_enqueue(ddm_batch* b, hipStream_t s) {
     O.base = b->off;
     O.out = b->out;
     b_traverse_kernel<true><<<b->grid, kTileWaves * kWave, 0, s>>>(
-        b->inst, b->G, b->tpf, b->gstart, b->gcount, b->perm, b->opts.qpt, b->tickets + 1,
+        b->inst, b->G, b->tpf, b->gstart, b->gcount, b->perm, b->tickets + 1,
         b->status, O);
     DDM_LAUNCHED("b_traverse_kernel");
   }
@@ -499,9 +501,10 @@ extern "C" ddm_status ddm_batch_create(const ddm_batch_instance* inst, uint32_t 
   for (uint32_t i = 0; i < count; ++i) {
     const ddm_batch_instance& q = inst[i];
     if (q.d < 1 || q.d > DDM_MAX_D || q.n == 0 || q.m == 0 || !q.sub_lo || !q.sub_hi ||
-        !q.upd_lo || !q.upd_hi || q.n >= (1u << 20) || q.reserved) {
+        !q.upd_lo || !q.upd_hi || q.n >= (1u << 20) ||
+        (q.qpt != 0 && q.qpt != 16 && q.qpt != 32 && q.qpt != 64)) {
       set_detail("ddm_batch_create: every instance needs 1 <= d <= DDM_MAX_D, "
-                 "0 < n < 2^20, m > 0 and coordinate pointers");
+                 "0 < n < 2^20, m > 0, coordinate pointers and qpt in {0, 16, 32, 64}");
       return DDM_E_INVALID_ARG;
     }
     uint32_t H = 0;
@@ -606,6 +609,7 @@ extern "C" ddm_status ddm_batch_create(const ddm_batch_instance* inst, uint32_t 
     bi.qbase = (uint32_t)qbase;
     bi.bbase = (uint32_t)bbase;
     bi.nb = std::max<uint32_t>(1, (q.m + 7) / 8);
+    bi.qpt = q.qpt ? q.qpt : o.qpt;
     bi.ebase = ebase;
     qbase += q.m;
     bbase += (uint64_t)q.d * bi.nb;
