@@ -342,6 +342,99 @@ ddm_status ddm_batch_result(ddm_batch* b, uint64_t* total, uint64_t* ranges);
  * ignored.                                                                    */
 void ddm_batch_free(ddm_batch* b);
 
+/* ---------------------------------------------------------------------------
+ * Serving loop (an addition to the paper; every request is the problem of
+ * Sec. III, matched as ddm_build + ddm_match / ddm_match_learned_begin do).
+ *
+ * Requests arrive at any time (ddm_server_submit, thread-safe, returns at
+ * once) and are matched concurrently by `workers` host threads, each
+ * driving its own HIP stream: a request starts as soon as a worker is free
+ * and the device-memory budget admits it, so requests overlap on the device
+ * with the ones already running.  Admission is by footprint: inputs + trees
+ * + match scratch when a request starts (FIFO order), then the predicted
+ * output (learned slot arena) and the exact output once known; the oldest
+ * request in flight may always exceed the budget, so progress is
+ * guaranteed.  With a predictor, requests of d <= 3 use the single-pass
+ * learned sizing; results are bit-identical either way.
+ *
+ * Results are copied into a pinned host pool owned by the server (or stay
+ * in device memory with deliver_device) and are announced through a
+ * completion queue (ddm_server_wait_any); the caller reads them with
+ * ddm_server_result and returns their memory with ddm_server_release.
+ * Timestamps are CLOCK_MONOTONIC nanoseconds.
+ * --------------------------------------------------------------------------*/
+typedef struct {
+  uint64_t hbm_budget;     /* device bytes requests in flight may hold
+                              (0 = 64 GiB)                                   */
+  uint64_t host_pool;      /* pinned host bytes for results (0 = 4 GiB)      */
+  uint32_t workers;        /* concurrent requests, 1..64 (0 = 8)             */
+  uint32_t tree_cache;     /* keyed trees kept resident after their request
+                              (LRU); 0 = none                                */
+  uint32_t deliver_device; /* nonzero: results stay in device memory         */
+  uint32_t reserved[4];    /* must be 0                                      */
+} ddm_server_opts;
+
+typedef struct {
+  const float* sub_lo;     /* device, [d][n]; may be NULL with a resident
+                              tree_key                                        */
+  const float* sub_hi;
+  const float* upd_lo;     /* device, [d][m]                                  */
+  const float* upd_hi;
+  uint32_t n, m, d;
+  uint32_t reserved;       /* must be 0                                       */
+  uint64_t tree_key;       /* nonzero: keep the subscription tree resident
+                              under this key / reuse the resident tree        */
+} ddm_request;
+
+typedef struct {
+  int32_t status;          /* 1 = pending, else the request's ddm_status      */
+  uint32_t on_device;      /* pairs is a device pointer                       */
+  uint64_t count;          /* K                                               */
+  const uint64_t* pairs;   /* K sorted keys, valid until ddm_server_release   */
+  int64_t t_arrival_ns;    /* arrival (given to submit, or submit time)       */
+  int64_t t_start_ns;      /* admitted onto a worker                          */
+  int64_t t_done_ns;       /* result in host (or device) memory               */
+  uint64_t slots;          /* learned slot arena of the request (0 if none)   */
+  uint32_t overflowed;     /* updates that took the exact fallback            */
+  uint32_t pad;
+} ddm_result;
+
+typedef struct {
+  uint64_t submitted, completed, queued, in_flight;
+  uint64_t hbm_used, hbm_peak, host_pool_used, trees_resident;
+} ddm_server_counters;
+
+typedef struct ddm_server ddm_server;
+
+/* Starts the worker threads on the current device.  pred may be NULL (plain
+ * two-pass matching); it must outlive the server.                            */
+ddm_status ddm_server_create(const ddm_server_opts* opts, ddm_predictor* pred,
+                             ddm_server** out);
+
+/* Queues a request.  The coordinate arrays must stay valid until the request
+ * completes; the server's streams wait for the work enqueued on `stream`
+ * before reading them.  arrival_ns: the request's arrival time (0 = now).   */
+ddm_status ddm_server_submit(ddm_server* s, const ddm_request* req, int64_t arrival_ns,
+                             void* stream, uint64_t* ticket);
+
+/* Waits up to timeout_ms for completions and moves at most max_tickets
+ * completed tickets into `tickets` (host); returns how many.                 */
+uint32_t ddm_server_wait_any(ddm_server* s, uint32_t timeout_ms, uint64_t* tickets,
+                             uint32_t max_tickets);
+
+/* State and result of a request (host struct).  For a failed request
+ * ddm_last_error_detail() holds its detail after this call.                 */
+ddm_status ddm_server_result(ddm_server* s, uint64_t ticket, ddm_result* res);
+
+/* Returns a finished request's result memory to the server.                 */
+ddm_status ddm_server_release(ddm_server* s, uint64_t ticket);
+
+ddm_status ddm_server_stats(ddm_server* s, ddm_server_counters* out);
+
+/* Waits for queued and running requests, stops the workers and frees
+ * everything the server holds (unreleased results included).                */
+void ddm_server_destroy(ddm_server* s);
+
 /* Static message for a status code.                                          */
 const char* ddm_strerror(ddm_status s);
 

@@ -15,7 +15,8 @@ from ._native import (DDMError, DDM_E_CAPACITY, FEATURES, PREDICTOR_PARAMS, TRAV
                       header_functions, lib, opts as _opts)
 
 __all__ = ["build", "match", "count", "Tree", "DDMError", "prof_enable", "prof_read",
-           "TRAVERSE", "header_functions", "Predictor", "features", "match_learned", "Batch"]
+           "TRAVERSE", "header_functions", "Predictor", "features", "match_learned", "Batch",
+           "Server"]
 
 
 def _torch():
@@ -403,5 +404,112 @@ class Batch:
     def __del__(self):
         try:
             self.free()
+        except Exception:
+            pass
+
+
+class Server:
+    """Concurrent matching of requests that arrive at any time (ddm_server_*).
+
+    submit() queues (s_lo, s_hi, u_lo, u_hi) GPU tensors and returns a
+    ticket; the tensors are kept alive until the ticket is released.
+    wait_any() blocks (releasing the GIL) until requests complete;
+    result(ticket) returns a dict with the status, timestamps and a numpy
+    copy of the sorted keys (uint64) when `copy` is set.
+    """
+
+    def __init__(self, predictor: Predictor | None = None, hbm_budget: int = 0,
+                 host_pool: int = 0, workers: int = 8, tree_cache: int = 0,
+                 deliver_device: bool = False):
+        from ._native import ServerOpts
+        o = ServerOpts()
+        o.hbm_budget, o.host_pool = int(hbm_budget), int(host_pool)
+        o.workers, o.tree_cache, o.deliver_device = int(workers), int(tree_cache), \
+            int(bool(deliver_device))
+        h = ctypes.c_void_p()
+        check(lib().ddm_server_create(ctypes.byref(o),
+                                      predictor.handle if predictor is not None else None,
+                                      ctypes.byref(h)), "ddm_server_create")
+        self._h = h
+        self._pred = predictor
+        self._keep = {}
+        self.deliver_device = bool(deliver_device)
+
+    @property
+    def handle(self):
+        if self._h is None:
+            raise RuntimeError("server already destroyed")
+        return self._h
+
+    def submit(self, s_lo, s_hi, u_lo, u_hi, tree_key: int = 0, arrival_ns: int = 0,
+               stream=None) -> int:
+        from ._native import Request
+        u_lo, u_hi = _coords(u_lo, u_hi, "Server updates")
+        r = Request()
+        keep = [u_lo, u_hi]
+        if s_lo is not None:
+            s_lo, s_hi = _coords(s_lo, s_hi, "Server subscriptions")
+            keep += [s_lo, s_hi]
+            r.sub_lo, r.sub_hi, r.n = _ptr(s_lo), _ptr(s_hi), int(s_lo.shape[1])
+        r.upd_lo, r.upd_hi = _ptr(u_lo), _ptr(u_hi)
+        r.m, r.d, r.tree_key = int(u_lo.shape[1]), int(u_lo.shape[0]), int(tree_key)
+        t = ctypes.c_uint64()
+        check(lib().ddm_server_submit(self.handle, ctypes.byref(r), int(arrival_ns),
+                                      _stream_handle(stream), ctypes.byref(t)),
+              "ddm_server_submit")
+        self._keep[int(t.value)] = keep
+        return int(t.value)
+
+    def wait_any(self, timeout_ms: int = 100, max_tickets: int = 1024) -> list[int]:
+        buf = (ctypes.c_uint64 * max_tickets)()
+        n = lib().ddm_server_wait_any(self.handle, int(timeout_ms), buf, max_tickets)
+        return [int(buf[i]) for i in range(n)]
+
+    def result(self, ticket: int, copy: bool = True) -> dict:
+        import numpy as np
+        from ._native import Result
+        r = Result()
+        check(lib().ddm_server_result(self.handle, int(ticket), ctypes.byref(r)),
+              "ddm_server_result")
+        d = {"status": int(r.status), "count": int(r.count), "t_arrival_ns": int(r.t_arrival_ns),
+             "t_start_ns": int(r.t_start_ns), "t_done_ns": int(r.t_done_ns),
+             "slots": int(r.slots), "overflowed": int(r.overflowed)}
+        if r.status not in (0, 1):
+            d["detail"] = lib().ddm_last_error_detail().decode()
+        if copy and r.status == 0:
+            if r.count == 0:
+                d["pairs"] = np.zeros(0, dtype=np.uint64)
+            elif r.on_device:
+                torch = _torch()
+
+                class _Dev:  # a view of the server's device buffer
+                    __cuda_array_interface__ = {"shape": (int(r.count),), "typestr": "<i8",
+                                                "data": (int(r.pairs), False), "version": 2}
+
+                d["pairs"] = torch.as_tensor(_Dev(), device="cuda").cpu().numpy().view(np.uint64)
+            else:
+                buf = (ctypes.c_uint64 * int(r.count)).from_address(int(r.pairs))
+                d["pairs"] = np.frombuffer(buf, dtype=np.uint64).copy()
+        return d
+
+    def release(self, ticket: int):
+        check(lib().ddm_server_release(self.handle, int(ticket)), "ddm_server_release")
+        self._keep.pop(int(ticket), None)
+
+    def stats(self) -> dict:
+        from ._native import ServerCounters
+        c = ServerCounters()
+        check(lib().ddm_server_stats(self.handle, ctypes.byref(c)), "ddm_server_stats")
+        return {k: int(getattr(c, k)) for k, _ in ServerCounters._fields_}
+
+    def close(self):
+        if self._h is not None:
+            lib().ddm_server_destroy(self._h)
+            self._h = None
+            self._keep.clear()
+
+    def __del__(self):
+        try:
+            self.close()
         except Exception:
             pass

@@ -52,6 +52,33 @@ class BatchOpts(ctypes.Structure):
                 ("use_graph", ctypes.c_uint32), ("reserved", ctypes.c_uint32 * 5)]
 
 
+class ServerOpts(ctypes.Structure):
+    _fields_ = [("hbm_budget", ctypes.c_uint64), ("host_pool", ctypes.c_uint64),
+                ("workers", ctypes.c_uint32), ("tree_cache", ctypes.c_uint32),
+                ("deliver_device", ctypes.c_uint32), ("reserved", ctypes.c_uint32 * 4)]
+
+
+class Request(ctypes.Structure):
+    _fields_ = [("sub_lo", ctypes.c_void_p), ("sub_hi", ctypes.c_void_p),
+                ("upd_lo", ctypes.c_void_p), ("upd_hi", ctypes.c_void_p),
+                ("n", ctypes.c_uint32), ("m", ctypes.c_uint32), ("d", ctypes.c_uint32),
+                ("reserved", ctypes.c_uint32), ("tree_key", ctypes.c_uint64)]
+
+
+class Result(ctypes.Structure):
+    _fields_ = [("status", ctypes.c_int32), ("on_device", ctypes.c_uint32),
+                ("count", ctypes.c_uint64), ("pairs", ctypes.c_void_p),
+                ("t_arrival_ns", ctypes.c_int64), ("t_start_ns", ctypes.c_int64),
+                ("t_done_ns", ctypes.c_int64), ("slots", ctypes.c_uint64),
+                ("overflowed", ctypes.c_uint32), ("pad", ctypes.c_uint32)]
+
+
+class ServerCounters(ctypes.Structure):
+    _fields_ = [(k, ctypes.c_uint64) for k in
+                ("submitted", "completed", "queued", "in_flight", "hbm_used", "hbm_peak",
+                 "host_pool_used", "trees_resident")]
+
+
 _lib = None
 
 vp = ctypes.c_void_p
@@ -114,6 +141,13 @@ def lib():
     _sig(L, "ddm_batch_run", i32, vp, vp)
     _sig(L, "ddm_batch_result", i32, vp, P(u64), vp)
     _sig(L, "ddm_batch_free", None, vp)
+    _sig(L, "ddm_server_create", i32, P(ServerOpts), vp, P(vp))
+    _sig(L, "ddm_server_submit", i32, vp, P(Request), ctypes.c_int64, vp, P(u64))
+    _sig(L, "ddm_server_wait_any", u32, vp, u32, vp, u32)
+    _sig(L, "ddm_server_result", i32, vp, u64, P(Result))
+    _sig(L, "ddm_server_release", i32, vp, u64)
+    _sig(L, "ddm_server_stats", i32, vp, P(ServerCounters))
+    _sig(L, "ddm_server_destroy", None, vp)
     _lib = L
     return L
 

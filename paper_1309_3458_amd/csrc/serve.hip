@@ -1,0 +1,564 @@
+// Serving loop: requests (a subscription set and an update set each) arrive
+// at any time and are matched concurrently on one GPU (an addition to the
+// paper; each request is the problem of Sec. III solved as in Algorithm 4).
+//
+// Host side only.  A pool of worker threads, each with its own HIP stream,
+// takes requests from one FIFO as soon as the device-memory budget admits
+// them; requests therefore start the moment a worker and memory free up and
+// their kernels overlap on the device with those of the requests already
+// running (continuous batching at request granularity).  The footprint of a
+// request is charged in two steps: inputs + trees + match scratch at
+// admission (known from n, m, d), then the predicted output (the learned
+// slot arena) and the exact output once the match has sized them.  A
+// request that would exceed the budget waits, except the oldest request in
+// flight, which always proceeds, so the loop cannot deadlock.
+//
+// Trees named by a nonzero key stay resident after their request (LRU), and
+// a later request with the same key matches against the resident tree
+// without rebuilding it.  Results are copied into a pinned host pool (or
+// kept on the device) and handed to the client through a completion queue.
+#include <chrono>
+#include <condition_variable>
+#include <deque>
+#include <list>
+#include <map>
+#include <mutex>
+#include <new>
+#include <string>
+#include <thread>
+#include <unordered_map>
+#include <vector>
+
+#include "ddm_internal.h"
+
+namespace {
+
+int64_t now_ns() {
+  return std::chrono::duration_cast<std::chrono::nanoseconds>(
+             std::chrono::steady_clock::now().time_since_epoch())
+      .count();
+}
+
+// first-fit allocator over one pinned host block
+struct HostPool {
+  char* base = nullptr;
+  size_t size = 0;
+  std::map<size_t, size_t> free_;  // offset -> bytes
+  size_t used = 0;
+  bool init(size_t bytes) {
+    size = (bytes + 4095) & ~size_t(4095);
+    if (size == 0) return true;
+    if (hipHostMalloc((void**)&base, size, hipHostMallocDefault) != hipSuccess) {
+      (void)hipGetLastError();
+      base = nullptr;
+      return false;
+    }
+    free_[0] = size;
+    return true;
+  }
+  char* alloc(size_t bytes) {
+    bytes = (bytes + 255) & ~size_t(255);
+    for (auto it = free_.begin(); it != free_.end(); ++it) {
+      if (it->second < bytes) continue;
+      const size_t off = it->first, sz = it->second;
+      free_.erase(it);
+      if (sz > bytes) free_[off + bytes] = sz - bytes;
+      used += bytes;
+      return base + off;
+    }
+    return nullptr;
+  }
+  void release(char* p, size_t bytes) {
+    bytes = (bytes + 255) & ~size_t(255);
+    size_t off = (size_t)(p - base);
+    used -= bytes;
+    auto nx = free_.lower_bound(off);
+    if (nx != free_.end() && off + bytes == nx->first) {
+      bytes += nx->second;
+      free_.erase(nx);
+    }
+    auto pv = free_.lower_bound(off);
+    if (pv != free_.begin()) {
+      --pv;
+      if (pv->first + pv->second == off) {
+        pv->second += bytes;
+        return;
+      }
+    }
+    free_[off] = bytes;
+  }
+};
+
+struct CachedTree {
+  ddm_tree* t = nullptr;
+  uint64_t bytes = 0;
+  int users = 0;
+  std::list<uint64_t>::iterator lru;
+};
+
+}  // namespace
+
+struct ddm_server_req {
+  uint64_t ticket = 0;
+  ddm_request r{};
+  hipEvent_t ready = nullptr;
+  int64_t t_arrival = 0, t_start = 0, t_done = 0;
+  uint64_t charged = 0;  // bytes charged to the budget
+  int32_t status = 1;    // 1 pending, else a ddm_status
+  std::string detail;
+  uint64_t K = 0, slots = 0;
+  uint32_t overflowed = 0;
+  char* host = nullptr;  // pinned result
+  uint64_t* dev = nullptr;
+  bool tree_cached = false;
+};
+
+struct ddm_server {
+  int device = 0;
+  ddm_server_opts o{};
+  ddm_predictor* pred = nullptr;
+  std::mutex mu;
+  std::condition_variable cv_work, cv_mem, cv_done;
+  bool stop = false;
+  uint64_t next_ticket = 1;
+  std::deque<ddm_server_req*> queue;                    // not yet admitted
+  std::unordered_map<uint64_t, ddm_server_req*> reqs;  // every unreleased request
+  std::vector<uint64_t> done;                           // completion queue
+  std::map<uint64_t, int> in_flight;                    // ticket -> 1
+  uint64_t used = 0, peak = 0;
+  uint64_t submitted = 0, completed = 0;
+  HostPool pool;
+  std::unordered_map<uint64_t, CachedTree> trees;
+  std::list<uint64_t> lru;  // front = most recent
+  std::vector<std::thread> workers;
+};
+
+namespace ddm {
+size_t tree_bytes_estimate(uint32_t n, uint32_t d);
+}
+
+using namespace ddm;
+
+namespace {
+
+uint64_t admission_bytes(const ddm_request& r, bool build) {
+  // inputs (already in device memory, held until the request completes),
+  // the tree unless it is resident, and the match scratch (per update: probe
+  // words, order, counts, offsets, lists; plus the bucket tables)
+  uint64_t b = 8ull * r.d * ((uint64_t)r.n + r.m);
+  if (build) b += tree_bytes_estimate(r.n, r.d);
+  b += 64ull * r.m + (1u << 20);
+  return b;
+}
+
+// Charge `bytes` to the budget; waits unless they fit or `q` is the oldest
+// request in flight.  Called with the lock held.
+void charge(ddm_server* S, std::unique_lock<std::mutex>& lk, ddm_server_req* q, uint64_t bytes) {
+  S->cv_mem.wait(lk, [&] {
+    return S->stop || S->used + bytes <= S->o.hbm_budget ||
+           (!S->in_flight.empty() && S->in_flight.begin()->first == q->ticket);
+  });
+  S->used += bytes;
+  q->charged += bytes;
+  if (S->used > S->peak) S->peak = S->used;
+}
+
+void uncharge(ddm_server* S, ddm_server_req* q, uint64_t bytes) {
+  S->used -= bytes;
+  q->charged -= bytes;
+  S->cv_mem.notify_all();
+}
+
+void finish(ddm_server* S, ddm_server_req* q, int32_t st, const std::string& detail) {
+  std::lock_guard<std::mutex> lk(S->mu);
+  q->status = st;
+  q->detail = detail;
+  q->t_done = now_ns();
+  S->in_flight.erase(q->ticket);
+  S->done.push_back(q->ticket);
+  ++S->completed;
+  S->cv_mem.notify_all();
+  S->cv_work.notify_all();
+  S->cv_done.notify_all();
+}
+
+ddm_status process(ddm_server* S, ddm_server_req* q, hipStream_t s, std::string* why) {
+  const ddm_request& r = q->r;
+  auto fail = [&](ddm_status st) {
+    *why = ddm_last_error_detail();
+    return st;
+  };
+  if (q->ready) DDM_HIP(hipStreamWaitEvent(s, q->ready, 0));
+  ddm_tree* t = nullptr;
+  bool from_cache = false;
+  if (r.tree_key) {
+    std::lock_guard<std::mutex> lk(S->mu);
+    auto it = S->trees.find(r.tree_key);
+    if (it != S->trees.end()) {
+      t = it->second.t;
+      ++it->second.users;
+      S->lru.erase(it->second.lru);
+      S->lru.push_front(r.tree_key);
+      it->second.lru = S->lru.begin();
+      from_cache = true;
+    }
+  }
+  if (!t) {
+    if (!r.sub_lo && r.tree_key) {
+      *why = "request names a tree key that is not resident and gives no subscriptions";
+      return DDM_E_INVALID_ARG;
+    }
+    ddm_status st = ddm_build(r.sub_lo, r.sub_hi, r.n, r.d, s, &t);
+    if (st != DDM_OK) return fail(st);
+  }
+  auto drop_tree = [&]() {
+    std::lock_guard<std::mutex> lk(S->mu);
+    if (from_cache) {
+      auto it = S->trees.find(r.tree_key);
+      --it->second.users;
+      return;
+    }
+    if (r.tree_key && S->o.tree_cache > 0 && S->trees.find(r.tree_key) == S->trees.end()) {
+      CachedTree c;
+      c.t = t;
+      c.bytes = tree_bytes_estimate(r.n, r.d);
+      S->lru.push_front(r.tree_key);
+      c.lru = S->lru.begin();
+      S->trees[r.tree_key] = c;
+      // the tree's bytes move from the request to the cache
+      q->charged -= std::min<uint64_t>(q->charged, c.bytes);
+      q->tree_cached = true;
+      while (S->trees.size() > S->o.tree_cache) {
+        uint64_t victim = 0;
+        for (auto it = S->lru.rbegin(); it != S->lru.rend(); ++it)
+          if (S->trees[*it].users == 0) {
+            victim = *it;
+            break;
+          }
+        if (!victim) break;
+        CachedTree& v = S->trees[victim];
+        S->lru.erase(v.lru);
+        S->used -= v.bytes;
+        ddm_tree_free(v.t);
+        S->trees.erase(victim);
+        S->cv_mem.notify_all();
+      }
+      return;
+    }
+    ddm_tree_free(t);
+  };
+  uint32_t tn = 0, td = 0;
+  (void)ddm_tree_info(t, &tn, &td, nullptr);
+  if (td != r.d) {
+    drop_tree();
+    *why = "the resident tree has another dimension than the request";
+    return DDM_E_INVALID_ARG;
+  }
+  if (r.m == 0 || tn == 0) {
+    // still validate the inputs that exist
+    ddm_status st = ddm_tree_check(t);
+    drop_tree();
+    q->K = 0;
+    return st == DDM_OK ? DDM_OK : fail(st);
+  }
+  ddm_match_opts mo{};
+  mo.traversal = DDM_TRAVERSE_AUTO;
+  ddm_pending* pend = nullptr;
+  uint64_t K = 0;
+  ddm_status st;
+  if (S->pred && r.d <= 3)
+    st = ddm_match_learned_begin(t, r.upd_lo, r.upd_hi, r.m, S->pred, 0, &K, s, &mo, &pend);
+  else
+    st = ddm_match_begin(t, r.upd_lo, r.upd_hi, r.m, &K, s, &mo, &pend);
+  if (st != DDM_OK) {
+    drop_tree();
+    return fail(st);
+  }
+  uint64_t slots = 0, budget = 0;
+  uint32_t ovf = 0;
+  if (pend) (void)ddm_pending_info(pend, &slots, &budget, &ovf);
+  q->K = K;
+  q->slots = slots;
+  q->overflowed = ovf;
+  const uint64_t out_bytes = 8 * std::max<uint64_t>(K, 1);
+  {
+    // predicted output (slot arena, already allocated by the match) and the
+    // exact output
+    std::unique_lock<std::mutex> lk(S->mu);
+    charge(S, lk, q, 8 * slots + out_bytes);
+  }
+  uint64_t* out = (uint64_t*)dev_alloc(out_bytes, s);
+  if (!out) {
+    ddm_match_abort(pend);
+    drop_tree();
+    *why = "device allocation of the result failed";
+    return DDM_E_NOMEM;
+  }
+  st = ddm_match_finish(pend, out, K);
+  drop_tree();
+  if (st != DDM_OK) {
+    dev_free((char*)out, s);
+    return fail(st);
+  }
+  if (S->o.deliver_device) {
+    DDM_HIP(hipStreamSynchronize(s));
+    q->dev = out;
+    std::lock_guard<std::mutex> lk(S->mu);
+    uncharge(S, q, 8 * slots);
+    return DDM_OK;
+  }
+  char* host = nullptr;
+  {
+    std::unique_lock<std::mutex> lk(S->mu);
+    if (out_bytes > S->pool.size) {
+      dev_free((char*)out, s);
+      *why = "result larger than the pinned host pool";
+      return DDM_E_CAPACITY;
+    }
+    S->cv_mem.wait(lk, [&] { return S->stop || (host = S->pool.alloc(out_bytes)) != nullptr; });
+    if (!host) {
+      dev_free((char*)out, s);
+      *why = "server stopped";
+      return DDM_E_INVALID_ARG;
+    }
+  }
+  q->host = host;
+  hipError_t e = hipMemcpyAsync(host, out, 8 * K, hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  dev_free((char*)out, s);
+  {
+    std::lock_guard<std::mutex> lk(S->mu);
+    uncharge(S, q, 8 * slots + out_bytes);
+  }
+  if (e != hipSuccess) return hip_fail(e, "result copy", __FILE__, __LINE__);
+  return DDM_OK;
+}
+
+void worker_main(ddm_server* S) {
+  (void)hipSetDevice(S->device);
+  hipStream_t s = nullptr;
+  if (hipStreamCreateWithFlags(&s, hipStreamNonBlocking) != hipSuccess) {
+    (void)hipGetLastError();
+    s = nullptr;
+  }
+  while (true) {
+    ddm_server_req* q = nullptr;
+    {
+      std::unique_lock<std::mutex> lk(S->mu);
+      S->cv_work.wait(lk, [&] {
+        if (S->stop) return true;
+        if (S->queue.empty()) return false;
+        ddm_server_req* h = S->queue.front();
+        const bool resident = h->r.tree_key && S->trees.count(h->r.tree_key);
+        return S->in_flight.empty() ||
+               S->used + admission_bytes(h->r, !resident) <= S->o.hbm_budget;
+      });
+      if (S->stop) break;
+      q = S->queue.front();
+      S->queue.pop_front();
+      const bool resident = q->r.tree_key && S->trees.count(q->r.tree_key);
+      const uint64_t b = admission_bytes(q->r, !resident);
+      S->used += b;
+      q->charged = b;
+      if (S->used > S->peak) S->peak = S->used;
+      S->in_flight[q->ticket] = 1;
+      q->t_start = now_ns();
+      if (!S->queue.empty()) S->cv_work.notify_one();
+    }
+    std::string why;
+    ddm_status st = s ? process(S, q, s, &why) : DDM_E_DEVICE;
+    if (!s) why = "worker stream creation failed";
+    if (st != DDM_OK && s) (void)hipStreamSynchronize(s);
+    {
+      // inputs, tree (unless cached) and scratch are no longer held; a
+      // device-side result stays charged until it is released
+      std::lock_guard<std::mutex> lk(S->mu);
+      const uint64_t keep = q->dev ? 8 * std::max<uint64_t>(q->K, 1) : 0;
+      uncharge(S, q, q->charged - std::min(keep, q->charged));
+    }
+    finish(S, q, st, why);
+  }
+  if (s) {
+    (void)hipStreamSynchronize(s);
+    (void)hipStreamDestroy(s);
+  }
+}
+
+}  // namespace
+
+extern "C" ddm_status ddm_server_create(const ddm_server_opts* opts, ddm_predictor* pred,
+                                        ddm_server** out) {
+  set_detail("");
+  if (!out) return DDM_E_INVALID_ARG;
+  *out = nullptr;
+  ddm_server_opts o{};
+  if (opts) o = *opts;
+  for (int i = 0; i < 4; ++i)
+    if (o.reserved[i]) {
+      set_detail("ddm_server_opts: reserved fields must be zero");
+      return DDM_E_INVALID_ARG;
+    }
+  if (o.hbm_budget == 0) o.hbm_budget = 64ull << 30;
+  if (o.host_pool == 0 && !o.deliver_device) o.host_pool = 4ull << 30;
+  if (o.workers == 0) o.workers = 8;
+  if (o.workers > 64) {
+    set_detail("ddm_server_opts: at most 64 workers");
+    return DDM_E_INVALID_ARG;
+  }
+  ddm_server* S = new (std::nothrow) ddm_server();
+  if (!S) return DDM_E_NOMEM;
+  S->o = o;
+  S->pred = pred;
+  hipError_t e = hipGetDevice(&S->device);
+  if (e != hipSuccess) {
+    delete S;
+    return hip_fail(e, "hipGetDevice", __FILE__, __LINE__);
+  }
+  if (!o.deliver_device && !S->pool.init(o.host_pool)) {
+    delete S;
+    set_detail("pinned host pool allocation failed");
+    return DDM_E_NOMEM;
+  }
+  for (uint32_t i = 0; i < o.workers; ++i) S->workers.emplace_back(worker_main, S);
+  *out = S;
+  return DDM_OK;
+}
+
+extern "C" ddm_status ddm_server_submit(ddm_server* S, const ddm_request* r, int64_t arrival_ns,
+                                        void* stream, uint64_t* ticket) {
+  set_detail("");
+  if (!S || !r || !ticket) return DDM_E_INVALID_ARG;
+  if (r->d < 1 || r->d > DDM_MAX_D || (r->m && (!r->upd_lo || !r->upd_hi)) ||
+      (!r->tree_key && r->n && (!r->sub_lo || !r->sub_hi)) || r->reserved) {
+    set_detail("ddm_server_submit: bad request (d, pointers or reserved field)");
+    return DDM_E_INVALID_ARG;
+  }
+  ddm_server_req* q = new (std::nothrow) ddm_server_req();
+  if (!q) return DDM_E_NOMEM;
+  q->r = *r;
+  q->t_arrival = arrival_ns ? arrival_ns : now_ns();
+  q->ready = pooled_event();
+  if (!q->ready) {
+    delete q;
+    set_detail("event creation failed");
+    return DDM_E_DEVICE;
+  }
+  hipError_t e = hipEventRecord(q->ready, (hipStream_t)stream);
+  if (e != hipSuccess) {
+    release_event(q->ready);
+    delete q;
+    return hip_fail(e, "hipEventRecord", __FILE__, __LINE__);
+  }
+  std::lock_guard<std::mutex> lk(S->mu);
+  q->ticket = S->next_ticket++;
+  S->reqs[q->ticket] = q;
+  S->queue.push_back(q);
+  ++S->submitted;
+  *ticket = q->ticket;
+  S->cv_work.notify_one();
+  return DDM_OK;
+}
+
+extern "C" uint32_t ddm_server_wait_any(ddm_server* S, uint32_t timeout_ms, uint64_t* tickets,
+                                        uint32_t max_tickets) {
+  if (!S || !tickets || max_tickets == 0) return 0;
+  std::unique_lock<std::mutex> lk(S->mu);
+  S->cv_done.wait_for(lk, std::chrono::milliseconds(timeout_ms),
+                      [&] { return !S->done.empty() || S->stop; });
+  const uint32_t n = (uint32_t)std::min<size_t>(max_tickets, S->done.size());
+  for (uint32_t i = 0; i < n; ++i) tickets[i] = S->done[i];
+  S->done.erase(S->done.begin(), S->done.begin() + n);
+  return n;
+}
+
+extern "C" ddm_status ddm_server_result(ddm_server* S, uint64_t ticket, ddm_result* res) {
+  set_detail("");
+  if (!S || !res) return DDM_E_INVALID_ARG;
+  std::lock_guard<std::mutex> lk(S->mu);
+  auto it = S->reqs.find(ticket);
+  if (it == S->reqs.end()) {
+    set_detail("unknown or released ticket");
+    return DDM_E_INVALID_ARG;
+  }
+  ddm_server_req* q = it->second;
+  *res = ddm_result{};
+  res->status = q->status;
+  if (q->status == 1) return DDM_OK;
+  res->count = q->K;
+  res->pairs = q->host ? (const uint64_t*)q->host : q->dev;
+  res->on_device = q->dev ? 1u : 0u;
+  res->t_arrival_ns = q->t_arrival;
+  res->t_start_ns = q->t_start;
+  res->t_done_ns = q->t_done;
+  res->slots = q->slots;
+  res->overflowed = q->overflowed;
+  if (q->status != DDM_OK) set_detail(q->detail);
+  return DDM_OK;
+}
+
+extern "C" ddm_status ddm_server_release(ddm_server* S, uint64_t ticket) {
+  set_detail("");
+  if (!S) return DDM_E_INVALID_ARG;
+  ddm_server_req* q = nullptr;
+  {
+    std::lock_guard<std::mutex> lk(S->mu);
+    auto it = S->reqs.find(ticket);
+    if (it == S->reqs.end() || it->second->status == 1) {
+      set_detail("unknown, released or unfinished ticket");
+      return DDM_E_INVALID_ARG;
+    }
+    q = it->second;
+    S->reqs.erase(it);
+    if (q->host) S->pool.release(q->host, 8 * std::max<uint64_t>(q->K, 1));
+    if (q->dev) {
+      S->used -= std::min(S->used, 8 * std::max<uint64_t>(q->K, 1));
+      dev_free((char*)q->dev, nullptr);
+    }
+    S->cv_mem.notify_all();
+    S->cv_work.notify_all();
+  }
+  release_event(q->ready);
+  delete q;
+  return DDM_OK;
+}
+
+extern "C" ddm_status ddm_server_stats(ddm_server* S, ddm_server_counters* st) {
+  if (!S || !st) return DDM_E_INVALID_ARG;
+  std::lock_guard<std::mutex> lk(S->mu);
+  st->submitted = S->submitted;
+  st->completed = S->completed;
+  st->queued = S->queue.size();
+  st->in_flight = S->in_flight.size();
+  st->hbm_used = S->used;
+  st->hbm_peak = S->peak;
+  st->host_pool_used = S->pool.used;
+  st->trees_resident = S->trees.size();
+  return DDM_OK;
+}
+
+extern "C" void ddm_server_destroy(ddm_server* S) {
+  if (!S) return;
+  {
+    // let queued and running requests finish first
+    std::unique_lock<std::mutex> lk(S->mu);
+    S->cv_done.wait(lk, [&] { return S->queue.empty() && S->in_flight.empty(); });
+    // resident trees are freed on the streams they were built on, which
+    // live as long as the workers
+    for (auto& kv : S->trees) ddm_tree_free(kv.second.t);
+    S->trees.clear();
+    S->stop = true;
+  }
+  S->cv_work.notify_all();
+  S->cv_mem.notify_all();
+  S->cv_done.notify_all();
+  for (auto& w : S->workers) w.join();
+  (void)hipSetDevice(S->device);
+  for (auto& kv : S->reqs) {
+    ddm_server_req* q = kv.second;
+    if (q->dev) dev_free((char*)q->dev, nullptr);
+    release_event(q->ready);
+    delete q;
+  }
+  if (S->pool.base) (void)hipHostFree(S->pool.base);
+  delete S;
+}

@@ -124,6 +124,24 @@ __global__ __launch_bounds__(kTreeThreads) void tree_high_kernel(TreeJobs J, uin
 
 static size_t al(size_t b) { return (b + 255) & ~size_t(255); }
 
+// device bytes of a tree over n subscriptions in d dimensions (one block)
+size_t tree_bytes_estimate(uint32_t n, uint32_t d) {
+  if (n == 0) return 0;
+  uint32_t H = 0;
+  while (H < 32 && ((1ull << H) - 1) < n) ++H;
+  const uint64_t P = (1ull << H) - 1;
+  const size_t rec_b = al(sizeof(float) * (size_t)(n + 1) * 2 * d);
+  const size_t mx_b = al(sizeof(float) * ((size_t)P + 1));
+  const size_t id_b = al(sizeof(uint32_t) * (size_t)(n + 1) * d);
+  const size_t key_b = al(sizeof(uint32_t) * (size_t)n * d);
+  const size_t bm_b = al(sizeof(float) * std::max<uint64_t>(1, (P + 1) >> kBlockLog));
+  const size_t si_b = al(sizeof(uint32_t) * (size_t)((n + 63) / 64) * d);
+  const size_t qu_b = al(sizeof(uint32_t) * kQuant * d);
+  return rec_b * d + mx_b * d + id_b + 2 * key_b + bm_b * d + 2 * si_b + qu_b + 256 + 256 +
+         al(sizeof(float) * 4 * DDM_MAX_D) + al(sizeof(uint32_t) * DDM_MAX_D * 2 * (kFeatBins + 1)) +
+         al(sizeof(uint32_t) * kSatWords);
+}
+
 ddm_status enqueue_tree_build(ddm_tree* t, const float* lo, const float* hi, hipStream_t s) {
   const uint32_t n = t->n, d = t->d;
   // scratch: ping-pong key buffers (lo and hi), payload ping-pong, sort tables
@@ -307,10 +325,7 @@ extern "C" ddm_status ddm_build(const float* sub_lo, const float* sub_hi, uint32
   t->ns = (n + 63) / 64;
   const size_t si_b = al(sizeof(uint32_t) * (size_t)t->ns * d);
   const size_t qu_b = al(sizeof(uint32_t) * kQuant * d);
-  const size_t total =
-      rec_b * d + mx_b * d + id_b + 2 * key_b + bm_b * d + 2 * si_b + qu_b + 256 + 256 +
-      al(sizeof(float) * 4 * DDM_MAX_D) + al(sizeof(uint32_t) * DDM_MAX_D * 2 * (kFeatBins + 1)) +
-      al(sizeof(uint32_t) * kSatWords);
+  const size_t total = tree_bytes_estimate(n, d);
   void* blk = dev_alloc(total, s);
   hipError_t e = hipSuccess;
   if (!blk) {

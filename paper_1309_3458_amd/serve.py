@@ -1,0 +1,133 @@
+"""Open-loop serving driver: Poisson arrivals of match requests into a Server.
+
+The client thread submits every request of a pre-drawn schedule at its
+arrival time (its coordinates are generated in device memory at that
+moment); the drain thread collects completions.  Latency is measured from
+the scheduled arrival to the result in host memory, on the server's own
+CLOCK_MONOTONIC timestamps, so a client that falls behind the schedule is
+charged to the latency, not hidden.
+"""
+from __future__ import annotations
+
+import math
+import threading
+import time
+
+import numpy as np
+
+from . import workloads as W
+
+
+def percentile(x, q):
+    if not len(x):
+        return float("nan")
+    return float(np.percentile(np.asarray(x, dtype=np.float64), q))
+
+
+def run(server, schedule, sample_every: int = 100, lead_s: float = 0.2, log=None,
+        sample_max_pairs: int = 20_000_000, sample_bytes: int = 4 << 30):
+    """Serve `schedule` (a list of workloads.Request) on `server`.
+
+    Returns a dict of statistics plus `samples`: {request index: keys (uint64)}
+    for every sample_every-th request (up to sample_max_pairs pairs each and
+    sample_bytes in all), for identity checks after the run.
+    """
+    import torch
+    stream = torch.cuda.Stream()
+    ticket_of = {}
+    lat, K, regions, late = [], [], [], []
+    samples = {}
+    kept = [0]
+    errors = []
+    done_evt = threading.Event()
+    n_req = len(schedule)
+    t0 = time.monotonic_ns() + int(lead_s * 1e9)
+
+    def client():
+        with torch.cuda.stream(stream):
+            for i, rq in enumerate(schedule):
+                target = t0 + int(rq.arrival_s * 1e9)
+                wait = (target - time.monotonic_ns()) / 1e9
+                if wait > 0:
+                    time.sleep(wait)
+                late.append(max(0, time.monotonic_ns() - target) / 1e6)
+                s_lo, s_hi, u_lo, u_hi = W.device_instance(rq.spec)
+                t = server.submit(s_lo, s_hi, u_lo, u_hi, arrival_ns=target, stream=stream)
+                ticket_of[t] = i
+
+    def drain():
+        got = 0
+        while got < n_req:
+            for t in server.wait_any(50):
+                while t not in ticket_of:  # submit returned but not recorded yet
+                    time.sleep(0)
+                i = ticket_of[t]
+                r = server.result(t, copy=False)
+                if (i % sample_every == 0 and r["status"] == 0 and r["count"] <= sample_max_pairs
+                        and kept[0] + 8 * r["count"] <= sample_bytes):
+                    r = server.result(t, copy=True)
+                    kept[0] += 8 * r["count"]
+                if r["status"] != 0:
+                    errors.append((i, r["status"], r.get("detail", "")))
+                else:
+                    lat.append((r["t_done_ns"] - r["t_arrival_ns"]) / 1e6)
+                    K.append(r["count"])
+                    regions.append(schedule[i].spec.N)
+                    if "pairs" in r:
+                        samples[i] = r["pairs"]
+                server.release(t)
+                got += 1
+                if log and got % 5000 == 0:
+                    log(f"served {got}/{n_req}: p50 {percentile(lat, 50):.2f} ms "
+                        f"p99 {percentile(lat, 99):.2f} ms, {server.stats()}")
+        done_evt.set()
+
+    th_c = threading.Thread(target=client, daemon=True)
+    th_d = threading.Thread(target=drain, daemon=True)
+    th_d.start()
+    th_c.start()
+    th_c.join()
+    th_d.join()
+    t_end = time.monotonic_ns()
+    span_s = (t_end - t0) / 1e9
+    st = server.stats()
+    return {
+        "requests": n_req, "completed": len(lat), "errors": errors[:10],
+        "n_errors": len(errors),
+        "latency_ms": {"p50": round(percentile(lat, 50), 3), "p99": round(percentile(lat, 99), 3),
+                       "mean": round(float(np.mean(lat)) if lat else math.nan, 3),
+                       "max": round(max(lat) if lat else math.nan, 3)},
+        "client_late_ms": {"p99": round(percentile(late, 99), 3),
+                           "max": round(max(late) if late else math.nan, 3)},
+        "pairs": int(sum(K)), "regions": int(sum(regions)), "span_s": round(span_s, 3),
+        "pairs_per_s": round(sum(K) / span_s, 1), "regions_per_s": round(sum(regions) / span_s, 1),
+        "hbm_peak_bytes": st["hbm_peak"],
+        "samples": samples,
+    }
+
+
+def check_samples(samples, schedule, max_oracle_pairs: int = 2_000_000, log=None):
+    """Every sampled result equals the same request matched alone on the GPU
+    (ddm_build + ddm_match); those with at most max_oracle_pairs pairs are
+    also compared with the CPU oracle.  Returns (checked, oracle_checked)."""
+    import torch
+
+    import paper_1309_3458_amd as P
+    alone_ok, oracle_ok = 0, 0
+    for i, got in sorted(samples.items()):
+        s_lo, s_hi, u_lo, u_hi = W.device_instance(schedule[i].spec)
+        t = P.build(s_lo, s_hi)
+        want = P.match(t, u_lo, u_hi).cpu().numpy().view(np.uint64)
+        t.free()
+        if not np.array_equal(got, want):
+            raise AssertionError(f"request {i}: served result differs from the result alone")
+        alone_ok += 1
+        if len(want) <= max_oracle_pairs and schedule[i].spec.N <= 200_000:
+            import oracle
+            h = [x.cpu().numpy() for x in (s_lo, s_hi, u_lo, u_hi)]
+            ref = oracle.itm(h[0], h[1], h[2], h[3], threads=16)
+            if not np.array_equal(got, ref):
+                raise AssertionError(f"request {i}: served result differs from the oracle")
+            oracle_ok += 1
+    torch.cuda.synchronize()
+    return alone_ok, oracle_ok

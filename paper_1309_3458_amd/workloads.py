@@ -222,3 +222,31 @@ def random_lengths(seed: int, n: int, m: int, d: int, L: float = 1000.0,
     u_lo, u_hi = draw(m)
     s_lo, s_hi = draw(n)
     return Instance(s_lo, s_hi, u_lo, u_hi, name=f"varlen{seed}")
+
+
+def request_seed(seed) -> int:
+    """64-bit seed of a request's device generator from its (seed, index)."""
+    a, b = seed
+    return (int(a) << 32) | int(b)
+
+
+def device_instance(spec: BatchSpec, device: str = "cuda"):
+    """A serving request's coordinates generated directly in device memory.
+
+    Same recipe as uniform_instance (lower corners uniform on [0, L)^d drawn
+    in float64 and rounded once to float32, hi = f32(lo + f32(side)), updates
+    first), drawn from a torch device generator seeded with
+    request_seed(spec.seed), so that arrivals need no host generation or
+    upload.  Returns (s_lo, s_hi, u_lo, u_hi) float32 tensors [d, n] / [d, m].
+    """
+    import torch
+    n, m = split_regions(spec.N)
+    d = spec.d
+    side = np.float32(side_for_alpha(spec.alpha, spec.N, d))
+    g = torch.Generator(device=device)
+    g.manual_seed(request_seed(spec.seed))
+    lo = (torch.rand((d, m + n), dtype=torch.float64, device=device, generator=g)
+          * L_SPACE).to(torch.float32)
+    hi = lo + torch.tensor(side, dtype=torch.float32, device=device)
+    return (lo[:, m:].contiguous(), hi[:, m:].contiguous(), lo[:, :m].contiguous(),
+            hi[:, :m].contiguous())

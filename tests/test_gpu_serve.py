@@ -1,0 +1,178 @@
+"""Serving loop on the GPU (ddm_server_*), through the C ABI.
+
+* a burst of mixed requests (d 1..3, sizes from 1 to 1e5 regions, alpha
+  from 0.01 to 100) served concurrently: every result is byte-identical to
+  the same request matched alone, and to the CPU oracle;
+* the learned single-pass sizing inside the server gives the same bytes;
+* resident trees: a request naming a kept tree matches against it without
+  subscriptions of its own;
+* a one-byte device budget still serves every request (one at a time);
+* an invalid request fails alone, the others complete;
+* results kept in device memory;
+* an open-loop Poisson run: every request completes, latencies are finite
+  and sampled results equal the results alone.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_1309_3458_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+def _torch():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch
+
+
+def dev(a):
+    torch = _torch()
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+def _mixed(seed, count):
+    rng = np.random.default_rng(seed)
+    insts = []
+    for k in range(count):
+        N = int(np.exp(rng.uniform(np.log(2), np.log(1e5))))
+        d = int(rng.integers(1, 4))
+        alpha = float(np.exp(rng.uniform(np.log(0.01), np.log(100))))
+        n, m = W.split_regions(N)
+        insts.append(W.uniform_instance([seed, k], max(n, 1), max(m, 1), d,
+                                        W.side_for_alpha(alpha, N, d)))
+    return insts
+
+
+def _serve_all(server, insts):
+    """Submit everything at once; collect (and release) results as they
+    complete, in submission order."""
+    tickets = [server.submit(dev(i.s_lo), dev(i.s_hi), dev(i.u_lo), dev(i.u_hi)) for i in insts]
+    res = {}
+    while len(res) < len(tickets):
+        for t in server.wait_any(1000):
+            res[t] = server.result(t)
+            server.release(t)
+    return [res[t] for t in tickets]
+
+
+def _alone(inst):
+    import paper_1309_3458_amd as P
+    t = P.build(dev(inst.s_lo), dev(inst.s_hi))
+    k = P.match(t, dev(inst.u_lo), dev(inst.u_hi)).cpu().numpy().view(np.uint64)
+    t.free()
+    return k
+
+
+@pytest.mark.parametrize("workers", [1, 8])
+def test_burst_equals_alone_and_oracle(workers):
+    import paper_1309_3458_amd as P
+    insts = _mixed(60 + workers, 40)
+    srv = P.Server(workers=workers, host_pool=1 << 30)
+    res = _serve_all(srv, insts)
+    for i, (inst, r) in enumerate(zip(insts, res)):
+        assert r["status"] == 0, r
+        want = oracle.itm(inst.s_lo, inst.s_hi, inst.u_lo, inst.u_hi, threads=8)
+        assert np.array_equal(r["pairs"], want), f"request {i}"
+        assert r["t_arrival_ns"] <= r["t_start_ns"] <= r["t_done_ns"]
+    srv.close()
+
+
+def test_learned_server_same_bytes():
+    import paper_1309_3458_amd as P
+    from paper_1309_3458_amd import learn
+    pred, _ = learn.train_predictor(n_inst=8, per_instance=4000, epochs=6)
+    insts = _mixed(70, 24)
+    srv = P.Server(predictor=pred, workers=6, host_pool=1 << 30)
+    res = _serve_all(srv, insts)
+    for inst, r in zip(insts, res):
+        assert r["status"] == 0
+        assert np.array_equal(r["pairs"], _alone(inst))
+    assert sum(r["slots"] for r in res) > 0
+    srv.close()
+
+
+def test_resident_tree_reuse():
+    import paper_1309_3458_amd as P
+    a = W.uniform_instance(80, 20000, 15000, 2, 3000.0)
+    b = W.uniform_instance(81, 20000, 9000, 2, 3000.0)
+    srv = P.Server(workers=2, tree_cache=4, host_pool=1 << 28)
+    t1 = srv.submit(dev(a.s_lo), dev(a.s_hi), dev(a.u_lo), dev(a.u_hi), tree_key=42)
+    while t1 not in srv.wait_any(1000):
+        pass
+    r1 = srv.result(t1)
+    srv.release(t1)
+    assert srv.stats()["trees_resident"] == 1
+    # b's updates against a's subscriptions, by key only
+    t2 = srv.submit(None, None, dev(b.u_lo), dev(b.u_hi), tree_key=42)
+    while t2 not in srv.wait_any(1000):
+        pass
+    r2 = srv.result(t2)
+    srv.release(t2)
+    assert np.array_equal(r1["pairs"], oracle.itm(a.s_lo, a.s_hi, a.u_lo, a.u_hi, threads=8))
+    assert np.array_equal(r2["pairs"], oracle.itm(a.s_lo, a.s_hi, b.u_lo, b.u_hi, threads=8))
+    # an unknown key without subscriptions fails cleanly
+    t3 = srv.submit(None, None, dev(b.u_lo), dev(b.u_hi), tree_key=43)
+    while t3 not in srv.wait_any(1000):
+        pass
+    assert srv.result(t3)["status"] == -1
+    srv.release(t3)
+    srv.close()
+
+
+def test_tiny_budget_serializes_but_serves_all():
+    import paper_1309_3458_amd as P
+    insts = _mixed(90, 12)
+    srv = P.Server(workers=4, hbm_budget=1, host_pool=1 << 28)
+    res = _serve_all(srv, insts)
+    for inst, r in zip(insts, res):
+        assert r["status"] == 0
+        assert np.array_equal(r["pairs"], _alone(inst))
+    # one at a time: admissions never overlap a running request
+    spans = sorted((r["t_start_ns"], r["t_done_ns"]) for r in res)
+    for (s0, e0), (s1, e1) in zip(spans, spans[1:]):
+        assert s1 >= e0 - 1_000_000  # worker hand-off within the same millisecond
+    srv.close()
+
+
+def test_invalid_request_fails_alone():
+    import paper_1309_3458_amd as P
+    insts = _mixed(91, 6)
+    bad = W.uniform_instance(92, 500, 400, 2, 1000.0)
+    bad.u_hi[1, 7] = bad.u_lo[1, 7] - 1.0
+    srv = P.Server(workers=3, host_pool=1 << 28)
+    res = _serve_all(srv, insts[:3] + [bad] + insts[3:])
+    assert res[3]["status"] == -2
+    for inst, r in zip(insts, res[:3] + res[4:]):
+        assert r["status"] == 0
+        assert np.array_equal(r["pairs"], _alone(inst))
+    srv.close()
+
+
+def test_device_delivery():
+    import paper_1309_3458_amd as P
+    insts = _mixed(93, 8)
+    srv = P.Server(workers=4, deliver_device=True)
+    res = _serve_all(srv, insts)
+    for inst, r in zip(insts, res):
+        assert r["status"] == 0
+        assert np.array_equal(r["pairs"], _alone(inst))
+    assert srv.stats()["hbm_used"] == 0
+    srv.close()
+
+
+def test_open_loop_poisson_run():
+    """0.5 s of Poisson arrivals at 400/s (d=3, N log-uniform in [1e3, 1e5]):
+    every request completes and every 10th equals its result alone."""
+    import paper_1309_3458_amd as P
+    from paper_1309_3458_amd import serve
+    sched = W.serving_schedule(seed=95, rate=400.0, duration_s=0.5, n_hi=1e5)
+    srv = P.Server(workers=8, host_pool=1 << 30)
+    st = serve.run(srv, sched, sample_every=10)
+    srv.close()
+    assert st["completed"] == len(sched) and st["n_errors"] == 0
+    assert 0 < st["latency_ms"]["p50"] <= st["latency_ms"]["p99"] < 10_000
+    alone, orc = serve.check_samples(st["samples"], sched)
+    assert alone == len(st["samples"]) >= len(sched) // 10 - 1
