@@ -28,11 +28,15 @@ ddm_status hip_fail(hipError_t e, const char* what, const char* file, int line) 
 // ---------------------------------------------------------------------------
 // device memory cache
 //
-// Blocks come from hipMalloc and are kept for the life of the process.  A
-// freed block remembers the stream that freed it and an event recorded on
-// that stream at the free: the same stream may reuse the block at once
-// (stream order), another stream only once the event has completed.  Reuse
-// is best fit among cached blocks at most 25% (+1 MiB) larger than asked.
+// Blocks come from hipMalloc and are cached when freed.  A freed block
+// remembers the stream that freed it and an event recorded on that stream at
+// the free: the same stream may reuse the block at once (stream order),
+// another stream only once the event has completed.  Reuse is best fit
+// among cached blocks at most 25% (+1 MiB) larger than asked; sizes above
+// 1 MiB are rounded up to one of 8 steps per power of two so that requests
+// of similar size share blocks.  The cached bytes are bounded: beyond
+// kCacheLimit, the largest cached blocks whose last use has completed are
+// returned to the driver.
 // ---------------------------------------------------------------------------
 struct CachedBlock {
   char* p;
@@ -73,7 +77,33 @@ void release_event(hipEvent_t e) {
 
 static size_t round_bytes(size_t b) {
   if (b <= (1u << 20)) return (b + 255) & ~size_t(255);
-  return (b + (1u << 20) - 1) & ~size_t((1u << 20) - 1);
+  // (8 + i) * 2^(e-3), i < 8: at most 12.5% above the request
+  int e = 63 - __builtin_clzll((unsigned long long)b);
+  const size_t step = size_t(1) << (e - 3);
+  return (b + step - 1) & ~(step - 1);
+}
+
+constexpr size_t kCacheLimit = size_t(16) << 30;
+static size_t g_cached = 0;  // bytes in g_free
+
+// Frees cached blocks, largest first, whose last use has completed, until
+// the cache is within its limit.  Called with g_mem_mu held; returns the
+// blocks to free outside the lock.
+static void trim_cache(std::vector<CachedBlock>* out) {
+  for (auto it = g_free->end(); g_cached > kCacheLimit && it != g_free->begin();) {
+    --it;
+    CachedBlock& b = it->second;
+    bool idle = false;
+    if (b.ev) {
+      const hipError_t q = hipEventQuery(b.ev);
+      idle = q == hipSuccess;
+      if (q != hipSuccess && q != hipErrorNotReady) (void)hipGetLastError();
+    }
+    if (!idle) continue;
+    out->push_back(b);
+    g_cached -= b.size;
+    it = g_free->erase(it);
+  }
 }
 
 char* dev_alloc(size_t bytes, hipStream_t s) {
@@ -100,6 +130,7 @@ char* dev_alloc(size_t bytes, hipStream_t s) {
       char* p = b.p;
       const size_t sz = b.size;
       if (b.ev) g_events->push_back(b.ev);
+      g_cached -= sz;
       g_free->erase(it);
       (*g_live)[p] = {sz, dev};
       return p;
@@ -116,6 +147,7 @@ char* dev_alloc(size_t bytes, hipStream_t s) {
       for (auto it = g_free->begin(); it != g_free->end();) {
         if (it->second.dev == dev) {
           drop.push_back(it->second);
+          g_cached -= it->second.size;
           it = g_free->erase(it);
         } else {
           ++it;
@@ -154,8 +186,23 @@ void dev_free(char* p, hipStream_t s) {
   hipEvent_t ev = pooled_event();
   if (ev) (void)hipEventRecord(ev, s);
   // without an event only the freeing stream may reuse the block
-  std::lock_guard<std::mutex> lk(g_mem_mu);
-  g_free->insert({sz, CachedBlock{p, sz, s, ev, dev}});
+  std::vector<CachedBlock> drop;
+  {
+    std::lock_guard<std::mutex> lk(g_mem_mu);
+    g_free->insert({sz, CachedBlock{p, sz, s, ev, dev}});
+    g_cached += sz;
+    if (g_cached > kCacheLimit) trim_cache(&drop);
+  }
+  if (drop.empty()) return;
+  int cur = 0;
+  (void)hipGetDevice(&cur);
+  for (auto& b : drop) {
+    if (b.dev != cur) (void)hipSetDevice(b.dev);
+    (void)hipFree(b.p);
+    if (b.dev != cur) (void)hipSetDevice(cur);
+    release_event(b.ev);
+  }
+  (void)hipGetLastError();
 }
 
 Scratch::~Scratch() {

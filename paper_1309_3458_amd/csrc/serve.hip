@@ -211,7 +211,11 @@ ddm_status process(ddm_server* S, ddm_server_req* q, hipStream_t s, std::string*
     ddm_status st = ddm_build(r.sub_lo, r.sub_hi, r.n, r.d, s, &t);
     if (st != DDM_OK) return fail(st);
   }
+  // The tree is given back (or cached) only once the stream has finished
+  // with it: a cached tree may be evicted, or used by another worker, as
+  // soon as it is handed over.
   auto drop_tree = [&]() {
+    (void)hipStreamSynchronize(s);
     std::lock_guard<std::mutex> lk(S->mu);
     if (from_cache) {
       auto it = S->trees.find(r.tree_key);
@@ -295,13 +299,13 @@ ddm_status process(ddm_server* S, ddm_server_req* q, hipStream_t s, std::string*
     return DDM_E_NOMEM;
   }
   st = ddm_match_finish(pend, out, K);
-  drop_tree();
   if (st != DDM_OK) {
+    drop_tree();
     dev_free((char*)out, s);
     return fail(st);
   }
   if (S->o.deliver_device) {
-    DDM_HIP(hipStreamSynchronize(s));
+    drop_tree();
     q->dev = out;
     std::lock_guard<std::mutex> lk(S->mu);
     uncharge(S, q, 8 * slots);
@@ -310,21 +314,20 @@ ddm_status process(ddm_server* S, ddm_server_req* q, hipStream_t s, std::string*
   char* host = nullptr;
   {
     std::unique_lock<std::mutex> lk(S->mu);
-    if (out_bytes > S->pool.size) {
-      dev_free((char*)out, s);
-      *why = "result larger than the pinned host pool";
-      return DDM_E_CAPACITY;
-    }
-    S->cv_mem.wait(lk, [&] { return S->stop || (host = S->pool.alloc(out_bytes)) != nullptr; });
-    if (!host) {
-      dev_free((char*)out, s);
-      *why = "server stopped";
-      return DDM_E_INVALID_ARG;
-    }
+    if (out_bytes <= S->pool.size)
+      S->cv_mem.wait(lk, [&] { return S->stop || (host = S->pool.alloc(out_bytes)) != nullptr; });
+  }
+  if (!host) {
+    drop_tree();
+    dev_free((char*)out, s);
+    *why = out_bytes > S->pool.size ? "result larger than the pinned host pool"
+                                    : "server stopped";
+    return out_bytes > S->pool.size ? DDM_E_CAPACITY : DDM_E_INVALID_ARG;
   }
   q->host = host;
   hipError_t e = hipMemcpyAsync(host, out, 8 * K, hipMemcpyDeviceToHost, s);
   if (e == hipSuccess) e = hipStreamSynchronize(s);
+  drop_tree();
   dev_free((char*)out, s);
   {
     std::lock_guard<std::mutex> lk(S->mu);
