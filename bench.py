@@ -17,6 +17,8 @@ Workloads:
   batch256              256 independent instances (N log-uniform in
                         [1e3, 2e5], d in {1,2,3}, alpha log-uniform in
                         [0.01, 100], seed 3), one graph replay per step
+  hbm_copy              a plain device-to-device copy of 1 GiB per step
+                        (calibrates the HBM traffic counters)
   serve                 open-loop Poisson arrivals (2000/s, d=3, N
                         log-uniform in [1e3, 1e6], alpha log-uniform in
                         [0.01, 100], seed 4) into the serving loop with
@@ -57,7 +59,7 @@ def parse():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--traversal", default="auto", choices=["auto", "lane", "tile"])
     ap.add_argument("--workload", default="d2_uniform",
-                    choices=["d2_uniform", "d2_hotspot", "batch256", "serve"])
+                    choices=["d2_uniform", "d2_hotspot", "batch256", "serve", "hbm_copy"])
     ap.add_argument("--duration", type=float, default=60.0,
                     help="serve: seconds of Poisson arrivals (the schedule is cut, not rescaled)")
     ap.add_argument("--rate", type=float, default=2000.0, help="serve: arrivals per second")
@@ -97,7 +99,7 @@ def candidates(inst):
 
 def roofline_alu(cand, ops, dom, dom_avg_ms):
     # Unit of work of a traversal pass: the per-dimension candidate test of
-    # Algorithm 3 (an update against a subscription that meets it in the probe
+    # Algorithm 4 (an update against a subscription that meets it in the probe
     # dimension), 2*d float compares each.
     achieved = ops / (dom_avg_ms / 1e3) / 1e9
     return {"bound": "alu", "achieved": round(achieved, 1), "peak": ALU_PEAK_GOPS,
@@ -434,6 +436,26 @@ def bench_serve(args):
     }
 
 
+def bench_copy(args):
+    """1 GiB device-to-device copy per step: the reference kernel whose
+    FETCH_SIZE / WRITE_SIZE counters calibrate the traffic of the others."""
+    import torch
+    nbytes = 1 << 30
+    a = torch.empty(nbytes // 8, dtype=torch.int64, device="cuda").fill_(1)
+    b = torch.empty_like(a)
+    for _ in range(args.warmup):
+        b.copy_(a)
+    wall, per, _ = evented_steps(lambda: b.copy_(a), args.steps)
+    gbs = 2 * nbytes / (wall / 1e3) / 1e9
+    return {"metric": "device copy bandwidth (read + write bytes / s)", "value": round(gbs, 1),
+            "unit": "GB/s", "ms_per_step": round(wall, 4), "step_ms": step_stats(per),
+            "dtype": "u8", "config": {"workload": "hbm_copy_1GiB", "bytes_read": nbytes,
+                                      "bytes_written": nbytes},
+            "roofline": {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS,
+                         "unit": "GB/s", "frac": round(gbs / HBM_PEAK_GBS, 4), "traffic": None},
+            "cpu_baseline": None}
+
+
 def main():
     args = parse()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
@@ -447,6 +469,8 @@ def main():
         rec = bench_batch(args)
     elif args.workload == "serve":
         rec = bench_serve(args)
+    elif args.workload == "hbm_copy":
+        rec = bench_copy(args)
     else:
         rec = bench_single(args)
     head = {"metric": rec.pop("metric"), "value": rec.pop("value"), "unit": rec.pop("unit"),

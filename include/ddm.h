@@ -8,7 +8,7 @@
  * of intersecting (update, subscription) pairs (Sec. III, problem
  * statement), computed the way the paper's ITM does it: one interval tree per
  * dimension built over S (Sec. IV), every update queried against it in
- * parallel (Algorithm 3 / Algorithm 4, "Parallelizing ITM"), and the
+ * parallel (Algorithm 4 / Algorithm 5, "Parallelizing ITM"), and the
  * per-dimension overlaps combined into d-rectangle overlaps (Sec. III-A).
  *
  * Conventions for every entry point
@@ -59,7 +59,7 @@ typedef enum {
 typedef struct ddm_tree ddm_tree;
 
 /* ddm_build -- interval trees over the subscription set (Sec. IV,
- * Interval-Tree-Create in Algorithm 4; Sec. III-A for one tree per dimension).
+ * Interval-Tree-Create in Algorithm 5; Sec. III-A for one tree per dimension).
  *
  *  sub_lo, sub_hi  device pointers, d*n float32 each, dimension-major.
  *  n               number of subscriptions; 0 is valid (every match is empty).
@@ -81,7 +81,7 @@ ddm_status ddm_build(const float* sub_lo, const float* sub_hi, uint32_t n, uint3
                      void* stream, ddm_tree** out_tree);
 
 /* ddm_match -- all (update, subscription) pairs that intersect
- * (Algorithm 4: one Interval-Query, Algorithm 3, per update, run in
+ * (Algorithm 5: one Interval-Query, Algorithm 4, per update, run in
  * parallel; Sec. III-A: overlap in every dimension).
  *
  *  t              tree from ddm_build (read only; may be matched concurrently
@@ -104,10 +104,10 @@ ddm_status ddm_match(const ddm_tree* t, const float* upd_lo, const float* upd_hi
                      void* stream);
 
 /* Traversal kernels selectable through ddm_match_ex (results never differ):
- *  DDM_TRAVERSE_LANE  one GPU lane per update, stackless form of Algorithm 3
+ *  DDM_TRAVERSE_LANE  one GPU lane per update, stackless form of Algorithm 4
  *                     on the implicit tree.
  *  DDM_TRAVERSE_TILE  one wavefront per 64 updates sorted by lower bound:
- *                     Algorithm 3 runs once on the tile's enclosing interval,
+ *                     Algorithm 4 runs once on the tile's enclosing interval,
  *                     candidates are compacted into LDS with wavefront
  *                     ballots and tested against all 64 updates.
  *  DDM_TRAVERSE_AUTO  library default (currently TILE).                     */
@@ -272,7 +272,7 @@ void ddm_tree_free(ddm_tree* t);
 
 /* ---------------------------------------------------------------------------
  * Batched matching (an addition to the paper; every instance is the
- * problem of Sec. III, solved as in Algorithm 4 with the trees of Sec. IV).
+ * problem of Sec. III, solved as in Algorithm 5 with the trees of Sec. IV).
  *
  * Many independent instances -- each its own subscription set, update set
  * and dimension -- matched by one fixed sequence of kernels: one tree build

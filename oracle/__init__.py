@@ -114,7 +114,7 @@ def sbm_1d(s_lo, s_hi, u_lo, u_hi) -> np.ndarray:
 
 
 def itm_1d_visits(s_lo, s_hi, u_lo, u_hi):
-    """Per-query node visits and hits of Algorithm 3, plus the tree height."""
+    """Per-query node visits and hits of Algorithm 4, plus the tree height."""
     d, n, m = _dims(s_lo, u_lo)
     assert d == 1
     a, pa = _f32(s_lo); b, pb = _f32(s_hi); c, pc = _f32(u_lo); e, pe = _f32(u_hi)

@@ -25,22 +25,22 @@
  *                     remaining ties), each node holding maxupper and
  *                     minlower of its subtree.  Built statically by taking
  *                     the median as the root (a perfectly balanced BST).
- *   itree_query       Algorithm 3 (Interval-Query), recursive, closed form:
+ *   itree_query       Algorithm 4 (Interval-Query), recursive, closed form:
  *                     prune if maxupper < q.lower or minlower > q.upper;
  *                     recurse left; test the node; recurse right iff
  *                     x.in.lower <= q.upper (the closed counterpart of the
  *                     printed strict condition).
- *   oracle_itm        Algorithm 4 per dimension, then the d-way combine of
+ *   oracle_itm        Algorithm 5 per dimension, then the d-way combine of
  *                     Sec. III-A written literally: per update, sort the d
  *                     per-dimension lists and intersect them.  The parallel
  *                     form splits updates into contiguous blocks, one per
  *                     thread (Sec. IV, "Parallelizing ITM"), and concatenates
  *                     the blocks in order.
  *   oracle_brute      Algorithm 2 (Brute Force) with the closed predicate.
- *   oracle_sbm_1d     Algorithm "Sort-Based Matching" (Sec. III-D), d = 1:
+ *   oracle_sbm_1d     Algorithm 3 (Sort-Based Matching, Sec. III-D), d = 1:
  *                     endpoints sorted, sweep with active sets; at equal
  *                     coordinates lower endpoints come first (closed reading).
- *   oracle_itm_1d_visits  Algorithm 3 per query with a visit counter, for the
+ *   oracle_itm_1d_visits  Algorithm 4 per query with a visit counter, for the
  *                     O(min{n, (k+1) log n}) cost bound of Sec. IV.
  */
 #include <stdint.h>
@@ -161,7 +161,7 @@ static int itree_create(itree_t* t, const float* lo, const float* hi, uint32_t n
 
 static void itree_free(itree_t* t) { free(t->nodes); t->nodes = NULL; }
 
-/* Algorithm 3, closed form (strict form under the diagnostic flag). */
+/* Algorithm 4, closed form (strict form under the diagnostic flag). */
 static void itree_query(const itree_t* t, int32_t xi, float ql, float qh, int strict,
                         vec32* out, uint64_t* visits) {
     if (xi < 0) return;
@@ -392,7 +392,7 @@ done:
 }
 
 /* ------------------------------------------------------------------ */
-/* Algorithm 3 with visit counts, one dimension (cost bound, Sec. IV)  */
+/* Algorithm 4 with visit counts, one dimension (cost bound, Sec. IV)  */
 /* ------------------------------------------------------------------ */
 int oracle_itm_1d_visits(const float* s_lo, const float* s_hi, uint32_t n,
                          const float* u_lo, const float* u_hi, uint32_t m,

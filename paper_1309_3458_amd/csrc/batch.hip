@@ -1,6 +1,6 @@
 // Many independent DDM instances matched together (an addition to the
 // paper's method; each instance is the problem of Sec. III solved as in
-// Algorithm 4).
+// Algorithm 5).
 //
 // Every step handles all instances in the same launches: one key kernel, one
 // radix sort over all arrays, one pass of tree kernels over all trees, one

@@ -1,4 +1,4 @@
-// Matching on the device: Algorithm 4 (IntTree-Matching) with Algorithm 3
+// Matching on the device: Algorithm 5 (IntTree-Matching) with Algorithm 4
 // (Interval-Query) for every update in parallel, Sec. IV "Parallelizing ITM",
 // and the d-dimensional combine of Sec. III-A.
 //
@@ -10,7 +10,7 @@
 //      d = 1 the count is already the final count.
 //   2. updates sorted by (k*, lower bound in k*) so that neighbouring lanes
 //      walk neighbouring parts of the same tree.
-//   3. count traversal (d > 1): Algorithm 3 on tree k*, every candidate also
+//   3. count traversal (d > 1): Algorithm 4 on tree k*, every candidate also
 //      tested in the other dimensions (membership in every per-dimension
 //      overlap set is decided by that dimension's own predicate, so the
 //      intersection of Sec. III-A is formed without listing the per-dimension
@@ -208,9 +208,9 @@ __global__ __launch_bounds__(256) void bucket_scatter_kernel(const uint32_t* __r
 }
 
 // --------------------------------------------------------------------------
-// 3/5a. one lane per update: Algorithm 3 without a stack.
+// 3/5a. one lane per update: Algorithm 4 without a stack.
 //
-// On the implicit in-order tree the recursion of Algorithm 3 becomes a walk
+// On the implicit in-order tree the recursion of Algorithm 4 becomes a walk
 // over positions in increasing order with two states:
 //   ENTER x  (call on subtree x of height h, span [a, x + 2^h - 1]):
 //            a > n (all padding)            -> stop (so is everything after);
@@ -223,7 +223,7 @@ __global__ __launch_bounds__(256) void bucket_scatter_kernel(const uint32_t* __r
 //            right child, or VISIT x + 1 at a leaf.
 // Positions after the end of a subtree are exactly the next in-order node
 // whose left subtree is complete, so no stack is needed.  The nodes tested
-// are those Algorithm 3 tests, in the same (in-order) order, except that the
+// are those Algorithm 4 tests, in the same (in-order) order, except that the
 // walk stops at the first lower bound beyond q.upper instead of returning
 // through ancestors that would all fail the same test.
 // --------------------------------------------------------------------------

@@ -1,6 +1,6 @@
 // Serving loop: requests (a subscription set and an update set each) arrive
 // at any time and are matched concurrently on one GPU (an addition to the
-// paper; each request is the problem of Sec. III solved as in Algorithm 4).
+// paper; each request is the problem of Sec. III solved as in Algorithm 5).
 //
 // Host side only.  A pool of worker threads, each with its own HIP stream,
 // takes requests from one FIFO as soon as the device-memory budget admits

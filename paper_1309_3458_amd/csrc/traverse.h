@@ -138,7 +138,7 @@ __device__ __forceinline__ void seg_bounds(const SegOut& O, uint32_t j, uint64_t
 // The tile's candidates in tree k are confined to positions
 // [Pbeg, Pend] = [min plo, max phi] of its updates.  The wave walks that
 // range block by block (64 positions; the tree's maxupper of position 64c and
-// of the height-5 subtree at 64c+32, i.e. Algorithm 3's pruning test cut at
+// of the height-5 subtree at 64c+32, i.e. Algorithm 4's pruning test cut at
 // height 5): 64 lanes read 64 block maxima at once and a ballot keeps the
 // blocks whose maxupper reaches the tile's smallest q.lower.  A kept block is
 // read one position per lane; positions meeting the tile's enclosing box in

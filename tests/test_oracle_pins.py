@@ -5,7 +5,7 @@ definition evaluated by brute force in numpy on tiny inputs, the worked example
 of Sec. III, the BITS counting identity (Sec. II) via ``numpy.searchsorted``,
 the closed-form expected pair count for uniformly placed boxes, a second exact
 algorithm (sort-based matching, Sec. III-D), structural invariants, and the
-O(min{n, (k+1) log n}) query cost of Algorithm 3 (Sec. IV).
+O(min{n, (k+1) log n}) query cost of Algorithm 4 (Sec. IV).
 """
 import os
 
@@ -55,7 +55,7 @@ def test_closed_semantics_pin():
 
     Closed segments (the text's [low, high]) meet at 5, so both pairs exist.
     Algorithm 1 as printed is strict and reports neither; with the strict
-    right-descent condition of Algorithm 3 S_b (right child of S_a in the
+    right-descent condition of Algorithm 4 S_b (right child of S_a in the
     (lower, upper) order) would not even be visited.
     """
     s_lo = np.array([[5, 5]], np.float32)
@@ -226,7 +226,7 @@ def test_result_independent_of_order():
 
 
 def test_query_cost_bound():
-    """Algorithm 3 enters at most min(n, 2 (k+1) H + 1) nodes for a query with
+    """Algorithm 4 enters at most min(n, 2 (k+1) H + 1) nodes for a query with
     k hits in a tree of height H: a node that is not pruned is an ancestor of
     a hit or straddles the boundary lower <= q.upper < lower (at most H such
     nodes); every entered node is the root or a child of a non-pruned one."""
