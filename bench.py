@@ -97,15 +97,25 @@ def candidates(inst):
     return float(c.sum())
 
 
-def roofline_alu(cand, ops, dom, dom_avg_ms):
+# Calibrated FETCH_SIZE + WRITE_SIZE of the fill traversal at the default
+# workload (profiles/traffic_d2_N1e6_alpha1_pmc.md), bytes per launch; valid
+# for this version of the tile traversal only.
+TRAFFIC_BYTES = {("d2_N1e6_alpha1_uniform", "plain", "traverse_tile_fill"): 274101.5 * 1024}
+
+
+def roofline_alu(cand, ops, dom, dom_avg_ms, traffic=None):
     # Unit of work of a traversal pass: the per-dimension candidate test of
     # Algorithm 4 (an update against a subscription that meets it in the probe
     # dimension), 2*d float compares each.
     achieved = ops / (dom_avg_ms / 1e3) / 1e9
-    return {"bound": "alu", "achieved": round(achieved, 1), "peak": ALU_PEAK_GOPS,
-            "unit": "Gop/s", "frac": round(achieved / ALU_PEAK_GOPS, 4), "traffic": None,
-            "kernel": dom, "kernel_avg_ms": round(dom_avg_ms, 4),
-            "candidates_per_launch": int(cand)}
+    r = {"bound": "alu", "achieved": round(achieved, 1), "peak": ALU_PEAK_GOPS,
+         "unit": "Gop/s", "frac": round(achieved / ALU_PEAK_GOPS, 4), "traffic": traffic,
+         "kernel": dom, "kernel_avg_ms": round(dom_avg_ms, 4),
+         "candidates_per_launch": int(cand)}
+    if traffic:
+        r["traffic_gbs"] = round(traffic / (dom_avg_ms / 1e3) / 1e9, 1)
+        r["traffic_frac_hbm_peak"] = round(r["traffic_gbs"] / HBM_PEAK_GBS, 4)
+    return r
 
 
 def evented_steps(step, steps):
@@ -226,7 +236,8 @@ def bench_single(args):
     ms_step = res[best]["ms_per_step"]
     cand = candidates(inst)
     roofline = roofline_alu(cand, cand * 2 * inst.d, res[best]["dominant"],
-                            res[best]["dominant_avg_ms"])
+                            res[best]["dominant_avg_ms"],
+                            TRAFFIC_BYTES.get((wname, best, res[best]["dominant"])))
 
     cpu = None
     if not args.no_cpu_baseline:

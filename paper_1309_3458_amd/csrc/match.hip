@@ -424,44 +424,86 @@ __global__ __launch_bounds__(256) void segsort_small_kernel(const uint64_t* __re
   }
 }
 
-// one workgroup per listed segment (17..2048 keys): ids bitonic-sorted in LDS
-__global__ __launch_bounds__(256) void segsort_mid_kernel(const uint64_t* __restrict__ off,
-                                                          uint64_t* __restrict__ out, SegSrc S,
-                                                          const uint32_t* __restrict__ lists,
-                                                          const uint32_t* __restrict__ list_count) {
-  __shared__ uint32_t sh[kSegMid];
-  const uint32_t cntl = list_count[0];
-  for (uint32_t li = blockIdx.x; li < cntl; li += gridDim.x) {
-    const uint32_t j = lists[li];
+// One wavefront per listed segment (17..2048 keys).  The segment's ids are
+// staged through LDS (coalesced global reads and writes) into registers in
+// blocked order, V = P2/64 per lane (P2 = the segment length rounded up to a
+// power of two, at least 64), and sorted by a bitonic network: exchanges of
+// partners less than V apart stay inside a lane's registers, the others
+// swap whole registers with the lane whose index differs in one bit.
+template <int V>
+__device__ __forceinline__ void wave_bitonic_segment(const uint64_t* __restrict__ src,
+                                                     uint64_t* __restrict__ dst, uint32_t len,
+                                                     uint64_t jhi, uint32_t* __restrict__ sh,
+                                                     uint32_t lane) {
+  constexpr uint32_t P2 = 64u * V;
+  for (uint32_t i = lane; i < P2; i += kWave) sh[i] = (i < len) ? (uint32_t)src[i] : 0xffffffffu;
+  wave_sync();
+  uint32_t v[V];
+#pragma unroll
+  for (int r = 0; r < V; ++r) v[r] = sh[lane * V + r];
+#pragma unroll
+  for (uint32_t k = 2; k <= P2; k <<= 1) {
+#pragma unroll
+    for (uint32_t j = k >> 1; j > 0; j >>= 1) {
+      if (j >= (uint32_t)V) {
+        // partner: lane ^ (j / V), same register
+        const uint32_t lx = j / V;
+        const bool lower = (lane & lx) == 0;
+#pragma unroll
+        for (int r = 0; r < V; ++r) {
+          const uint32_t o = (uint32_t)__shfl_xor((int)v[r], (int)lx, kWave);
+          const bool up = ((lane * V + r) & k) == 0;
+          // the lower index keeps the smaller key when sorting up
+          v[r] = (lower == up) ? min(v[r], o) : max(v[r], o);
+        }
+      } else {
+#pragma unroll
+        for (int r = 0; r < V; ++r) {
+          if (((uint32_t)r & j) != 0) continue;
+          const int q = r + (int)j;
+          const bool up = ((lane * V + r) & k) == 0;
+          const uint32_t a = v[r], b = v[q];
+          const bool sw = up ? (a > b) : (a < b);
+          v[r] = sw ? b : a;
+          v[q] = sw ? a : b;
+        }
+      }
+    }
+  }
+  wave_sync();
+#pragma unroll
+  for (int r = 0; r < V; ++r) sh[lane * V + r] = v[r];
+  wave_sync();
+  for (uint32_t i = lane; i < len; i += kWave) dst[i] = jhi | sh[i];
+  wave_sync();
+}
+
+constexpr int kSegWaves = 4;  // wavefronts per workgroup of the mid sort
+
+__global__ __launch_bounds__(kSegWaves * kWave) void segsort_mid_kernel(
+    const uint64_t* __restrict__ off, uint64_t* __restrict__ out, SegSrc S,
+    const uint32_t* __restrict__ lists, const uint32_t* __restrict__ list_count) {
+  __shared__ uint32_t shw[kSegWaves][kSegMid];
+  const uint32_t wave = threadIdx.x / kWave;
+  const uint32_t lane = lane_id();
+  uint32_t* sh = shw[wave];
+  const uint32_t cntl = uniform_u32(list_count[0]);
+  const uint32_t nw = gridDim.x * kSegWaves;
+  for (uint32_t li = blockIdx.x * kSegWaves + wave; li < cntl; li += nw) {
+    const uint32_t j = uniform_u32(lists[li]);
     const uint64_t b = off[j];
-    const uint32_t len = (uint32_t)(off[j + 1] - b);
+    const uint32_t len = uniform_u32((uint32_t)(off[j + 1] - b));
     bool in_place;
     const uint64_t* src = seg_src(S, j, out, b, &in_place);
     // every key of the segment carries the same update id in its high word
-    const uint64_t jhi = src[0] & 0xffffffff00000000ull;
-    uint32_t P2 = 32;
-    while (P2 < len) P2 <<= 1;
-    for (uint32_t i = threadIdx.x; i < P2; i += 256)
-      sh[i] = (i < len) ? (uint32_t)src[i] : 0xffffffffu;
-    __syncthreads();
-    for (uint32_t k = 2; k <= P2; k <<= 1) {
-      for (uint32_t jj = k >> 1; jj > 0; jj >>= 1) {
-        for (uint32_t i = threadIdx.x; i < P2; i += 256) {
-          const uint32_t l = i ^ jj;
-          if (l > i) {
-            const uint32_t a = sh[i], c = sh[l];
-            const bool up = (i & k) == 0;
-            if (up ? (a > c) : (a < c)) {
-              sh[i] = c;
-              sh[l] = a;
-            }
-          }
-        }
-        __syncthreads();
-      }
-    }
-    for (uint32_t i = threadIdx.x; i < len; i += 256) out[b + i] = jhi | sh[i];
-    __syncthreads();
+    const uint64_t jhi = readlane_u64(src[0], 0) & 0xffffffff00000000ull;
+    uint64_t* dst = out + b;
+    if (len <= 64) wave_bitonic_segment<1>(src, dst, len, jhi, sh, lane);
+    else if (len <= 128) wave_bitonic_segment<2>(src, dst, len, jhi, sh, lane);
+    else if (len <= 256) wave_bitonic_segment<4>(src, dst, len, jhi, sh, lane);
+    else if (len <= 512) wave_bitonic_segment<8>(src, dst, len, jhi, sh, lane);
+    else if (len <= 1024) wave_bitonic_segment<16>(src, dst, len, jhi, sh, lane);
+    else wave_bitonic_segment<32>(src, dst, len, jhi, sh, lane);
   }
 }
 
@@ -950,7 +992,7 @@ ddm_status sort_segments(const uint64_t* off, uint32_t m, uint64_t* out, uint64_
   ProfScope ps("segsort", s);
   segsort_small_kernel<<<(m + 255) / 256, 256, 0, s>>>(off, m, out, S, lists, lists_count);
   DDM_LAUNCHED("segsort_small_kernel");
-  segsort_mid_kernel<<<8192, 256, 0, s>>>(off, out, S, lists, lists_count);
+  segsort_mid_kernel<<<4096, kSegWaves * kWave, 0, s>>>(off, out, S, lists, lists_count);
   DDM_LAUNCHED("segsort_mid_kernel");
   const uint32_t words = std::min<uint32_t>(kMaxBitWords, (n + 31) / 32);
   uint32_t* tmp = nullptr;
