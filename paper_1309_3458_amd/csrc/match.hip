@@ -507,6 +507,86 @@ __global__ __launch_bounds__(kSegWaves * kWave) void segsort_mid_kernel(
   }
 }
 
+// One workgroup per listed segment of 2049..16384 keys.  The ids of a
+// segment are distinct; they are counted into 1024 buckets of consecutive
+// ids (id >> shift) in LDS, placed by bucket, and each bucket (16 ids on
+// average at the largest size) is insertion-sorted by one thread.  A segment
+// with a bucket of more than kBucketCap ids is left to the bitmap kernel
+// below; every segment handled here is marked done in its list entry.
+constexpr uint32_t kBucketSegMax = 16384;
+constexpr uint32_t kSegBuckets = 1024;
+constexpr uint32_t kBucketCap = 64;
+constexpr uint32_t kListDone = 0x80000000u;
+
+__global__ __launch_bounds__(kSegBuckets) void segsort_bucket_kernel(
+    const uint64_t* __restrict__ off, uint32_t m, uint64_t* __restrict__ out, SegSrc S,
+    uint32_t* __restrict__ lists, const uint32_t* __restrict__ list_count, uint32_t shift) {
+  __shared__ uint32_t sorted[kBucketSegMax];
+  __shared__ uint32_t cur[kSegBuckets];
+  __shared__ uint32_t start[kSegBuckets + 1];
+  __shared__ uint32_t wsum[kSegBuckets / kWave];
+  __shared__ uint32_t maxb;
+  const uint32_t cntl = list_count[1];
+  const uint32_t tid = threadIdx.x, lane = lane_id(), wave = tid / kWave;
+  for (uint32_t li = blockIdx.x; li < cntl; li += gridDim.x) {
+    const uint32_t j = lists[m + li];
+    const uint64_t b = off[j];
+    const uint64_t len64 = off[j + 1] - b;
+    if (len64 > kBucketSegMax) continue;
+    const uint32_t len = (uint32_t)len64;
+    bool in_place;
+    const uint64_t* src = seg_src(S, j, out, b, &in_place);
+    const uint64_t jhi = src[0] & 0xffffffff00000000ull;
+    cur[tid] = 0;
+    if (tid == 0) maxb = 0;
+    __syncthreads();
+    for (uint32_t i = tid; i < len; i += kSegBuckets)
+      atomicAdd(&cur[min((uint32_t)src[i] >> shift, kSegBuckets - 1u)], 1u);
+    __syncthreads();
+    const uint32_t h = cur[tid];
+    atomicMax(&maxb, h);
+    uint32_t inc = h;
+#pragma unroll
+    for (int o = 1; o < kWave; o <<= 1) {
+      const uint32_t t2 = __shfl_up(inc, o, kWave);
+      if (lane >= (uint32_t)o) inc += t2;
+    }
+    if (lane == kWave - 1) wsum[wave] = inc;
+    __syncthreads();
+    uint32_t before = 0;
+    for (uint32_t q = 0; q < wave; ++q) before += wsum[q];
+    const uint32_t st = before + inc - h;
+    start[tid] = st;
+    cur[tid] = st;
+    if (tid == 0) start[kSegBuckets] = len;
+    __syncthreads();
+    const bool skip = maxb > kBucketCap;
+    __syncthreads();  // every thread has read maxb before the next segment resets it
+    if (skip) continue;
+    for (uint32_t i = tid; i < len; i += kSegBuckets) {
+      const uint32_t id = (uint32_t)src[i];
+      sorted[atomicAdd(&cur[min(id >> shift, kSegBuckets - 1u)], 1u)] = id;
+    }
+    __syncthreads();
+    {
+      const uint32_t s0 = start[tid], s1 = start[tid + 1];
+      for (uint32_t i = s0 + 1; i < s1; ++i) {
+        const uint32_t x = sorted[i];
+        uint32_t k = i;
+        while (k > s0 && sorted[k - 1] > x) {
+          sorted[k] = sorted[k - 1];
+          --k;
+        }
+        sorted[k] = x;
+      }
+    }
+    __syncthreads();
+    for (uint32_t i = tid; i < len; i += kSegBuckets) out[b + i] = jhi | sorted[i];
+    if (tid == 0) lists[m + li] = j | kListDone;
+    __syncthreads();
+  }
+}
+
 // One workgroup per long segment: mark ids in an LDS bitmap (dynamic size:
 // `words` 32-bit words covering a window of ids), then emit them in
 // increasing order.  Ids span [0, n): with more than one window, in-place
@@ -528,6 +608,7 @@ __global__ __launch_bounds__(kBigThreads) void segsort_big_kernel(
   const uint32_t nwin = (n + span - 1) / span;
   for (uint32_t li = blockIdx.x; li < cntl; li += gridDim.x) {
     const uint32_t j = lists[m + li];
+    if (j & kListDone) continue;  // sorted by the bucket kernel
     const uint64_t b = off[j];
     const uint64_t len = off[j + 1] - b;
     bool in_place;
@@ -1007,6 +1088,13 @@ ddm_status sort_segments(const uint64_t* off, uint32_t m, uint64_t* out, uint64_
   }
   ddm_status r = ensure_segsort_attr();
   if (r != DDM_OK) return r;
+  {
+    uint32_t bits = 0;
+    while (bits < 32 && (1ull << bits) < n) ++bits;
+    const uint32_t shift = bits > 10 ? bits - 10 : 0;
+    segsort_bucket_kernel<<<1024, kSegBuckets, 0, s>>>(off, m, out, S, lists, lists_count, shift);
+    DDM_LAUNCHED("segsort_bucket_kernel");
+  }
   segsort_big_kernel<<<512, kBigThreads, words * sizeof(uint32_t), s>>>(off, m, out, S, lists,
                                                                         lists_count, tmp, n, words);
   DDM_LAUNCHED("segsort_big_kernel");

@@ -96,6 +96,36 @@ def test_long_segments():
         assert_keys_equal(gpu_match(inst, tr), want)
 
 
+@pytest.mark.parametrize("clustered", [False, True])
+def test_segment_sort_size_classes(clustered):
+    """Segments of every size class of the segment sort: 1, 2..16 (one lane),
+    17..2048 (one wavefront, all six register widths), 2049..16384 (bucket
+    sort) and above (bitmap).  With clustered ids (5000 consecutive ids share
+    one box) the bucket sort's per-bucket capacity is exceeded and those
+    segments take the bitmap path."""
+    rng = np.random.default_rng(19 + clustered)
+    n = 100000
+    s_lo = rng.uniform(0, 1e5, (1, n)).astype(np.float32)
+    s_hi = (s_lo + np.float32(1.0)).astype(np.float32)
+    if clustered:
+        s_lo[0, 1000:6000] = np.float32(5e4)
+        s_hi[0, 1000:6000] = np.float32(5e4 + 1)
+    # query widths chosen to hit each class (about 2 boxes per unit length)
+    widths = [0.0, 1.0, 10.0, 40.0, 100.0, 200.0, 400.0, 800.0, 2000.0, 5000.0, 12000.0, 30000.0]
+    m = len(widths) * 8
+    u_lo = rng.uniform(0, 1e5 - 6e4, (1, m)).astype(np.float32)
+    u_lo[0, ::4] = np.float32(5e4 - 10.0)  # a quarter of them cover the cluster
+    u_hi = (u_lo + np.repeat(np.asarray(widths, np.float32), 8)[None, :]).astype(np.float32)
+    inst = W.Instance(s_lo, s_hi, u_lo, u_hi)
+    want = oracle.itm(s_lo, s_hi, u_lo, u_hi, threads=8)
+    cnt = oracle.counts_per_update(want, m)
+    for lo, hi in [(2, 16), (17, 64), (65, 128), (129, 256), (257, 512), (513, 1024),
+                   (1025, 2048), (2049, 16384), (16385, 1 << 30)]:
+        assert ((cnt >= lo) & (cnt <= hi)).any(), (lo, hi, np.sort(cnt))
+    for tr in TRAVERSALS:
+        assert_keys_equal(gpu_match(inst, tr), want)
+
+
 def test_empty_sets():
     import paper_1309_3458_amd as P
     torch = _torch()
