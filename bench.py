@@ -17,6 +17,9 @@ Workloads:
   batch256              256 independent instances (N log-uniform in
                         [1e3, 2e5], d in {1,2,3}, alpha log-uniform in
                         [0.01, 100], seed 3), one graph replay per step
+  sweep_1d              the paper's experiment on the GPU: d=1, N from 5e4
+                        to 5e5, alpha in {0.01, 1, 100}; ITM (build +
+                        match) beside GPU Brute-Force Matching
   hbm_copy              a plain device-to-device copy of 1 GiB per step
                         (calibrates the HBM traffic counters)
   serve                 open-loop Poisson arrivals (2000/s, d=3, N
@@ -59,7 +62,8 @@ def parse():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--traversal", default="auto", choices=["auto", "lane", "tile"])
     ap.add_argument("--workload", default="d2_uniform",
-                    choices=["d2_uniform", "d2_hotspot", "batch256", "serve", "hbm_copy"])
+                    choices=["d2_uniform", "d2_hotspot", "batch256", "serve", "hbm_copy",
+                             "sweep_1d"])
     ap.add_argument("--duration", type=float, default=60.0,
                     help="serve: seconds of Poisson arrivals (the schedule is cut, not rescaled)")
     ap.add_argument("--rate", type=float, default=2000.0, help="serve: arrivals per second")
@@ -447,6 +451,56 @@ def bench_serve(args):
     }
 
 
+def bench_sweep(args):
+    """Sec. V's experiment (d = 1, n = m = N/2, uniform lower ends on [0, L),
+    common length alpha L / N) on the GPU: ITM build + match per step, and
+    Brute-Force Matching (Algorithm 2) on the same inputs."""
+    import torch
+
+    import paper_1309_3458_amd as P
+    from paper_1309_3458_amd import workloads as W
+
+    rows = []
+    dev = lambda a: torch.from_numpy(a).cuda()
+    for N in (50_000, 100_000, 200_000, 300_000, 400_000, 500_000):
+        for alpha in (0.01, 1.0, 100.0):
+            n, m = W.split_regions(N)
+            inst = W.uniform_instance([5, N, int(alpha * 100)], n, m, 1,
+                                      W.side_for_alpha(alpha, N, 1))
+            s_lo, s_hi, u_lo, u_hi = dev(inst.s_lo), dev(inst.s_hi), dev(inst.u_lo), dev(inst.u_hi)
+            t = P.build(s_lo, s_hi)
+            K = int(P.match(t, u_lo, u_hi).numel())
+            t.free()
+            out = torch.empty(max(K, 1), dtype=torch.int64, device="cuda")
+
+            def step():
+                t = P.build(s_lo, s_hi)
+                k = P.match(t, u_lo, u_hi, out=out).numel()
+                t.free()
+                return k
+
+            for _ in range(args.warmup):
+                step()
+            wall, per, k2 = evented_steps(step, args.steps)
+            assert k2 == K
+            bf = lambda: P.match_brute(s_lo, s_hi, u_lo, u_hi, out=out).numel()
+            bf()
+            bwall, bper, kb = evented_steps(bf, 3)
+            assert kb == K
+            rows.append({"N": N, "alpha": alpha, "K": K, "itm_ms": step_stats(per),
+                         "brute_ms": step_stats(bper),
+                         "itm_pairs_per_s": round(K / (wall / 1e3), 1),
+                         "speedup_itm_vs_brute": round(bwall / wall, 2)})
+            log(f"N={N} alpha={alpha}: K={K} ITM {wall:.4f} ms, BF {bwall:.3f} ms")
+    last = [r for r in rows if r["N"] == 500_000 and r["alpha"] == 100.0][0]
+    return {"metric": "ITM build+match time, d=1 sweep of the paper's experiment",
+            "value": last["itm_pairs_per_s"], "unit": "pairs/s",
+            "ms_per_step": last["itm_ms"]["mean"], "dtype": "f32",
+            "config": {"workload": "sweep_1d_N5e4-5e5_alpha0.01-1-100",
+                       "value_at": "N=5e5 alpha=100"},
+            "sweep": rows, "roofline": None, "cpu_baseline": None}
+
+
 def bench_copy(args):
     """1 GiB device-to-device copy per step: the reference kernel whose
     FETCH_SIZE / WRITE_SIZE counters calibrate the traffic of the others."""
@@ -482,6 +536,8 @@ def main():
         rec = bench_serve(args)
     elif args.workload == "hbm_copy":
         rec = bench_copy(args)
+    elif args.workload == "sweep_1d":
+        rec = bench_sweep(args)
     else:
         rec = bench_single(args)
     head = {"metric": rec.pop("metric"), "value": rec.pop("value"), "unit": rec.pop("unit"),

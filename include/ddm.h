@@ -248,6 +248,21 @@ ddm_status ddm_count(const ddm_tree* t, const float* upd_lo, const float* upd_hi
                      uint32_t* counts, uint64_t* out_total, void* stream,
                      const ddm_match_opts* opts);
 
+/* ddm_match_brute -- the same result as ddm_build + ddm_match, computed by
+ * Brute-Force Matching (Algorithm 2: every update tested against every
+ * subscription, closed predicate in every dimension).  The paper's
+ * embarrassingly parallel baseline, for comparison on the same GPU.
+ *  sub_lo/sub_hi  device, d*n float32, dimension-major; upd_lo/upd_hi
+ *                 device, d*m float32; out_pairs device, capacity uint64
+ *                 (may be NULL when capacity is 0); out_count host, always
+ *                 receives K on DDM_OK / DDM_E_CAPACITY.
+ * Synchronizes the stream once; DDM_E_CAPACITY writes nothing; invalid
+ * coordinates give DDM_E_INVALID_INPUT.  Cost O(n m d).                     */
+ddm_status ddm_match_brute(const float* sub_lo, const float* sub_hi, uint32_t n,
+                           const float* upd_lo, const float* upd_hi, uint32_t m, uint32_t d,
+                           uint64_t* out_pairs, uint64_t capacity, uint64_t* out_count,
+                           void* stream);
+
 /* ddm_tree_check -- waits for the build to finish and reports whether the
  * subscription coordinates were valid (DDM_OK or DDM_E_INVALID_INPUT).      */
 ddm_status ddm_tree_check(const ddm_tree* t);
