@@ -205,6 +205,11 @@ void dev_free(char* p, hipStream_t s) {
   (void)hipGetLastError();
 }
 
+ddm_status scratch_overrun(const char* where) {
+  set_detail(std::string(where) + ": scratch takes exceed the reserved block");
+  return DDM_E_DEVICE;
+}
+
 Scratch::~Scratch() {
   if (base_) dev_free(base_, s_);
 }

@@ -126,6 +126,7 @@ extern "C" ddm_status ddm_match_brute(const float* sub_lo, const float* sub_hi, 
   uint64_t* tmp = sc.take<uint64_t>(scan_tmp_words(m));
   int32_t* flag = sc.take<int32_t>(1);
   uint64_t* words = sc.take<uint64_t>(2);
+  if (!sc.fits()) return scratch_overrun("ddm_match_brute");
   brute_init_kernel<<<1, 64, 0, s>>>(flag);
   DDM_LAUNCHED("brute_init_kernel");
   ddm_status r = launch_brute<false>(d, sub_lo, sub_hi, n, upd_lo, upd_hi, m, cnt, nullptr,

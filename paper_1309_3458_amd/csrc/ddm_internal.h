@@ -52,6 +52,9 @@ struct Scratch {
   // the block returns to the cache, ordered on the stream, at destruction.
   void reserve(size_t bytes) { want_ += (bytes + 255) & ~size_t(255); }
   bool commit();
+  // Every take() must have its own reserve() of the same size, in any
+  // order; fits() tells whether the takes so far stay inside the block and
+  // must be checked before any kernel uses the memory.
   template <class T>
   T* take(size_t count) {
     size_t b = (count * sizeof(T) + 255) & ~size_t(255);
@@ -59,10 +62,15 @@ struct Scratch {
     used_ += b;
     return reinterpret_cast<T*>(p);
   }
+  bool fits() const { return used_ <= want_; }
   hipStream_t s_;
   char* base_ = nullptr;
   size_t want_ = 0, used_ = 0;
 };
+
+// error for a scratch layout whose takes exceed its reservations (a
+// programming error caught before any kernel touches the memory)
+ddm_status scratch_overrun(const char* where);
 
 // stream-aware device memory cache and event pool (api.hip)
 char* dev_alloc(size_t bytes, hipStream_t s);

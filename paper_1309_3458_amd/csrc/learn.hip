@@ -184,6 +184,7 @@ ddm_status enqueue_feature_stats(const FeatArgs& A, hipStream_t s) {
   sc.reserve(sizeof(double) * nparts * A.d);
   if (!sc.commit()) return DDM_E_NOMEM;
   double* part = sc.take<double>(nparts * A.d);
+  if (!sc.fits()) return scratch_overrun("feature statistics");
   const uint32_t cnt = A.d * 2 * (kFeatBins + 1);
   feat_zero_kernel<<<(std::max(cnt, kSatWords) + 255) / 256, 256, 0, s>>>(A.fcum, cnt, A.sat);
   DDM_LAUNCHED("feat_zero_kernel");
@@ -535,6 +536,7 @@ ddm_status launch_mlp_grad(const float* params, const float* X, const float* Y, 
   if (!sc.commit()) return DDM_E_NOMEM;
   float* part = sc.take<float>(kParams * (size_t)nb);
   float* pl = sc.take<float>(nb);
+  if (!sc.fits()) return scratch_overrun("predictor gradient");
   ProfScope ps("mlp_grad", s);
   mlp_grad_kernel<<<nb, kGB, 0, s>>>(params, X, Y, N, part, pl);
   DDM_LAUNCHED("mlp_grad_kernel");
@@ -716,6 +718,7 @@ extern "C" ddm_status ddm_predictor_train(ddm_predictor* p, const float* X, cons
   sc.reserve(sizeof(float) * (size_t)nbat * epochs);
   if (!sc.commit()) return DDM_E_NOMEM;
   float* losses = sc.take<float>((size_t)nbat * epochs);
+  if (!sc.fits()) return scratch_overrun("predictor training");
   for (uint32_t e = 0; e < epochs; ++e) {
     for (uint32_t b = 0; b < nbat; ++b) {
       const uint32_t s0 = b * batch;

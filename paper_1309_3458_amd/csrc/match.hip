@@ -882,17 +882,22 @@ static ddm_status front_half(const ddm_tree* t, const float* ulo, const float* u
     sc.reserve(sizeof(uint32_t) * m);                   // perm_ovf
     sc.reserve(sizeof(uint32_t) * DDM_MAX_D);           // govf
   }
+  // one reservation per take below (each is rounded up to 256 bytes)
   sc.reserve(sizeof(uint32_t) * m);          // cmin
   sc.reserve(m);                             // kstar
-  sc.reserve(sizeof(uint32_t) * m * 3);      // rank, bucket, perm
+  sc.reserve(sizeof(uint32_t) * m);          // rank
+  sc.reserve(sizeof(uint32_t) * m);          // bucket
+  sc.reserve(sizeof(uint32_t) * m);          // perm
   sc.reserve(sizeof(uint32_t) * kBuckets);   // bucket histogram / offsets
-  sc.reserve(sizeof(uint32_t) * 2 * DDM_MAX_D);  // gstart, gcount
+  sc.reserve(sizeof(uint32_t) * DDM_MAX_D);  // gstart
+  sc.reserve(sizeof(uint32_t) * DDM_MAX_D);  // gcount
   sc.reserve(sizeof(int32_t));               // flag
   sc.reserve(sizeof(uint32_t) * m);          // cnt
   sc.reserve(sizeof(uint64_t) * (m + 1));    // off
   sc.reserve(sizeof(uint64_t) * scan_tmp_words(m));
-  sc.reserve(sizeof(uint32_t) * (2 * (size_t)m + 2));  // segment lists + counts
-  sc.reserve(sizeof(uint64_t) * 4);                    // device words for readback
+  sc.reserve(sizeof(uint32_t) * 2 * (size_t)m);  // segment lists
+  sc.reserve(sizeof(uint32_t) * 2);              // segment list counts
+  sc.reserve(sizeof(uint64_t) * 4);              // device words for readback
   if (!sc.commit()) return DDM_E_NOMEM;
   st.cmin = sc.take<uint32_t>(m);
   st.kstar = sc.take<uint8_t>(m);
@@ -916,6 +921,9 @@ static ddm_status front_half(const ddm_tree* t, const float* ulo, const float* u
     st.soff = sc.take<uint64_t>(m + 1);
     st.perm_ovf = sc.take<uint32_t>(m);
     st.govf = sc.take<uint32_t>(DDM_MAX_D);
+  }
+  if (!sc.fits()) return scratch_overrun("front_half");
+  if (st.learned) {
     learned_init_kernel<<<1, 64, 0, s>>>(st.govf);
     DDM_LAUNCHED("learned_init_kernel");
   }
@@ -966,6 +974,7 @@ static ddm_status front_half(const ddm_tree* t, const float* ulo, const float* u
     st.slots_sc.reserve(sizeof(uint64_t) * (budget ? budget : 1));
     if (!st.slots_sc.commit()) return DDM_E_NOMEM;
     st.slots = st.slots_sc.take<uint64_t>(budget ? budget : 1);
+    if (!st.slots_sc.fits()) return scratch_overrun("slot arena");
     SO.base = st.soff;
     SO.cap = st.cap;
     SO.limit = budget;
@@ -1083,6 +1092,7 @@ ddm_status sort_segments(const uint64_t* off, uint32_t m, uint64_t* out, uint64_
     sc.reserve(sizeof(uint32_t) * K);
     if (!sc.commit()) return DDM_E_NOMEM;
     tmp = sc.take<uint32_t>(K);
+    if (!sc.fits()) return scratch_overrun("segment sort");
     copy_ids_kernel<<<(unsigned)((K + 255) / 256), 256, 0, s>>>(out, tmp, K);
     DDM_LAUNCHED("copy_ids_kernel");
   }

@@ -165,6 +165,7 @@ ddm_status enqueue_tree_build(ddm_tree* t, const float* lo, const float* hi, hip
   SortArr* arrs = sc.take<SortArr>(narr);
   uint32_t* tile_map = sc.take<uint32_t>(ntiles);
   uint32_t* hist = sc.take<uint32_t>(256 * (size_t)ntiles);
+  if (!sc.fits()) return scratch_overrun("tree build");
 
   {
     ProfScope ps("build_keys", s);
