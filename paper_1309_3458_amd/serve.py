@@ -1,11 +1,10 @@
 """Open-loop serving driver: Poisson arrivals of match requests into a Server.
 
-The client thread submits every request of a pre-drawn schedule at its
-arrival time (its coordinates are generated in device memory at that
-moment); the drain thread collects completions.  Latency is measured from
-the scheduled arrival to the result in host memory, on the server's own
-CLOCK_MONOTONIC timestamps, so a client that falls behind the schedule is
-charged to the latency, not hidden.
+Every request of a pre-drawn schedule is submitted at its arrival time;
+its coordinates are generated in device memory shortly before.  Latency is
+measured from the scheduled arrival to the result in host memory, on the
+server's own CLOCK_MONOTONIC timestamps, so a client that falls behind the
+schedule is charged to the latency, not hidden.
 """
 from __future__ import annotations
 
@@ -24,36 +23,65 @@ def percentile(x, q):
     return float(np.percentile(np.asarray(x, dtype=np.float64), q))
 
 
-def run(server, schedule, sample_every: int = 100, lead_s: float = 0.2, log=None,
-        sample_max_pairs: int = 20_000_000, sample_bytes: int = 4 << 30):
+def run(server, schedule, sample_every: int = 100, lead_s: float = 0.5, log=None,
+        sample_max_pairs: int = 20_000_000, sample_bytes: int = 4 << 30,
+        lookahead_s: float = 0.25):
     """Serve `schedule` (a list of workloads.Request) on `server`.
 
-    Returns a dict of statistics plus `samples`: {request index: keys (uint64)}
-    for every sample_every-th request (up to sample_max_pairs pairs each and
-    sample_bytes in all), for identity checks after the run.
+    Three threads: the generator draws each request's coordinates in device
+    memory up to `lookahead_s` before its arrival (the data a real client
+    would have ready when it sends the request); the submitter hands each
+    request to the server at its scheduled arrival time; the drain thread
+    collects completions.  Latency runs from the scheduled arrival to the
+    result in host memory.  Returns a dict of statistics plus `samples`:
+    {request index: keys (uint64)} for every sample_every-th request (up to
+    sample_max_pairs pairs each and sample_bytes in all), for identity
+    checks after the run.
     """
+    import collections
+
     import torch
-    stream = torch.cuda.Stream()
+    gen_stream = torch.cuda.Stream()
+    sub_stream = torch.cuda.Stream()
+    ready = collections.deque()
+    cv = threading.Condition()
     ticket_of = {}
-    lat, K, regions, late = [], [], [], []
+    lat, wait, service, K, regions, late = [], [], [], [], [], []
     samples = {}
     kept = [0]
     errors = []
-    done_evt = threading.Event()
     n_req = len(schedule)
     t0 = time.monotonic_ns() + int(lead_s * 1e9)
+    la = int(lookahead_s * 1e9)
 
-    def client():
-        with torch.cuda.stream(stream):
+    def generator():
+        with torch.cuda.stream(gen_stream):
             for i, rq in enumerate(schedule):
-                target = t0 + int(rq.arrival_s * 1e9)
-                wait = (target - time.monotonic_ns()) / 1e9
-                if wait > 0:
-                    time.sleep(wait)
-                late.append(max(0, time.monotonic_ns() - target) / 1e6)
-                s_lo, s_hi, u_lo, u_hi = W.device_instance(rq.spec)
-                t = server.submit(s_lo, s_hi, u_lo, u_hi, arrival_ns=target, stream=stream)
-                ticket_of[t] = i
+                target = t0 + int(rq.arrival_s * 1e9) - la
+                dt = (target - time.monotonic_ns()) / 1e9
+                if dt > 0:
+                    time.sleep(dt)
+                tens = W.device_instance(rq.spec)
+                ev = torch.cuda.Event()
+                ev.record(gen_stream)
+                with cv:
+                    ready.append((i, tens, ev))
+                    cv.notify()
+
+    def submitter():
+        for i, rq in enumerate(schedule):
+            target = t0 + int(rq.arrival_s * 1e9)
+            with cv:
+                while not ready or ready[0][0] != i:
+                    cv.wait()
+                _, tens, ev = ready.popleft()
+            dt = (target - time.monotonic_ns()) / 1e9
+            if dt > 0:
+                time.sleep(dt)
+            late.append(max(0, time.monotonic_ns() - target) / 1e6)
+            ev.synchronize()
+            t = server.submit(*tens, arrival_ns=target, stream=sub_stream)
+            ticket_of[t] = i
 
     def drain():
         got = 0
@@ -71,6 +99,8 @@ def run(server, schedule, sample_every: int = 100, lead_s: float = 0.2, log=None
                     errors.append((i, r["status"], r.get("detail", "")))
                 else:
                     lat.append((r["t_done_ns"] - r["t_arrival_ns"]) / 1e6)
+                    wait.append((r["t_start_ns"] - r["t_arrival_ns"]) / 1e6)
+                    service.append((r["t_done_ns"] - r["t_start_ns"]) / 1e6)
                     K.append(r["count"])
                     regions.append(schedule[i].spec.N)
                     if "pairs" in r:
@@ -80,23 +110,25 @@ def run(server, schedule, sample_every: int = 100, lead_s: float = 0.2, log=None
                 if log and got % 5000 == 0:
                     log(f"served {got}/{n_req}: p50 {percentile(lat, 50):.2f} ms "
                         f"p99 {percentile(lat, 99):.2f} ms, {server.stats()}")
-        done_evt.set()
 
-    th_c = threading.Thread(target=client, daemon=True)
-    th_d = threading.Thread(target=drain, daemon=True)
-    th_d.start()
-    th_c.start()
-    th_c.join()
-    th_d.join()
+    threads = [threading.Thread(target=f, daemon=True) for f in (drain, generator, submitter)]
+    for th in threads:
+        th.start()
+    for th in threads:
+        th.join()
     t_end = time.monotonic_ns()
     span_s = (t_end - t0) / 1e9
     st = server.stats()
+
+    def pct(x):
+        return {"p50": round(percentile(x, 50), 3), "p99": round(percentile(x, 99), 3),
+                "mean": round(float(np.mean(x)) if x else math.nan, 3),
+                "max": round(max(x) if x else math.nan, 3)}
+
     return {
         "requests": n_req, "completed": len(lat), "errors": errors[:10],
         "n_errors": len(errors),
-        "latency_ms": {"p50": round(percentile(lat, 50), 3), "p99": round(percentile(lat, 99), 3),
-                       "mean": round(float(np.mean(lat)) if lat else math.nan, 3),
-                       "max": round(max(lat) if lat else math.nan, 3)},
+        "latency_ms": pct(lat), "queue_wait_ms": pct(wait), "service_ms": pct(service),
         "client_late_ms": {"p99": round(percentile(late, 99), 3),
                            "max": round(max(late) if late else math.nan, 3)},
         "pairs": int(sum(K)), "regions": int(sum(regions)), "span_s": round(span_s, 3),
