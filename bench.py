@@ -68,6 +68,12 @@ def parse():
                     help="serve: seconds of Poisson arrivals (the schedule is cut, not rescaled)")
     ap.add_argument("--rate", type=float, default=2000.0, help="serve: arrivals per second")
     ap.add_argument("--workers", type=int, default=8, help="serve: concurrent requests")
+    ap.add_argument("--batch-max", type=int, default=0,
+                    help="serve: small requests matched together (0 = library default, 1 = off)")
+    ap.add_argument("--batch-small", type=int, default=0,
+                    help="serve: largest n + m of a request that may be batched (0 = default)")
+    ap.add_argument("--deliver-device", action="store_true",
+                    help="serve: results stay in device memory (no PCIe copy)")
     ap.add_argument("--n-hi", type=float, default=1e6,
                     help="serve: largest request size N (the schedule's log-uniform range "
                          "is [1e3, n_hi])")
@@ -394,7 +400,9 @@ def bench_serve(args):
     else:
         pred, rep = learn.train_predictor(n_inst=32, per_instance=16000, epochs=20)
         log(f"predictor trained: {rep}")
-    srv = P.Server(predictor=pred, workers=args.workers, host_pool=4 << 30)
+    srv = P.Server(predictor=pred, workers=args.workers, host_pool=4 << 30,
+                   batch_max=args.batch_max, batch_small=args.batch_small,
+                   deliver_device=args.deliver_device)
     # warm-up on a different schedule (allocator caches, code objects)
     warm = W.serving_schedule(seed=104, rate=args.rate, duration_s=0.5, n_hi=args.n_hi)
     serve.run(srv, warm, sample_every=10 ** 9)
@@ -438,7 +446,8 @@ def bench_serve(args):
                    "pairs": st["pairs"], "regions": st["regions"], "workers": args.workers,
                    "learned_sizing": True,
                    "inputs": "generated in device memory just before arrival",
-                   "results": "pinned host memory"},
+                   "results": "device memory" if args.deliver_device else "pinned host memory",
+                   "batch_max": args.batch_max, "batch_small": args.batch_small},
         "checks": {"sampled_equal_alone": alone, "sampled_equal_oracle": n_or},
         "hbm_peak_bytes": st["hbm_peak_bytes"],
         "roofline": None,

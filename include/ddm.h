@@ -353,6 +353,18 @@ ddm_status ddm_batch_run(ddm_batch* b, void* stream);
  * nothing was written.                                                       */
 ddm_status ddm_batch_result(ddm_batch* b, uint64_t* total, uint64_t* ranges);
 
+/* Two-step run for batches created without a graph (opts.use_graph = 0),
+ * for callers that size the output from the count:
+ * ddm_batch_count enqueues everything up to the per-instance offsets on
+ * `stream`, waits for it, and returns the total (host) and, if ranges is not
+ * NULL, the count + 1 instance offsets (host); DDM_E_INVALID_INPUT if an
+ * instance has invalid coordinates.  ddm_batch_fill then writes the pairs
+ * into out_pairs (device, capacity uint64; the pointer given at creation is
+ * not used) on `stream`; DDM_E_CAPACITY, writing nothing, if capacity is
+ * below the total.  Each count is followed by at most one fill.             */
+ddm_status ddm_batch_count(ddm_batch* b, void* stream, uint64_t* total, uint64_t* ranges);
+ddm_status ddm_batch_fill(ddm_batch* b, uint64_t* out_pairs, uint64_t capacity, void* stream);
+
 /* ddm_batch_free -- waits for the batch's work and releases it; NULL is
  * ignored.                                                                    */
 void ddm_batch_free(ddm_batch* b);
@@ -365,7 +377,9 @@ void ddm_batch_free(ddm_batch* b);
  * once) and are matched concurrently by `workers` host threads, each
  * driving its own HIP stream: a request starts as soon as a worker is free
  * and the device-memory budget admits it, so requests overlap on the device
- * with the ones already running.  Admission is by footprint: inputs + trees
+ * with the ones already running.  Small requests queued together are
+ * matched as one batch (the ddm_batch kernels, sized on the device by their
+ * exact counts); large ones one by one.  Admission is by footprint: inputs + trees
  * + match scratch when a request starts (FIFO order), then the predicted
  * output (learned slot arena) and the exact output once known; the oldest
  * request in flight may always exceed the budget, so progress is
@@ -386,7 +400,11 @@ typedef struct {
   uint32_t tree_cache;     /* keyed trees kept resident after their request
                               (LRU); 0 = none                                */
   uint32_t deliver_device; /* nonzero: results stay in device memory         */
-  uint32_t reserved[4];    /* must be 0                                      */
+  uint32_t batch_max;      /* small requests matched together by one worker
+                              (batched kernels); 0 = 64, 1 = never batch    */
+  uint32_t batch_small;    /* a request is small if n + m <= batch_small
+                              (and n < 2^20, no tree key); 0 = 2^18        */
+  uint32_t reserved[2];    /* must be 0                                      */
 } ddm_server_opts;
 
 typedef struct {

@@ -415,6 +415,23 @@ class Batch:
         check(code, "ddm_batch_result")
         return self.total, rg
 
+    def count_pairs(self, stream=None):
+        """Two-step form (batches without a graph): the total and the
+        instance offsets, before any output exists."""
+        import numpy as np
+        tot = ctypes.c_uint64()
+        rg = np.zeros(self.count + 1, dtype=np.uint64)
+        check(lib().ddm_batch_count(self.handle, _stream_handle(stream), ctypes.byref(tot),
+                                    rg.ctypes.data_as(ctypes.c_void_p)), "ddm_batch_count")
+        self.total, self._ranges = int(tot.value), rg
+        return self.total, rg
+
+    def fill(self, out, stream=None):
+        """Second step: the pairs into `out` (int64 GPU tensor)."""
+        check(lib().ddm_batch_fill(self.handle, _ptr(out), out.numel(), _stream_handle(stream)),
+              "ddm_batch_fill")
+        self.out = out
+
     def pairs(self, i: int):
         if self._ranges is None:
             self.result()
@@ -445,12 +462,13 @@ class Server:
 
     def __init__(self, predictor: Predictor | None = None, hbm_budget: int = 0,
                  host_pool: int = 0, workers: int = 8, tree_cache: int = 0,
-                 deliver_device: bool = False):
+                 deliver_device: bool = False, batch_max: int = 0, batch_small: int = 0):
         from ._native import ServerOpts
         o = ServerOpts()
         o.hbm_budget, o.host_pool = int(hbm_budget), int(host_pool)
         o.workers, o.tree_cache, o.deliver_device = int(workers), int(tree_cache), \
             int(bool(deliver_device))
+        o.batch_max, o.batch_small = int(batch_max), int(batch_small)
         h = ctypes.c_void_p()
         check(lib().ddm_server_create(ctypes.byref(o),
                                       predictor.handle if predictor is not None else None,

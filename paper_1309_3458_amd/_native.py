@@ -55,7 +55,8 @@ class BatchOpts(ctypes.Structure):
 class ServerOpts(ctypes.Structure):
     _fields_ = [("hbm_budget", ctypes.c_uint64), ("host_pool", ctypes.c_uint64),
                 ("workers", ctypes.c_uint32), ("tree_cache", ctypes.c_uint32),
-                ("deliver_device", ctypes.c_uint32), ("reserved", ctypes.c_uint32 * 4)]
+                ("deliver_device", ctypes.c_uint32), ("batch_max", ctypes.c_uint32),
+                ("batch_small", ctypes.c_uint32), ("reserved", ctypes.c_uint32 * 2)]
 
 
 class Request(ctypes.Structure):
@@ -142,6 +143,8 @@ def lib():
     _sig(L, "ddm_batch_run", i32, vp, vp)
     _sig(L, "ddm_batch_result", i32, vp, P(u64), vp)
     _sig(L, "ddm_batch_free", None, vp)
+    _sig(L, "ddm_batch_count", i32, vp, vp, P(u64), vp)
+    _sig(L, "ddm_batch_fill", i32, vp, vp, u64, vp)
     _sig(L, "ddm_server_create", i32, P(ServerOpts), vp, P(vp))
     _sig(L, "ddm_server_submit", i32, vp, P(Request), ctypes.c_int64, vp, P(u64))
     _sig(L, "ddm_server_wait_any", u32, vp, u32, vp, u32)

@@ -392,12 +392,14 @@ struct ddm_batch {
   uint32_t* zero_base = nullptr;  // contiguous words cleared per run
   uint32_t nzero = 0;
   uint32_t* list_counters = nullptr;  // two words in the cleared block
+  bool counted = false;               // ddm_batch_count ran, ddm_batch_fill may follow
 };
 
 namespace ddm {
 ddm_status ensure_segsort_attr();
 
-static ddm_status batch_enqueue(ddm_batch* b, hipStream_t s) {
+// count half: trees, probe, order, count traversal, offsets, ranges
+static ddm_status batch_count_half(ddm_batch* b, hipStream_t s) {
   // clear counters, histograms, flags and length bounds
   b_reset_kernel<<<(b->nzero + 255) / 256, 256, 0, s>>>(b->zero_base, b->nzero);
   DDM_LAUNCHED("b_reset_kernel");
@@ -439,6 +441,12 @@ static ddm_status batch_enqueue(ddm_batch* b, hipStream_t s) {
   b_ranges_kernel<<<(b->count + 1 + 255) / 256, 256, 0, s>>>(b->inst, b->count, b->off,
                                                              b->words + 2);
   DDM_LAUNCHED("b_ranges_kernel");
+  return DDM_OK;
+}
+
+// fill half: capacity and validity check, fill traversal, segment sort into
+// b->out (b->capacity keys)
+static ddm_status batch_fill_half(ddm_batch* b, hipStream_t s) {
   b_status_kernel<<<1, 64, 0, s>>>(b->inst, b->count, b->off, b->M, b->capacity, b->status,
                                    b->words);
   DDM_LAUNCHED("b_status_kernel");
@@ -455,6 +463,12 @@ static ddm_status batch_enqueue(ddm_batch* b, hipStream_t s) {
     DDM_LAUNCHED("b_traverse_kernel");
   }
   return sort_segments_inplace(b->off, b->M, b->out, b->nmax, b->lists, b->list_counters, s);
+}
+
+static ddm_status batch_enqueue(ddm_batch* b, hipStream_t s) {
+  ddm_status r = batch_count_half(b, s);
+  if (r != DDM_OK) return r;
+  return batch_fill_half(b, s);
 }
 
 }  // namespace ddm
@@ -791,9 +805,9 @@ extern "C" ddm_status ddm_batch_create(const ddm_batch_instance* inst, uint32_t 
   if (e == hipSuccess) e = up(b->tile_map, htile.data(), sizeof(uint32_t) * htile.size());
   if (e == hipSuccess)
     e = hipHostMalloc((void**)&b->host_words, sizeof(uint64_t) * (count + 3), hipHostMallocDefault);
-  if (e == hipSuccess) e = hipStreamCreateWithFlags(&b->cap, hipStreamNonBlocking);
-  if (e == hipSuccess) e = hipEventCreateWithFlags(&b->ev_in, hipEventDisableTiming);
-  if (e == hipSuccess) e = hipEventCreateWithFlags(&b->ev_out, hipEventDisableTiming);
+  if (e == hipSuccess && o.use_graph) e = hipStreamCreateWithFlags(&b->cap, hipStreamNonBlocking);
+  if (e == hipSuccess && o.use_graph) e = hipEventCreateWithFlags(&b->ev_in, hipEventDisableTiming);
+  if (e == hipSuccess && o.use_graph) e = hipEventCreateWithFlags(&b->ev_out, hipEventDisableTiming);
   if (e != hipSuccess) {
     ddm_status r = hip_fail(e, "ddm_batch_create", __FILE__, __LINE__);
     ddm_batch_free(b);
@@ -856,6 +870,55 @@ extern "C" ddm_status ddm_batch_result(ddm_batch* b, uint64_t* total, uint64_t* 
     return DDM_E_CAPACITY;
   }
   return DDM_OK;
+}
+
+extern "C" ddm_status ddm_batch_count(ddm_batch* b, void* stream, uint64_t* total,
+                                      uint64_t* ranges) {
+  set_detail("");
+  if (!b || !total) return DDM_E_INVALID_ARG;
+  if (b->opts.use_graph) {
+    set_detail("ddm_batch_count: only for batches created without a graph");
+    return DDM_E_INVALID_ARG;
+  }
+  hipStream_t s = (hipStream_t)stream;
+  b->last = s;
+  ddm_status r = batch_count_half(b, s);
+  if (r != DDM_OK) return r;
+  // validity only: the capacity is given to ddm_batch_fill
+  b_status_kernel<<<1, 64, 0, s>>>(b->inst, b->count, b->off, b->M, ~0ull, b->status, b->words);
+  DDM_LAUNCHED("b_status_kernel");
+  DDM_HIP(hipMemcpyAsync(b->host_words, b->words, sizeof(uint64_t) * (b->count + 3),
+                         hipMemcpyDeviceToHost, s));
+  DDM_HIP(hipStreamSynchronize(s));
+  *total = b->host_words[0];
+  if (ranges)
+    for (uint32_t i = 0; i <= b->count; ++i) ranges[i] = b->host_words[2 + i];
+  b->counted = true;
+  if (b->host_words[1] & kBatchStatusInput) {
+    set_detail("a batch instance has NaN/inf coordinates or lo > hi");
+    return DDM_E_INVALID_INPUT;
+  }
+  return DDM_OK;
+}
+
+extern "C" ddm_status ddm_batch_fill(ddm_batch* b, uint64_t* out_pairs, uint64_t capacity,
+                                     void* stream) {
+  set_detail("");
+  if (!b || (capacity && !out_pairs)) return DDM_E_INVALID_ARG;
+  if (!b->counted) {
+    set_detail("ddm_batch_fill: ddm_batch_count must run first");
+    return DDM_E_INVALID_ARG;
+  }
+  if (b->host_words[0] > capacity) {
+    set_detail("batch result larger than capacity");
+    return DDM_E_CAPACITY;
+  }
+  hipStream_t s = (hipStream_t)stream;
+  b->last = s;
+  b->out = out_pairs;
+  b->capacity = capacity;
+  b->counted = false;
+  return batch_fill_half(b, s);
 }
 
 extern "C" void ddm_batch_free(ddm_batch* b) {

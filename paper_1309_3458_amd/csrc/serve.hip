@@ -6,7 +6,10 @@
 // takes requests from one FIFO as soon as the device-memory budget admits
 // them; requests therefore start the moment a worker and memory free up and
 // their kernels overlap on the device with those of the requests already
-// running (continuous batching at request granularity).  The footprint of a
+// running.  A worker that takes a small request also takes the small
+// requests queued behind it (up to batch_max) and matches them together
+// with the batched kernels (continuous batching: whatever has arrived by the
+// time a worker frees up joins the next launch).  The footprint of a
 // request is charged in two steps: inputs + trees + match scratch at
 // admission (known from n, m, d), then the predicted output (the learned
 // slot arena) and the exact output once the match has sized them.  A
@@ -337,6 +340,123 @@ ddm_status process(ddm_server* S, ddm_server_req* q, hipStream_t s, std::string*
   return DDM_OK;
 }
 
+bool batchable(const ddm_server* S, const ddm_request& r) {
+  return S->o.batch_max > 1 && r.tree_key == 0 && r.n > 0 && r.m > 0 && r.n < (1u << 20) &&
+         (uint64_t)r.n + r.m <= S->o.batch_small && r.sub_lo && r.sub_hi;
+}
+
+// Small requests admitted together are matched as one batch (one tree build,
+// one probe, persistent count and fill traversals over all of them); the
+// pairs of each request are its own, bit for bit.  A batch that reports
+// invalid coordinates is redone request by request, so that only the
+// offending request fails.
+void process_batch(ddm_server* S, const std::vector<ddm_server_req*>& G, hipStream_t s,
+                   std::vector<ddm_status>* st, std::vector<std::string>* why) {
+  const uint32_t count = (uint32_t)G.size();
+  st->assign(count, DDM_OK);
+  why->assign(count, std::string());
+  auto alone = [&]() {
+    for (uint32_t i = 0; i < count; ++i) {
+      (*st)[i] = process(S, G[i], s, &(*why)[i]);
+      if ((*st)[i] != DDM_OK) (void)hipStreamSynchronize(s);
+    }
+  };
+  for (auto* q : G)
+    if (q->ready && hipStreamWaitEvent(s, q->ready, 0) != hipSuccess) {
+      (void)hipGetLastError();
+      return alone();
+    }
+  std::vector<ddm_batch_instance> inst(count);
+  for (uint32_t i = 0; i < count; ++i) {
+    const ddm_request& r = G[i]->r;
+    inst[i] = ddm_batch_instance{r.sub_lo, r.sub_hi, r.upd_lo, r.upd_hi, r.n, r.m, r.d, 0};
+  }
+  ddm_batch_opts bo{};
+  ddm_batch* b = nullptr;
+  if (ddm_batch_create(inst.data(), count, nullptr, 0, &bo, &b) != DDM_OK) return alone();
+  std::vector<uint64_t> ranges(count + 1);
+  uint64_t total = 0;
+  ddm_status r = ddm_batch_count(b, s, &total, ranges.data());
+  if (r != DDM_OK) {
+    ddm_batch_free(b);
+    return alone();
+  }
+  const uint64_t out_bytes = 8 * std::max<uint64_t>(total, 1);
+  {
+    std::unique_lock<std::mutex> lk(S->mu);
+    charge(S, lk, G[0], out_bytes);
+  }
+  uint64_t* out = (uint64_t*)dev_alloc(out_bytes, s);
+  if (!out) {
+    ddm_batch_free(b);
+    std::lock_guard<std::mutex> lk(S->mu);
+    uncharge(S, G[0], out_bytes);
+    for (uint32_t i = 0; i < count; ++i) {
+      (*st)[i] = DDM_E_NOMEM;
+      (*why)[i] = "device allocation of a batch result failed";
+    }
+    return;
+  }
+  r = ddm_batch_fill(b, out, total, s);
+  if (r == DDM_OK && !S->o.deliver_device) {
+    for (uint32_t i = 0; i < count && r == DDM_OK; ++i) {
+      ddm_server_req* q = G[i];
+      q->K = ranges[i + 1] - ranges[i];
+      const uint64_t bytes = 8 * std::max<uint64_t>(q->K, 1);
+      char* host = nullptr;
+      {
+        std::unique_lock<std::mutex> lk(S->mu);
+        if (bytes <= S->pool.size)
+          S->cv_mem.wait(lk, [&] { return S->stop || (host = S->pool.alloc(bytes)) != nullptr; });
+      }
+      if (!host) {
+        (*st)[i] = bytes > S->pool.size ? DDM_E_CAPACITY : DDM_E_INVALID_ARG;
+        (*why)[i] = "no room in the pinned host pool";
+        continue;
+      }
+      q->host = host;
+      if (q->K && hipMemcpyAsync(host, out + ranges[i], 8 * q->K, hipMemcpyDeviceToHost, s) !=
+                      hipSuccess) {
+        r = hip_fail(hipGetLastError(), "result copy", __FILE__, __LINE__);
+      }
+    }
+  } else if (r == DDM_OK) {
+    // device delivery: every request gets its own copy of its range
+    for (uint32_t i = 0; i < count && r == DDM_OK; ++i) {
+      ddm_server_req* q = G[i];
+      q->K = ranges[i + 1] - ranges[i];
+      const uint64_t bytes = 8 * std::max<uint64_t>(q->K, 1);
+      uint64_t* d = (uint64_t*)dev_alloc(bytes, s);
+      if (!d) {
+        (*st)[i] = DDM_E_NOMEM;
+        (*why)[i] = "device allocation of a result failed";
+        continue;
+      }
+      if (q->K && hipMemcpyAsync(d, out + ranges[i], 8 * q->K, hipMemcpyDeviceToDevice, s) !=
+                      hipSuccess)
+        r = hip_fail(hipGetLastError(), "result copy", __FILE__, __LINE__);
+      q->dev = d;
+      std::unique_lock<std::mutex> lk(S->mu);
+      S->used += bytes;  // held until the request is released
+      if (S->used > S->peak) S->peak = S->used;
+    }
+  }
+  if (hipStreamSynchronize(s) != hipSuccess && r == DDM_OK)
+    r = hip_fail(hipGetLastError(), "batch", __FILE__, __LINE__);
+  ddm_batch_free(b);
+  dev_free((char*)out, s);
+  {
+    std::lock_guard<std::mutex> lk(S->mu);
+    uncharge(S, G[0], out_bytes);
+  }
+  if (r != DDM_OK)
+    for (uint32_t i = 0; i < count; ++i)
+      if ((*st)[i] == DDM_OK) {
+        (*st)[i] = r;
+        (*why)[i] = ddm_last_error_detail();
+      }
+}
+
 void worker_main(ddm_server* S) {
   (void)hipSetDevice(S->device);
   hipStream_t s = nullptr;
@@ -344,8 +464,11 @@ void worker_main(ddm_server* S) {
     (void)hipGetLastError();
     s = nullptr;
   }
+  std::vector<ddm_server_req*> G;
+  std::vector<ddm_status> sts;
+  std::vector<std::string> whys;
   while (true) {
-    ddm_server_req* q = nullptr;
+    G.clear();
     {
       std::unique_lock<std::mutex> lk(S->mu);
       S->cv_work.wait(lk, [&] {
@@ -357,29 +480,48 @@ void worker_main(ddm_server* S) {
                S->used + admission_bytes(h->r, !resident) <= S->o.hbm_budget;
       });
       if (S->stop) break;
-      q = S->queue.front();
-      S->queue.pop_front();
-      const bool resident = q->r.tree_key && S->trees.count(q->r.tree_key);
-      const uint64_t b = admission_bytes(q->r, !resident);
-      S->used += b;
-      q->charged = b;
-      if (S->used > S->peak) S->peak = S->used;
-      S->in_flight[q->ticket] = 1;
-      q->t_start = now_ns();
+      // the head request, then (if it is small) the small requests behind it
+      // that the budget admits, up to batch_max
+      while (!S->queue.empty()) {
+        ddm_server_req* h = S->queue.front();
+        const bool resident = h->r.tree_key && S->trees.count(h->r.tree_key);
+        const uint64_t b = admission_bytes(h->r, !resident);
+        if (!G.empty() && (G.size() >= S->o.batch_max || !batchable(S, h->r) ||
+                           S->used + b > S->o.hbm_budget))
+          break;
+        S->queue.pop_front();
+        S->used += b;
+        h->charged = b;
+        if (S->used > S->peak) S->peak = S->used;
+        S->in_flight[h->ticket] = 1;
+        h->t_start = now_ns();
+        G.push_back(h);
+        if (!batchable(S, h->r)) break;
+      }
       if (!S->queue.empty()) S->cv_work.notify_one();
     }
-    std::string why;
-    ddm_status st = s ? process(S, q, s, &why) : DDM_E_DEVICE;
-    if (!s) why = "worker stream creation failed";
-    if (st != DDM_OK && s) (void)hipStreamSynchronize(s);
-    {
-      // inputs, tree (unless cached) and scratch are no longer held; a
-      // device-side result stays charged until it is released
-      std::lock_guard<std::mutex> lk(S->mu);
-      const uint64_t keep = q->dev ? 8 * std::max<uint64_t>(q->K, 1) : 0;
-      uncharge(S, q, q->charged - std::min(keep, q->charged));
+    if (!s) {
+      sts.assign(G.size(), DDM_E_DEVICE);
+      whys.assign(G.size(), "worker stream creation failed");
+    } else if (G.size() == 1) {
+      sts.assign(1, DDM_OK);
+      whys.assign(1, std::string());
+      sts[0] = process(S, G[0], s, &whys[0]);
+      if (sts[0] != DDM_OK) (void)hipStreamSynchronize(s);
+    } else {
+      process_batch(S, G, s, &sts, &whys);
     }
-    finish(S, q, st, why);
+    for (size_t i = 0; i < G.size(); ++i) {
+      ddm_server_req* q = G[i];
+      {
+        // inputs, tree (unless cached) and scratch are no longer held; a
+        // device-side result stays charged until it is released
+        std::lock_guard<std::mutex> lk(S->mu);
+        const uint64_t keep = (q->dev && G.size() == 1) ? 8 * std::max<uint64_t>(q->K, 1) : 0;
+        uncharge(S, q, q->charged - std::min(keep, q->charged));
+      }
+      finish(S, q, sts[i], whys[i]);
+    }
   }
   if (s) {
     (void)hipStreamSynchronize(s);
@@ -396,7 +538,7 @@ extern "C" ddm_status ddm_server_create(const ddm_server_opts* opts, ddm_predict
   *out = nullptr;
   ddm_server_opts o{};
   if (opts) o = *opts;
-  for (int i = 0; i < 4; ++i)
+  for (int i = 0; i < 2; ++i)
     if (o.reserved[i]) {
       set_detail("ddm_server_opts: reserved fields must be zero");
       return DDM_E_INVALID_ARG;
@@ -404,6 +546,12 @@ extern "C" ddm_status ddm_server_create(const ddm_server_opts* opts, ddm_predict
   if (o.hbm_budget == 0) o.hbm_budget = 64ull << 30;
   if (o.host_pool == 0 && !o.deliver_device) o.host_pool = 4ull << 30;
   if (o.workers == 0) o.workers = 8;
+  if (o.batch_max == 0) o.batch_max = 64;
+  if (o.batch_small == 0) o.batch_small = 1u << 18;
+  if (o.batch_max > DDM_BATCH_MAX_INSTANCES) {
+    set_detail("ddm_server_opts: batch_max above DDM_BATCH_MAX_INSTANCES");
+    return DDM_E_INVALID_ARG;
+  }
   if (o.workers > 64) {
     set_detail("ddm_server_opts: at most 64 workers");
     return DDM_E_INVALID_ARG;

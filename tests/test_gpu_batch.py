@@ -127,6 +127,35 @@ def test_graph_replays_equal_eager_and_follow_inputs():
     g.free()
 
 
+def test_two_step_count_then_fill():
+    """ddm_batch_count gives the total and ranges before any output exists;
+    ddm_batch_fill then writes exactly the one-step bytes."""
+    import paper_1309_3458_amd as P
+    torch = _torch()
+    insts = _small_batch(36, 10)
+    want = [oracle.itm(i.s_lo, i.s_hi, i.u_lo, i.u_hi, threads=8) for i in insts]
+    b = P.Batch(_tensors(insts), 0, use_graph=False)
+    tot, rg = b.count_pairs()
+    assert tot == sum(len(w) for w in want)
+    assert np.array_equal(np.diff(rg.astype(np.int64)), [len(w) for w in want])
+    out = torch.empty(tot, dtype=torch.int64, device="cuda")
+    b.fill(out)
+    torch.cuda.synchronize()
+    host = out.cpu().numpy().view(np.uint64)
+    for i, w in enumerate(want):
+        assert np.array_equal(host[int(rg[i]):int(rg[i + 1])], w)
+    # count again, then a fill that does not fit
+    b.count_pairs()
+    with pytest.raises(P.DDMError) as e:
+        b.fill(out[: max(0, tot - 1)])
+    assert e.value.code == -3
+    b.free()
+    g = P.Batch(_tensors(insts[:2]), 10 ** 7, use_graph=True)
+    with pytest.raises(P.DDMError):
+        g.count_pairs()
+    g.free()
+
+
 def test_capacity_and_invalid_input():
     import paper_1309_3458_amd as P
     torch = _torch()

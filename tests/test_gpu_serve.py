@@ -66,11 +66,13 @@ def _alone(inst):
     return k
 
 
-@pytest.mark.parametrize("workers", [1, 8])
-def test_burst_equals_alone_and_oracle(workers):
+@pytest.mark.parametrize("workers,batch_max", [(1, 1), (8, 1), (1, 0), (8, 0), (3, 5)])
+def test_burst_equals_alone_and_oracle(workers, batch_max):
+    """batch_max 1: every request alone; 0: small requests queued together
+    are matched as one batch (default 64); 5: small batches."""
     import paper_1309_3458_amd as P
     insts = _mixed(60 + workers, 40)
-    srv = P.Server(workers=workers, host_pool=1 << 30)
+    srv = P.Server(workers=workers, host_pool=1 << 30, batch_max=batch_max)
     res = _serve_all(srv, insts)
     for i, (inst, r) in enumerate(zip(insts, res)):
         assert r["status"] == 0, r
@@ -151,10 +153,11 @@ def test_invalid_request_fails_alone():
     srv.close()
 
 
-def test_device_delivery():
+@pytest.mark.parametrize("batch_max", [1, 0])
+def test_device_delivery(batch_max):
     import paper_1309_3458_amd as P
     insts = _mixed(93, 8)
-    srv = P.Server(workers=4, deliver_device=True)
+    srv = P.Server(workers=2, deliver_device=True, batch_max=batch_max)
     res = _serve_all(srv, insts)
     for inst, r in zip(insts, res):
         assert r["status"] == 0
