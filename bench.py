@@ -74,6 +74,8 @@ def parse():
                     help="serve: largest n + m of a request that may be batched (0 = default)")
     ap.add_argument("--deliver-device", action="store_true",
                     help="serve: results stay in device memory (no PCIe copy)")
+    ap.add_argument("--compact", action="store_true",
+                    help="serve: host results as subscription ids + update offsets")
     ap.add_argument("--n-hi", type=float, default=1e6,
                     help="serve: largest request size N (the schedule's log-uniform range "
                          "is [1e3, n_hi])")
@@ -402,7 +404,7 @@ def bench_serve(args):
         log(f"predictor trained: {rep}")
     srv = P.Server(predictor=pred, workers=args.workers, host_pool=4 << 30,
                    batch_max=args.batch_max, batch_small=args.batch_small,
-                   deliver_device=args.deliver_device)
+                   deliver_device=args.deliver_device, compact=args.compact)
     # warm-up on a different schedule (allocator caches, code objects)
     warm = W.serving_schedule(seed=104, rate=args.rate, duration_s=0.5, n_hi=args.n_hi)
     serve.run(srv, warm, sample_every=10 ** 9)
@@ -447,7 +449,8 @@ def bench_serve(args):
                    "learned_sizing": True,
                    "inputs": "generated in device memory just before arrival",
                    "results": "device memory" if args.deliver_device else "pinned host memory",
-                   "batch_max": args.batch_max, "batch_small": args.batch_small},
+                   "batch_max": args.batch_max, "batch_small": args.batch_small,
+                   "compact_results": args.compact},
         "checks": {"sampled_equal_alone": alone, "sampled_equal_oracle": n_or},
         "hbm_peak_bytes": st["hbm_peak_bytes"],
         "roofline": None,

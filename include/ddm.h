@@ -263,6 +263,23 @@ ddm_status ddm_match_brute(const float* sub_lo, const float* sub_hi, uint32_t n,
                            uint64_t* out_pairs, uint64_t capacity, uint64_t* out_count,
                            void* stream);
 
+/* ddm_tree_update -- moves `count` subscriptions of a resident tree to new
+ * extents (dynamic DDM: extents move between matches, Sec. I, Sec. VI), so
+ * that later matches see the moved set without a new ddm_build.
+ *  ids            device, count distinct uint32 subscription ids (< n).
+ *  new_lo/new_hi  device, [d][count] float32, dimension-major: the new
+ *                 extent of subscription ids[c] is column c.
+ *  out_rebuilt    host, may be NULL: 0 if every tree kept its (lower bound,
+ *                 id) order and was refitted in place (records rewritten,
+ *                 maxupper and the search samples recomputed, no sort), 1 if
+ *                 the order changed and the tree was rebuilt from its own
+ *                 records with the moves applied.
+ * Synchronizes the stream once.  DDM_E_INVALID_INPUT (tree unchanged) for
+ * an id out of range or an invalid new extent.  The caller must make sure
+ * that no match on another stream reads the tree meanwhile.               */
+ddm_status ddm_tree_update(ddm_tree* t, const uint32_t* ids, const float* new_lo,
+                           const float* new_hi, uint32_t count, void* stream, int* out_rebuilt);
+
 /* ddm_tree_check -- waits for the build to finish and reports whether the
  * subscription coordinates were valid (DDM_OK or DDM_E_INVALID_INPUT).      */
 ddm_status ddm_tree_check(const ddm_tree* t);
@@ -377,9 +394,9 @@ void ddm_batch_free(ddm_batch* b);
  * once) and are matched concurrently by `workers` host threads, each
  * driving its own HIP stream: a request starts as soon as a worker is free
  * and the device-memory budget admits it, so requests overlap on the device
- * with the ones already running.  Small requests queued together are
- * matched as one batch (the ddm_batch kernels, sized on the device by their
- * exact counts); large ones one by one.  Admission is by footprint: inputs + trees
+ * with the ones already running.  Optionally (batch_max > 1) small
+ * requests queued together are matched as one batch (the ddm_batch kernels,
+ * sized on the device by their exact counts).  Admission is by footprint: inputs + trees
  * + match scratch when a request starts (FIFO order), then the predicted
  * output (learned slot arena) and the exact output once known; the oldest
  * request in flight may always exceed the budget, so progress is
@@ -400,11 +417,16 @@ typedef struct {
   uint32_t tree_cache;     /* keyed trees kept resident after their request
                               (LRU); 0 = none                                */
   uint32_t deliver_device; /* nonzero: results stay in device memory         */
-  uint32_t batch_max;      /* small requests matched together by one worker
-                              (batched kernels); 0 = 64, 1 = never batch    */
+  uint32_t batch_max;      /* up to this many small requests are matched
+                              together by one worker (batched kernels);
+                              0 or 1 = never batch                          */
   uint32_t batch_small;    /* a request is small if n + m <= batch_small
                               (and n < 2^20, no tree key); 0 = 2^18        */
-  uint32_t reserved[2];    /* must be 0                                      */
+  uint32_t compact;        /* nonzero: host results as subscription ids
+                              (uint32, K) plus update offsets (uint64, m+1)
+                              instead of 64-bit keys -- the same pairs in
+                              the same order, in about half the bytes       */
+  uint32_t reserved[1];    /* must be 0                                      */
 } ddm_server_opts;
 
 typedef struct {
@@ -423,13 +445,19 @@ typedef struct {
   int32_t status;          /* 1 = pending, else the request's ddm_status      */
   uint32_t on_device;      /* pairs is a device pointer                       */
   uint64_t count;          /* K                                               */
-  const uint64_t* pairs;   /* K sorted keys, valid until ddm_server_release   */
+  const uint64_t* pairs;   /* K sorted keys, valid until ddm_server_release;
+                              NULL for compact results                       */
   int64_t t_arrival_ns;    /* arrival (given to submit, or submit time)       */
   int64_t t_start_ns;      /* admitted onto a worker                          */
   int64_t t_done_ns;       /* result in host (or device) memory               */
   uint64_t slots;          /* learned slot arena of the request (0 if none)   */
   uint32_t overflowed;     /* updates that took the exact fallback            */
-  uint32_t pad;
+  uint32_t m;              /* updates of the request                          */
+  const uint32_t* sub_ids;      /* compact results (host): the subscription
+                                   of every pair, K entries                  */
+  const uint64_t* upd_offsets;  /* compact results (host): update j's pairs
+                                   are sub_ids[upd_offsets[j] ..
+                                   upd_offsets[j+1]), m + 1 entries          */
 } ddm_result;
 
 typedef struct {

@@ -78,6 +78,23 @@ class Tree:
                                     ids.ctypes.data, mx.ctypes.data), "ddm_tree_export")
         return lo, hi, ids, mx
 
+    def update(self, ids, new_lo, new_hi, stream=None) -> bool:
+        """Move subscriptions `ids` (int32/uint32 GPU tensor) to new extents
+        ([d, count] float32 GPU tensors); True if the tree was rebuilt, False
+        if it was refitted in place."""
+        torch = _torch()
+        new_lo, new_hi = _coords(new_lo, new_hi, "Tree.update")
+        if ids.dtype not in (torch.int32, torch.uint32) or not ids.is_cuda:
+            raise TypeError("Tree.update: ids must be an int32 GPU tensor")
+        ids = ids.contiguous()
+        if new_lo.shape != (self.d, ids.numel()):
+            raise ValueError("Tree.update: new extents must be [d, len(ids)]")
+        rb = ctypes.c_int()
+        check(lib().ddm_tree_update(self.handle, _ptr(ids), _ptr(new_lo), _ptr(new_hi),
+                                    ids.numel(), _stream_handle(stream), ctypes.byref(rb)),
+              "ddm_tree_update")
+        return bool(rb.value)
+
     def free(self):
         if self._h is not None:
             lib().ddm_tree_free(self._h)
@@ -462,13 +479,15 @@ class Server:
 
     def __init__(self, predictor: Predictor | None = None, hbm_budget: int = 0,
                  host_pool: int = 0, workers: int = 8, tree_cache: int = 0,
-                 deliver_device: bool = False, batch_max: int = 0, batch_small: int = 0):
+                 deliver_device: bool = False, batch_max: int = 0, batch_small: int = 0,
+                 compact: bool = False):
         from ._native import ServerOpts
         o = ServerOpts()
         o.hbm_budget, o.host_pool = int(hbm_budget), int(host_pool)
         o.workers, o.tree_cache, o.deliver_device = int(workers), int(tree_cache), \
             int(bool(deliver_device))
-        o.batch_max, o.batch_small = int(batch_max), int(batch_small)
+        o.batch_max, o.batch_small, o.compact = int(batch_max), int(batch_small), \
+            int(bool(compact))
         h = ctypes.c_void_p()
         check(lib().ddm_server_create(ctypes.byref(o),
                                       predictor.handle if predictor is not None else None,
@@ -520,7 +539,16 @@ class Server:
         if r.status not in (0, 1):
             d["detail"] = lib().ddm_last_error_detail().decode()
         if copy and r.status == 0:
-            if r.count == 0:
+            if r.sub_ids is not None or r.upd_offsets is not None:
+                # compact form -> the same keys
+                K, m = int(r.count), int(r.m)
+                ids = np.frombuffer((ctypes.c_uint32 * K).from_address(int(r.sub_ids)),
+                                    dtype=np.uint32) if K else np.zeros(0, np.uint32)
+                off = np.frombuffer((ctypes.c_uint64 * (m + 1)).from_address(int(r.upd_offsets)),
+                                    dtype=np.uint64)
+                upd = np.repeat(np.arange(m, dtype=np.uint64), np.diff(off).astype(np.int64))
+                d["pairs"] = (upd << np.uint64(32)) | ids.astype(np.uint64)
+            elif r.count == 0:
                 d["pairs"] = np.zeros(0, dtype=np.uint64)
             elif r.on_device:
                 torch = _torch()

@@ -56,7 +56,8 @@ class ServerOpts(ctypes.Structure):
     _fields_ = [("hbm_budget", ctypes.c_uint64), ("host_pool", ctypes.c_uint64),
                 ("workers", ctypes.c_uint32), ("tree_cache", ctypes.c_uint32),
                 ("deliver_device", ctypes.c_uint32), ("batch_max", ctypes.c_uint32),
-                ("batch_small", ctypes.c_uint32), ("reserved", ctypes.c_uint32 * 2)]
+                ("batch_small", ctypes.c_uint32), ("compact", ctypes.c_uint32),
+                ("reserved", ctypes.c_uint32 * 1)]
 
 
 class Request(ctypes.Structure):
@@ -71,7 +72,8 @@ class Result(ctypes.Structure):
                 ("count", ctypes.c_uint64), ("pairs", ctypes.c_void_p),
                 ("t_arrival_ns", ctypes.c_int64), ("t_start_ns", ctypes.c_int64),
                 ("t_done_ns", ctypes.c_int64), ("slots", ctypes.c_uint64),
-                ("overflowed", ctypes.c_uint32), ("pad", ctypes.c_uint32)]
+                ("overflowed", ctypes.c_uint32), ("m", ctypes.c_uint32),
+                ("sub_ids", ctypes.c_void_p), ("upd_offsets", ctypes.c_void_p)]
 
 
 class ServerCounters(ctypes.Structure):
@@ -118,6 +120,7 @@ def lib():
     _sig(L, "ddm_count", i32, vp, vp, vp, u32, vp, P(u64), vp, P(MatchOpts))
     _sig(L, "ddm_match_brute", i32, vp, vp, u32, vp, vp, u32, u32, vp, u64, P(u64), vp)
     _sig(L, "ddm_tree_check", i32, vp)
+    _sig(L, "ddm_tree_update", i32, vp, vp, vp, vp, u32, vp, P(i32))
     _sig(L, "ddm_tree_info", i32, vp, P(u32), P(u32), P(u32))
     _sig(L, "ddm_tree_export", i32, vp, u32, vp, vp, vp, vp)
     _sig(L, "ddm_tree_free", None, vp)

@@ -112,6 +112,8 @@ struct ddm_server_req {
   uint64_t K = 0, slots = 0;
   uint32_t overflowed = 0;
   char* host = nullptr;  // pinned result
+  uint64_t host_bytes = 0;
+  bool compact = false;
   uint64_t* dev = nullptr;
   bool tree_cached = false;
 };
@@ -183,6 +185,80 @@ void finish(ddm_server* S, ddm_server_req* q, int32_t st, const std::string& det
   S->cv_mem.notify_all();
   S->cv_work.notify_all();
   S->cv_done.notify_all();
+}
+
+// compact form of K sorted keys of m updates: the subscription ids and the
+// offsets of every update's pairs
+__global__ void compact_ids_kernel(const uint64_t* __restrict__ keys, uint64_t K,
+                                   uint32_t* __restrict__ ids) {
+  const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < K) ids[i] = (uint32_t)keys[i];
+}
+
+__global__ void compact_offsets_kernel(const uint64_t* __restrict__ keys, uint64_t K, uint32_t m,
+                                       uint64_t* __restrict__ off) {
+  const uint32_t j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j > m) return;
+  const uint64_t x = (uint64_t)j << 32;
+  uint64_t lo = 0, hi = K;  // first key >= x
+  while (lo < hi) {
+    const uint64_t mid = (lo + hi) >> 1;
+    if (keys[mid] < x) lo = mid + 1;
+    else hi = mid;
+  }
+  off[j] = lo;
+}
+
+uint64_t host_result_bytes(bool compact, uint64_t K, uint32_t m) {
+  if (!compact) return 8 * std::max<uint64_t>(K, 1);
+  return ((4 * K + 7) & ~uint64_t(7)) + 8 * ((uint64_t)m + 1);
+}
+
+// Copies the K keys at `keys` (device, ordered on s) of request q into a
+// slot of the pinned pool, as keys or in compact form; waits for the copy.
+ddm_status deliver_host(ddm_server* S, ddm_server_req* q, const uint64_t* keys, uint64_t K,
+                        hipStream_t s, std::string* why) {
+  const bool compact = S->o.compact != 0;
+  const uint64_t bytes = host_result_bytes(compact, K, q->r.m);
+  char* host = nullptr;
+  {
+    std::unique_lock<std::mutex> lk(S->mu);
+    if (bytes <= S->pool.size)
+      S->cv_mem.wait(lk, [&] { return S->stop || (host = S->pool.alloc(bytes)) != nullptr; });
+  }
+  if (!host) {
+    *why = bytes > S->pool.size ? "result larger than the pinned host pool" : "server stopped";
+    return bytes > S->pool.size ? DDM_E_CAPACITY : DDM_E_INVALID_ARG;
+  }
+  q->host = host;
+  q->host_bytes = bytes;
+  q->compact = compact;
+  hipError_t e = hipSuccess;
+  char* tmp = nullptr;
+  if (!compact) {
+    if (K) e = hipMemcpyAsync(host, keys, 8 * K, hipMemcpyDeviceToHost, s);
+  } else {
+    tmp = dev_alloc(bytes, s);
+    if (!tmp) {
+      *why = "device allocation of a compact result failed";
+      return DDM_E_NOMEM;
+    }
+    const uint64_t ids_bytes = (4 * K + 7) & ~uint64_t(7);
+    if (K) {
+      compact_ids_kernel<<<(unsigned)((K + 255) / 256), 256, 0, s>>>(keys, K, (uint32_t*)tmp);
+      e = hipGetLastError();
+    }
+    if (e == hipSuccess) {
+      compact_offsets_kernel<<<(q->r.m + 1 + 255) / 256, 256, 0, s>>>(keys, K, q->r.m,
+                                                                        (uint64_t*)(tmp + ids_bytes));
+      e = hipGetLastError();
+    }
+    if (e == hipSuccess) e = hipMemcpyAsync(host, tmp, bytes, hipMemcpyDeviceToHost, s);
+  }
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (tmp) dev_free(tmp, s);
+  if (e != hipSuccess) return hip_fail(e, "result copy", __FILE__, __LINE__);
+  return DDM_OK;
 }
 
 ddm_status process(ddm_server* S, ddm_server_req* q, hipStream_t s, std::string* why) {
@@ -314,30 +390,14 @@ ddm_status process(ddm_server* S, ddm_server_req* q, hipStream_t s, std::string*
     uncharge(S, q, 8 * slots);
     return DDM_OK;
   }
-  char* host = nullptr;
-  {
-    std::unique_lock<std::mutex> lk(S->mu);
-    if (out_bytes <= S->pool.size)
-      S->cv_mem.wait(lk, [&] { return S->stop || (host = S->pool.alloc(out_bytes)) != nullptr; });
-  }
-  if (!host) {
-    drop_tree();
-    dev_free((char*)out, s);
-    *why = out_bytes > S->pool.size ? "result larger than the pinned host pool"
-                                    : "server stopped";
-    return out_bytes > S->pool.size ? DDM_E_CAPACITY : DDM_E_INVALID_ARG;
-  }
-  q->host = host;
-  hipError_t e = hipMemcpyAsync(host, out, 8 * K, hipMemcpyDeviceToHost, s);
-  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  st = deliver_host(S, q, out, K, s, why);
   drop_tree();
   dev_free((char*)out, s);
   {
     std::lock_guard<std::mutex> lk(S->mu);
     uncharge(S, q, 8 * slots + out_bytes);
   }
-  if (e != hipSuccess) return hip_fail(e, "result copy", __FILE__, __LINE__);
-  return DDM_OK;
+  return st;
 }
 
 bool batchable(const ddm_server* S, const ddm_request& r) {
@@ -399,26 +459,10 @@ void process_batch(ddm_server* S, const std::vector<ddm_server_req*>& G, hipStre
   }
   r = ddm_batch_fill(b, out, total, s);
   if (r == DDM_OK && !S->o.deliver_device) {
-    for (uint32_t i = 0; i < count && r == DDM_OK; ++i) {
+    for (uint32_t i = 0; i < count; ++i) {
       ddm_server_req* q = G[i];
       q->K = ranges[i + 1] - ranges[i];
-      const uint64_t bytes = 8 * std::max<uint64_t>(q->K, 1);
-      char* host = nullptr;
-      {
-        std::unique_lock<std::mutex> lk(S->mu);
-        if (bytes <= S->pool.size)
-          S->cv_mem.wait(lk, [&] { return S->stop || (host = S->pool.alloc(bytes)) != nullptr; });
-      }
-      if (!host) {
-        (*st)[i] = bytes > S->pool.size ? DDM_E_CAPACITY : DDM_E_INVALID_ARG;
-        (*why)[i] = "no room in the pinned host pool";
-        continue;
-      }
-      q->host = host;
-      if (q->K && hipMemcpyAsync(host, out + ranges[i], 8 * q->K, hipMemcpyDeviceToHost, s) !=
-                      hipSuccess) {
-        r = hip_fail(hipGetLastError(), "result copy", __FILE__, __LINE__);
-      }
+      (*st)[i] = deliver_host(S, q, out + ranges[i], q->K, s, &(*why)[i]);
     }
   } else if (r == DDM_OK) {
     // device delivery: every request gets its own copy of its range
@@ -538,7 +582,7 @@ extern "C" ddm_status ddm_server_create(const ddm_server_opts* opts, ddm_predict
   *out = nullptr;
   ddm_server_opts o{};
   if (opts) o = *opts;
-  for (int i = 0; i < 2; ++i)
+  for (int i = 0; i < 1; ++i)
     if (o.reserved[i]) {
       set_detail("ddm_server_opts: reserved fields must be zero");
       return DDM_E_INVALID_ARG;
@@ -546,7 +590,7 @@ extern "C" ddm_status ddm_server_create(const ddm_server_opts* opts, ddm_predict
   if (o.hbm_budget == 0) o.hbm_budget = 64ull << 30;
   if (o.host_pool == 0 && !o.deliver_device) o.host_pool = 4ull << 30;
   if (o.workers == 0) o.workers = 8;
-  if (o.batch_max == 0) o.batch_max = 64;
+  if (o.batch_max == 0) o.batch_max = 1;
   if (o.batch_small == 0) o.batch_small = 1u << 18;
   if (o.batch_max > DDM_BATCH_MAX_INSTANCES) {
     set_detail("ddm_server_opts: batch_max above DDM_BATCH_MAX_INSTANCES");
@@ -636,7 +680,13 @@ extern "C" ddm_status ddm_server_result(ddm_server* S, uint64_t ticket, ddm_resu
   res->status = q->status;
   if (q->status == 1) return DDM_OK;
   res->count = q->K;
-  res->pairs = q->host ? (const uint64_t*)q->host : q->dev;
+  res->m = q->r.m;
+  if (q->compact) {
+    res->sub_ids = (const uint32_t*)q->host;
+    res->upd_offsets = (const uint64_t*)(q->host + ((4 * q->K + 7) & ~uint64_t(7)));
+  } else {
+    res->pairs = q->host ? (const uint64_t*)q->host : q->dev;
+  }
   res->on_device = q->dev ? 1u : 0u;
   res->t_arrival_ns = q->t_arrival;
   res->t_start_ns = q->t_start;
@@ -660,7 +710,7 @@ extern "C" ddm_status ddm_server_release(ddm_server* S, uint64_t ticket) {
     }
     q = it->second;
     S->reqs.erase(it);
-    if (q->host) S->pool.release(q->host, 8 * std::max<uint64_t>(q->K, 1));
+    if (q->host) S->pool.release(q->host, q->host_bytes);
     if (q->dev) {
       S->used -= std::min(S->used, 8 * std::max<uint64_t>(q->K, 1));
       dev_free((char*)q->dev, nullptr);

@@ -118,6 +118,11 @@ __global__ __launch_bounds__(kTreeThreads) void tree_low_kernel(TreeJobs J) {
   tree_low_chunk(J.j[blockIdx.y], blockIdx.x);
 }
 
+// the same pass over records already in place (extents moved)
+__global__ __launch_bounds__(kTreeThreads) void tree_refit_kernel(TreeJobs J) {
+  tree_low_chunk<false>(J.j[blockIdx.y], blockIdx.x);
+}
+
 __global__ __launch_bounds__(kTreeThreads) void tree_high_kernel(TreeJobs J, uint32_t S) {
   tree_high_chunk(J.j[blockIdx.y], blockIdx.x, S);
 }
@@ -140,6 +145,60 @@ size_t tree_bytes_estimate(uint32_t n, uint32_t d) {
   return rec_b * d + mx_b * d + id_b + 2 * key_b + bm_b * d + 2 * si_b + qu_b + 256 + 256 +
          al(sizeof(float) * 4 * DDM_MAX_D) + al(sizeof(uint32_t) * DDM_MAX_D * 2 * (kFeatBins + 1)) +
          al(sizeof(uint32_t) * kSatWords);
+}
+
+static TreeJobs make_jobs(const ddm_tree* t, const float* lo, const float* hi) {
+  const bool sort_hi = t->d == 1;
+  TreeJobs J{};
+  for (uint32_t k = 0; k < t->d; ++k) {
+    TreeJob& j = J.j[k];
+    j.s_lo = lo;
+    j.s_hi = hi;
+    j.rec = t->rec[k];
+    j.maxhi = t->maxhi[k];
+    j.bmax = t->bmax[k];
+    j.id = t->id[k];
+    j.skey_lo = t->skey_lo[k];
+    j.skey_hi = sort_hi ? t->skey_hi[k] : nullptr;
+    j.sidx_lo = t->sidx_lo[k];
+    j.sidx_hi = sort_hi ? t->sidx_hi[k] : nullptr;
+    j.quant = t->quant[k];
+    j.maxlen_bits = (uint32_t*)t->maxlen + k;
+    j.n = t->n;
+    j.d = t->d;
+    j.k = k;
+    j.P = t->P;
+    j.C = t->C;
+    j.H = t->H;
+    j.ns = t->ns;
+  }
+  return J;
+}
+
+// samples/quantiles of the sorted keys, then maxupper and block maxima; the
+// records are gathered from the inputs (gather) or already in place
+static ddm_status enqueue_tree_passes(const ddm_tree* t, const TreeJobs& J, bool gather,
+                                      hipStream_t s) {
+  const uint32_t d = t->d;
+  {
+    dim3 g((std::max(t->ns, kQuant) + 255) / 256, d);
+    build_index_kernel<<<g, 256, 0, s>>>(J);
+    DDM_LAUNCHED("build_index_kernel");
+  }
+  ProfScope ps("tree_build", s);
+  dim3 g((t->P + 1 + kChunk - 1) / kChunk, d);
+  if (gather)
+    tree_low_kernel<<<g, kTreeThreads, 0, s>>>(J);
+  else
+    tree_refit_kernel<<<g, kTreeThreads, 0, s>>>(J);
+  DDM_LAUNCHED("tree_low_kernel");
+  for (uint32_t S = kChunkLog; S < t->H; S += kChunkLog) {
+    const uint32_t q_end = (t->P >> S) + 1;
+    dim3 g2((q_end + kChunk - 1) / kChunk, d);
+    tree_high_kernel<<<g2, kTreeThreads, 0, s>>>(J, S);
+    DDM_LAUNCHED("tree_high_kernel");
+  }
+  return DDM_OK;
 }
 
 ddm_status enqueue_tree_build(ddm_tree* t, const float* lo, const float* hi, hipStream_t s) {
@@ -199,47 +258,218 @@ ddm_status enqueue_tree_build(ddm_tree* t, const float* lo, const float* hi, hip
   if (st != DDM_OK) return st;
   st = radix_sort_batch(arrs, narr, tile_map, ntiles, hist, 0, 4, s);
   if (st != DDM_OK) return st;
-  TreeJobs J{};
+  return enqueue_tree_passes(t, make_jobs(t, lo, hi), true, s);
+}
+
+// ---------------------------------------------------------------------------
+// Moving subscriptions of a resident tree (dynamic DDM: extents move between
+// matches, Sec. I and Sec. VI).  If the moved lower bounds keep every tree's
+// (lower bound, id) order, the records are rewritten in place and maxupper,
+// block maxima, samples and quantiles are recomputed over the records
+// (refit, no sort); otherwise the subscription set is read back from the
+// records, the moves applied, and the tree rebuilt.
+// ---------------------------------------------------------------------------
+struct TreePtrs {
+  float* rec[DDM_MAX_D];
+  const uint32_t* id[DDM_MAX_D];
+  uint32_t* pos[DDM_MAX_D];  // position of every subscription in tree k
+  uint32_t* key[DDM_MAX_D];  // sorted lower keys with the moves applied
+  uint32_t n, d;
+};
+
+__global__ void upd_pos_kernel(TreePtrs A) {
+  const uint32_t k = blockIdx.y;
+  const uint32_t p = 1 + blockIdx.x * blockDim.x + threadIdx.x;
+  if (p <= A.n) A.pos[k][A.id[k][p]] = p;
+}
+
+// ids in range and new extents valid (flag bit 2)
+__global__ void upd_check_kernel(const uint32_t* __restrict__ ids, const float* __restrict__ lo,
+                                 const float* __restrict__ hi, uint32_t count, uint32_t n,
+                                 uint32_t d, int32_t* __restrict__ flag) {
+  const uint32_t c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= count) return;
+  bool bad = ids[c] >= n;
+  for (uint32_t k = 0; k < d; ++k)
+    bad = bad || !valid_extent(lo[(size_t)k * count + c], hi[(size_t)k * count + c]);
+  if (bad) atomicOr(flag, 4);
+}
+
+__global__ void upd_keys_kernel(TreePtrs A, const uint32_t* __restrict__ ids,
+                                const float* __restrict__ lo, uint32_t count) {
+  const uint32_t k = blockIdx.y;
+  const uint32_t c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= count) return;
+  const uint32_t i = ids[c];
+  if (i >= A.n) return;
+  A.key[k][A.pos[k][i] - 1] = f2key(lo[(size_t)k * count + c]);
+}
+
+// (key, id) strictly increasing along every tree after the moves? (bit 3)
+__global__ void upd_order_kernel(TreePtrs A, int32_t* __restrict__ flag) {
+  const uint32_t k = blockIdx.y;
+  const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i + 1 >= A.n) return;
+  const uint32_t a = A.key[k][i], b = A.key[k][i + 1];
+  if (a > b || (a == b && A.id[k][i + 1] > A.id[k][i + 2])) atomicOr(flag, 8);
+}
+
+// the moved extents into their record of every tree
+__global__ void upd_apply_kernel(TreePtrs A, const uint32_t* __restrict__ ids,
+                                 const float* __restrict__ lo, const float* __restrict__ hi,
+                                 uint32_t count) {
+  const uint32_t k = blockIdx.y;
+  const uint32_t c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= count) return;
+  const uint32_t D = A.d;
+  float* r = A.rec[k] + (size_t)A.pos[k][ids[c]] * 2 * D;
+  r[0] = lo[(size_t)k * count + c];
+  r[1] = hi[(size_t)k * count + c];
+  uint32_t slot = 1;
+  for (uint32_t kk = 0; kk < D; ++kk) {
+    if (kk == k) continue;
+    r[2 * slot] = lo[(size_t)kk * count + c];
+    r[2 * slot + 1] = hi[(size_t)kk * count + c];
+    ++slot;
+  }
+}
+
+__global__ void upd_zero_maxlen_kernel(uint32_t* __restrict__ maxlen_bits, uint32_t d) {
+  if (threadIdx.x < d) maxlen_bits[threadIdx.x] = 0;
+}
+
+// d = 1: upper keys of the records, to be sorted again
+__global__ void upd_hi_keys_kernel(const float* __restrict__ rec, uint32_t n,
+                                   uint32_t* __restrict__ khi) {
+  const uint32_t p = 1 + blockIdx.x * blockDim.x + threadIdx.x;
+  if (p <= n) khi[p - 1] = f2key(rec[(size_t)p * 2 + 1]);
+}
+
+// the subscription set back from tree 0's records (slot s holds dimension s)
+__global__ void upd_gather_kernel(const float* __restrict__ rec, const uint32_t* __restrict__ id,
+                                  uint32_t n, uint32_t d, float* __restrict__ lo,
+                                  float* __restrict__ hi) {
+  const uint32_t p = 1 + blockIdx.x * blockDim.x + threadIdx.x;
+  if (p > n) return;
+  const uint32_t i = id[p];
+  const float* r = rec + (size_t)p * 2 * d;
   for (uint32_t k = 0; k < d; ++k) {
-    TreeJob& j = J.j[k];
-    j.s_lo = lo;
-    j.s_hi = hi;
-    j.rec = t->rec[k];
-    j.maxhi = t->maxhi[k];
-    j.bmax = t->bmax[k];
-    j.id = t->id[k];
-    j.skey_lo = t->skey_lo[k];
-    j.skey_hi = sort_hi ? t->skey_hi[k] : nullptr;
-    j.sidx_lo = t->sidx_lo[k];
-    j.sidx_hi = sort_hi ? t->sidx_hi[k] : nullptr;
-    j.quant = t->quant[k];
-    j.maxlen_bits = (uint32_t*)t->maxlen + k;
-    j.n = n;
-    j.d = d;
-    j.k = k;
-    j.P = t->P;
-    j.C = t->C;
-    j.H = t->H;
-    j.ns = t->ns;
+    lo[(size_t)k * n + i] = r[2 * k];
+    hi[(size_t)k * n + i] = r[2 * k + 1];
+  }
+}
+
+__global__ void upd_scatter_kernel(const uint32_t* __restrict__ ids,
+                                   const float* __restrict__ nlo, const float* __restrict__ nhi,
+                                   uint32_t count, uint32_t n, uint32_t d,
+                                   float* __restrict__ lo, float* __restrict__ hi) {
+  const uint32_t c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= count) return;
+  const uint32_t i = ids[c];
+  for (uint32_t k = 0; k < d; ++k) {
+    lo[(size_t)k * n + i] = nlo[(size_t)k * count + c];
+    hi[(size_t)k * n + i] = nhi[(size_t)k * count + c];
+  }
+}
+
+static ddm_status tree_update(ddm_tree* t, const uint32_t* ids, const float* nlo,
+                              const float* nhi, uint32_t count, hipStream_t s, int* rebuilt) {
+  const uint32_t n = t->n, d = t->d;
+  Scratch sc(s);
+  sc.reserve(sizeof(uint32_t) * (size_t)n * d);  // positions
+  sc.reserve(sizeof(uint32_t) * (size_t)n * d);  // keys with the moves
+  sc.reserve(sizeof(int32_t));                   // flag
+  if (!sc.commit()) return DDM_E_NOMEM;
+  uint32_t* pos = sc.take<uint32_t>((size_t)n * d);
+  uint32_t* keys = sc.take<uint32_t>((size_t)n * d);
+  int32_t* flag = sc.take<int32_t>(1);
+  if (!sc.fits()) return scratch_overrun("tree update");
+  TreePtrs A{};
+  for (uint32_t k = 0; k < d; ++k) {
+    A.rec[k] = t->rec[k];
+    A.id[k] = t->id[k];
+    A.pos[k] = pos + (size_t)k * n;
+    A.key[k] = keys + (size_t)k * n;
+    DDM_HIP(hipMemcpyAsync(A.key[k], t->skey_lo[k], sizeof(uint32_t) * n,
+                           hipMemcpyDeviceToDevice, s));
+  }
+  A.n = n;
+  A.d = d;
+  tree_init_kernel<<<1, 64, 0, s>>>(flag, nullptr, 0);
+  DDM_LAUNCHED("tree_init_kernel");
+  upd_pos_kernel<<<dim3((n + 255) / 256, d), 256, 0, s>>>(A);
+  DDM_LAUNCHED("upd_pos_kernel");
+  upd_check_kernel<<<(count + 255) / 256, 256, 0, s>>>(ids, nlo, nhi, count, n, d, flag);
+  DDM_LAUNCHED("upd_check_kernel");
+  upd_keys_kernel<<<dim3((count + 255) / 256, d), 256, 0, s>>>(A, ids, nlo, count);
+  DDM_LAUNCHED("upd_keys_kernel");
+  upd_order_kernel<<<dim3((n + 255) / 256, d), 256, 0, s>>>(A, flag);
+  DDM_LAUNCHED("upd_order_kernel");
+  int32_t f = 0;
+  DDM_HIP(hipMemcpyAsync(&f, flag, sizeof(f), hipMemcpyDeviceToHost, s));
+  DDM_HIP(hipStreamSynchronize(s));
+  if (f & 4) {
+    set_detail("ddm_tree_update: id out of range, or NaN/inf or lo > hi in the new extents");
+    return DDM_E_INVALID_INPUT;
   }
   {
-    dim3 g((std::max(t->ns, kQuant) + 255) / 256, d);
-    build_index_kernel<<<g, 256, 0, s>>>(J);
-    DDM_LAUNCHED("build_index_kernel");
+    // learned-sizing statistics describe the old set
+    std::lock_guard<std::mutex> lk(t->fmu);
+    t->fstats_ready = false;
   }
-  {
-    ProfScope ps("tree_build", s);
-    dim3 g((t->P + 1 + kChunk - 1) / kChunk, d);
-    tree_low_kernel<<<g, kTreeThreads, 0, s>>>(J);
-    DDM_LAUNCHED("tree_low_kernel");
-    for (uint32_t S = kChunkLog; S < t->H; S += kChunkLog) {
-      const uint32_t q_end = (t->P >> S) + 1;
-      dim3 g2((q_end + kChunk - 1) / kChunk, d);
-      tree_high_kernel<<<g2, kTreeThreads, 0, s>>>(J, S);
-      DDM_LAUNCHED("tree_high_kernel");
+  if (!(f & 8)) {
+    *rebuilt = 0;
+    upd_apply_kernel<<<dim3((count + 255) / 256, d), 256, 0, s>>>(A, ids, nlo, nhi, count);
+    DDM_LAUNCHED("upd_apply_kernel");
+    for (uint32_t k = 0; k < d; ++k)
+      DDM_HIP(hipMemcpyAsync(t->skey_lo[k], A.key[k], sizeof(uint32_t) * n,
+                             hipMemcpyDeviceToDevice, s));
+    upd_zero_maxlen_kernel<<<1, 64, 0, s>>>((uint32_t*)t->maxlen, d);
+    DDM_LAUNCHED("upd_zero_maxlen_kernel");
+    if (d == 1) {
+      // the upper keys stay a sorted multiset for the exact counts
+      const uint32_t tiles = (n + kSortTile - 1) / kSortTile;
+      Scratch ss(s);
+      ss.reserve(sizeof(uint32_t) * n);
+      ss.reserve(sizeof(SortArr));
+      ss.reserve(sizeof(uint32_t) * tiles);
+      ss.reserve(sizeof(uint32_t) * 256 * (size_t)tiles);
+      if (!ss.commit()) return DDM_E_NOMEM;
+      uint32_t* ktmp = ss.take<uint32_t>(n);
+      SortArr* arr = ss.take<SortArr>(1);
+      uint32_t* tile_map = ss.take<uint32_t>(tiles);
+      uint32_t* hist = ss.take<uint32_t>(256 * (size_t)tiles);
+      if (!ss.fits()) return scratch_overrun("tree update");
+      upd_hi_keys_kernel<<<(n + 255) / 256, 256, 0, s>>>(t->rec[0], n, t->skey_hi[0]);
+      DDM_LAUNCHED("upd_hi_keys_kernel");
+      SortArr h{};
+      h.k[0] = t->skey_hi[0];
+      h.k[1] = ktmp;
+      h.n = n;
+      h.tile0 = 0;
+      ddm_status st = sort_setup_small(&h, 1, arr, tile_map, tiles, s);
+      if (st != DDM_OK) return st;
+      st = radix_sort_batch(arr, 1, tile_map, tiles, hist, 0, 4, s);
+      if (st != DDM_OK) return st;
+      return enqueue_tree_passes(t, make_jobs(t, nullptr, nullptr), false, s);
     }
+    return enqueue_tree_passes(t, make_jobs(t, nullptr, nullptr), false, s);
   }
-  return DDM_OK;
+  *rebuilt = 1;
+  Scratch sr(s);
+  sr.reserve(sizeof(float) * (size_t)n * d);
+  sr.reserve(sizeof(float) * (size_t)n * d);
+  if (!sr.commit()) return DDM_E_NOMEM;
+  float* lo = sr.take<float>((size_t)n * d);
+  float* hi = sr.take<float>((size_t)n * d);
+  if (!sr.fits()) return scratch_overrun("tree update");
+  upd_gather_kernel<<<(n + 255) / 256, 256, 0, s>>>(t->rec[0], t->id[0], n, d, lo, hi);
+  DDM_LAUNCHED("upd_gather_kernel");
+  upd_scatter_kernel<<<(count + 255) / 256, 256, 0, s>>>(ids, nlo, nhi, count, n, d, lo, hi);
+  DDM_LAUNCHED("upd_scatter_kernel");
+  tree_init_kernel<<<1, 64, 0, s>>>(t->flag, (uint32_t*)t->maxlen, d);
+  DDM_LAUNCHED("tree_init_kernel");
+  return enqueue_tree_build(t, lo, hi, s);
 }
 
 // Enqueue the feature statistics on stream s the first time a learned match
@@ -387,6 +617,32 @@ extern "C" ddm_status ddm_build(const float* sub_lo, const float* sub_hi, uint32
   }
   *out_tree = t;
   return DDM_OK;
+}
+
+extern "C" ddm_status ddm_tree_update(ddm_tree* t, const uint32_t* ids, const float* new_lo,
+                                      const float* new_hi, uint32_t count, void* stream,
+                                      int* out_rebuilt) {
+  set_detail("");
+  if (!t || (count && (!ids || !new_lo || !new_hi))) {
+    set_detail("ddm_tree_update: NULL argument");
+    return DDM_E_INVALID_ARG;
+  }
+  if (out_rebuilt) *out_rebuilt = 0;
+  if (count == 0) return DDM_OK;
+  if (t->n == 0 || count > t->n) {
+    set_detail("ddm_tree_update: more moves than subscriptions");
+    return DDM_E_INVALID_ARG;
+  }
+  int cur = -1;
+  DDM_HIP(hipGetDevice(&cur));
+  if (cur != t->device) {
+    set_detail("ddm_tree_update: the current device is not the tree's device");
+    return DDM_E_INVALID_ARG;
+  }
+  int rb = 0;
+  ddm_status st = tree_update(t, ids, new_lo, new_hi, count, (hipStream_t)stream, &rb);
+  if (out_rebuilt) *out_rebuilt = rb;
+  return st;
 }
 
 extern "C" void ddm_tree_free(ddm_tree* t) {

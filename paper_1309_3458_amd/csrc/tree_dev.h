@@ -36,9 +36,11 @@ __device__ __forceinline__ void tree_index_item(const TreeJob& J, uint32_t c) {
   if (c < kQuant) J.quant[c] = J.skey_lo[(uint32_t)(((uint64_t)c * J.n) / kQuant)];
 }
 
-// Pass 0 on chunk c (2048 consecutive positions): gather the records and
-// compute maxhi for heights 0..10 in LDS, the block maxima (height 5 plus
-// the position above) and the length bound.
+// Pass 0 on chunk c (2048 consecutive positions): gather the records (or,
+// with GATHER false, read the records already in place, after extents have
+// moved) and compute maxhi for heights 0..10 in LDS, the block maxima
+// (height 5 plus the position above) and the length bound.
+template <bool GATHER = true>
 __device__ __forceinline__ void tree_low_chunk(const TreeJob& J, uint32_t c) {
   __shared__ float mx[kChunk];
   __shared__ uint32_t wlen[kTreeThreads / kWave];
@@ -54,20 +56,26 @@ __device__ __forceinline__ void tree_low_chunk(const TreeJob& J, uint32_t c) {
     const uint32_t p = c * kChunk + r;
     float h = -INFINITY;
     if (p >= 1 && p <= J.n) {
-      const uint32_t i = ids[p];
       float* dst = rec + (size_t)p * 2 * D;
-      const float l0 = J.s_lo[(size_t)k * J.n + i];
-      dst[0] = l0;
-      h = J.s_hi[(size_t)k * J.n + i];
-      dst[1] = h;
-      if (valid_extent(l0, h)) lenb = max(lenb, __float_as_uint(nextafterf(h - l0, INFINITY)));
-      uint32_t slot = 1;
-      for (uint32_t kk = 0; kk < D; ++kk) {
-        if (kk == k) continue;
-        dst[2 * slot] = J.s_lo[(size_t)kk * J.n + i];
-        dst[2 * slot + 1] = J.s_hi[(size_t)kk * J.n + i];
-        ++slot;
+      float l0;
+      if (GATHER) {
+        const uint32_t i = ids[p];
+        l0 = J.s_lo[(size_t)k * J.n + i];
+        dst[0] = l0;
+        h = J.s_hi[(size_t)k * J.n + i];
+        dst[1] = h;
+        uint32_t slot = 1;
+        for (uint32_t kk = 0; kk < D; ++kk) {
+          if (kk == k) continue;
+          dst[2 * slot] = J.s_lo[(size_t)kk * J.n + i];
+          dst[2 * slot + 1] = J.s_hi[(size_t)kk * J.n + i];
+          ++slot;
+        }
+      } else {
+        l0 = dst[0];
+        h = dst[1];
       }
+      if (valid_extent(l0, h)) lenb = max(lenb, __float_as_uint(nextafterf(h - l0, INFINITY)));
     }
     mx[r] = h;
   }

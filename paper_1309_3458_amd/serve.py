@@ -25,7 +25,7 @@ def percentile(x, q):
 
 def run(server, schedule, sample_every: int = 100, lead_s: float = 0.5, log=None,
         sample_max_pairs: int = 20_000_000, sample_bytes: int = 4 << 30,
-        lookahead_s: float = 0.25):
+        lookahead_s: float = 1.0):
     """Serve `schedule` (a list of workloads.Request) on `server`.
 
     Three threads: the generator draws each request's coordinates in device

@@ -66,13 +66,16 @@ def _alone(inst):
     return k
 
 
-@pytest.mark.parametrize("workers,batch_max", [(1, 1), (8, 1), (1, 0), (8, 0), (3, 5)])
-def test_burst_equals_alone_and_oracle(workers, batch_max):
-    """batch_max 1: every request alone; 0: small requests queued together
-    are matched as one batch (default 64); 5: small batches."""
+@pytest.mark.parametrize("workers,batch_max,compact", [(1, 1, False), (8, 1, False),
+                                                     (1, 64, False), (8, 64, False),
+                                                     (3, 5, True), (8, 1, True)])
+def test_burst_equals_alone_and_oracle(workers, batch_max, compact):
+    """batch_max 1: every request alone; 64 / 5: small requests queued
+    together are matched as one batch; compact: results as subscription ids
+    plus update offsets (rebuilt into keys by the binding)."""
     import paper_1309_3458_amd as P
     insts = _mixed(60 + workers, 40)
-    srv = P.Server(workers=workers, host_pool=1 << 30, batch_max=batch_max)
+    srv = P.Server(workers=workers, host_pool=1 << 30, batch_max=batch_max, compact=compact)
     res = _serve_all(srv, insts)
     for i, (inst, r) in enumerate(zip(insts, res)):
         assert r["status"] == 0, r
@@ -153,7 +156,7 @@ def test_invalid_request_fails_alone():
     srv.close()
 
 
-@pytest.mark.parametrize("batch_max", [1, 0])
+@pytest.mark.parametrize("batch_max", [1, 64])
 def test_device_delivery(batch_max):
     import paper_1309_3458_amd as P
     insts = _mixed(93, 8)
