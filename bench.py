@@ -438,6 +438,7 @@ def bench_serve(args):
         "regions_per_s": st["regions_per_s"],
         "ms_per_step": round(st["span_s"] * 1e3, 3),
         "latency_ms": st["latency_ms"],
+        "latency_from_submit_ms": st["latency_from_submit_ms"],
         "queue_wait_ms": st["queue_wait_ms"],
         "service_ms": st["service_ms"],
         "client_late_ms": st["client_late_ms"],

@@ -527,7 +527,15 @@ class Server:
         n = lib().ddm_server_wait_any(self.handle, int(timeout_ms), buf, max_tickets)
         return [int(buf[i]) for i in range(n)]
 
-    def result(self, ticket: int, copy: bool = True) -> dict:
+    @staticmethod
+    def keys_from_compact(sub_ids, upd_offsets):
+        """The 64-bit keys of a compact result."""
+        import numpy as np
+        m = len(upd_offsets) - 1
+        upd = np.repeat(np.arange(m, dtype=np.uint64), np.diff(upd_offsets).astype(np.int64))
+        return (upd << np.uint64(32)) | sub_ids.astype(np.uint64)
+
+    def result(self, ticket: int, copy: bool = True, keys: bool = True) -> dict:
         import numpy as np
         from ._native import Result
         r = Result()
@@ -540,14 +548,16 @@ class Server:
             d["detail"] = lib().ddm_last_error_detail().decode()
         if copy and r.status == 0:
             if r.sub_ids is not None or r.upd_offsets is not None:
-                # compact form -> the same keys
+                # compact form (copied); keys=True rebuilds the same keys
                 K, m = int(r.count), int(r.m)
                 ids = np.frombuffer((ctypes.c_uint32 * K).from_address(int(r.sub_ids)),
-                                    dtype=np.uint32) if K else np.zeros(0, np.uint32)
+                                    dtype=np.uint32).copy() if K else np.zeros(0, np.uint32)
                 off = np.frombuffer((ctypes.c_uint64 * (m + 1)).from_address(int(r.upd_offsets)),
-                                    dtype=np.uint64)
-                upd = np.repeat(np.arange(m, dtype=np.uint64), np.diff(off).astype(np.int64))
-                d["pairs"] = (upd << np.uint64(32)) | ids.astype(np.uint64)
+                                    dtype=np.uint64).copy()
+                if keys:
+                    d["pairs"] = Server.keys_from_compact(ids, off)
+                else:
+                    d["sub_ids"], d["upd_offsets"] = ids, off
             elif r.count == 0:
                 d["pairs"] = np.zeros(0, dtype=np.uint64)
             elif r.on_device:

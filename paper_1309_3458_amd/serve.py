@@ -33,7 +33,9 @@ def run(server, schedule, sample_every: int = 100, lead_s: float = 0.5, log=None
     would have ready when it sends the request); the submitter hands each
     request to the server at its scheduled arrival time; the drain thread
     collects completions.  Latency runs from the scheduled arrival to the
-    result in host memory.  Returns a dict of statistics plus `samples`:
+    result in host memory (and, separately, from the moment the request was
+    handed to the server, which excludes any lag of the client's own
+    generation on the shared GPU).  Returns a dict of statistics plus `samples`:
     {request index: keys (uint64)} for every sample_every-th request (up to
     sample_max_pairs pairs each and sample_bytes in all), for identity
     checks after the run.
@@ -46,7 +48,8 @@ def run(server, schedule, sample_every: int = 100, lead_s: float = 0.5, log=None
     ready = collections.deque()
     cv = threading.Condition()
     ticket_of = {}
-    lat, wait, service, K, regions, late = [], [], [], [], [], []
+    lat, lat_sub, wait, service, K, regions, late = [], [], [], [], [], [], []
+    submit_ns = {}
     samples = {}
     kept = [0]
     errors = []
@@ -78,9 +81,11 @@ def run(server, schedule, sample_every: int = 100, lead_s: float = 0.5, log=None
             dt = (target - time.monotonic_ns()) / 1e9
             if dt > 0:
                 time.sleep(dt)
-            late.append(max(0, time.monotonic_ns() - target) / 1e6)
             ev.synchronize()
+            now = time.monotonic_ns()
+            late.append(max(0, now - target) / 1e6)
             t = server.submit(*tens, arrival_ns=target, stream=sub_stream)
+            submit_ns[i] = now
             ticket_of[t] = i
 
     def drain():
@@ -93,18 +98,21 @@ def run(server, schedule, sample_every: int = 100, lead_s: float = 0.5, log=None
                 r = server.result(t, copy=False)
                 if (i % sample_every == 0 and r["status"] == 0 and r["count"] <= sample_max_pairs
                         and kept[0] + 8 * r["count"] <= sample_bytes):
-                    r = server.result(t, copy=True)
+                    r = server.result(t, copy=True, keys=False)
                     kept[0] += 8 * r["count"]
                 if r["status"] != 0:
                     errors.append((i, r["status"], r.get("detail", "")))
                 else:
                     lat.append((r["t_done_ns"] - r["t_arrival_ns"]) / 1e6)
+                    lat_sub.append((r["t_done_ns"] - submit_ns.get(i, r["t_arrival_ns"])) / 1e6)
                     wait.append((r["t_start_ns"] - r["t_arrival_ns"]) / 1e6)
                     service.append((r["t_done_ns"] - r["t_start_ns"]) / 1e6)
                     K.append(r["count"])
                     regions.append(schedule[i].spec.N)
                     if "pairs" in r:
                         samples[i] = r["pairs"]
+                    elif "sub_ids" in r:
+                        samples[i] = (r["sub_ids"], r["upd_offsets"])
                 server.release(t)
                 got += 1
                 if log and got % 5000 == 0:
@@ -128,7 +136,8 @@ def run(server, schedule, sample_every: int = 100, lead_s: float = 0.5, log=None
     return {
         "requests": n_req, "completed": len(lat), "errors": errors[:10],
         "n_errors": len(errors),
-        "latency_ms": pct(lat), "queue_wait_ms": pct(wait), "service_ms": pct(service),
+        "latency_ms": pct(lat), "latency_from_submit_ms": pct(lat_sub),
+        "queue_wait_ms": pct(wait), "service_ms": pct(service),
         "client_late_ms": {"p99": round(percentile(late, 99), 3),
                            "max": round(max(late) if late else math.nan, 3)},
         "pairs": int(sum(K)), "regions": int(sum(regions)), "span_s": round(span_s, 3),
@@ -147,6 +156,9 @@ def check_samples(samples, schedule, max_oracle_pairs: int = 2_000_000, log=None
     import paper_1309_3458_amd as P
     alone_ok, oracle_ok = 0, 0
     for i, got in sorted(samples.items()):
+        if isinstance(got, tuple):  # compact result
+            got = P.Server.keys_from_compact(*got)
+            samples[i] = got
         s_lo, s_hi, u_lo, u_hi = W.device_instance(schedule[i].spec)
         t = P.build(s_lo, s_hi)
         want = P.match(t, u_lo, u_hi).cpu().numpy().view(np.uint64)
