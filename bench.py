@@ -110,9 +110,10 @@ def candidates(inst):
 
 
 # Calibrated FETCH_SIZE + WRITE_SIZE of the fill traversal at the default
-# workload (profiles/traffic_d2_N1e6_alpha1_pmc.md), bytes per launch; valid
-# for this version of the tile traversal only.
-TRAFFIC_BYTES = {("d2_N1e6_alpha1_uniform", "plain", "traverse_tile_fill"): 274101.5 * 1024}
+# workload, bytes per launch, keyed (workload, path, kernel); valid for the
+# version of the tile traversal the counters were taken on
+# (profiles/traffic_d2_N1e6_alpha1_pmc.md), empty until they are retaken.
+TRAFFIC_BYTES = {}
 
 
 def roofline_alu(cand, ops, dom, dom_avg_ms, traffic=None):

@@ -61,6 +61,22 @@ int tree_device(const ddm_tree* t);
 constexpr uint32_t kBucketsPerDim = 8192;
 constexpr uint32_t kBuckets = kBucketsPerDim * DDM_MAX_D;
 
+// d > 1: the first half of a dimension's buckets are ranges of the position
+// in tree k*; an update whose candidate range is long (more than
+// kCellRange positions, where testing the tile's candidates against its
+// updates dominates) goes instead to the second half: cells of
+// kProbeBins(D) position ranges times kCellBins(D) ranges (equal numbers of
+// lower bounds, from the quantiles) of each other dimension, so that the
+// updates of a tile are close in every dimension and the tile's enclosing
+// box filters most candidates before they are tested one by one.  With
+// short ranges scanning the range dominates and 1-D order keeps it short.
+constexpr uint32_t kLineBins = kBucketsPerDim / 2;
+constexpr uint32_t kCellRange = 4096;
+__host__ __device__ constexpr uint32_t kCellBins(int D) { return D == 2 ? 8 : D == 3 ? 4 : 2; }
+__host__ __device__ constexpr uint32_t kProbeBins(int D) {
+  return kLineBins / (D == 2 ? 8 : D == 3 ? 16 : 8);
+}
+
 __global__ __launch_bounds__(256) void bits1_kernel(TreeDev T, const float* __restrict__ ulo,
                                                     const float* __restrict__ uhi, uint32_t m,
                                                     uint32_t* __restrict__ cmin,
@@ -111,10 +127,12 @@ __global__ __launch_bounds__(1024) void probe_kernel(TreeDev T, const float* __r
   bool bad = false;
   if (act) {
     uint32_t best = 0xffffffffu, bk = 0, bqa = 0, bx = 0;
+    float mid[D];
 #pragma unroll
     for (int k = 0; k < D; ++k) {
       const float a = ulo[(size_t)k * m + j], b = uhi[(size_t)k * m + j];
       bad = bad || !valid_extent(a, b);
+      mid[k] = 0.5f * a + 0.5f * b;
       const uint32_t xh = f2key(b);
       const uint32_t qa = quant_count(sq[k], xh, true);
       const uint32_t qb = quant_count(sq[k], f2key(nextafterf(a - T.maxlen[k], -INFINITY)), false);
@@ -148,8 +166,20 @@ __global__ __launch_bounds__(1024) void probe_kernel(TreeDev T, const float* __r
       fine = 0.f;
     }
     kstar[j] = (uint8_t)bk;
-    const uint32_t sub = min((uint32_t)(fine * (float)(kBucketsPerDim / kQuant)),
-                             kBucketsPerDim - 1u);
+    constexpr uint32_t B0 = kProbeBins(D), B1 = kCellBins(D);
+    uint32_t sub;
+    if (!bad && (uint64_t)best * T.n > (uint64_t)kCellRange * kQuant) {
+      sub = min((uint32_t)(fine * (float)B0 / (float)kQuant), B0 - 1u);
+#pragma unroll
+      for (int k = 0; k < D; ++k) {
+        if ((uint32_t)k == bk) continue;
+        const uint32_t qp = quant_count(sq[k], f2key(mid[k]), true);
+        sub = sub * B1 + min(qp * B1 / (kQuant + 1u), B1 - 1u);
+      }
+      sub += kLineBins;
+    } else {
+      sub = min((uint32_t)(fine * (float)kLineBins / (float)kQuant), kLineBins - 1u);
+    }
     const uint32_t bu = bk * kBucketsPerDim + sub;
     bucket[j] = bu;
     rank[j] = atomicAdd(&bhist[bu], 1u);
@@ -205,6 +235,54 @@ __global__ __launch_bounds__(256) void bucket_scatter_kernel(const uint32_t* __r
                                                              uint32_t* __restrict__ perm) {
   const uint32_t j = blockIdx.x * blockDim.x + threadIdx.x;
   if (j < m) perm[bhist[bucket[j]] + rank[j]] = j;
+}
+
+// tiles of at most 64 updates per bucket: exclusive prefix of their numbers
+// (one workgroup; boff holds the buckets' exclusive offsets, the last
+// bucket ends at m)
+__global__ __launch_bounds__(1024) void tile_prefix_kernel(const uint32_t* __restrict__ boff,
+                                                           uint32_t m,
+                                                           uint32_t* __restrict__ tprefix) {
+  constexpr uint32_t per = kBuckets / 1024;
+  __shared__ uint32_t wsum[1024 / kWave];
+  const uint32_t tid = threadIdx.x, lane = lane_id(), wave = tid / kWave;
+  uint32_t tl[per];
+  uint32_t sum = 0;
+#pragma unroll
+  for (uint32_t i = 0; i < per; ++i) {
+    const uint32_t b = tid * per + i;
+    const uint32_t e = b + 1 < kBuckets ? boff[b + 1] : m;
+    tl[i] = (e - boff[b] + 63u) / 64u;
+    sum += tl[i];
+  }
+  uint32_t inc = sum;
+#pragma unroll
+  for (int o = 1; o < kWave; o <<= 1) {
+    const uint32_t t2 = __shfl_up(inc, o, kWave);
+    if (lane >= (uint32_t)o) inc += t2;
+  }
+  if (lane == kWave - 1) wsum[wave] = inc;
+  __syncthreads();
+  uint32_t run = 0, total = 0;
+  for (uint32_t w = 0; w < 1024 / kWave; ++w) {
+    if (w < wave) run += wsum[w];
+    total += wsum[w];
+  }
+  run += inc - sum;
+#pragma unroll
+  for (uint32_t i = 0; i < per; ++i) {
+    tprefix[tid * per + i] = run;
+    run += tl[i];
+  }
+  if (tid == 0) tprefix[kBuckets] = total;
+}
+
+// tile -> bucket
+__global__ __launch_bounds__(256) void tile_map_kernel(const uint32_t* __restrict__ tprefix,
+                                                       uint32_t* __restrict__ tmap) {
+  const uint32_t b = blockIdx.x * blockDim.x + threadIdx.x;
+  if (b >= kBuckets) return;
+  for (uint32_t t = tprefix[b]; t < tprefix[b + 1]; ++t) tmap[t] = b;
 }
 
 // --------------------------------------------------------------------------
@@ -361,6 +439,34 @@ __device__ __forceinline__ void bitonic_regs(uint64_t (&v)[N]) {
 // is in place in the output.  The sorts below read a segment from its source
 // and write it sorted to its final position, so moving slots into place
 // costs no extra pass.
+// bucket-aligned tiles, one wavefront each (the grid covers the largest
+// possible number of tiles; the waves beyond the actual number return)
+template <int D, bool FILL>
+__global__ __launch_bounds__(kTileWaves * kWave) void tile_bucket_kernel(
+    TreeDev T, const float* __restrict__ ulo, const float* __restrict__ uhi, uint32_t m,
+    UpdSet US, SegOut O) {
+  constexpr int R = 2 * D;
+  constexpr int RV = (R + 3) / 4;
+  __shared__ float s_cand[kTileWaves][R * kRing];
+  __shared__ uint32_t s_cid[kTileWaves][kRing];
+  __shared__ float4 s_q[kTileWaves][kWave * RV];
+  const uint32_t wave = threadIdx.x / kWave;
+  const uint32_t lane = lane_id();
+  const uint32_t total = uniform_u32(US.tprefix[kBuckets]);
+  {
+    const uint32_t item = blockIdx.x * kTileWaves + wave;
+    if (item >= total) return;
+    const uint32_t b = uniform_u32(US.tmap[item]);
+    const uint32_t lt = item - uniform_u32(US.tprefix[b]);
+    const uint32_t start = uniform_u32(US.boff[b]);
+    const uint32_t end = b + 1 < kBuckets ? uniform_u32(US.boff[b + 1]) : US.total;
+    const uint32_t qbeg = start + lt * 64u;
+    const uint32_t nq = min(64u, end - qbeg);
+    tile_body<D, FILL>(T, ulo, uhi, m, US.perm, 0u, b / kBucketsPerDim, qbeg, nq, O,
+                       s_cand[wave], s_cid[wave], s_q[wave], lane);
+  }
+}
+
 struct SegSrc {
   const uint64_t* slots;  // nullptr: every segment is in place
   SegOut so;              // slot bounds (base = slot offsets, cap, limit)
@@ -727,10 +833,18 @@ static ddm_status launch_traverse(const MatchPlan& P, const TreeDev& T, const fl
   } else {
     ProfScope ps(FILL ? (US.qpt == 1 ? "traverse_tile1_fill" : "traverse_tile_fill")
                       : "traverse_tile_count", s);
-    const uint32_t tiles = (US.total + US.qpt - 1) / US.qpt + D;
-    tile_kernel<D, FILL><<<(tiles + kTileWaves - 1) / kTileWaves, kTileWaves * kWave, 0, s>>>(
-        T, ulo, uhi, m, US, O);
-    DDM_LAUNCHED("tile_kernel");
+    if (US.tmap) {
+      // at most one partial tile per bucket
+      const uint32_t tiles = (US.total + 63u) / 64u + std::min<uint32_t>(US.total, kBuckets);
+      const uint32_t grid = (tiles + kTileWaves - 1) / kTileWaves;
+      tile_bucket_kernel<D, FILL><<<grid, kTileWaves * kWave, 0, s>>>(T, ulo, uhi, m, US, O);
+      DDM_LAUNCHED("tile_bucket_kernel");
+    } else {
+      const uint32_t tiles = (US.total + US.qpt - 1) / US.qpt + D;
+      tile_kernel<D, FILL><<<(tiles + kTileWaves - 1) / kTileWaves, kTileWaves * kWave, 0, s>>>(
+          T, ulo, uhi, m, US, O);
+      DDM_LAUNCHED("tile_kernel");
+    }
   }
   return DDM_OK;
 }
@@ -796,18 +910,30 @@ struct MatchState {
   uint32_t* perm_ovf = nullptr;
   uint32_t* govf = nullptr;
   uint32_t novf = 0;
+  // bucket-aligned tiles and the traversals' tickets (count, fill)
+  uint32_t* tprefix = nullptr;
+  uint32_t* tmap = nullptr;
+  uint32_t* tickets = nullptr;
   explicit MatchState(hipStream_t s) : sc(s), slots_sc(s) {}
-  UpdSet all() const { return UpdSet{perm, gstart, gcount, m, 64}; }
+  UpdSet all(bool fill) const {
+    UpdSet U{perm, gstart, gcount, m, 64};
+    U.boff = bhist;
+    U.tprefix = tprefix;
+    U.tmap = tmap;
+    U.ticket = tickets + (fill ? 1 : 0);
+    return U;
+  }
 };
 
 __global__ void match_init_kernel(uint32_t* __restrict__ gcount, int32_t* __restrict__ flag,
                                   uint32_t* __restrict__ lists_count,
-                                  uint32_t* __restrict__ bhist) {
+                                  uint32_t* __restrict__ bhist, uint32_t* __restrict__ tickets) {
   const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i < kBuckets) bhist[i] = 0;
   if (i < DDM_MAX_D) gcount[i] = 0;
   if (i == 0) *flag = 0;
   if (i < 2) lists_count[i] = 0;
+  if (i < 2) tickets[i] = 0;
 }
 
 __global__ void gather_flags_kernel(const int32_t* __restrict__ tflag,
@@ -898,6 +1024,10 @@ static ddm_status front_half(const ddm_tree* t, const float* ulo, const float* u
   sc.reserve(sizeof(uint32_t) * 2 * (size_t)m);  // segment lists
   sc.reserve(sizeof(uint32_t) * 2);              // segment list counts
   sc.reserve(sizeof(uint64_t) * 4);              // device words for readback
+  const size_t max_tiles = ((size_t)m + 63) / 64 + kBuckets;
+  sc.reserve(sizeof(uint32_t) * (kBuckets + 1));  // tile prefix
+  sc.reserve(sizeof(uint32_t) * max_tiles);       // tile -> bucket
+  sc.reserve(sizeof(uint32_t) * 2);               // tickets
   if (!sc.commit()) return DDM_E_NOMEM;
   st.cmin = sc.take<uint32_t>(m);
   st.kstar = sc.take<uint8_t>(m);
@@ -915,6 +1045,9 @@ static ddm_status front_half(const ddm_tree* t, const float* ulo, const float* u
   *lists = sc.take<uint32_t>(2 * (size_t)m);
   *lists_count = sc.take<uint32_t>(2);
   uint64_t* dwords = sc.take<uint64_t>(4);
+  st.tprefix = sc.take<uint32_t>(kBuckets + 1);
+  st.tmap = sc.take<uint32_t>(max_tiles);
+  st.tickets = sc.take<uint32_t>(2);
   if (st.learned) {
     st.X = sc.take<float>((size_t)m * kFeatures);
     st.cap = sc.take<uint32_t>(m);
@@ -928,7 +1061,8 @@ static ddm_status front_half(const ddm_tree* t, const float* ulo, const float* u
     DDM_LAUNCHED("learned_init_kernel");
   }
 
-  match_init_kernel<<<kBuckets / 256, 256, 0, s>>>(st.gcount, st.flag, *lists_count, st.bhist);
+  match_init_kernel<<<kBuckets / 256, 256, 0, s>>>(st.gcount, st.flag, *lists_count, st.bhist,
+                                                   st.tickets);
   DDM_LAUNCHED("match_init_kernel");
   ddm_status r;
   switch (d) {
@@ -945,6 +1079,12 @@ static ddm_status front_half(const ddm_tree* t, const float* ulo, const float* u
     bucket_scatter_kernel<<<(m + 255) / 256, 256, 0, s>>>(st.bucket, st.rank, m, st.bhist,
                                                           st.perm);
     DDM_LAUNCHED("bucket_scatter_kernel");
+    if (P.traversal == DDM_TRAVERSE_TILE) {
+      tile_prefix_kernel<<<1, 1024, 0, s>>>(st.bhist, m, st.tprefix);
+      DDM_LAUNCHED("tile_prefix_kernel");
+      tile_map_kernel<<<kBuckets / 256, 256, 0, s>>>(st.tprefix, st.tmap);
+      DDM_LAUNCHED("tile_map_kernel");
+    }
   }
   // per-update counts
   const uint32_t* counts = st.cmin;
@@ -980,13 +1120,13 @@ static ddm_status front_half(const ddm_tree* t, const float* ulo, const float* u
     SO.limit = budget;
     SO.cnt = st.cnt;
     SO.out = st.slots;
-    r = traverse_any<true>(d, P, T, ulo, uhi, m, st.all(), st.kstar, SO, s);
+    r = traverse_any<true>(d, P, T, ulo, uhi, m, st.all(true), st.kstar, SO, s);
     if (r != DDM_OK) return r;
     counts = st.cnt;
   } else if (d > 1) {
     SegOut O{};
     O.cnt = st.cnt;
-    r = traverse_any<false>(d, P, T, ulo, uhi, m, st.all(), st.kstar, O, s);
+    r = traverse_any<false>(d, P, T, ulo, uhi, m, st.all(false), st.kstar, O, s);
     if (r != DDM_OK) return r;
     counts = st.cnt;
   }
@@ -999,7 +1139,7 @@ static ddm_status front_half(const ddm_tree* t, const float* ulo, const float* u
   gather_flags_kernel<<<1, 64, 0, s>>>(tree_flag(t), st.flag, st.off, m, dwords);
   DDM_LAUNCHED("gather_flags_kernel");
   if (st.learned) {
-    overflow_kernel<<<(m + 255) / 256, 256, 0, s>>>(st.all(), d, SO, st.cnt, st.perm_ovf,
+    overflow_kernel<<<(m + 255) / 256, 256, 0, s>>>(st.all(false), d, SO, st.cnt, st.perm_ovf,
                                                     st.govf);
     DDM_LAUNCHED("overflow_kernel");
     learned_words_kernel<<<1, 64, 0, s>>>(st.govf, st.soff, m, dwords);
@@ -1272,7 +1412,7 @@ extern "C" ddm_status ddm_match_finish(ddm_pending* pd, uint64_t* out_pairs, uin
                                pd->s);
       }
     } else {
-      r = traverse_any<true>(tree_d(pd->t), pd->plan, T, pd->ulo, pd->uhi, pd->m, st.all(),
+      r = traverse_any<true>(tree_d(pd->t), pd->plan, T, pd->ulo, pd->uhi, pd->m, st.all(true),
                              st.kstar, O, pd->s);
     }
     if (r == DDM_OK) {

@@ -90,6 +90,15 @@ struct UpdSet {
   const uint32_t* gcount;
   uint32_t total;     // upper bound of sum(gcount), for the launch size
   uint32_t qpt = 64;  // updates per wavefront in the tile traversal (64 or 1)
+  // bucket-aligned tiles (optional): bucket b holds perm[boff[b] ..
+  // boff[b+1]) (the last ends at `total`), tiles of 64 updates never cross a
+  // bucket, tile t belongs to bucket tmap[t], the buckets' first tiles are
+  // tprefix[b] and there are tprefix[nbuckets] tiles; wavefronts take tiles
+  // from *ticket
+  const uint32_t* boff = nullptr;
+  const uint32_t* tprefix = nullptr;
+  const uint32_t* tmap = nullptr;
+  uint32_t* ticket = nullptr;
 };
 
 // Where a traversal writes.  COUNT (fill == false): cnt[j] = hits of j.
@@ -289,6 +298,23 @@ __device__ __forceinline__ void tile_body(const TreeDev& T, const float* __restr
     wave_sync();
   };
 
+  // one block of 64 candidate positions: test against the tile's box in
+  // every dimension, compact the survivors into the ring
+  auto stage = [&](const float (&v)[R], uint32_t id, bool inb) {
+    bool cnd = inb;
+#pragma unroll
+    for (int s = 0; s < D; ++s) cnd = cnd & (v[2 * s] <= ehi[s]) & (elo[s] <= v[2 * s + 1]);
+    const uint64_t cm = ballot(cnd);
+    if (cnd) {
+      const uint32_t slot = (tail + mask_rank(cm)) & (kRing - 1);
+#pragma unroll
+      for (int r = 0; r < R; ++r) s_cand[r * kRing + slot] = v[r];
+      s_cid[slot] = id;
+    }
+    tail += (uint32_t)__popcll(cm);
+    if (tail - head >= (uint32_t)kWave) flush(kWave);
+  };
+
   if (Pbeg <= Pend) {
     const uint32_t c0 = Pbeg >> kBlockLog, c1 = Pend >> kBlockLog;
     for (uint32_t cb = c0; cb <= c1; cb += kWave) {
@@ -296,31 +322,31 @@ __device__ __forceinline__ void tile_body(const TreeDev& T, const float* __restr
       const bool keep = (c <= c1) && (bmx[c] >= elo[0]);
       uint64_t bm = ballot(keep);
       while (bm != 0) {
-        const uint32_t b = (uint32_t)__builtin_ctzll(bm);
+        // two kept blocks at a time: both loads are in flight together
+        const uint32_t b0 = (uint32_t)__builtin_ctzll(bm);
         bm &= bm - 1;
-        const uint32_t blk = cb + b;
-        const uint32_t a = max(blk << kBlockLog, Pbeg);
-        const uint32_t e = min((blk << kBlockLog) + (1u << kBlockLog) - 1u, Pend);
-        // positions a..e, one per lane
-        const uint32_t p = a + lane;
-        bool cnd = false;
-        float v[R];
-        if (p <= e) {
-          load_rec<D>(rec + (size_t)p * R, v);
-          cnd = true;
+        const bool two = bm != 0;
+        const uint32_t b1 = two ? (uint32_t)__builtin_ctzll(bm) : b0;
+        if (two) bm &= bm - 1;
+        const uint32_t blkA = cb + b0, blkB = cb + b1;
+        const uint32_t pA = max(blkA << kBlockLog, Pbeg) + lane;
+        const uint32_t pB = max(blkB << kBlockLog, Pbeg) + lane;
+        const bool inA = pA <= min((blkA << kBlockLog) + (1u << kBlockLog) - 1u, Pend);
+        const bool inB = two && pB <= min((blkB << kBlockLog) + (1u << kBlockLog) - 1u, Pend);
+        float vA[R], vB[R];
+        uint32_t idA = 0, idB = 0;
 #pragma unroll
-          for (int s = 0; s < D; ++s)
-            cnd = cnd & (v[2 * s] <= ehi[s]) & (elo[s] <= v[2 * s + 1]);
+        for (int r = 0; r < R; ++r) vA[r] = vB[r] = 0.f;
+        if (inA) {
+          load_rec<D>(rec + (size_t)pA * R, vA);
+          idA = ids[pA];
         }
-        const uint64_t cm = ballot(cnd);
-        if (cnd) {
-          const uint32_t slot = (tail + mask_rank(cm)) & (kRing - 1);
-#pragma unroll
-          for (int r = 0; r < R; ++r) s_cand[r * kRing + slot] = v[r];
-          s_cid[slot] = ids[p];
+        if (inB) {
+          load_rec<D>(rec + (size_t)pB * R, vB);
+          idB = ids[pB];
         }
-        tail += (uint32_t)__popcll(cm);
-        if (tail - head >= (uint32_t)kWave) flush(kWave);
+        stage(vA, idA, inA);
+        stage(vB, idB, inB);
       }
     }
     if (tail != head) flush(tail - head);
