@@ -338,7 +338,9 @@ typedef struct {
 typedef struct {
   uint32_t qpt;          /* default updates per traversal work item: 16, 32
                             or 64 (0 = 64)                                  */
-  uint32_t waves_per_cu; /* persistent traversal occupancy, 1..64 (0 = 16)  */
+  uint32_t waves_per_cu; /* 0: one wavefront per tile of the traversals;
+                            1..64: a persistent grid of this many
+                            wavefronts per CU taking tiles from a ticket    */
   uint32_t use_graph;    /* nonzero: capture on the first run, then replay  */
   uint32_t reserved[5];  /* must be 0                                       */
 } ddm_batch_opts;

@@ -380,7 +380,7 @@ class Batch:
     may be overwritten in place between runs (same shapes).
     """
 
-    def __init__(self, instances, capacity: int, qpt: int = 64, waves_per_cu: int = 16,
+    def __init__(self, instances, capacity: int, qpt: int = 64, waves_per_cu: int = 0,
                  use_graph: bool = True, out=None, qpts=None):
         from ._native import BatchInstance, BatchOpts
         torch = _torch()

@@ -252,14 +252,25 @@ __global__ __launch_bounds__(1024) void b_groups_kernel(const BInst* __restrict_
   }
 }
 
-// Persistent traversal: wavefronts take tiles from the ticket until the
-// prefix tp[G] of tiles is exhausted (every wavefront reaches that exit).
+// tile -> group (instance, probe dimension), one thread per group
+__global__ __launch_bounds__(256) void b_tilemap_kernel(uint32_t G, const uint32_t* __restrict__ tp,
+                                                        uint32_t* __restrict__ tmap) {
+  const uint32_t g = blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= G) return;
+  for (uint32_t t = tp[g]; t < tp[g + 1]; ++t) tmap[t] = g;
+}
+
+// Traversal over the tiles of every group.  persistent == 0: one wavefront
+// per tile (the grid covers the largest possible number of tiles, waves
+// beyond the actual number return); otherwise a fixed grid whose
+// wavefronts take tiles from the ticket until they are exhausted.
 template <bool FILL>
 __global__ __launch_bounds__(kTileWaves * kWave) void b_traverse_kernel(
     const BInst* __restrict__ I, uint32_t G, const uint32_t* __restrict__ tp,
-    const uint32_t* __restrict__ gstart, const uint32_t* __restrict__ gcount,
-    const uint32_t* __restrict__ perm, uint32_t* __restrict__ ticket,
-    const uint32_t* __restrict__ status, SegOut O) {
+    const uint32_t* __restrict__ tmap, const uint32_t* __restrict__ gstart,
+    const uint32_t* __restrict__ gcount, const uint32_t* __restrict__ perm,
+    uint32_t* __restrict__ ticket, uint32_t persistent, const uint32_t* __restrict__ status,
+    SegOut O) {
   __shared__ float s_cand[kTileWaves][2 * DDM_MAX_D * kRing];
   __shared__ uint32_t s_cid[kTileWaves][kRing];
   __shared__ float4 s_q[kTileWaves][kWave * 2];
@@ -267,19 +278,16 @@ __global__ __launch_bounds__(kTileWaves * kWave) void b_traverse_kernel(
   const uint32_t lane = lane_id();
   if (FILL && uniform_u32(*status) != 0) return;
   const uint32_t total = uniform_u32(tp[G]);
+  uint32_t next = blockIdx.x * kTileWaves + wave;
   while (true) {
-    uint32_t item = 0;
-    if (lane == 0) item = atomicAdd(ticket, 1u);
-    item = uniform_u32(__shfl(item, 0, kWave));
-    if (item >= total) break;
-    // group g: last with tp[g] <= item
-    uint32_t lo = 0, hi = G;
-    while (hi - lo > 1) {
-      const uint32_t mid = (lo + hi) >> 1;
-      if (tp[mid] <= item) lo = mid;
-      else hi = mid;
+    uint32_t item = next;
+    if (persistent) {
+      if (lane == 0) item = atomicAdd(ticket, 1u);
+      item = uniform_u32(__shfl(item, 0, kWave));
     }
-    const uint32_t g = uniform_u32(lo);
+    if (item >= total) break;
+    next = total;  // without a ticket a wavefront takes one tile
+    const uint32_t g = uniform_u32(tmap[item]);
     const uint32_t inst = g / DDM_MAX_D, k = g % DDM_MAX_D;
     const BInst& b = I[inst];
     const uint32_t qpt = uniform_u32(b.qpt);
@@ -387,6 +395,9 @@ struct ddm_batch {
   uint32_t *gstart = nullptr, *gcount = nullptr, *tpc = nullptr, *tpf = nullptr;
   uint32_t* lists = nullptr;
   uint32_t* tickets = nullptr;  // [2]; lists counters follow the lists
+  uint32_t* tmapc = nullptr;    // tile -> group, count and fill traversals
+  uint32_t* tmapf = nullptr;
+  uint32_t tiles_max = 0;       // bound of the tiles of either traversal
   uint32_t* status = nullptr;
   uint64_t* words = nullptr;   // total, status, ranges[count+1]
   uint32_t* zero_base = nullptr;  // contiguous words cleared per run
@@ -427,13 +438,17 @@ static ddm_status batch_count_half(ddm_batch* b, hipStream_t s) {
   b_groups_kernel<<<1, 1024, 0, s>>>(b->inst, b->count, b->boff, b->gstart, b->gcount, b->tpc,
                                      b->tpf);
   DDM_LAUNCHED("b_groups_kernel");
+  b_tilemap_kernel<<<(b->G + 255) / 256, 256, 0, s>>>(b->G, b->tpc, b->tmapc);
+  DDM_LAUNCHED("b_tilemap_kernel");
+  b_tilemap_kernel<<<(b->G + 255) / 256, 256, 0, s>>>(b->G, b->tpf, b->tmapf);
+  DDM_LAUNCHED("b_tilemap_kernel");
   {
     ProfScope ps("batch_traverse_count", s);
     SegOut O{};
     O.cnt = b->cnt;
     b_traverse_kernel<false><<<b->grid, kTileWaves * kWave, 0, s>>>(
-        b->inst, b->G, b->tpc, b->gstart, b->gcount, b->perm, b->tickets,
-        b->status, O);
+        b->inst, b->G, b->tpc, b->tmapc, b->gstart, b->gcount, b->perm, b->tickets,
+        b->opts.waves_per_cu, b->status, O);
     DDM_LAUNCHED("b_traverse_kernel");
   }
   r = scan_u32_u64(b->cnt, b->off, b->M, b->scan_tmp_q, s);
@@ -458,8 +473,8 @@ static ddm_status batch_fill_half(ddm_batch* b, hipStream_t s) {
     O.base = b->off;
     O.out = b->out;
     b_traverse_kernel<true><<<b->grid, kTileWaves * kWave, 0, s>>>(
-        b->inst, b->G, b->tpf, b->gstart, b->gcount, b->perm, b->tickets + 1,
-        b->status, O);
+        b->inst, b->G, b->tpf, b->tmapf, b->gstart, b->gcount, b->perm, b->tickets + 1,
+        b->opts.waves_per_cu, b->status, O);
     DDM_LAUNCHED("b_traverse_kernel");
   }
   return sort_segments_inplace(b->off, b->M, b->out, b->nmax, b->lists, b->list_counters, s);
@@ -504,7 +519,6 @@ extern "C" ddm_status ddm_batch_create(const ddm_batch_instance* inst, uint32_t 
     set_detail("ddm_batch_opts: qpt must be 16, 32 or 64");
     return DDM_E_INVALID_ARG;
   }
-  if (o.waves_per_cu == 0) o.waves_per_cu = 16;
   if (o.waves_per_cu > 64) {
     set_detail("ddm_batch_opts: waves_per_cu must be at most 64");
     return DDM_E_INVALID_ARG;
@@ -512,6 +526,7 @@ extern "C" ddm_status ddm_batch_create(const ddm_batch_instance* inst, uint32_t 
   uint64_t M = 0, elems = 0, Btot = 0;
   uint32_t nmax = 0, ntrees = 0, narr = 0, ntiles = 0, nlow = 0, nprobe = 0, items = kQuant;
   uint32_t maxH = 0;
+  uint64_t tiles_max = 0;
   for (uint32_t i = 0; i < count; ++i) {
     const ddm_batch_instance& q = inst[i];
     if (q.d < 1 || q.d > DDM_MAX_D || q.n == 0 || q.m == 0 || !q.sub_lo || !q.sub_hi ||
@@ -536,6 +551,8 @@ extern "C" ddm_status ddm_batch_create(const ddm_batch_instance* inst, uint32_t 
     nlow += q.d * ((P + 1 + kChunk - 1) / kChunk);
     nprobe += (q.m + kProbeThreads - 1) / kProbeThreads;
     items = std::max(items, (q.n + 63) / 64);
+    const uint32_t qq = q.qpt ? q.qpt : o.qpt;
+    tiles_max += (q.m + qq - 1) / qq + q.d;  // at most one partial tile per group
   }
   if (M >= (1ull << 31) || Btot >= (1ull << 31)) {
     set_detail("ddm_batch_create: too many updates");
@@ -565,7 +582,10 @@ extern "C" ddm_status ddm_batch_create(const ddm_batch_instance* inst, uint32_t 
   }
   int cus = 256;
   (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, b->device);
-  b->grid = std::max<uint32_t>(1, (uint32_t)cus * o.waves_per_cu / kTileWaves);
+  b->tiles_max = (uint32_t)std::min<uint64_t>(tiles_max, 0xffffffffull);
+  b->grid = o.waves_per_cu
+                ? std::max<uint32_t>(1, (uint32_t)cus * o.waves_per_cu / kTileWaves)
+                : std::max<uint32_t>(1, (b->tiles_max + kTileWaves - 1) / kTileWaves);
 
   // ---- host-side layout ----
   size_t cur = 0;
@@ -663,6 +683,8 @@ extern "C" ddm_status ddm_batch_create(const ddm_batch_instance* inst, uint32_t 
   const size_t o_stb = take(sizeof(uint64_t) * scan_tmp_words((uint32_t)Btot));
   const size_t o_stq = take(sizeof(uint64_t) * scan_tmp_words((uint32_t)M));
   const size_t o_groups = take(sizeof(uint32_t) * (4 * (size_t)b->G + 2));
+  const size_t o_tmapc = take(sizeof(uint32_t) * tiles_max);
+  const size_t o_tmapf = take(sizeof(uint32_t) * tiles_max);
   const size_t o_lists = take(sizeof(uint32_t) * 2 * M);
   const size_t o_status = take(sizeof(uint32_t) * 4);
   const size_t o_words = take(sizeof(uint64_t) * (count + 3));
@@ -787,6 +809,8 @@ extern "C" ddm_status ddm_batch_create(const ddm_batch_instance* inst, uint32_t 
   b->tpc = gr + 2 * (size_t)b->G;
   b->tpf = gr + 3 * (size_t)b->G + 1;
   b->lists = P32(o_lists);
+  b->tmapc = P32(o_tmapc);
+  b->tmapf = P32(o_tmapf);
   b->status = P32(o_status);
   b->words = (uint64_t*)(base + o_words);
 

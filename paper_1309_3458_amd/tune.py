@@ -8,8 +8,8 @@ tests run every value):
   round(log10 alpha)): dense classes favour full 64-update tiles, sparse ones
   with short candidate ranges can prefer narrower tiles whose enclosing
   interval is tighter;
-* waves_per_cu, the occupancy of the persistent traversal grid, chosen for
-  the whole workload.
+* waves_per_cu, 0 for one wavefront per tile or the occupancy of a
+  persistent traversal grid, chosen for the whole workload.
 
 The tuner times graph replays of the batch on the current GPU and writes a
 JSON table: {"device": ..., "waves_per_cu": W, "qpt": {"lg,d,la": q, ...},
@@ -29,7 +29,7 @@ import time
 PKG = os.path.dirname(os.path.abspath(__file__))
 DEFAULT_TABLE = os.path.join(PKG, "tuning", "batch_gfx950.json")
 QPTS = (16, 32, 64)
-WAVES = (4, 8, 12, 16, 24)
+WAVES = (0, 8, 16, 24)
 
 
 def bucket(N: int, d: int, alpha: float) -> str:
@@ -39,7 +39,7 @@ def bucket(N: int, d: int, alpha: float) -> str:
 
 
 class Table:
-    def __init__(self, qpt=None, waves_per_cu: int = 16, device: str = "", timings=None):
+    def __init__(self, qpt=None, waves_per_cu: int = 0, device: str = "", timings=None):
         self.qpt_map = dict(qpt or {})
         self.waves_per_cu = int(waves_per_cu)
         self.device = device
@@ -51,7 +51,7 @@ class Table:
             return cls()
         with open(path) as f:
             t = json.load(f)
-        return cls(t.get("qpt"), t.get("waves_per_cu", 16), t.get("device", ""),
+        return cls(t.get("qpt"), t.get("waves_per_cu", 0), t.get("device", ""),
                    t.get("timings"))
 
     def save(self, path: str):
@@ -90,7 +90,7 @@ def batch_total(tens, qpts=None) -> int:
     return tot
 
 
-def time_batch(tens, K: int, qpts=None, waves_per_cu: int = 16, reps: int = 10,
+def time_batch(tens, K: int, qpts=None, waves_per_cu: int = 0, reps: int = 10,
                out=None) -> float:
     """Mean ms of a graph replay of the batch."""
     import torch
@@ -150,12 +150,12 @@ def tune(specs, per_class: int = 4, reps: int = 10, seed: int = 500, log=print) 
     K = batch_total(tens, qpts)
     out = torch.empty(K, dtype=torch.int64, device="cuda")
     ms = {w: time_batch(tens, K, qpts, w, reps=reps, out=out) for w in WAVES}
-    ms64 = time_batch(tens, K, None, 16, reps=reps, out=out)
+    ms64 = time_batch(tens, K, None, 0, reps=reps, out=out)
     table.waves_per_cu = min(ms, key=ms.get)
     table.timings["waves_per_cu"] = {str(w): round(v, 4) for w, v in ms.items()}
-    table.timings["untuned_q64_w16"] = round(ms64, 4)
+    table.timings["untuned_q64_w0"] = round(ms64, 4)
     log(f"whole workload K={K}: " + " ".join(f"w{w}={v:.3f}ms" for w, v in ms.items())
-        + f" -> {table.waves_per_cu}; untuned (qpt 64, 16 waves/CU) {ms64:.3f}ms")
+        + f" -> {table.waves_per_cu}; untuned (qpt 64, one wave per tile) {ms64:.3f}ms")
     return table
 
 

@@ -83,7 +83,7 @@ def test_batch_edge_instances():
     b.free()
 
 
-@pytest.mark.parametrize("qpt,wpc", [(16, 1), (32, 4), (64, 24), (64, 64)])
+@pytest.mark.parametrize("qpt,wpc", [(16, 1), (32, 4), (64, 24), (64, 64), (16, 0), (64, 0)])
 def test_batch_work_item_sizes(qpt, wpc):
     insts = _small_batch(32, 12)
     want = [oracle.itm(i.s_lo, i.s_hi, i.u_lo, i.u_hi, threads=8) for i in insts]
