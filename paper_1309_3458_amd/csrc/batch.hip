@@ -252,12 +252,20 @@ __global__ __launch_bounds__(1024) void b_groups_kernel(const BInst* __restrict_
   }
 }
 
-// tile -> group (instance, probe dimension), one thread per group
+// tile -> group (instance, probe dimension): one thread per possible tile,
+// binary search of the groups' first tiles
 __global__ __launch_bounds__(256) void b_tilemap_kernel(uint32_t G, const uint32_t* __restrict__ tp,
-                                                        uint32_t* __restrict__ tmap) {
-  const uint32_t g = blockIdx.x * blockDim.x + threadIdx.x;
-  if (g >= G) return;
-  for (uint32_t t = tp[g]; t < tp[g + 1]; ++t) tmap[t] = g;
+                                                        uint32_t* __restrict__ tmap,
+                                                        uint32_t tiles_max) {
+  const uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= tiles_max || t >= tp[G]) return;
+  uint32_t lo = 0, hi = G;  // last g with tp[g] <= t
+  while (hi - lo > 1) {
+    const uint32_t mid = (lo + hi) >> 1;
+    if (tp[mid] <= t) lo = mid;
+    else hi = mid;
+  }
+  tmap[t] = lo;
 }
 
 // Traversal over the tiles of every group.  persistent == 0: one wavefront
@@ -438,9 +446,11 @@ static ddm_status batch_count_half(ddm_batch* b, hipStream_t s) {
   b_groups_kernel<<<1, 1024, 0, s>>>(b->inst, b->count, b->boff, b->gstart, b->gcount, b->tpc,
                                      b->tpf);
   DDM_LAUNCHED("b_groups_kernel");
-  b_tilemap_kernel<<<(b->G + 255) / 256, 256, 0, s>>>(b->G, b->tpc, b->tmapc);
+  b_tilemap_kernel<<<(b->tiles_max + 255) / 256, 256, 0, s>>>(b->G, b->tpc, b->tmapc,
+                                                               b->tiles_max);
   DDM_LAUNCHED("b_tilemap_kernel");
-  b_tilemap_kernel<<<(b->G + 255) / 256, 256, 0, s>>>(b->G, b->tpf, b->tmapf);
+  b_tilemap_kernel<<<(b->tiles_max + 255) / 256, 256, 0, s>>>(b->G, b->tpf, b->tmapf,
+                                                               b->tiles_max);
   DDM_LAUNCHED("b_tilemap_kernel");
   {
     ProfScope ps("batch_traverse_count", s);

@@ -188,30 +188,58 @@ __global__ __launch_bounds__(1024) void probe_kernel(TreeDev T, const float* __r
 }
 
 // exclusive scan of the bucket counts (one workgroup, through LDS); the
-// number of updates of each probe dimension falls out of group boundaries
+// number of updates of each probe dimension falls out of group boundaries.
+// With tprefix non-null, also the exclusive prefix of the buckets' tiles of
+// at most 64 updates (tprefix[kBuckets] = all tiles).
 __global__ __launch_bounds__(1024) void bucket_scan_kernel(uint32_t* __restrict__ bhist,
                                                            uint32_t m,
                                                            uint32_t* __restrict__ gstart_out,
-                                                           uint32_t* __restrict__ gcount) {
+                                                           uint32_t* __restrict__ gcount,
+                                                           uint32_t* __restrict__ tprefix) {
   constexpr uint32_t per = kBuckets / 1024;
   __shared__ uint32_t sb[kBuckets];
   __shared__ uint32_t wsum[1024 / kWave];
+  __shared__ uint32_t tws[1024 / kWave];
   __shared__ uint32_t gstart[DDM_MAX_D + 1];
   const uint32_t tid = threadIdx.x, lane = lane_id(), wave = tid / kWave;
   for (uint32_t i = tid; i < kBuckets; i += 1024) sb[i] = bhist[i];
   __syncthreads();
-  uint32_t sum = 0;
-  for (uint32_t i = 0; i < per; ++i) sum += sb[tid * per + i];
-  uint32_t inc = sum;
+  uint32_t sum = 0, tsum = 0;
+  for (uint32_t i = 0; i < per; ++i) {
+    sum += sb[tid * per + i];
+    tsum += (sb[tid * per + i] + 63u) / 64u;
+  }
+  uint32_t inc = sum, tinc = tsum;
 #pragma unroll
   for (int o = 1; o < kWave; o <<= 1) {
     const uint32_t t2 = __shfl_up(inc, o, kWave);
-    if (lane >= (uint32_t)o) inc += t2;
+    const uint32_t t3 = __shfl_up(tinc, o, kWave);
+    if (lane >= (uint32_t)o) {
+      inc += t2;
+      tinc += t3;
+    }
   }
-  if (lane == kWave - 1) wsum[wave] = inc;
+  if (lane == kWave - 1) {
+    wsum[wave] = inc;
+    tws[wave] = tinc;
+  }
   __syncthreads();
-  uint32_t before = 0;
-  for (uint32_t w = 0; w < wave; ++w) before += wsum[w];
+  uint32_t before = 0, tbefore = 0, ttotal = 0;
+  for (uint32_t w = 0; w < 1024 / kWave; ++w) {
+    if (w < wave) {
+      before += wsum[w];
+      tbefore += tws[w];
+    }
+    ttotal += tws[w];
+  }
+  if (tprefix) {
+    uint32_t trun = tbefore + tinc - tsum;
+    for (uint32_t i = 0; i < per; ++i) {
+      tprefix[tid * per + i] = trun;
+      trun += (sb[tid * per + i] + 63u) / 64u;
+    }
+    if (tid == 0) tprefix[kBuckets] = ttotal;
+  }
   uint32_t run = before + inc - sum;
   if ((tid * per) % kBucketsPerDim == 0) gstart[(tid * per) / kBucketsPerDim] = run;
   if (tid == 0) gstart[DDM_MAX_D] = m;
@@ -235,46 +263,6 @@ __global__ __launch_bounds__(256) void bucket_scatter_kernel(const uint32_t* __r
                                                              uint32_t* __restrict__ perm) {
   const uint32_t j = blockIdx.x * blockDim.x + threadIdx.x;
   if (j < m) perm[bhist[bucket[j]] + rank[j]] = j;
-}
-
-// tiles of at most 64 updates per bucket: exclusive prefix of their numbers
-// (one workgroup; boff holds the buckets' exclusive offsets, the last
-// bucket ends at m)
-__global__ __launch_bounds__(1024) void tile_prefix_kernel(const uint32_t* __restrict__ boff,
-                                                           uint32_t m,
-                                                           uint32_t* __restrict__ tprefix) {
-  constexpr uint32_t per = kBuckets / 1024;
-  __shared__ uint32_t wsum[1024 / kWave];
-  const uint32_t tid = threadIdx.x, lane = lane_id(), wave = tid / kWave;
-  uint32_t tl[per];
-  uint32_t sum = 0;
-#pragma unroll
-  for (uint32_t i = 0; i < per; ++i) {
-    const uint32_t b = tid * per + i;
-    const uint32_t e = b + 1 < kBuckets ? boff[b + 1] : m;
-    tl[i] = (e - boff[b] + 63u) / 64u;
-    sum += tl[i];
-  }
-  uint32_t inc = sum;
-#pragma unroll
-  for (int o = 1; o < kWave; o <<= 1) {
-    const uint32_t t2 = __shfl_up(inc, o, kWave);
-    if (lane >= (uint32_t)o) inc += t2;
-  }
-  if (lane == kWave - 1) wsum[wave] = inc;
-  __syncthreads();
-  uint32_t run = 0, total = 0;
-  for (uint32_t w = 0; w < 1024 / kWave; ++w) {
-    if (w < wave) run += wsum[w];
-    total += wsum[w];
-  }
-  run += inc - sum;
-#pragma unroll
-  for (uint32_t i = 0; i < per; ++i) {
-    tprefix[tid * per + i] = run;
-    run += tl[i];
-  }
-  if (tid == 0) tprefix[kBuckets] = total;
 }
 
 // tile -> bucket
@@ -1074,14 +1062,13 @@ static ddm_status front_half(const ddm_tree* t, const float* ulo, const float* u
   if (r != DDM_OK) return r;
   {
     ProfScope ps("order", s);
-    bucket_scan_kernel<<<1, 1024, 0, s>>>(st.bhist, m, st.gstart, st.gcount);
+    bucket_scan_kernel<<<1, 1024, 0, s>>>(st.bhist, m, st.gstart, st.gcount,
+                                          P.traversal == DDM_TRAVERSE_TILE ? st.tprefix : nullptr);
     DDM_LAUNCHED("bucket_scan_kernel");
     bucket_scatter_kernel<<<(m + 255) / 256, 256, 0, s>>>(st.bucket, st.rank, m, st.bhist,
                                                           st.perm);
     DDM_LAUNCHED("bucket_scatter_kernel");
     if (P.traversal == DDM_TRAVERSE_TILE) {
-      tile_prefix_kernel<<<1, 1024, 0, s>>>(st.bhist, m, st.tprefix);
-      DDM_LAUNCHED("tile_prefix_kernel");
       tile_map_kernel<<<kBuckets / 256, 256, 0, s>>>(st.tprefix, st.tmap);
       DDM_LAUNCHED("tile_map_kernel");
     }
