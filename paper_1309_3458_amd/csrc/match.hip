@@ -898,30 +898,27 @@ struct MatchState {
   uint32_t* perm_ovf = nullptr;
   uint32_t* govf = nullptr;
   uint32_t novf = 0;
-  // bucket-aligned tiles and the traversals' tickets (count, fill)
+  // bucket-aligned tiles
   uint32_t* tprefix = nullptr;
   uint32_t* tmap = nullptr;
-  uint32_t* tickets = nullptr;
   explicit MatchState(hipStream_t s) : sc(s), slots_sc(s) {}
-  UpdSet all(bool fill) const {
+  UpdSet all() const {
     UpdSet U{perm, gstart, gcount, m, 64};
     U.boff = bhist;
     U.tprefix = tprefix;
     U.tmap = tmap;
-    U.ticket = tickets + (fill ? 1 : 0);
     return U;
   }
 };
 
 __global__ void match_init_kernel(uint32_t* __restrict__ gcount, int32_t* __restrict__ flag,
                                   uint32_t* __restrict__ lists_count,
-                                  uint32_t* __restrict__ bhist, uint32_t* __restrict__ tickets) {
+                                  uint32_t* __restrict__ bhist) {
   const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i < kBuckets) bhist[i] = 0;
   if (i < DDM_MAX_D) gcount[i] = 0;
   if (i == 0) *flag = 0;
   if (i < 2) lists_count[i] = 0;
-  if (i < 2) tickets[i] = 0;
 }
 
 __global__ void gather_flags_kernel(const int32_t* __restrict__ tflag,
@@ -1015,7 +1012,6 @@ static ddm_status front_half(const ddm_tree* t, const float* ulo, const float* u
   const size_t max_tiles = ((size_t)m + 63) / 64 + kBuckets;
   sc.reserve(sizeof(uint32_t) * (kBuckets + 1));  // tile prefix
   sc.reserve(sizeof(uint32_t) * max_tiles);       // tile -> bucket
-  sc.reserve(sizeof(uint32_t) * 2);               // tickets
   if (!sc.commit()) return DDM_E_NOMEM;
   st.cmin = sc.take<uint32_t>(m);
   st.kstar = sc.take<uint8_t>(m);
@@ -1035,7 +1031,6 @@ static ddm_status front_half(const ddm_tree* t, const float* ulo, const float* u
   uint64_t* dwords = sc.take<uint64_t>(4);
   st.tprefix = sc.take<uint32_t>(kBuckets + 1);
   st.tmap = sc.take<uint32_t>(max_tiles);
-  st.tickets = sc.take<uint32_t>(2);
   if (st.learned) {
     st.X = sc.take<float>((size_t)m * kFeatures);
     st.cap = sc.take<uint32_t>(m);
@@ -1049,8 +1044,7 @@ static ddm_status front_half(const ddm_tree* t, const float* ulo, const float* u
     DDM_LAUNCHED("learned_init_kernel");
   }
 
-  match_init_kernel<<<kBuckets / 256, 256, 0, s>>>(st.gcount, st.flag, *lists_count, st.bhist,
-                                                   st.tickets);
+  match_init_kernel<<<kBuckets / 256, 256, 0, s>>>(st.gcount, st.flag, *lists_count, st.bhist);
   DDM_LAUNCHED("match_init_kernel");
   ddm_status r;
   switch (d) {
@@ -1107,13 +1101,13 @@ static ddm_status front_half(const ddm_tree* t, const float* ulo, const float* u
     SO.limit = budget;
     SO.cnt = st.cnt;
     SO.out = st.slots;
-    r = traverse_any<true>(d, P, T, ulo, uhi, m, st.all(true), st.kstar, SO, s);
+    r = traverse_any<true>(d, P, T, ulo, uhi, m, st.all(), st.kstar, SO, s);
     if (r != DDM_OK) return r;
     counts = st.cnt;
   } else if (d > 1) {
     SegOut O{};
     O.cnt = st.cnt;
-    r = traverse_any<false>(d, P, T, ulo, uhi, m, st.all(false), st.kstar, O, s);
+    r = traverse_any<false>(d, P, T, ulo, uhi, m, st.all(), st.kstar, O, s);
     if (r != DDM_OK) return r;
     counts = st.cnt;
   }
@@ -1126,7 +1120,7 @@ static ddm_status front_half(const ddm_tree* t, const float* ulo, const float* u
   gather_flags_kernel<<<1, 64, 0, s>>>(tree_flag(t), st.flag, st.off, m, dwords);
   DDM_LAUNCHED("gather_flags_kernel");
   if (st.learned) {
-    overflow_kernel<<<(m + 255) / 256, 256, 0, s>>>(st.all(false), d, SO, st.cnt, st.perm_ovf,
+    overflow_kernel<<<(m + 255) / 256, 256, 0, s>>>(st.all(), d, SO, st.cnt, st.perm_ovf,
                                                     st.govf);
     DDM_LAUNCHED("overflow_kernel");
     learned_words_kernel<<<1, 64, 0, s>>>(st.govf, st.soff, m, dwords);
@@ -1399,7 +1393,7 @@ extern "C" ddm_status ddm_match_finish(ddm_pending* pd, uint64_t* out_pairs, uin
                                pd->s);
       }
     } else {
-      r = traverse_any<true>(tree_d(pd->t), pd->plan, T, pd->ulo, pd->uhi, pd->m, st.all(true),
+      r = traverse_any<true>(tree_d(pd->t), pd->plan, T, pd->ulo, pd->uhi, pd->m, st.all(),
                              st.kstar, O, pd->s);
     }
     if (r == DDM_OK) {

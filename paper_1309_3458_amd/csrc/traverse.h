@@ -93,12 +93,10 @@ struct UpdSet {
   // bucket-aligned tiles (optional): bucket b holds perm[boff[b] ..
   // boff[b+1]) (the last ends at `total`), tiles of 64 updates never cross a
   // bucket, tile t belongs to bucket tmap[t], the buckets' first tiles are
-  // tprefix[b] and there are tprefix[nbuckets] tiles; wavefronts take tiles
-  // from *ticket
+  // tprefix[b] and there are tprefix[nbuckets] tiles
   const uint32_t* boff = nullptr;
   const uint32_t* tprefix = nullptr;
   const uint32_t* tmap = nullptr;
-  uint32_t* ticket = nullptr;
 };
 
 // Where a traversal writes.  COUNT (fill == false): cnt[j] = hits of j.
