@@ -19,7 +19,8 @@ Workloads:
                         [0.01, 100], seed 3), one graph replay per step
   sweep_1d              the paper's experiment on the GPU: d=1, N from 5e4
                         to 5e5, alpha in {0.01, 1, 100}; ITM (build +
-                        match) beside GPU Brute-Force Matching
+                        match) beside GPU Brute-Force and Sort-Based
+                        Matching
   hbm_copy              a plain device-to-device copy of 1 GiB per step
                         (calibrates the HBM traffic counters)
   serve                 open-loop Poisson arrivals (2000/s, d=3, N
@@ -468,7 +469,8 @@ def bench_serve(args):
 def bench_sweep(args):
     """Sec. V's experiment (d = 1, n = m = N/2, uniform lower ends on [0, L),
     common length alpha L / N) on the GPU: ITM build + match per step, and
-    Brute-Force Matching (Algorithm 2) on the same inputs."""
+    Brute-Force Matching (Algorithm 2) and Sort-Based Matching (Algorithm 3)
+    on the same inputs."""
     import torch
 
     import paper_1309_3458_amd as P
@@ -501,11 +503,18 @@ def bench_sweep(args):
             bf()
             bwall, bper, kb = evented_steps(bf, 3)
             assert kb == K
+            sb = lambda: P.match_sbm(s_lo, s_hi, u_lo, u_hi, out=out).numel()
+            for _ in range(args.warmup):
+                sb()
+            swall, sper, ks = evented_steps(sb, args.steps)
+            assert ks == K
             rows.append({"N": N, "alpha": alpha, "K": K, "itm_ms": step_stats(per),
-                         "brute_ms": step_stats(bper),
+                         "brute_ms": step_stats(bper), "sbm_ms": step_stats(sper),
                          "itm_pairs_per_s": round(K / (wall / 1e3), 1),
-                         "speedup_itm_vs_brute": round(bwall / wall, 2)})
-            log(f"N={N} alpha={alpha}: K={K} ITM {wall:.4f} ms, BF {bwall:.3f} ms")
+                         "speedup_itm_vs_brute": round(bwall / wall, 2),
+                         "speedup_itm_vs_sbm": round(swall / wall, 2)})
+            log(f"N={N} alpha={alpha}: K={K} ITM {wall:.4f} ms, SBM {swall:.4f} ms, "
+                f"BF {bwall:.3f} ms")
     last = [r for r in rows if r["N"] == 500_000 and r["alpha"] == 100.0][0]
     return {"metric": "ITM build+match time, d=1 sweep of the paper's experiment",
             "value": last["itm_pairs_per_s"], "unit": "pairs/s",

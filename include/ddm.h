@@ -263,6 +263,23 @@ ddm_status ddm_match_brute(const float* sub_lo, const float* sub_hi, uint32_t n,
                            uint64_t* out_pairs, uint64_t capacity, uint64_t* out_count,
                            void* stream);
 
+/* ddm_match_sbm -- the same result as ddm_build + ddm_match, computed by
+ * Sort-Based Matching (Algorithm 3, Sec. III-D): the endpoints of dimension
+ * 0 are sorted and swept; the sweep is cut into segments of 64 subscription
+ * lower endpoints whose starting sets of active subscriptions are formed
+ * from a prefix, and every update resumes the sweep at its segment's start.
+ * The other dimensions are tested on every pair the sweep reports (the
+ * combine of Sec. III-A).  The paper's sweep-line comparison system, for
+ * comparison on the same GPU.
+ *  Arguments, ownership and errors as for ddm_match_brute; n, m < 2^31.
+ * Synchronizes the stream twice.  Cost O((n + m) log(n + m)) for the sorts
+ * plus, per update, the subscriptions active at its segment's start and the
+ * lower endpoints between that start and its upper endpoint.                */
+ddm_status ddm_match_sbm(const float* sub_lo, const float* sub_hi, uint32_t n,
+                         const float* upd_lo, const float* upd_hi, uint32_t m, uint32_t d,
+                         uint64_t* out_pairs, uint64_t capacity, uint64_t* out_count,
+                         void* stream);
+
 /* ddm_tree_update -- moves `count` subscriptions of a resident tree to new
  * extents (dynamic DDM: extents move between matches, Sec. I, Sec. VI), so
  * that later matches see the moved set without a new ddm_build.

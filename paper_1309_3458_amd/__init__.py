@@ -16,7 +16,7 @@ from ._native import (DDMError, DDM_E_CAPACITY, FEATURES, PREDICTOR_PARAMS, TRAV
 
 __all__ = ["build", "match", "count", "Tree", "DDMError", "prof_enable", "prof_read",
            "TRAVERSE", "header_functions", "Predictor", "features", "match_learned", "Batch",
-           "Server", "match_brute"]
+           "Server", "match_brute", "match_sbm"]
 
 
 def _torch():
@@ -190,29 +190,39 @@ def count(tree: Tree, u_lo, u_hi, traversal: str = "auto", block: int = 0, strea
     return counts, int(K.value)
 
 
-def match_brute(s_lo, s_hi, u_lo, u_hi, stream=None, out=None):
-    """Brute-force matching on the GPU (the paper's baseline); same keys as
-    build() + match()."""
+def _match_pairwise(entry: str, s_lo, s_hi, u_lo, u_hi, stream, out):
     torch = _torch()
-    s_lo, s_hi = _coords(s_lo, s_hi, "match_brute subscriptions")
-    u_lo, u_hi = _coords(u_lo, u_hi, "match_brute updates")
+    s_lo, s_hi = _coords(s_lo, s_hi, f"{entry} subscriptions")
+    u_lo, u_hi = _coords(u_lo, u_hi, f"{entry} updates")
     if s_lo.shape[0] != u_lo.shape[0]:
-        raise ValueError("match_brute: subscriptions and updates differ in d")
+        raise ValueError(f"{entry}: subscriptions and updates differ in d")
     n, m, d = int(s_lo.shape[1]), int(u_lo.shape[1]), int(s_lo.shape[0])
+    fn = getattr(lib(), entry)
     K = ctypes.c_uint64()
     h = _stream_handle(stream)
     cap = out.numel() if out is not None else 0
-    code = lib().ddm_match_brute(_ptr(s_lo), _ptr(s_hi), n, _ptr(u_lo), _ptr(u_hi), m, d,
-                                 _ptr(out) if out is not None else None, cap,
-                                 ctypes.byref(K), h)
+    code = fn(_ptr(s_lo), _ptr(s_hi), n, _ptr(u_lo), _ptr(u_hi), m, d,
+              _ptr(out) if out is not None else None, cap, ctypes.byref(K), h)
     if out is None and code == DDM_E_CAPACITY:
         out = torch.empty(int(K.value), dtype=torch.int64, device=u_lo.device)
-        code = lib().ddm_match_brute(_ptr(s_lo), _ptr(s_hi), n, _ptr(u_lo), _ptr(u_hi), m, d,
-                                     _ptr(out), out.numel(), ctypes.byref(K), h)
-    check(code, "ddm_match_brute")
+        code = fn(_ptr(s_lo), _ptr(s_hi), n, _ptr(u_lo), _ptr(u_hi), m, d,
+                  _ptr(out), out.numel(), ctypes.byref(K), h)
+    check(code, entry)
     if out is None:
         out = torch.empty(0, dtype=torch.int64, device=u_lo.device)
     return out[:int(K.value)]
+
+
+def match_brute(s_lo, s_hi, u_lo, u_hi, stream=None, out=None):
+    """Brute-force matching on the GPU (the paper's baseline); same keys as
+    build() + match()."""
+    return _match_pairwise("ddm_match_brute", s_lo, s_hi, u_lo, u_hi, stream, out)
+
+
+def match_sbm(s_lo, s_hi, u_lo, u_hi, stream=None, out=None):
+    """Sort-based matching on the GPU (the paper's sweep-line comparison
+    system); same keys as build() + match()."""
+    return _match_pairwise("ddm_match_sbm", s_lo, s_hi, u_lo, u_hi, stream, out)
 
 
 def prof_enable(on: bool = True, only: str | None = None):

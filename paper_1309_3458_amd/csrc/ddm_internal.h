@@ -331,6 +331,10 @@ ddm_status sort_setup_small(const SortArr* host_arrs, uint32_t narr, SortArr* ar
 ddm_status sort_segments_inplace(const uint64_t* off, uint32_t m, uint64_t* out, uint32_t n,
                                  uint32_t* lists, uint32_t* lists_count, hipStream_t s);
 
+// the same for K pairs and any n (ids above 2^20 are sorted from a copy)
+ddm_status sort_segments_keys(const uint64_t* off, uint32_t m, uint64_t* out, uint64_t K,
+                              uint32_t n, uint32_t* lists, uint32_t* lists_count, hipStream_t s);
+
 // exclusive scan of u32 counts into u64 offsets out[0..m], out[m] = total.
 // tmp: scan_tmp_words(m) uint64 scratch.
 size_t scan_tmp_words(uint32_t m);

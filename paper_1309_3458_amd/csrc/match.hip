@@ -1197,6 +1197,11 @@ ddm_status sort_segments_inplace(const uint64_t* off, uint32_t m, uint64_t* out,
   return sort_segments(off, m, out, 0, n, lists, lists_count, s, SegSrc{});
 }
 
+ddm_status sort_segments_keys(const uint64_t* off, uint32_t m, uint64_t* out, uint64_t K,
+                              uint32_t n, uint32_t* lists, uint32_t* lists_count, hipStream_t s) {
+  return sort_segments(off, m, out, K, n, lists, lists_count, s, SegSrc{});
+}
+
 ddm_status sort_segments(const uint64_t* off, uint32_t m, uint64_t* out, uint64_t K, uint32_t n,
                          uint32_t* lists, uint32_t* lists_count, hipStream_t s,
                          const SegSrc& S) {
