@@ -280,6 +280,33 @@ ddm_status ddm_match_sbm(const float* sub_lo, const float* sub_hi, uint32_t n,
                          uint64_t* out_pairs, uint64_t capacity, uint64_t* out_count,
                          void* stream);
 
+/* ddm_match_sets -- the result of ddm_build(S) + ddm_match(U) for two sets
+ * given together, with the tree built on the smaller set.  Sec. IV assumes
+ * n <= m without loss of generality, swapping the roles of S and U
+ * otherwise: when swapped, the tree is built on the updates, queried with
+ * the subscriptions, and the keys are transposed back on the device (a
+ * stable radix sort by update id), so the output is bit-identical to the
+ * unswapped one.
+ *  sub_lo/sub_hi  device, d*n float32, dimension-major; upd_lo/upd_hi
+ *                 device, d*m float32.
+ *  swap_policy    DDM_SWAP_AUTO (swap when n > m), DDM_SWAP_NEVER or
+ *                 DDM_SWAP_ALWAYS.  A swap transposes on the device and
+ *                 needs capacity < 2^32: AUTO does not swap beyond it,
+ *                 ALWAYS returns DDM_E_INVALID_ARG.
+ *  out_pairs      device, capacity uint64 (may be NULL when capacity is 0).
+ *  out_count      host, receives K on DDM_OK / DDM_E_CAPACITY.
+ *  out_swapped    host, may be NULL: 1 if the tree was built on the updates.
+ * The tree is freed before return.  Synchronizes the stream once (to read
+ * K).  DDM_E_CAPACITY writes nothing; invalid coordinates of either set give
+ * DDM_E_INVALID_INPUT.  A swap needs 16 bytes of scratch per pair.          */
+#define DDM_SWAP_AUTO 0
+#define DDM_SWAP_NEVER 1
+#define DDM_SWAP_ALWAYS 2
+ddm_status ddm_match_sets(const float* sub_lo, const float* sub_hi, uint32_t n,
+                          const float* upd_lo, const float* upd_hi, uint32_t m, uint32_t d,
+                          int swap_policy, uint64_t* out_pairs, uint64_t capacity,
+                          uint64_t* out_count, int* out_swapped, void* stream);
+
 /* ddm_tree_update -- moves `count` subscriptions of a resident tree to new
  * extents (dynamic DDM: extents move between matches, Sec. I, Sec. VI), so
  * that later matches see the moved set without a new ddm_build.

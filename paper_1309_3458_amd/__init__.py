@@ -16,7 +16,8 @@ from ._native import (DDMError, DDM_E_CAPACITY, FEATURES, PREDICTOR_PARAMS, TRAV
 
 __all__ = ["build", "match", "count", "Tree", "DDMError", "prof_enable", "prof_read",
            "TRAVERSE", "header_functions", "Predictor", "features", "match_learned", "Batch",
-           "Server", "match_brute", "match_sbm"]
+           "Server", "match_brute", "match_sbm",
+           "match_sets", "SWAP_AUTO", "SWAP_NEVER", "SWAP_ALWAYS"]
 
 
 def _torch():
@@ -223,6 +224,41 @@ def match_sbm(s_lo, s_hi, u_lo, u_hi, stream=None, out=None):
     """Sort-based matching on the GPU (the paper's sweep-line comparison
     system); same keys as build() + match()."""
     return _match_pairwise("ddm_match_sbm", s_lo, s_hi, u_lo, u_hi, stream, out)
+
+
+SWAP_AUTO, SWAP_NEVER, SWAP_ALWAYS = 0, 1, 2
+
+
+def match_sets(s_lo, s_hi, u_lo, u_hi, swap=SWAP_AUTO, stream=None, out=None,
+               return_swapped=False):
+    """build() + match() for two sets given together, with the tree on the
+    smaller set (roles of subscriptions and updates swapped when n > m under
+    SWAP_AUTO); the keys are the same as build(s) + match(u)."""
+    torch = _torch()
+    s_lo, s_hi = _coords(s_lo, s_hi, "match_sets subscriptions")
+    u_lo, u_hi = _coords(u_lo, u_hi, "match_sets updates")
+    if s_lo.shape[0] != u_lo.shape[0]:
+        raise ValueError("match_sets: subscriptions and updates differ in d")
+    n, m, d = int(s_lo.shape[1]), int(u_lo.shape[1]), int(s_lo.shape[0])
+    K = ctypes.c_uint64()
+    sw = ctypes.c_int(0)
+    h = _stream_handle(stream)
+
+    def call(buf):
+        return lib().ddm_match_sets(_ptr(s_lo), _ptr(s_hi), n, _ptr(u_lo), _ptr(u_hi), m, d,
+                                    int(swap), _ptr(buf) if buf is not None else None,
+                                    buf.numel() if buf is not None else 0, ctypes.byref(K),
+                                    ctypes.byref(sw), h)
+
+    code = call(out)
+    if out is None and code == DDM_E_CAPACITY:
+        out = torch.empty(int(K.value), dtype=torch.int64, device=u_lo.device)
+        code = call(out)
+    check(code, "ddm_match_sets")
+    if out is None:
+        out = torch.empty(0, dtype=torch.int64, device=u_lo.device)
+    res = out[:int(K.value)]
+    return (res, bool(sw.value)) if return_swapped else res
 
 
 def prof_enable(on: bool = True, only: str | None = None):

@@ -120,6 +120,8 @@ def lib():
     _sig(L, "ddm_count", i32, vp, vp, vp, u32, vp, P(u64), vp, P(MatchOpts))
     _sig(L, "ddm_match_brute", i32, vp, vp, u32, vp, vp, u32, u32, vp, u64, P(u64), vp)
     _sig(L, "ddm_match_sbm", i32, vp, vp, u32, vp, vp, u32, u32, vp, u64, P(u64), vp)
+    _sig(L, "ddm_match_sets", i32, vp, vp, u32, vp, vp, u32, u32, i32, vp, u64, P(u64),
+         P(ctypes.c_int), vp)
     _sig(L, "ddm_tree_check", i32, vp)
     _sig(L, "ddm_tree_update", i32, vp, vp, vp, vp, u32, vp, P(i32))
     _sig(L, "ddm_tree_info", i32, vp, P(u32), P(u32), P(u32))
