@@ -429,7 +429,7 @@ __device__ __forceinline__ void bitonic_regs(uint64_t (&v)[N]) {
 // costs no extra pass.
 // bucket-aligned tiles, one wavefront each (the grid covers the largest
 // possible number of tiles; the waves beyond the actual number return)
-template <int D, bool FILL>
+template <int D, bool FILL, bool STASH = false>
 __global__ __launch_bounds__(kTileWaves * kWave) void tile_bucket_kernel(
     TreeDev T, const float* __restrict__ ulo, const float* __restrict__ uhi, uint32_t m,
     UpdSet US, SegOut O) {
@@ -450,8 +450,8 @@ __global__ __launch_bounds__(kTileWaves * kWave) void tile_bucket_kernel(
     const uint32_t end = b + 1 < kBuckets ? uniform_u32(US.boff[b + 1]) : US.total;
     const uint32_t qbeg = start + lt * 64u;
     const uint32_t nq = min(64u, end - qbeg);
-    tile_body<D, FILL>(T, ulo, uhi, m, US.perm, 0u, b / kBucketsPerDim, qbeg, nq, O,
-                       s_cand[wave], s_cid[wave], s_q[wave], lane);
+    tile_body<D, FILL, STASH>(T, ulo, uhi, m, US.perm, 0u, b / kBucketsPerDim, qbeg, nq, O,
+                              s_cand[wave], s_cid[wave], s_q[wave], lane, item);
   }
 }
 
@@ -820,12 +820,17 @@ static ddm_status launch_traverse(const MatchPlan& P, const TreeDev& T, const fl
     DDM_LAUNCHED("lane_kernel");
   } else {
     ProfScope ps(FILL ? (US.qpt == 1 ? "traverse_tile1_fill" : "traverse_tile_fill")
-                      : "traverse_tile_count", s);
+                      : (O.skey && US.tmap ? "traverse_tile_count_stash" : "traverse_tile_count"),
+                 s);
     if (US.tmap) {
       // at most one partial tile per bucket
       const uint32_t tiles = (US.total + 63u) / 64u + std::min<uint32_t>(US.total, kBuckets);
       const uint32_t grid = (tiles + kTileWaves - 1) / kTileWaves;
-      tile_bucket_kernel<D, FILL><<<grid, kTileWaves * kWave, 0, s>>>(T, ulo, uhi, m, US, O);
+      if (!FILL && O.skey)
+        tile_bucket_kernel<D, false, true><<<grid, kTileWaves * kWave, 0, s>>>(T, ulo, uhi, m,
+                                                                              US, O);
+      else
+        tile_bucket_kernel<D, FILL><<<grid, kTileWaves * kWave, 0, s>>>(T, ulo, uhi, m, US, O);
       DDM_LAUNCHED("tile_bucket_kernel");
     } else {
       const uint32_t tiles = (US.total + US.qpt - 1) / US.qpt + D;
@@ -901,7 +906,20 @@ struct MatchState {
   // bucket-aligned tiles
   uint32_t* tprefix = nullptr;
   uint32_t* tmap = nullptr;
-  explicit MatchState(hipStream_t s) : sc(s), slots_sc(s) {}
+  // stash of the count traversal (plain path, d > 1): usable when complete
+  Scratch stash_sc;
+  bool stash = false;
+  uint64_t* skey = nullptr;
+  uint32_t* srank = nullptr;
+  uint32_t* sused = nullptr;
+  uint32_t* snext = nullptr;
+  uint32_t smax = 0;
+  uint32_t sfirst = 0;
+  uint32_t sslice = 0;
+  uint32_t stiles = 0;     // tiles that ran
+  uint32_t sused_max = 0;  // most counted chunks used in one slice
+  bool stash_ok = false;
+  explicit MatchState(hipStream_t s) : sc(s), slots_sc(s), stash_sc(s) {}
   UpdSet all() const {
     UpdSet U{perm, gstart, gcount, m, 64};
     U.boff = bhist;
@@ -977,10 +995,90 @@ __global__ void learned_words_kernel(const uint32_t* __restrict__ govf,
   }
 }
 
+__global__ void stash_init_kernel(uint32_t* __restrict__ snext, uint32_t sfirst,
+                                  uint32_t sslice) {
+  const uint32_t t = threadIdx.x;
+  if (t < kStashSlices) snext[t] = sfirst + t * sslice;
+  if (t == kStashSlices) snext[t] = 0;
+}
+
+// dst[2] = (tiles << 32) | most counted chunks used in a slice,
+// dst[3] = overflow
+__global__ void stash_words_kernel(const uint32_t* __restrict__ snext,
+                                   const uint32_t* __restrict__ tprefix, uint32_t sfirst,
+                                   uint32_t sslice, uint64_t* __restrict__ dst) {
+  if (threadIdx.x == 0) {
+    uint32_t mx = 0;
+    for (uint32_t s = 0; s < kStashSlices; ++s)
+      mx = max(mx, min(snext[s] - (sfirst + s * sslice), sslice));
+    dst[2] = ((uint64_t)tprefix[kBuckets] << 32) | mx;
+    dst[3] = snext[kStashSlices];
+  }
+}
+
+// stashed hits to their final places: out[off[j] + rank] (the same places
+// the fill traversal gives them).  Thread e covers entry e of the static
+// chunks of the `tiles` tiles that ran, then, slice by slice, the first
+// `used` counted chunks of each slice.
+__global__ void stash_scatter_kernel(const uint64_t* __restrict__ skey,
+                                     const uint32_t* __restrict__ srank,
+                                     const uint32_t* __restrict__ sused,
+                                     const uint32_t* __restrict__ snext, uint32_t tiles,
+                                     uint32_t sfirst, uint32_t sslice, uint32_t used,
+                                     const uint64_t* __restrict__ off, uint32_t m,
+                                     uint64_t* __restrict__ out) {
+  const uint64_t e0 = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const uint64_t nstatic = (uint64_t)tiles * kStashStatic * kStashChunk;
+  uint64_t e;
+  if (e0 < nstatic) {
+    e = e0;
+  } else {
+    if (used == 0) return;
+    const uint64_t r = e0 - nstatic, per = (uint64_t)used * kStashChunk;
+    const uint32_t sl = (uint32_t)(r / per);
+    if (sl >= kStashSlices) return;
+    const uint32_t c = sfirst + sl * sslice + (uint32_t)((r % per) / kStashChunk);
+    if (c >= snext[sl]) return;
+    e = (uint64_t)c * kStashChunk + r % kStashChunk;
+  }
+  const uint32_t c = (uint32_t)(e / kStashChunk);
+  if ((uint32_t)(e % kStashChunk) >= sused[c]) return;
+  const uint64_t key = skey[e];
+  const uint32_t j = (uint32_t)(key >> 32);
+  if (j >= m) return;
+  const uint64_t dst = off[j] + srank[e];
+  if (dst < off[j + 1]) out[dst] = key;
+}
+
+// at most 2^28 stashed hits (4 GiB of stash); larger results overflow it and
+// take the fill traversal
+constexpr uint64_t kStashMaxEntries = 1ull << 28;
+
+// stash entries: the hint (a caller's capacity) or 4 per update, plus one
+// chunk per possible tile (a tile's last chunk is partly used; the bound is
+// the launch's own: one tile per 64 updates plus one partial tile per
+// bucket), plus 64Ki
+static uint64_t stash_tiles(uint32_t m) {
+  return (m + 63u) / 64u + std::min<uint64_t>(m, kBuckets);
+}
+// counted chunks per slice: room for the hint (or 4 hits per update) plus
+// one partly used chunk per tile and 1024 more, over the slices
+static uint32_t stash_slice(uint32_t m, uint64_t hint) {
+  const uint64_t dyn = std::min<uint64_t>(std::max<uint64_t>(hint, 4ull * m), kStashMaxEntries);
+  const uint64_t c = (dyn + kStashChunk - 1) / kStashChunk + stash_tiles(m) + 1024;
+  return (uint32_t)((c + kStashSlices - 1) / kStashSlices);
+}
+
+size_t match_stash_bytes(uint32_t m) {
+  const uint64_t c = stash_tiles(m) * kStashStatic + (uint64_t)stash_slice(m, 0) * kStashSlices;
+  return (size_t)(c * kStashChunk * 12 + c * 4 + 1024);
+}
+
 static ddm_status front_half(const ddm_tree* t, const float* ulo, const float* uhi, uint32_t m,
                              const MatchPlan& P, MatchState& st, uint32_t* counts_out,
                              uint32_t** lists, uint32_t** lists_count, hipStream_t s,
-                             const ddm_predictor* pred = nullptr, uint64_t budget = 0) {
+                             const ddm_predictor* pred = nullptr, uint64_t budget = 0,
+                             bool want_stash = false, uint64_t stash_hint = 0) {
   const uint32_t d = tree_d(t);
   const TreeDev T = tree_dev(t);
   Scratch& sc = st.sc;
@@ -1107,6 +1205,37 @@ static ddm_status front_half(const ddm_tree* t, const float* ulo, const float* u
   } else if (d > 1) {
     SegOut O{};
     O.cnt = st.cnt;
+    st.stash = want_stash && !counts_out && P.traversal == DDM_TRAVERSE_TILE;
+    if (st.stash) {
+      // the count traversal also keeps every hit, so that no fill traversal
+      // is needed when they all fit; without the memory it only counts
+      st.sfirst = (uint32_t)(stash_tiles(m) * kStashStatic);
+      st.sslice = stash_slice(m, stash_hint);
+      st.smax = st.sfirst + st.sslice * kStashSlices;
+      const uint64_t e = (uint64_t)st.smax * kStashChunk;
+      st.stash_sc.reserve(sizeof(uint64_t) * e);
+      st.stash_sc.reserve(sizeof(uint32_t) * e);
+      st.stash_sc.reserve(sizeof(uint32_t) * st.smax);
+      st.stash_sc.reserve(sizeof(uint32_t) * (kStashSlices + 1));
+      if (!st.stash_sc.commit()) {
+        set_detail("");
+        st.stash = false;
+      } else {
+        st.skey = st.stash_sc.take<uint64_t>(e);
+        st.srank = st.stash_sc.take<uint32_t>(e);
+        st.sused = st.stash_sc.take<uint32_t>(st.smax);
+        st.snext = st.stash_sc.take<uint32_t>(kStashSlices + 1);
+        if (!st.stash_sc.fits()) return scratch_overrun("stash");
+        stash_init_kernel<<<1, 64, 0, s>>>(st.snext, st.sfirst, st.sslice);
+        DDM_LAUNCHED("stash_init_kernel");
+        O.skey = st.skey;
+        O.srank = st.srank;
+        O.sused = st.sused;
+        O.snext = st.snext;
+        O.sfirst = st.sfirst;
+        O.sslice = st.sslice;
+      }
+    }
     r = traverse_any<false>(d, P, T, ulo, uhi, m, st.all(), st.kstar, O, s);
     if (r != DDM_OK) return r;
     counts = st.cnt;
@@ -1119,6 +1248,10 @@ static ddm_status front_half(const ddm_tree* t, const float* ulo, const float* u
   if (r != DDM_OK) return r;
   gather_flags_kernel<<<1, 64, 0, s>>>(tree_flag(t), st.flag, st.off, m, dwords);
   DDM_LAUNCHED("gather_flags_kernel");
+  if (st.stash) {
+    stash_words_kernel<<<1, 64, 0, s>>>(st.snext, st.tprefix, st.sfirst, st.sslice, dwords);
+    DDM_LAUNCHED("stash_words_kernel");
+  }
   if (st.learned) {
     overflow_kernel<<<(m + 255) / 256, 256, 0, s>>>(st.all(), d, SO, st.cnt, st.perm_ovf,
                                                     st.govf);
@@ -1136,6 +1269,11 @@ static ddm_status front_half(const ddm_tree* t, const float* ulo, const float* u
   if (st.learned) {
     st.novf = (uint32_t)hw[2];
     st.slots_total = hw[3];
+  }
+  if (st.stash) {
+    st.stash_ok = hw[3] == 0;
+    st.stiles = (uint32_t)(hw[2] >> 32);
+    st.sused_max = (uint32_t)hw[2];
   }
   if (flags & 0xffffffffull) {
     set_detail("subscription coordinates: NaN/inf or lo > hi");
@@ -1254,10 +1392,22 @@ struct ddm_pending {
   explicit ddm_pending(hipStream_t st_) : st(st_), s(st_) {}
 };
 
+static ddm_status match_begin(const ddm_tree* t, const float* upd_lo, const float* upd_hi,
+                              uint32_t m, uint64_t* out_count, void* stream,
+                              const ddm_match_opts* opts, ddm_pending** out_pending,
+                              bool want_stash, uint64_t stash_hint);
+
 extern "C" ddm_status ddm_match_begin(const ddm_tree* t, const float* upd_lo,
                                       const float* upd_hi, uint32_t m, uint64_t* out_count,
                                       void* stream, const ddm_match_opts* opts,
                                       ddm_pending** out_pending) {
+  return match_begin(t, upd_lo, upd_hi, m, out_count, stream, opts, out_pending, true, 0);
+}
+
+static ddm_status match_begin(const ddm_tree* t, const float* upd_lo, const float* upd_hi,
+                              uint32_t m, uint64_t* out_count, void* stream,
+                              const ddm_match_opts* opts, ddm_pending** out_pending,
+                              bool want_stash, uint64_t stash_hint) {
   set_detail("");
   if (!out_count || !out_pending) {
     set_detail("out_count / out_pending is NULL");
@@ -1282,7 +1432,8 @@ extern "C" ddm_status ddm_match_begin(const ddm_tree* t, const float* upd_lo,
   pd->ulo = upd_lo;
   pd->uhi = upd_hi;
   pd->m = m;
-  r = front_half(t, upd_lo, upd_hi, m, P, pd->st, nullptr, &pd->lists, &pd->lists_count, s);
+  r = front_half(t, upd_lo, upd_hi, m, P, pd->st, nullptr, &pd->lists, &pd->lists_count, s,
+                 nullptr, 0, want_stash, stash_hint);
   if (r != DDM_OK) {
     delete pd;
     return r;
@@ -1397,6 +1548,17 @@ extern "C" ddm_status ddm_match_finish(ddm_pending* pd, uint64_t* out_pairs, uin
         r = traverse_any<true>(tree_d(pd->t), TP, T, pd->ulo, pd->uhi, pd->m, OV, st.kstar, O,
                                pd->s);
       }
+    } else if (st.stash_ok) {
+      ProfScope ps("stash_scatter", pd->s);
+      const uint64_t n = ((uint64_t)st.stiles * kStashStatic +
+                          (uint64_t)st.sused_max * kStashSlices) * kStashChunk;
+      if (n > 0) {
+        stash_scatter_kernel<<<(unsigned)((n + 255) / 256), 256, 0, pd->s>>>(
+            st.skey, st.srank, st.sused, st.snext, st.stiles, st.sfirst, st.sslice,
+            st.sused_max, st.off, pd->m, out_pairs);
+        const hipError_t le = hipGetLastError();
+        if (le != hipSuccess) r = hip_fail(le, "stash_scatter_kernel", __FILE__, __LINE__);
+      }
     } else {
       r = traverse_any<true>(tree_d(pd->t), pd->plan, T, pd->ulo, pd->uhi, pd->m, st.all(),
                              st.kstar, O, pd->s);
@@ -1425,7 +1587,10 @@ extern "C" ddm_status ddm_match_ex(const ddm_tree* t, const float* upd_lo, const
                                    uint64_t* out_count, void* stream,
                                    const ddm_match_opts* opts) {
   ddm_pending* pd = nullptr;
-  ddm_status r = ddm_match_begin(t, upd_lo, upd_hi, m, out_count, stream, opts, &pd);
+  // the capacity sizes the count traversal's stash (none for a size query,
+  // nor for capacities beyond what a stash may hold)
+  ddm_status r = match_begin(t, upd_lo, upd_hi, m, out_count, stream, opts, &pd,
+                             capacity > 0 && capacity <= kStashMaxEntries, capacity);
   if (r != DDM_OK) return r;
   if (*out_count > capacity) {
     ddm_match_abort(pd);

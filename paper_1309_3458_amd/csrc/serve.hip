@@ -140,6 +140,7 @@ struct ddm_server {
 
 namespace ddm {
 size_t tree_bytes_estimate(uint32_t n, uint32_t d);
+size_t match_stash_bytes(uint32_t m);
 }
 
 using namespace ddm;
@@ -149,10 +150,12 @@ namespace {
 uint64_t admission_bytes(const ddm_request& r, bool build) {
   // inputs (already in device memory, held until the request completes),
   // the tree unless it is resident, and the match scratch (per update: probe
-  // words, order, counts, offsets, lists; plus the bucket tables)
+  // words, order, counts, offsets, lists; plus the bucket tables; and the
+  // count traversal's stash of hits)
   uint64_t b = 8ull * r.d * ((uint64_t)r.n + r.m);
   if (build) b += tree_bytes_estimate(r.n, r.d);
   b += 64ull * r.m + (1u << 20);
+  if (r.d > 1) b += match_stash_bytes(r.m);
   return b;
 }
 

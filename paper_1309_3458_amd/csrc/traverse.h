@@ -104,12 +104,32 @@ struct UpdSet {
 // segment end: base[j+1] (final offsets, cap == nullptr) or
 // min(base[j] + cap[j], limit) (slots of the single-pass form); with cnt
 // non-null the total number of hits (written or not) is stored in cnt[j].
+// COUNT with a stash (skey non-null, tile traversal only): every hit is also
+// appended, with its rank among its update's hits, to chunks of kStashChunk
+// entries.  Tile t owns chunks kStashStatic*t .. +kStashStatic-1 (no atomic
+// for tiles with few hits); further chunks come from the slice
+// t % kStashSlices of the counted chunks: slice s spans sslice chunks from
+// sfirst + s*sslice and snext[s] is its next free chunk (separate counters,
+// so that tiles do not queue on one address).  snext[kStashSlices] becomes
+// non-zero once a slice is used up (the stash is then incomplete and the
+// counts alone are valid).  sused[c] = entries written in chunk c; every
+// tile writes it for each of its static chunks.
+constexpr uint32_t kStashChunk = 64;
+constexpr uint32_t kStashStatic = 2;
+constexpr uint32_t kStashSlices = 32;
+
 struct SegOut {
   const uint64_t* base;
   const uint32_t* cap;
   uint64_t limit;
   uint32_t* cnt;
   uint64_t* out;
+  uint64_t* skey = nullptr;
+  uint32_t* srank = nullptr;
+  uint32_t* sused = nullptr;
+  uint32_t* snext = nullptr;
+  uint32_t sfirst = 0;
+  uint32_t sslice = 0;
 };
 
 __device__ __forceinline__ bool upd_index(const UpdSet& U, uint32_t t, uint32_t d,
@@ -175,13 +195,14 @@ __device__ __forceinline__ uint32_t wave_max_u32(uint32_t v) {
 // qoff is subtracted to index the instance's coordinates), probe dimension k
 // of tree set T.  LDS per wavefront: s_cand [2D][kRing] floats, s_cid
 // [kRing], s_q [64][RV] float4.
-template <int D, bool FILL>
+template <int D, bool FILL, bool STASH = false>
 __device__ __forceinline__ void tile_body(const TreeDev& T, const float* __restrict__ ulo,
                                           const float* __restrict__ uhi, uint32_t m,
                                           const uint32_t* __restrict__ perm, uint32_t qoff,
                                           uint32_t k, uint32_t qbeg, uint32_t nq, const SegOut& O,
                                           float* __restrict__ s_cand, uint32_t* __restrict__ s_cid,
-                                          float4* __restrict__ s_q, uint32_t lane) {
+                                          float4* __restrict__ s_q, uint32_t lane,
+                                          uint32_t tile_id = 0) {
   constexpr int R = 2 * D;
   constexpr int RV = (R + 3) / 4;
   const bool qv = lane < nq;
@@ -242,6 +263,12 @@ __device__ __forceinline__ void tile_body(const TreeDev& T, const float* __restr
   const float* __restrict__ bmx = T.bmax[k];
   const uint32_t* __restrict__ ids = T.id[k];
   uint32_t head = 0, tail = 0;
+  // stash chunk of the wave (uniform): id, entries used, last static chunk,
+  // still stashing
+  uint32_t sch = tile_id * kStashStatic, sfill = 0;
+  const uint32_t slast = sch + kStashStatic - 1;
+  bool sok = STASH;
+  uint64_t myhm = 0;  // this lane's update: hits among the flushed candidates
 
   auto flush = [&](uint32_t c) {
     wave_sync();
@@ -286,10 +313,75 @@ __device__ __forceinline__ void tile_body(const TreeDev& T, const float* __restr
             const uint64_t dst = b + mask_rank(hm[u]);
             if (((hm[u] >> lane) & 1ull) && dst < e) out[dst] = jq | sid;
             if (lane == qq) mybase += pc;
+          } else if constexpr (STASH) {
+            if (lane == qq) myhm = hm[u];
           } else {
             if (lane == qq) mycnt += pc;
           }
         }
+      }
+    }
+    if constexpr (STASH) {
+      // each lane stashes its own update's hits among these candidates: a
+      // wave prefix of the hit counts places them, one chunk request (if
+      // any) covers the whole flush (most flushes have no hit at all)
+      if (ballot(myhm != 0) != 0) {
+        const uint32_t pcl = (uint32_t)__popcll(myhm);
+        uint32_t incl = pcl;
+#pragma unroll
+        for (int o = 1; o < kWave; o <<= 1) {
+          const uint32_t t = (uint32_t)__shfl_up((int)incl, o, kWave);
+          if (lane >= (uint32_t)o) incl += t;
+        }
+        const uint32_t tot = (uint32_t)__builtin_amdgcn_readlane((int)incl, kWave - 1);
+        if (tot > 0 && sok) {
+          const uint32_t room = kStashChunk - sfill;
+          uint32_t first = 0, nnew = 0;
+          if (room < tot) {
+            // hits beyond the current chunk go to consecutive new ones: the
+            // tile's next static chunks, else counted ones (the static
+            // chunks left over are then marked empty)
+            nnew = (tot - room + kStashChunk - 1) / kStashChunk;
+            if (sch + nnew <= slast) {
+              first = sch + 1;
+            } else {
+              const uint32_t sl = tile_id % kStashSlices;
+              const uint32_t send = O.sfirst + (sl + 1) * O.sslice;
+              uint32_t f = 0;
+              if (lane == 0) f = atomicAdd(O.snext + sl, nnew);
+              first = uniform_u32(f);
+              if (sch < slast && lane < slast - sch) O.sused[sch + 1 + lane] = 0;
+              if (first >= send || nnew > send - first) {
+                sok = false;
+                if (lane == 0) atomicOr(O.snext + kStashSlices, 1u);
+              }
+            }
+          }
+          if (sok) {
+            uint64_t hv = myhm;
+            uint32_t v = incl - pcl, r = mycnt;
+            while (hv) {
+              const uint32_t ci = (uint32_t)__builtin_ctzll(hv);
+              hv &= hv - 1;
+              const uint64_t e = v < room ? (uint64_t)sch * kStashChunk + sfill + v
+                                          : (uint64_t)first * kStashChunk + (v - room);
+              O.skey[e] = jhi | s_cid[(head + ci) & (kRing - 1)];
+              O.srank[e] = r;
+              ++v;
+              ++r;
+            }
+            if (nnew) {
+              if (lane == 0) O.sused[sch] = kStashChunk;
+              if (lane + 1 < nnew) O.sused[first + lane] = kStashChunk;
+              sch = first + nnew - 1;
+              sfill = tot - room - (nnew - 1) * kStashChunk;
+            } else {
+              sfill += tot;
+            }
+          }
+        }
+        mycnt += pcl;
+        myhm = 0;
       }
     }
     head += c;
@@ -348,6 +440,10 @@ __device__ __forceinline__ void tile_body(const TreeDev& T, const float* __restr
       }
     }
     if (tail != head) flush(tail - head);
+  }
+  if (STASH && sok) {
+    if (lane == 0) O.sused[sch] = sfill;
+    if (sch < slast && lane < slast - sch) O.sused[sch + 1 + lane] = 0;
   }
   if (qv) {
     if (!FILL) O.cnt[gj] = mycnt;
