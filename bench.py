@@ -110,13 +110,13 @@ def candidates(inst):
     return float(c.sum())
 
 
-# Calibrated FETCH_SIZE + WRITE_SIZE of the fill traversal at the default
+# Calibrated FETCH_SIZE + WRITE_SIZE of the dominant traversal at the default
 # workload, bytes per launch, keyed (workload, path, kernel); valid for the
 # version of the tile traversal the counters were taken on
 # (profiles/traffic_d2_N1e6_alpha1_pmc.md): FETCH_SIZE x 2.000 and
 # WRITE_SIZE x 1.000, the factors a 1 GiB device copy calibrates.
-TRAFFIC_BYTES = {("d2_N1e6_alpha1_uniform", "plain", "traverse_tile_fill"):
-                 (160250.4 * 2.0 + 29371.5 * 1.0) * 1024}
+TRAFFIC_BYTES = {("d2_N1e6_alpha1_uniform", "plain", "traverse_tile_count_stash"):
+                 (133248.1 * 2.0 + 33213.9 * 1.0) * 1024}
 
 
 def roofline_alu(cand, ops, dom, dom_avg_ms, traffic=None):
