@@ -325,6 +325,19 @@ ddm_status radix_sort_batch(const SortArr* arrs_dev, uint32_t narr, const uint32
 ddm_status sort_setup_small(const SortArr* host_arrs, uint32_t narr, SortArr* arrs_dev,
                             uint32_t* tile_map, uint32_t ntiles, hipStream_t s);
 
+// one-sweep radix sort (stable LSD, 8-bit digits) of 1..kOsMaxArrays arrays
+// whose sizes the host knows (host_arrs: k[0]/v[0] hold the input, k[1]/v[1]
+// the second buffers; v may be null): one zeroing and one histogram kernel,
+// then one kernel per pass; the result ends in k[npasses & 1] / v[...].
+// scratch: radix_onesweep_scratch_bytes(...) bytes of device memory; err: a
+// device word that receives kFlagSortTimeout if a look-back wait gave up
+// (the order is then wrong).
+constexpr uint32_t kOsMaxArrays = 2 * DDM_MAX_D;
+constexpr int32_t kFlagSortTimeout = 0x40000000;
+size_t radix_onesweep_scratch_bytes(const SortArr* host_arrs, uint32_t narr, int npasses);
+ddm_status radix_sort_onesweep(const SortArr* host_arrs, uint32_t narr, int npasses,
+                               void* scratch, int32_t* err, hipStream_t s);
+
 // per-segment sort of the pairs in place (segments off[j] .. off[j+1]);
 // ids must be below 2^20.  lists: 2m+2 uint32 scratch (last two words are
 // counters, zeroed by the caller beforehand).

@@ -1275,6 +1275,10 @@ static ddm_status front_half(const ddm_tree* t, const float* ulo, const float* u
     st.stiles = (uint32_t)(hw[2] >> 32);
     st.sused_max = (uint32_t)hw[2];
   }
+  if (flags & (uint64_t)(uint32_t)kFlagSortTimeout) {
+    set_detail("tree build: a radix sort look-back wait gave up");
+    return DDM_E_DEVICE;
+  }
   if (flags & 0xffffffffull) {
     set_detail("subscription coordinates: NaN/inf or lo > hi");
     return DDM_E_INVALID_INPUT;

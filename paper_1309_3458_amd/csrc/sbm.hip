@@ -211,14 +211,14 @@ extern "C" ddm_status ddm_match_sbm(const float* sub_lo, const float* sub_hi, ui
   if (n == 0 || m == 0) return DDM_OK;
   hipStream_t s = (hipStream_t)stream;
   const uint32_t B = (n + kSbmSeg - 1) / kSbmSeg;
-  const uint32_t tn = (n + kSortTile - 1) / kSortTile, tm = (m + kSortTile - 1) / kSortTile;
-  const uint32_t ntiles = 2 * tn + tm;
+  SortArr host[3] = {SortArr{{nullptr, nullptr}, {nullptr, nullptr}, n, 0},
+                     SortArr{{nullptr, nullptr}, {nullptr, nullptr}, n, 0},
+                     SortArr{{nullptr, nullptr}, {nullptr, nullptr}, m, 0}};
+  const size_t sort_bytes = radix_onesweep_scratch_bytes(host, 3, 4);
   Scratch sc(s);
   for (int i = 0; i < 6; ++i) sc.reserve(sizeof(uint32_t) * n);  // lower keys, ids, upper keys
   for (int i = 0; i < 4; ++i) sc.reserve(sizeof(uint32_t) * m);  // update keys, ids
-  sc.reserve(sizeof(SortArr) * 3);
-  sc.reserve(sizeof(uint32_t) * ntiles);
-  sc.reserve(sizeof(uint32_t) * 256 * (size_t)ntiles);
+  sc.reserve(sort_bytes);
   sc.reserve(sizeof(float) * 2 * (size_t)d * n);
   sc.reserve(sizeof(uint32_t) * B);  // acnt
   sc.reserve(sizeof(uint32_t) * B);  // acur
@@ -237,9 +237,7 @@ extern "C" ddm_status ddm_match_sbm(const float* sub_lo, const float* sub_hi, ui
   uint32_t* khi[2] = {sc.take<uint32_t>(n), sc.take<uint32_t>(n)};
   uint32_t* ukey[2] = {sc.take<uint32_t>(m), sc.take<uint32_t>(m)};
   uint32_t* uid[2] = {sc.take<uint32_t>(m), sc.take<uint32_t>(m)};
-  SortArr* arrs = sc.take<SortArr>(3);
-  uint32_t* tile_map = sc.take<uint32_t>(ntiles);
-  uint32_t* hist = sc.take<uint32_t>(256 * (size_t)ntiles);
+  char* sort_scratch = sc.take<char>(sort_bytes);
   float* rec = sc.take<float>(2 * (size_t)d * n);
   uint32_t* acnt = sc.take<uint32_t>(B);
   uint32_t* acur = sc.take<uint32_t>(B);
@@ -268,13 +266,10 @@ extern "C" ddm_status ddm_match_sbm(const float* sub_lo, const float* sub_hi, ui
   // the sorted endpoint list: lower and upper endpoints of the subscriptions
   // (ties of the lower keys broken by id: the radix sort is stable) and the
   // updates' lower endpoints, which give the order of the update lanes
-  SortArr host[3];
   host[0] = SortArr{{klo[0], klo[1]}, {kid[0], kid[1]}, n, 0};
-  host[1] = SortArr{{khi[0], khi[1]}, {nullptr, nullptr}, n, tn};
-  host[2] = SortArr{{ukey[0], ukey[1]}, {uid[0], uid[1]}, m, 2 * tn};
-  ddm_status r = sort_setup_small(host, 3, arrs, tile_map, ntiles, s);
-  if (r != DDM_OK) return r;
-  r = radix_sort_batch(arrs, 3, tile_map, ntiles, hist, 0, 4, s);
+  host[1] = SortArr{{khi[0], khi[1]}, {nullptr, nullptr}, n, 0};
+  host[2] = SortArr{{ukey[0], ukey[1]}, {uid[0], uid[1]}, m, 0};
+  ddm_status r = radix_sort_onesweep(host, 3, 4, sort_scratch, flag, s);
   if (r != DDM_OK) return r;
   {
     ProfScope ps("sbm_segments", s);
@@ -290,6 +285,10 @@ extern "C" ddm_status ddm_match_sbm(const float* sub_lo, const float* sub_hi, ui
   uint64_t h[2] = {0, 0};
   DDM_HIP(hipMemcpyAsync(h, words, sizeof(h), hipMemcpyDeviceToHost, s));
   DDM_HIP(hipStreamSynchronize(s));
+  if (h[1] & (uint32_t)kFlagSortTimeout) {
+    set_detail("ddm_match_sbm: a radix sort look-back wait gave up");
+    return DDM_E_DEVICE;
+  }
   if (h[1]) {
     set_detail(h[1] & 1 ? "subscription coordinates: NaN/inf or lo > hi"
                         : "update coordinates: NaN/inf or lo > hi");

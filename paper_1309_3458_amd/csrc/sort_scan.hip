@@ -8,6 +8,8 @@
 // are ordered through LDS counters, which keeps the sort stable.
 #include "ddm_internal.h"
 
+#include <algorithm>
+
 namespace ddm {
 
 // ---------------------------------------------------------------------------
@@ -206,6 +208,242 @@ ddm_status sort_setup_small(const SortArr* host_arrs, uint32_t narr, SortArr* ar
   const uint32_t cnt = ntiles > narr ? ntiles : narr;
   sort_setup_kernel<<<(cnt + 255) / 256, 256, 0, s>>>(D, arrs_dev, tile_map, ntiles);
   DDM_LAUNCHED("sort_setup_kernel");
+  return DDM_OK;
+}
+
+// ---------------------------------------------------------------------------
+// one-sweep radix sort of a few arrays with host-known sizes
+//
+// The digit totals of every pass come from one histogram kernel (they do not
+// depend on the order of the keys).  Each pass is then one kernel: a tile
+// (2048 keys, 512 per wavefront in order) ranks its keys with per-wavefront
+// digit counters (no workgroup barrier per round), publishes its digit
+// counts, and takes the counts of the tiles before it in the same array by
+// decoupled look-back: each digit walks back over the tiles' published
+// (flag, count) words until one holds an inclusive prefix.  Tiles take their
+// index from a counter in the order they start, so every tile they wait for
+// has started and publishes without waiting on later tiles.  A wait longer
+// than kOsSpinLimit sleeps gives up, raises kFlagSortTimeout in *err and
+// goes on with a wrong offset, so that every wave still exits.
+// ---------------------------------------------------------------------------
+constexpr uint32_t kOsHistKeys = 16384;  // keys per workgroup of the histogram kernel
+constexpr uint64_t kOsAgg = 1ull << 32, kOsIncl = 2ull << 32;
+constexpr uint32_t kOsSpinLimit = 1u << 22;
+
+struct OsDesc {
+  SortArr a[kOsMaxArrays];
+  uint32_t narr;
+  uint32_t hblk0[kOsMaxArrays + 1];  // first histogram workgroup of each array
+  uint32_t tile0[kOsMaxArrays + 1];  // first tile of each array
+};
+
+__device__ __forceinline__ uint32_t os_array(const uint32_t* first, uint32_t narr, uint32_t x) {
+  uint32_t a = 0;
+  for (uint32_t q = 1; q < narr; ++q)
+    if (first[q] <= x) a = q;
+  return a;
+}
+
+__global__ void os_zero_kernel(uint32_t* __restrict__ ghist, uint32_t nh,
+                               uint32_t* __restrict__ ctr, uint64_t* __restrict__ status,
+                               size_t nstatus) {
+  const size_t g = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const size_t stride = (size_t)gridDim.x * blockDim.x;
+  for (size_t i = g; i < nh; i += stride) ghist[i] = 0;
+  for (size_t i = g; i < nstatus; i += stride) status[i] = 0;
+  if (g < 4) ctr[g] = 0;
+}
+
+__global__ __launch_bounds__(kSortThreads) void os_hist_kernel(OsDesc D, uint32_t* __restrict__ ghist,
+                                                               int npasses) {
+  __shared__ uint32_t h[4][256];
+  const uint32_t tid = threadIdx.x;
+#pragma unroll
+  for (int p = 0; p < 4; ++p) h[p][tid] = 0;
+  __syncthreads();
+  const uint32_t a = os_array(D.hblk0, D.narr, blockIdx.x);
+  const SortArr& A = D.a[a];
+  const uint32_t begin = (blockIdx.x - D.hblk0[a]) * kOsHistKeys;
+  const uint32_t end = min(A.n, begin + kOsHistKeys);
+  const uint32_t* __restrict__ src = A.k[0];
+  for (uint32_t i = begin + tid; i < end; i += kSortThreads) {
+    const uint32_t k = src[i];
+    for (int p = 0; p < npasses; ++p) atomicAdd(&h[p][(k >> (8 * p)) & 255u], 1u);
+  }
+  __syncthreads();
+  for (int p = 0; p < npasses; ++p) {
+    const uint32_t c = h[p][tid];
+    if (c) atomicAdd(&ghist[((size_t)a * 4 + p) * 256 + tid], c);
+  }
+}
+
+__global__ __launch_bounds__(kSortThreads) void os_pass_kernel(OsDesc D,
+                                                               const uint32_t* __restrict__ ghist,
+                                                               uint32_t* __restrict__ ctr,
+                                                               uint64_t* __restrict__ status,
+                                                               uint32_t ntiles, int pass,
+                                                               int32_t* __restrict__ err) {
+  constexpr uint32_t W = kSortThreads / kWave;
+  constexpr uint32_t R = kSortTile / kSortThreads;  // keys per lane
+  __shared__ uint32_t s_t;
+  __shared__ uint32_t wcnt[W][256];
+  __shared__ uint32_t woff[W][256];
+  __shared__ uint32_t wsum[W];
+  const uint32_t tid = threadIdx.x, wave = tid / kWave, lane = lane_id();
+  if (tid == 0) s_t = atomicAdd(ctr + pass, 1u);
+  for (uint32_t i = lane; i < 256; i += kWave) wcnt[wave][i] = 0;
+  __syncthreads();
+  const uint32_t t = s_t;
+  const uint32_t a = os_array(D.tile0, D.narr, t);
+  const SortArr& A = D.a[a];
+  const uint32_t lt = t - D.tile0[a];
+  const uint32_t* __restrict__ ks = A.k[pass & 1];
+  uint32_t* __restrict__ kd = A.k[(pass & 1) ^ 1];
+  const uint32_t* __restrict__ vs = A.v[pass & 1];
+  uint32_t* __restrict__ vd = A.v[(pass & 1) ^ 1];
+  const uint32_t base = lt * kSortTile + wave * (R * kWave);
+  const uint32_t shift = 8u * (uint32_t)pass;
+  uint32_t key[R], val[R], loc[R];
+#pragma unroll
+  for (uint32_t r = 0; r < R; ++r) {
+    const uint32_t i = base + r * kWave + lane;
+    const bool valid = i < A.n;
+    key[r] = valid ? ks[i] : 0u;
+    val[r] = (valid && vs) ? vs[i] : 0u;
+  }
+  // ranks inside the wavefront's 512 keys, in key order (stable)
+#pragma unroll
+  for (uint32_t r = 0; r < R; ++r) {
+    const bool valid = base + r * kWave + lane < A.n;
+    const uint32_t dig = (key[r] >> shift) & 255u;
+    const uint64_t peers = match_digit8(dig, ballot(valid));
+    const uint32_t rk = mask_rank(peers);
+    const uint32_t b = valid ? wcnt[wave][dig] : 0u;
+    loc[r] = b + rk;
+    if (valid && rk == 0) wcnt[wave][dig] = b + (uint32_t)__popcll(peers);
+  }
+  __syncthreads();
+  {
+    // thread d: the tile's count of digit d, its wavefronts' prefixes, the
+    // digit's base in the array, and the count in earlier tiles
+    const uint32_t d = tid;
+    uint32_t run = 0;
+#pragma unroll
+    for (uint32_t w = 0; w < W; ++w) {
+      const uint32_t c = wcnt[w][d];
+      woff[w][d] = run;
+      run += c;
+    }
+    const uint32_t tc = run;
+    const uint32_t g = ghist[((size_t)a * 4 + pass) * 256 + d];
+    uint32_t inc = g;
+#pragma unroll
+    for (int o = 1; o < kWave; o <<= 1) {
+      const uint32_t x = (uint32_t)__shfl_up((int)inc, o, kWave);
+      if (lane >= (uint32_t)o) inc += x;
+    }
+    if (lane == kWave - 1) wsum[wave] = inc;
+    uint64_t* __restrict__ st = status + (size_t)pass * ntiles * 256;
+    uint32_t excl = 0;
+    if (lt == 0) {
+      __hip_atomic_store(st + (size_t)t * 256 + d, kOsIncl | tc, __ATOMIC_RELAXED,
+                         __HIP_MEMORY_SCOPE_AGENT);
+    } else {
+      __hip_atomic_store(st + (size_t)t * 256 + d, kOsAgg | tc, __ATOMIC_RELAXED,
+                         __HIP_MEMORY_SCOPE_AGENT);
+      uint32_t j = t - 1, spin = 0;
+      while (true) {
+        const uint64_t v = __hip_atomic_load(st + (size_t)j * 256 + d, __ATOMIC_RELAXED,
+                                             __HIP_MEMORY_SCOPE_AGENT);
+        if ((v >> 32) == 0) {
+          if (++spin > kOsSpinLimit) {
+            atomicOr(err, kFlagSortTimeout);
+            break;
+          }
+          __builtin_amdgcn_s_sleep(1);
+          continue;
+        }
+        excl += (uint32_t)v;
+        if ((v & kOsIncl) || j == D.tile0[a]) break;
+        --j;
+      }
+      __hip_atomic_store(st + (size_t)t * 256 + d, kOsIncl | (excl + tc), __ATOMIC_RELAXED,
+                         __HIP_MEMORY_SCOPE_AGENT);
+    }
+    __syncthreads();
+    uint32_t gb = inc - g;
+    for (uint32_t w = 0; w < wave; ++w) gb += wsum[w];
+#pragma unroll
+    for (uint32_t w = 0; w < W; ++w) woff[w][d] += gb + excl;
+  }
+  __syncthreads();
+#pragma unroll
+  for (uint32_t r = 0; r < R; ++r) {
+    if (base + r * kWave + lane < A.n) {
+      const uint32_t pos = woff[wave][(key[r] >> shift) & 255u] + loc[r];
+      if (pos < A.n) {  // always, unless a look-back wait gave up
+        kd[pos] = key[r];
+        if (vd) vd[pos] = val[r];
+      }
+    }
+  }
+}
+
+static void os_layout(const SortArr* host_arrs, uint32_t narr, OsDesc* D, uint32_t* nhblk,
+                      uint32_t* ntiles) {
+  uint32_t hb = 0, tl = 0;
+  *D = OsDesc{};
+  D->narr = narr;
+  for (uint32_t i = 0; i < narr; ++i) {
+    D->a[i] = host_arrs[i];
+    D->hblk0[i] = hb;
+    D->tile0[i] = tl;
+    hb += (host_arrs[i].n + kOsHistKeys - 1) / kOsHistKeys;
+    tl += (host_arrs[i].n + kSortTile - 1) / kSortTile;
+  }
+  D->hblk0[narr] = hb;
+  D->tile0[narr] = tl;
+  *nhblk = hb;
+  *ntiles = tl;
+}
+
+size_t radix_onesweep_scratch_bytes(const SortArr* host_arrs, uint32_t narr, int npasses) {
+  OsDesc D;
+  uint32_t hb, tl;
+  os_layout(host_arrs, narr, &D, &hb, &tl);
+  return 256 + sizeof(uint32_t) * 1024 * (size_t)narr + sizeof(uint64_t) * 256 * (size_t)tl *
+                                                            (size_t)(npasses > 0 ? npasses : 1);
+}
+
+ddm_status radix_sort_onesweep(const SortArr* host_arrs, uint32_t narr, int npasses,
+                               void* scratch, int32_t* err, hipStream_t s) {
+  if (narr == 0 || narr > kOsMaxArrays || npasses < 0 || npasses > 4) {
+    set_detail("radix_sort_onesweep: 1..8 arrays, 0..4 passes");
+    return DDM_E_INVALID_ARG;
+  }
+  if (npasses == 0) return DDM_OK;
+  OsDesc D;
+  uint32_t hb, tl;
+  os_layout(host_arrs, narr, &D, &hb, &tl);
+  if (tl == 0) return DDM_OK;
+  uint32_t* ctr = (uint32_t*)scratch;  // 4 counters, padded to 256 bytes
+  uint32_t* ghist = (uint32_t*)((char*)scratch + 256);
+  uint64_t* status = (uint64_t*)(ghist + 1024 * (size_t)narr);
+  const size_t nstatus = 256 * (size_t)tl * (size_t)npasses;
+  {
+    ProfScope ps("radix_hist", s);
+    const size_t work = std::max<size_t>(nstatus, 1024 * (size_t)narr);
+    const unsigned zb = (unsigned)std::min<size_t>((work + 255) / 256, 2048);
+    os_zero_kernel<<<zb, 256, 0, s>>>(ghist, 1024 * narr, ctr, status, nstatus);
+    DDM_LAUNCHED("os_zero_kernel");
+    os_hist_kernel<<<hb, kSortThreads, 0, s>>>(D, ghist, npasses);
+    DDM_LAUNCHED("os_hist_kernel");
+  }
+  for (int p = 0; p < npasses; ++p) {
+    ProfScope ps("radix_scatter", s);
+    os_pass_kernel<<<tl, kSortThreads, 0, s>>>(D, ghist, ctr, status, tl, p, err);
+    DDM_LAUNCHED("os_pass_kernel");
+  }
   return DDM_OK;
 }
 

@@ -207,23 +207,21 @@ ddm_status enqueue_tree_build(ddm_tree* t, const float* lo, const float* hi, hip
   // upper bounds are sorted only for d == 1, where the BITS counts are the
   // final counts; for d > 1 the probe dimension comes from lower bounds only
   const bool sort_hi = d == 1;
-  const uint32_t tiles_per = (n + kSortTile - 1) / kSortTile;
   const uint32_t narr = sort_hi ? 2 * d : d;
-  const uint32_t ntiles = tiles_per * narr;
+  // the sort's arrays (buffer 1 of each is filled in once scratch exists)
+  SortArr host[2 * DDM_MAX_D];
+  for (uint32_t i = 0; i < narr; ++i) host[i] = SortArr{{nullptr, nullptr}, {nullptr, nullptr}, n, 0};
+  const size_t sort_bytes = radix_onesweep_scratch_bytes(host, narr, 4);
   Scratch sc(s);
   sc.reserve(sizeof(uint32_t) * (size_t)n * d);  // lo keys tmp
   sc.reserve(sizeof(uint32_t) * (size_t)n * d);  // hi keys tmp
   sc.reserve(sizeof(uint32_t) * (size_t)n * d);  // payload tmp
-  sc.reserve(sizeof(SortArr) * narr);
-  sc.reserve(sizeof(uint32_t) * ntiles);
-  sc.reserve(sizeof(uint32_t) * 256 * (size_t)ntiles);
+  sc.reserve(sort_bytes);
   if (!sc.commit()) return DDM_E_NOMEM;
   uint32_t* klo_tmp = sc.take<uint32_t>((size_t)n * d);
   uint32_t* khi_tmp = sc.take<uint32_t>((size_t)n * d);
   uint32_t* val_tmp = sc.take<uint32_t>((size_t)n * d);
-  SortArr* arrs = sc.take<SortArr>(narr);
-  uint32_t* tile_map = sc.take<uint32_t>(ntiles);
-  uint32_t* hist = sc.take<uint32_t>(256 * (size_t)ntiles);
+  char* sort_scratch = sc.take<char>(sort_bytes);
   if (!sc.fits()) return scratch_overrun("tree build");
 
   {
@@ -233,30 +231,19 @@ ddm_status enqueue_tree_build(ddm_tree* t, const float* lo, const float* hi, hip
         lo, hi, n, d, t->skey_lo[0], sort_hi ? t->skey_hi[0] : nullptr, t->id[0], t->flag);
     DDM_LAUNCHED("build_keys_kernel");
   }
-  SortArr host[2 * DDM_MAX_D];
   uint32_t na = 0;
   for (uint32_t k = 0; k < d; ++k) {
-    SortArr& a = host[na];
+    SortArr& a = host[na++];
     a.k[0] = t->skey_lo[k];
     a.k[1] = klo_tmp + (size_t)k * n;
     a.v[0] = t->id[k] + 1;
     a.v[1] = val_tmp + (size_t)k * n;
-    a.n = n;
-    a.tile0 = na * tiles_per;
-    ++na;
     if (!sort_hi) continue;
-    SortArr& b = host[na];
+    SortArr& b = host[na++];
     b.k[0] = t->skey_hi[k];
     b.k[1] = khi_tmp + (size_t)k * n;
-    b.v[0] = nullptr;
-    b.v[1] = nullptr;
-    b.n = n;
-    b.tile0 = na * tiles_per;
-    ++na;
   }
-  ddm_status st = sort_setup_small(host, narr, arrs, tile_map, ntiles, s);
-  if (st != DDM_OK) return st;
-  st = radix_sort_batch(arrs, narr, tile_map, ntiles, hist, 0, 4, s);
+  ddm_status st = radix_sort_onesweep(host, narr, 4, sort_scratch, t->flag, s);
   if (st != DDM_OK) return st;
   return enqueue_tree_passes(t, make_jobs(t, lo, hi), true, s);
 }
@@ -428,28 +415,20 @@ static ddm_status tree_update(ddm_tree* t, const uint32_t* ids, const float* nlo
     DDM_LAUNCHED("upd_zero_maxlen_kernel");
     if (d == 1) {
       // the upper keys stay a sorted multiset for the exact counts
-      const uint32_t tiles = (n + kSortTile - 1) / kSortTile;
+      SortArr h{{nullptr, nullptr}, {nullptr, nullptr}, n, 0};
+      const size_t sort_bytes = radix_onesweep_scratch_bytes(&h, 1, 4);
       Scratch ss(s);
       ss.reserve(sizeof(uint32_t) * n);
-      ss.reserve(sizeof(SortArr));
-      ss.reserve(sizeof(uint32_t) * tiles);
-      ss.reserve(sizeof(uint32_t) * 256 * (size_t)tiles);
+      ss.reserve(sort_bytes);
       if (!ss.commit()) return DDM_E_NOMEM;
       uint32_t* ktmp = ss.take<uint32_t>(n);
-      SortArr* arr = ss.take<SortArr>(1);
-      uint32_t* tile_map = ss.take<uint32_t>(tiles);
-      uint32_t* hist = ss.take<uint32_t>(256 * (size_t)tiles);
+      char* sort_scratch = ss.take<char>(sort_bytes);
       if (!ss.fits()) return scratch_overrun("tree update");
       upd_hi_keys_kernel<<<(n + 255) / 256, 256, 0, s>>>(t->rec[0], n, t->skey_hi[0]);
       DDM_LAUNCHED("upd_hi_keys_kernel");
-      SortArr h{};
       h.k[0] = t->skey_hi[0];
       h.k[1] = ktmp;
-      h.n = n;
-      h.tile0 = 0;
-      ddm_status st = sort_setup_small(&h, 1, arr, tile_map, tiles, s);
-      if (st != DDM_OK) return st;
-      st = radix_sort_batch(arr, 1, tile_map, tiles, hist, 0, 4, s);
+      ddm_status st = radix_sort_onesweep(&h, 1, 4, sort_scratch, t->flag, s);
       if (st != DDM_OK) return st;
       return enqueue_tree_passes(t, make_jobs(t, nullptr, nullptr), false, s);
     }
@@ -665,6 +644,10 @@ extern "C" ddm_status ddm_tree_check(const ddm_tree* t) {
   int32_t f = 0;
   DDM_HIP(hipStreamSynchronize(t->stream));
   DDM_HIP(hipMemcpy(&f, t->flag, sizeof(f), hipMemcpyDeviceToHost));
+  if (f & kFlagSortTimeout) {
+    set_detail("tree build: a radix sort look-back wait gave up");
+    return DDM_E_DEVICE;
+  }
   if (f) {
     set_detail("subscription coordinates: NaN/inf or lo > hi");
     return DDM_E_INVALID_INPUT;
