@@ -226,7 +226,8 @@ ddm_status sort_setup_small(const SortArr* host_arrs, uint32_t narr, SortArr* ar
 // than kOsSpinLimit sleeps gives up, raises kFlagSortTimeout in *err and
 // goes on with a wrong offset, so that every wave still exits.
 // ---------------------------------------------------------------------------
-constexpr uint32_t kOsHistKeys = 16384;  // keys per workgroup of the histogram kernel
+constexpr uint32_t kOsHistKeys = 4096;  // keys per workgroup of the histogram kernel
+constexpr uint32_t kOsWindow = 8;       // predecessor tiles read together in a look-back step
 constexpr uint64_t kOsAgg = 1ull << 32, kOsIncl = 2ull << 32;
 constexpr uint32_t kOsSpinLimit = 1u << 22;
 
@@ -288,7 +289,11 @@ __global__ __launch_bounds__(kSortThreads) void os_pass_kernel(OsDesc D,
   __shared__ uint32_t s_t;
   __shared__ uint32_t wcnt[W][256];
   __shared__ uint32_t woff[W][256];
-  __shared__ uint32_t wsum[W];
+  __shared__ uint32_t wsum[2][W];
+  __shared__ uint32_t ldst[256];  // first slot of each digit in the tile's staged order
+  __shared__ uint32_t gpos[256];  // where that run starts in the output
+  __shared__ uint32_t lkey[kSortTile];
+  __shared__ uint32_t lval[kSortTile];
   const uint32_t tid = threadIdx.x, wave = tid / kWave, lane = lane_id();
   if (tid == 0) s_t = atomicAdd(ctr + pass, 1u);
   for (uint32_t i = lane; i < 256; i += kWave) wcnt[wave][i] = 0;
@@ -301,7 +306,9 @@ __global__ __launch_bounds__(kSortThreads) void os_pass_kernel(OsDesc D,
   uint32_t* __restrict__ kd = A.k[(pass & 1) ^ 1];
   const uint32_t* __restrict__ vs = A.v[pass & 1];
   uint32_t* __restrict__ vd = A.v[(pass & 1) ^ 1];
-  const uint32_t base = lt * kSortTile + wave * (R * kWave);
+  const uint32_t tbase = lt * kSortTile;
+  const uint32_t tn = min(kSortTile, A.n - tbase);  // keys in this tile
+  const uint32_t base = tbase + wave * (R * kWave);
   const uint32_t shift = 8u * (uint32_t)pass;
   uint32_t key[R], val[R], loc[R];
 #pragma unroll
@@ -324,25 +331,31 @@ __global__ __launch_bounds__(kSortThreads) void os_pass_kernel(OsDesc D,
   }
   __syncthreads();
   {
-    // thread d: the tile's count of digit d, its wavefronts' prefixes, the
-    // digit's base in the array, and the count in earlier tiles
+    // thread d: the tile's count of digit d, the digit's base in the array
+    // and in the tile (scans over the digits), and the count of digit d in
+    // the array's earlier tiles (look-back)
     const uint32_t d = tid;
-    uint32_t run = 0;
+    uint32_t c[W], tc = 0;
 #pragma unroll
     for (uint32_t w = 0; w < W; ++w) {
-      const uint32_t c = wcnt[w][d];
-      woff[w][d] = run;
-      run += c;
+      c[w] = wcnt[w][d];
+      tc += c[w];
     }
-    const uint32_t tc = run;
     const uint32_t g = ghist[((size_t)a * 4 + pass) * 256 + d];
-    uint32_t inc = g;
+    uint32_t inc = g, inc2 = tc;
 #pragma unroll
     for (int o = 1; o < kWave; o <<= 1) {
       const uint32_t x = (uint32_t)__shfl_up((int)inc, o, kWave);
-      if (lane >= (uint32_t)o) inc += x;
+      const uint32_t y = (uint32_t)__shfl_up((int)inc2, o, kWave);
+      if (lane >= (uint32_t)o) {
+        inc += x;
+        inc2 += y;
+      }
     }
-    if (lane == kWave - 1) wsum[wave] = inc;
+    if (lane == kWave - 1) {
+      wsum[0][wave] = inc;
+      wsum[1][wave] = inc2;
+    }
     uint64_t* __restrict__ st = status + (size_t)pass * ntiles * 256;
     uint32_t excl = 0;
     if (lt == 0) {
@@ -351,40 +364,81 @@ __global__ __launch_bounds__(kSortThreads) void os_pass_kernel(OsDesc D,
     } else {
       __hip_atomic_store(st + (size_t)t * 256 + d, kOsAgg | tc, __ATOMIC_RELAXED,
                          __HIP_MEMORY_SCOPE_AGENT);
-      uint32_t j = t - 1, spin = 0;
-      while (true) {
-        const uint64_t v = __hip_atomic_load(st + (size_t)j * 256 + d, __ATOMIC_RELAXED,
-                                             __HIP_MEMORY_SCOPE_AGENT);
-        if ((v >> 32) == 0) {
+      // tiles j-1, j-2, ... down to the array's first tile, kOsWindow at a
+      // time (their loads are in flight together); a tile that has not
+      // published yet is read again
+      const uint32_t first = D.tile0[a];
+      uint32_t j = t, spin = 0;
+      bool done = false;
+      while (!done) {
+        uint64_t v[kOsWindow];
+#pragma unroll
+        for (uint32_t q = 0; q < kOsWindow; ++q)
+          v[q] = (j - first > q) ? __hip_atomic_load(st + (size_t)(j - 1 - q) * 256 + d,
+                                                     __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)
+                                 : 0ull;
+        uint32_t used = 0;
+        bool wait = false;
+#pragma unroll
+        for (uint32_t q = 0; q < kOsWindow; ++q) {
+          if (done || wait || j - first <= q) continue;
+          if ((v[q] >> 32) == 0) {
+            wait = true;
+            continue;
+          }
+          excl += (uint32_t)v[q];
+          ++used;
+          if (v[q] & kOsIncl) done = true;
+        }
+        j -= used;
+        if (!done && j == first) done = true;  // never: the first tile is inclusive
+        if (wait && !done) {
           if (++spin > kOsSpinLimit) {
             atomicOr(err, kFlagSortTimeout);
             break;
           }
           __builtin_amdgcn_s_sleep(1);
-          continue;
         }
-        excl += (uint32_t)v;
-        if ((v & kOsIncl) || j == D.tile0[a]) break;
-        --j;
       }
       __hip_atomic_store(st + (size_t)t * 256 + d, kOsIncl | (excl + tc), __ATOMIC_RELAXED,
                          __HIP_MEMORY_SCOPE_AGENT);
     }
     __syncthreads();
-    uint32_t gb = inc - g;
-    for (uint32_t w = 0; w < wave; ++w) gb += wsum[w];
+    uint32_t gb = inc - g, lb = inc2 - tc;
+    for (uint32_t w = 0; w < wave; ++w) {
+      gb += wsum[0][w];
+      lb += wsum[1][w];
+    }
+    ldst[d] = lb;
+    gpos[d] = gb + excl;
+    uint32_t run = lb;
 #pragma unroll
-    for (uint32_t w = 0; w < W; ++w) woff[w][d] += gb + excl;
+    for (uint32_t w = 0; w < W; ++w) {
+      woff[w][d] = run;
+      run += c[w];
+    }
   }
   __syncthreads();
+  // stage the tile in digit order in LDS, then write each digit's run to
+  // consecutive output slots (neighbouring lanes write neighbouring words)
 #pragma unroll
   for (uint32_t r = 0; r < R; ++r) {
     if (base + r * kWave + lane < A.n) {
-      const uint32_t pos = woff[wave][(key[r] >> shift) & 255u] + loc[r];
-      if (pos < A.n) {  // always, unless a look-back wait gave up
-        kd[pos] = key[r];
-        if (vd) vd[pos] = val[r];
+      const uint32_t lp = woff[wave][(key[r] >> shift) & 255u] + loc[r];
+      if (lp < kSortTile) {
+        lkey[lp] = key[r];
+        lval[lp] = val[r];
       }
+    }
+  }
+  __syncthreads();
+  for (uint32_t i = tid; i < tn; i += kSortThreads) {
+    const uint32_t k = lkey[i];
+    const uint32_t dig = (k >> shift) & 255u;
+    const uint32_t pos = gpos[dig] + (i - ldst[dig]);
+    if (pos < A.n) {  // always, unless a look-back wait gave up
+      kd[pos] = k;
+      if (vd) vd[pos] = lval[i];
     }
   }
 }
