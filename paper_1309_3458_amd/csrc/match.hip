@@ -196,18 +196,25 @@ __global__ __launch_bounds__(1024) void bucket_scan_kernel(uint32_t* __restrict_
                                                            uint32_t* __restrict__ gstart_out,
                                                            uint32_t* __restrict__ gcount,
                                                            uint32_t* __restrict__ tprefix) {
+  // thread tid owns buckets tid*32 .. tid*32+31, kept in registers; the LDS
+  // copy is padded (one word per 32) so that these reads do not conflict,
+  // and global reads and writes go through it in coalesced order
   constexpr uint32_t per = kBuckets / 1024;
-  __shared__ uint32_t sb[kBuckets];
+  static_assert(per == 32, "one padding word per 32 buckets");
+  __shared__ uint32_t sb[kBuckets + kBuckets / 32];
   __shared__ uint32_t wsum[1024 / kWave];
   __shared__ uint32_t tws[1024 / kWave];
   __shared__ uint32_t gstart[DDM_MAX_D + 1];
   const uint32_t tid = threadIdx.x, lane = lane_id(), wave = tid / kWave;
-  for (uint32_t i = tid; i < kBuckets; i += 1024) sb[i] = bhist[i];
+  for (uint32_t i = tid; i < kBuckets; i += 1024) sb[i + (i >> 5)] = bhist[i];
   __syncthreads();
+  uint32_t c[per];
   uint32_t sum = 0, tsum = 0;
+#pragma unroll
   for (uint32_t i = 0; i < per; ++i) {
-    sum += sb[tid * per + i];
-    tsum += (sb[tid * per + i] + 63u) / 64u;
+    c[i] = sb[tid * (per + 1) + i];
+    sum += c[i];
+    tsum += (c[i] + 63u) / 64u;
   }
   uint32_t inc = sum, tinc = tsum;
 #pragma unroll
@@ -234,22 +241,26 @@ __global__ __launch_bounds__(1024) void bucket_scan_kernel(uint32_t* __restrict_
   }
   if (tprefix) {
     uint32_t trun = tbefore + tinc - tsum;
+#pragma unroll
     for (uint32_t i = 0; i < per; ++i) {
-      tprefix[tid * per + i] = trun;
-      trun += (sb[tid * per + i] + 63u) / 64u;
+      sb[tid * (per + 1) + i] = trun;
+      trun += (c[i] + 63u) / 64u;
     }
+    __syncthreads();
+    for (uint32_t i = tid; i < kBuckets; i += 1024) tprefix[i] = sb[i + (i >> 5)];
     if (tid == 0) tprefix[kBuckets] = ttotal;
+    __syncthreads();
   }
   uint32_t run = before + inc - sum;
   if ((tid * per) % kBucketsPerDim == 0) gstart[(tid * per) / kBucketsPerDim] = run;
   if (tid == 0) gstart[DDM_MAX_D] = m;
+#pragma unroll
   for (uint32_t i = 0; i < per; ++i) {
-    const uint32_t v = sb[tid * per + i];
-    sb[tid * per + i] = run;
-    run += v;
+    sb[tid * (per + 1) + i] = run;
+    run += c[i];
   }
   __syncthreads();
-  for (uint32_t i = tid; i < kBuckets; i += 1024) bhist[i] = sb[i];
+  for (uint32_t i = tid; i < kBuckets; i += 1024) bhist[i] = sb[i + (i >> 5)];
   if (tid < DDM_MAX_D) {
     gcount[tid] = gstart[tid + 1] - gstart[tid];
     gstart_out[tid] = gstart[tid];
@@ -929,23 +940,40 @@ struct MatchState {
   }
 };
 
+// zeroes the match's counters; with a stash (snext non-null) also sets the
+// slices' next free chunks
 __global__ void match_init_kernel(uint32_t* __restrict__ gcount, int32_t* __restrict__ flag,
                                   uint32_t* __restrict__ lists_count,
-                                  uint32_t* __restrict__ bhist) {
+                                  uint32_t* __restrict__ bhist, uint32_t* __restrict__ snext,
+                                  uint32_t sfirst, uint32_t sslice) {
   const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i < kBuckets) bhist[i] = 0;
   if (i < DDM_MAX_D) gcount[i] = 0;
   if (i == 0) *flag = 0;
   if (i < 2) lists_count[i] = 0;
+  if (snext && i <= kStashSlices) snext[i] = i < kStashSlices ? sfirst + i * sslice : 0u;
 }
 
+// the words the host reads after the count: dst[0] = K, dst[1] = the tree's
+// and the updates' flags; with a stash, dst[2] = (tiles << 32) | most
+// counted chunks used in one slice, dst[3] = overflow
 __global__ void gather_flags_kernel(const int32_t* __restrict__ tflag,
                                     const int32_t* __restrict__ uflag,
                                     const uint64_t* __restrict__ off, uint32_t m,
-                                    uint64_t* __restrict__ dst) {
+                                    uint64_t* __restrict__ dst,
+                                    const uint32_t* __restrict__ snext,
+                                    const uint32_t* __restrict__ tprefix, uint32_t sfirst,
+                                    uint32_t sslice) {
   if (threadIdx.x == 0) {
     dst[0] = off[m];
     dst[1] = (uint64_t)(uint32_t)(*tflag) | ((uint64_t)(uint32_t)(*uflag) << 32);
+    if (snext) {
+      uint32_t mx = 0;
+      for (uint32_t s = 0; s < kStashSlices; ++s)
+        mx = max(mx, min(snext[s] - (sfirst + s * sslice), sslice));
+      dst[2] = ((uint64_t)tprefix[kBuckets] << 32) | mx;
+      dst[3] = snext[kStashSlices];
+    }
   }
 }
 
@@ -992,27 +1020,6 @@ __global__ void learned_words_kernel(const uint32_t* __restrict__ govf,
     for (int g = 0; g < DDM_MAX_D; ++g) t += govf[g];
     dst[2] = t;
     dst[3] = soff[m];
-  }
-}
-
-__global__ void stash_init_kernel(uint32_t* __restrict__ snext, uint32_t sfirst,
-                                  uint32_t sslice) {
-  const uint32_t t = threadIdx.x;
-  if (t < kStashSlices) snext[t] = sfirst + t * sslice;
-  if (t == kStashSlices) snext[t] = 0;
-}
-
-// dst[2] = (tiles << 32) | most counted chunks used in a slice,
-// dst[3] = overflow
-__global__ void stash_words_kernel(const uint32_t* __restrict__ snext,
-                                   const uint32_t* __restrict__ tprefix, uint32_t sfirst,
-                                   uint32_t sslice, uint64_t* __restrict__ dst) {
-  if (threadIdx.x == 0) {
-    uint32_t mx = 0;
-    for (uint32_t s = 0; s < kStashSlices; ++s)
-      mx = max(mx, min(snext[s] - (sfirst + s * sslice), sslice));
-    dst[2] = ((uint64_t)tprefix[kBuckets] << 32) | mx;
-    dst[3] = snext[kStashSlices];
   }
 }
 
@@ -1142,7 +1149,34 @@ static ddm_status front_half(const ddm_tree* t, const float* ulo, const float* u
     DDM_LAUNCHED("learned_init_kernel");
   }
 
-  match_init_kernel<<<kBuckets / 256, 256, 0, s>>>(st.gcount, st.flag, *lists_count, st.bhist);
+  // the count traversal's stash (plain path, d > 1, tile traversal)
+  st.stash = !st.learned && d > 1 && want_stash && !counts_out &&
+             P.traversal == DDM_TRAVERSE_TILE;
+  if (st.stash) {
+    // the count traversal also keeps every hit, so that no fill traversal
+    // is needed when they all fit; without the memory it only counts
+    st.sfirst = (uint32_t)(stash_tiles(m) * kStashStatic);
+    st.sslice = stash_slice(m, stash_hint);
+    st.smax = st.sfirst + st.sslice * kStashSlices;
+    const uint64_t e = (uint64_t)st.smax * kStashChunk;
+    st.stash_sc.reserve(sizeof(uint64_t) * e);
+    st.stash_sc.reserve(sizeof(uint32_t) * e);
+    st.stash_sc.reserve(sizeof(uint32_t) * st.smax);
+    st.stash_sc.reserve(sizeof(uint32_t) * (kStashSlices + 1));
+    if (!st.stash_sc.commit()) {
+      set_detail("");
+      st.stash = false;
+    } else {
+      st.skey = st.stash_sc.take<uint64_t>(e);
+      st.srank = st.stash_sc.take<uint32_t>(e);
+      st.sused = st.stash_sc.take<uint32_t>(st.smax);
+      st.snext = st.stash_sc.take<uint32_t>(kStashSlices + 1);
+      if (!st.stash_sc.fits()) return scratch_overrun("stash");
+    }
+  }
+  match_init_kernel<<<kBuckets / 256, 256, 0, s>>>(st.gcount, st.flag, *lists_count, st.bhist,
+                                                   st.stash ? st.snext : nullptr, st.sfirst,
+                                                   st.sslice);
   DDM_LAUNCHED("match_init_kernel");
   ddm_status r;
   switch (d) {
@@ -1205,36 +1239,13 @@ static ddm_status front_half(const ddm_tree* t, const float* ulo, const float* u
   } else if (d > 1) {
     SegOut O{};
     O.cnt = st.cnt;
-    st.stash = want_stash && !counts_out && P.traversal == DDM_TRAVERSE_TILE;
     if (st.stash) {
-      // the count traversal also keeps every hit, so that no fill traversal
-      // is needed when they all fit; without the memory it only counts
-      st.sfirst = (uint32_t)(stash_tiles(m) * kStashStatic);
-      st.sslice = stash_slice(m, stash_hint);
-      st.smax = st.sfirst + st.sslice * kStashSlices;
-      const uint64_t e = (uint64_t)st.smax * kStashChunk;
-      st.stash_sc.reserve(sizeof(uint64_t) * e);
-      st.stash_sc.reserve(sizeof(uint32_t) * e);
-      st.stash_sc.reserve(sizeof(uint32_t) * st.smax);
-      st.stash_sc.reserve(sizeof(uint32_t) * (kStashSlices + 1));
-      if (!st.stash_sc.commit()) {
-        set_detail("");
-        st.stash = false;
-      } else {
-        st.skey = st.stash_sc.take<uint64_t>(e);
-        st.srank = st.stash_sc.take<uint32_t>(e);
-        st.sused = st.stash_sc.take<uint32_t>(st.smax);
-        st.snext = st.stash_sc.take<uint32_t>(kStashSlices + 1);
-        if (!st.stash_sc.fits()) return scratch_overrun("stash");
-        stash_init_kernel<<<1, 64, 0, s>>>(st.snext, st.sfirst, st.sslice);
-        DDM_LAUNCHED("stash_init_kernel");
-        O.skey = st.skey;
-        O.srank = st.srank;
-        O.sused = st.sused;
-        O.snext = st.snext;
-        O.sfirst = st.sfirst;
-        O.sslice = st.sslice;
-      }
+      O.skey = st.skey;
+      O.srank = st.srank;
+      O.sused = st.sused;
+      O.snext = st.snext;
+      O.sfirst = st.sfirst;
+      O.sslice = st.sslice;
     }
     r = traverse_any<false>(d, P, T, ulo, uhi, m, st.all(), st.kstar, O, s);
     if (r != DDM_OK) return r;
@@ -1246,12 +1257,10 @@ static ddm_status front_half(const ddm_tree* t, const float* ulo, const float* u
   }
   r = scan_u32_u64(counts, st.off, m, stmp, s);
   if (r != DDM_OK) return r;
-  gather_flags_kernel<<<1, 64, 0, s>>>(tree_flag(t), st.flag, st.off, m, dwords);
+  gather_flags_kernel<<<1, 64, 0, s>>>(tree_flag(t), st.flag, st.off, m, dwords,
+                                       st.stash ? st.snext : nullptr, st.tprefix, st.sfirst,
+                                       st.sslice);
   DDM_LAUNCHED("gather_flags_kernel");
-  if (st.stash) {
-    stash_words_kernel<<<1, 64, 0, s>>>(st.snext, st.tprefix, st.sfirst, st.sslice, dwords);
-    DDM_LAUNCHED("stash_words_kernel");
-  }
   if (st.learned) {
     overflow_kernel<<<(m + 255) / 256, 256, 0, s>>>(st.all(), d, SO, st.cnt, st.perm_ovf,
                                                     st.govf);

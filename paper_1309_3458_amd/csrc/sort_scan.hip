@@ -228,6 +228,7 @@ ddm_status sort_setup_small(const SortArr* host_arrs, uint32_t narr, SortArr* ar
 // ---------------------------------------------------------------------------
 constexpr uint32_t kOsHistKeys = 4096;  // keys per workgroup of the histogram kernel
 constexpr uint32_t kOsWindow = 8;       // predecessor tiles read together in a look-back step
+constexpr uint32_t kOsTile = 2048;      // keys per tile of a pass
 constexpr uint64_t kOsAgg = 1ull << 32, kOsIncl = 2ull << 32;
 constexpr uint32_t kOsSpinLimit = 1u << 22;
 
@@ -285,15 +286,15 @@ __global__ __launch_bounds__(kSortThreads) void os_pass_kernel(OsDesc D,
                                                                uint32_t ntiles, int pass,
                                                                int32_t* __restrict__ err) {
   constexpr uint32_t W = kSortThreads / kWave;
-  constexpr uint32_t R = kSortTile / kSortThreads;  // keys per lane
+  constexpr uint32_t R = kOsTile / kSortThreads;  // keys per lane
   __shared__ uint32_t s_t;
   __shared__ uint32_t wcnt[W][256];
   __shared__ uint32_t woff[W][256];
   __shared__ uint32_t wsum[2][W];
   __shared__ uint32_t ldst[256];  // first slot of each digit in the tile's staged order
   __shared__ uint32_t gpos[256];  // where that run starts in the output
-  __shared__ uint32_t lkey[kSortTile];
-  __shared__ uint32_t lval[kSortTile];
+  __shared__ uint32_t lkey[kOsTile];
+  __shared__ uint32_t lval[kOsTile];
   const uint32_t tid = threadIdx.x, wave = tid / kWave, lane = lane_id();
   if (tid == 0) s_t = atomicAdd(ctr + pass, 1u);
   for (uint32_t i = lane; i < 256; i += kWave) wcnt[wave][i] = 0;
@@ -306,8 +307,8 @@ __global__ __launch_bounds__(kSortThreads) void os_pass_kernel(OsDesc D,
   uint32_t* __restrict__ kd = A.k[(pass & 1) ^ 1];
   const uint32_t* __restrict__ vs = A.v[pass & 1];
   uint32_t* __restrict__ vd = A.v[(pass & 1) ^ 1];
-  const uint32_t tbase = lt * kSortTile;
-  const uint32_t tn = min(kSortTile, A.n - tbase);  // keys in this tile
+  const uint32_t tbase = lt * kOsTile;
+  const uint32_t tn = min(kOsTile, A.n - tbase);  // keys in this tile
   const uint32_t base = tbase + wave * (R * kWave);
   const uint32_t shift = 8u * (uint32_t)pass;
   uint32_t key[R], val[R], loc[R];
@@ -425,7 +426,7 @@ __global__ __launch_bounds__(kSortThreads) void os_pass_kernel(OsDesc D,
   for (uint32_t r = 0; r < R; ++r) {
     if (base + r * kWave + lane < A.n) {
       const uint32_t lp = woff[wave][(key[r] >> shift) & 255u] + loc[r];
-      if (lp < kSortTile) {
+      if (lp < kOsTile) {
         lkey[lp] = key[r];
         lval[lp] = val[r];
       }
@@ -453,7 +454,7 @@ static void os_layout(const SortArr* host_arrs, uint32_t narr, OsDesc* D, uint32
     D->hblk0[i] = hb;
     D->tile0[i] = tl;
     hb += (host_arrs[i].n + kOsHistKeys - 1) / kOsHistKeys;
-    tl += (host_arrs[i].n + kSortTile - 1) / kSortTile;
+    tl += (host_arrs[i].n + kOsTile - 1) / kOsTile;
   }
   D->hblk0[narr] = hb;
   D->tile0[narr] = tl;
@@ -592,6 +593,37 @@ __global__ __launch_bounds__(kScanThreads) void scan_tiles_kernel(const uint32_t
   if (blockIdx.x == gridDim.x - 1 && threadIdx.x == 0) out[m] = sums[gridDim.x];
 }
 
+// scan_tiles_kernel with the tile's base computed in the workgroup from the
+// tile sums before it (for few tiles: saves the pass over the sums)
+constexpr uint32_t kScanFusedTiles = 2048;
+
+__global__ __launch_bounds__(kScanThreads) void scan_tiles_fused_kernel(
+    const uint32_t* __restrict__ in, uint32_t m, const uint64_t* __restrict__ sums,
+    uint64_t* __restrict__ out) {
+  uint64_t prev = 0;
+  for (uint32_t i = threadIdx.x; i < blockIdx.x; i += kScanThreads) prev += sums[i];
+  uint64_t tbase;
+  (void)block_excl_scan_u64(prev, &tbase);
+  const uint32_t base = blockIdx.x * kScanTile + threadIdx.x * kScanItems;
+  uint32_t v[kScanItems];
+  uint64_t acc = 0;
+#pragma unroll
+  for (int r = 0; r < kScanItems; ++r) {
+    const uint32_t i = base + r;
+    v[r] = (i < m) ? in[i] : 0u;
+    acc += v[r];
+  }
+  uint64_t tot;
+  uint64_t run = tbase + block_excl_scan_u64(acc, &tot);
+#pragma unroll
+  for (int r = 0; r < kScanItems; ++r) {
+    const uint32_t i = base + r;
+    if (i < m) out[i] = run;
+    run += v[r];
+  }
+  if (blockIdx.x == gridDim.x - 1 && threadIdx.x == 0) out[m] = tbase + tot;
+}
+
 size_t scan_tmp_words(uint32_t m) { return (size_t)(m + kScanTile - 1) / kScanTile + 1; }
 
 ddm_status scan_u32_u64(const uint32_t* in, uint64_t* out, uint32_t m, uint64_t* tmp,
@@ -607,6 +639,11 @@ ddm_status scan_u32_u64(const uint32_t* in, uint64_t* out, uint32_t m, uint64_t*
   ProfScope ps("scan", s);
   scan_tile_sums<<<nt, kScanThreads, 0, s>>>(in, m, tmp);
   DDM_LAUNCHED("scan_tile_sums");
+  if (nt <= kScanFusedTiles) {
+    scan_tiles_fused_kernel<<<nt, kScanThreads, 0, s>>>(in, m, tmp, out);
+    DDM_LAUNCHED("scan_tiles_fused_kernel");
+    return DDM_OK;
+  }
   scan_sums_kernel<<<1, kScanThreads, 0, s>>>(tmp, nt);
   DDM_LAUNCHED("scan_sums_kernel");
   scan_tiles_kernel<<<nt, kScanThreads, 0, s>>>(in, m, tmp, out);
