@@ -137,10 +137,11 @@ ddm_status ddm_match_ex(const ddm_tree* t, const float* upd_lo, const float* upd
  * ddm_match_abort exactly once.  It keeps the device state of the count; the
  * update coordinates must stay valid until ddm_match_finish.  For d > 1 the
  * count also keeps the hits it finds, 12 bytes each, in scratch with room
- * for 4 hits per update (ddm_match_ex: for its capacity) plus a 64-hit chunk
- * per possible work tile (m/64 + min(m, 32768) tiles), at most 2^28 hits:
- * if all of them fit, ddm_match_finish places them instead of running the
- * traversal again.  Results never depend on it.
+ * for 4 hits per update plus six 64-hit chunks per possible work tile
+ * (m/64 + min(m, 32768) tiles): if all of them fit, ddm_match_finish places
+ * them instead of running the traversal again.  ddm_match_ex sizes this
+ * scratch for its capacity instead, and keeps no hits when the capacity
+ * exceeds 8 hits per update or 2^28 hits.  Results never depend on it.
  *
  * ddm_match_finish writes the K sorted pairs into out_pairs (device, capacity
  * slots) on the stream given to ddm_match_begin, and releases the handle in

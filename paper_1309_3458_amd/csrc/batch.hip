@@ -188,11 +188,15 @@ __global__ __launch_bounds__(1024) void b_groups_kernel(const BInst* __restrict_
                                                         uint32_t* __restrict__ gstart,
                                                         uint32_t* __restrict__ gcount,
                                                         uint32_t* __restrict__ tpc,
-                                                        uint32_t* __restrict__ tpf) {
+                                                        uint32_t* __restrict__ tpf,
+                                                        uint32_t* __restrict__ snext,
+                                                        uint32_t sfirst, uint32_t sslice) {
   __shared__ uint32_t wsum[2][1024 / kWave];
   __shared__ uint32_t carry[2];
   const uint32_t G = count * DDM_MAX_D;
   const uint32_t tid = threadIdx.x, lane = lane_id(), wave = tid / kWave;
+  // the count traversal's stash: next free chunk of each slice, overflow
+  if (snext && tid <= kStashSlices) snext[tid] = tid < kStashSlices ? sfirst + tid * sslice : 0u;
   if (tid == 0) carry[0] = carry[1] = 0;
   __syncthreads();
   for (uint32_t base = 0; base < G; base += 1024) {
@@ -272,19 +276,21 @@ __global__ __launch_bounds__(256) void b_tilemap_kernel(uint32_t G, const uint32
 // per tile (the grid covers the largest possible number of tiles, waves
 // beyond the actual number return); otherwise a fixed grid whose
 // wavefronts take tiles from the ticket until they are exhausted.
-template <bool FILL>
+template <bool FILL, bool STASH = false>
 __global__ __launch_bounds__(kTileWaves * kWave) void b_traverse_kernel(
     const BInst* __restrict__ I, uint32_t G, const uint32_t* __restrict__ tp,
     const uint32_t* __restrict__ tmap, const uint32_t* __restrict__ gstart,
     const uint32_t* __restrict__ gcount, const uint32_t* __restrict__ perm,
     uint32_t* __restrict__ ticket, uint32_t persistent, const uint32_t* __restrict__ status,
-    SegOut O) {
+    SegOut O, const uint32_t* __restrict__ stash_done) {
   __shared__ float s_cand[kTileWaves][2 * DDM_MAX_D * kRing];
   __shared__ uint32_t s_cid[kTileWaves][kRing];
   __shared__ float4 s_q[kTileWaves][kWave * 2];
   const uint32_t wave = threadIdx.x / kWave;
   const uint32_t lane = lane_id();
   if (FILL && uniform_u32(*status) != 0) return;
+  // the stash holds the pairs of every instance with d > 1
+  const bool skip_multi = FILL && stash_done && uniform_u32(*stash_done) != 0;
   const uint32_t total = uniform_u32(tp[G]);
   uint32_t next = blockIdx.x * kTileWaves + wave;
   while (true) {
@@ -303,22 +309,24 @@ __global__ __launch_bounds__(kTileWaves * kWave) void b_traverse_kernel(
     const uint32_t gs = uniform_u32(gcount[g]);
     const uint32_t qbeg = uniform_u32(gstart[g]) + lt * qpt;
     const uint32_t nq = min(qpt, gs - lt * qpt);
-    switch (uniform_u32(b.d)) {
+    const uint32_t dd = uniform_u32(b.d);
+    if (skip_multi && dd > 1) continue;
+    switch (dd) {
       case 1:
-        tile_body<1, FILL>(b.T, b.u_lo, b.u_hi, b.m, perm, b.qbase, k, qbeg, nq, O,
-                           s_cand[wave], s_cid[wave], s_q[wave], lane);
+        tile_body<1, FILL, STASH>(b.T, b.u_lo, b.u_hi, b.m, perm, b.qbase, k, qbeg, nq, O,
+                                  s_cand[wave], s_cid[wave], s_q[wave], lane, item);
         break;
       case 2:
-        tile_body<2, FILL>(b.T, b.u_lo, b.u_hi, b.m, perm, b.qbase, k, qbeg, nq, O,
-                           s_cand[wave], s_cid[wave], s_q[wave], lane);
+        tile_body<2, FILL, STASH>(b.T, b.u_lo, b.u_hi, b.m, perm, b.qbase, k, qbeg, nq, O,
+                                  s_cand[wave], s_cid[wave], s_q[wave], lane, item);
         break;
       case 3:
-        tile_body<3, FILL>(b.T, b.u_lo, b.u_hi, b.m, perm, b.qbase, k, qbeg, nq, O,
-                           s_cand[wave], s_cid[wave], s_q[wave], lane);
+        tile_body<3, FILL, STASH>(b.T, b.u_lo, b.u_hi, b.m, perm, b.qbase, k, qbeg, nq, O,
+                                  s_cand[wave], s_cid[wave], s_q[wave], lane, item);
         break;
       default:
-        tile_body<4, FILL>(b.T, b.u_lo, b.u_hi, b.m, perm, b.qbase, k, qbeg, nq, O,
-                           s_cand[wave], s_cid[wave], s_q[wave], lane);
+        tile_body<4, FILL, STASH>(b.T, b.u_lo, b.u_hi, b.m, perm, b.qbase, k, qbeg, nq, O,
+                                  s_cand[wave], s_cid[wave], s_q[wave], lane, item);
         break;
     }
     wave_sync();
@@ -326,17 +334,62 @@ __global__ __launch_bounds__(kTileWaves * kWave) void b_traverse_kernel(
 }
 
 // capacity and input check (one thread): status and total for the host
+// With a stash (snext non-null), *stash_done = 1 if the check passed and
+// the stash holds every hit of the count traversal (then the stash scatter
+// places the pairs of the instances with d > 1 and the fill skips them).
 __global__ void b_status_kernel(const BInst* __restrict__ I, uint32_t count,
                                 const uint64_t* __restrict__ off, uint32_t M, uint64_t capacity,
-                                uint32_t* __restrict__ status, uint64_t* __restrict__ words) {
+                                uint32_t* __restrict__ status, uint64_t* __restrict__ words,
+                                const uint32_t* __restrict__ snext,
+                                uint32_t* __restrict__ stash_done) {
   if (threadIdx.x != 0) return;
   const uint64_t total = off[M];
   uint32_t st = total > capacity ? kBatchStatusCapacity : 0u;
   for (uint32_t i = 0; i < count; ++i)
     if (*I[i].flag) st |= kBatchStatusInput;
   *status = st;
+  if (snext) *stash_done = (st == 0 && snext[kStashSlices] == 0) ? 1u : 0u;
   words[0] = total;
   words[1] = st;
+}
+
+// stashed hits to out[off[gj] + rank]: first the static chunks of the count
+// traversal's tiles, then, slice by slice, the counted chunks in use (their
+// tile is recorded per chunk); a chunk's tile gives its group and instance,
+// which turn the instance-local update index of the key into the global one
+__global__ __launch_bounds__(256) void b_stash_scatter_kernel(
+    const BInst* __restrict__ I, uint32_t G, uint32_t M, const uint32_t* __restrict__ tpc,
+    const uint32_t* __restrict__ tmapc, const uint64_t* __restrict__ skey,
+    const uint32_t* __restrict__ srank, const uint32_t* __restrict__ sused,
+    const uint32_t* __restrict__ sowner, const uint32_t* __restrict__ snext, uint32_t sfirst,
+    uint32_t sslice, const uint32_t* __restrict__ stash_done, const uint64_t* __restrict__ off,
+    uint64_t* __restrict__ out) {
+  if (uniform_u32(*stash_done) == 0) return;
+  const uint64_t nthr = (uint64_t)gridDim.x * blockDim.x;
+  const uint64_t g0 = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  auto place = [&](uint64_t e, uint32_t tile) {
+    const uint32_t c = (uint32_t)(e / kStashChunk);
+    if ((uint32_t)(e % kStashChunk) >= sused[c]) return;
+    const uint64_t key = skey[e];
+    const uint32_t inst = tmapc[tile] / DDM_MAX_D;
+    const uint32_t gj = I[inst].qbase + (uint32_t)(key >> 32);
+    if (gj >= M) return;
+    const uint64_t dst = off[gj] + srank[e];
+    if (dst < off[gj + 1]) out[dst] = key;
+  };
+  const uint32_t tiles = tpc[G];
+  const uint64_t nst = (uint64_t)tiles * kStashStatic * kStashChunk;
+  for (uint64_t e = g0; e < nst; e += nthr)
+    place(e, (uint32_t)(e / ((uint64_t)kStashStatic * kStashChunk)));
+  for (uint32_t sl = 0; sl < kStashSlices; ++sl) {
+    const uint64_t c0 = (uint64_t)sfirst + (uint64_t)sl * sslice;
+    const uint64_t c1 = min<uint64_t>(snext[sl], c0 + sslice);
+    const uint64_t ne = (c1 - c0) * kStashChunk;
+    for (uint64_t i = g0; i < ne; i += nthr) {
+      const uint64_t e = c0 * kStashChunk + i;
+      place(e, sowner[e / kStashChunk]);
+    }
+  }
 }
 
 // after a failed check every segment is emptied, so that the segment sort
@@ -412,6 +465,12 @@ struct ddm_batch {
   uint32_t nzero = 0;
   uint32_t* list_counters = nullptr;  // two words in the cleared block
   bool counted = false;               // ddm_batch_count ran, ddm_batch_fill may follow
+  // the count traversal's stash of hits (capacity > 0, some instance d > 1)
+  bool stash = false;
+  uint64_t* skey = nullptr;
+  uint32_t *srank = nullptr, *sused = nullptr, *sowner = nullptr, *snext = nullptr;
+  uint32_t* stash_done = nullptr;
+  uint32_t sfirst = 0, sslice = 0, smax = 0;
 };
 
 namespace ddm {
@@ -444,7 +503,8 @@ static ddm_status batch_count_half(ddm_batch* b, hipStream_t s) {
   b_scatter_kernel<<<(b->M + 255) / 256, 256, 0, s>>>(b->bucket, b->rank, b->M, b->boff, b->perm);
   DDM_LAUNCHED("b_scatter_kernel");
   b_groups_kernel<<<1, 1024, 0, s>>>(b->inst, b->count, b->boff, b->gstart, b->gcount, b->tpc,
-                                     b->tpf);
+                                     b->tpf, b->stash ? b->snext : nullptr, b->sfirst,
+                                     b->sslice);
   DDM_LAUNCHED("b_groups_kernel");
   b_tilemap_kernel<<<(b->tiles_max + 255) / 256, 256, 0, s>>>(b->G, b->tpc, b->tmapc,
                                                                b->tiles_max);
@@ -456,9 +516,22 @@ static ddm_status batch_count_half(ddm_batch* b, hipStream_t s) {
     ProfScope ps("batch_traverse_count", s);
     SegOut O{};
     O.cnt = b->cnt;
-    b_traverse_kernel<false><<<b->grid, kTileWaves * kWave, 0, s>>>(
-        b->inst, b->G, b->tpc, b->tmapc, b->gstart, b->gcount, b->perm, b->tickets,
-        b->opts.waves_per_cu, b->status, O);
+    if (b->stash) {
+      O.skey = b->skey;
+      O.srank = b->srank;
+      O.sused = b->sused;
+      O.sowner = b->sowner;
+      O.snext = b->snext;
+      O.sfirst = b->sfirst;
+      O.sslice = b->sslice;
+      b_traverse_kernel<false, true><<<b->grid, kTileWaves * kWave, 0, s>>>(
+          b->inst, b->G, b->tpc, b->tmapc, b->gstart, b->gcount, b->perm, b->tickets,
+          b->opts.waves_per_cu, b->status, O, nullptr);
+    } else {
+      b_traverse_kernel<false><<<b->grid, kTileWaves * kWave, 0, s>>>(
+          b->inst, b->G, b->tpc, b->tmapc, b->gstart, b->gcount, b->perm, b->tickets,
+          b->opts.waves_per_cu, b->status, O, nullptr);
+    }
     DDM_LAUNCHED("b_traverse_kernel");
   }
   r = scan_u32_u64(b->cnt, b->off, b->M, b->scan_tmp_q, s);
@@ -473,10 +546,18 @@ static ddm_status batch_count_half(ddm_batch* b, hipStream_t s) {
 // b->out (b->capacity keys)
 static ddm_status batch_fill_half(ddm_batch* b, hipStream_t s) {
   b_status_kernel<<<1, 64, 0, s>>>(b->inst, b->count, b->off, b->M, b->capacity, b->status,
-                                   b->words);
+                                   b->words, b->stash ? b->snext : nullptr, b->stash_done);
   DDM_LAUNCHED("b_status_kernel");
   b_clear_kernel<<<256, 256, 0, s>>>(b->status, b->off, b->M);
   DDM_LAUNCHED("b_clear_kernel");
+  if (b->stash) {
+    ProfScope ps("batch_stash_scatter", s);
+    b_stash_scatter_kernel<<<2048, 256, 0, s>>>(b->inst, b->G, b->M, b->tpc, b->tmapc, b->skey,
+                                                b->srank, b->sused, b->sowner, b->snext,
+                                                b->sfirst, b->sslice, b->stash_done, b->off,
+                                                b->out);
+    DDM_LAUNCHED("b_stash_scatter_kernel");
+  }
   {
     ProfScope ps("batch_traverse_fill", s);
     SegOut O{};
@@ -484,7 +565,7 @@ static ddm_status batch_fill_half(ddm_batch* b, hipStream_t s) {
     O.out = b->out;
     b_traverse_kernel<true><<<b->grid, kTileWaves * kWave, 0, s>>>(
         b->inst, b->G, b->tpf, b->tmapf, b->gstart, b->gcount, b->perm, b->tickets + 1,
-        b->opts.waves_per_cu, b->status, O);
+        b->opts.waves_per_cu, b->status, O, b->stash ? b->stash_done : nullptr);
     DDM_LAUNCHED("b_traverse_kernel");
   }
   return sort_segments_inplace(b->off, b->M, b->out, b->nmax, b->lists, b->list_counters, s);
@@ -698,6 +779,34 @@ extern "C" ddm_status ddm_batch_create(const ddm_batch_instance* inst, uint32_t 
   const size_t o_lists = take(sizeof(uint32_t) * 2 * M);
   const size_t o_status = take(sizeof(uint32_t) * 4);
   const size_t o_words = take(sizeof(uint64_t) * (count + 3));
+  // the stash: static chunks of every possible count tile, then slices for
+  // the capacity (or 4 hits per update) plus a partly used chunk per tile
+  bool any_multi = false;
+  for (uint32_t i = 0; i < count; ++i) any_multi = any_multi || inst[i].d > 1;
+  b->stash = any_multi && capacity > 0 && capacity <= kStashMaxEntries &&
+             capacity <= kStashMaxPerUpdate * M;
+  size_t o_skey = 0, o_srank = 0, o_sused = 0, o_sowner = 0, o_snext = 0;
+  if (b->stash) {
+    const uint64_t dyn = std::min<uint64_t>(std::max<uint64_t>(capacity, 4ull * M),
+                                            kStashMaxEntries);
+    const uint64_t cdyn =
+        (dyn + kStashChunk - 1) / kStashChunk + (uint64_t)b->tiles_max * kStashGrab + 1024;
+    const uint64_t sfirst = (uint64_t)b->tiles_max * kStashStatic;
+    const uint64_t sslice = (cdyn + kStashSlices - 1) / kStashSlices;
+    const uint64_t smax = sfirst + sslice * kStashSlices;
+    if (smax >= (1ull << 32) / kStashChunk) {
+      b->stash = false;
+    } else {
+      b->sfirst = (uint32_t)sfirst;
+      b->sslice = (uint32_t)sslice;
+      b->smax = (uint32_t)smax;
+      o_skey = take(sizeof(uint64_t) * smax * kStashChunk);
+      o_srank = take(sizeof(uint32_t) * smax * kStashChunk);
+      o_sused = take(sizeof(uint32_t) * smax);
+      o_sowner = take(sizeof(uint32_t) * smax);
+      o_snext = take(sizeof(uint32_t) * (kStashSlices + 2));
+    }
+  }
   const size_t total = cur;
 
   b->mem = dev_alloc(total, nullptr);
@@ -823,6 +932,14 @@ extern "C" ddm_status ddm_batch_create(const ddm_batch_instance* inst, uint32_t 
   b->tmapf = P32(o_tmapf);
   b->status = P32(o_status);
   b->words = (uint64_t*)(base + o_words);
+  if (b->stash) {
+    b->skey = (uint64_t*)(base + o_skey);
+    b->srank = P32(o_srank);
+    b->sused = P32(o_sused);
+    b->sowner = P32(o_sowner);
+    b->snext = P32(o_snext);
+    b->stash_done = b->snext + kStashSlices + 1;
+  }
 
   // ---- upload the static tables ----
   auto up = [&](void* dst, const void* src, size_t bytes) -> hipError_t {
@@ -919,7 +1036,8 @@ extern "C" ddm_status ddm_batch_count(ddm_batch* b, void* stream, uint64_t* tota
   ddm_status r = batch_count_half(b, s);
   if (r != DDM_OK) return r;
   // validity only: the capacity is given to ddm_batch_fill
-  b_status_kernel<<<1, 64, 0, s>>>(b->inst, b->count, b->off, b->M, ~0ull, b->status, b->words);
+  b_status_kernel<<<1, 64, 0, s>>>(b->inst, b->count, b->off, b->M, ~0ull, b->status, b->words,
+                                   nullptr, nullptr);
   DDM_LAUNCHED("b_status_kernel");
   DDM_HIP(hipMemcpyAsync(b->host_words, b->words, sizeof(uint64_t) * (b->count + 3),
                          hipMemcpyDeviceToHost, s));

@@ -1057,10 +1057,6 @@ __global__ void stash_scatter_kernel(const uint64_t* __restrict__ skey,
   if (dst < off[j + 1]) out[dst] = key;
 }
 
-// at most 2^28 stashed hits (4 GiB of stash); larger results overflow it and
-// take the fill traversal
-constexpr uint64_t kStashMaxEntries = 1ull << 28;
-
 // stash entries: the hint (a caller's capacity) or 4 per update, plus one
 // chunk per possible tile (a tile's last chunk is partly used; the bound is
 // the launch's own: one tile per 64 updates plus one partial tile per
@@ -1072,7 +1068,7 @@ static uint64_t stash_tiles(uint32_t m) {
 // one partly used chunk per tile and 1024 more, over the slices
 static uint32_t stash_slice(uint32_t m, uint64_t hint) {
   const uint64_t dyn = std::min<uint64_t>(std::max<uint64_t>(hint, 4ull * m), kStashMaxEntries);
-  const uint64_t c = (dyn + kStashChunk - 1) / kStashChunk + stash_tiles(m) + 1024;
+  const uint64_t c = (dyn + kStashChunk - 1) / kStashChunk + stash_tiles(m) * kStashGrab + 1024;
   return (uint32_t)((c + kStashSlices - 1) / kStashSlices);
 }
 
@@ -1601,9 +1597,11 @@ extern "C" ddm_status ddm_match_ex(const ddm_tree* t, const float* upd_lo, const
                                    const ddm_match_opts* opts) {
   ddm_pending* pd = nullptr;
   // the capacity sizes the count traversal's stash (none for a size query,
-  // nor for capacities beyond what a stash may hold)
+  // for capacities beyond what a stash may hold, or for dense results)
   ddm_status r = match_begin(t, upd_lo, upd_hi, m, out_count, stream, opts, &pd,
-                             capacity > 0 && capacity <= kStashMaxEntries, capacity);
+                             capacity > 0 && capacity <= kStashMaxEntries &&
+                                 capacity <= kStashMaxPerUpdate * m,
+                             capacity);
   if (r != DDM_OK) return r;
   if (*out_count > capacity) {
     ddm_match_abort(pd);

@@ -108,15 +108,24 @@ struct UpdSet {
 // appended, with its rank among its update's hits, to chunks of kStashChunk
 // entries.  Tile t owns chunks kStashStatic*t .. +kStashStatic-1 (no atomic
 // for tiles with few hits); further chunks come from the slice
-// t % kStashSlices of the counted chunks: slice s spans sslice chunks from
-// sfirst + s*sslice and snext[s] is its next free chunk (separate counters,
-// so that tiles do not queue on one address).  snext[kStashSlices] becomes
+// t % kStashSlices of the counted chunks, at least kStashGrab at a time
+// (the tile keeps the surplus for its next hits): slice s spans sslice
+// chunks from sfirst + s*sslice and snext[s] is its next free chunk
+// (separate counters, so that tiles do not queue on one address).  snext[kStashSlices] becomes
 // non-zero once a slice is used up (the stash is then incomplete and the
 // counts alone are valid).  sused[c] = entries written in chunk c; every
 // tile writes it for each of its static chunks.
 constexpr uint32_t kStashChunk = 64;
 constexpr uint32_t kStashStatic = 2;
-constexpr uint32_t kStashSlices = 32;
+constexpr uint32_t kStashSlices = 256;
+constexpr uint32_t kStashGrab = 4;  // at least this many counted chunks per request
+// at most 2^28 stashed hits (4 GiB of stash); larger results overflow it and
+// take the fill traversal
+constexpr uint64_t kStashMaxEntries = 1ull << 28;
+// a caller's capacity above this many hits per update means dense results,
+// for which writing and moving every hit costs more than traversing again
+// (measured: 2 hits per update gain, 18 lose); no stash then
+constexpr uint64_t kStashMaxPerUpdate = 8;
 
 struct SegOut {
   const uint64_t* base;
@@ -128,6 +137,7 @@ struct SegOut {
   uint32_t* srank = nullptr;
   uint32_t* sused = nullptr;
   uint32_t* snext = nullptr;
+  uint32_t* sowner = nullptr;  // optional: tile of every counted chunk a tile takes
   uint32_t sfirst = 0;
   uint32_t sslice = 0;
 };
@@ -266,7 +276,7 @@ __device__ __forceinline__ void tile_body(const TreeDev& T, const float* __restr
   // stash chunk of the wave (uniform): id, entries used, last static chunk,
   // still stashing
   uint32_t sch = tile_id * kStashStatic, sfill = 0;
-  const uint32_t slast = sch + kStashStatic - 1;
+  uint32_t slast = sch + kStashStatic - 1;  // last chunk the tile holds
   bool sok = STASH;
   uint64_t myhm = 0;  // this lane's update: hits among the flushed candidates
 
@@ -345,15 +355,33 @@ __device__ __forceinline__ void tile_body(const TreeDev& T, const float* __restr
             if (sch + nnew <= slast) {
               first = sch + 1;
             } else {
-              const uint32_t sl = tile_id % kStashSlices;
-              const uint32_t send = O.sfirst + (sl + 1) * O.sslice;
-              uint32_t f = 0;
-              if (lane == 0) f = atomicAdd(O.snext + sl, nnew);
-              first = uniform_u32(f);
+              // the tile's slice first, then the following ones; the part
+              // of a slice too short for the request is marked empty
+              const uint32_t take = max(nnew, kStashGrab);
               if (sch < slast && lane < slast - sch) O.sused[sch + 1 + lane] = 0;
-              if (first >= send || nnew > send - first) {
+              bool got = false;
+              for (uint32_t a = 0, sl = tile_id % kStashSlices; a < kStashSlices && !got;
+                   ++a, sl = (sl + 1) % kStashSlices) {
+                const uint32_t send = O.sfirst + (sl + 1) * O.sslice;
+                uint32_t f = 0;
+                if (lane == 0) {
+                  // a slice already used up is passed over without an atomic
+                  f = __hip_atomic_load(O.snext + sl, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                  if (f < send) f = atomicAdd(O.snext + sl, take);
+                }
+                first = uniform_u32(f);
+                if (first < send && take <= send - first) {
+                  got = true;
+                } else if (first < send && lane < send - first) {
+                  O.sused[first + lane] = 0;
+                }
+              }
+              if (!got) {
                 sok = false;
                 if (lane == 0) atomicOr(O.snext + kStashSlices, 1u);
+              } else {
+                if (O.sowner && lane < take) O.sowner[first + lane] = tile_id;
+                slast = first + take - 1;
               }
             }
           }

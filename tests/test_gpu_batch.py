@@ -244,3 +244,37 @@ def test_batched_workload_full_size():
         assert np.array_equal(got[i][np.isin(upd, sample)], w), f"instance {i}"
     b.free()
     torch.cuda.synchronize()
+
+
+@pytest.mark.parametrize("use_graph", [False, True])
+def test_sparse_batch_uses_the_stash(use_graph):
+    """Few hits per update (alpha about 1, d = 2 and 3, plus d = 1 instances
+    that the fill traversal writes): a capacity of at most 8 hits per update
+    keeps the count traversal's hits, and the stash scatter places the
+    pairs of the d > 1 instances; graph replays give the same bytes."""
+    import paper_1309_3458_amd as P
+    insts = []
+    for i in range(12):
+        d = (1, 2, 3)[i % 3]
+        n, m = 3000 + 911 * i, 2000 + 677 * i
+        insts.append(W.uniform_instance([920, i], n, m, d, W.side_for_alpha(1.0, n + m, d)))
+    want = [oracle.itm(i.s_lo, i.s_hi, i.u_lo, i.u_hi, threads=8) for i in insts]
+    K = sum(len(w) for w in want)
+    M = sum(i.m for i in insts)
+    assert 0 < K <= 8 * M
+    b = _batch(_tensors(insts), K, use_graph=use_graph)
+    P.prof_enable(True)
+    P.prof_read()
+    try:
+        for r in range(3):
+            b.run()
+            got, tot = _slices(b)
+            assert tot == K
+            for i, (g, w) in enumerate(zip(got, want)):
+                assert np.array_equal(g, w), f"run {r}, instance {i}"
+        rec = P.prof_read()
+    finally:
+        P.prof_enable(False)
+    if not use_graph:
+        assert "batch_stash_scatter" in rec
+    b.free()

@@ -62,17 +62,34 @@ def test_stash_holds_every_hit(d):
 
 def test_stash_overflow_falls_back_to_fill():
     """Many hits per update: the default stash (sized from m) overflows and
-    the fill traversal places the pairs; sized from an exact capacity the
-    stash holds them."""
+    the fill traversal places the pairs; a capacity of more than 8 hits per
+    update keeps no stash at all."""
     import paper_1309_3458_amd as P
     torch = _torch()
-    inst = W.uniform_instance(910, 30000, 4001, 2, 40000.0)
+    inst = W.uniform_instance(910, 60000, 4001, 2, 60000.0)
     want = oracle.itm(inst.s_lo, inst.s_hi, inst.u_lo, inst.u_hi, threads=8)
-    assert len(want) > 50 * inst.m
+    assert len(want) > 500 * inst.m
     t = P.build(dev(inst.s_lo), dev(inst.s_hi))
     got, stash, fill = _paths(lambda: P.match(t, dev(inst.u_lo), dev(inst.u_hi)))
     assert fill and not stash
     assert np.array_equal(_keys(got), want)
+    out = torch.empty(len(want), dtype=torch.int64, device="cuda")
+    k, stash, fill = _paths(lambda: P.match_into(t, dev(inst.u_lo), dev(inst.u_hi), out))
+    assert k == len(want) and fill and not stash
+    assert np.array_equal(_keys(out), want)
+    t.free()
+
+
+def test_stash_exact_capacity_near_the_density_limit():
+    """A capacity just under 8 hits per update sizes the stash exactly (a
+    tile whose own slice of counted chunks is used up takes chunks from the
+    next slices); the stash holds every hit."""
+    import paper_1309_3458_amd as P
+    torch = _torch()
+    inst = W.uniform_instance(915, 60000, 40000, 2, 5600.0)
+    want = oracle.itm(inst.s_lo, inst.s_hi, inst.u_lo, inst.u_hi, threads=8)
+    assert 2 * inst.m < len(want) <= 8 * inst.m
+    t = P.build(dev(inst.s_lo), dev(inst.s_hi))
     out = torch.empty(len(want), dtype=torch.int64, device="cuda")
     k, stash, fill = _paths(lambda: P.match_into(t, dev(inst.u_lo), dev(inst.u_hi), out))
     assert k == len(want) and stash and not fill
