@@ -78,10 +78,13 @@ int tree_device(const ddm_tree* t) { return t->device; }
 
 // validate, order-preserving keys, identity payload (id arrays shifted by one
 // so that the sorted payload lands directly at positions 1..n)
+// keys, identity payload and validity of every coordinate; with recin, the
+// set is also written as n records (lo_0, hi_0, lo_1, hi_1, ...) so that the
+// tree's gather reads one contiguous record per position
 __global__ void build_keys_kernel(const float* __restrict__ lo, const float* __restrict__ hi,
                                   uint32_t n, uint32_t d, uint32_t* __restrict__ klo,
                                   uint32_t* __restrict__ khi, uint32_t* __restrict__ id_base,
-                                  int32_t* __restrict__ flag) {
+                                  int32_t* __restrict__ flag, float* __restrict__ recin) {
   const uint64_t idx = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const uint64_t total = (uint64_t)n * d;
   bool bad = false;
@@ -93,6 +96,7 @@ __global__ void build_keys_kernel(const float* __restrict__ lo, const float* __r
     klo[idx] = f2key(a);
     if (khi) khi[idx] = f2key(b);
     id_base[(size_t)k * (n + 1) + 1 + i] = i;
+    if (recin) *reinterpret_cast<float2*>(recin + ((size_t)i * d + k) * 2) = make_float2(a, b);
   }
   if (ballot(bad) != 0 && lane_id() == 0) atomicOr(flag, 1);
 }
@@ -217,18 +221,21 @@ ddm_status enqueue_tree_build(ddm_tree* t, const float* lo, const float* hi, hip
   sc.reserve(sizeof(uint32_t) * (size_t)n * d);  // hi keys tmp
   sc.reserve(sizeof(uint32_t) * (size_t)n * d);  // payload tmp
   sc.reserve(sort_bytes);
+  sc.reserve(sizeof(float) * 2 * (size_t)n * d);  // the set as records
   if (!sc.commit()) return DDM_E_NOMEM;
   uint32_t* klo_tmp = sc.take<uint32_t>((size_t)n * d);
   uint32_t* khi_tmp = sc.take<uint32_t>((size_t)n * d);
   uint32_t* val_tmp = sc.take<uint32_t>((size_t)n * d);
   char* sort_scratch = sc.take<char>(sort_bytes);
+  float* recin = sc.take<float>(2 * (size_t)n * d);
   if (!sc.fits()) return scratch_overrun("tree build");
 
   {
     ProfScope ps("build_keys", s);
     const uint64_t total = (uint64_t)n * d;
     build_keys_kernel<<<(unsigned)((total + 255) / 256), 256, 0, s>>>(
-        lo, hi, n, d, t->skey_lo[0], sort_hi ? t->skey_hi[0] : nullptr, t->id[0], t->flag);
+        lo, hi, n, d, t->skey_lo[0], sort_hi ? t->skey_hi[0] : nullptr, t->id[0], t->flag,
+        recin);
     DDM_LAUNCHED("build_keys_kernel");
   }
   uint32_t na = 0;
@@ -245,7 +252,9 @@ ddm_status enqueue_tree_build(ddm_tree* t, const float* lo, const float* hi, hip
   }
   ddm_status st = radix_sort_onesweep(host, narr, 4, sort_scratch, t->flag, s);
   if (st != DDM_OK) return st;
-  return enqueue_tree_passes(t, make_jobs(t, lo, hi), true, s);
+  TreeJobs J = make_jobs(t, lo, hi);
+  for (uint32_t k = 0; k < d; ++k) J.j[k].recin = recin;
+  return enqueue_tree_passes(t, J, true, s);
 }
 
 // ---------------------------------------------------------------------------

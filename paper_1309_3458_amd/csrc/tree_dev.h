@@ -21,6 +21,7 @@ struct TreeJob {
   uint32_t* quant;         // kQuant quantiles
   uint32_t* maxlen_bits;   // one word: bound of the lengths (float bits)
   uint32_t n, d, k, P, C, H, ns;
+  const float* recin;      // optional: the set as n records (lo_0, hi_0, lo_1, ...)
 };
 
 constexpr int kChunk = 2048;        // positions per workgroup in a maxhi pass
@@ -58,7 +59,22 @@ __device__ __forceinline__ void tree_low_chunk(const TreeJob& J, uint32_t c) {
     if (p >= 1 && p <= J.n) {
       float* dst = rec + (size_t)p * 2 * D;
       float l0;
-      if (GATHER) {
+      if (GATHER && J.recin) {
+        // one contiguous record per subscription: one random access
+        const uint32_t i = ids[p];
+        const float* src = J.recin + (size_t)i * 2 * D;
+        l0 = src[2 * k];
+        h = src[2 * k + 1];
+        dst[0] = l0;
+        dst[1] = h;
+        uint32_t slot = 1;
+        for (uint32_t kk = 0; kk < D; ++kk) {
+          if (kk == k) continue;
+          dst[2 * slot] = src[2 * kk];
+          dst[2 * slot + 1] = src[2 * kk + 1];
+          ++slot;
+        }
+      } else if (GATHER) {
         const uint32_t i = ids[p];
         l0 = J.s_lo[(size_t)k * J.n + i];
         dst[0] = l0;
