@@ -349,9 +349,10 @@ ddm_status sort_segments_keys(const uint64_t* off, uint32_t m, uint64_t* out, ui
                               uint32_t n, uint32_t* lists, uint32_t* lists_count, hipStream_t s);
 
 // exclusive scan of u32 counts into u64 offsets out[0..m], out[m] = total.
-// tmp: scan_tmp_words(m) uint64 scratch.
+// tmp: scan_tmp_words(m) uint64 scratch.  maxout (optional, zeroed by the
+// caller): receives the largest count.
 size_t scan_tmp_words(uint32_t m);
 ddm_status scan_u32_u64(const uint32_t* in, uint64_t* out, uint32_t m, uint64_t* tmp,
-                        hipStream_t s);
+                        hipStream_t s, uint32_t* maxout = nullptr);
 
 }  // namespace ddm

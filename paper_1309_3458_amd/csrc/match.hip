@@ -190,29 +190,35 @@ __global__ __launch_bounds__(1024) void probe_kernel(TreeDev T, const float* __r
 // exclusive scan of the bucket counts (one workgroup, through LDS); the
 // number of updates of each probe dimension falls out of group boundaries.
 // With tprefix non-null, also the exclusive prefix of the buckets' tiles of
-// at most 64 updates (tprefix[kBuckets] = all tiles).
+// at most 64 updates (tprefix[kBuckets] = all tiles).  Only the d *
+// kBucketsPerDim buckets of the probe dimensions in use are scanned (PER =
+// d * 8 per thread); bhist and tprefix are written up to that bound
+// inclusive, so that the last bucket has an end.
+template <uint32_t PER>
 __global__ __launch_bounds__(1024) void bucket_scan_kernel(uint32_t* __restrict__ bhist,
                                                            uint32_t m,
                                                            uint32_t* __restrict__ gstart_out,
                                                            uint32_t* __restrict__ gcount,
                                                            uint32_t* __restrict__ tprefix) {
-  // thread tid owns buckets tid*32 .. tid*32+31, kept in registers; the LDS
-  // copy is padded (one word per 32) so that these reads do not conflict,
-  // and global reads and writes go through it in coalesced order
-  constexpr uint32_t per = kBuckets / 1024;
-  static_assert(per == 32, "one padding word per 32 buckets");
-  __shared__ uint32_t sb[kBuckets + kBuckets / 32];
+  // thread tid owns buckets tid*PER .. tid*PER+PER-1, kept in registers; the
+  // LDS copy is padded (one word per PER, PER + 1 odd) so that these reads
+  // do not conflict, and global reads and writes go through it in
+  // coalesced order
+  constexpr uint32_t NB = PER * 1024;
+  static_assert(NB <= kBuckets && NB % kBucketsPerDim == 0, "whole probe dimensions");
+  __shared__ uint32_t sb[NB + 1024];
   __shared__ uint32_t wsum[1024 / kWave];
   __shared__ uint32_t tws[1024 / kWave];
   __shared__ uint32_t gstart[DDM_MAX_D + 1];
   const uint32_t tid = threadIdx.x, lane = lane_id(), wave = tid / kWave;
-  for (uint32_t i = tid; i < kBuckets; i += 1024) sb[i + (i >> 5)] = bhist[i];
+  if (tid <= DDM_MAX_D) gstart[tid] = m;  // dimensions beyond d hold no update
+  for (uint32_t i = tid; i < NB; i += 1024) sb[i + i / PER] = bhist[i];
   __syncthreads();
-  uint32_t c[per];
+  uint32_t c[PER];
   uint32_t sum = 0, tsum = 0;
 #pragma unroll
-  for (uint32_t i = 0; i < per; ++i) {
-    c[i] = sb[tid * (per + 1) + i];
+  for (uint32_t i = 0; i < PER; ++i) {
+    c[i] = sb[tid * (PER + 1) + i];
     sum += c[i];
     tsum += (c[i] + 63u) / 64u;
   }
@@ -242,25 +248,29 @@ __global__ __launch_bounds__(1024) void bucket_scan_kernel(uint32_t* __restrict_
   if (tprefix) {
     uint32_t trun = tbefore + tinc - tsum;
 #pragma unroll
-    for (uint32_t i = 0; i < per; ++i) {
-      sb[tid * (per + 1) + i] = trun;
+    for (uint32_t i = 0; i < PER; ++i) {
+      sb[tid * (PER + 1) + i] = trun;
       trun += (c[i] + 63u) / 64u;
     }
     __syncthreads();
-    for (uint32_t i = tid; i < kBuckets; i += 1024) tprefix[i] = sb[i + (i >> 5)];
-    if (tid == 0) tprefix[kBuckets] = ttotal;
+    for (uint32_t i = tid; i < NB; i += 1024) tprefix[i] = sb[i + i / PER];
+    if (tid == 0) {
+      tprefix[NB] = ttotal;
+      tprefix[kBuckets] = ttotal;
+    }
     __syncthreads();
   }
   uint32_t run = before + inc - sum;
-  if ((tid * per) % kBucketsPerDim == 0) gstart[(tid * per) / kBucketsPerDim] = run;
-  if (tid == 0) gstart[DDM_MAX_D] = m;
 #pragma unroll
-  for (uint32_t i = 0; i < per; ++i) {
-    sb[tid * (per + 1) + i] = run;
+  for (uint32_t i = 0; i < PER; ++i) {
+    const uint32_t x = tid * PER + i;  // a probe dimension starts at x % kBucketsPerDim == 0
+    if (x % kBucketsPerDim == 0) gstart[x / kBucketsPerDim] = run;
+    sb[tid * (PER + 1) + i] = run;
     run += c[i];
   }
   __syncthreads();
-  for (uint32_t i = tid; i < kBuckets; i += 1024) bhist[i] = sb[i + (i >> 5)];
+  for (uint32_t i = tid; i < NB; i += 1024) bhist[i] = sb[i + i / PER];
+  if (tid == 0 && NB < kBuckets) bhist[NB] = m;
   if (tid < DDM_MAX_D) {
     gcount[tid] = gstart[tid + 1] - gstart[tid];
     gstart_out[tid] = gstart[tid];
@@ -278,9 +288,9 @@ __global__ __launch_bounds__(256) void bucket_scatter_kernel(const uint32_t* __r
 
 // tile -> bucket
 __global__ __launch_bounds__(256) void tile_map_kernel(const uint32_t* __restrict__ tprefix,
-                                                       uint32_t* __restrict__ tmap) {
+                                                       uint32_t* __restrict__ tmap, uint32_t nb) {
   const uint32_t b = blockIdx.x * blockDim.x + threadIdx.x;
-  if (b >= kBuckets) return;
+  if (b >= nb) return;
   for (uint32_t t = tprefix[b]; t < tprefix[b + 1]; ++t) tmap[t] = b;
 }
 
@@ -917,6 +927,8 @@ struct MatchState {
   // bucket-aligned tiles
   uint32_t* tprefix = nullptr;
   uint32_t* tmap = nullptr;
+  uint32_t* maxcnt = nullptr;  // device: the largest count (longest segment)
+  uint64_t maxseg = ~0ull;     // host copy after the count
   // stash of the count traversal (plain path, d > 1): usable when complete
   Scratch stash_sc;
   bool stash = false;
@@ -945,26 +957,31 @@ struct MatchState {
 __global__ void match_init_kernel(uint32_t* __restrict__ gcount, int32_t* __restrict__ flag,
                                   uint32_t* __restrict__ lists_count,
                                   uint32_t* __restrict__ bhist, uint32_t* __restrict__ snext,
-                                  uint32_t sfirst, uint32_t sslice) {
+                                  uint32_t sfirst, uint32_t sslice, uint32_t* __restrict__ maxcnt) {
   const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i < kBuckets) bhist[i] = 0;
   if (i < DDM_MAX_D) gcount[i] = 0;
-  if (i == 0) *flag = 0;
+  if (i == 0) {
+    *flag = 0;
+    *maxcnt = 0;
+  }
   if (i < 2) lists_count[i] = 0;
   if (snext && i <= kStashSlices) snext[i] = i < kStashSlices ? sfirst + i * sslice : 0u;
 }
 
 // the words the host reads after the count: dst[0] = K, dst[1] = the tree's
 // and the updates' flags; with a stash, dst[2] = (tiles << 32) | most
-// counted chunks used in one slice, dst[3] = overflow
+// counted chunks used in one slice, dst[3] = overflow; dst[4] = the largest
+// count
 __global__ void gather_flags_kernel(const int32_t* __restrict__ tflag,
                                     const int32_t* __restrict__ uflag,
                                     const uint64_t* __restrict__ off, uint32_t m,
                                     uint64_t* __restrict__ dst,
                                     const uint32_t* __restrict__ snext,
                                     const uint32_t* __restrict__ tprefix, uint32_t sfirst,
-                                    uint32_t sslice) {
+                                    uint32_t sslice, const uint32_t* __restrict__ maxcnt) {
   if (threadIdx.x == 0) {
+    dst[4] = *maxcnt;
     dst[0] = off[m];
     dst[1] = (uint64_t)(uint32_t)(*tflag) | ((uint64_t)(uint32_t)(*uflag) << 32);
     if (snext) {
@@ -1109,7 +1126,8 @@ static ddm_status front_half(const ddm_tree* t, const float* ulo, const float* u
   sc.reserve(sizeof(uint64_t) * scan_tmp_words(m));
   sc.reserve(sizeof(uint32_t) * 2 * (size_t)m);  // segment lists
   sc.reserve(sizeof(uint32_t) * 2);              // segment list counts
-  sc.reserve(sizeof(uint64_t) * 4);              // device words for readback
+  sc.reserve(sizeof(uint64_t) * 8);              // device words for readback
+  sc.reserve(sizeof(uint32_t));                  // largest count
   const size_t max_tiles = ((size_t)m + 63) / 64 + kBuckets;
   sc.reserve(sizeof(uint32_t) * (kBuckets + 1));  // tile prefix
   sc.reserve(sizeof(uint32_t) * max_tiles);       // tile -> bucket
@@ -1129,7 +1147,8 @@ static ddm_status front_half(const ddm_tree* t, const float* ulo, const float* u
   uint64_t* stmp = sc.take<uint64_t>(scan_tmp_words(m));
   *lists = sc.take<uint32_t>(2 * (size_t)m);
   *lists_count = sc.take<uint32_t>(2);
-  uint64_t* dwords = sc.take<uint64_t>(4);
+  uint64_t* dwords = sc.take<uint64_t>(8);
+  st.maxcnt = sc.take<uint32_t>(1);
   st.tprefix = sc.take<uint32_t>(kBuckets + 1);
   st.tmap = sc.take<uint32_t>(max_tiles);
   if (st.learned) {
@@ -1172,7 +1191,7 @@ static ddm_status front_half(const ddm_tree* t, const float* ulo, const float* u
   }
   match_init_kernel<<<kBuckets / 256, 256, 0, s>>>(st.gcount, st.flag, *lists_count, st.bhist,
                                                    st.stash ? st.snext : nullptr, st.sfirst,
-                                                   st.sslice);
+                                                   st.sslice, st.maxcnt);
   DDM_LAUNCHED("match_init_kernel");
   ddm_status r;
   switch (d) {
@@ -1184,14 +1203,20 @@ static ddm_status front_half(const ddm_tree* t, const float* ulo, const float* u
   if (r != DDM_OK) return r;
   {
     ProfScope ps("order", s);
-    bucket_scan_kernel<<<1, 1024, 0, s>>>(st.bhist, m, st.gstart, st.gcount,
-                                          P.traversal == DDM_TRAVERSE_TILE ? st.tprefix : nullptr);
+    uint32_t* tp = P.traversal == DDM_TRAVERSE_TILE ? st.tprefix : nullptr;
+    switch (d) {
+      case 1: bucket_scan_kernel<8><<<1, 1024, 0, s>>>(st.bhist, m, st.gstart, st.gcount, tp); break;
+      case 2: bucket_scan_kernel<16><<<1, 1024, 0, s>>>(st.bhist, m, st.gstart, st.gcount, tp); break;
+      case 3: bucket_scan_kernel<24><<<1, 1024, 0, s>>>(st.bhist, m, st.gstart, st.gcount, tp); break;
+      default: bucket_scan_kernel<32><<<1, 1024, 0, s>>>(st.bhist, m, st.gstart, st.gcount, tp); break;
+    }
     DDM_LAUNCHED("bucket_scan_kernel");
     bucket_scatter_kernel<<<(m + 255) / 256, 256, 0, s>>>(st.bucket, st.rank, m, st.bhist,
                                                           st.perm);
     DDM_LAUNCHED("bucket_scatter_kernel");
     if (P.traversal == DDM_TRAVERSE_TILE) {
-      tile_map_kernel<<<kBuckets / 256, 256, 0, s>>>(st.tprefix, st.tmap);
+      const uint32_t nb = d * kBucketsPerDim;
+      tile_map_kernel<<<(nb + 255) / 256, 256, 0, s>>>(st.tprefix, st.tmap, nb);
       DDM_LAUNCHED("tile_map_kernel");
     }
   }
@@ -1251,11 +1276,11 @@ static ddm_status front_half(const ddm_tree* t, const float* ulo, const float* u
     copy_counts_kernel<<<(m + 255) / 256, 256, 0, s>>>(counts, counts_out, m);
     DDM_LAUNCHED("copy_counts_kernel");
   }
-  r = scan_u32_u64(counts, st.off, m, stmp, s);
+  r = scan_u32_u64(counts, st.off, m, stmp, s, st.maxcnt);
   if (r != DDM_OK) return r;
   gather_flags_kernel<<<1, 64, 0, s>>>(tree_flag(t), st.flag, st.off, m, dwords,
                                        st.stash ? st.snext : nullptr, st.tprefix, st.sfirst,
-                                       st.sslice);
+                                       st.sslice, st.maxcnt);
   DDM_LAUNCHED("gather_flags_kernel");
   if (st.learned) {
     overflow_kernel<<<(m + 255) / 256, 256, 0, s>>>(st.all(), d, SO, st.cnt, st.perm_ovf,
@@ -1267,10 +1292,11 @@ static ddm_status front_half(const ddm_tree* t, const float* ulo, const float* u
   uint64_t* hw = nullptr;
   r = host_words(&hw);
   if (r != DDM_OK) return r;
-  DDM_HIP(hipMemcpyAsync(hw, dwords, 4 * sizeof(uint64_t), hipMemcpyDeviceToHost, s));
+  DDM_HIP(hipMemcpyAsync(hw, dwords, 5 * sizeof(uint64_t), hipMemcpyDeviceToHost, s));
   DDM_HIP(hipStreamSynchronize(s));
   const uint64_t flags = hw[1];
   st.K = hw[0];
+  st.maxseg = hw[4];
   if (st.learned) {
     st.novf = (uint32_t)hw[2];
     st.slots_total = hw[3];
@@ -1319,7 +1345,8 @@ static ddm_status check_common(const ddm_tree* t, const float* ulo, const float*
 }
 
 ddm_status sort_segments(const uint64_t* off, uint32_t m, uint64_t* out, uint64_t K, uint32_t n,
-                         uint32_t* lists, uint32_t* lists_count, hipStream_t s, const SegSrc& S);
+                         uint32_t* lists, uint32_t* lists_count, hipStream_t s, const SegSrc& S,
+                         uint64_t max_len = ~0ull);
 
 // the big-segment kernel's LDS bitmap exceeds the default dynamic LDS limit
 ddm_status ensure_segsort_attr() {
@@ -1349,14 +1376,18 @@ ddm_status sort_segments_keys(const uint64_t* off, uint32_t m, uint64_t* out, ui
   return sort_segments(off, m, out, K, n, lists, lists_count, s, SegSrc{});
 }
 
+// max_len: the longest segment if known; size classes that cannot occur
+// are not launched
 ddm_status sort_segments(const uint64_t* off, uint32_t m, uint64_t* out, uint64_t K, uint32_t n,
                          uint32_t* lists, uint32_t* lists_count, hipStream_t s,
-                         const SegSrc& S) {
+                         const SegSrc& S, uint64_t max_len) {
   ProfScope ps("segsort", s);
   segsort_small_kernel<<<(m + 255) / 256, 256, 0, s>>>(off, m, out, S, lists, lists_count);
   DDM_LAUNCHED("segsort_small_kernel");
+  if (max_len <= 16) return DDM_OK;  // every segment sorted in registers
   segsort_mid_kernel<<<4096, kSegWaves * kWave, 0, s>>>(off, out, S, lists, lists_count);
   DDM_LAUNCHED("segsort_mid_kernel");
+  if (max_len <= kSegMid) return DDM_OK;
   const uint32_t words = std::min<uint32_t>(kMaxBitWords, (n + 31) / 32);
   uint32_t* tmp = nullptr;
   Scratch sc(s);
@@ -1582,7 +1613,7 @@ extern "C" ddm_status ddm_match_finish(ddm_pending* pd, uint64_t* out_pairs, uin
         S.cnt = st.cnt;
       }
       r = sort_segments(st.off, pd->m, out_pairs, st.K, tree_n(pd->t), pd->lists,
-                        pd->lists_count, pd->s, S);
+                        pd->lists_count, pd->s, S, st.maxseg);
     }
   }
   delete pd;

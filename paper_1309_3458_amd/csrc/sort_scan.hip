@@ -541,17 +541,36 @@ __device__ __forceinline__ uint64_t block_excl_scan_u64(uint64_t v, uint64_t* to
 
 __global__ __launch_bounds__(kScanThreads) void scan_tile_sums(const uint32_t* __restrict__ in,
                                                                uint32_t m,
-                                                               uint64_t* __restrict__ sums) {
+                                                               uint64_t* __restrict__ sums,
+                                                               uint32_t* __restrict__ maxout) {
   const uint32_t base = blockIdx.x * kScanTile;
   uint64_t acc = 0;
+  uint32_t mx = 0;
 #pragma unroll
   for (int r = 0; r < kScanItems; ++r) {
     const uint32_t i = base + r * kScanThreads + threadIdx.x;
-    if (i < m) acc += in[i];
+    if (i < m) {
+      const uint32_t v = in[i];
+      acc += v;
+      mx = max(mx, v);
+    }
   }
   uint64_t tot;
   (void)block_excl_scan_u64(acc, &tot);
   if (threadIdx.x == 0) sums[blockIdx.x] = tot;
+  if (maxout) {
+    // one atomic per workgroup (the device-scope atomics on one word queue)
+    __shared__ uint32_t wmax[kScanThreads / kWave];
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) mx = max(mx, (uint32_t)__shfl_xor((int)mx, o, kWave));
+    if (lane_id() == 0) wmax[threadIdx.x / kWave] = mx;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      uint32_t b = 0;
+      for (uint32_t w = 0; w < kScanThreads / kWave; ++w) b = max(b, wmax[w]);
+      if (b) atomicMax(maxout, b);
+    }
+  }
 }
 
 __global__ __launch_bounds__(kScanThreads) void scan_sums_kernel(uint64_t* __restrict__ sums,
@@ -627,7 +646,7 @@ __global__ __launch_bounds__(kScanThreads) void scan_tiles_fused_kernel(
 size_t scan_tmp_words(uint32_t m) { return (size_t)(m + kScanTile - 1) / kScanTile + 1; }
 
 ddm_status scan_u32_u64(const uint32_t* in, uint64_t* out, uint32_t m, uint64_t* tmp,
-                        hipStream_t s) {
+                        hipStream_t s, uint32_t* maxout) {
   const uint32_t nt = (m + kScanTile - 1) / kScanTile;
   if (nt == 0) {
     // m == 0: out[0] = 0 (a kernel rather than a memset node, so that the
@@ -637,7 +656,7 @@ ddm_status scan_u32_u64(const uint32_t* in, uint64_t* out, uint32_t m, uint64_t*
     return DDM_OK;
   }
   ProfScope ps("scan", s);
-  scan_tile_sums<<<nt, kScanThreads, 0, s>>>(in, m, tmp);
+  scan_tile_sums<<<nt, kScanThreads, 0, s>>>(in, m, tmp, maxout);
   DDM_LAUNCHED("scan_tile_sums");
   if (nt <= kScanFusedTiles) {
     scan_tiles_fused_kernel<<<nt, kScanThreads, 0, s>>>(in, m, tmp, out);
