@@ -228,7 +228,7 @@ ddm_status sort_setup_small(const SortArr* host_arrs, uint32_t narr, SortArr* ar
 // ---------------------------------------------------------------------------
 constexpr uint32_t kOsHistKeys = 4096;  // keys per workgroup of the histogram kernel
 constexpr uint32_t kOsWindow = 8;       // predecessor tiles read together in a look-back step
-constexpr uint32_t kOsTile = 2048;      // keys per tile of a pass
+constexpr uint32_t kOsTile = 4096;      // keys per tile of a pass
 constexpr uint64_t kOsAgg = 1ull << 32, kOsIncl = 2ull << 32;
 constexpr uint32_t kOsSpinLimit = 1u << 22;
 
@@ -284,7 +284,8 @@ __global__ __launch_bounds__(kSortThreads) void os_pass_kernel(OsDesc D,
                                                                uint32_t* __restrict__ ctr,
                                                                uint64_t* __restrict__ status,
                                                                uint32_t ntiles, int pass,
-                                                               int32_t* __restrict__ err) {
+                                                               int32_t* __restrict__ err,
+                                                               uint32_t direct) {
   constexpr uint32_t W = kSortThreads / kWave;
   constexpr uint32_t R = kOsTile / kSortThreads;  // keys per lane
   __shared__ uint32_t s_t;
@@ -296,10 +297,10 @@ __global__ __launch_bounds__(kSortThreads) void os_pass_kernel(OsDesc D,
   __shared__ uint32_t lkey[kOsTile];
   __shared__ uint32_t lval[kOsTile];
   const uint32_t tid = threadIdx.x, wave = tid / kWave, lane = lane_id();
-  if (tid == 0) s_t = atomicAdd(ctr + pass, 1u);
+  if (!direct && tid == 0) s_t = atomicAdd(ctr + pass, 1u);
   for (uint32_t i = lane; i < 256; i += kWave) wcnt[wave][i] = 0;
   __syncthreads();
-  const uint32_t t = s_t;
+  const uint32_t t = direct ? blockIdx.x : s_t;
   const uint32_t a = os_array(D.tile0, D.narr, t);
   const SortArr& A = D.a[a];
   const uint32_t lt = t - D.tile0[a];
@@ -444,6 +445,20 @@ __global__ __launch_bounds__(kSortThreads) void os_pass_kernel(OsDesc D,
   }
 }
 
+// workgroups of the pass kernel the current device holds at once (0 if
+// the runtime cannot say, which keeps the counter)
+static uint32_t os_resident_blocks() {
+  int dev = 0, cus = 0, per = 0;
+  if (hipGetDevice(&dev) != hipSuccess ||
+      hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+      hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, (const void*)os_pass_kernel,
+                                                   kSortThreads, 0) != hipSuccess) {
+    (void)hipGetLastError();
+    return 0;
+  }
+  return (uint32_t)std::max(0, cus) * (uint32_t)std::max(0, per);
+}
+
 static void os_layout(const SortArr* host_arrs, uint32_t narr, OsDesc* D, uint32_t* nhblk,
                       uint32_t* ntiles) {
   uint32_t hb = 0, tl = 0;
@@ -494,9 +509,13 @@ ddm_status radix_sort_onesweep(const SortArr* host_arrs, uint32_t narr, int npas
     os_hist_kernel<<<hb, kSortThreads, 0, s>>>(D, ghist, npasses);
     DDM_LAUNCHED("os_hist_kernel");
   }
+  // when every workgroup of a pass fits on the device at once, a tile takes
+  // its index from its workgroup (every tile it waits for is running);
+  // otherwise from a counter in start order
+  const uint32_t direct = tl <= os_resident_blocks() ? 1u : 0u;
   for (int p = 0; p < npasses; ++p) {
     ProfScope ps("radix_scatter", s);
-    os_pass_kernel<<<tl, kSortThreads, 0, s>>>(D, ghist, ctr, status, tl, p, err);
+    os_pass_kernel<<<tl, kSortThreads, 0, s>>>(D, ghist, ctr, status, tl, p, err, direct);
     DDM_LAUNCHED("os_pass_kernel");
   }
   return DDM_OK;
