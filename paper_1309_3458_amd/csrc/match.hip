@@ -128,20 +128,38 @@ __global__ __launch_bounds__(1024) void probe_kernel(TreeDev T, const float* __r
   if (act) {
     uint32_t best = 0xffffffffu, bk = 0, bqa = 0, bx = 0;
     float mid[D];
+    uint32_t xh[D], xl[D], qa[D], qb[D];
 #pragma unroll
     for (int k = 0; k < D; ++k) {
       const float a = ulo[(size_t)k * m + j], b = uhi[(size_t)k * m + j];
       bad = bad || !valid_extent(a, b);
       mid[k] = 0.5f * a + 0.5f * b;
-      const uint32_t xh = f2key(b);
-      const uint32_t qa = quant_count(sq[k], xh, true);
-      const uint32_t qb = quant_count(sq[k], f2key(nextafterf(a - T.maxlen[k], -INFINITY)), false);
-      const uint32_t est = qa - min(qa, qb);
+      xh[k] = f2key(b);
+      xl[k] = f2key(nextafterf(a - T.maxlen[k], -INFINITY));
+      qa[k] = 0;
+      qb[k] = 0;
+    }
+    // the 2D quantile searches (#quantiles <= xh, #quantiles < xl per
+    // dimension) advance in lockstep, so their LDS reads overlap
+#pragma unroll
+    for (uint32_t step = kQuant; step > 0; step >>= 1) {
+#pragma unroll
+      for (int k = 0; k < D; ++k) {
+        const uint32_t ca = qa[k] + step, cb = qb[k] + step;
+        const uint32_t va = ca <= kQuant ? sq[k][ca - 1] : 0xffffffffu;
+        const uint32_t vb = cb <= kQuant ? sq[k][cb - 1] : 0xffffffffu;
+        if (ca <= kQuant && va <= xh[k]) qa[k] = ca;
+        if (cb <= kQuant && vb < xl[k]) qb[k] = cb;
+      }
+    }
+#pragma unroll
+    for (int k = 0; k < D; ++k) {
+      const uint32_t est = qa[k] - min(qa[k], qb[k]);
       if (est < best) {
         best = est;
         bk = (uint32_t)k;
-        bqa = qa;
-        bx = xh;
+        bqa = qa[k];
+        bx = xh[k];
       }
     }
     // position of q.hi in tree k*, interpolated between its two quantiles
