@@ -9,6 +9,7 @@
 #include "ddm_internal.h"
 
 #include <algorithm>
+#include <atomic>
 
 namespace ddm {
 
@@ -446,17 +447,29 @@ __global__ __launch_bounds__(kSortThreads) void os_pass_kernel(OsDesc D,
 }
 
 // workgroups of the pass kernel the current device holds at once (0 if
-// the runtime cannot say, which keeps the counter)
+// the runtime cannot say, which keeps the counter); asked once per device
 static uint32_t os_resident_blocks() {
+  constexpr int kDevs = 64;
+  static std::atomic<uint32_t> cache[kDevs];  // value + 1, 0 = not asked yet
   int dev = 0, cus = 0, per = 0;
-  if (hipGetDevice(&dev) != hipSuccess ||
-      hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
-      hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, (const void*)os_pass_kernel,
-                                                   kSortThreads, 0) != hipSuccess) {
+  if (hipGetDevice(&dev) != hipSuccess) {
     (void)hipGetLastError();
     return 0;
   }
-  return (uint32_t)std::max(0, cus) * (uint32_t)std::max(0, per);
+  if (dev >= 0 && dev < kDevs) {
+    const uint32_t c = cache[dev].load(std::memory_order_relaxed);
+    if (c) return c - 1;
+  }
+  uint32_t r = 0;
+  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess &&
+      hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, (const void*)os_pass_kernel,
+                                                   kSortThreads, 0) == hipSuccess) {
+    r = (uint32_t)std::max(0, cus) * (uint32_t)std::max(0, per);
+  } else {
+    (void)hipGetLastError();
+  }
+  if (dev >= 0 && dev < kDevs) cache[dev].store(r + 1, std::memory_order_relaxed);
+  return r;
 }
 
 static void os_layout(const SortArr* host_arrs, uint32_t narr, OsDesc* D, uint32_t* nhblk,
