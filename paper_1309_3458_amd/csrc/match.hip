@@ -62,16 +62,18 @@ constexpr uint32_t kBucketsPerDim = 8192;
 constexpr uint32_t kBuckets = kBucketsPerDim * DDM_MAX_D;
 
 // d > 1: the first half of a dimension's buckets are ranges of the position
-// in tree k*; an update whose candidate range is long (more than
-// kCellRange positions, where testing the tile's candidates against its
-// updates dominates) goes instead to the second half: cells of
-// kProbeBins(D) position ranges times kCellBins(D) ranges (equal numbers of
-// lower bounds, from the quantiles) of each other dimension, so that the
-// updates of a tile are close in every dimension and the tile's enclosing
-// box filters most candidates before they are tested one by one.  With
-// short ranges scanning the range dominates and 1-D order keeps it short.
+// in tree k*; an update whose candidate range is longer than kCellRange
+// positions goes instead to the second half: cells of kProbeBins(D)
+// position ranges times kCellBins(D) ranges (equal numbers of lower
+// bounds, from the quantiles) of each other dimension, so that the updates
+// of a tile are close in every dimension and the tile's enclosing box
+// filters most candidates before they are tested one by one.  Only very
+// short ranges, where scanning dominates, keep the 1-D order.  Measured
+// (match, one MI355X): 10^6 boxes d = 2 alpha = 1 0.40 -> 0.30 ms, d = 3
+// 0.50 -> 0.25 ms, alpha = 10 1.22 -> 1.00 ms, against a threshold of 4096;
+// alpha = 0.1, d = 4 and the hotspot workload unchanged.
 constexpr uint32_t kLineBins = kBucketsPerDim / 2;
-constexpr uint32_t kCellRange = 4096;
+constexpr uint32_t kCellRange = 256;
 __host__ __device__ constexpr uint32_t kCellBins(int D) { return D == 2 ? 8 : D == 3 ? 4 : 2; }
 __host__ __device__ constexpr uint32_t kProbeBins(int D) {
   return kLineBins / (D == 2 ? 8 : D == 3 ? 16 : 8);
