@@ -108,13 +108,14 @@ __global__ __launch_bounds__(kProbeThreads) void b_probe_kernel(const BInst* __r
                                                                 uint32_t* __restrict__ rank,
                                                                 uint32_t* __restrict__ bhist,
                                                                 uint32_t* __restrict__ cnt) {
-  __shared__ uint32_t sq[DDM_MAX_D][kQuant];
+  __shared__ uint32_t sq[DDM_MAX_D][kQuantPad];
   const uint2 w = map[blockIdx.x];
   const BInst& b = I[w.x];
   const uint32_t d = b.d;
   if (d > 1)
     for (uint32_t k = 0; k < d; ++k)
-      for (uint32_t i = threadIdx.x; i < kQuant; i += kProbeThreads) sq[k][i] = b.T.quant[k][i];
+      for (uint32_t i = threadIdx.x; i < kQuant; i += kProbeThreads)
+        sq[k][qslot(i)] = b.T.quant[k][i];
   __syncthreads();
   const uint32_t j = w.y * kProbeThreads + threadIdx.x;
   const bool act = j < b.m;
@@ -154,7 +155,7 @@ __global__ __launch_bounds__(kProbeThreads) void b_probe_kernel(const BInst* __r
       if (bqa >= kQuant) {
         fine = (float)kQuant - 0.5f;
       } else if (bqa > 0) {
-        const uint32_t kl = sq[bk][bqa - 1], ku = sq[bk][bqa];
+        const uint32_t kl = sq[bk][qslot(bqa - 1)], ku = sq[bk][qslot(bqa)];
         const float fr = ku > kl ? (float)(bx - kl) / (float)(ku - kl) : 0.f;
         fine = (float)(bqa - 1) + fminf(fr, 0.999f);
       }

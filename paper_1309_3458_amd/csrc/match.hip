@@ -63,21 +63,33 @@ constexpr uint32_t kBuckets = kBucketsPerDim * DDM_MAX_D;
 
 // d > 1: the first half of a dimension's buckets are ranges of the position
 // in tree k*; an update whose candidate range is longer than kCellRange
-// positions goes instead to the second half: cells of kProbeBins(D)
-// position ranges times kCellBins(D) ranges (equal numbers of lower
-// bounds, from the quantiles) of each other dimension, so that the updates
-// of a tile are close in every dimension and the tile's enclosing box
-// filters most candidates before they are tested one by one.  Only very
-// short ranges, where scanning dominates, keep the 1-D order.  Measured
-// (match, one MI355X): 10^6 boxes d = 2 alpha = 1 0.40 -> 0.30 ms, d = 3
-// 0.50 -> 0.25 ms, alpha = 10 1.22 -> 1.00 ms, against a threshold of 4096;
-// alpha = 0.1, d = 4 and the hotspot workload unchanged.
+// positions goes instead to the second half: cells of B0 position ranges
+// times B1 ranges (equal numbers of lower bounds, from the quantiles) of
+// each other dimension, B0 * B1^(d-1) = kLineBins, so that the updates of a
+// tile are close in every dimension and the tile's enclosing box filters
+// most candidates before they are tested one by one.  Only very short
+// ranges, where scanning dominates, keep the 1-D order.  The shape follows
+// the update's estimated range: a tile scans its cell's width plus one
+// update's range, so B0 is the power of two nearest to the number of
+// ranges of that length in the tree (B1 = 2^e, B0 = kLineBins / 2^(e(d-1))).
+// Measured (match, one MI355X): 10^6 boxes d = 2 alpha = 1 0.40 -> 0.30 ms,
+// d = 3 0.50 -> 0.25 ms, alpha = 10 1.22 -> 1.00 ms, against a threshold of
+// 4096 and fixed shapes.
 constexpr uint32_t kLineBins = kBucketsPerDim / 2;
 constexpr uint32_t kCellRange = 256;
-__host__ __device__ constexpr uint32_t kCellBins(int D) { return D == 2 ? 8 : D == 3 ? 4 : 2; }
-__host__ __device__ constexpr uint32_t kProbeBins(int D) {
-  return kLineBins / (D == 2 ? 8 : D == 3 ? 16 : 8);
+constexpr float kCellBias = 0.0f;  // log2 of (B0 * range / positions) aimed at
+
+// log2 B1 for an update whose candidate range holds about `best` of the
+// kQuant quantile steps (B0 then about kQuant / best), at least 2 cells per
+// dimension and at least 16 position ranges
+template <int D>
+__device__ __forceinline__ uint32_t cell_log2(uint32_t best) {
+  const float x = (log2f((float)best) - kCellBias) / (float)(D - 1);
+  const int e = (int)floorf(x + 0.5f);
+  return (uint32_t)max(1, min(e, 8 / (D - 1)));
 }
+// the shape of a probe dimension no sampled update takes with cells
+__host__ __device__ constexpr uint32_t kCellLog2Default(int D) { return D == 2 ? 3 : D == 3 ? 2 : 1; }
 
 __global__ __launch_bounds__(256) void bits1_kernel(TreeDev T, const float* __restrict__ ulo,
                                                     const float* __restrict__ uhi, uint32_t m,
@@ -111,59 +123,128 @@ __global__ __launch_bounds__(256) void bits1_kernel(TreeDev T, const float* __re
   if (ballot(bad) != 0 && lane_id() == 0) atomicOr(flag, 2);
 }
 
+// the probe estimate of update j: the dimension k* with the fewest
+// candidate positions (best, in quantile steps), #quantiles <= q.hi there
+// (bqa) and its key (bx), the box centre, and whether the extent is invalid
+template <int D>
+struct ProbeEst {
+  uint32_t best, bk, bqa, bx;
+  float mid[D];
+  bool bad;
+};
+
+template <int D>
+__device__ __forceinline__ ProbeEst<D> probe_estimate(const TreeDev& T,
+                                                      const uint32_t (*sq)[kQuantPad],
+                                                      const float* __restrict__ ulo,
+                                                      const float* __restrict__ uhi, uint32_t m,
+                                                      uint32_t j) {
+  ProbeEst<D> P;
+  P.best = 0xffffffffu;
+  P.bk = 0;
+  P.bqa = 0;
+  P.bx = 0;
+  P.bad = false;
+  uint32_t xh[D], xl[D], qa[D], qb[D];
+#pragma unroll
+  for (int k = 0; k < D; ++k) {
+    const float a = ulo[(size_t)k * m + j], b = uhi[(size_t)k * m + j];
+    P.bad = P.bad || !valid_extent(a, b);
+    P.mid[k] = 0.5f * a + 0.5f * b;
+    xh[k] = f2key(b);
+    xl[k] = f2key(nextafterf(a - T.maxlen[k], -INFINITY));
+    qa[k] = 0;
+    qb[k] = 0;
+  }
+  // the 2D quantile searches (#quantiles <= xh, #quantiles < xl per
+  // dimension) advance in lockstep, so their LDS reads overlap
+#pragma unroll
+  for (uint32_t step = kQuant; step > 0; step >>= 1) {
+#pragma unroll
+    for (int k = 0; k < D; ++k) {
+      const uint32_t ca = qa[k] + step, cb = qb[k] + step;
+      const uint32_t va = ca <= kQuant ? sq[k][qslot(ca - 1)] : 0xffffffffu;
+      const uint32_t vb = cb <= kQuant ? sq[k][qslot(cb - 1)] : 0xffffffffu;
+      if (ca <= kQuant && va <= xh[k]) qa[k] = ca;
+      if (cb <= kQuant && vb < xl[k]) qb[k] = cb;
+    }
+  }
+#pragma unroll
+  for (int k = 0; k < D; ++k) {
+    const uint32_t est = qa[k] - min(qa[k], qb[k]);
+    if (est < P.best) {
+      P.best = est;
+      P.bk = (uint32_t)k;
+      P.bqa = qa[k];
+      P.bx = xh[k];
+    }
+  }
+  return P;
+}
+
+template <int D>
+__device__ __forceinline__ bool cell_mode(uint32_t best, uint32_t n) {
+  return (uint64_t)best * n > (uint64_t)kCellRange * kQuant;
+}
+
+// The cell shape of each probe dimension (run by one workgroup of 256
+// threads): the most common cell_log2 over up to 256 updates spread evenly
+// over the set, among those that would take that dimension with cells.
+// One shape per dimension keeps the cells of different updates from sharing
+// buckets while meaning different boxes (a tile that mixed them would scan
+// the union of far-apart ranges).
+template <int D>
+__device__ __forceinline__ void sample_cell_shape(const TreeDev& T, const float* __restrict__ ulo,
+                                                  const float* __restrict__ uhi, uint32_t m,
+                                                  uint32_t* __restrict__ shape) {
+  __shared__ uint32_t sq[D][kQuantPad];
+  __shared__ uint32_t hist[D][16];
+  for (uint32_t i = threadIdx.x; i < D * 16; i += blockDim.x) hist[i / 16][i % 16] = 0;
+#pragma unroll
+  for (int k = 0; k < D; ++k)
+    for (uint32_t i = threadIdx.x; i < kQuant; i += blockDim.x) sq[k][qslot(i)] = T.quant[k][i];
+  __syncthreads();
+  const uint32_t S = min(m, (uint32_t)blockDim.x);
+  if (threadIdx.x < S) {
+    const uint32_t j = (uint32_t)(((uint64_t)threadIdx.x * m) / S);
+    const ProbeEst<D> P = probe_estimate<D>(T, sq, ulo, uhi, m, j);
+    if (!P.bad && cell_mode<D>(P.best, T.n)) atomicAdd(&hist[P.bk][cell_log2<D>(P.best)], 1u);
+  }
+  __syncthreads();
+  if (threadIdx.x < D) {
+    const uint32_t k = threadIdx.x;
+    uint32_t e = kCellLog2Default(D), c = 0;
+    for (uint32_t x = 1; x < 16; ++x)
+      if (hist[k][x] > c) {
+        c = hist[k][x];
+        e = x;
+      }
+    shape[k] = e;
+  }
+}
+
 template <int D>
 __global__ __launch_bounds__(1024) void probe_kernel(TreeDev T, const float* __restrict__ ulo,
                                                      const float* __restrict__ uhi, uint32_t m,
+                                                     const uint32_t* __restrict__ shape,
                                                      uint8_t* __restrict__ kstar,
                                                      uint32_t* __restrict__ bucket,
                                                      uint32_t* __restrict__ rank,
                                                      uint32_t* __restrict__ bhist,
                                                      int32_t* __restrict__ flag) {
-  __shared__ uint32_t sq[D][kQuant];
+  __shared__ uint32_t sq[D][kQuantPad];
 #pragma unroll
   for (int k = 0; k < D; ++k)
-    for (uint32_t i = threadIdx.x; i < kQuant; i += blockDim.x) sq[k][i] = T.quant[k][i];
+    for (uint32_t i = threadIdx.x; i < kQuant; i += blockDim.x) sq[k][qslot(i)] = T.quant[k][i];
   __syncthreads();
   const uint32_t j = blockIdx.x * blockDim.x + threadIdx.x;
   const bool act = j < m;
   bool bad = false;
   if (act) {
-    uint32_t best = 0xffffffffu, bk = 0, bqa = 0, bx = 0;
-    float mid[D];
-    uint32_t xh[D], xl[D], qa[D], qb[D];
-#pragma unroll
-    for (int k = 0; k < D; ++k) {
-      const float a = ulo[(size_t)k * m + j], b = uhi[(size_t)k * m + j];
-      bad = bad || !valid_extent(a, b);
-      mid[k] = 0.5f * a + 0.5f * b;
-      xh[k] = f2key(b);
-      xl[k] = f2key(nextafterf(a - T.maxlen[k], -INFINITY));
-      qa[k] = 0;
-      qb[k] = 0;
-    }
-    // the 2D quantile searches (#quantiles <= xh, #quantiles < xl per
-    // dimension) advance in lockstep, so their LDS reads overlap
-#pragma unroll
-    for (uint32_t step = kQuant; step > 0; step >>= 1) {
-#pragma unroll
-      for (int k = 0; k < D; ++k) {
-        const uint32_t ca = qa[k] + step, cb = qb[k] + step;
-        const uint32_t va = ca <= kQuant ? sq[k][ca - 1] : 0xffffffffu;
-        const uint32_t vb = cb <= kQuant ? sq[k][cb - 1] : 0xffffffffu;
-        if (ca <= kQuant && va <= xh[k]) qa[k] = ca;
-        if (cb <= kQuant && vb < xl[k]) qb[k] = cb;
-      }
-    }
-#pragma unroll
-    for (int k = 0; k < D; ++k) {
-      const uint32_t est = qa[k] - min(qa[k], qb[k]);
-      if (est < best) {
-        best = est;
-        bk = (uint32_t)k;
-        bqa = qa[k];
-        bx = xh[k];
-      }
-    }
+    const ProbeEst<D> P = probe_estimate<D>(T, sq, ulo, uhi, m, j);
+    bad = P.bad;
+    uint32_t bk = P.bk;
+    const uint32_t best = P.best, bqa = P.bqa, bx = P.bx;
     // position of q.hi in tree k*, interpolated between its two quantiles
     float fine;
     if (bqa == 0) {
@@ -175,8 +256,8 @@ __global__ __launch_bounds__(1024) void probe_kernel(TreeDev T, const float* __r
 #pragma unroll
       for (int k = 0; k < D; ++k)
         if ((uint32_t)k == bk) {
-          kl = sq[k][bqa - 1];
-          ku = sq[k][bqa];
+          kl = sq[k][qslot(bqa - 1)];
+          ku = sq[k][qslot(bqa)];
         }
       const float fr = ku > kl ? (float)(bx - kl) / (float)(ku - kl) : 0.f;
       fine = (float)(bqa - 1) + fminf(fr, 0.999f);
@@ -186,14 +267,15 @@ __global__ __launch_bounds__(1024) void probe_kernel(TreeDev T, const float* __r
       fine = 0.f;
     }
     kstar[j] = (uint8_t)bk;
-    constexpr uint32_t B0 = kProbeBins(D), B1 = kCellBins(D);
     uint32_t sub;
-    if (!bad && (uint64_t)best * T.n > (uint64_t)kCellRange * kQuant) {
+    if (!bad && cell_mode<D>(best, T.n)) {
+      const uint32_t e = shape[bk];
+      const uint32_t B1 = 1u << e, B0 = kLineBins >> ((D - 1) * e);
       sub = min((uint32_t)(fine * (float)B0 / (float)kQuant), B0 - 1u);
 #pragma unroll
       for (int k = 0; k < D; ++k) {
         if ((uint32_t)k == bk) continue;
-        const uint32_t qp = quant_count(sq[k], f2key(mid[k]), true);
+        const uint32_t qp = quant_count(sq[k], f2key(P.mid[k]), true);
         sub = sub * B1 + min(qp * B1 / (kQuant + 1u), B1 - 1u);
       }
       sub += kLineBins;
@@ -297,21 +379,20 @@ __global__ __launch_bounds__(1024) void bucket_scan_kernel(uint32_t* __restrict_
   }
 }
 
+// updates in bucket order; with tmap non-null also tile -> bucket for the
+// nb buckets (thread j does update j and bucket j)
 __global__ __launch_bounds__(256) void bucket_scatter_kernel(const uint32_t* __restrict__ bucket,
                                                              const uint32_t* __restrict__ rank,
                                                              uint32_t m,
                                                              const uint32_t* __restrict__ bhist,
-                                                             uint32_t* __restrict__ perm) {
+                                                             uint32_t* __restrict__ perm,
+                                                             const uint32_t* __restrict__ tprefix,
+                                                             uint32_t* __restrict__ tmap,
+                                                             uint32_t nb) {
   const uint32_t j = blockIdx.x * blockDim.x + threadIdx.x;
   if (j < m) perm[bhist[bucket[j]] + rank[j]] = j;
-}
-
-// tile -> bucket
-__global__ __launch_bounds__(256) void tile_map_kernel(const uint32_t* __restrict__ tprefix,
-                                                       uint32_t* __restrict__ tmap, uint32_t nb) {
-  const uint32_t b = blockIdx.x * blockDim.x + threadIdx.x;
-  if (b >= nb) return;
-  for (uint32_t t = tprefix[b]; t < tprefix[b + 1]; ++t) tmap[t] = b;
+  if (tmap && j < nb)
+    for (uint32_t t = tprefix[j]; t < tprefix[j + 1]; ++t) tmap[t] = j;
 }
 
 // --------------------------------------------------------------------------
@@ -931,6 +1012,7 @@ struct MatchState {
   uint32_t* perm = nullptr;
   uint32_t* gstart = nullptr;
   uint32_t* gcount = nullptr;
+  uint32_t* shape = nullptr;  // cell shape (log2 B1) of each probe dimension
   int32_t* flag = nullptr;
   uint32_t* cnt = nullptr;
   uint64_t* off = nullptr;
@@ -977,11 +1059,14 @@ struct MatchState {
 };
 
 // zeroes the match's counters; with a stash (snext non-null) also sets the
-// slices' next free chunks
-__global__ void match_init_kernel(uint32_t* __restrict__ gcount, int32_t* __restrict__ flag,
-                                  uint32_t* __restrict__ lists_count,
-                                  uint32_t* __restrict__ bhist, uint32_t* __restrict__ snext,
-                                  uint32_t sfirst, uint32_t sslice, uint32_t* __restrict__ maxcnt) {
+// slices' next free chunks; for d > 1 (D > 1) the last workgroup also picks
+// the cell shape of every probe dimension
+template <int D>
+__global__ __launch_bounds__(256) void match_init_kernel(
+    uint32_t* __restrict__ gcount, int32_t* __restrict__ flag, uint32_t* __restrict__ lists_count,
+    uint32_t* __restrict__ bhist, uint32_t* __restrict__ snext, uint32_t sfirst, uint32_t sslice,
+    uint32_t* __restrict__ maxcnt, TreeDev T, const float* __restrict__ ulo,
+    const float* __restrict__ uhi, uint32_t m, uint32_t* __restrict__ shape) {
   const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i < kBuckets) bhist[i] = 0;
   if (i < DDM_MAX_D) gcount[i] = 0;
@@ -991,6 +1076,9 @@ __global__ void match_init_kernel(uint32_t* __restrict__ gcount, int32_t* __rest
   }
   if (i < 2) lists_count[i] = 0;
   if (snext && i <= kStashSlices) snext[i] = i < kStashSlices ? sfirst + i * sslice : 0u;
+  if constexpr (D > 1) {
+    if (blockIdx.x == gridDim.x - 1) sample_cell_shape<D>(T, ulo, uhi, m, shape);
+  }
 }
 
 // the words the host reads after the count: dst[0] = K, dst[1] = the tree's
@@ -1004,14 +1092,20 @@ __global__ void gather_flags_kernel(const int32_t* __restrict__ tflag,
                                     const uint32_t* __restrict__ snext,
                                     const uint32_t* __restrict__ tprefix, uint32_t sfirst,
                                     uint32_t sslice, const uint32_t* __restrict__ maxcnt) {
-  if (threadIdx.x == 0) {
+  // one wavefront; the lanes share the slices
+  const uint32_t lane = threadIdx.x;
+  if (lane == 0) {
     dst[4] = *maxcnt;
     dst[0] = off[m];
     dst[1] = (uint64_t)(uint32_t)(*tflag) | ((uint64_t)(uint32_t)(*uflag) << 32);
-    if (snext) {
-      uint32_t mx = 0;
-      for (uint32_t s = 0; s < kStashSlices; ++s)
-        mx = max(mx, min(snext[s] - (sfirst + s * sslice), sslice));
+  }
+  if (snext) {
+    uint32_t mx = 0;
+    for (uint32_t s = lane; s < kStashSlices; s += kWave)
+      mx = max(mx, min(snext[s] - (sfirst + s * sslice), sslice));
+#pragma unroll
+    for (int o = kWave / 2; o > 0; o >>= 1) mx = max(mx, (uint32_t)__shfl_xor((int)mx, o, kWave));
+    if (lane == 0) {
       dst[2] = ((uint64_t)tprefix[kBuckets] << 32) | mx;
       dst[3] = snext[kStashSlices];
     }
@@ -1028,8 +1122,8 @@ static ddm_status launch_probe(const TreeDev& T, const float* ulo, const float* 
     DDM_LAUNCHED("bits1_kernel");
   } else {
     ProfScope ps("probe", s);
-    probe_kernel<D><<<(m + 1023) / 1024, 1024, 0, s>>>(T, ulo, uhi, m, st.kstar, st.bucket,
-                                                       st.rank, st.bhist, st.flag);
+    probe_kernel<D><<<(m + 1023) / 1024, 1024, 0, s>>>(T, ulo, uhi, m, st.shape, st.kstar,
+                                                       st.bucket, st.rank, st.bhist, st.flag);
     DDM_LAUNCHED("probe_kernel");
   }
   return DDM_OK;
@@ -1144,6 +1238,7 @@ static ddm_status front_half(const ddm_tree* t, const float* ulo, const float* u
   sc.reserve(sizeof(uint32_t) * kBuckets);   // bucket histogram / offsets
   sc.reserve(sizeof(uint32_t) * DDM_MAX_D);  // gstart
   sc.reserve(sizeof(uint32_t) * DDM_MAX_D);  // gcount
+  sc.reserve(sizeof(uint32_t) * DDM_MAX_D);  // shape
   sc.reserve(sizeof(int32_t));               // flag
   sc.reserve(sizeof(uint32_t) * m);          // cnt
   sc.reserve(sizeof(uint64_t) * (m + 1));    // off
@@ -1164,6 +1259,7 @@ static ddm_status front_half(const ddm_tree* t, const float* ulo, const float* u
   st.bhist = sc.take<uint32_t>(kBuckets);
   st.gstart = sc.take<uint32_t>(DDM_MAX_D);
   st.gcount = sc.take<uint32_t>(DDM_MAX_D);
+  st.shape = sc.take<uint32_t>(DDM_MAX_D);
   st.m = m;
   st.flag = sc.take<int32_t>(1);
   st.cnt = sc.take<uint32_t>(m);
@@ -1213,10 +1309,22 @@ static ddm_status front_half(const ddm_tree* t, const float* ulo, const float* u
       if (!st.stash_sc.fits()) return scratch_overrun("stash");
     }
   }
-  match_init_kernel<<<kBuckets / 256, 256, 0, s>>>(st.gcount, st.flag, *lists_count, st.bhist,
-                                                   st.stash ? st.snext : nullptr, st.sfirst,
-                                                   st.sslice, st.maxcnt);
-  DDM_LAUNCHED("match_init_kernel");
+  {
+    uint32_t* sn = st.stash ? st.snext : nullptr;
+    const unsigned g = kBuckets / 256;
+#define DDM_INIT(DD)                                                                         \
+  match_init_kernel<DD><<<g, 256, 0, s>>>(st.gcount, st.flag, *lists_count, st.bhist, sn,   \
+                                          st.sfirst, st.sslice, st.maxcnt, T, ulo, uhi, m, \
+                                          st.shape)
+    switch (d) {
+      case 1: DDM_INIT(1); break;
+      case 2: DDM_INIT(2); break;
+      case 3: DDM_INIT(3); break;
+      default: DDM_INIT(4); break;
+    }
+#undef DDM_INIT
+    DDM_LAUNCHED("match_init_kernel");
+  }
   ddm_status r;
   switch (d) {
     case 1: r = launch_probe<1>(T, ulo, uhi, m, st, s); break;
@@ -1235,14 +1343,11 @@ static ddm_status front_half(const ddm_tree* t, const float* ulo, const float* u
       default: bucket_scan_kernel<32><<<1, 1024, 0, s>>>(st.bhist, m, st.gstart, st.gcount, tp); break;
     }
     DDM_LAUNCHED("bucket_scan_kernel");
-    bucket_scatter_kernel<<<(m + 255) / 256, 256, 0, s>>>(st.bucket, st.rank, m, st.bhist,
-                                                          st.perm);
+    const bool tiles = P.traversal == DDM_TRAVERSE_TILE;
+    const uint32_t nb = tiles ? d * kBucketsPerDim : 0u;
+    bucket_scatter_kernel<<<(std::max(m, nb) + 255) / 256, 256, 0, s>>>(
+        st.bucket, st.rank, m, st.bhist, st.perm, st.tprefix, tiles ? st.tmap : nullptr, nb);
     DDM_LAUNCHED("bucket_scatter_kernel");
-    if (P.traversal == DDM_TRAVERSE_TILE) {
-      const uint32_t nb = d * kBucketsPerDim;
-      tile_map_kernel<<<(nb + 255) / 256, 256, 0, s>>>(st.tprefix, st.tmap, nb);
-      DDM_LAUNCHED("tile_map_kernel");
-    }
   }
   // per-update counts
   const uint32_t* counts = st.cmin;

@@ -217,19 +217,29 @@ ddm_status sort_setup_small(const SortArr* host_arrs, uint32_t narr, SortArr* ar
 //
 // The digit totals of every pass come from one histogram kernel (they do not
 // depend on the order of the keys).  Each pass is then one kernel: a tile
-// (2048 keys, 512 per wavefront in order) ranks its keys with per-wavefront
-// digit counters (no workgroup barrier per round), publishes its digit
-// counts, and takes the counts of the tiles before it in the same array by
-// decoupled look-back: each digit walks back over the tiles' published
-// (flag, count) words until one holds an inclusive prefix.  Tiles take their
-// index from a counter in the order they start, so every tile they wait for
-// has started and publishes without waiting on later tiles.  A wait longer
-// than kOsSpinLimit sleeps gives up, raises kFlagSortTimeout in *err and
-// goes on with a wrong offset, so that every wave still exits.
+// (4096 or 8192 keys, 512 per wavefront in order) ranks its keys with
+// per-wavefront digit counters (no workgroup barrier per round), publishes
+// its digit counts, and takes the counts of the tiles before it in the same
+// array by decoupled look-back: each digit walks back over the tiles'
+// published (flag, count) words until one holds an inclusive prefix.  The
+// look-back reads grow with the square of the tiles per array, and every
+// tile runs its phases one after another (load, rank, look-back, stage,
+// write), so few large tiles with many wavefronts each are faster than many
+// small ones, as long as there are compute units for more of them.  When
+// the device holds every tile at once a tile takes its index from its
+// workgroup; otherwise from a counter in the order tiles start, so every
+// tile they wait for has started and publishes without waiting on later
+// tiles.  A wait longer than kOsSpinLimit sleeps gives up, raises
+// kFlagSortTimeout in *err and goes on with a wrong offset, so that every
+// wave still exits.
 // ---------------------------------------------------------------------------
 constexpr uint32_t kOsHistKeys = 4096;  // keys per workgroup of the histogram kernel
 constexpr uint32_t kOsWindow = 8;       // predecessor tiles read together in a look-back step
-constexpr uint32_t kOsTile = 4096;      // keys per tile of a pass
+// tiles of a pass: 4096 keys and 512 threads while one tile per compute
+// unit covers the arrays, otherwise 8192 keys and 1024 threads (8 keys per
+// lane either way)
+constexpr uint32_t kOsTileSmall = 4096, kOsThreadsSmall = 512;
+constexpr uint32_t kOsTileLarge = 8192, kOsThreadsLarge = 1024;
 constexpr uint64_t kOsAgg = 1ull << 32, kOsIncl = 2ull << 32;
 constexpr uint32_t kOsSpinLimit = 1u << 22;
 
@@ -280,19 +290,21 @@ __global__ __launch_bounds__(kSortThreads) void os_hist_kernel(OsDesc D, uint32_
   }
 }
 
-__global__ __launch_bounds__(kSortThreads) void os_pass_kernel(OsDesc D,
-                                                               const uint32_t* __restrict__ ghist,
-                                                               uint32_t* __restrict__ ctr,
-                                                               uint64_t* __restrict__ status,
-                                                               uint32_t ntiles, int pass,
-                                                               int32_t* __restrict__ err,
-                                                               uint32_t direct) {
-  constexpr uint32_t W = kSortThreads / kWave;
-  constexpr uint32_t R = kOsTile / kSortThreads;  // keys per lane
+template <uint32_t kOsThreads, uint32_t kOsTile>
+__global__ __launch_bounds__(kOsThreads) void os_pass_kernel(OsDesc D,
+                                                            const uint32_t* __restrict__ ghist,
+                                                            uint32_t* __restrict__ ctr,
+                                                            uint64_t* __restrict__ status,
+                                                            uint32_t ntiles, int pass,
+                                                            int32_t* __restrict__ err,
+                                                            uint32_t direct) {
+  constexpr uint32_t W = kOsThreads / kWave;  // wavefronts ranking the tile
+  constexpr uint32_t DW = 256 / kWave;        // wavefronts that own one digit per lane
+  constexpr uint32_t R = kOsTile / kOsThreads;  // keys per lane
   __shared__ uint32_t s_t;
   __shared__ uint32_t wcnt[W][256];
   __shared__ uint32_t woff[W][256];
-  __shared__ uint32_t wsum[2][W];
+  __shared__ uint32_t wsum[2][DW];
   __shared__ uint32_t ldst[256];  // first slot of each digit in the tile's staged order
   __shared__ uint32_t gpos[256];  // where that run starts in the output
   __shared__ uint32_t lkey[kOsTile];
@@ -313,6 +325,10 @@ __global__ __launch_bounds__(kSortThreads) void os_pass_kernel(OsDesc D,
   const uint32_t tn = min(kOsTile, A.n - tbase);  // keys in this tile
   const uint32_t base = tbase + wave * (R * kWave);
   const uint32_t shift = 8u * (uint32_t)pass;
+  // the first DW wavefronts own one digit per lane in the scans below
+  const bool owner = tid < 256;
+  const uint32_t d = tid & 255u;
+  const uint32_t g = owner ? ghist[((size_t)a * 4 + pass) * 256 + d] : 0u;
   uint32_t key[R], val[R], loc[R];
 #pragma unroll
   for (uint32_t r = 0; r < R; ++r) {
@@ -321,7 +337,7 @@ __global__ __launch_bounds__(kSortThreads) void os_pass_kernel(OsDesc D,
     key[r] = valid ? ks[i] : 0u;
     val[r] = (valid && vs) ? vs[i] : 0u;
   }
-  // ranks inside the wavefront's 512 keys, in key order (stable)
+  // ranks inside the wavefront's R * 64 keys, in key order (stable)
 #pragma unroll
   for (uint32_t r = 0; r < R; ++r) {
     const bool valid = base + r * kWave + lane < A.n;
@@ -333,19 +349,15 @@ __global__ __launch_bounds__(kSortThreads) void os_pass_kernel(OsDesc D,
     if (valid && rk == 0) wcnt[wave][dig] = b + (uint32_t)__popcll(peers);
   }
   __syncthreads();
-  {
-    // thread d: the tile's count of digit d, the digit's base in the array
-    // and in the tile (scans over the digits), and the count of digit d in
-    // the array's earlier tiles (look-back)
-    const uint32_t d = tid;
-    uint32_t c[W], tc = 0;
+  // digit owners: the tile's count of digit d, the digit's base in the array
+  // and in the tile (scans over the digits), and the count of digit d in the
+  // array's earlier tiles (look-back)
+  uint32_t inc = 0, inc2 = 0, tc = 0, excl = 0;
+  if (owner) {
 #pragma unroll
-    for (uint32_t w = 0; w < W; ++w) {
-      c[w] = wcnt[w][d];
-      tc += c[w];
-    }
-    const uint32_t g = ghist[((size_t)a * 4 + pass) * 256 + d];
-    uint32_t inc = g, inc2 = tc;
+    for (uint32_t w = 0; w < W; ++w) tc += wcnt[w][d];
+    inc = g;
+    inc2 = tc;
 #pragma unroll
     for (int o = 1; o < kWave; o <<= 1) {
       const uint32_t x = (uint32_t)__shfl_up((int)inc, o, kWave);
@@ -360,7 +372,6 @@ __global__ __launch_bounds__(kSortThreads) void os_pass_kernel(OsDesc D,
       wsum[1][wave] = inc2;
     }
     uint64_t* __restrict__ st = status + (size_t)pass * ntiles * 256;
-    uint32_t excl = 0;
     if (lt == 0) {
       __hip_atomic_store(st + (size_t)t * 256 + d, kOsIncl | tc, __ATOMIC_RELAXED,
                          __HIP_MEMORY_SCOPE_AGENT);
@@ -406,7 +417,9 @@ __global__ __launch_bounds__(kSortThreads) void os_pass_kernel(OsDesc D,
       __hip_atomic_store(st + (size_t)t * 256 + d, kOsIncl | (excl + tc), __ATOMIC_RELAXED,
                          __HIP_MEMORY_SCOPE_AGENT);
     }
-    __syncthreads();
+  }
+  __syncthreads();
+  if (owner) {
     uint32_t gb = inc - g, lb = inc2 - tc;
     for (uint32_t w = 0; w < wave; ++w) {
       gb += wsum[0][w];
@@ -418,7 +431,7 @@ __global__ __launch_bounds__(kSortThreads) void os_pass_kernel(OsDesc D,
 #pragma unroll
     for (uint32_t w = 0; w < W; ++w) {
       woff[w][d] = run;
-      run += c[w];
+      run += wcnt[w][d];
     }
   }
   __syncthreads();
@@ -435,7 +448,7 @@ __global__ __launch_bounds__(kSortThreads) void os_pass_kernel(OsDesc D,
     }
   }
   __syncthreads();
-  for (uint32_t i = tid; i < tn; i += kSortThreads) {
+  for (uint32_t i = tid; i < tn; i += kOsThreads) {
     const uint32_t k = lkey[i];
     const uint32_t dig = (k >> shift) & 255u;
     const uint32_t pos = gpos[dig] + (i - ldst[dig]);
@@ -446,34 +459,67 @@ __global__ __launch_bounds__(kSortThreads) void os_pass_kernel(OsDesc D,
   }
 }
 
-// workgroups of the pass kernel the current device holds at once (0 if
-// the runtime cannot say, which keeps the counter); asked once per device
-static uint32_t os_resident_blocks() {
-  constexpr int kDevs = 64;
-  static std::atomic<uint32_t> cache[kDevs];  // value + 1, 0 = not asked yet
-  int dev = 0, cus = 0, per = 0;
+// compute units of the current device (0 if the runtime cannot say); and
+// workgroups of a pass kernel the device holds at once (0 if unknown, which
+// keeps the counter); each asked once per device
+constexpr int kOsDevs = 64;
+
+static uint32_t os_device() {
+  int dev = 0;
   if (hipGetDevice(&dev) != hipSuccess) {
     (void)hipGetLastError();
-    return 0;
+    return ~0u;
   }
-  if (dev >= 0 && dev < kDevs) {
-    const uint32_t c = cache[dev].load(std::memory_order_relaxed);
-    if (c) return c - 1;
-  }
+  return dev >= 0 && dev < kOsDevs ? (uint32_t)dev : ~0u;
+}
+
+static uint32_t os_cus() {
+  static std::atomic<uint32_t> cache[kOsDevs];  // value + 1, 0 = not asked yet
+  const uint32_t dev = os_device();
+  if (dev == ~0u) return 0;
+  const uint32_t c = cache[dev].load(std::memory_order_relaxed);
+  if (c) return c - 1;
+  int cus = 0;
   uint32_t r = 0;
-  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess &&
-      hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, (const void*)os_pass_kernel,
-                                                   kSortThreads, 0) == hipSuccess) {
-    r = (uint32_t)std::max(0, cus) * (uint32_t)std::max(0, per);
-  } else {
+  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, (int)dev) == hipSuccess)
+    r = (uint32_t)std::max(0, cus);
+  else
     (void)hipGetLastError();
-  }
-  if (dev >= 0 && dev < kDevs) cache[dev].store(r + 1, std::memory_order_relaxed);
+  cache[dev].store(r + 1, std::memory_order_relaxed);
   return r;
 }
 
-static void os_layout(const SortArr* host_arrs, uint32_t narr, OsDesc* D, uint32_t* nhblk,
-                      uint32_t* ntiles) {
+template <uint32_t THREADS, uint32_t TILE>
+static uint32_t os_resident_blocks() {
+  static std::atomic<uint32_t> cache[kOsDevs];  // value + 1, 0 = not asked yet
+  const uint32_t dev = os_device();
+  if (dev == ~0u) return 0;
+  const uint32_t c = cache[dev].load(std::memory_order_relaxed);
+  if (c) return c - 1;
+  int per = 0;
+  uint32_t r = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(
+          &per, (const void*)os_pass_kernel<THREADS, TILE>, THREADS, 0) == hipSuccess)
+    r = os_cus() * (uint32_t)std::max(0, per);
+  else
+    (void)hipGetLastError();
+  cache[dev].store(r + 1, std::memory_order_relaxed);
+  return r;
+}
+
+static uint32_t os_tiles(const SortArr* host_arrs, uint32_t narr, uint32_t tile) {
+  uint32_t tl = 0;
+  for (uint32_t i = 0; i < narr; ++i) tl += (host_arrs[i].n + tile - 1) / tile;
+  return tl;
+}
+
+// the tile size of a sort of these arrays
+static uint32_t os_tile_keys(const SortArr* host_arrs, uint32_t narr) {
+  return os_tiles(host_arrs, narr, kOsTileSmall) <= os_cus() ? kOsTileSmall : kOsTileLarge;
+}
+
+static void os_layout(const SortArr* host_arrs, uint32_t narr, uint32_t tile, OsDesc* D,
+                      uint32_t* nhblk, uint32_t* ntiles) {
   uint32_t hb = 0, tl = 0;
   *D = OsDesc{};
   D->narr = narr;
@@ -482,7 +528,7 @@ static void os_layout(const SortArr* host_arrs, uint32_t narr, OsDesc* D, uint32
     D->hblk0[i] = hb;
     D->tile0[i] = tl;
     hb += (host_arrs[i].n + kOsHistKeys - 1) / kOsHistKeys;
-    tl += (host_arrs[i].n + kOsTile - 1) / kOsTile;
+    tl += (host_arrs[i].n + tile - 1) / tile;
   }
   D->hblk0[narr] = hb;
   D->tile0[narr] = tl;
@@ -493,7 +539,8 @@ static void os_layout(const SortArr* host_arrs, uint32_t narr, OsDesc* D, uint32
 size_t radix_onesweep_scratch_bytes(const SortArr* host_arrs, uint32_t narr, int npasses) {
   OsDesc D;
   uint32_t hb, tl;
-  os_layout(host_arrs, narr, &D, &hb, &tl);
+  // the smaller tiles bound the status words of either tile size
+  os_layout(host_arrs, narr, kOsTileSmall, &D, &hb, &tl);
   return 256 + sizeof(uint32_t) * 1024 * (size_t)narr + sizeof(uint64_t) * 256 * (size_t)tl *
                                                             (size_t)(npasses > 0 ? npasses : 1);
 }
@@ -507,7 +554,7 @@ ddm_status radix_sort_onesweep(const SortArr* host_arrs, uint32_t narr, int npas
   if (npasses == 0) return DDM_OK;
   OsDesc D;
   uint32_t hb, tl;
-  os_layout(host_arrs, narr, &D, &hb, &tl);
+  os_layout(host_arrs, narr, os_tile_keys(host_arrs, narr), &D, &hb, &tl);
   if (tl == 0) return DDM_OK;
   uint32_t* ctr = (uint32_t*)scratch;  // 4 counters, padded to 256 bytes
   uint32_t* ghist = (uint32_t*)((char*)scratch + 256);
@@ -525,10 +572,18 @@ ddm_status radix_sort_onesweep(const SortArr* host_arrs, uint32_t narr, int npas
   // when every workgroup of a pass fits on the device at once, a tile takes
   // its index from its workgroup (every tile it waits for is running);
   // otherwise from a counter in start order
-  const uint32_t direct = tl <= os_resident_blocks() ? 1u : 0u;
+  const bool small = os_tile_keys(host_arrs, narr) == kOsTileSmall;
+  const uint32_t resident = small ? os_resident_blocks<kOsThreadsSmall, kOsTileSmall>()
+                                  : os_resident_blocks<kOsThreadsLarge, kOsTileLarge>();
+  const uint32_t direct = tl <= resident ? 1u : 0u;
   for (int p = 0; p < npasses; ++p) {
     ProfScope ps("radix_scatter", s);
-    os_pass_kernel<<<tl, kSortThreads, 0, s>>>(D, ghist, ctr, status, tl, p, err, direct);
+    if (small)
+      os_pass_kernel<kOsThreadsSmall, kOsTileSmall>
+          <<<tl, kOsThreadsSmall, 0, s>>>(D, ghist, ctr, status, tl, p, err, direct);
+    else
+      os_pass_kernel<kOsThreadsLarge, kOsTileLarge>
+          <<<tl, kOsThreadsLarge, 0, s>>>(D, ghist, ctr, status, tl, p, err, direct);
     DDM_LAUNCHED("os_pass_kernel");
   }
   return DDM_OK;

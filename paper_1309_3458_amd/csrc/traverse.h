@@ -479,7 +479,14 @@ __device__ __forceinline__ void tile_body(const TreeDev& T, const float* __restr
   }
 }
 
-// number of quantiles <= x (upper) or < x, LDS binary lifting
+// Quantiles held in LDS are padded by one word after every 64: the lanes of
+// a binary search read indices a power of two apart, which without padding
+// fall into one LDS bank at the middle levels of the search.
+constexpr uint32_t kQuantPad = kQuant + kQuant / 64;
+__device__ __forceinline__ uint32_t qslot(uint32_t i) { return i + (i >> 6); }
+
+// number of quantiles <= x (upper) or < x, LDS binary lifting over the
+// padded copy
 __device__ __forceinline__ uint32_t quant_count(const uint32_t* __restrict__ q, uint32_t x,
                                                 bool upper) {
   uint32_t pos = 0;
@@ -487,7 +494,7 @@ __device__ __forceinline__ uint32_t quant_count(const uint32_t* __restrict__ q, 
   for (uint32_t step = kQuant; step > 0; step >>= 1) {
     const uint32_t c = pos + step;
     if (c <= kQuant) {
-      const uint32_t v = q[c - 1];
+      const uint32_t v = q[qslot(c - 1)];
       if (upper ? (v <= x) : (v < x)) pos = c;
     }
   }
