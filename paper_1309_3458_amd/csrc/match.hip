@@ -187,12 +187,15 @@ __device__ __forceinline__ bool cell_mode(uint32_t best, uint32_t n) {
   return (uint64_t)best * n > (uint64_t)kCellRange * kQuant;
 }
 
-// The cell shape of each probe dimension (run by one workgroup of 256
-// threads): the most common cell_log2 over up to 256 updates spread evenly
-// over the set, among those that would take that dimension with cells.
+// The cell shape of each probe dimension (run by one workgroup of at least
+// kShapeSamples threads): the most common cell_log2 over up to
+// kShapeSamples updates spread evenly over the set, among those that would
+// take that dimension with cells.
 // One shape per dimension keeps the cells of different updates from sharing
 // buckets while meaning different boxes (a tile that mixed them would scan
 // the union of far-apart ranges).
+constexpr uint32_t kShapeSamples = 256;
+
 template <int D>
 __device__ __forceinline__ void sample_cell_shape(const TreeDev& T, const float* __restrict__ ulo,
                                                   const float* __restrict__ uhi, uint32_t m,
@@ -204,11 +207,24 @@ __device__ __forceinline__ void sample_cell_shape(const TreeDev& T, const float*
   for (int k = 0; k < D; ++k)
     for (uint32_t i = threadIdx.x; i < kQuant; i += blockDim.x) sq[k][qslot(i)] = T.quant[k][i];
   __syncthreads();
-  const uint32_t S = min(m, (uint32_t)blockDim.x);
-  if (threadIdx.x < S) {
-    const uint32_t j = (uint32_t)(((uint64_t)threadIdx.x * m) / S);
-    const ProbeEst<D> P = probe_estimate<D>(T, sq, ulo, uhi, m, j);
-    if (!P.bad && cell_mode<D>(P.best, T.n)) atomicAdd(&hist[P.bk][cell_log2<D>(P.best)], 1u);
+  const uint32_t S = min(m, kShapeSamples);
+  if (threadIdx.x < kShapeSamples) {
+    // (k*, shape) of this lane's sample, or none; counted per wavefront
+    // (one LDS add per distinct value, as the samples mostly agree)
+    uint32_t key = ~0u;
+    if (threadIdx.x < S) {
+      const uint32_t j = (uint32_t)(((uint64_t)threadIdx.x * m) / S);
+      const ProbeEst<D> P = probe_estimate<D>(T, sq, ulo, uhi, m, j);
+      if (!P.bad && cell_mode<D>(P.best, T.n)) key = P.bk * 16u + cell_log2<D>(P.best);
+    }
+    uint64_t left = ballot(key != ~0u);
+    while (left) {
+      const uint32_t lead = (uint32_t)__builtin_ctzll(left);
+      const uint32_t lk = (uint32_t)__shfl((int)key, (int)lead, kWave);
+      const uint64_t same = ballot(key == lk) & left;
+      if (lane_id() == lead) atomicAdd(&hist[lk / 16u][lk % 16u], (uint32_t)__popcll(same));
+      left &= ~same;
+    }
   }
   __syncthreads();
   if (threadIdx.x < D) {
@@ -1062,7 +1078,7 @@ struct MatchState {
 // slices' next free chunks; for d > 1 (D > 1) the last workgroup also picks
 // the cell shape of every probe dimension
 template <int D>
-__global__ __launch_bounds__(256) void match_init_kernel(
+__global__ __launch_bounds__(1024) void match_init_kernel(
     uint32_t* __restrict__ gcount, int32_t* __restrict__ flag, uint32_t* __restrict__ lists_count,
     uint32_t* __restrict__ bhist, uint32_t* __restrict__ snext, uint32_t sfirst, uint32_t sslice,
     uint32_t* __restrict__ maxcnt, TreeDev T, const float* __restrict__ ulo,
@@ -1311,9 +1327,9 @@ static ddm_status front_half(const ddm_tree* t, const float* ulo, const float* u
   }
   {
     uint32_t* sn = st.stash ? st.snext : nullptr;
-    const unsigned g = kBuckets / 256;
-#define DDM_INIT(DD)                                                                         \
-  match_init_kernel<DD><<<g, 256, 0, s>>>(st.gcount, st.flag, *lists_count, st.bhist, sn,   \
+    const unsigned g = kBuckets / 1024;
+#define DDM_INIT(DD)                                                                          \
+  match_init_kernel<DD><<<g, 1024, 0, s>>>(st.gcount, st.flag, *lists_count, st.bhist, sn,   \
                                           st.sfirst, st.sslice, st.maxcnt, T, ulo, uhi, m, \
                                           st.shape)
     switch (d) {
