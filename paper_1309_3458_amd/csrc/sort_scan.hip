@@ -279,9 +279,19 @@ __global__ __launch_bounds__(kSortThreads) void os_hist_kernel(OsDesc D, uint32_
   const uint32_t begin = (blockIdx.x - D.hblk0[a]) * kOsHistKeys;
   const uint32_t end = min(A.n, begin + kOsHistKeys);
   const uint32_t* __restrict__ src = A.k[0];
-  for (uint32_t i = begin + tid; i < end; i += kSortThreads) {
-    const uint32_t k = src[i];
-    for (int p = 0; p < npasses; ++p) atomicAdd(&h[p][(k >> (8 * p)) & 255u], 1u);
+  // all of this thread's keys are loaded before any is counted, so that the
+  // loads are in flight together
+  constexpr uint32_t R = kOsHistKeys / kSortThreads;
+  uint32_t key[R];
+#pragma unroll
+  for (uint32_t r = 0; r < R; ++r) {
+    const uint32_t i = begin + r * kSortThreads + tid;
+    key[r] = i < end ? src[i] : 0u;
+  }
+#pragma unroll
+  for (uint32_t r = 0; r < R; ++r) {
+    if (begin + r * kSortThreads + tid >= end) break;
+    for (int p = 0; p < npasses; ++p) atomicAdd(&h[p][(key[r] >> (8 * p)) & 255u], 1u);
   }
   __syncthreads();
   for (int p = 0; p < npasses; ++p) {
