@@ -231,9 +231,10 @@ SWAP_AUTO, SWAP_NEVER, SWAP_ALWAYS = 0, 1, 2
 
 def match_sets(s_lo, s_hi, u_lo, u_hi, swap=SWAP_AUTO, stream=None, out=None,
                return_swapped=False):
-    """build() + match() for two sets given together, with the tree on the
-    smaller set (roles of subscriptions and updates swapped when n > m under
-    SWAP_AUTO); the keys are the same as build(s) + match(u)."""
+    """build() + match() for two sets given together, optionally with the
+    tree on the smaller set (roles of subscriptions and updates swapped when
+    n > m and d >= 3 under SWAP_AUTO, always under SWAP_ALWAYS); the keys
+    are the same as build(s) + match(u)."""
     torch = _torch()
     s_lo, s_hi = _coords(s_lo, s_hi, "match_sets subscriptions")
     u_lo, u_hi = _coords(u_lo, u_hi, "match_sets updates")

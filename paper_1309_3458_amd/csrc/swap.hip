@@ -61,7 +61,10 @@ extern "C" ddm_status ddm_match_sets(const float* sub_lo, const float* sub_hi, u
     }
     swap = true;
   } else if (swap_policy == DDM_SWAP_AUTO) {
-    swap = n > m && small_cap;
+    // measured: with d <= 2 the per-update work and the transposition cost
+    // more than the larger tree saves; with d >= 3 the larger tree's long
+    // candidate ranges dominate
+    swap = n > m && d >= 3 && small_cap;
   }
   hipStream_t s = (hipStream_t)stream;
   ddm_tree* t = nullptr;
