@@ -570,6 +570,9 @@ __device__ __forceinline__ void bitonic_regs(uint64_t (&v)[N]) {
 // The traversal is latency-bound, so the register budget is set for eight
 // wavefronts per SIMD (the d = 2 stash form then keeps two values in
 // scratch, and measured 5% faster than at seven wavefronts).
+constexpr uint32_t kXcds = 8;     // accelerator dies (each with its own L2) of the device
+constexpr uint32_t kXcdRun = 32;  // consecutive workgroups of tiles given to one die
+
 template <int D, bool FILL, bool STASH = false>
 __global__ __launch_bounds__(kTileWaves * kWave) __attribute__((amdgpu_waves_per_eu(8)))
 void tile_bucket_kernel(
@@ -584,7 +587,20 @@ void tile_bucket_kernel(
   const uint32_t lane = lane_id();
   const uint32_t total = uniform_u32(US.tprefix[kBuckets]);
   {
-    const uint32_t item = blockIdx.x * kTileWaves + wave;
+    // Workgroups go to the XCDs in turn (workgroup i to XCD i mod kXcds).
+    // Neighbouring tiles (the cells of one probe range) scan the same part
+    // of the tree, so within each window of kXcds * kXcdRun workgroups the
+    // ones on XCD x take kXcdRun consecutive groups of tiles, whose scans
+    // then share that XCD's L2; the workgroups past the last whole window
+    // keep their order.  Any one-to-one map is correct; this one only
+    // changes which L2 serves a tile (measured at 10^6 boxes: d = 2, alpha
+    // = 1 -1%, d = 3 -8%, d = 4 -25%, d = 2, alpha = 10 +7%).
+    const uint32_t nblk = (total + kTileWaves - 1) / kTileWaves;
+    uint32_t blk = blockIdx.x;
+    if (blk >= nblk) return;
+    constexpr uint32_t W = kXcds * kXcdRun;
+    if (blk < nblk / W * W) blk = blk / W * W + blk % kXcds * kXcdRun + blk % W / kXcds;
+    const uint32_t item = blk * kTileWaves + wave;
     if (item >= total) return;
     const uint32_t b = uniform_u32(US.tmap[item]);
     const uint32_t lt = item - uniform_u32(US.tprefix[b]);
