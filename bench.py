@@ -116,7 +116,7 @@ def candidates(inst):
 # (profiles/traffic_d2_N1e6_alpha1_pmc.md): FETCH_SIZE x 2.000 and
 # WRITE_SIZE x 1.000, the factors a 1 GiB device copy calibrates.
 TRAFFIC_BYTES = {("d2_N1e6_alpha1_uniform", "plain", "traverse_tile_count_stash"):
-                 (161933.6 * 2.0 + 38446.0 * 1.0) * 1024}
+                 (90790.3 * 2.0 + 38934.2 * 1.0) * 1024}
 
 
 def roofline_alu(cand, ops, dom, dom_avg_ms, traffic=None):
