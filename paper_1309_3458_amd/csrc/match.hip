@@ -669,6 +669,8 @@ __global__ __launch_bounds__(256) void segsort_small_kernel(const uint64_t* __re
     sort_small_segment<8>(src, out + b, len);
   } else if (len <= 16) {
     sort_small_segment<16>(src, out + b, len);
+  } else if (len <= 32) {
+    sort_small_segment<32>(src, out + b, len);
   } else if (len <= kSegMid) {
     lists[atomicAdd(&list_count[0], 1u)] = j;
   } else {
@@ -676,7 +678,7 @@ __global__ __launch_bounds__(256) void segsort_small_kernel(const uint64_t* __re
   }
 }
 
-// One wavefront per listed segment (17..2048 keys).  The segment's ids are
+// One wavefront per listed segment (33..2048 keys).  The segment's ids are
 // staged through LDS (coalesced global reads and writes) into registers in
 // blocked order, V = P2/64 per lane (P2 = the segment length rounded up to a
 // power of two, at least 64), and sorted by a bitonic network: exchanges of
@@ -1545,7 +1547,7 @@ ddm_status sort_segments(const uint64_t* off, uint32_t m, uint64_t* out, uint64_
   ProfScope ps("segsort", s);
   segsort_small_kernel<<<(m + 255) / 256, 256, 0, s>>>(off, m, out, S, lists, lists_count);
   DDM_LAUNCHED("segsort_small_kernel");
-  if (max_len <= 16) return DDM_OK;  // every segment sorted in registers
+  if (max_len <= 32) return DDM_OK;  // every segment sorted in registers
   segsort_mid_kernel<<<4096, kSegWaves * kWave, 0, s>>>(off, out, S, lists, lists_count);
   DDM_LAUNCHED("segsort_mid_kernel");
   if (max_len <= kSegMid) return DDM_OK;
