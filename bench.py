@@ -137,17 +137,24 @@ def roofline_alu(cand, ops, dom, dom_avg_ms, traffic=None):
 def evented_steps(step, steps):
     """Run `steps` steps with a HIP event between consecutive steps on the
     current stream; returns (wall ms per step, per-step ms list, last K)."""
+    import gc
     import torch
     ev = [torch.cuda.Event(enable_timing=True) for _ in range(steps + 1)]
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    ev[0].record()
-    K = None
-    for i in range(steps):
-        K = step()
-        ev[i + 1].record()
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
+    # no collector pause of the host inside the timed region
+    gc.collect()
+    gc.disable()
+    try:
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        ev[0].record()
+        K = None
+        for i in range(steps):
+            K = step()
+            ev[i + 1].record()
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+    finally:
+        gc.enable()
     per = [ev[i].elapsed_time(ev[i + 1]) for i in range(steps)]
     return (t1 - t0) * 1e3 / steps, per, K
 
