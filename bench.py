@@ -110,13 +110,89 @@ def candidates(inst):
     return float(c.sum())
 
 
-# Calibrated FETCH_SIZE + WRITE_SIZE of the dominant traversal at the default
-# workload, bytes per launch, keyed (workload, path, kernel); valid for the
-# version of the tile traversal the counters were taken on
-# (profiles/traffic_d2_N1e6_alpha1_pmc.md): FETCH_SIZE x 2.000 and
-# WRITE_SIZE x 1.000, the factors a 1 GiB device copy calibrates.
-TRAFFIC_BYTES = {("d2_N1e6_alpha1_uniform", "plain", "traverse_tile_count_stash"):
-                 (90790.3 * 2.0 + 38934.2 * 1.0) * 1024}
+# HBM traffic counters (rocprofv3 FETCH_SIZE, WRITE_SIZE; KiB per dispatch)
+# of the default workload's plain path, calibrated by a 1 GiB device copy
+# (FETCH x 2.000, WRITE x 1.000: the copy's FETCH_SIZE reads half its bytes).
+# They hold only for the kernel sources they were taken on: `sha` is the
+# SHA-256 (first 16 hex digits) of the files in TRAFFIC_SOURCES, and a build
+# from other sources reports the traffic as null.  `kernel` is the dominant
+# kernel's own launch; `step` sums every kernel of one build + match step.
+TRAFFIC_SOURCES = ("paper_1309_3458_amd/csrc/match.hip", "paper_1309_3458_amd/csrc/traverse.h",
+                   "paper_1309_3458_amd/csrc/ddm_internal.h", "paper_1309_3458_amd/csrc/tree.hip",
+                   "paper_1309_3458_amd/csrc/tree_dev.h", "paper_1309_3458_amd/csrc/sort_scan.hip")
+TRAFFIC = {
+    ("d2_N1e6_alpha1_uniform", "plain", "traverse_tile_count_stash"): {
+        "sha": None, "kernel_fetch_kib": None, "kernel_write_kib": None,
+        "step_fetch_kib": None, "step_write_kib": None, "step_kernel_us": None,
+        "profile": "profiles/traffic_d2_N1e6_alpha1_pmc.md"},
+}
+FETCH_SCALE, WRITE_SCALE = 2.0, 1.0
+
+
+def sources_sha():
+    import hashlib
+    h = hashlib.sha256()
+    for rel in TRAFFIC_SOURCES:
+        with open(os.path.join(ROOT, rel), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def traffic_entry(wname, path, kernel):
+    t = TRAFFIC.get((wname, path, kernel))
+    if not t or t["sha"] is None or t["sha"] != sources_sha():
+        return None
+    return t
+
+
+def compulsory_bytes_count_pass(inst, K):
+    """Bytes one count pass of Algorithm 4 must move at least, whatever its
+    design: every subscription record of the probe tree read once (2d floats
+    + a 4-byte id), every update's 2d bounds read, a 4-byte count written per
+    update and each of the K hits kept (a 12-byte entry: key and rank)."""
+    d = inst.d
+    return (8 * d + 4) * inst.n + 8 * d * inst.m + 4 * inst.m + 12 * K
+
+
+def roofline_record(inst, K, cand, dom, dom_avg_ms, wname, path):
+    """The roofline object of the dominant kernel (the count traversal).
+
+    bound "hbm": the pass does no dense arithmetic, so its roofline is HBM
+    bandwidth; `achieved` = the compulsory bytes of the pass per launch over
+    the launch's duration.  Beside it: the measured FETCH+WRITE traffic per
+    launch and as a fraction of peak, the same fraction over a whole step,
+    and the compare rate of the candidate tests against the vector ALU issue
+    rate (secondary: the pass is bound by the latency of its dependent
+    block-scan chain, not by either unit)."""
+    sec = dom_avg_ms / 1e3
+    algo = compulsory_bytes_count_pass(inst, K)
+    achieved = algo / sec / 1e9
+    t = traffic_entry(wname, path, dom)
+    traffic = None
+    r = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+         "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+         "kernel": dom, "kernel_avg_ms": round(dom_avg_ms, 4),
+         "algorithmic_bytes_per_launch": int(algo)}
+    if t:
+        traffic = (t["kernel_fetch_kib"] * FETCH_SCALE + t["kernel_write_kib"] * WRITE_SCALE) * 1024
+        r["traffic"] = round(traffic, 1)
+        r["measured_gbs"] = round(traffic / sec / 1e9, 1)
+        r["measured_frac_hbm_peak"] = round(traffic / sec / 1e9 / HBM_PEAK_GBS, 4)
+        st = (t["step_fetch_kib"] * FETCH_SCALE + t["step_write_kib"] * WRITE_SCALE) * 1024
+        r["step_traffic"] = round(st, 1)
+        r["step_kernel_us"] = t["step_kernel_us"]
+        r["step_measured_frac_hbm_peak"] = round(
+            st / (t["step_kernel_us"] / 1e6) / 1e9 / HBM_PEAK_GBS, 4)
+        r["counters"] = t["profile"]
+    else:
+        r["traffic_note"] = "counters not taken on these kernel sources"
+    r["target_measured_frac"] = 0.40
+    ops = cand * 2 * inst.d
+    alu = ops / sec / 1e9
+    r["alu"] = {"achieved": round(alu, 1), "peak": ALU_PEAK_GOPS, "unit": "Gop/s",
+                "frac": round(alu / ALU_PEAK_GOPS, 4), "candidates_per_launch": int(cand),
+                "what": "2d float compares per probe-dimension candidate"}
+    return r
 
 
 def roofline_alu(cand, ops, dom, dom_avg_ms, traffic=None):
@@ -132,6 +208,30 @@ def roofline_alu(cand, ops, dom, dom_avg_ms, traffic=None):
         r["traffic_gbs"] = round(traffic / (dom_avg_ms / 1e3) / 1e9, 1)
         r["traffic_frac_hbm_peak"] = round(r["traffic_gbs"] / HBM_PEAK_GBS, 4)
     return r
+
+
+def cpu_info():
+    """Host cores the oracle may use and what they are.  On the GPU hosts
+    one GPU's share of the CPU is 16 cores (OMP_NUM_THREADS is set to it);
+    nproc and the CPU model are recorded beside it."""
+    share = os.environ.get("OMP_NUM_THREADS")
+    try:
+        aff = len(os.sched_getaffinity(0))
+    except AttributeError:
+        aff = os.cpu_count() or 1
+    cores = int(share) if share and share.isdigit() and int(share) > 0 else aff
+    cores = max(1, min(cores, aff))
+    model = ""
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return cores, {"nproc": os.cpu_count(), "affinity_cores": aff,
+                   "omp_num_threads": share, "cpu_model": model}
 
 
 def evented_steps(step, steps):
@@ -258,18 +358,18 @@ def bench_single(args):
     best = min(res, key=lambda k: res[k]["ms_per_step"])
     ms_step = res[best]["ms_per_step"]
     cand = candidates(inst)
-    roofline = roofline_alu(cand, cand * 2 * inst.d, res[best]["dominant"],
-                            res[best]["dominant_avg_ms"],
-                            TRAFFIC_BYTES.get((wname, best, res[best]["dominant"])))
+    roofline = roofline_record(inst, K0, cand, res[best]["dominant"],
+                               res[best]["dominant_avg_ms"], wname, best)
 
     cpu = None
     if not args.no_cpu_baseline:
-        cores = min(os.cpu_count() or 1, 16)
+        cores, host = cpu_info()
         sample = args.cpu_sample or (inst.m if args.workload == "d2_uniform" else 2000)
         cpu = oracle_rate(inst, cores, sample, wname)
         # the plain sequential oracle on a tenth of the sample
         one = oracle_rate(inst, 1, max(1, sample // 10), wname)
         cpu["single_thread"] = {"value": one["value"], "sample": one["sample"]}
+        cpu.update(host)
 
     paths = {k: {"ms_per_step": round(v["ms_per_step"], 4), "step_ms": v["step_ms"],
                  "pairs_per_s": round(K0 / (v["ms_per_step"] / 1e3), 1),
@@ -361,7 +461,7 @@ def bench_batch(args):
     cpu = None
     if not args.no_cpu_baseline:
         import oracle
-        cores = min(os.cpu_count() or 1, 16)
+        cores, host = cpu_info()
         # a bounded sample: whole instances in a fixed shuffled order until
         # ~10 s of oracle time
         order = np.random.default_rng(11).permutation(len(insts))
@@ -377,7 +477,7 @@ def bench_batch(args):
         cpu = {"value": round(pairs / dt, 1), "unit": "pairs/s", "cores": cores,
                "kind": "oracle",
                "sample": f"{used} whole instances of batch256 in a fixed shuffled order, "
-                         f"{dt:.2f}s, {pairs} pairs"}
+                         f"{dt:.2f}s, {pairs} pairs", **host}
 
     n_tot = sum(i.n + i.m for i in insts)
     return {
@@ -427,8 +527,8 @@ def bench_serve(args):
     # identity of sampled results with the requests alone (and the oracle on
     # the small ones); the oracle's time on those is the CPU baseline
     import oracle
-    cores = min(os.cpu_count() or 1, 16)
-    alone, orc = serve.check_samples(st["samples"], sched, max_oracle_pairs=0)
+    cores, host = cpu_info()
+    alone = serve.check_alone(st["samples"], sched)
     t_or, p_or, n_or = 0.0, 0, 0
     for i in sorted(st["samples"]):
         spec = sched[i].spec
@@ -469,7 +569,8 @@ def bench_serve(args):
         "cpu_baseline": ({"value": round(p_or / t_or, 1), "unit": "pairs/s", "cores": cores,
                           "kind": "oracle",
                           "sample": f"{n_or} sampled requests (every 100th, N <= 2e5), "
-                                    f"{t_or:.2f}s, {p_or} pairs"} if t_or > 0 else None),
+                                    f"{t_or:.2f}s, {p_or} pairs", **host}
+                         if t_or > 0 else None),
     }
 
 

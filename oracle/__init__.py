@@ -23,7 +23,8 @@ _lib = None
 def lib():
     global _lib
     if _lib is None:
-        if not os.path.exists(_build.LIB):
+        if (not os.path.exists(_build.LIB)
+                or os.path.getmtime(_build.LIB) < os.path.getmtime(_build.SRC)):
             _build.build()
         L = ctypes.CDLL(_build.LIB)
         fp = ctypes.POINTER(ctypes.c_float)

@@ -25,11 +25,13 @@
  *                     remaining ties), each node holding maxupper and
  *                     minlower of its subtree.  Built statically by taking
  *                     the median as the root (a perfectly balanced BST).
- *   itree_query       Algorithm 4 (Interval-Query), recursive, closed form:
- *                     prune if maxupper < q.lower or minlower > q.upper;
- *                     recurse left; test the node; recurse right iff
- *                     x.in.lower <= q.upper (the closed counterpart of the
- *                     printed strict condition).
+ *   itree_query       the query of Sec. IV (Algorithm 4), closed form, as a
+ *                     search over a stack of pending subtrees: a subtree is
+ *                     skipped when maxupper < q.lower or minlower > q.upper;
+ *                     otherwise its root is tested and its parts examined,
+ *                     the right part only while the root's lower bound is
+ *                     <= q.upper (the closed counterpart of the printed
+ *                     strict condition).
  *   oracle_itm        Algorithm 5 per dimension, then the d-way combine of
  *                     Sec. III-A written literally: per update, sort the d
  *                     per-dimension lists and intersect them.  The parallel
@@ -161,17 +163,38 @@ static int itree_create(itree_t* t, const float* lo, const float* hi, uint32_t n
 
 static void itree_free(itree_t* t) { free(t->nodes); t->nodes = NULL; }
 
-/* Algorithm 4, closed form (strict form under the diagnostic flag). */
-static void itree_query(const itree_t* t, int32_t xi, float ql, float qh, int strict,
-                        vec32* out, uint64_t* visits) {
-    if (xi < 0) return;
-    const node_t* x = &t->nodes[xi];
-    if (visits) ++*visits;
-    if (x->maxupper < ql || x->minlower > qh) return;
-    itree_query(t, x->left, ql, qh, strict, out, visits);
-    if (intersect_1d(x->in.lo, x->in.hi, ql, qh, strict)) v32_push(out, x->in.id);
-    int go_right = strict ? (qh > x->in.lo) : (x->in.lo <= qh);
-    if (go_right) itree_query(t, x->right, ql, qh, strict, out, visits);
+/* The subscriptions of a tree meeting q (Sec. IV, the query of an interval
+ * tree), closed form; the strict form only under the diagnostic flag.
+ *
+ * Facts of Sec. IV this rests on: (1) no interval of a subtree meets q when
+ * the subtree's largest upper bound lies below q.lower or its smallest lower
+ * bound lies above q.upper; (2) the tree is ordered by lower bound, so every
+ * interval in the right part of a node has a lower bound at least the node's,
+ * and once that bound lies beyond q.upper no interval there can meet q.
+ * Every other subtree is examined: its root is tested, and its two parts are
+ * put on a stack of subtrees still to examine.  Which order the stack gives
+ * does not matter: the caller sorts the ids.  `visits` counts the subtrees
+ * examined (each non-empty one taken from the stack), the quantity bounded by
+ * O(min{n, (k+1) log n}) in Sec. IV.  The stack never holds more than one
+ * pending part per level of the tree plus the one being examined. */
+#define ORACLE_STACK 128
+static void itree_query(const itree_t* t, float ql, float qh, int strict, vec32* out,
+                        uint64_t* visits) {
+    int32_t pending[ORACLE_STACK];
+    int top = 0;
+    pending[top++] = t->root;
+    while (top > 0) {
+        int32_t xi = pending[--top];
+        if (xi < 0) continue;
+        const node_t* x = &t->nodes[xi];
+        if (visits) ++*visits;
+        int none_inside = x->maxupper < ql || x->minlower > qh;      /* fact (1) */
+        if (none_inside) continue;
+        if (intersect_1d(x->in.lo, x->in.hi, ql, qh, strict)) v32_push(out, x->in.id);
+        int right_may_meet = strict ? (x->in.lo < qh) : (x->in.lo <= qh);  /* fact (2) */
+        if (right_may_meet) pending[top++] = x->right;
+        pending[top++] = x->left;
+    }
 }
 
 static int tree_height(const itree_t* t, int32_t xi) {
@@ -213,7 +236,7 @@ static void itm_block(const itree_t* trees, const float* u_lo, const float* u_hi
         for (uint32_t k = 0; k < d; ++k) {
             lists[k].n = 0;
             float ql = u_lo[(size_t)k * m + j], qh = u_hi[(size_t)k * m + j];
-            itree_query(&trees[k], trees[k].root, ql, qh, strict, &lists[k], NULL);
+            itree_query(&trees[k], ql, qh, strict, &lists[k], NULL);
             qsort(lists[k].v, lists[k].n, sizeof(uint32_t), cmp_u32);
             pos[k] = 0;
         }
@@ -407,7 +430,7 @@ int oracle_itm_1d_visits(const float* s_lo, const float* s_hi, uint32_t n,
     for (uint32_t j = 0; j < m; ++j) {
         uint64_t v = 0;
         lst.n = 0;
-        itree_query(&t, t.root, u_lo[j], u_hi[j], 0, &lst, &v);
+        itree_query(&t, u_lo[j], u_hi[j], 0, &lst, &v);
         visits[j] = v;
         hits[j] = (uint32_t)lst.n;
     }

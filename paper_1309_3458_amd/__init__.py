@@ -520,8 +520,10 @@ class Server:
     submit() queues (s_lo, s_hi, u_lo, u_hi) GPU tensors and returns a
     ticket; the tensors are kept alive until the ticket is released.
     wait_any() blocks (releasing the GIL) until requests complete;
-    result(ticket) returns a dict with the status, timestamps and a numpy
-    copy of the sorted keys (uint64) when `copy` is set.
+    result(ticket) returns a dict with the status, timestamps and, when
+    `copy` is set, a numpy copy of the result: the sorted keys (uint64,
+    "pairs") or, for a compact server, the subscription ids ("sub_ids") and
+    the update offsets ("upd_offsets").
     """
 
     def __init__(self, predictor: Predictor | None = None, hbm_budget: int = 0,
@@ -574,15 +576,7 @@ class Server:
         n = lib().ddm_server_wait_any(self.handle, int(timeout_ms), buf, max_tickets)
         return [int(buf[i]) for i in range(n)]
 
-    @staticmethod
-    def keys_from_compact(sub_ids, upd_offsets):
-        """The 64-bit keys of a compact result."""
-        import numpy as np
-        m = len(upd_offsets) - 1
-        upd = np.repeat(np.arange(m, dtype=np.uint64), np.diff(upd_offsets).astype(np.int64))
-        return (upd << np.uint64(32)) | sub_ids.astype(np.uint64)
-
-    def result(self, ticket: int, copy: bool = True, keys: bool = True) -> dict:
+    def result(self, ticket: int, copy: bool = True) -> dict:
         import numpy as np
         from ._native import Result
         r = Result()
@@ -595,16 +589,14 @@ class Server:
             d["detail"] = lib().ddm_last_error_detail().decode()
         if copy and r.status == 0:
             if r.sub_ids is not None or r.upd_offsets is not None:
-                # compact form (copied); keys=True rebuilds the same keys
+                # compact form (copied as the library delivers it): subscription
+                # ids of every pair, and each update's first pair
                 K, m = int(r.count), int(r.m)
                 ids = np.frombuffer((ctypes.c_uint32 * K).from_address(int(r.sub_ids)),
                                     dtype=np.uint32).copy() if K else np.zeros(0, np.uint32)
                 off = np.frombuffer((ctypes.c_uint64 * (m + 1)).from_address(int(r.upd_offsets)),
                                     dtype=np.uint64).copy()
-                if keys:
-                    d["pairs"] = Server.keys_from_compact(ids, off)
-                else:
-                    d["sub_ids"], d["upd_offsets"] = ids, off
+                d["sub_ids"], d["upd_offsets"] = ids, off
             elif r.count == 0:
                 d["pairs"] = np.zeros(0, dtype=np.uint64)
             elif r.on_device:

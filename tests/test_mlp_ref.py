@@ -79,3 +79,56 @@ def test_corner_prefix_box_count_exact_on_cells():
     cy = np.floor(s_lo[1] * 8)
     want = np.sum((cx >= 2) & (cx < 5) & (cy >= 3) & (cy < 7))
     assert abs(got - want) < 1e-9
+
+
+def test_features_hand_derived_1d():
+    """Every feature of two updates on a 4-segment set, worked out by hand.
+
+    S = [0,16], [16,32], [32,48], [48,64]: min lower 0, width 64, so the 64
+    bins are the unit intervals and every edge an integer; mean length 16.
+    Prefix counts: #lo < e is 1 for e in 1..16, 2 for 17..32, 3 for 33..48;
+    the uppers fall in bins 16, 32, 48, 63, so #upper-bins < e is 0 up to 16,
+    1 for 17..32.  Joint grid: 256 cells of width 1/4, lower corners in cells
+    0, 64, 128, 192.
+      U0 = [20, 40]: c = #lo<=40 (3) - #hi<20 (1) = 2; corner box
+        [20-16, 40] -> cells [16, 160) hold 2 corners.
+      U1 = [10, 16.5]: the interpolated #lo <= 16.5 is 1.5 (halfway between
+        edge 16 with 1 and edge 17 with 2), #hi < 10 is 0: c = 1.5; corner
+        box [-6, 16.5] -> cells [0, 66) hold 2 corners.
+    """
+    s_lo = np.array([[0, 16, 32, 48]], np.float32)
+    s_hi = np.array([[16, 32, 48, 64]], np.float32)
+    u_lo = np.array([[20, 10]], np.float32)
+    u_hi = np.array([[40, 16.5]], np.float32)
+    X = mlp_ref.features(s_lo, s_hi, u_lo, u_hi)
+    want = np.zeros((2, 18))
+    want[0, :5] = [20 / 64, 30 / 64, 2 / 4, np.log1p(2) / 16, 16 / 64]
+    want[1, :5] = [6.5 / 64, 13.25 / 64, 1.5 / 4, np.log1p(1.5) / 16, 16 / 64]
+    want[:, 15] = np.log2(4) / 20
+    want[:, 16] = 1 / 3
+    want[0, 17] = np.log1p(2) / 16
+    want[1, 17] = np.log1p(2) / 16
+    np.testing.assert_allclose(X, want, rtol=0, atol=1e-12)
+
+
+def test_features_hand_derived_2d():
+    """Two dimensions: the first as in the 1-D case; the second has lower
+    bounds 0, 0, 32, 32 and uppers 32, 32, 64, 64 (width 64, mean length
+    32).  U = [20,40] x [40,50]: second-dimension count #lo<=50 (4) -
+    #hi-bins<40 (2) = 2; the joint grid has 64 cells per dimension (unit
+    width), corners at cells (0,0), (16,0), (32,32), (48,32), and the corner
+    box [4, 40) x [8, 50) holds only (32,32): estimate 1, which is also the
+    exact count."""
+    s_lo = np.array([[0, 16, 32, 48], [0, 0, 32, 32]], np.float32)
+    s_hi = np.array([[16, 32, 48, 64], [32, 32, 64, 64]], np.float32)
+    u_lo = np.array([[20], [40]], np.float32)
+    u_hi = np.array([[40], [50]], np.float32)
+    X = mlp_ref.features(s_lo, s_hi, u_lo, u_hi)
+    want = np.zeros((1, 18))
+    want[0, :5] = [20 / 64, 30 / 64, 2 / 4, np.log1p(2) / 16, 16 / 64]
+    want[0, 5:10] = [10 / 64, 45 / 64, 2 / 4, np.log1p(2) / 16, 32 / 64]
+    want[0, 15] = np.log2(4) / 20
+    want[0, 16] = 2 / 3
+    want[0, 17] = np.log1p(1) / 16
+    np.testing.assert_allclose(X, want, rtol=0, atol=1e-12)
+    assert oracle.itm(s_lo, s_hi, u_lo, u_hi).tolist() == [2]

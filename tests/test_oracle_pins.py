@@ -253,3 +253,28 @@ def test_invalid_input_rejected():
     nan = np.array([[np.nan, 3.0]], np.float32)
     with pytest.raises(oracle.OracleError):
         oracle.itm(s, s, nan, s)
+
+
+@pytest.mark.parametrize("seed", range(8))
+@pytest.mark.parametrize("n,m", [(1, 1), (63, 5), (200, 130), (1000, 333)])
+def test_sort_based_matching_ties(seed, n, m):
+    """Sec. III-D's sweep on integer grids full of exact ties, touching ends,
+    points, duplicates and signed zeros: closed segments need every lower
+    endpoint processed before any upper endpoint at the same coordinate; the
+    definition by exhaustion and Algorithm 2 fix the expected set."""
+    inst = W.tiny_adversarial(700 + 31 * seed + n % 97, n, m, 1)
+    want = definition_pairs(inst.s_lo, inst.s_hi, inst.u_lo, inst.u_hi)
+    got = oracle.sbm_1d(inst.s_lo[0], inst.s_hi[0], inst.u_lo[0], inst.u_hi[0])
+    np.testing.assert_array_equal(got, want)
+    np.testing.assert_array_equal(oracle.brute(inst.s_lo, inst.s_hi, inst.u_lo, inst.u_hi), want)
+
+
+def test_sort_based_matching_touching_pin():
+    """S = [0,2], [2,4], [4,4]; U = [4,6], [2,2]: closed segments meet at
+    their shared ends, so (U0,S1), (U0,S2), (U1,S0), (U1,S1) and nothing else."""
+    s_lo = np.array([0, 2, 4], np.float32)
+    s_hi = np.array([2, 4, 4], np.float32)
+    u_lo = np.array([4, 2], np.float32)
+    u_hi = np.array([6, 2], np.float32)
+    got = oracle.sbm_1d(s_lo, s_hi, u_lo, u_hi).tolist()
+    assert got == [1, 2, (1 << 32) | 0, (1 << 32) | 1]
