@@ -254,6 +254,30 @@ ddm_status ddm_count(const ddm_tree* t, const float* upd_lo, const float* upd_hi
                      uint32_t* counts, uint64_t* out_total, void* stream,
                      const ddm_match_opts* opts);
 
+/* ddm_match_scratch_bytes -- device scratch, in bytes, that a match of m
+ * updates against a d-dimensional tree set takes, for a given form:
+ *  form       DDM_SCRATCH_PLAIN    count -> scan -> fill (what a match
+ *                                  carved from fixed memory takes; a result
+ *                                  with more than 2^20 subscriptions and a
+ *                                  segment over 2048 pairs also takes 4
+ *                                  bytes per pair for its segment sort),
+ *             DDM_SCRATCH_STASH    plus the count traversal's stash of hits
+ *                                  (d > 1; hint = the caller's capacity, 0 =
+ *                                  the default of 4 hits per update),
+ *             DDM_SCRATCH_LEARNED  the single pass (d > 1) without its slot
+ *                                  arena (8 bytes per predicted slot).
+ *  bytes      host pointer, receives the size (0 for m = 0).
+ * Computed on the host by the same layout code the match runs, with no GPU
+ * and no memory behind it; it also checks that every piece the match takes
+ * lies inside what it reserves (DDM_E_DEVICE if not: a defect of the
+ * library).  DDM_E_INVALID_ARG for d outside [1, DDM_MAX_D], an unknown
+ * form, m >= 2^31 or a NULL `bytes`.                                        */
+#define DDM_SCRATCH_PLAIN 0u
+#define DDM_SCRATCH_STASH 1u
+#define DDM_SCRATCH_LEARNED 2u
+ddm_status ddm_match_scratch_bytes(uint32_t m, uint32_t d, uint32_t form, uint64_t hint,
+                                   uint64_t* bytes);
+
 /* ddm_match_brute -- the same result as ddm_build + ddm_match, computed by
  * Brute-Force Matching (Algorithm 2: every update tested against every
  * subscription, closed predicate in every dimension).  The paper's

@@ -118,6 +118,7 @@ def lib():
     _sig(L, "ddm_match_finish", i32, vp, vp, u64)
     _sig(L, "ddm_match_abort", None, vp)
     _sig(L, "ddm_count", i32, vp, vp, vp, u32, vp, P(u64), vp, P(MatchOpts))
+    _sig(L, "ddm_match_scratch_bytes", i32, u32, u32, u32, u64, P(u64))
     _sig(L, "ddm_match_brute", i32, vp, vp, u32, vp, vp, u32, u32, vp, u64, P(u64), vp)
     _sig(L, "ddm_match_sbm", i32, vp, vp, u32, vp, vp, u32, u32, vp, u64, P(u64), vp)
     _sig(L, "ddm_match_sets", i32, vp, vp, u32, vp, vp, u32, u32, i32, vp, u64, P(u64),

@@ -211,11 +211,26 @@ ddm_status scratch_overrun(const char* where) {
 }
 
 Scratch::~Scratch() {
-  if (base_) dev_free(base_, s_);
+  if (base_ && !ext_ && !dry_) dev_free(base_, s_);
 }
 
 bool Scratch::commit() {
   if (want_ == 0) want_ = 256;
+  if (dry_) {
+    base_ = reinterpret_cast<char*>(uintptr_t(1) << 40);
+    used_ = 0;
+    return true;
+  }
+  if (ext_) {
+    if (want_ > ext_cap_) {
+      set_detail("scratch needs " + std::to_string(want_) + " bytes, the fixed scratch holds " +
+                 std::to_string(ext_cap_));
+      return false;
+    }
+    base_ = ext_;
+    used_ = 0;
+    return true;
+  }
   base_ = dev_alloc(want_, s_);
   if (!base_) {
     set_detail("device scratch allocation failed");

@@ -52,6 +52,17 @@ struct Scratch {
   // the block returns to the cache, ordered on the stream, at destruction.
   void reserve(size_t bytes) { want_ += (bytes + 255) & ~size_t(255); }
   bool commit();
+  // Carve from caller-owned device memory instead (base 256-byte aligned,
+  // `cap` bytes): commit() then fails, with the detail set, when the
+  // reservations exceed `cap`, and nothing is freed at destruction.
+  void use_external(char* base, size_t cap) {
+    ext_ = base;
+    ext_cap_ = cap;
+  }
+  // Host-only layout check: commit() at a fixed dummy address without any
+  // memory behind it, so that take() and fits() can be exercised on a CPU.
+  // The pointers handed out must never be dereferenced.
+  void dry_run() { dry_ = true; }
   // Every take() must have its own reserve() of the same size, in any
   // order; fits() tells whether the takes so far stay inside the block and
   // must be checked before any kernel uses the memory.
@@ -66,6 +77,9 @@ struct Scratch {
   hipStream_t s_;
   char* base_ = nullptr;
   size_t want_ = 0, used_ = 0;
+  char* ext_ = nullptr;
+  size_t ext_cap_ = 0;
+  bool dry_ = false;
 };
 
 // error for a scratch layout whose takes exceed its reservations (a
@@ -343,6 +357,15 @@ ddm_status radix_sort_onesweep(const SortArr* host_arrs, uint32_t narr, int npas
 // counters, zeroed by the caller beforehand).
 ddm_status sort_segments_inplace(const uint64_t* off, uint32_t m, uint64_t* out, uint32_t n,
                                  uint32_t* lists, uint32_t* lists_count, hipStream_t s);
+
+// The plain match (count -> scan -> fill, no stash) with all its scratch in
+// caller-provided device memory [base, base + cap) and the count read back
+// into pageable host memory, so that it allocates nothing (match.hip; `who`
+// names the caller in error details).
+ddm_status match_external_scratch(const ddm_tree* t, const float* upd_lo, const float* upd_hi,
+                                  uint32_t m, uint64_t* out_pairs, uint64_t capacity,
+                                  uint64_t* out_count, hipStream_t s, char* base, size_t cap,
+                                  const char* who);
 
 // the same for K pairs and any n (ids above 2^20 are sorted from a copy)
 ddm_status sort_segments_keys(const uint64_t* off, uint32_t m, uint64_t* out, uint64_t K,

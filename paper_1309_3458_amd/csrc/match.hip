@@ -1082,6 +1082,9 @@ struct MatchState {
   uint32_t stiles = 0;     // tiles that ran
   uint32_t sused_max = 0;  // most counted chunks used in one slice
   bool stash_ok = false;
+  // no allocation of any kind (the scratch is external, the read-back goes
+  // to pageable host memory): the no-allocation entry point
+  bool noalloc = false;
   explicit MatchState(hipStream_t s) : sc(s), slots_sc(s), stash_sc(s) {}
   UpdSet all() const {
     UpdSet U{perm, gstart, gcount, m, 64};
@@ -1246,24 +1249,28 @@ size_t match_stash_bytes(uint32_t m) {
   return (size_t)(c * kStashChunk * 12 + c * 4 + 1024);
 }
 
-static ddm_status front_half(const ddm_tree* t, const float* ulo, const float* uhi, uint32_t m,
-                             const MatchPlan& P, MatchState& st, uint32_t* counts_out,
-                             uint32_t** lists, uint32_t** lists_count, hipStream_t s,
-                             const ddm_predictor* pred = nullptr, uint64_t budget = 0,
-                             bool want_stash = false, uint64_t stash_hint = 0) {
-  const uint32_t d = tree_d(t);
-  const TreeDev T = tree_dev(t);
-  Scratch& sc = st.sc;
-  // the single pass replaces the count traversal, which only exists for d > 1
-  st.learned = pred != nullptr && d > 1;
-  if (st.learned) {
+// The scratch layout of the match's front half: one reservation per piece
+// (each rounded up to 256 bytes by Scratch), then the pieces taken in the
+// same sizes.  The match, the no-allocation match and the host-only layout
+// check (ddm_match_scratch_bytes) share these two functions, so that a
+// piece taken without its reservation is caught on the host.
+struct FrontPieces {
+  uint64_t* stmp = nullptr;
+  uint32_t* lists = nullptr;
+  uint32_t* lists_count = nullptr;
+  uint64_t* dwords = nullptr;
+};
+
+static size_t front_max_tiles(uint32_t m) { return ((size_t)m + 63) / 64 + kBuckets; }
+
+static void front_reserve(Scratch& sc, uint32_t m, bool learned) {
+  if (learned) {
     sc.reserve(sizeof(float) * (size_t)m * kFeatures);  // X
     sc.reserve(sizeof(uint32_t) * m);                   // cap
     sc.reserve(sizeof(uint64_t) * (m + 1));             // soff
     sc.reserve(sizeof(uint32_t) * m);                   // perm_ovf
     sc.reserve(sizeof(uint32_t) * DDM_MAX_D);           // govf
   }
-  // one reservation per take below (each is rounded up to 256 bytes)
   sc.reserve(sizeof(uint32_t) * m);          // cmin
   sc.reserve(m);                             // kstar
   sc.reserve(sizeof(uint32_t) * m);          // rank
@@ -1281,10 +1288,11 @@ static ddm_status front_half(const ddm_tree* t, const float* ulo, const float* u
   sc.reserve(sizeof(uint32_t) * 2);              // segment list counts
   sc.reserve(sizeof(uint64_t) * 8);              // device words for readback
   sc.reserve(sizeof(uint32_t));                  // largest count
-  const size_t max_tiles = ((size_t)m + 63) / 64 + kBuckets;
-  sc.reserve(sizeof(uint32_t) * (kBuckets + 1));  // tile prefix
-  sc.reserve(sizeof(uint32_t) * max_tiles);       // tile -> bucket
-  if (!sc.commit()) return DDM_E_NOMEM;
+  sc.reserve(sizeof(uint32_t) * (kBuckets + 1));     // tile prefix
+  sc.reserve(sizeof(uint32_t) * front_max_tiles(m));  // tile -> bucket
+}
+
+static void front_take(Scratch& sc, MatchState& st, uint32_t m, bool learned, FrontPieces* fp) {
   st.cmin = sc.take<uint32_t>(m);
   st.kstar = sc.take<uint8_t>(m);
   st.rank = sc.take<uint32_t>(m);
@@ -1298,20 +1306,60 @@ static ddm_status front_half(const ddm_tree* t, const float* ulo, const float* u
   st.flag = sc.take<int32_t>(1);
   st.cnt = sc.take<uint32_t>(m);
   st.off = sc.take<uint64_t>(m + 1);
-  uint64_t* stmp = sc.take<uint64_t>(scan_tmp_words(m));
-  *lists = sc.take<uint32_t>(2 * (size_t)m);
-  *lists_count = sc.take<uint32_t>(2);
-  uint64_t* dwords = sc.take<uint64_t>(8);
+  fp->stmp = sc.take<uint64_t>(scan_tmp_words(m));
+  fp->lists = sc.take<uint32_t>(2 * (size_t)m);
+  fp->lists_count = sc.take<uint32_t>(2);
+  fp->dwords = sc.take<uint64_t>(8);
   st.maxcnt = sc.take<uint32_t>(1);
   st.tprefix = sc.take<uint32_t>(kBuckets + 1);
-  st.tmap = sc.take<uint32_t>(max_tiles);
-  if (st.learned) {
+  st.tmap = sc.take<uint32_t>(front_max_tiles(m));
+  if (learned) {
     st.X = sc.take<float>((size_t)m * kFeatures);
     st.cap = sc.take<uint32_t>(m);
     st.soff = sc.take<uint64_t>(m + 1);
     st.perm_ovf = sc.take<uint32_t>(m);
     st.govf = sc.take<uint32_t>(DDM_MAX_D);
   }
+}
+
+// the count traversal's stash: sizes (into st) and reservations, then takes
+static void stash_reserve(Scratch& sc, MatchState& st, uint32_t m, uint64_t hint) {
+  st.sfirst = (uint32_t)(stash_tiles(m) * kStashStatic);
+  st.sslice = stash_slice(m, hint);
+  st.smax = st.sfirst + st.sslice * kStashSlices;
+  const uint64_t e = (uint64_t)st.smax * kStashChunk;
+  sc.reserve(sizeof(uint64_t) * e);
+  sc.reserve(sizeof(uint32_t) * e);
+  sc.reserve(sizeof(uint32_t) * st.smax);
+  sc.reserve(sizeof(uint32_t) * (kStashSlices + 1));
+}
+
+static void stash_take(Scratch& sc, MatchState& st) {
+  const uint64_t e = (uint64_t)st.smax * kStashChunk;
+  st.skey = sc.take<uint64_t>(e);
+  st.srank = sc.take<uint32_t>(e);
+  st.sused = sc.take<uint32_t>(st.smax);
+  st.snext = sc.take<uint32_t>(kStashSlices + 1);
+}
+
+static ddm_status front_half(const ddm_tree* t, const float* ulo, const float* uhi, uint32_t m,
+                             const MatchPlan& P, MatchState& st, uint32_t* counts_out,
+                             uint32_t** lists, uint32_t** lists_count, hipStream_t s,
+                             const ddm_predictor* pred = nullptr, uint64_t budget = 0,
+                             bool want_stash = false, uint64_t stash_hint = 0) {
+  const uint32_t d = tree_d(t);
+  const TreeDev T = tree_dev(t);
+  Scratch& sc = st.sc;
+  // the single pass replaces the count traversal, which only exists for d > 1
+  st.learned = pred != nullptr && d > 1;
+  front_reserve(sc, m, st.learned);
+  if (!sc.commit()) return DDM_E_NOMEM;
+  FrontPieces fp;
+  front_take(sc, st, m, st.learned, &fp);
+  uint64_t* stmp = fp.stmp;
+  *lists = fp.lists;
+  *lists_count = fp.lists_count;
+  uint64_t* dwords = fp.dwords;
   if (!sc.fits()) return scratch_overrun("front_half");
   if (st.learned) {
     learned_init_kernel<<<1, 64, 0, s>>>(st.govf);
@@ -1324,22 +1372,12 @@ static ddm_status front_half(const ddm_tree* t, const float* ulo, const float* u
   if (st.stash) {
     // the count traversal also keeps every hit, so that no fill traversal
     // is needed when they all fit; without the memory it only counts
-    st.sfirst = (uint32_t)(stash_tiles(m) * kStashStatic);
-    st.sslice = stash_slice(m, stash_hint);
-    st.smax = st.sfirst + st.sslice * kStashSlices;
-    const uint64_t e = (uint64_t)st.smax * kStashChunk;
-    st.stash_sc.reserve(sizeof(uint64_t) * e);
-    st.stash_sc.reserve(sizeof(uint32_t) * e);
-    st.stash_sc.reserve(sizeof(uint32_t) * st.smax);
-    st.stash_sc.reserve(sizeof(uint32_t) * (kStashSlices + 1));
+    stash_reserve(st.stash_sc, st, m, stash_hint);
     if (!st.stash_sc.commit()) {
       set_detail("");
       st.stash = false;
     } else {
-      st.skey = st.stash_sc.take<uint64_t>(e);
-      st.srank = st.stash_sc.take<uint32_t>(e);
-      st.sused = st.stash_sc.take<uint32_t>(st.smax);
-      st.snext = st.stash_sc.take<uint32_t>(kStashSlices + 1);
+      stash_take(st.stash_sc, st);
       if (!st.stash_sc.fits()) return scratch_overrun("stash");
     }
   }
@@ -1452,9 +1490,12 @@ static ddm_status front_half(const ddm_tree* t, const float* ulo, const float* u
     learned_words_kernel<<<1, 64, 0, s>>>(st.govf, st.soff, m, dwords);
     DDM_LAUNCHED("learned_words_kernel");
   }
-  uint64_t* hw = nullptr;
-  r = host_words(&hw);
-  if (r != DDM_OK) return r;
+  uint64_t hw_local[8] = {};
+  uint64_t* hw = hw_local;
+  if (!st.noalloc) {
+    r = host_words(&hw);
+    if (r != DDM_OK) return r;
+  }
   DDM_HIP(hipMemcpyAsync(hw, dwords, 5 * sizeof(uint64_t), hipMemcpyDeviceToHost, s));
   DDM_HIP(hipStreamSynchronize(s));
   const uint64_t flags = hw[1];
@@ -1509,7 +1550,7 @@ static ddm_status check_common(const ddm_tree* t, const float* ulo, const float*
 
 ddm_status sort_segments(const uint64_t* off, uint32_t m, uint64_t* out, uint64_t K, uint32_t n,
                          uint32_t* lists, uint32_t* lists_count, hipStream_t s, const SegSrc& S,
-                         uint64_t max_len = ~0ull);
+                         uint64_t max_len = ~0ull, Scratch* tmp_sc = nullptr);
 
 // the big-segment kernel's LDS bitmap exceeds the default dynamic LDS limit
 ddm_status ensure_segsort_attr() {
@@ -1540,10 +1581,11 @@ ddm_status sort_segments_keys(const uint64_t* off, uint32_t m, uint64_t* out, ui
 }
 
 // max_len: the longest segment if known; size classes that cannot occur
-// are not launched
+// are not launched.  tmp_sc: where the id copy of the bitmap sort comes from
+// (an external scratch in the no-allocation match), else allocated here.
 ddm_status sort_segments(const uint64_t* off, uint32_t m, uint64_t* out, uint64_t K, uint32_t n,
                          uint32_t* lists, uint32_t* lists_count, hipStream_t s,
-                         const SegSrc& S, uint64_t max_len) {
+                         const SegSrc& S, uint64_t max_len, Scratch* tmp_sc) {
   ProfScope ps("segsort", s);
   segsort_small_kernel<<<(m + 255) / 256, 256, 0, s>>>(off, m, out, S, lists, lists_count);
   DDM_LAUNCHED("segsort_small_kernel");
@@ -1553,7 +1595,8 @@ ddm_status sort_segments(const uint64_t* off, uint32_t m, uint64_t* out, uint64_
   if (max_len <= kSegMid) return DDM_OK;
   const uint32_t words = std::min<uint32_t>(kMaxBitWords, (n + 31) / 32);
   uint32_t* tmp = nullptr;
-  Scratch sc(s);
+  Scratch local(s);
+  Scratch& sc = tmp_sc ? *tmp_sc : local;
   if (n > words * 32) {
     // ids of in-place segments are read window by window from a copy
     sc.reserve(sizeof(uint32_t) * K);
@@ -1839,3 +1882,117 @@ extern "C" ddm_status ddm_count(const ddm_tree* t, const float* upd_lo, const fl
   if (out_total) *out_total = st.K;
   return DDM_OK;
 }
+
+// --------------------------------------------------------------------------
+// Scratch sizes of the match, computed on the host by the same layout
+// functions the match uses (a dry run: no memory, no GPU).
+// --------------------------------------------------------------------------
+extern "C" ddm_status ddm_match_scratch_bytes(uint32_t m, uint32_t d, uint32_t form,
+                                              uint64_t hint, uint64_t* bytes) {
+  set_detail("");
+  if (!bytes || d < 1 || d > DDM_MAX_D || form > DDM_SCRATCH_LEARNED || m >= 0x80000000u) {
+    set_detail("ddm_match_scratch_bytes: bad argument");
+    return DDM_E_INVALID_ARG;
+  }
+  *bytes = 0;
+  if (m == 0) return DDM_OK;
+  MatchState st(nullptr);
+  const bool learned = form == DDM_SCRATCH_LEARNED && d > 1;
+  Scratch& sc = st.sc;
+  sc.dry_run();
+  front_reserve(sc, m, learned);
+  if (!sc.commit()) return DDM_E_NOMEM;
+  FrontPieces fp;
+  front_take(sc, st, m, learned, &fp);
+  if (!sc.fits()) return scratch_overrun("front_half");
+  uint64_t total = sc.want_;
+  if (form == DDM_SCRATCH_STASH && d > 1) {
+    Scratch& ss = st.stash_sc;
+    ss.dry_run();
+    stash_reserve(ss, st, m, hint);
+    if (!ss.commit()) return DDM_E_NOMEM;
+    stash_take(ss, st);
+    if (!ss.fits()) return scratch_overrun("stash");
+    total += ss.want_;
+  }
+  *bytes = total;
+  return DDM_OK;
+}
+
+namespace ddm {
+
+// --------------------------------------------------------------------------
+// The plain match (count -> scan -> fill, no stash) with every piece of
+// scratch carved from caller-provided device memory [base, base + cap) and
+// the count read back into pageable host memory: no allocation of any kind.
+// Errors: DDM_E_INVALID_ARG when the layout for m updates does not fit in
+// cap bytes, or when the id copy of the bitmap sort (more than 2^20
+// subscriptions and a segment beyond kSegMid pairs: 4 bytes per pair) does
+// not fit in what is left, both before anything is written; otherwise as
+// ddm_match.
+// --------------------------------------------------------------------------
+ddm_status match_external_scratch(const ddm_tree* t, const float* upd_lo, const float* upd_hi,
+                                  uint32_t m, uint64_t* out_pairs, uint64_t capacity,
+                                  uint64_t* out_count, hipStream_t s, char* base, size_t cap,
+                                  const char* who) {
+  set_detail("");
+  if (!out_count) {
+    set_detail("out_count is NULL");
+    return DDM_E_INVALID_ARG;
+  }
+  *out_count = 0;
+  ddm_status r = check_common(t, upd_lo, upd_hi, m);
+  if (r != DDM_OK) return r;
+  if (m == 0 || tree_n(t) == 0) {
+    if (tree_n(t) != 0) return ddm_tree_check(t);
+    return DDM_OK;
+  }
+  uint64_t need = 0;
+  r = ddm_match_scratch_bytes(m, tree_d(t), DDM_SCRATCH_PLAIN, 0, &need);
+  if (r != DDM_OK) return r;
+  if (need > cap) {
+    set_detail(std::string(who) + ": " + std::to_string(m) + " updates need " +
+               std::to_string(need) + " bytes of scratch; it holds " + std::to_string(cap));
+    return DDM_E_INVALID_ARG;
+  }
+  MatchPlan P;
+  r = parse_opts(nullptr, &P);
+  if (r != DDM_OK) return r;
+  MatchState st(s);
+  st.noalloc = true;
+  st.sc.use_external(base, cap);
+  uint32_t *lists = nullptr, *lists_count = nullptr;
+  r = front_half(t, upd_lo, upd_hi, m, P, st, nullptr, &lists, &lists_count, s, nullptr, 0,
+                 false, 0);
+  if (r != DDM_OK) return r;
+  *out_count = st.K;
+  if (st.K > capacity) {
+    set_detail("result larger than capacity");
+    return DDM_E_CAPACITY;
+  }
+  if (st.K == 0) return DDM_OK;
+  if (!out_pairs) {
+    set_detail("out_pairs is NULL");
+    return DDM_E_INVALID_ARG;
+  }
+  const size_t used = st.sc.used_;
+  if (tree_n(t) > kMaxBitWords * 32 && st.maxseg > kSegMid &&
+      ((sizeof(uint32_t) * st.K + 255) & ~size_t(255)) > cap - used) {
+    set_detail(std::string(who) + ": sorting segments over " + std::to_string(kSegMid) +
+               " pairs among more than 2^20 subscriptions needs 4 bytes per pair (" +
+               std::to_string(st.K) + " pairs) beyond the scratch");
+    return DDM_E_INVALID_ARG;
+  }
+  SegOut O{};
+  O.base = st.off;
+  O.out = out_pairs;
+  const TreeDev T = tree_dev(t);
+  r = traverse_any<true>(tree_d(t), P, T, upd_lo, upd_hi, m, st.all(), st.kstar, O, s);
+  if (r != DDM_OK) return r;
+  Scratch rest(s);
+  rest.use_external(base + used, cap - used);
+  return sort_segments(st.off, m, out_pairs, st.K, tree_n(t), lists, lists_count, s, SegSrc{},
+                       st.maxseg, &rest);
+}
+
+}  // namespace ddm
