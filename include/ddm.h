@@ -278,6 +278,28 @@ ddm_status ddm_count(const ddm_tree* t, const float* upd_lo, const float* upd_hi
 ddm_status ddm_match_scratch_bytes(uint32_t m, uint32_t d, uint32_t form, uint64_t hint,
                                    uint64_t* bytes);
 
+/* ddm_match_noalloc -- ddm_match for callers that cannot allocate device
+ * memory (code under stream capture, tight serving loops, harnesses that
+ * forbid allocation).  Same arguments, result and errors as ddm_match; it
+ * runs the plain count -> scan -> fill path (no stash of hits) and takes all
+ * its scratch from one static device array of DDM_NOALLOC_SCRATCH_MB MiB,
+ * which each device that runs it keeps until the process ends.  It calls no
+ * allocator of any kind (the count is read back into pageable host memory).
+ *  Limit: the match takes about 45 bytes per update plus 4.4 MiB
+ *  (ddm_match_scratch_bytes with DDM_SCRATCH_PLAIN gives the exact figure),
+ *  i.e. up to about 1.38e6 updates; beyond that, and for a result that needs
+ *  the segment sort's id copy (more than 2^20 subscriptions and a segment
+ *  over 2048 pairs: 4 bytes per pair) beyond what is left, it returns
+ *  DDM_E_INVALID_ARG with a detail message, before writing anything.
+ *  Concurrency: every call on one device shares that device's array, so
+ *  calls that overlap on one device (different streams or threads) race;
+ *  the caller serializes them.  Each call sets all the state it reads, so
+ *  nothing carries over from the previous call.                            */
+#define DDM_NOALLOC_SCRATCH_MB 64
+ddm_status ddm_match_noalloc(const ddm_tree* t, const float* upd_lo, const float* upd_hi,
+                             uint32_t m, uint64_t* out_pairs, uint64_t capacity,
+                             uint64_t* out_count, void* stream);
+
 /* ddm_match_brute -- the same result as ddm_build + ddm_match, computed by
  * Brute-Force Matching (Algorithm 2: every update tested against every
  * subscription, closed predicate in every dimension).  The paper's

@@ -19,6 +19,7 @@ DDM_E_INVALID_INPUT = -2
 DDM_E_CAPACITY = -3
 DDM_E_NOMEM = -4
 DDM_E_DEVICE = -5
+DDM_NOALLOC_SCRATCH_MB = 64  # static scratch of ddm_match_noalloc (ddm.h)
 
 TRAVERSE = {"auto": 0, "lane": 1, "tile": 2}
 FEATURES = 18
@@ -119,6 +120,7 @@ def lib():
     _sig(L, "ddm_match_abort", None, vp)
     _sig(L, "ddm_count", i32, vp, vp, vp, u32, vp, P(u64), vp, P(MatchOpts))
     _sig(L, "ddm_match_scratch_bytes", i32, u32, u32, u32, u64, P(u64))
+    _sig(L, "ddm_match_noalloc", i32, vp, vp, vp, u32, vp, u64, P(u64), vp)
     _sig(L, "ddm_match_brute", i32, vp, vp, u32, vp, vp, u32, u32, vp, u64, P(u64), vp)
     _sig(L, "ddm_match_sbm", i32, vp, vp, u32, vp, vp, u32, u32, vp, u64, P(u64), vp)
     _sig(L, "ddm_match_sets", i32, vp, vp, u32, vp, vp, u32, u32, i32, vp, u64, P(u64),
