@@ -21,6 +21,9 @@ Workloads:
                         to 5e5, alpha in {0.01, 1, 100}; ITM (build +
                         match) beside GPU Brute-Force and Sort-Based
                         Matching
+  sweep_fig7            the time surface of the paper's Fig. 7 on the GPU: ITM
+                        build + match for d=1, N from 5e4 to 5e5 and alpha
+                        over 0 < alpha <= 100 (0.01 .. 100, half-decade steps)
   hbm_copy              a plain device-to-device copy of 1 GiB per step
                         (calibrates the HBM traffic counters)
   serve                 open-loop Poisson arrivals (2000/s, d=3, N
@@ -64,7 +67,7 @@ def parse():
     ap.add_argument("--traversal", default="auto", choices=["auto", "lane", "tile"])
     ap.add_argument("--workload", default="d2_uniform",
                     choices=["d2_uniform", "d2_hotspot", "batch256", "serve", "hbm_copy",
-                             "sweep_1d"])
+                             "sweep_1d", "sweep_fig7"])
     ap.add_argument("--duration", type=float, default=60.0,
                     help="serve: seconds of Poisson arrivals (the schedule is cut, not rescaled)")
     ap.add_argument("--rate", type=float, default=2000.0, help="serve: arrivals per second")
@@ -632,6 +635,61 @@ def bench_sweep(args):
             "sweep": rows, "roofline": None, "cpu_baseline": None}
 
 
+def bench_fig7(args):
+    """Fig. 7 of Sec. V on the GPU: ITM (build + match, one step each) over
+    N in {50, 100, ..., 500} x 10^3 extents (n = m = N/2, d = 1, uniform lower
+    ends, common length alpha L / N) and alpha from 0.01 to 100 in
+    half-decade steps.  The mean time per step of every cell, K and pairs/s
+    go into the JSON line; a markdown table of the times goes to stderr."""
+    import torch
+
+    import paper_1309_3458_amd as P
+    from paper_1309_3458_amd import workloads as W
+
+    Ns = [50_000 * i for i in range(1, 11)]
+    alphas = [0.01, 0.03, 0.1, 0.3, 1.0, 3.0, 10.0, 30.0, 100.0]
+    steps = min(args.steps, 10)
+    dev = lambda a: torch.from_numpy(a).cuda()
+    rows = []
+    for N in Ns:
+        for alpha in alphas:
+            n, m = W.split_regions(N)
+            inst = W.uniform_instance([7, N, int(round(alpha * 100))], n, m, 1,
+                                      W.side_for_alpha(alpha, N, 1))
+            s_lo, s_hi, u_lo, u_hi = dev(inst.s_lo), dev(inst.s_hi), dev(inst.u_lo), dev(inst.u_hi)
+            t = P.build(s_lo, s_hi)
+            K = int(P.match(t, u_lo, u_hi).numel())
+            t.free()
+            out = torch.empty(max(K, 1), dtype=torch.int64, device="cuda")
+
+            def step():
+                t = P.build(s_lo, s_hi)
+                k = P.match(t, u_lo, u_hi, out=out).numel()
+                t.free()
+                return k
+
+            for _ in range(min(args.warmup, 2)):
+                step()
+            wall, per, k2 = evented_steps(step, steps)
+            assert k2 == K
+            rows.append({"N": N, "alpha": alpha, "K": K, "ms": step_stats(per),
+                         "pairs_per_s": round(K / (wall / 1e3), 1)})
+    head = "| N \\ alpha | " + " | ".join(f"{a:g}" for a in alphas) + " |"
+    log("ITM build + match, mean ms per step (d = 1, one MI355X)")
+    log(head)
+    log("|" + "---|" * (len(alphas) + 1))
+    for N in Ns:
+        cells = [f"{r['ms']['mean']:.3f}" for r in rows if r["N"] == N]
+        log(f"| {N} | " + " | ".join(cells) + " |")
+    last = [r for r in rows if r["N"] == Ns[-1] and r["alpha"] == alphas[-1]][0]
+    return {"metric": "ITM build+match time over (N, alpha), d=1 (Fig. 7 of the paper)",
+            "value": last["pairs_per_s"], "unit": "pairs/s", "ms_per_step": last["ms"]["mean"],
+            "dtype": "f32",
+            "config": {"workload": "sweep_fig7_d1_N5e4-5e5_alpha0.01-100",
+                       "value_at": "N=5e5 alpha=100", "steps_per_cell": steps},
+            "grid": rows, "roofline": None, "cpu_baseline": None}
+
+
 def bench_copy(args):
     """1 GiB device-to-device copy per step: the reference kernel whose
     FETCH_SIZE / WRITE_SIZE counters calibrate the traffic of the others."""
@@ -669,6 +727,8 @@ def main():
         rec = bench_copy(args)
     elif args.workload == "sweep_1d":
         rec = bench_sweep(args)
+    elif args.workload == "sweep_fig7":
+        rec = bench_fig7(args)
     else:
         rec = bench_single(args)
     head = {"metric": rec.pop("metric"), "value": rec.pop("value"), "unit": rec.pop("unit"),

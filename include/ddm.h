@@ -498,10 +498,16 @@ void ddm_batch_free(ddm_batch* b);
  * and the device-memory budget admits it, so requests overlap on the device
  * with the ones already running.  Optionally (batch_max > 1) small
  * requests queued together are matched as one batch (the ddm_batch kernels,
- * sized on the device by their exact counts).  Admission is by footprint: inputs + trees
- * + match scratch when a request starts (FIFO order), then the predicted
- * output (learned slot arena) and the exact output once known; the oldest
- * request in flight may always exceed the budget, so progress is
+ * sized on the device by their exact counts).  Admission is by footprint:
+ * inputs + trees + match scratch when a request starts (FIFO order); with
+ * learned sizing, the slot arena (8 bytes per predicted slot) plus an
+ * output estimate of the same size once the prediction is known and before
+ * the arena is allocated; the exact output once known.  A request waits
+ * until its bytes fit.  When every request in flight is waiting, the
+ * youngest one that has not yet allocated its arena or output gives back
+ * everything it holds and goes back to the head of the queue (counted in
+ * ddm_server_counters.requeued); only a request alone in flight, or one no
+ * waiting request can make room for, goes past the budget, so progress is
  * guaranteed.  With a predictor, requests of d <= 3 use the single-pass
  * learned sizing; results are bit-identical either way.
  *
@@ -565,6 +571,8 @@ typedef struct {
 typedef struct {
   uint64_t submitted, completed, queued, in_flight;
   uint64_t hbm_used, hbm_peak, host_pool_used, trees_resident;
+  uint64_t requeued;  /* admissions given back when every request in flight
+                         waited for memory (the request started again later) */
 } ddm_server_counters;
 
 typedef struct ddm_server ddm_server;

@@ -80,7 +80,7 @@ class Result(ctypes.Structure):
 class ServerCounters(ctypes.Structure):
     _fields_ = [(k, ctypes.c_uint64) for k in
                 ("submitted", "completed", "queued", "in_flight", "hbm_used", "hbm_peak",
-                 "host_pool_used", "trees_resident")]
+                 "host_pool_used", "trees_resident", "requeued")]
 
 
 _lib = None

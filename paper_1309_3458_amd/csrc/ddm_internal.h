@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <functional>
 #include <string>
 
 #include "ddm.h"
@@ -366,6 +367,21 @@ ddm_status match_external_scratch(const ddm_tree* t, const float* upd_lo, const 
                                   uint32_t m, uint64_t* out_pairs, uint64_t capacity,
                                   uint64_t* out_count, hipStream_t s, char* base, size_t cap,
                                   const char* who);
+
+// The learned single pass (as ddm_match_learned_begin) for a caller that
+// accounts device memory: once the predicted number of slots is known, and
+// before the slot arena is allocated, grant(predicted) is called (it may
+// block) and returns the number of slots granted; the arena holds at most
+// that many, and updates beyond it overflow into the exact fill.
+// Returning kArenaRefused makes the match return DDM_E_NOMEM before it
+// allocates anything more.
+using ArenaGrant = std::function<uint64_t(uint64_t)>;
+constexpr uint64_t kArenaRefused = ~0ull;
+ddm_status match_learned_begin_granted(const ddm_tree* t, const float* upd_lo,
+                                       const float* upd_hi, uint32_t m,
+                                       const ddm_predictor* pred, uint64_t* out_count,
+                                       hipStream_t s, const ddm_match_opts* opts,
+                                       ddm_pending** out_pending, const ArenaGrant& grant);
 
 // the same for K pairs and any n (ids above 2^20 are sorted from a copy)
 ddm_status sort_segments_keys(const uint64_t* off, uint32_t m, uint64_t* out, uint64_t K,

@@ -60,6 +60,12 @@ int tree_device(const ddm_tree* t);
 // --------------------------------------------------------------------------
 constexpr uint32_t kBucketsPerDim = 8192;
 constexpr uint32_t kBuckets = kBucketsPerDim * DDM_MAX_D;
+// The rank of an update in its bucket comes from a device-scope atomic on
+// the bucket's counter; counters 128 bytes apart (one per cache line), so
+// that the atomics of different buckets do not queue on one line (at
+// 10^6 boxes all updates fall into the 4096 cells of their probe dimension,
+// and with packed counters about a thousand atomics would share each line).
+constexpr uint32_t kCntPad = 32;
 
 // d > 1: the first half of a dimension's buckets are ranges of the position
 // in tree k*; an update whose candidate range is longer than kCellRange
@@ -118,7 +124,7 @@ __global__ __launch_bounds__(256) void bits1_kernel(TreeDev T, const float* __re
     const uint32_t bu = min((uint32_t)(((uint64_t)ph * kBucketsPerDim) / ((uint64_t)T.n + 1)),
                             kBucketsPerDim - 1u);
     bucket[j] = bu;
-    rank[j] = atomicAdd(&bhist[bu], 1u);
+    rank[j] = atomicAdd(&bhist[bu * kCntPad], 1u);
   }
   if (ballot(bad) != 0 && lane_id() == 0) atomicOr(flag, 2);
 }
@@ -128,7 +134,7 @@ __global__ __launch_bounds__(256) void bits1_kernel(TreeDev T, const float* __re
 // (bqa) and its key (bx), the box centre, and whether the extent is invalid
 template <int D>
 struct ProbeEst {
-  uint32_t best, bk, bqa, bx;
+  uint32_t best, bk, bqa, bqb, bx;
   float mid[D];
   bool bad;
 };
@@ -143,6 +149,7 @@ __device__ __forceinline__ ProbeEst<D> probe_estimate(const TreeDev& T,
   P.best = 0xffffffffu;
   P.bk = 0;
   P.bqa = 0;
+  P.bqb = 0;
   P.bx = 0;
   P.bad = false;
   uint32_t xh[D], xl[D], qa[D], qb[D];
@@ -176,6 +183,7 @@ __device__ __forceinline__ ProbeEst<D> probe_estimate(const TreeDev& T,
       P.best = est;
       P.bk = (uint32_t)k;
       P.bqa = qa[k];
+      P.bqb = qb[k];
       P.bx = xh[k];
     }
   }
@@ -247,7 +255,8 @@ __global__ __launch_bounds__(1024) void probe_kernel(TreeDev T, const float* __r
                                                      uint32_t* __restrict__ bucket,
                                                      uint32_t* __restrict__ rank,
                                                      uint32_t* __restrict__ bhist,
-                                                     int32_t* __restrict__ flag) {
+                                                     int32_t* __restrict__ flag,
+                                                     uint2* __restrict__ pb) {
   __shared__ uint32_t sq[D][kQuantPad];
 #pragma unroll
   for (int k = 0; k < D; ++k)
@@ -283,6 +292,17 @@ __global__ __launch_bounds__(1024) void probe_kernel(TreeDev T, const float* __r
       fine = 0.f;
     }
     kstar[j] = (uint8_t)bk;
+    // bounds of the candidate positions in tree k* from the quantiles
+    // quant[i] = skey_lo[floor(i n / kQuant)]: bqb quantiles lie below
+    // t = q.lo - maxlen, so at least floor((bqb - 1) n / kQuant) + 1 keys do;
+    // bqa quantiles are <= q.hi and quantile bqa is not, so at most
+    // floor(bqa n / kQuant) keys are (positions are 1-based)
+    {
+      const uint32_t qb = P.bqb, qa = bqa;
+      const uint32_t lo = qb ? (uint32_t)(((uint64_t)(qb - 1) * T.n) / kQuant) + 1u : 0u;
+      const uint32_t hi = qa < kQuant ? (uint32_t)(((uint64_t)qa * T.n) / kQuant) : T.n;
+      pb[j] = bad ? make_uint2(1u, 0u) : make_uint2(lo + 1u, hi);
+    }
     uint32_t sub;
     if (!bad && cell_mode<D>(best, T.n)) {
       const uint32_t e = shape[bk];
@@ -300,7 +320,7 @@ __global__ __launch_bounds__(1024) void probe_kernel(TreeDev T, const float* __r
     }
     const uint32_t bu = bk * kBucketsPerDim + sub;
     bucket[j] = bu;
-    rank[j] = atomicAdd(&bhist[bu], 1u);
+    rank[j] = atomicAdd(&bhist[bu * kCntPad], 1u);
   }
   if (ballot(bad) != 0 && lane_id() == 0) atomicOr(flag, 2);
 }
@@ -312,6 +332,15 @@ __global__ __launch_bounds__(1024) void probe_kernel(TreeDev T, const float* __r
 // kBucketsPerDim buckets of the probe dimensions in use are scanned (PER =
 // d * 8 per thread); bhist and tprefix are written up to that bound
 // inclusive, so that the last bucket has an end.
+// the padded bucket counters gathered into consecutive words (many
+// workgroups, so that the single-workgroup scan below reads dense memory)
+__global__ __launch_bounds__(256) void bucket_gather_kernel(const uint32_t* __restrict__ bcnt,
+                                                            uint32_t nb,
+                                                            uint32_t* __restrict__ dense) {
+  const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < nb) dense[i] = bcnt[(size_t)i * kCntPad];
+}
+
 template <uint32_t PER>
 __global__ __launch_bounds__(1024) void bucket_scan_kernel(uint32_t* __restrict__ bhist,
                                                            uint32_t m,
@@ -533,7 +562,7 @@ __global__ __launch_bounds__(kTileWaves * kWave) void tile_kernel(
   qbeg = uniform_u32(qbeg);
 
   tile_body<D, FILL>(T, ulo, uhi, m, US.perm, 0, k, qbeg, nq, O, &s_cand[wave][0][0],
-                     &s_cid[wave][0], &s_q[wave][0][0], lane);
+                     &s_cid[wave][0], &s_q[wave][0][0], lane, 0u, US.pb);
 }
 
 // --------------------------------------------------------------------------
@@ -609,7 +638,7 @@ void tile_bucket_kernel(
     const uint32_t qbeg = start + lt * 64u;
     const uint32_t nq = min(64u, end - qbeg);
     tile_body<D, FILL, STASH>(T, ulo, uhi, m, US.perm, 0u, b / kBucketsPerDim, qbeg, nq, O,
-                              s_cand[wave], s_cid[wave], s_q[wave], lane, item);
+                              s_cand[wave], s_cid[wave], s_q[wave], lane, item, US.pb);
   }
 }
 
@@ -1043,10 +1072,13 @@ struct MatchState {
   uint32_t* rank = nullptr;
   uint32_t* bucket = nullptr;
   uint32_t* bhist = nullptr;
+  uint32_t* bcnt = nullptr;  // bucket counters, kCntPad words apart
   uint32_t* perm = nullptr;
   uint32_t* gstart = nullptr;
   uint32_t* gcount = nullptr;
   uint32_t* shape = nullptr;  // cell shape (log2 B1) of each probe dimension
+  uint32_t* pb = nullptr;     // per update: candidate position bounds (d > 1)
+  bool pb_ok = false;
   int32_t* flag = nullptr;
   uint32_t* cnt = nullptr;
   uint64_t* off = nullptr;
@@ -1091,6 +1123,7 @@ struct MatchState {
     U.boff = bhist;
     U.tprefix = tprefix;
     U.tmap = tmap;
+    U.pb = pb_ok ? pb : nullptr;
     return U;
   }
 };
@@ -1101,11 +1134,11 @@ struct MatchState {
 template <int D>
 __global__ __launch_bounds__(1024) void match_init_kernel(
     uint32_t* __restrict__ gcount, int32_t* __restrict__ flag, uint32_t* __restrict__ lists_count,
-    uint32_t* __restrict__ bhist, uint32_t* __restrict__ snext, uint32_t sfirst, uint32_t sslice,
+    uint32_t* __restrict__ bcnt, uint32_t* __restrict__ snext, uint32_t sfirst, uint32_t sslice,
     uint32_t* __restrict__ maxcnt, TreeDev T, const float* __restrict__ ulo,
     const float* __restrict__ uhi, uint32_t m, uint32_t* __restrict__ shape) {
   const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < kBuckets) bhist[i] = 0;
+  if (i < kBuckets) bcnt[(size_t)i * kCntPad] = 0;
   if (i < DDM_MAX_D) gcount[i] = 0;
   if (i == 0) {
     *flag = 0;
@@ -1155,12 +1188,13 @@ static ddm_status launch_probe(const TreeDev& T, const float* ulo, const float* 
   if (D == 1) {
     ProfScope ps("bits", s);
     bits1_kernel<<<(m + 255) / 256, 256, 0, s>>>(T, ulo, uhi, m, st.cmin, st.kstar, st.bucket,
-                                                 st.rank, st.bhist, st.flag);
+                                                 st.rank, st.bcnt, st.flag);
     DDM_LAUNCHED("bits1_kernel");
   } else {
     ProfScope ps("probe", s);
     probe_kernel<D><<<(m + 1023) / 1024, 1024, 0, s>>>(T, ulo, uhi, m, st.shape, st.kstar,
-                                                       st.bucket, st.rank, st.bhist, st.flag);
+                                                       st.bucket, st.rank, st.bcnt, st.flag,
+                                                       reinterpret_cast<uint2*>(st.pb));
     DDM_LAUNCHED("probe_kernel");
   }
   return DDM_OK;
@@ -1276,7 +1310,8 @@ static void front_reserve(Scratch& sc, uint32_t m, bool learned) {
   sc.reserve(sizeof(uint32_t) * m);          // rank
   sc.reserve(sizeof(uint32_t) * m);          // bucket
   sc.reserve(sizeof(uint32_t) * m);          // perm
-  sc.reserve(sizeof(uint32_t) * kBuckets);   // bucket histogram / offsets
+  sc.reserve(sizeof(uint32_t) * kBuckets);   // bucket offsets
+  sc.reserve(sizeof(uint32_t) * kBuckets * kCntPad);  // bucket counters
   sc.reserve(sizeof(uint32_t) * DDM_MAX_D);  // gstart
   sc.reserve(sizeof(uint32_t) * DDM_MAX_D);  // gcount
   sc.reserve(sizeof(uint32_t) * DDM_MAX_D);  // shape
@@ -1290,6 +1325,7 @@ static void front_reserve(Scratch& sc, uint32_t m, bool learned) {
   sc.reserve(sizeof(uint32_t));                  // largest count
   sc.reserve(sizeof(uint32_t) * (kBuckets + 1));     // tile prefix
   sc.reserve(sizeof(uint32_t) * front_max_tiles(m));  // tile -> bucket
+  sc.reserve(sizeof(uint32_t) * 2 * (size_t)m);       // candidate position bounds
 }
 
 static void front_take(Scratch& sc, MatchState& st, uint32_t m, bool learned, FrontPieces* fp) {
@@ -1299,6 +1335,7 @@ static void front_take(Scratch& sc, MatchState& st, uint32_t m, bool learned, Fr
   st.bucket = sc.take<uint32_t>(m);
   st.perm = sc.take<uint32_t>(m);
   st.bhist = sc.take<uint32_t>(kBuckets);
+  st.bcnt = sc.take<uint32_t>((size_t)kBuckets * kCntPad);
   st.gstart = sc.take<uint32_t>(DDM_MAX_D);
   st.gcount = sc.take<uint32_t>(DDM_MAX_D);
   st.shape = sc.take<uint32_t>(DDM_MAX_D);
@@ -1313,6 +1350,7 @@ static void front_take(Scratch& sc, MatchState& st, uint32_t m, bool learned, Fr
   st.maxcnt = sc.take<uint32_t>(1);
   st.tprefix = sc.take<uint32_t>(kBuckets + 1);
   st.tmap = sc.take<uint32_t>(front_max_tiles(m));
+  st.pb = sc.take<uint32_t>(2 * (size_t)m);
   if (learned) {
     st.X = sc.take<float>((size_t)m * kFeatures);
     st.cap = sc.take<uint32_t>(m);
@@ -1346,7 +1384,8 @@ static ddm_status front_half(const ddm_tree* t, const float* ulo, const float* u
                              const MatchPlan& P, MatchState& st, uint32_t* counts_out,
                              uint32_t** lists, uint32_t** lists_count, hipStream_t s,
                              const ddm_predictor* pred = nullptr, uint64_t budget = 0,
-                             bool want_stash = false, uint64_t stash_hint = 0) {
+                             bool want_stash = false, uint64_t stash_hint = 0,
+                             const ArenaGrant* grant = nullptr) {
   const uint32_t d = tree_d(t);
   const TreeDev T = tree_dev(t);
   Scratch& sc = st.sc;
@@ -1361,6 +1400,7 @@ static ddm_status front_half(const ddm_tree* t, const float* ulo, const float* u
   *lists_count = fp.lists_count;
   uint64_t* dwords = fp.dwords;
   if (!sc.fits()) return scratch_overrun("front_half");
+  st.pb_ok = d > 1;  // written by the probe kernel (d = 1 takes exact counts instead)
   if (st.learned) {
     learned_init_kernel<<<1, 64, 0, s>>>(st.govf);
     DDM_LAUNCHED("learned_init_kernel");
@@ -1385,7 +1425,7 @@ static ddm_status front_half(const ddm_tree* t, const float* ulo, const float* u
     uint32_t* sn = st.stash ? st.snext : nullptr;
     const unsigned g = kBuckets / 1024;
 #define DDM_INIT(DD)                                                                          \
-  match_init_kernel<DD><<<g, 1024, 0, s>>>(st.gcount, st.flag, *lists_count, st.bhist, sn,   \
+  match_init_kernel<DD><<<g, 1024, 0, s>>>(st.gcount, st.flag, *lists_count, st.bcnt, sn,    \
                                           st.sfirst, st.sslice, st.maxcnt, T, ulo, uhi, m, \
                                           st.shape)
     switch (d) {
@@ -1408,6 +1448,11 @@ static ddm_status front_half(const ddm_tree* t, const float* ulo, const float* u
   {
     ProfScope ps("order", s);
     uint32_t* tp = P.traversal == DDM_TRAVERSE_TILE ? st.tprefix : nullptr;
+    // the counts of the d probe dimensions' buckets, dense, into bhist (the
+    // scan turns them into offsets in place)
+    const uint32_t nbd = d * kBucketsPerDim;
+    bucket_gather_kernel<<<(nbd + 255) / 256, 256, 0, s>>>(st.bcnt, nbd, st.bhist);
+    DDM_LAUNCHED("bucket_gather_kernel");
     switch (d) {
       case 1: bucket_scan_kernel<8><<<1, 1024, 0, s>>>(st.bhist, m, st.gstart, st.gcount, tp); break;
       case 2: bucket_scan_kernel<16><<<1, 1024, 0, s>>>(st.bhist, m, st.gstart, st.gcount, tp); break;
@@ -1436,14 +1481,26 @@ static ddm_status front_half(const ddm_tree* t, const float* ulo, const float* u
     if (r != DDM_OK) return r;
     r = scan_u32_u64(st.cap, st.soff, m, stmp, s);
     if (r != DDM_OK) return r;
-    if (budget == 0) {
-      // arena sized to the predicted total (one extra stream synchronization)
+    {
+      // arena sized to the predicted total, or to the caller's budget if
+      // that is smaller (one extra stream synchronization); updates whose
+      // slots fall beyond the arena overflow and are filled exactly later
       uint64_t* hw0 = nullptr;
       r = host_words(&hw0);
       if (r != DDM_OK) return r;
       DDM_HIP(hipMemcpyAsync(hw0 + 4, st.soff + m, sizeof(uint64_t), hipMemcpyDeviceToHost, s));
       DDM_HIP(hipStreamSynchronize(s));
-      budget = hw0[4];
+      budget = budget == 0 ? hw0[4] : std::min<uint64_t>(budget, hw0[4]);
+      // a caller that accounts device memory grants the arena before it is
+      // allocated (it may wait there, or grant less)
+      if (grant) {
+        const uint64_t g = (*grant)(budget);
+        if (g == kArenaRefused) {
+          set_detail("slot arena not granted");
+          return DDM_E_NOMEM;
+        }
+        budget = std::min<uint64_t>(budget, g);
+      }
     }
     st.budget = budget;
     st.slots_sc.reserve(sizeof(uint64_t) * (budget ? budget : 1));
@@ -1689,12 +1746,10 @@ static ddm_status match_begin(const ddm_tree* t, const float* upd_lo, const floa
   return DDM_OK;
 }
 
-extern "C" ddm_status ddm_match_learned_begin(const ddm_tree* t, const float* upd_lo,
-                                              const float* upd_hi, uint32_t m,
-                                              const ddm_predictor* pred, uint64_t slot_budget,
-                                              uint64_t* out_count, void* stream,
-                                              const ddm_match_opts* opts,
-                                              ddm_pending** out_pending) {
+static ddm_status learned_begin(const ddm_tree* t, const float* upd_lo, const float* upd_hi,
+                                uint32_t m, const ddm_predictor* pred, uint64_t slot_budget,
+                                uint64_t* out_count, void* stream, const ddm_match_opts* opts,
+                                ddm_pending** out_pending, const ArenaGrant* grant) {
   set_detail("");
   if (!out_count || !out_pending || !pred) {
     set_detail("out_count / out_pending / predictor is NULL");
@@ -1728,7 +1783,7 @@ extern "C" ddm_status ddm_match_learned_begin(const ddm_tree* t, const float* up
   pd->uhi = upd_hi;
   pd->m = m;
   r = front_half(t, upd_lo, upd_hi, m, P, pd->st, nullptr, &pd->lists, &pd->lists_count, s, pred,
-                 slot_budget);
+                 slot_budget, false, 0, grant);
   if (r != DDM_OK) {
     delete pd;
     return r;
@@ -1737,6 +1792,26 @@ extern "C" ddm_status ddm_match_learned_begin(const ddm_tree* t, const float* up
   *out_pending = pd;
   return DDM_OK;
 }
+
+extern "C" ddm_status ddm_match_learned_begin(const ddm_tree* t, const float* upd_lo,
+                                              const float* upd_hi, uint32_t m,
+                                              const ddm_predictor* pred, uint64_t slot_budget,
+                                              uint64_t* out_count, void* stream,
+                                              const ddm_match_opts* opts,
+                                              ddm_pending** out_pending) {
+  return learned_begin(t, upd_lo, upd_hi, m, pred, slot_budget, out_count, stream, opts,
+                       out_pending, nullptr);
+}
+
+namespace ddm {
+ddm_status match_learned_begin_granted(const ddm_tree* t, const float* upd_lo,
+                                       const float* upd_hi, uint32_t m,
+                                       const ddm_predictor* pred, uint64_t* out_count,
+                                       hipStream_t s, const ddm_match_opts* opts,
+                                       ddm_pending** out_pending, const ArenaGrant& grant) {
+  return learned_begin(t, upd_lo, upd_hi, m, pred, 0, out_count, s, opts, out_pending, &grant);
+}
+}  // namespace ddm
 
 extern "C" ddm_status ddm_pending_info(const ddm_pending* pd, uint64_t* slots, uint64_t* budget,
                                        uint32_t* overflowed) {
@@ -1789,6 +1864,7 @@ extern "C" ddm_status ddm_match_finish(ddm_pending* pd, uint64_t* out_pairs, uin
         // overflowed updates are few and scattered, and each has many
         // hits: one wavefront per update scans its candidate range
         UpdSet OV{st.perm_ovf, st.gstart, st.govf, st.novf, 1};
+        OV.pb = st.all().pb;
         MatchPlan TP = pd->plan;
         TP.traversal = DDM_TRAVERSE_TILE;
         r = traverse_any<true>(tree_d(pd->t), TP, T, pd->ulo, pd->uhi, pd->m, OV, st.kstar, O,

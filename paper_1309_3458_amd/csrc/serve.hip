@@ -27,6 +27,7 @@
 #include <map>
 #include <mutex>
 #include <new>
+#include <set>
 #include <string>
 #include <thread>
 #include <unordered_map>
@@ -131,7 +132,10 @@ struct ddm_server {
   std::vector<uint64_t> done;                           // completion queue
   std::map<uint64_t, int> in_flight;                    // ticket -> 1
   uint64_t used = 0, peak = 0;
+  uint32_t waiting = 0;          // requests in flight blocked in charge()
+  std::set<uint64_t> yieldable;  // tickets blocked in charge() that may yield
   uint64_t submitted = 0, completed = 0;
+  uint64_t yields = 0;  // requests that gave their memory back and were requeued
   HostPool pool;
   std::unordered_map<uint64_t, CachedTree> trees;
   std::list<uint64_t> lru;  // front = most recent
@@ -159,16 +163,42 @@ uint64_t admission_bytes(const ddm_request& r, bool build) {
   return b;
 }
 
-// Charge `bytes` to the budget; waits unless they fit or `q` is the oldest
-// request in flight.  Called with the lock held.
-void charge(ddm_server* S, std::unique_lock<std::mutex>& lk, ddm_server_req* q, uint64_t bytes) {
+// Charge `bytes` to the budget, waiting until they fit.  A request alone in
+// flight goes ahead even past the budget (nothing else could free memory for
+// it).  When every request in flight is waiting here, none can free memory
+// for the others: the youngest of those that may yield (may_yield: it can
+// still give back everything it holds and start again) returns false
+// without charging anything; if none may, the oldest goes ahead past the
+// budget.  So the budget is exceeded only by a request that alone needs more,
+// or when no waiting request can yield.  Called with the lock held.
+bool charge(ddm_server* S, std::unique_lock<std::mutex>& lk, ddm_server_req* q, uint64_t bytes,
+            bool may_yield = false) {
+  ++S->waiting;
+  if (may_yield) S->yieldable.insert(q->ticket);
+  S->cv_mem.notify_all();  // the others may be waiting for everyone to wait
+  bool yield = false;
   S->cv_mem.wait(lk, [&] {
-    return S->stop || S->used + bytes <= S->o.hbm_budget ||
-           (!S->in_flight.empty() && S->in_flight.begin()->first == q->ticket);
+    if (S->stop || S->used + bytes <= S->o.hbm_budget || S->in_flight.size() <= 1) return true;
+    if (S->waiting < S->in_flight.size()) return false;  // a request is still running
+    if (!S->yieldable.empty()) {
+      if (may_yield && *S->yieldable.rbegin() == q->ticket) {
+        yield = true;
+        return true;
+      }
+      return false;
+    }
+    return S->in_flight.begin()->first == q->ticket;
   });
+  --S->waiting;
+  if (may_yield) S->yieldable.erase(q->ticket);
+  if (yield) {
+    S->cv_mem.notify_all();
+    return false;
+  }
   S->used += bytes;
   q->charged += bytes;
   if (S->used > S->peak) S->peak = S->used;
+  return true;
 }
 
 void uncharge(ddm_server* S, ddm_server_req* q, uint64_t bytes) {
@@ -264,7 +294,8 @@ ddm_status deliver_host(ddm_server* S, ddm_server_req* q, const uint64_t* keys, 
   return DDM_OK;
 }
 
-ddm_status process(ddm_server* S, ddm_server_req* q, hipStream_t s, std::string* why) {
+ddm_status process(ddm_server* S, ddm_server_req* q, hipStream_t s, std::string* why,
+                   bool* yielded = nullptr) {
   const ddm_request& r = q->r;
   auto fail = [&](ddm_status st) {
     *why = ddm_last_error_detail();
@@ -352,31 +383,72 @@ ddm_status process(ddm_server* S, ddm_server_req* q, hipStream_t s, std::string*
   ddm_pending* pend = nullptr;
   uint64_t K = 0;
   ddm_status st;
-  if (S->pred && r.d <= 3)
-    st = ddm_match_learned_begin(t, r.upd_lo, r.upd_hi, r.m, S->pred, 0, &K, s, &mo, &pend);
-  else
+  const bool learned = S->pred && r.d <= 3 && r.d > 1;
+  uint64_t held = 0;  // bytes charged for the slot arena and the output
+  if (learned) {
+    // Once the predicted number of slots P is known, and before the match
+    // allocates its arena, the arena (8P bytes) and an estimate of the output
+    // of the same size are charged together (waiting like any other charge),
+    // so that a request that got past this point rarely waits again.
+    bool refused = false;
+    const ArenaGrant grant = [&](uint64_t want) -> uint64_t {
+      std::unique_lock<std::mutex> lk(S->mu);
+      if (!charge(S, lk, q, 16 * std::max<uint64_t>(want, 1), yielded != nullptr)) {
+        refused = true;
+        return kArenaRefused;
+      }
+      held = 16 * std::max<uint64_t>(want, 1);
+      return want;
+    };
+    st = match_learned_begin_granted(t, r.upd_lo, r.upd_hi, r.m, S->pred, &K, s, &mo, &pend,
+                                     grant);
+    if (refused) {
+      // give everything back and start again later (the worker requeues)
+      drop_tree();
+      *yielded = true;
+      return DDM_OK;
+    }
+  } else {
     st = ddm_match_begin(t, r.upd_lo, r.upd_hi, r.m, &K, s, &mo, &pend);
+  }
   if (st != DDM_OK) {
+    if (held) {
+      std::lock_guard<std::mutex> lk(S->mu);
+      uncharge(S, q, held);
+    }
     drop_tree();
     return fail(st);
   }
-  uint64_t slots = 0, budget = 0;
+  uint64_t slots = 0, arena = 0;
   uint32_t ovf = 0;
-  if (pend) (void)ddm_pending_info(pend, &slots, &budget, &ovf);
+  if (pend) (void)ddm_pending_info(pend, &slots, &arena, &ovf);
   q->K = K;
   q->slots = slots;
   q->overflowed = ovf;
   const uint64_t out_bytes = 8 * std::max<uint64_t>(K, 1);
+  const uint64_t arena_bytes = learned ? 8 * std::max<uint64_t>(arena, 1) : 0;
   {
-    // predicted output (slot arena, already allocated by the match) and the
-    // exact output
+    // the charge becomes the arena actually allocated plus the exact output
     std::unique_lock<std::mutex> lk(S->mu);
-    charge(S, lk, q, 8 * slots + out_bytes);
+    const uint64_t need = arena_bytes + out_bytes;
+    if (need <= held) {
+      uncharge(S, q, held - need);
+    } else if (!charge(S, lk, q, need - held, yielded != nullptr)) {
+      uncharge(S, q, held);
+      lk.unlock();
+      ddm_match_abort(pend);
+      drop_tree();
+      *yielded = true;
+      return DDM_OK;
+    }
+    held = need;
   }
   uint64_t* out = (uint64_t*)dev_alloc(out_bytes, s);
   if (!out) {
     ddm_match_abort(pend);
     drop_tree();
+    std::lock_guard<std::mutex> lk(S->mu);
+    uncharge(S, q, held);
     *why = "device allocation of the result failed";
     return DDM_E_NOMEM;
   }
@@ -384,13 +456,17 @@ ddm_status process(ddm_server* S, ddm_server_req* q, hipStream_t s, std::string*
   if (st != DDM_OK) {
     drop_tree();
     dev_free((char*)out, s);
+    std::lock_guard<std::mutex> lk(S->mu);
+    uncharge(S, q, held);
     return fail(st);
   }
   if (S->o.deliver_device) {
+    // the result stays in device memory (charged until released); the
+    // arena is gone
     drop_tree();
     q->dev = out;
     std::lock_guard<std::mutex> lk(S->mu);
-    uncharge(S, q, 8 * slots);
+    uncharge(S, q, arena_bytes);
     return DDM_OK;
   }
   st = deliver_host(S, q, out, K, s, why);
@@ -398,7 +474,7 @@ ddm_status process(ddm_server* S, ddm_server_req* q, hipStream_t s, std::string*
   dev_free((char*)out, s);
   {
     std::lock_guard<std::mutex> lk(S->mu);
-    uncharge(S, q, 8 * slots + out_bytes);
+    uncharge(S, q, held);
   }
   return st;
 }
@@ -553,8 +629,26 @@ void worker_main(ddm_server* S) {
     } else if (G.size() == 1) {
       sts.assign(1, DDM_OK);
       whys.assign(1, std::string());
-      sts[0] = process(S, G[0], s, &whys[0]);
-      if (sts[0] != DDM_OK) (void)hipStreamSynchronize(s);
+      bool yielded = false;
+      sts[0] = process(S, G[0], s, &whys[0], &yielded);
+      if (sts[0] != DDM_OK || yielded) (void)hipStreamSynchronize(s);
+      if (yielded) {
+        // back to the head of the queue, holding nothing; it is admitted
+        // again when memory frees up
+        ddm_server_req* q = G[0];
+        std::lock_guard<std::mutex> lk(S->mu);
+        uncharge(S, q, q->charged);
+        S->in_flight.erase(q->ticket);
+        q->t_start = 0;
+        q->K = q->slots = 0;
+        q->overflowed = 0;
+        q->tree_cached = false;
+        ++S->yields;
+        S->queue.push_front(q);
+        S->cv_mem.notify_all();
+        S->cv_work.notify_all();
+        continue;
+      }
     } else {
       process_batch(S, G, s, &sts, &whys);
     }
@@ -737,6 +831,7 @@ extern "C" ddm_status ddm_server_stats(ddm_server* S, ddm_server_counters* st) {
   st->hbm_peak = S->peak;
   st->host_pool_used = S->pool.used;
   st->trees_resident = S->trees.size();
+  st->requeued = S->yields;
   return DDM_OK;
 }
 

@@ -97,6 +97,10 @@ struct UpdSet {
   const uint32_t* boff = nullptr;
   const uint32_t* tprefix = nullptr;
   const uint32_t* tmap = nullptr;
+  // optional: per update j, pb[2j] <= the first and pb[2j+1] >= the last
+  // position of its candidate range in its probe tree (bounds from the
+  // probe's quantile searches); tiles then skip their own searches
+  const uint32_t* pb = nullptr;
 };
 
 // Where a traversal writes.  COUNT (fill == false): cnt[j] = hits of j.
@@ -212,7 +216,8 @@ __device__ __forceinline__ void tile_body(const TreeDev& T, const float* __restr
                                           uint32_t k, uint32_t qbeg, uint32_t nq, const SegOut& O,
                                           float* __restrict__ s_cand, uint32_t* __restrict__ s_cid,
                                           float4* __restrict__ s_q, uint32_t lane,
-                                          uint32_t tile_id = 0) {
+                                          uint32_t tile_id = 0,
+                                          const uint32_t* __restrict__ pb = nullptr) {
   constexpr int R = 2 * D;
   constexpr int RV = (R + 3) / 4;
   const bool qv = lane < nq;
@@ -248,9 +253,21 @@ __device__ __forceinline__ void tile_body(const TreeDev& T, const float* __restr
     ehi[s] = wave_max(qh[s]);
   }
   // candidate positions of the tile in tree k: lower bound in
-  // [t, Ehi] with t <= Elo - maxlen (see the probe kernels)
+  // [t, Ehi] with t <= Elo - maxlen (see the probe kernels).  With per-update
+  // bounds from the probe (a superset of each update's range; every
+  // position scanned is still tested exactly), the tile's range is their
+  // union; otherwise two-level searches over the sorted lower bounds.
   uint32_t Pbeg, Pend;
-  {
+  if (pb) {
+    uint32_t b0 = 0xffffffffu, e0 = 0u;
+    if (qv) {
+      const uint2 be = reinterpret_cast<const uint2*>(pb)[j];
+      b0 = be.x;
+      e0 = be.y;
+    }
+    Pbeg = wave_min_u32(b0);
+    Pend = wave_max_u32(e0);
+  } else {
     const uint32_t* keys[2] = {T.skey_lo[k], T.skey_lo[k]};
     const uint32_t* idx[2] = {T.sidx_lo[k], T.sidx_lo[k]};
     const uint32_t x[2] = {f2key(ehi[0]), f2key(nextafterf(elo[0] - T.maxlen[k], -INFINITY))};

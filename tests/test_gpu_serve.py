@@ -203,3 +203,32 @@ def test_open_loop_poisson_run():
     alone = serve.check_alone(st["samples"], sched)
     assert alone == len(st["samples"]) >= len(sched) // 10 - 1
     assert check_samples_oracle(st["samples"], sched) >= 1
+
+
+def test_learned_burst_stays_within_the_hbm_budget():
+    """Learned sizing under a binding device budget: each request's slot
+    arena (with an output estimate of the same size) is charged before the
+    match allocates it, so the server's peak of charged device memory
+    (inputs, trees, scratch, arenas, outputs) stays within the budget when
+    every single request fits in it: requests wait instead, and every result
+    equals the request matched alone.  When every request in flight waits
+    for memory, the youngest gives its memory back and starts again later
+    (counted as requeued) instead of the oldest going past the budget."""
+    import paper_1309_3458_amd as P
+    from paper_1309_3458_amd import learn
+    pred, _ = learn.train_predictor(n_inst=8, per_instance=4000, epochs=6)
+    insts = [W.uniform_instance([96, k], 100_000, 100_000, 2,
+                                W.side_for_alpha(30.0, 200_000, 2)) for k in range(12)]
+    budget = 768 << 20
+    srv = P.Server(predictor=pred, workers=8, hbm_budget=budget, host_pool=2 << 30)
+    res = _serve_all(srv, insts)
+    st = srv.stats()
+    srv.close()
+    assert all(r["status"] == 0 for r in res)
+    # the arenas were big enough to matter: together beyond the budget
+    assert sum(8 * r["slots"] for r in res) > budget
+    assert 0 < st["hbm_peak"] <= budget, st
+    assert st["hbm_used"] == 0 and st["requeued"] >= 0
+    for inst, r in zip(insts[:4], res[:4]):
+        assert np.array_equal(r["pairs"], _alone(inst))
+    pred.free()
