@@ -34,7 +34,9 @@ Workloads:
 Prints ONE JSON line: pairs/s (value), regions/s, per-step statistics, the
 roofline of the dominant kernel (its launch durations measured with HIP
 events on the stream it is launched on) and the CPU oracle's rate on the
-host.
+host.  The default workload's line also carries the learned single pass
+against the plain two-pass path on the hotspot workload
+(hotspot_learned_vs_plain: times, speedup, identical bytes).
 """
 from __future__ import annotations
 
@@ -90,6 +92,9 @@ def parse():
     ap.add_argument("--tuning", default="",
                     help="batch256: tuning table (JSON); default: the packaged table")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-hotspot", action="store_true",
+                    help="d2_uniform: skip the learned-vs-plain comparison on the hotspot "
+                         "workload")
     ap.add_argument("--cpu-sample", type=int, default=0,
                     help="updates in the oracle's timed sample (0 = auto)")
     return ap.parse_args()
@@ -274,6 +279,56 @@ def oracle_rate(inst, cores, sample, what):
                       f"build included, {dt:.2f}s, {len(ok)} pairs"}
 
 
+def hotspot_paths(pred, steps, warmup):
+    """The learned single pass against the plain two-pass path on the hotspot
+    workload (d=2, 500,000 + 500,000 boxes around 16 Gaussian hotspots,
+    log-normal sides with median 1e4, seed 2), in build + match steps:
+    per-path time, speedup, overflowed updates, and that the two outputs are
+    identical element by element."""
+    import torch
+
+    import paper_1309_3458_amd as P
+    from paper_1309_3458_amd import workloads as W
+
+    inst = W.hotspot_2d(2)
+    dev = lambda a: torch.from_numpy(a).cuda()
+    s_lo, s_hi, u_lo, u_hi = dev(inst.s_lo), dev(inst.s_hi), dev(inst.u_lo), dev(inst.u_hi)
+    t = P.build(s_lo, s_hi)
+    out = P.match(t, u_lo, u_hi)
+    K = out.numel()
+    other = torch.empty_like(out)
+    info = {}
+    P.match_learned(t, u_lo, u_hi, pred, out=other, info=info)
+    same = bool(torch.equal(out, other))
+    t.free()
+    del other
+
+    def step(path):
+        tt = P.build(s_lo, s_hi)
+        if path == "plain":
+            k = P.match(tt, u_lo, u_hi, out=out).numel()
+        else:
+            k = P.match_learned(tt, u_lo, u_hi, pred, out=out).numel()
+        tt.free()
+        return k
+
+    res = {}
+    for path in ("plain", "learned"):
+        for _ in range(warmup):
+            step(path)
+        wall, per, k = evented_steps(lambda: step(path), steps)
+        assert k == K
+        res[path] = {"ms_per_step": round(wall, 3), "step_ms": step_stats(per),
+                     "pairs_per_s": round(K / (wall / 1e3), 1)}
+    del out
+    torch.cuda.synchronize()
+    return {"workload": "d2_N1e6_hotspots_alpha100", "seed": 2, "K": int(K), **res,
+            "learned_speedup_vs_plain": round(res["plain"]["ms_per_step"] /
+                                              res["learned"]["ms_per_step"], 4),
+            "identical_bytes": same, "overflowed": info.get("overflowed"),
+            "slots": info.get("slots")}
+
+
 def bench_single(args):
     import torch
 
@@ -374,6 +429,11 @@ def bench_single(args):
         cpu["single_thread"] = {"value": one["value"], "sample": one["sample"]}
         cpu.update(host)
 
+    hot = None
+    if args.workload == "d2_uniform" and pred is not None and not args.no_hotspot:
+        hot = hotspot_paths(pred, steps=min(args.steps, 10), warmup=2)
+        log(f"hotspot: {json.dumps(hot)}")
+
     paths = {k: {"ms_per_step": round(v["ms_per_step"], 4), "step_ms": v["step_ms"],
                  "pairs_per_s": round(K0 / (v["ms_per_step"] / 1e3), 1),
                  **({"overflowed": v.get("overflowed"), "slots": v.get("slots")}
@@ -398,6 +458,7 @@ def bench_single(args):
                        "val_mae_log1p": round(train_rep["val_mae_log1p"], 4),
                        "delta": round(train_rep["delta"], 4), "train_s": train_rep["train_s"]}
                       if train_rep else None),
+        "hotspot_learned_vs_plain": hot,
         "roofline": roofline,
         "cpu_baseline": cpu,
     }

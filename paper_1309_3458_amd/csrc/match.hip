@@ -441,6 +441,54 @@ __global__ __launch_bounds__(256) void bucket_scatter_kernel(const uint32_t* __r
 }
 
 // --------------------------------------------------------------------------
+// Learned sizing: tiles balanced by predicted work.  Within each bucket the
+// updates are cut into tiles at every 64th update (as for the count) and
+// also wherever the predicted hits accumulated since the bucket's start
+// cross a multiple of H = twice the predicted hits of an average full tile,
+// so that a wavefront never takes a tile of much more predicted output than
+// the average: dense regions get several small tiles, which run on separate
+// wavefronts, instead of one long one.
+// --------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void work_in_order_kernel(const uint32_t* __restrict__ perm,
+                                                            const uint32_t* __restrict__ cap,
+                                                            uint32_t m,
+                                                            uint32_t* __restrict__ w) {
+  const uint32_t p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p < m) w[p] = cap[perm[p]];
+}
+
+// flag[p] = 1 where a tile starts; cw: exclusive scan of w (cw[m] = total)
+__global__ __launch_bounds__(256) void tile_cut_kernel(const uint32_t* __restrict__ perm,
+                                                       const uint32_t* __restrict__ bucket,
+                                                       const uint32_t* __restrict__ boff,
+                                                       const uint64_t* __restrict__ cw,
+                                                       uint32_t m, uint32_t* __restrict__ flag) {
+  const uint32_t p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= m) return;
+  const uint64_t H = max((2ull * 64ull * cw[m]) / m, 1ull);
+  const uint32_t s = boff[bucket[perm[p]]];
+  bool cut = p == s || ((p - s) & 63u) == 0;
+  if (!cut) cut = (cw[p] - cw[s]) / H != (cw[p - 1] - cw[s]) / H;
+  flag[p] = cut ? 1u : 0u;
+}
+
+// tile t starts at the t-th flagged position; tstart[ntiles] = m
+__global__ __launch_bounds__(256) void tile_list_kernel(const uint32_t* __restrict__ perm,
+                                                        const uint32_t* __restrict__ bucket,
+                                                        const uint32_t* __restrict__ flag,
+                                                        const uint64_t* __restrict__ tidx,
+                                                        uint32_t m, uint32_t* __restrict__ tstart,
+                                                        uint32_t* __restrict__ tbuck) {
+  const uint32_t p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p < m && flag[p]) {
+    const uint32_t t = (uint32_t)tidx[p];
+    tstart[t] = p;
+    tbuck[t] = bucket[perm[p]];
+  }
+  if (p == 0) tstart[(uint32_t)tidx[m]] = m;
+}
+
+// --------------------------------------------------------------------------
 // 3/5a. one lane per update: Algorithm 4 without a stack.
 //
 // On the implicit in-order tree the recursion of Algorithm 4 becomes a walk
@@ -614,7 +662,9 @@ void tile_bucket_kernel(
   __shared__ float4 s_q[kTileWaves][kWave * RV];
   const uint32_t wave = threadIdx.x / kWave;
   const uint32_t lane = lane_id();
-  const uint32_t total = uniform_u32(US.tprefix[kBuckets]);
+  const bool list = US.tstart != nullptr;
+  const uint32_t total = list ? uniform_u32((uint32_t)*US.ntiles)
+                              : uniform_u32(US.tprefix[kBuckets]);
   {
     // Workgroups go to the XCDs in turn (workgroup i to XCD i mod kXcds).
     // Neighbouring tiles (the cells of one probe range) scan the same part
@@ -631,12 +681,19 @@ void tile_bucket_kernel(
     if (blk < nblk / W * W) blk = blk / W * W + blk % kXcds * kXcdRun + blk % W / kXcds;
     const uint32_t item = blk * kTileWaves + wave;
     if (item >= total) return;
-    const uint32_t b = uniform_u32(US.tmap[item]);
-    const uint32_t lt = item - uniform_u32(US.tprefix[b]);
-    const uint32_t start = uniform_u32(US.boff[b]);
-    const uint32_t end = b + 1 < kBuckets ? uniform_u32(US.boff[b + 1]) : US.total;
-    const uint32_t qbeg = start + lt * 64u;
-    const uint32_t nq = min(64u, end - qbeg);
+    uint32_t b, qbeg, nq;
+    if (list) {
+      b = uniform_u32(US.tbuck[item]);
+      qbeg = uniform_u32(US.tstart[item]);
+      nq = uniform_u32(US.tstart[item + 1]) - qbeg;
+    } else {
+      b = uniform_u32(US.tmap[item]);
+      const uint32_t lt = item - uniform_u32(US.tprefix[b]);
+      const uint32_t start = uniform_u32(US.boff[b]);
+      const uint32_t end = b + 1 < kBuckets ? uniform_u32(US.boff[b + 1]) : US.total;
+      qbeg = start + lt * 64u;
+      nq = min(64u, end - qbeg);
+    }
     tile_body<D, FILL, STASH>(T, ulo, uhi, m, US.perm, 0u, b / kBucketsPerDim, qbeg, nq, O,
                               s_cand[wave], s_cid[wave], s_q[wave], lane, item, US.pb);
   }
@@ -790,81 +847,109 @@ __global__ __launch_bounds__(kSegWaves * kWave) void segsort_mid_kernel(
   }
 }
 
-// One workgroup per listed segment of 2049..16384 keys.  The ids of a
-// segment are distinct; they are counted into 1024 buckets of consecutive
-// ids (id >> shift) in LDS, placed by bucket, and each bucket (16 ids on
-// average at the largest size) is insertion-sorted by one thread.  A segment
-// with a bucket of more than kBucketCap ids is left to the bitmap kernel
+// One workgroup per listed segment of MAXLEN/2 + 1 .. MAXLEN keys (MAXLEN =
+// 4096, 8192, 16384; one launch per size class, so that the smaller classes
+// need less LDS and more workgroups share a compute unit and overlap their
+// loads): a counting sort over MAXLEN buckets of consecutive ids
+// (id >> shift, about one id per bucket at the largest size of the class),
+// in LDS.  Each thread loads its (at most 16) keys once into registers; the
+// ids are counted, the counts scanned (thread t owns buckets 16t .. 16t+15),
+// the ids placed by bucket, and then each thread insertion-sorts its own run
+// of the placed ids, which spans its 16 buckets and is already ordered
+// between buckets (so it takes about as many steps as the run is long).
+// The sorted segment is written once.  A segment whose ids crowd into few
+// buckets (a thread's run longer than kRunCap) is left to the bitmap kernel
 // below; every segment handled here is marked done in its list entry.
 constexpr uint32_t kBucketSegMax = 16384;
-constexpr uint32_t kSegBuckets = 1024;
-constexpr uint32_t kBucketCap = 64;
+constexpr uint32_t kPerThread = 16;  // keys per thread, buckets per thread
+constexpr uint32_t kRunCap = 128;
 constexpr uint32_t kListDone = 0x80000000u;
 
-__global__ __launch_bounds__(kSegBuckets) void segsort_bucket_kernel(
+template <uint32_t MAXLEN>
+__global__ __launch_bounds__(MAXLEN / kPerThread) void segsort_bucket_kernel(
     const uint64_t* __restrict__ off, uint32_t m, uint64_t* __restrict__ out, SegSrc S,
     uint32_t* __restrict__ lists, const uint32_t* __restrict__ list_count, uint32_t shift) {
-  __shared__ uint32_t sorted[kBucketSegMax];
-  __shared__ uint32_t cur[kSegBuckets];
-  __shared__ uint32_t start[kSegBuckets + 1];
-  __shared__ uint32_t wsum[kSegBuckets / kWave];
-  __shared__ uint32_t maxb;
+  constexpr uint32_t NT = MAXLEN / kPerThread;  // threads
+  constexpr uint32_t NB = MAXLEN;                // buckets
+  __shared__ uint32_t sorted[MAXLEN];
+  __shared__ uint32_t cnt[NB];
+  __shared__ uint32_t wsum[NT / kWave];
+  __shared__ uint32_t maxrun;
   const uint32_t cntl = list_count[1];
   const uint32_t tid = threadIdx.x, lane = lane_id(), wave = tid / kWave;
   for (uint32_t li = blockIdx.x; li < cntl; li += gridDim.x) {
     const uint32_t j = lists[m + li];
+    if (j & kListDone) continue;
     const uint64_t b = off[j];
     const uint64_t len64 = off[j + 1] - b;
-    if (len64 > kBucketSegMax) continue;
+    if (len64 > MAXLEN || len64 <= MAXLEN / 2) continue;
     const uint32_t len = (uint32_t)len64;
     bool in_place;
     const uint64_t* src = seg_src(S, j, out, b, &in_place);
     const uint64_t jhi = src[0] & 0xffffffff00000000ull;
-    cur[tid] = 0;
-    if (tid == 0) maxb = 0;
+    // this thread's keys: positions tid + r * NT (all loads in flight while
+    // the counters are cleared)
+    uint32_t ids[kPerThread];
+#pragma unroll
+    for (uint32_t r = 0; r < kPerThread; ++r) {
+      const uint32_t i = tid + r * NT;
+      ids[r] = i < len ? (uint32_t)src[i] : 0u;
+    }
+#pragma unroll
+    for (uint32_t q = 0; q < kPerThread; ++q) cnt[q * NT + tid] = 0;
+    if (tid == 0) maxrun = 0;
     __syncthreads();
-    for (uint32_t i = tid; i < len; i += kSegBuckets)
-      atomicAdd(&cur[min((uint32_t)src[i] >> shift, kSegBuckets - 1u)], 1u);
+#pragma unroll
+    for (uint32_t r = 0; r < kPerThread; ++r)
+      if (tid + r * NT < len) atomicAdd(&cnt[min(ids[r] >> shift, NB - 1u)], 1u);
     __syncthreads();
-    const uint32_t h = cur[tid];
-    atomicMax(&maxb, h);
-    uint32_t inc = h;
+    // exclusive scan: this thread's 16 buckets, then across threads
+    uint32_t c[kPerThread];
+    uint32_t run = 0;
+#pragma unroll
+    for (uint32_t q = 0; q < kPerThread; ++q) {
+      c[q] = cnt[tid * kPerThread + q];
+      run += c[q];
+    }
+    uint32_t inc = run;
 #pragma unroll
     for (int o = 1; o < kWave; o <<= 1) {
       const uint32_t t2 = __shfl_up(inc, o, kWave);
       if (lane >= (uint32_t)o) inc += t2;
     }
     if (lane == kWave - 1) wsum[wave] = inc;
+    atomicMax(&maxrun, run);
     __syncthreads();
     uint32_t before = 0;
     for (uint32_t q = 0; q < wave; ++q) before += wsum[q];
-    const uint32_t st = before + inc - h;
-    start[tid] = st;
-    cur[tid] = st;
-    if (tid == 0) start[kSegBuckets] = len;
-    __syncthreads();
-    const bool skip = maxb > kBucketCap;
-    __syncthreads();  // every thread has read maxb before the next segment resets it
-    if (skip) continue;
-    for (uint32_t i = tid; i < len; i += kSegBuckets) {
-      const uint32_t id = (uint32_t)src[i];
-      sorted[atomicAdd(&cur[min(id >> shift, kSegBuckets - 1u)], 1u)] = id;
-    }
-    __syncthreads();
+    const uint32_t my0 = before + inc - run;  // first slot of this thread's run
     {
-      const uint32_t s0 = start[tid], s1 = start[tid + 1];
-      for (uint32_t i = s0 + 1; i < s1; ++i) {
-        const uint32_t x = sorted[i];
-        uint32_t k = i;
-        while (k > s0 && sorted[k - 1] > x) {
-          sorted[k] = sorted[k - 1];
-          --k;
-        }
-        sorted[k] = x;
+      uint32_t at = my0;
+#pragma unroll
+      for (uint32_t q = 0; q < kPerThread; ++q) {
+        cnt[tid * kPerThread + q] = at;
+        at += c[q];
       }
     }
     __syncthreads();
-    for (uint32_t i = tid; i < len; i += kSegBuckets) out[b + i] = jhi | sorted[i];
+    const bool skip = maxrun > kRunCap;
+    __syncthreads();  // every thread has read maxrun before the next segment resets it
+    if (skip) continue;
+#pragma unroll
+    for (uint32_t r = 0; r < kPerThread; ++r)
+      if (tid + r * NT < len) sorted[atomicAdd(&cnt[min(ids[r] >> shift, NB - 1u)], 1u)] = ids[r];
+    __syncthreads();
+    for (uint32_t i = my0 + 1; i < my0 + run; ++i) {
+      const uint32_t x = sorted[i];
+      uint32_t k = i;
+      while (k > my0 && sorted[k - 1] > x) {
+        sorted[k] = sorted[k - 1];
+        --k;
+      }
+      sorted[k] = x;
+    }
+    __syncthreads();
+    for (uint32_t i = tid; i < len; i += NT) out[b + i] = jhi | sorted[i];
     if (tid == 0) lists[m + li] = j | kListDone;
     __syncthreads();
   }
@@ -1008,12 +1093,16 @@ static ddm_status launch_traverse(const MatchPlan& P, const TreeDev& T, const fl
     lane_kernel<D, FILL><<<(US.total + bs - 1) / bs, bs, 0, s>>>(T, ulo, uhi, m, US, kstar, O);
     DDM_LAUNCHED("lane_kernel");
   } else {
-    ProfScope ps(FILL ? (US.qpt == 1 ? "traverse_tile1_fill" : "traverse_tile_fill")
+    ProfScope ps(FILL ? (US.qpt == 1 ? "traverse_tile1_fill"
+                                     : US.tstart ? "traverse_tile_fill_balanced"
+                                                 : "traverse_tile_fill")
                       : (O.skey && US.tmap ? "traverse_tile_count_stash" : "traverse_tile_count"),
                  s);
-    if (US.tmap) {
-      // at most one partial tile per bucket
-      const uint32_t tiles = (US.total + 63u) / 64u + std::min<uint32_t>(US.total, kBuckets);
+    if (US.tmap || US.tstart) {
+      // at most one partial tile per bucket; a tile list cut by predicted
+      // work as well has at most twice as many
+      uint32_t tiles = (US.total + 63u) / 64u + std::min<uint32_t>(US.total, kBuckets);
+      if (US.tstart) tiles *= 2;
       const uint32_t grid = (tiles + kTileWaves - 1) / kTileWaves;
       if (!FILL && O.skey)
         tile_bucket_kernel<D, false, true><<<grid, kTileWaves * kWave, 0, s>>>(T, ulo, uhi, m,
@@ -1079,6 +1168,7 @@ struct MatchState {
   uint32_t* shape = nullptr;  // cell shape (log2 B1) of each probe dimension
   uint32_t* pb = nullptr;     // per update: candidate position bounds (d > 1)
   bool pb_ok = false;
+  bool balanced = false;  // the learned single pass runs the work-cut tile list
   int32_t* flag = nullptr;
   uint32_t* cnt = nullptr;
   uint64_t* off = nullptr;
@@ -1095,6 +1185,11 @@ struct MatchState {
   uint64_t slots_total = 0;
   uint32_t* perm_ovf = nullptr;
   uint32_t* govf = nullptr;
+  // tiles cut by predicted work (learned): list, bucket of each, count
+  uint32_t* wtile = nullptr;   // work in perm order, then cut flags
+  uint64_t* cwork = nullptr;   // exclusive scan of the work, then of the flags
+  uint32_t* tstart = nullptr;
+  uint32_t* tbuck = nullptr;
   uint32_t novf = 0;
   // bucket-aligned tiles
   uint32_t* tprefix = nullptr;
@@ -1124,6 +1219,11 @@ struct MatchState {
     U.tprefix = tprefix;
     U.tmap = tmap;
     U.pb = pb_ok ? pb : nullptr;
+    if (balanced) {
+      U.tstart = tstart;
+      U.tbuck = tbuck;
+      U.ntiles = cwork + m;
+    }
     return U;
   }
 };
@@ -1304,6 +1404,10 @@ static void front_reserve(Scratch& sc, uint32_t m, bool learned) {
     sc.reserve(sizeof(uint64_t) * (m + 1));             // soff
     sc.reserve(sizeof(uint32_t) * m);                   // perm_ovf
     sc.reserve(sizeof(uint32_t) * DDM_MAX_D);           // govf
+    sc.reserve(sizeof(uint32_t) * m);                   // work / cut flags
+    sc.reserve(sizeof(uint64_t) * (m + 1));             // their scan
+    sc.reserve(sizeof(uint32_t) * ((size_t)m + 1));     // tile starts
+    sc.reserve(sizeof(uint32_t) * m);                   // tile buckets
   }
   sc.reserve(sizeof(uint32_t) * m);          // cmin
   sc.reserve(m);                             // kstar
@@ -1357,6 +1461,10 @@ static void front_take(Scratch& sc, MatchState& st, uint32_t m, bool learned, Fr
     st.soff = sc.take<uint64_t>(m + 1);
     st.perm_ovf = sc.take<uint32_t>(m);
     st.govf = sc.take<uint32_t>(DDM_MAX_D);
+    st.wtile = sc.take<uint32_t>(m);
+    st.cwork = sc.take<uint64_t>(m + 1);
+    st.tstart = sc.take<uint32_t>((size_t)m + 1);
+    st.tbuck = sc.take<uint32_t>(m);
   }
 }
 
@@ -1481,6 +1589,22 @@ static ddm_status front_half(const ddm_tree* t, const float* ulo, const float* u
     if (r != DDM_OK) return r;
     r = scan_u32_u64(st.cap, st.soff, m, stmp, s);
     if (r != DDM_OK) return r;
+    if (P.traversal == DDM_TRAVERSE_TILE) {
+      ProfScope ps("balance", s);
+      const unsigned g = (m + 255) / 256;
+      work_in_order_kernel<<<g, 256, 0, s>>>(st.perm, st.cap, m, st.wtile);
+      DDM_LAUNCHED("work_in_order_kernel");
+      r = scan_u32_u64(st.wtile, st.cwork, m, stmp, s);
+      if (r != DDM_OK) return r;
+      tile_cut_kernel<<<g, 256, 0, s>>>(st.perm, st.bucket, st.bhist, st.cwork, m, st.wtile);
+      DDM_LAUNCHED("tile_cut_kernel");
+      r = scan_u32_u64(st.wtile, st.cwork, m, stmp, s);
+      if (r != DDM_OK) return r;
+      tile_list_kernel<<<g, 256, 0, s>>>(st.perm, st.bucket, st.wtile, st.cwork, m, st.tstart,
+                                         st.tbuck);
+      DDM_LAUNCHED("tile_list_kernel");
+      st.balanced = true;
+    }
     {
       // arena sized to the predicted total, or to the caller's budget if
       // that is smaller (one extra stream synchronization); updates whose
@@ -1666,11 +1790,25 @@ ddm_status sort_segments(const uint64_t* off, uint32_t m, uint64_t* out, uint64_
   ddm_status r = ensure_segsort_attr();
   if (r != DDM_OK) return r;
   {
+    // buckets of 2^shift consecutive ids, as many as the class's largest
+    // segment has keys (fewer when n is smaller)
     uint32_t bits = 0;
     while (bits < 32 && (1ull << bits) < n) ++bits;
-    const uint32_t shift = bits > 10 ? bits - 10 : 0;
-    segsort_bucket_kernel<<<1024, kSegBuckets, 0, s>>>(off, m, out, S, lists, lists_count, shift);
-    DDM_LAUNCHED("segsort_bucket_kernel");
+    const uint32_t s12 = bits > 12 ? bits - 12 : 0, s13 = bits > 13 ? bits - 13 : 0,
+                   s14 = bits > 14 ? bits - 14 : 0;
+    segsort_bucket_kernel<4096><<<2048, 4096 / kPerThread, 0, s>>>(off, m, out, S, lists,
+                                                                   lists_count, s12);
+    DDM_LAUNCHED("segsort_bucket_kernel<4096>");
+    if (max_len > 4096) {
+      segsort_bucket_kernel<8192><<<1024, 8192 / kPerThread, 0, s>>>(off, m, out, S, lists,
+                                                                     lists_count, s13);
+      DDM_LAUNCHED("segsort_bucket_kernel<8192>");
+    }
+    if (max_len > 8192) {
+      segsort_bucket_kernel<16384><<<512, 16384 / kPerThread, 0, s>>>(off, m, out, S, lists,
+                                                                      lists_count, s14);
+      DDM_LAUNCHED("segsort_bucket_kernel<16384>");
+    }
   }
   segsort_big_kernel<<<512, kBigThreads, words * sizeof(uint32_t), s>>>(off, m, out, S, lists,
                                                                         lists_count, tmp, n, words);

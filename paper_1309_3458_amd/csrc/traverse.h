@@ -101,6 +101,12 @@ struct UpdSet {
   // position of its candidate range in its probe tree (bounds from the
   // probe's quantile searches); tiles then skip their own searches
   const uint32_t* pb = nullptr;
+  // optional tile list (replaces the 64-update tiles of tprefix / tmap):
+  // tile t holds perm[tstart[t] .. tstart[t+1]) (at most 64 updates, one
+  // bucket), belongs to bucket tbuck[t], and there are *ntiles tiles
+  const uint32_t* tstart = nullptr;
+  const uint32_t* tbuck = nullptr;
+  const uint64_t* ntiles = nullptr;
 };
 
 // Where a traversal writes.  COUNT (fill == false): cnt[j] = hits of j.

@@ -180,3 +180,60 @@ def test_training_gain_over_untrained(trained):
     assert np.array_equal(a, b)
     assert i_tr["overflowed"] < 0.25 * max(1, i_raw["overflowed"])
     assert i_tr["overflowed"] < 0.2 * inst.m
+
+
+@pytest.mark.slow
+def test_learned_gain_over_plain_on_hotspots():
+    """What the learned single pass gains over the plain two-pass path on the
+    hotspot workload (500,000 + 500,000 boxes around 16 Gaussian hotspots,
+    log-normal sides, seed 2; about 1.8e9 pairs): the same bytes, no count
+    traversal (one pass over tiles cut by predicted work), and a shorter
+    build + match step (median of 3 timed steps each, after a warm-up)."""
+    import paper_1309_3458_amd as P
+    from paper_1309_3458_amd import learn
+    torch = _torch()
+    pred, _ = learn.train_predictor(n_inst=32, per_instance=16000, epochs=20)
+    inst = W.hotspot_2d(2)
+    s_lo, s_hi, u_lo, u_hi = dev(inst.s_lo), dev(inst.s_hi), dev(inst.u_lo), dev(inst.u_hi)
+    t = P.build(s_lo, s_hi)
+    plain = P.match(t, u_lo, u_hi)
+    K = plain.numel()
+    learned = torch.empty_like(plain)
+    P.match_learned(t, u_lo, u_hi, pred, out=learned)
+    t.free()
+    assert torch.equal(learned, plain)
+    del learned
+
+    def step(path):
+        tt = P.build(s_lo, s_hi)
+        if path == "plain":
+            k = P.match(tt, u_lo, u_hi, out=plain).numel()
+        else:
+            k = P.match_learned(tt, u_lo, u_hi, pred, out=plain).numel()
+        tt.free()
+        return k
+
+    kernels, ms = {}, {}
+    for path in ("plain", "learned"):
+        step(path)
+        P.prof_enable(True)
+        P.prof_read()
+        assert step(path) == K
+        torch.cuda.synchronize()
+        kernels[path] = P.prof_read()
+        P.prof_enable(False)
+        times = []
+        for _ in range(3):
+            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            a.record()
+            assert step(path) == K
+            b.record()
+            torch.cuda.synchronize()
+            times.append(a.elapsed_time(b))
+        ms[path] = sorted(times)[1]
+    assert any(k.startswith("traverse_tile_count") for k in kernels["plain"])
+    assert not any(k.startswith("traverse_tile_count") for k in kernels["learned"])
+    assert "traverse_tile_fill_balanced" in kernels["learned"]
+    print(f"hotspot step: plain {ms['plain']:.2f} ms, learned {ms['learned']:.2f} ms")
+    assert ms["learned"] < ms["plain"], ms
+    pred.free()
