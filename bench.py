@@ -24,6 +24,10 @@ Workloads:
   sweep_fig7            the time surface of the paper's Fig. 7 on the GPU: ITM
                         build + match for d=1, N from 5e4 to 5e5 and alpha
                         over 0 < alpha <= 100 (0.01 .. 100, half-decade steps)
+  dynamic               dynamic DDM on the d=2, 10^6-box workload: moves of 1% of
+                        the updates or of the subscriptions (resident trees
+                        and result, only the moved extents' pairs recomputed)
+                        against a full build + match of the moved sets
   hbm_copy              a plain device-to-device copy of 1 GiB per step
                         (calibrates the HBM traffic counters)
   serve                 open-loop Poisson arrivals (2000/s, d=3, N
@@ -69,7 +73,7 @@ def parse():
     ap.add_argument("--traversal", default="auto", choices=["auto", "lane", "tile"])
     ap.add_argument("--workload", default="d2_uniform",
                     choices=["d2_uniform", "d2_hotspot", "batch256", "serve", "hbm_copy",
-                             "sweep_1d", "sweep_fig7"])
+                             "sweep_1d", "sweep_fig7", "dynamic"])
     ap.add_argument("--duration", type=float, default=60.0,
                     help="serve: seconds of Poisson arrivals (the schedule is cut, not rescaled)")
     ap.add_argument("--rate", type=float, default=2000.0, help="serve: arrivals per second")
@@ -751,6 +755,57 @@ def bench_fig7(args):
             "grid": rows, "roofline": None, "cpu_baseline": None}
 
 
+def bench_dynamic(args):
+    """Dynamic DDM (the paper's dynamic scenario) on the d=2, 500,000 +
+    500,000 squares workload (alpha = 1, seed 1): each step moves 1% of one
+    set (updates and subscriptions alternately) to new uniform positions;
+    the resident matcher recomputes only the moved extents' pairs.  Beside it:
+    a full build + match of the same sets."""
+    import numpy as np
+    import torch
+
+    import paper_1309_3458_amd as P
+    from paper_1309_3458_amd import workloads as W
+
+    inst = W.uniform_2d_1m(1)
+    dev = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()
+    dy = P.Dynamic(dev(inst.s_lo), dev(inst.s_hi), dev(inst.u_lo), dev(inst.u_hi))
+    rng = np.random.default_rng(11)
+    c = inst.m // 100
+    side = np.float32(inst.side)
+    moves = []
+    for i in range(args.warmup + args.steps):
+        which = i % 2
+        ids = dev(rng.choice(inst.n if which == 0 else inst.m, c, replace=False).astype(np.int32))
+        lo = rng.uniform(0, 1e6, (2, c)).astype(np.float32)
+        moves.append((which, ids, dev(lo), dev((lo + side).astype(np.float32))))
+    it = iter(moves)
+    for _ in range(args.warmup):
+        dy.move(*next(it))
+    wall, per, K = evented_steps(lambda: dy.move(*next(it)), args.steps)
+    s_lo, s_hi, u_lo, u_hi = dev(inst.s_lo), dev(inst.s_hi), dev(inst.u_lo), dev(inst.u_hi)
+    out = torch.empty(K + (1 << 16), dtype=torch.int64, device="cuda")
+
+    def full():
+        t = P.build(s_lo, s_hi)
+        k = P.match(t, u_lo, u_hi, out=out).numel()
+        t.free()
+        return k
+
+    for _ in range(args.warmup):
+        full()
+    fwall, fper, _ = evented_steps(full, args.steps)
+    dy.free()
+    return {"metric": "dynamic DDM: time per move of 1% of one set (resident trees and result)",
+            "value": round(wall, 4), "unit": "ms", "ms_per_step": round(wall, 4),
+            "higher_is_better": False, "dtype": "f32",
+            "config": {"workload": "dynamic_d2_N1e6_alpha1_move1pct", "seed": 1,
+                       "moved_per_step": c, "K_after": int(K)},
+            "step_ms": step_stats(per), "full_rematch_ms": step_stats(fper),
+            "speedup_vs_full_rematch": round(fwall / wall, 2),
+            "roofline": None, "cpu_baseline": None}
+
+
 def bench_copy(args):
     """1 GiB device-to-device copy per step: the reference kernel whose
     FETCH_SIZE / WRITE_SIZE counters calibrate the traffic of the others."""
@@ -790,11 +845,14 @@ def main():
         rec = bench_sweep(args)
     elif args.workload == "sweep_fig7":
         rec = bench_fig7(args)
+    elif args.workload == "dynamic":
+        rec = bench_dynamic(args)
     else:
         rec = bench_single(args)
     head = {"metric": rec.pop("metric"), "value": rec.pop("value"), "unit": rec.pop("unit"),
             "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
-            "ms_per_step": rec.pop("ms_per_step"), "higher_is_better": True,
+            "ms_per_step": rec.pop("ms_per_step"),
+            "higher_is_better": rec.pop("higher_is_better", True),
             "scaling": "weak", "vs_baseline": None, "dtype": rec.pop("dtype"),
             "data": "synthetic", "config": rec.pop("config")}
     head.update(rec)

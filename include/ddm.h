@@ -380,6 +380,43 @@ ddm_status ddm_match_sets(const float* sub_lo, const float* sub_hi, uint32_t n,
 ddm_status ddm_tree_update(ddm_tree* t, const uint32_t* ids, const float* new_lo,
                            const float* new_hi, uint32_t count, void* stream, int* out_rebuilt);
 
+/* ---------------------------------------------------------------------------
+ * Dynamic DDM (the paper's dynamic scenario, Sec. IV and Sec. VI): both
+ * extent sets, an interval tree over each (T_S over the subscriptions, T_U
+ * over the updates) and the current result stay resident on the device;
+ * moving extents recomputes only the moved extents' pairs.
+ *
+ * ddm_dynamic_create -- copies S (n extents) and U (m extents), device,
+ *   [d][count] float32 dimension-major, builds both trees and matches
+ *   everything once.  Synchronizes the stream.  DDM_E_INVALID_INPUT for a
+ *   NaN/inf coordinate or lo > hi in either set.
+ * ddm_dynamic_move -- moves `count` extents of one set (set =
+ *   DDM_DYNAMIC_SUBSCRIPTIONS or DDM_DYNAMIC_UPDATES) to new extents:
+ *   ids device uint32 (distinct, below the set's size), new_lo/new_hi
+ *   device [d][count] float32 (column c is the new extent of ids[c]).  The
+ *   moved set's tree is refitted or rebuilt (as ddm_tree_update); a moved
+ *   update's column of M is recomputed with one query of T_S, a moved
+ *   subscription's row with one query of T_U; the resident result drops the
+ *   moved ids' old pairs and merges the new ones.  out_count (host, may be
+ *   NULL) receives the new K.  Synchronizes the stream a few times.  On
+ *   DDM_E_INVALID_INPUT (id out of range or repeated, invalid extent)
+ *   nothing changes.  K must stay below 2^32.
+ * ddm_dynamic_result -- the current pairs (device pointer, sorted
+ *   (update << 32) | subscription keys, valid until the next move or free)
+ *   and their number (host pointers).
+ * ddm_dynamic_free -- releases everything.                                  */
+typedef struct ddm_dynamic ddm_dynamic;
+#define DDM_DYNAMIC_SUBSCRIPTIONS 0u
+#define DDM_DYNAMIC_UPDATES 1u
+ddm_status ddm_dynamic_create(const float* sub_lo, const float* sub_hi, uint32_t n,
+                              const float* upd_lo, const float* upd_hi, uint32_t m, uint32_t d,
+                              void* stream, ddm_dynamic** out);
+ddm_status ddm_dynamic_move(ddm_dynamic* dy, uint32_t set, const uint32_t* ids,
+                            const float* new_lo, const float* new_hi, uint32_t count,
+                            void* stream, uint64_t* out_count);
+ddm_status ddm_dynamic_result(const ddm_dynamic* dy, const uint64_t** pairs, uint64_t* count);
+void ddm_dynamic_free(ddm_dynamic* dy);
+
 /* ddm_tree_check -- waits for the build to finish and reports whether the
  * subscription coordinates were valid (DDM_OK or DDM_E_INVALID_INPUT).      */
 ddm_status ddm_tree_check(const ddm_tree* t);

@@ -11,12 +11,12 @@ from __future__ import annotations
 import ctypes
 import json
 
-from ._native import (DDMError, DDM_E_CAPACITY, FEATURES, PREDICTOR_PARAMS, TRAVERSE, check,
-                      header_functions, lib, opts as _opts)
+from ._native import (DDMError, DDM_E_CAPACITY, DDM_E_INVALID_INPUT, FEATURES, PREDICTOR_PARAMS,
+                      TRAVERSE, check, header_functions, lib, opts as _opts)
 
 __all__ = ["build", "match", "count", "Tree", "DDMError", "prof_enable", "prof_read",
            "TRAVERSE", "header_functions", "Predictor", "features", "match_learned", "Batch",
-           "Server", "match_brute", "match_sbm",
+           "Server", "Dynamic", "match_brute", "match_sbm",
            "match_sets", "SWAP_AUTO", "SWAP_NEVER", "SWAP_ALWAYS"]
 
 
@@ -413,6 +413,77 @@ def match_learned(tree: Tree, u_lo, u_hi, predictor: Predictor, slot_budget: int
         raise DDMError(DDM_E_CAPACITY, "match_learned", f"K={k} > capacity {out.numel()}")
     check(lib().ddm_match_finish(pend, _ptr(out), out.numel()), "ddm_match_finish")
     return out[:k]
+
+
+class Dynamic:
+    """Both extent sets, a tree over each and the current result kept on the
+    device (ddm_dynamic_*): move(set, ids, new_lo, new_hi) moves extents of
+    one set and recomputes only their pairs; pairs() is the current sorted
+    result (int64 keys (update << 32) | subscription)."""
+
+    SUBSCRIPTIONS = 0
+    UPDATES = 1
+
+    def __init__(self, s_lo, s_hi, u_lo, u_hi, stream=None):
+        s_lo, s_hi = _coords(s_lo, s_hi, "Dynamic subscriptions")
+        u_lo, u_hi = _coords(u_lo, u_hi, "Dynamic updates")
+        if s_lo.shape[0] != u_lo.shape[0]:
+            raise ValueError("Dynamic: subscriptions and updates differ in d")
+        self.d, self.n, self.m = int(s_lo.shape[0]), int(s_lo.shape[1]), int(u_lo.shape[1])
+        h = ctypes.c_void_p()
+        check(lib().ddm_dynamic_create(_ptr(s_lo), _ptr(s_hi), self.n, _ptr(u_lo), _ptr(u_hi),
+                                       self.m, self.d, _stream_handle(stream), ctypes.byref(h)),
+              "ddm_dynamic_create")
+        self._h = h
+
+    @property
+    def handle(self):
+        if self._h is None:
+            raise RuntimeError("dynamic matcher already freed")
+        return self._h
+
+    def move(self, which: int, ids, new_lo, new_hi, stream=None) -> int:
+        """Moves extents ids (int32/uint32 GPU tensor, distinct) of set
+        `which` (SUBSCRIPTIONS or UPDATES) to new_lo/new_hi (float32 [d, c]
+        GPU tensors); returns the new pair count."""
+        torch = _torch()
+        new_lo, new_hi = _coords(new_lo, new_hi, "Dynamic.move")
+        if ids.dtype not in (torch.int32,) or not ids.is_cuda:
+            raise TypeError("Dynamic.move: ids must be an int32 CUDA tensor")
+        ids = ids.contiguous()
+        K = ctypes.c_uint64()
+        check(lib().ddm_dynamic_move(self.handle, int(which), _ptr(ids) if ids.numel() else None,
+                                     _ptr(new_lo), _ptr(new_hi), int(ids.numel()),
+                                     _stream_handle(stream), ctypes.byref(K)),
+              "ddm_dynamic_move")
+        return int(K.value)
+
+    def pairs(self):
+        """A copy of the current result (int64 CUDA tensor)."""
+        torch = _torch()
+        p, K = ctypes.c_void_p(), ctypes.c_uint64()
+        check(lib().ddm_dynamic_result(self.handle, ctypes.byref(p), ctypes.byref(K)),
+              "ddm_dynamic_result")
+        k = int(K.value)
+        if k == 0:
+            return torch.zeros(0, dtype=torch.int64, device="cuda")
+
+        class _Dev:  # a view of the library's device buffer
+            __cuda_array_interface__ = {"shape": (k,), "typestr": "<i8",
+                                        "data": (int(p.value), False), "version": 2}
+
+        return torch.as_tensor(_Dev(), device="cuda").clone()
+
+    def free(self):
+        if self._h is not None:
+            lib().ddm_dynamic_free(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
 
 
 class Batch:

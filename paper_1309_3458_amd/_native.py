@@ -19,6 +19,8 @@ DDM_E_INVALID_INPUT = -2
 DDM_E_CAPACITY = -3
 DDM_E_NOMEM = -4
 DDM_E_DEVICE = -5
+DDM_DYNAMIC_SUBSCRIPTIONS = 0
+DDM_DYNAMIC_UPDATES = 1
 DDM_NOALLOC_SCRATCH_MB = 64  # static scratch of ddm_match_noalloc (ddm.h)
 
 TRAVERSE = {"auto": 0, "lane": 1, "tile": 2}
@@ -126,6 +128,10 @@ def lib():
     _sig(L, "ddm_match_sets", i32, vp, vp, u32, vp, vp, u32, u32, i32, vp, u64, P(u64),
          P(ctypes.c_int), vp)
     _sig(L, "ddm_tree_check", i32, vp)
+    _sig(L, "ddm_dynamic_create", i32, vp, vp, u32, vp, vp, u32, u32, vp, P(vp))
+    _sig(L, "ddm_dynamic_move", i32, vp, u32, vp, vp, vp, u32, vp, P(u64))
+    _sig(L, "ddm_dynamic_result", i32, vp, P(vp), P(u64))
+    _sig(L, "ddm_dynamic_free", None, vp)
     _sig(L, "ddm_tree_update", i32, vp, vp, vp, vp, u32, vp, P(i32))
     _sig(L, "ddm_tree_info", i32, vp, P(u32), P(u32), P(u32))
     _sig(L, "ddm_tree_export", i32, vp, u32, vp, vp, vp, vp)
