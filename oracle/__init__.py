@@ -43,6 +43,9 @@ def lib():
         L.oracle_itm_1d_visits.argtypes = [fp, fp, ctypes.c_uint32, fp, fp,
                                            ctypes.c_uint32, u64p, u32p, u32p]
         L.oracle_itm_1d_visits.restype = ctypes.c_int
+        L.oracle_pst_1d.argtypes = [fp, fp, ctypes.c_uint32, fp, fp, ctypes.c_uint32,
+                                    u64pp, u64p, u64p, u32p]
+        L.oracle_pst_1d.restype = ctypes.c_int
         L.oracle_free.argtypes = [ctypes.c_void_p]
         L.oracle_max_threads.restype = ctypes.c_int
         _lib = L
@@ -129,6 +132,22 @@ def itm_1d_visits(s_lo, s_hi, u_lo, u_hi):
     if rc != 0:
         raise OracleError(rc)
     return visits, hits, int(H.value)
+
+
+def pst_1d(s_lo, s_hi, u_lo, u_hi):
+    """Sorted keys from the priority search tree (d = 1), plus per-query
+    nodes visited and hits."""
+    d, n, m = _dims(s_lo, u_lo)
+    assert d == 1
+    a, pa = _f32(s_lo); b, pb = _f32(s_hi); c, pc = _f32(u_lo); e, pe = _f32(u_hi)
+    keys = ctypes.POINTER(ctypes.c_uint64)()
+    cnt = ctypes.c_uint64(0)
+    visits = np.zeros(m, dtype=np.uint64)
+    hits = np.zeros(m, dtype=np.uint32)
+    rc = lib().oracle_pst_1d(pa, pb, n, pc, pe, m, ctypes.byref(keys), ctypes.byref(cnt),
+                             visits.ctypes.data_as(ctypes.POINTER(ctypes.c_uint64)),
+                             hits.ctypes.data_as(ctypes.POINTER(ctypes.c_uint32)))
+    return _take_keys(rc, keys, cnt), visits, hits
 
 
 def max_threads() -> int:

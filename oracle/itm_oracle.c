@@ -44,6 +44,11 @@
  *                     coordinates lower endpoints come first (closed reading).
  *   oracle_itm_1d_visits  Algorithm 4 per query with a visit counter, for the
  *                     O(min{n, (k+1) log n}) cost bound of Sec. IV.
+ *   oracle_pst_1d     the alternative Sec. IV names: a priority search tree
+ *                     (McCreight) over the points (lower, upper), queried
+ *                     with lower <= q.upper and upper >= q.lower (closed), in
+ *                     O(log n + k); returns the pairs, or per query the
+ *                     nodes visited and the hits, to compare with Algorithm 4.
  */
 #include <stdint.h>
 #include <stdlib.h>
@@ -436,6 +441,101 @@ int oracle_itm_1d_visits(const float* s_lo, const float* s_hi, uint32_t n,
     }
     free(lst.v);
     itree_free(&t);
+    return OR_OK;
+}
+
+/* ------------------------------------------------------------------ */
+/* Priority search tree (Sec. IV names it as a drop-in alternative)    */
+/* ------------------------------------------------------------------ */
+/* Every node holds the point of largest upper bound among the points of its
+ * subtree; the other points, in lower-bound order, are split at the median
+ * into the two subtrees (left: smaller lower bounds).  min_lo is the smallest
+ * lower bound in the node's subtree (the node's point included). */
+typedef struct { seg_t pt; float min_lo; int32_t left, right; } pnode_t;
+typedef struct { pnode_t* nodes; int32_t count; int32_t root; } pst_t;
+
+/* Subtree over the lower-bound-sorted points seg[lo, hi). */
+static int32_t pst_build_rec(pst_t* t, seg_t* seg, int32_t lo, int32_t hi) {
+    if (lo >= hi) return -1;
+    int32_t best = lo;
+    for (int32_t i = lo + 1; i < hi; ++i) {
+        if (seg[i].hi > seg[best].hi) best = i;  /* first of equal uppers */
+    }
+    seg_t top = seg[best];
+    const float min_lo = seg[lo].lo;
+    /* remove it, keeping the others in lower-bound order */
+    memmove(&seg[lo + 1], &seg[lo], (size_t)(best - lo) * sizeof(seg_t));
+    int32_t v = t->count++;
+    t->nodes[v].pt = top;
+    t->nodes[v].min_lo = min_lo;
+    int32_t rest = lo + 1, mid = rest + (hi - rest) / 2;
+    int32_t l = pst_build_rec(t, seg, rest, mid);
+    int32_t r = pst_build_rec(t, seg, mid, hi);
+    t->nodes[v].left = l;
+    t->nodes[v].right = r;
+    return v;
+}
+
+static int pst_create(pst_t* t, const float* lo, const float* hi, uint32_t n) {
+    t->count = 0;
+    t->root = -1;
+    t->nodes = NULL;
+    if (n == 0) return OR_OK;
+    seg_t* s = (seg_t*)malloc((size_t)n * sizeof(seg_t));
+    t->nodes = (pnode_t*)malloc((size_t)n * sizeof(pnode_t));
+    if (!s || !t->nodes) { free(s); free(t->nodes); t->nodes = NULL; return OR_E_NOMEM; }
+    for (uint32_t i = 0; i < n; ++i) { s[i].lo = lo[i]; s[i].hi = hi[i]; s[i].id = i; }
+    qsort(s, n, sizeof(seg_t), cmp_seg);
+    t->root = pst_build_rec(t, s, 0, (int32_t)n);
+    free(s);
+    return OR_OK;
+}
+
+/* Points with lower <= qh and upper >= ql (the closed segments meeting q):
+ * a subtree is left as soon as its node's upper is below ql (no point below
+ * it has a larger upper) or its smallest lower bound is above qh (no point
+ * in it starts early enough); otherwise the node's point is reported if it
+ * starts early enough, and both subtrees are searched. */
+static void pst_query(const pst_t* t, int32_t v, float ql, float qh, vec32* out,
+                      uint64_t* visits) {
+    if (v < 0) return;
+    const pnode_t* x = &t->nodes[v];
+    if (visits) ++*visits;
+    if (x->pt.hi < ql || x->min_lo > qh) return;
+    if (x->pt.lo <= qh) v32_push(out, x->pt.id);
+    pst_query(t, x->left, ql, qh, out, visits);
+    pst_query(t, x->right, ql, qh, out, visits);
+}
+
+int oracle_pst_1d(const float* s_lo, const float* s_hi, uint32_t n,
+                  const float* u_lo, const float* u_hi, uint32_t m,
+                  uint64_t** out_keys, uint64_t* out_count,
+                  uint64_t* visits, uint32_t* hits) {
+    if (out_keys) *out_keys = NULL;
+    if (out_count) *out_count = 0;
+    int rc = check_args(s_lo, s_hi, n, u_lo, u_hi, m, 1);
+    if (rc != OR_OK) return rc;
+    pst_t t;
+    rc = pst_create(&t, s_lo, s_hi, n);
+    if (rc != OR_OK) return rc;
+    vec32 lst = {0};
+    vec64 keys = {0};
+    for (uint32_t j = 0; j < m; ++j) {
+        uint64_t v = 0;
+        lst.n = 0;
+        pst_query(&t, t.root, u_lo[j], u_hi[j], &lst, &v);
+        if (visits) visits[j] = v;
+        if (hits) hits[j] = (uint32_t)lst.n;
+        if (out_keys) {
+            qsort(lst.v, lst.n, sizeof(uint32_t), cmp_u32);
+            for (size_t a = 0; a < lst.n; ++a) v64_push(&keys, ((uint64_t)j << 32) | lst.v[a]);
+        }
+    }
+    int oom = lst.oom || keys.oom;
+    free(lst.v);
+    free(t.nodes);
+    if (oom) { free(keys.v); return OR_E_NOMEM; }
+    if (out_keys) { *out_keys = keys.v; *out_count = keys.n; } else { free(keys.v); }
     return OR_OK;
 }
 

@@ -278,3 +278,30 @@ def test_sort_based_matching_touching_pin():
     u_hi = np.array([6, 2], np.float32)
     got = oracle.sbm_1d(s_lo, s_hi, u_lo, u_hi).tolist()
     assert got == [1, 2, (1 << 32) | 0, (1 << 32) | 1]
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_priority_search_tree_equals_definition(seed):
+    """The priority search tree Sec. IV names as a drop-in alternative gives
+    the definition's pairs on tie-heavy grids (touching ends, points,
+    duplicates, signed zeros) and on variable lengths."""
+    inst = W.tiny_adversarial(800 + seed, 300 + 37 * seed, 250, 1)
+    want = definition_pairs(inst.s_lo, inst.s_hi, inst.u_lo, inst.u_hi)
+    keys, visits, hits = oracle.pst_1d(inst.s_lo[0], inst.s_hi[0], inst.u_lo[0], inst.u_hi[0])
+    np.testing.assert_array_equal(keys, want)
+    np.testing.assert_array_equal(hits, oracle.counts_per_update(want, inst.m))
+    var = W.random_lengths(810 + seed, 2000, 1500, 1, max_len=80.0)
+    keys, _, _ = oracle.pst_1d(var.s_lo[0], var.s_hi[0], var.u_lo[0], var.u_hi[0])
+    np.testing.assert_array_equal(keys, definition_pairs(var.s_lo, var.s_hi, var.u_lo, var.u_hi))
+
+
+def test_priority_search_tree_cost_bound():
+    """O(log n + k) per query: a node whose subtree search goes on either
+    reports a hit (at most k) or straddles q.upper (its subtree starts at or
+    before q.upper, its own point after it: at most one per level, H levels),
+    and every visited node is the root or a child of such a node, so
+    visits <= 2 (k + H) + 1 (H = ceil(log2(n + 1)))."""
+    inst = W.random_lengths(41, 1 << 14, 3000, 1, L=1e5, max_len=300.0)
+    _, visits, hits = oracle.pst_1d(inst.s_lo[0], inst.s_hi[0], inst.u_lo[0], inst.u_hi[0])
+    H = int(np.ceil(np.log2(inst.n + 1)))
+    assert (visits.astype(np.int64) <= 2 * (hits.astype(np.int64) + H) + 1).all()
