@@ -12,6 +12,8 @@ step; the match alone on a resident tree is reported beside it.
 Workloads:
   d2_uniform (default)  d=2, 500,000 subscriptions + 500,000 updates, square
                         side 1000 on [0, 1e6)^2 (alpha = 1), seed 1
+  d3_uniform            d=3, 500,000 + 500,000 cubes, side 1e6*(1/1e6)^(1/3)
+                        (alpha = 1), seed 1
   d2_hotspot            d=2, 500,000 + 500,000 boxes around 16 Gaussian
                         hotspots, log-normal sides (median 1e4), seed 2
   batch256              256 independent instances (N log-uniform in
@@ -72,7 +74,7 @@ def parse():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--traversal", default="auto", choices=["auto", "lane", "tile"])
     ap.add_argument("--workload", default="d2_uniform",
-                    choices=["d2_uniform", "d2_hotspot", "batch256", "serve", "hbm_copy",
+                    choices=["d2_uniform", "d2_hotspot", "d3_uniform", "batch256", "serve", "hbm_copy",
                              "sweep_1d", "sweep_fig7", "dynamic"])
     ap.add_argument("--duration", type=float, default=60.0,
                     help="serve: seconds of Poisson arrivals (the schedule is cut, not rescaled)")
@@ -343,6 +345,9 @@ def bench_single(args):
     if args.workload == "d2_uniform":
         inst = W.uniform_2d_1m(1)
         wname, seed = "d2_N1e6_alpha1_uniform", 1
+    elif args.workload == "d3_uniform":
+        inst = W.uniform_instance(1, 500_000, 500_000, 3, W.side_for_alpha(1.0, 1_000_000, 3))
+        wname, seed = "d3_N1e6_alpha1_uniform", 1
     else:
         inst = W.hotspot_2d(2)
         wname, seed = "d2_N1e6_hotspots_alpha100", 2

@@ -647,19 +647,36 @@ __device__ __forceinline__ void bitonic_regs(uint64_t (&v)[N]) {
 // The traversal is latency-bound, so the register budget is set for eight
 // wavefronts per SIMD (the d = 2 stash form then keeps two values in
 // scratch, and measured 5% faster than at seven wavefronts).
+#ifndef DDM_TILE_COUNT_WAVES
+#define DDM_TILE_COUNT_WAVES 7
+#endif
 constexpr uint32_t kXcds = 8;     // accelerator dies (each with its own L2) of the device
 constexpr uint32_t kXcdRun = 32;  // consecutive workgroups of tiles given to one die
 
+// The count pass (d >= 2) runs the transposed flush beside the untransposed
+// one; with both, seven wavefronts per SIMD leave it room without spilling.
+template <int D, bool FILL>
+constexpr int tile_waves_per_eu() {
+  return (!FILL && D >= 2) ? DDM_TILE_COUNT_WAVES : 8;
+}
+
 template <int D, bool FILL, bool STASH = false>
-__global__ __launch_bounds__(kTileWaves * kWave) __attribute__((amdgpu_waves_per_eu(8)))
+__global__ __launch_bounds__(kTileWaves * kWave)
+__attribute__((amdgpu_waves_per_eu(tile_waves_per_eu<D, FILL>())))
 void tile_bucket_kernel(
     TreeDev T, const float* __restrict__ ulo, const float* __restrict__ uhi, uint32_t m,
     UpdSet US, SegOut O) {
   constexpr int R = 2 * D;
   constexpr int RV = (R + 3) / 4;
+  // the count pass (d >= 2) takes the transposed flush
+  constexpr bool XP = !FILL && D >= 2;
+  constexpr int XW = XP ? kWave : 1;
   __shared__ float s_cand[kTileWaves][R * kRing];
   __shared__ uint32_t s_cid[kTileWaves][kRing];
   __shared__ float4 s_q[kTileWaves][kWave * RV];
+  __shared__ float s_lo1[kTileWaves][XW];
+  __shared__ uint32_t s_xcnt[kTileWaves][XW];
+  __shared__ uint32_t s_xj[kTileWaves][XW];
   const uint32_t wave = threadIdx.x / kWave;
   const uint32_t lane = lane_id();
   const bool list = US.tstart != nullptr;
@@ -694,8 +711,9 @@ void tile_bucket_kernel(
       qbeg = start + lt * 64u;
       nq = min(64u, end - qbeg);
     }
-    tile_body<D, FILL, STASH>(T, ulo, uhi, m, US.perm, 0u, b / kBucketsPerDim, qbeg, nq, O,
-                              s_cand[wave], s_cid[wave], s_q[wave], lane, item, US.pb);
+    tile_body<D, FILL, STASH, XP>(T, ulo, uhi, m, US.perm, 0u, b / kBucketsPerDim, qbeg, nq, O,
+                                  s_cand[wave], s_cid[wave], s_q[wave], lane, item, US.pb,
+                                  XpLds{s_lo1[wave], s_xcnt[wave], s_xj[wave]});
   }
 }
 

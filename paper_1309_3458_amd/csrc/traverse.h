@@ -215,7 +215,25 @@ __device__ __forceinline__ uint32_t wave_max_u32(uint32_t v) {
 // qoff is subtracted to index the instance's coordinates), probe dimension k
 // of tree set T.  LDS per wavefront: s_cand [2D][kRing] floats, s_cid
 // [kRing], s_q [64][RV] float4.
-template <int D, bool FILL, bool STASH = false>
+// XP (count pass only, d >= 2, one instance): the flush is transposed.  The
+// tile's updates are sorted once by their lower bound in record slot 1 (the
+// first dimension after the probe dimension) into LDS (s_lo1, s_q, s_xj);
+// each candidate lane binary-searches the window of updates whose slot-1
+// extent can meet its own (lower bound in [c.lo1 - longest update, c.hi1],
+// bounds rounded outwards, so the window is a superset) and tests only those
+// exactly, in every dimension.  A cell of the tile spans a far wider range
+// in the other dimensions than one update, so a window holds a few updates
+// where the untransposed flush tests all 64.  Hits are counted per update
+// in LDS (s_xcnt); the atomic's result is the hit's rank for the stash.
+constexpr uint32_t kXpWindow = 8;  // widest window the transposed flush takes
+
+struct XpLds {
+  float* lo1;     // [64] sorted slot-1 lower bounds (+inf past nq)
+  uint32_t* cnt;  // [64] hits per sorted update
+  uint32_t* j;    // [64] update index of each sorted update
+};
+
+template <int D, bool FILL, bool STASH = false, bool XP = false>
 __device__ __forceinline__ void tile_body(const TreeDev& T, const float* __restrict__ ulo,
                                           const float* __restrict__ uhi, uint32_t m,
                                           const uint32_t* __restrict__ perm, uint32_t qoff,
@@ -223,9 +241,11 @@ __device__ __forceinline__ void tile_body(const TreeDev& T, const float* __restr
                                           float* __restrict__ s_cand, uint32_t* __restrict__ s_cid,
                                           float4* __restrict__ s_q, uint32_t lane,
                                           uint32_t tile_id = 0,
-                                          const uint32_t* __restrict__ pb = nullptr) {
+                                          const uint32_t* __restrict__ pb = nullptr,
+                                          XpLds xl = XpLds{}) {
   constexpr int R = 2 * D;
   constexpr int RV = (R + 3) / 4;
+  static_assert(!XP || (!FILL && D >= 2), "the transposed flush counts, for d >= 2");
   const bool qv = lane < nq;
   const uint32_t gj = qv ? perm[qbeg + lane] : 0u;  // global update index
   const uint32_t j = gj - qoff;                      // index within the instance
@@ -238,6 +258,46 @@ __device__ __forceinline__ void tile_body(const TreeDev& T, const float* __restr
       ql[s] = INFINITY;
       qh[s] = -INFINITY;
     }
+  }
+  float tmax1 = 0.f;  // XP: longest slot-1 extent of the tile, rounded up
+  uint32_t jx = j;    // the update this lane stands for (XP: in sorted order)
+  if constexpr (XP) {
+    // bitonic sort of the lanes' (slot-1 lower bound, lane) pairs; lanes
+    // past nq sort last
+    float key = qv ? ql[1] : INFINITY;
+    uint32_t src = lane;
+#pragma unroll
+    for (uint32_t kk = 2; kk <= (uint32_t)kWave; kk <<= 1) {
+#pragma unroll
+      for (uint32_t jj = kk >> 1; jj > 0; jj >>= 1) {
+        const float ok = __shfl_xor(key, (int)jj, kWave);
+        const uint32_t os = (uint32_t)__shfl_xor((int)src, (int)jj, kWave);
+        const bool up = (lane & kk) == 0, lower = (lane & jj) == 0;
+        const bool other_less = ok < key || (ok == key && os < src);
+        if (lower == up ? other_less : !other_less) {
+          key = ok;
+          src = os;
+        }
+      }
+    }
+    // this lane now holds the rank-`lane` update: take its bounds
+    float sl[D], sh[D];
+#pragma unroll
+    for (int s = 0; s < D; ++s) {
+      sl[s] = __shfl(ql[s], (int)src, kWave);
+      sh[s] = __shfl(qh[s], (int)src, kWave);
+    }
+    const uint32_t sj = (uint32_t)__shfl((int)j, (int)src, kWave);
+#pragma unroll
+    for (int s = 0; s < D; ++s) {
+      ql[s] = sl[s];
+      qh[s] = sh[s];
+    }
+    xl.lo1[lane] = qv ? sl[1] : INFINITY;
+    xl.cnt[lane] = 0;
+    xl.j[lane] = sj;
+    jx = sj;
+    tmax1 = nextafterf(wave_max(qv ? sh[1] - sl[1] : 0.f), INFINITY);
   }
   {
     float qr[4 * RV];
@@ -288,7 +348,7 @@ __device__ __forceinline__ void tile_body(const TreeDev& T, const float* __restr
   if (FILL && qv) seg_bounds(O, gj, &mybase, &myend);
   const uint64_t mystart = mybase;
   uint64_t* __restrict__ out = O.out;
-  const uint64_t jhi = (uint64_t)j << 32;
+  const uint64_t jhi = (uint64_t)jx << 32;
   const uint32_t nq4 = (nq + 3u) & ~3u;
   wave_sync();
 
@@ -303,7 +363,66 @@ __device__ __forceinline__ void tile_body(const TreeDev& T, const float* __restr
   bool sok = STASH;
   uint64_t myhm = 0;  // this lane's update: hits among the flushed candidates
 
-  auto flush = [&](uint32_t c) {
+  // stash: room for `tot` more entries from this wave, in the current chunk
+  // and (if needed) nnew more chunks starting at `first` (static ones of the
+  // tile, else counted ones from the slices); false once the stash is full
+  auto stash_room = [&](uint32_t tot, uint32_t* room_out, uint32_t* first_out,
+                        uint32_t* nnew_out) {
+    const uint32_t room = kStashChunk - sfill;
+    uint32_t first = 0, nnew = 0;
+    if (room < tot) {
+      nnew = (tot - room + kStashChunk - 1) / kStashChunk;
+      if (sch + nnew <= slast) {
+        first = sch + 1;
+      } else {
+        // the tile's slice first, then the following ones; the part of a
+        // slice too short for the request is marked empty
+        const uint32_t take = max(nnew, kStashGrab);
+        if (sch < slast && lane < slast - sch) O.sused[sch + 1 + lane] = 0;
+        bool got = false;
+        for (uint32_t a = 0, sl = tile_id % kStashSlices; a < kStashSlices && !got;
+             ++a, sl = (sl + 1) % kStashSlices) {
+          const uint32_t send = O.sfirst + (sl + 1) * O.sslice;
+          uint32_t f = 0;
+          if (lane == 0) {
+            // a slice already used up is passed over without an atomic
+            f = __hip_atomic_load(O.snext + sl, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            if (f < send) f = atomicAdd(O.snext + sl, take);
+          }
+          first = uniform_u32(f);
+          if (first < send && take <= send - first) {
+            got = true;
+          } else if (first < send && lane < send - first) {
+            O.sused[first + lane] = 0;
+          }
+        }
+        if (!got) {
+          sok = false;
+          if (lane == 0) atomicOr(O.snext + kStashSlices, 1u);
+        } else {
+          if (O.sowner && lane < take) O.sowner[first + lane] = tile_id;
+          slast = first + take - 1;
+        }
+      }
+    }
+    *room_out = room;
+    *first_out = first;
+    *nnew_out = nnew;
+    return sok;
+  };
+  // the stash has taken `tot` entries (room, first, nnew as stash_room gave)
+  auto stash_advance = [&](uint32_t tot, uint32_t room, uint32_t first, uint32_t nnew) {
+    if (nnew) {
+      if (lane == 0) O.sused[sch] = kStashChunk;
+      if (lane + 1 < nnew) O.sused[first + lane] = kStashChunk;
+      sch = first + nnew - 1;
+      sfill = tot - room - (nnew - 1) * kStashChunk;
+    } else {
+      sfill += tot;
+    }
+  };
+
+  auto flush_classic = [&](uint32_t c) {
     wave_sync();
     const uint64_t cvm = (c >= (uint32_t)kWave) ? ~0ull : ((1ull << c) - 1ull);
     const uint32_t slot = (head + lane) & (kRing - 1);
@@ -346,7 +465,7 @@ __device__ __forceinline__ void tile_body(const TreeDev& T, const float* __restr
             const uint64_t dst = b + mask_rank(hm[u]);
             if (((hm[u] >> lane) & 1ull) && dst < e) out[dst] = jq | sid;
             if (lane == qq) mybase += pc;
-          } else if constexpr (STASH) {
+          } else if constexpr (STASH || XP) {
             if (lane == qq) myhm = hm[u];
           } else {
             if (lane == qq) mycnt += pc;
@@ -410,7 +529,7 @@ __device__ __forceinline__ void tile_body(const TreeDev& T, const float* __restr
           }
           if (sok) {
             uint64_t hv = myhm;
-            uint32_t v = incl - pcl, r = mycnt;
+            uint32_t v = incl - pcl, r = XP ? (lane < nq ? xl.cnt[lane] : 0u) : mycnt;
             while (hv) {
               const uint32_t ci = (uint32_t)__builtin_ctzll(hv);
               hv &= hv - 1;
@@ -431,12 +550,98 @@ __device__ __forceinline__ void tile_body(const TreeDev& T, const float* __restr
             }
           }
         }
-        mycnt += pcl;
+        if constexpr (XP) {
+          if (lane < nq) xl.cnt[lane] += pcl;
+        } else {
+          mycnt += pcl;
+        }
         myhm = 0;
+      }
+    } else if constexpr (XP) {
+      if (lane < nq) xl.cnt[lane] += (uint32_t)__popcll(myhm);
+      myhm = 0;
+    }
+    head += c;
+    wave_sync();
+  };
+  auto flush_xp = [&](uint32_t c) {
+    wave_sync();
+    const bool in = lane < c;
+    const uint32_t slot = (head + lane) & (kRing - 1);
+    float v[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) v[r] = s_cand[r * kRing + slot];
+    const uint32_t sid = s_cid[slot];
+    // window [a, b) of the sorted updates that may meet the candidate in
+    // slot 1: lower bound >= c.lo1 - tmax1 (rounded down) and <= c.hi1
+    const float klo = nextafterf(v[2] - tmax1, -INFINITY), khi = v[3];
+    uint32_t a = 0, b = 0;
+#pragma unroll
+    for (uint32_t step = kWave; step > 0; step >>= 1) {
+      if (a + step <= (uint32_t)kWave && xl.lo1[a + step - 1] < klo) a += step;
+      if (b + step <= (uint32_t)kWave && xl.lo1[b + step - 1] <= khi) b += step;
+    }
+    if (!in) b = a;
+    // dense cells (wide windows): the untransposed loop over all updates is
+    // cheaper; it keeps its counts and ranks in the same LDS counters
+    if (wave_max_u32(b - a) > kXpWindow) {
+      flush_classic(c);
+      return;
+    }
+    auto meets = [&](uint32_t u) {
+      float q[4 * RV];
+#pragma unroll
+      for (int vv = 0; vv < RV; ++vv) {
+        const float4 t4 = s_q[u * RV + vv];
+        q[4 * vv] = t4.x;
+        q[4 * vv + 1] = t4.y;
+        q[4 * vv + 2] = t4.z;
+        q[4 * vv + 3] = t4.w;
+      }
+      bool ok = true;
+#pragma unroll
+      for (int s2 = 0; s2 < D; ++s2)
+        ok = ok && (v[2 * s2] <= q[2 * s2 + 1]) && (q[2 * s2] <= v[2 * s2 + 1]);
+      return ok;
+    };
+    if constexpr (!STASH) {
+      for (uint32_t u = a; u < b; ++u)
+        if (meets(u)) atomicAdd(&xl.cnt[u], 1u);
+    } else {
+      uint32_t nh = 0;
+      for (uint32_t u = a; u < b; ++u) nh += meets(u) ? 1u : 0u;
+      if (ballot(nh != 0) != 0) {
+        uint32_t incl = nh;
+#pragma unroll
+        for (int o = 1; o < kWave; o <<= 1) {
+          const uint32_t t = (uint32_t)__shfl_up((int)incl, o, kWave);
+          if (lane >= (uint32_t)o) incl += t;
+        }
+        const uint32_t tot = (uint32_t)__builtin_amdgcn_readlane((int)incl, kWave - 1);
+        uint32_t room = 0, first = 0, nnew = 0;
+        const bool keep = sok && stash_room(tot, &room, &first, &nnew);
+        uint32_t vpos = incl - nh;
+        for (uint32_t u = a; u < b; ++u) {
+          if (!meets(u)) continue;
+          const uint32_t r = atomicAdd(&xl.cnt[u], 1u);
+          if (keep) {
+            const uint64_t e = vpos < room ? (uint64_t)sch * kStashChunk + sfill + vpos
+                                           : (uint64_t)first * kStashChunk + (vpos - room);
+            O.skey[e] = ((uint64_t)xl.j[u] << 32) | sid;
+            O.srank[e] = r;
+          }
+          ++vpos;
+        }
+        if (keep) stash_advance(tot, room, first, nnew);
       }
     }
     head += c;
     wave_sync();
+  };
+
+  auto flush = [&](uint32_t c) {
+    if constexpr (XP) flush_xp(c);
+    else flush_classic(c);
   };
 
   // one block of 64 candidate positions: test against the tile's box in
@@ -496,7 +701,10 @@ __device__ __forceinline__ void tile_body(const TreeDev& T, const float* __restr
     if (lane == 0) O.sused[sch] = sfill;
     if (sch < slast && lane < slast - sch) O.sused[sch + 1 + lane] = 0;
   }
-  if (qv) {
+  if constexpr (XP) {
+    wave_sync();
+    if (qv) O.cnt[xl.j[lane] + qoff] = xl.cnt[lane];
+  } else if (qv) {
     if (!FILL) O.cnt[gj] = mycnt;
     else if (O.cnt) O.cnt[gj] = (uint32_t)(mybase - mystart);
   }
