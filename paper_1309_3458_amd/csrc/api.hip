@@ -83,7 +83,11 @@ static size_t round_bytes(size_t b) {
   return (b + step - 1) & ~(step - 1);
 }
 
-constexpr size_t kCacheLimit = size_t(16) << 30;
+// about a fifth of one GPU's 288 GB of HBM: the slot arena of a large
+// learned match (tens of GB) stays cached from one step to the next instead
+// of going back to the driver and being mapped again (seconds at that size);
+// an allocation that fails gives the cache back and retries
+constexpr size_t kCacheLimit = size_t(64) << 30;
 static size_t g_cached = 0;  // bytes in g_free
 
 // Frees cached blocks, largest first, whose last use has completed, until

@@ -1049,6 +1049,380 @@ __global__ __launch_bounds__(kBigThreads) void segsort_big_kernel(
   }
 }
 
+// One workgroup per listed segment (more than kSegMid keys) when every id
+// is below 2^20.  The ids of one update are distinct, so each is marked in
+// an LDS bitmap of ceil(n/32) words, and an id's place in the sorted
+// segment is the number of marked ids below it: the marks of the uint4
+// entries before its own (a scan of the entries' counts) plus those below
+// it in its entry.  Entry r*kBmThreads + t is counted by thread t
+// (conflict-free 16-byte LDS reads); the entries' exclusive counts within
+// their wave's block are kept as 16-bit values, the blocks' starts come
+// from a scan of the wave totals that every wave does itself.  Each thread
+// then ranks the ids it loaded (held in registers), and once every id is
+// ranked the bitmap's LDS becomes the staging array: each id is written at
+// its place there (as id + 1, 0 meaning empty), the rest of the array is
+// cleared, and consecutive threads write the staged keys out (coalesced)
+// and clear what they read.  Ids past the first kBmPre * kBmThreads of a
+// segment are loaded again when ranked and written straight to their
+// place; a segment longer than the array is staged in array-sized chunks.
+// Wave scans use DPP row shifts and row broadcasts.
+//
+// Each workgroup takes every G-th listed segment, and its loads run ahead
+// (vector loads through buffer resources, so that the LDS waits of the work
+// in between force no wait for them): a segment's first kBmPre * kBmThreads
+// ids are loaded once the segment two before it is written, so that they
+// arrive while the one in between is sorted (two register buffers, used in
+// turn); its offsets are loaded three segments ahead, its list entry four.
+__device__ __forceinline__ uint32_t popc4(uint4 q) {
+  return __popc(q.x) + __popc(q.y) + __popc(q.z) + __popc(q.w);
+}
+
+// inclusive sum of v over lanes 0..lane of the wavefront: row shifts by 1,
+// 2, 4 and 8 (lanes before the row's start add 0) give each 16-lane row
+// its own prefix; broadcasting lane 15 into row 1 and lane 47 into row 3,
+// then lane 31 into rows 2 and 3, carries the row totals forward
+__device__ __forceinline__ uint32_t wave_scan_dpp(uint32_t v) {
+  v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x111, 0xf, 0xf, true);
+  v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x112, 0xf, 0xf, true);
+  v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x114, 0xf, 0xf, true);
+  v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x118, 0xf, 0xf, true);
+  v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x142, 0xa, 0xf, false);
+  v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x143, 0xc, 0xf, false);
+  return v;
+}
+
+// largest v over the wavefront (the same row shifts and broadcasts, with
+// max; lanes before a row's start contribute 0), read from the last lane
+__device__ __forceinline__ uint32_t wave_max_dpp(uint32_t v) {
+  v = max(v, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x111, 0xf, 0xf, true));
+  v = max(v, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x112, 0xf, 0xf, true));
+  v = max(v, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x114, 0xf, 0xf, true));
+  v = max(v, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x118, 0xf, 0xf, true));
+  v = max(v, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x142, 0xa, 0xf, false));
+  v = max(v, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x143, 0xc, 0xf, false));
+  return (uint32_t)__builtin_amdgcn_readlane((int)v, kWave - 1);
+}
+
+// word 3 of a raw buffer resource on gfx9 parts (32-bit data format)
+constexpr int kBufferFlags = 0x00020000;
+typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
+
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t buf_rsrc(const void* p, uint32_t bytes) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(p), (short)0, (int)bytes,
+                                           kBufferFlags);
+}
+__device__ __forceinline__ uint64_t buf_u64(const uint64_t* p) {
+  const u32x2 v = __builtin_amdgcn_raw_buffer_load_b64(buf_rsrc(p, 8), 0, 0, 0);
+  return (uint64_t)v.x | ((uint64_t)v.y << 32);
+}
+__device__ __forceinline__ uint32_t buf_u32(const uint32_t* p) {
+  return (uint32_t)__builtin_amdgcn_raw_buffer_load_b32(buf_rsrc(p, 4), 0, 0, 0);
+}
+__device__ __forceinline__ uint32_t uniform_v(uint32_t v) {
+  return (uint32_t)__builtin_amdgcn_readfirstlane((int)v);
+}
+__device__ __forceinline__ uint64_t uniform_v64(uint64_t v) {
+  return ((uint64_t)uniform_v((uint32_t)(v >> 32)) << 32) | uniform_v((uint32_t)v);
+}
+
+// a listed segment's offsets (off[j], and the low word of off[j + 1]: the
+// length is below 2^32), and in the single-pass form its slot base, the low
+// word of its end (base + capacity, or the next base without capacities)
+// and its hit count, as loaded
+struct BmMeta {
+  uint64_t b, sb;
+  uint32_t elo, selo, cnt;
+};
+// where a segment is written (out + b, len keys) and read from
+struct BmSeg {
+  uint64_t b;
+  uint32_t len;
+  const uint64_t* src;
+};
+
+#ifndef DDM_BM_THREADS
+#define DDM_BM_THREADS 1024
+#endif
+#ifndef DDM_BM_WAVES
+#define DDM_BM_WAVES 8
+#endif
+constexpr int kBmThreads = DDM_BM_THREADS;
+constexpr uint32_t kBmPre = 8192 / kBmThreads;  // ids per thread loaded ahead, per segment
+constexpr uint32_t kBmLong = 1024;               // staged positions per chunk, long segments
+// most uint4 entries per thread: ids below 2^19 (narrow), below 2^20
+constexpr uint32_t kBmRNarrow = (kMaxBitWords / 2) / 4 / kBmThreads;
+constexpr uint32_t kBmRWide = kMaxBitWords / 4 / kBmThreads;
+
+// LDS of the bitmap sort: the bitmap (uint4 entries), a 16-bit start per
+// entry (padded to 8 bytes), the long-segment staging array and its spare
+// slot (padded to 16 bytes)
+constexpr size_t bitmap_lds_bytes(uint32_t words) {
+  return (size_t)((words + 3) / 4) * sizeof(uint4) +
+         (size_t)(((words + 3) / 4 + 3) / 4) * 4 * sizeof(uint16_t) +
+         (size_t)(kBmLong + 4) * sizeof(uint32_t);
+}
+
+// MAXR: most uint4 entries per thread (kBmRNarrow or kBmRWide); SLOTS:
+// segments may be read from the slots of the single-pass form
+template <uint32_t MAXR, bool SLOTS>
+__global__ __launch_bounds__(kBmThreads) __attribute__((amdgpu_waves_per_eu(DDM_BM_WAVES)))
+void segsort_bitmap_kernel(const uint64_t* __restrict__ off, uint32_t m,
+                           uint64_t* __restrict__ out, SegSrc S,
+                           const uint32_t* __restrict__ lists,
+                           const uint32_t* __restrict__ list_count, uint32_t words) {
+  extern __shared__ uint4 bm4[];
+  const uint32_t w4 = (words + 3) / 4;
+  uint32_t* bits = reinterpret_cast<uint32_t*>(bm4);  // bitmap, then staging
+  uint16_t* ep = reinterpret_cast<uint16_t*>(bm4 + w4);  // entry starts within blocks
+  uint32_t* lstage = reinterpret_cast<uint32_t*>(ep + 4 * ((w4 + 3) / 4));  // long segments
+  const uint32_t cap = w4 * 4;  // staging capacity (ids)
+  constexpr uint32_t NW = kBmThreads / kWave;
+  __shared__ uint32_t part[MAXR * NW];
+  __shared__ uint32_t s_hi;
+  const uint32_t cntl = list_count[1];
+  const uint32_t tid = threadIdx.x, lane = lane_id(), wave = tid / kWave;
+  const uint32_t R = min(MAXR, (w4 + kBmThreads - 1) / kBmThreads);
+  const uint32_t G = gridDim.x;
+  const uint32_t* l1 = lists + m;
+  constexpr uint32_t PRE = kBmPre * kBmThreads;  // ids held in registers
+
+  auto list_at = [&](uint32_t li) { return li < cntl ? buf_u32(l1 + li) : 0u; };
+  auto meta_of = [&](uint32_t li, uint32_t jv) {
+    BmMeta q{0, 0, 0, 0, 0};
+    if (li < cntl) {
+      const uint32_t j = uniform_v(jv);
+      q.b = buf_u64(off + j);
+      q.elo = buf_u32(reinterpret_cast<const uint32_t*>(off + j + 1));
+      if (SLOTS) {
+        q.sb = buf_u64(S.so.base + j);
+        q.selo = S.so.cap ? buf_u32(S.so.cap + j)
+                          : buf_u32(reinterpret_cast<const uint32_t*>(S.so.base + j + 1));
+        q.cnt = buf_u32(S.cnt + j);
+      }
+    }
+    return q;
+  };
+  // a segment's keys are in its slot when every hit fits there, else in place
+  auto seg_of = [&](uint32_t li, const BmMeta& q) {
+    BmSeg g{0, 0, out};
+    if (li >= cntl) return g;
+    g.b = uniform_v64(q.b);
+    g.len = uniform_v(q.elo) - (uint32_t)g.b;
+    g.src = out + g.b;
+    if (SLOTS) {
+      // slot room: min(base + cap, limit) - base (cap form), else next base - base
+      const uint64_t sb = uniform_v64(q.sb);
+      uint64_t room;
+      if (S.so.cap) {
+        const uint64_t cp = uniform_v(q.selo);
+        room = S.so.limit > sb ? min(cp, S.so.limit - sb) : 0ull;
+      } else {
+        room = (uint32_t)(uniform_v(q.selo) - (uint32_t)sb);
+      }
+      if ((uint64_t)uniform_v(q.cnt) <= room) g.src = S.slots + sb;
+    }
+    return g;
+  };
+  // kBmPre ids per thread from key index `first` on (key first + tid + r *
+  // kBmThreads), through a buffer resource over the segment's len keys: one
+  // address register for all loads, and a load past the end returns 0
+  // (len <= n <= 2^20, so len * 8 fits)
+  auto load_ids = [&](const BmSeg& g, uint32_t first, uint32_t (&v)[kBmPre]) {
+    const __amdgpu_buffer_rsrc_t rs = buf_rsrc(g.src, g.len * (uint32_t)sizeof(uint64_t));
+#pragma unroll
+    for (uint32_t r = 0; r < kBmPre; ++r)
+      v[r] = (uint32_t)__builtin_amdgcn_raw_buffer_load_b32(
+          rs, (int)(tid * sizeof(uint64_t)),
+          (int)((first + r * kBmThreads) * sizeof(uint64_t)), 0);
+  };
+  auto load_hi = [&](const BmSeg& g) {  // key 0's high word (the update)
+    return (uint32_t)__builtin_amdgcn_raw_buffer_load_b32(
+        buf_rsrc(g.src, g.len * (uint32_t)sizeof(uint64_t)), 0, 4, 0);
+  };
+  // rounds wholly past the end are skipped (uniform); in the last one a
+  // lane past the end ORs 0 (its loaded id is 0)
+  auto mark = [&](const uint32_t (&v)[kBmPre], uint32_t first, uint32_t len) {
+#pragma unroll
+    for (uint32_t r = 0; r < kBmPre; ++r) {
+      if (first + r * kBmThreads >= len) break;
+      const uint32_t bit = first + tid + r * kBmThreads < len ? 1u << (v[r] & 31u) : 0u;
+      atomicOr(&bits[v[r] >> 5], bit);
+    }
+  };
+
+  BmMeta mt;    // offsets of the segment two ahead of the one being sorted
+  uint32_t jn;  // list entry of the segment three ahead
+
+  // one segment: ids holds its first ids (loaded two segments ago); on
+  // return it holds those of the segment two on, g and hi are updated alike
+  auto body = [&](uint32_t li, uint32_t (&ids)[kBmPre], uint32_t& hi, BmSeg& g) {
+    const BmSeg cg = g;
+    if (tid == 0) s_hi = hi;
+    mark(ids, 0u, cg.len);
+    for (uint32_t first = PRE; first < cg.len; first += PRE) {
+      uint32_t more[kBmPre];
+      load_ids(cg, first, more);
+      mark(more, first, cg.len);
+    }
+    __syncthreads();  // every id of the segment is read and marked
+
+    // the segment two on and the offsets of the one after it
+    const BmSeg g2 = seg_of(li + 2 * G, mt);
+    mt = meta_of(li + 3 * G, jn);
+    jn = list_at(li + 4 * G);
+
+    // marks per entry: the entry's start within its (block, wave) and the
+    // wave totals
+#pragma unroll 1
+    for (uint32_t r = 0; r < R; ++r) {
+      const uint32_t x = r * kBmThreads + tid;
+      const uint32_t c = x < w4 ? popc4(bm4[x]) : 0u;
+      const uint32_t inc = wave_scan_dpp(c);
+      if (x < w4) ep[x] = (uint16_t)(inc - c);
+      if (lane == kWave - 1) part[r * NW + wave] = inc;
+    }
+    __syncthreads();
+    // every wave: exclusive prefix of the R * NW totals in (block, wave)
+    // order (= entry order), two per lane
+    const uint32_t e0 = 2 * lane, e1 = 2 * lane + 1;
+    const uint32_t a0 = e0 < R * NW ? part[e0] : 0u, a1 = e1 < R * NW ? part[e1] : 0u;
+    const uint32_t ex0 = wave_scan_dpp(a0 + a1) - a0 - a1;
+    // place of id among the segment's ids (its block's start from the lane
+    // holding that block's prefix)
+    auto rank = [&](uint32_t id) {
+      const uint32_t e = id >> 7, h = (id >> 5) & 3u, blk = e >> 6;
+      const uint4 q = bm4[e];
+      const uint32_t wh = h == 0 ? q.x : h == 1 ? q.y : h == 2 ? q.z : q.w;
+      const uint32_t below = (h > 0 ? __popc(q.x) : 0u) + (h > 1 ? __popc(q.y) : 0u) +
+                             (h > 2 ? __popc(q.z) : 0u) + __popc(wh & ((1u << (id & 31u)) - 1u));
+      const uint32_t pl = blk >> 1;
+      const uint32_t exl = (uint32_t)__shfl((int)ex0, (int)pl, kWave);
+      const uint32_t a0l = (uint32_t)__shfl((int)a0, (int)pl, kWave);
+      return ((blk & 1u) ? exl + a0l : exl) + (uint32_t)ep[e] + below;
+    };
+    const uint64_t jhi = (uint64_t)s_hi << 32;
+    uint64_t* dst = out + cg.b;
+    if (cg.len > PRE) {
+      // a segment longer than the register window: its ids are read back
+      // from the bitmap in order (the keys in memory may already be
+      // overwritten), chunk by chunk of kBmLong positions through the small
+      // staging array.  Per entry block, a wave whose positions miss the
+      // chunk skips it; else the lanes take their set bits lowest first,
+      // the k-th in step k of a loop as long as the wave's fullest entry (a
+      // lane out of bits or of the chunk writes the spare slot)
+      for (uint32_t cbase = 0; cbase < cg.len; cbase += kBmLong) {
+        const uint32_t cend = min(cbase + kBmLong, cg.len);
+#pragma unroll 1
+        for (uint32_t r = 0; r < R; ++r) {
+          const uint32_t eidx = r * NW + wave;
+          const uint32_t pl = eidx >> 1;
+          const uint32_t exl = (uint32_t)__builtin_amdgcn_readlane((int)ex0, (int)pl);
+          const uint32_t a0l = (uint32_t)__builtin_amdgcn_readlane((int)a0, (int)pl);
+          const uint32_t a1l = (uint32_t)__builtin_amdgcn_readlane((int)a1, (int)pl);
+          const uint32_t wstart = (eidx & 1u) ? exl + a0l : exl;
+          const uint32_t wtot = (eidx & 1u) ? a1l : a0l;
+          if (wtot == 0 || wstart >= cend || wstart + wtot <= cbase) continue;
+          const uint32_t x = r * kBmThreads + tid;
+          const uint4 q = x < w4 ? bm4[x] : make_uint4(0u, 0u, 0u, 0u);
+          const uint32_t c = popc4(q);
+          const uint32_t p0 = wstart + wave_scan_dpp(c) - c;
+          const uint32_t maxc = wave_max_dpp(c);
+          uint64_t lo = (uint64_t)q.x | ((uint64_t)q.y << 32);
+          uint64_t hi2 = (uint64_t)q.z | ((uint64_t)q.w << 32);
+          for (uint32_t k = 0; k < maxc; ++k) {
+            const bool in_lo = lo != 0;
+            const uint64_t w = in_lo ? lo : hi2;
+            const uint32_t bit = (uint32_t)__builtin_ctzll(w | (1ull << 63)) + (in_lo ? 0u : 64u);
+            const uint64_t wc = w & (w - 1);
+            lo = in_lo ? wc : lo;
+            hi2 = in_lo ? hi2 : wc;
+            const uint32_t p = p0 + k;
+            const bool ok = k < c && p >= cbase && p < cend;
+            lstage[ok ? p - cbase : kBmLong] = x * 128u + bit;
+          }
+        }
+        __syncthreads();
+        for (uint32_t i = tid; i < cend - cbase; i += kBmThreads) dst[cbase + i] = jhi | lstage[i];
+        __syncthreads();  // staging free; at the end the bitmap is no longer read
+      }
+#pragma unroll 1
+      for (uint32_t r = 0; r < R; ++r) {
+        const uint32_t x = r * kBmThreads + tid;
+        if (x < w4) bm4[x] = make_uint4(0u, 0u, 0u, 0u);
+      }
+      __syncthreads();  // bitmap clear
+    } else {
+      // (every lane of a wave ranks, valid id or not: rank reads other lanes)
+      uint32_t pos[kBmPre];
+#pragma unroll
+      for (uint32_t r = 0; r < kBmPre; ++r) {
+        pos[r] = ~0u;
+        if (r * kBmThreads >= cg.len) continue;
+        const uint32_t rk = rank(ids[r]);
+        if (tid + r * kBmThreads < cg.len) pos[r] = rk;
+      }
+      __syncthreads();  // every id ranked: the bitmap is no longer read
+
+      for (uint32_t cbase = 0; cbase < cg.len; cbase += cap) {
+        const uint32_t cn = min(cap, cg.len - cbase);
+        if (cbase == 0) {
+          // clear the array past the staged positions (whole entries)
+          const uint32_t x0 = (cn + 3) / 4;
+#pragma unroll 1
+          for (uint32_t r = 0; r < R; ++r) {
+            const uint32_t x = r * kBmThreads + tid;
+            if (x >= x0 && x < w4) bm4[x] = make_uint4(0u, 0u, 0u, 0u);
+          }
+        }
+#pragma unroll
+        for (uint32_t r = 0; r < kBmPre; ++r)
+          if (pos[r] - cbase < cn) bits[pos[r] - cbase] = ids[r] + 1u;
+        __syncthreads();
+        for (uint32_t i = tid; i < cn; i += kBmThreads) {
+          const uint32_t v = bits[i];
+          if (v) dst[cbase + i] = jhi | (v - 1u);
+          bits[i] = 0u;
+        }
+        // the words of the last staged entry past the staged positions
+        if (tid < 4 && cn + tid < 4 * ((cn + 3) / 4)) bits[cn + tid] = 0u;
+        __syncthreads();  // array clear; s_hi and part read
+      }
+    }
+    // the ids of the segment two on load while the next one is sorted
+    g = g2;
+    load_ids(g, 0u, ids);
+    hi = load_hi(g);
+  };
+
+  uint32_t li = blockIdx.x;
+  if (li >= cntl) return;
+  for (uint32_t r = 0; r < R; ++r) {
+    const uint32_t x = r * kBmThreads + tid;
+    if (x < w4) bm4[x] = make_uint4(0u, 0u, 0u, 0u);
+  }
+  __syncthreads();
+  // prologue: the first two segments' ids, the third's offsets, the fourth's
+  // list entry
+  BmSeg g0 = seg_of(li, meta_of(li, list_at(li)));
+  uint32_t ids0[kBmPre], hi0;
+  load_ids(g0, 0u, ids0);
+  hi0 = load_hi(g0);
+  BmSeg g1 = seg_of(li + G, meta_of(li + G, list_at(li + G)));
+  uint32_t ids1[kBmPre], hi1;
+  load_ids(g1, 0u, ids1);
+  hi1 = load_hi(g1);
+  mt = meta_of(li + 2 * G, list_at(li + 2 * G));
+  jn = list_at(li + 3 * G);
+  for (;;) {
+    body(li, ids0, hi0, g0);
+    li += G;
+    if (li >= cntl) break;
+    body(li, ids1, hi1, g1);
+    li += G;
+    if (li >= cntl) break;
+  }
+}
+
 __global__ void copy_ids_kernel(const uint64_t* __restrict__ in, uint32_t* __restrict__ outp,
                                 uint64_t K) {
   const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -1751,7 +2125,7 @@ ddm_status sort_segments(const uint64_t* off, uint32_t m, uint64_t* out, uint64_
                          uint32_t* lists, uint32_t* lists_count, hipStream_t s, const SegSrc& S,
                          uint64_t max_len = ~0ull, Scratch* tmp_sc = nullptr);
 
-// the big-segment kernel's LDS bitmap exceeds the default dynamic LDS limit
+// the bitmap kernels' LDS exceeds the default dynamic LDS limit
 ddm_status ensure_segsort_attr() {
   static std::once_flag once;
   static hipError_t err = hipSuccess;
@@ -1759,6 +2133,13 @@ ddm_status ensure_segsort_attr() {
     err = hipFuncSetAttribute((const void*)segsort_big_kernel,
                               hipFuncAttributeMaxDynamicSharedMemorySize,
                               (int)(kMaxBitWords * sizeof(uint32_t)));
+    const void* fns[4] = {(const void*)segsort_bitmap_kernel<kBmRNarrow, false>,
+                          (const void*)segsort_bitmap_kernel<kBmRNarrow, true>,
+                          (const void*)segsort_bitmap_kernel<kBmRWide, false>,
+                          (const void*)segsort_bitmap_kernel<kBmRWide, true>};
+    for (int i = 0; i < 4 && err == hipSuccess; ++i)
+      err = hipFuncSetAttribute(fns[i], hipFuncAttributeMaxDynamicSharedMemorySize,
+                                (int)bitmap_lds_bytes(i < 2 ? kMaxBitWords / 2 : kMaxBitWords));
   });
   if (err != hipSuccess) return hip_fail(err, "hipFuncSetAttribute", __FILE__, __LINE__);
   return DDM_OK;
@@ -1792,6 +2173,38 @@ ddm_status sort_segments(const uint64_t* off, uint32_t m, uint64_t* out, uint64_
   segsort_mid_kernel<<<4096, kSegWaves * kWave, 0, s>>>(off, out, S, lists, lists_count);
   DDM_LAUNCHED("segsort_mid_kernel");
   if (max_len <= kSegMid) return DDM_OK;
+  ddm_status r = ensure_segsort_attr();
+  if (r != DDM_OK) return r;
+  if (n <= kMaxBitWords * 32) {
+    // one bitmap window: every listed segment by the bitmap kernel, one
+    // resident workgroup per slot of the chip (each takes every G-th segment)
+    const uint32_t words = std::max<uint32_t>(1u, (n + 31) / 32);
+    const size_t lds = bitmap_lds_bytes(words);
+    int dev = 0, cus = 0, per = 0;
+    DDM_HIP(hipGetDevice(&dev));
+    DDM_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+    const bool narrow = n <= kMaxBitWords * 16, slots = S.slots != nullptr;
+    const void* fn = narrow ? (slots ? (const void*)segsort_bitmap_kernel<kBmRNarrow, true>
+                                     : (const void*)segsort_bitmap_kernel<kBmRNarrow, false>)
+                            : (slots ? (const void*)segsort_bitmap_kernel<kBmRWide, true>
+                                     : (const void*)segsort_bitmap_kernel<kBmRWide, false>);
+    DDM_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, fn, kBmThreads, lds));
+    const uint32_t grid = (uint32_t)std::max(1, cus * std::max(1, per));
+    if (narrow && slots)
+      segsort_bitmap_kernel<kBmRNarrow, true><<<grid, kBmThreads, lds, s>>>(off, m, out, S, lists,
+                                                                   lists_count, words);
+    else if (narrow)
+      segsort_bitmap_kernel<kBmRNarrow, false><<<grid, kBmThreads, lds, s>>>(off, m, out, S, lists,
+                                                                    lists_count, words);
+    else if (slots)
+      segsort_bitmap_kernel<kBmRWide, true><<<grid, kBmThreads, lds, s>>>(off, m, out, S, lists,
+                                                                   lists_count, words);
+    else
+      segsort_bitmap_kernel<kBmRWide, false><<<grid, kBmThreads, lds, s>>>(off, m, out, S, lists,
+                                                                    lists_count, words);
+    DDM_LAUNCHED("segsort_bitmap_kernel");
+    return DDM_OK;
+  }
   const uint32_t words = std::min<uint32_t>(kMaxBitWords, (n + 31) / 32);
   uint32_t* tmp = nullptr;
   Scratch local(s);
@@ -1805,8 +2218,6 @@ ddm_status sort_segments(const uint64_t* off, uint32_t m, uint64_t* out, uint64_
     copy_ids_kernel<<<(unsigned)((K + 255) / 256), 256, 0, s>>>(out, tmp, K);
     DDM_LAUNCHED("copy_ids_kernel");
   }
-  ddm_status r = ensure_segsort_attr();
-  if (r != DDM_OK) return r;
   {
     // buckets of 2^shift consecutive ids, as many as the class's largest
     // segment has keys (fewer when n is smaller)

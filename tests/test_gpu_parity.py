@@ -99,10 +99,10 @@ def test_long_segments():
 @pytest.mark.parametrize("clustered", [False, True])
 def test_segment_sort_size_classes(clustered):
     """Segments of every size class of the segment sort: 1, 2..16 (one lane),
-    17..2048 (one wavefront, all six register widths), 2049..16384 (bucket
-    sort) and above (bitmap).  With clustered ids (5000 consecutive ids share
-    one box) the bucket sort's per-bucket capacity is exceeded and those
-    segments take the bitmap path."""
+    17..2048 (one wavefront, all six register widths), 2049..8192 (bitmap
+    ranks of ids held in registers) and above (bitmap read back in order).
+    With clustered ids (5000 consecutive ids share one box) the marks crowd
+    into few bitmap entries."""
     rng = np.random.default_rng(19 + clustered)
     n = 100000
     s_lo = rng.uniform(0, 1e5, (1, n)).astype(np.float32)
