@@ -1289,12 +1289,16 @@ void segsort_bitmap_kernel(const uint64_t* __restrict__ off, uint32_t m,
     const uint32_t ex0 = wave_scan_dpp(a0 + a1) - a0 - a1;
     // place of id among the segment's ids (its block's start from the lane
     // holding that block's prefix)
+    auto low_bits = [](uint32_t w, int t) {
+      const uint32_t tt = (uint32_t)min(max(t, 0), 32);
+      return tt >= 32u ? w : __builtin_amdgcn_ubfe(w, 0u, tt);
+    };
     auto rank = [&](uint32_t id) {
-      const uint32_t e = id >> 7, h = (id >> 5) & 3u, blk = e >> 6;
+      const uint32_t e = id >> 7, blk = e >> 6;
+      const int b = (int)(id & 127u);
       const uint4 q = bm4[e];
-      const uint32_t wh = h == 0 ? q.x : h == 1 ? q.y : h == 2 ? q.z : q.w;
-      const uint32_t below = (h > 0 ? __popc(q.x) : 0u) + (h > 1 ? __popc(q.y) : 0u) +
-                             (h > 2 ? __popc(q.z) : 0u) + __popc(wh & ((1u << (id & 31u)) - 1u));
+      const uint32_t below = __popc(low_bits(q.x, b)) + __popc(low_bits(q.y, b - 32)) +
+                             __popc(low_bits(q.z, b - 64)) + __popc(low_bits(q.w, b - 96));
       const uint32_t pl = blk >> 1;
       const uint32_t exl = (uint32_t)__shfl((int)ex0, (int)pl, kWave);
       const uint32_t a0l = (uint32_t)__shfl((int)a0, (int)pl, kWave);
@@ -1359,7 +1363,7 @@ void segsort_bitmap_kernel(const uint64_t* __restrict__ off, uint32_t m,
         pos[r] = ~0u;
         if (r * kBmThreads >= cg.len) continue;
         const uint32_t rk = rank(ids[r]);
-        if (tid + r * kBmThreads < cg.len) pos[r] = rk;
+        pos[r] = tid + r * kBmThreads < cg.len ? rk : ~0u;
       }
       __syncthreads();  // every id ranked: the bitmap is no longer read
 
