@@ -441,14 +441,27 @@ __global__ __launch_bounds__(256) void bucket_scatter_kernel(const uint32_t* __r
 }
 
 // --------------------------------------------------------------------------
-// Learned sizing: tiles balanced by predicted work.  Within each bucket the
-// updates are cut into tiles at every 64th update (as for the count) and
-// also wherever the predicted hits accumulated since the bucket's start
-// cross a multiple of H = twice the predicted hits of an average full tile,
-// so that a wavefront never takes a tile of much more predicted output than
-// the average: dense regions get several small tiles, which run on separate
-// wavefronts, instead of one long one.
+// Tiles balanced by work (the learned single pass: predicted hits; the
+// plain fill: the exact counts).  Within each bucket the updates are cut
+// into tiles at every 64th update (as for the count) and also wherever the
+// hits accumulated since the bucket's start cross a multiple of H (below),
+// so that a wavefront never takes a tile of much more output than H: dense
+// regions get several small tiles, which run on separate wavefronts,
+// instead of one long one.
 // --------------------------------------------------------------------------
+// H = twice an average full tile's work / kCutDiv, but at least
+// kCutMinHits: with 16, an average tile of 64 updates of the hotspot
+// workload (3600 hits per update) is cut in about eight (a flush's
+// per-update work then spreads over more wavefronts; each piece scans its
+// candidate range again).  Measured on that workload's learned fill:
+// kCutDiv 1 11.1 ms, 4 8.7, 16 7.9, 64 10.3, 256 13.2.  Tiles of a few
+// thousand hits gain nothing from the cut (uniform sets at 200 hits per
+// update: fill 0.51 ms uncut, 1.04 ms cut in eight), hence the floor.
+#ifndef DDM_CUT_DIV
+#define DDM_CUT_DIV 16
+#endif
+constexpr uint32_t kCutDiv = DDM_CUT_DIV;
+constexpr uint64_t kCutMinHits = 32768;
 __global__ __launch_bounds__(256) void work_in_order_kernel(const uint32_t* __restrict__ perm,
                                                             const uint32_t* __restrict__ cap,
                                                             uint32_t m,
@@ -465,7 +478,7 @@ __global__ __launch_bounds__(256) void tile_cut_kernel(const uint32_t* __restric
                                                        uint32_t m, uint32_t* __restrict__ flag) {
   const uint32_t p = blockIdx.x * blockDim.x + threadIdx.x;
   if (p >= m) return;
-  const uint64_t H = max((2ull * 64ull * cw[m]) / m, 1ull);
+  const uint64_t H = max((2ull * 64ull * cw[m]) / ((uint64_t)m * kCutDiv), kCutMinHits);
   const uint32_t s = boff[bucket[perm[p]]];
   bool cut = p == s || ((p - s) & 63u) == 0;
   if (!cut) cut = (cw[p] - cw[s]) / H != (cw[p - 1] - cw[s]) / H;
@@ -644,9 +657,11 @@ __device__ __forceinline__ void bitonic_regs(uint64_t (&v)[N]) {
 // costs no extra pass.
 // bucket-aligned tiles, one wavefront each (the grid covers the largest
 // possible number of tiles; the waves beyond the actual number return).
-// The traversal is latency-bound, so the register budget is set for eight
-// wavefronts per SIMD (the d = 2 stash form then keeps two values in
-// scratch, and measured 5% faster than at seven wavefronts).
+// The traversal is latency-bound, so the register budget of the fill and of
+// the d = 1 forms is set for eight wavefronts per SIMD; the count kernels
+// for d >= 2 (with the transposed flush beside the direct one) for seven,
+// where they spill nothing (at eight they kept 12 registers per lane in
+// scratch and ran 4% slower).
 #ifndef DDM_TILE_COUNT_WAVES
 #define DDM_TILE_COUNT_WAVES 7
 #endif
@@ -1496,9 +1511,13 @@ static ddm_status launch_traverse(const MatchPlan& P, const TreeDev& T, const fl
                  s);
     if (US.tmap || US.tstart) {
       // at most one partial tile per bucket; a tile list cut by predicted
-      // work as well has at most twice as many
+      // work as well has at most one more tile per crossing of a multiple
+      // of H (at most total / H = m * kCutDiv / 128), and never more tiles
+      // than updates
       uint32_t tiles = (US.total + 63u) / 64u + std::min<uint32_t>(US.total, kBuckets);
-      if (US.tstart) tiles *= 2;
+      if (US.tstart)
+        tiles = (uint32_t)std::min<uint64_t>(
+            (uint64_t)tiles + ((uint64_t)US.total * kCutDiv + 127u) / 128u + 1u, US.total);
       const uint32_t grid = (tiles + kTileWaves - 1) / kTileWaves;
       if (!FILL && O.skey)
         tile_bucket_kernel<D, false, true><<<grid, kTileWaves * kWave, 0, s>>>(T, ulo, uhi, m,
@@ -2412,6 +2431,41 @@ extern "C" ddm_status ddm_features(const ddm_tree* t, const float* upd_lo, const
   return launch_features(tree_feat(t), tree_d(t), upd_lo, upd_hi, m, X, (hipStream_t)stream);
 }
 
+// The fill of the plain two-pass form on tiles balanced by the exact
+// counts (the cut of the learned single pass): U gets the tile list; its
+// arrays live in bsc, which the caller keeps until the fill has run.
+static ddm_status balance_fill_tiles(const MatchState& st, uint32_t m, Scratch& bsc, UpdSet* U,
+                                     hipStream_t s) {
+  bsc.reserve(sizeof(uint32_t) * m);                  // work, then cut flags
+  bsc.reserve(sizeof(uint64_t) * ((size_t)m + 1));    // their scans
+  bsc.reserve(sizeof(uint32_t) * ((size_t)m + 1));    // tile starts
+  bsc.reserve(sizeof(uint32_t) * m);                  // tile buckets
+  bsc.reserve(sizeof(uint64_t) * scan_tmp_words(m));  // scan scratch
+  if (!bsc.commit()) return DDM_E_NOMEM;
+  uint32_t* w = bsc.take<uint32_t>(m);
+  uint64_t* cw = bsc.take<uint64_t>((size_t)m + 1);
+  uint32_t* ts = bsc.take<uint32_t>((size_t)m + 1);
+  uint32_t* tb = bsc.take<uint32_t>(m);
+  uint64_t* tmp = bsc.take<uint64_t>(scan_tmp_words(m));
+  if (!bsc.fits()) return scratch_overrun("fill tile balance");
+  ProfScope ps("balance", s);
+  const unsigned g = (m + 255) / 256;
+  work_in_order_kernel<<<g, 256, 0, s>>>(st.perm, st.cnt, m, w);
+  DDM_LAUNCHED("work_in_order_kernel");
+  ddm_status r = scan_u32_u64(w, cw, m, tmp, s);
+  if (r != DDM_OK) return r;
+  tile_cut_kernel<<<g, 256, 0, s>>>(st.perm, st.bucket, st.bhist, cw, m, w);
+  DDM_LAUNCHED("tile_cut_kernel");
+  r = scan_u32_u64(w, cw, m, tmp, s);
+  if (r != DDM_OK) return r;
+  tile_list_kernel<<<g, 256, 0, s>>>(st.perm, st.bucket, w, cw, m, ts, tb);
+  DDM_LAUNCHED("tile_list_kernel");
+  U->tstart = ts;
+  U->tbuck = tb;
+  U->ntiles = cw + m;
+  return DDM_OK;
+}
+
 extern "C" ddm_status ddm_match_finish(ddm_pending* pd, uint64_t* out_pairs, uint64_t capacity) {
   set_detail("");
   if (!pd) return DDM_OK;  // empty match: nothing to do
@@ -2453,8 +2507,18 @@ extern "C" ddm_status ddm_match_finish(ddm_pending* pd, uint64_t* out_pairs, uin
         if (le != hipSuccess) r = hip_fail(le, "stash_scatter_kernel", __FILE__, __LINE__);
       }
     } else {
-      r = traverse_any<true>(tree_d(pd->t), pd->plan, T, pd->ulo, pd->uhi, pd->m, st.all(),
-                             st.kstar, O, pd->s);
+      // tiles cut by the exact counts (not in the no-allocation form), when
+      // a tile of 64 of the longest segments could exceed the cut's H
+      UpdSet U = st.all();
+      Scratch bsc(pd->s);
+      const uint64_t H = std::max<uint64_t>(
+          (2ull * 64ull * st.K) / ((uint64_t)pd->m * kCutDiv), kCutMinHits);
+      if (!st.noalloc && pd->plan.traversal == DDM_TRAVERSE_TILE && U.tmap &&
+          (st.maxseg == ~0ull || 64ull * st.maxseg > H))
+        r = balance_fill_tiles(st, pd->m, bsc, &U, pd->s);
+      if (r == DDM_OK)
+        r = traverse_any<true>(tree_d(pd->t), pd->plan, T, pd->ulo, pd->uhi, pd->m, U, st.kstar,
+                               O, pd->s);
     }
     if (r == DDM_OK) {
       SegSrc S{};
