@@ -566,7 +566,10 @@ __global__ __launch_bounds__(1024) void lane_kernel(TreeDev T, const float* __re
       load_rec<D>(rec + (size_t)x * R, v);
       if (v[0] > qh[0]) break;
       if (overlaps<D>(v, ql, qh)) {
-        if (FILL && c < lim) out[base + c] = jhi | ids[x];
+        if (FILL && c < lim) {
+          if (O.ids) O.ids[base + c] = ids[x];
+          else out[base + c] = jhi | ids[x];
+        }
         ++c;
       }
       const uint32_t h = (uint32_t)__builtin_ctz(x);
@@ -736,6 +739,9 @@ struct SegSrc {
   const uint64_t* slots;  // nullptr: every segment is in place
   SegOut so;              // slot bounds (base = slot offsets, cap, limit)
   const uint32_t* cnt;    // hits per update
+  // the fill wrote 4-byte subscription ids here (same places as out): the
+  // segments are read from it and the keys formed with the update's index
+  const uint32_t* ids = nullptr;
 };
 
 __device__ __forceinline__ const uint64_t* seg_src(const SegSrc& S, uint32_t j,
@@ -767,6 +773,21 @@ __device__ __forceinline__ void sort_small_segment(const uint64_t* __restrict__ 
 
 constexpr uint32_t kSegMid = 2048;  // longest segment sorted in LDS by bitonic
 
+// the same, from 4-byte ids, keys formed with the update's high word
+template <int N>
+__device__ __forceinline__ void sort_small_ids(const uint32_t* __restrict__ src, uint64_t jhi,
+                                               uint64_t* __restrict__ dst, uint32_t len) {
+  uint64_t v[N];
+#pragma unroll
+  for (int i = 0; i < N; ++i) v[i] = ((uint32_t)i < len) ? (jhi | src[i]) : ~0ull;
+  bitonic_regs<N>(v);
+#pragma unroll
+  for (int i = 0; i < N; ++i)
+    if ((uint32_t)i < len) dst[i] = v[i];
+}
+
+// IDS: the segments are the fill's 4-byte ids (S.ids), else keys
+template <bool IDS>
 __global__ __launch_bounds__(256) void segsort_small_kernel(const uint64_t* __restrict__ off,
                                                             uint32_t m, uint64_t* __restrict__ out,
                                                             SegSrc S,
@@ -777,9 +798,19 @@ __global__ __launch_bounds__(256) void segsort_small_kernel(const uint64_t* __re
   const uint64_t b = off[j];
   const uint64_t len64 = off[j + 1] - b;
   if (len64 == 0) return;
+  const uint32_t len = len64 > 0xffffffffull ? 0xffffffffu : (uint32_t)len64;
+  if (IDS && len <= 32) {
+    const uint32_t* ip = S.ids + b;
+    const uint64_t jhi = (uint64_t)j << 32;
+    if (len == 1) out[b] = jhi | ip[0];
+    else if (len <= 4) sort_small_ids<4>(ip, jhi, out + b, len);
+    else if (len <= 8) sort_small_ids<8>(ip, jhi, out + b, len);
+    else if (len <= 16) sort_small_ids<16>(ip, jhi, out + b, len);
+    else sort_small_ids<32>(ip, jhi, out + b, len);
+    return;
+  }
   bool in_place;
   const uint64_t* src = seg_src(S, j, out, b, &in_place);
-  const uint32_t len = len64 > 0xffffffffull ? 0xffffffffu : (uint32_t)len64;
   if (len == 1) {
     if (!in_place) out[b] = src[0];
   } else if (len <= 4) {
@@ -803,8 +834,8 @@ __global__ __launch_bounds__(256) void segsort_small_kernel(const uint64_t* __re
 // power of two, at least 64), and sorted by a bitonic network: exchanges of
 // partners less than V apart stay inside a lane's registers, the others
 // swap whole registers with the lane whose index differs in one bit.
-template <int V>
-__device__ __forceinline__ void wave_bitonic_segment(const uint64_t* __restrict__ src,
+template <int V, typename SRC>
+__device__ __forceinline__ void wave_bitonic_segment(const SRC* __restrict__ src,
                                                      uint64_t* __restrict__ dst, uint32_t len,
                                                      uint64_t jhi, uint32_t* __restrict__ sh,
                                                      uint32_t lane) {
@@ -853,6 +884,21 @@ __device__ __forceinline__ void wave_bitonic_segment(const uint64_t* __restrict_
 
 constexpr int kSegWaves = 4;  // wavefronts per workgroup of the mid sort
 
+// the register width for a segment of len (33..2048) keys
+template <typename SRC>
+__device__ __forceinline__ void sort_wave_segment(const SRC* __restrict__ src,
+                                                  uint64_t* __restrict__ dst, uint32_t len,
+                                                  uint64_t jhi, uint32_t* __restrict__ sh,
+                                                  uint32_t lane) {
+  if (len <= 64) wave_bitonic_segment<1>(src, dst, len, jhi, sh, lane);
+  else if (len <= 128) wave_bitonic_segment<2>(src, dst, len, jhi, sh, lane);
+  else if (len <= 256) wave_bitonic_segment<4>(src, dst, len, jhi, sh, lane);
+  else if (len <= 512) wave_bitonic_segment<8>(src, dst, len, jhi, sh, lane);
+  else if (len <= 1024) wave_bitonic_segment<16>(src, dst, len, jhi, sh, lane);
+  else wave_bitonic_segment<32>(src, dst, len, jhi, sh, lane);
+}
+
+template <bool IDS>
 __global__ __launch_bounds__(kSegWaves * kWave) void segsort_mid_kernel(
     const uint64_t* __restrict__ off, uint64_t* __restrict__ out, SegSrc S,
     const uint32_t* __restrict__ lists, const uint32_t* __restrict__ list_count) {
@@ -866,17 +912,16 @@ __global__ __launch_bounds__(kSegWaves * kWave) void segsort_mid_kernel(
     const uint32_t j = uniform_u32(lists[li]);
     const uint64_t b = off[j];
     const uint32_t len = uniform_u32((uint32_t)(off[j + 1] - b));
-    bool in_place;
-    const uint64_t* src = seg_src(S, j, out, b, &in_place);
-    // every key of the segment carries the same update id in its high word
-    const uint64_t jhi = readlane_u64(src[0], 0) & 0xffffffff00000000ull;
     uint64_t* dst = out + b;
-    if (len <= 64) wave_bitonic_segment<1>(src, dst, len, jhi, sh, lane);
-    else if (len <= 128) wave_bitonic_segment<2>(src, dst, len, jhi, sh, lane);
-    else if (len <= 256) wave_bitonic_segment<4>(src, dst, len, jhi, sh, lane);
-    else if (len <= 512) wave_bitonic_segment<8>(src, dst, len, jhi, sh, lane);
-    else if (len <= 1024) wave_bitonic_segment<16>(src, dst, len, jhi, sh, lane);
-    else wave_bitonic_segment<32>(src, dst, len, jhi, sh, lane);
+    if constexpr (IDS) {
+      sort_wave_segment(S.ids + b, dst, len, (uint64_t)j << 32, sh, lane);
+    } else {
+      bool in_place;
+      const uint64_t* src = seg_src(S, j, out, b, &in_place);
+      // every key of the segment carries the same update id in its high word
+      const uint64_t jhi = readlane_u64(src[0], 0) & 0xffffffff00000000ull;
+      sort_wave_segment(src, dst, len, jhi, sh, lane);
+    }
   }
 }
 
@@ -1146,13 +1191,14 @@ __device__ __forceinline__ uint64_t uniform_v64(uint64_t v) {
 // and its hit count, as loaded
 struct BmMeta {
   uint64_t b, sb;
-  uint32_t elo, selo, cnt;
+  uint32_t elo, selo, cnt, j;
 };
 // where a segment is written (out + b, len keys) and read from
 struct BmSeg {
   uint64_t b;
   uint32_t len;
   const uint64_t* src;
+  uint32_t j;  // the update (the keys' high word when they are formed from ids)
 };
 
 #ifndef DDM_BM_THREADS
@@ -1203,9 +1249,10 @@ void segsort_bitmap_kernel(const uint64_t* __restrict__ off, uint32_t m,
 
   auto list_at = [&](uint32_t li) { return li < cntl ? buf_u32(l1 + li) : 0u; };
   auto meta_of = [&](uint32_t li, uint32_t jv) {
-    BmMeta q{0, 0, 0, 0, 0};
+    BmMeta q{0, 0, 0, 0, 0, 0};
     if (li < cntl) {
       const uint32_t j = uniform_v(jv);
+      q.j = j;
       q.b = buf_u64(off + j);
       q.elo = buf_u32(reinterpret_cast<const uint32_t*>(off + j + 1));
       if (SLOTS) {
@@ -1219,8 +1266,9 @@ void segsort_bitmap_kernel(const uint64_t* __restrict__ off, uint32_t m,
   };
   // a segment's keys are in its slot when every hit fits there, else in place
   auto seg_of = [&](uint32_t li, const BmMeta& q) {
-    BmSeg g{0, 0, out};
+    BmSeg g{0, 0, out, 0};
     if (li >= cntl) return g;
+    g.j = uniform_v(q.j);
     g.b = uniform_v64(q.b);
     g.len = uniform_v(q.elo) - (uint32_t)g.b;
     g.src = out + g.b;
@@ -1242,15 +1290,18 @@ void segsort_bitmap_kernel(const uint64_t* __restrict__ off, uint32_t m,
   // kBmThreads), through a buffer resource over the segment's len keys: one
   // address register for all loads, and a load past the end returns 0
   // (len <= n <= 2^20, so len * 8 fits)
+  // (from the fill's 4-byte ids when there are: contiguous words)
   auto load_ids = [&](const BmSeg& g, uint32_t first, uint32_t (&v)[kBmPre]) {
-    const __amdgpu_buffer_rsrc_t rs = buf_rsrc(g.src, g.len * (uint32_t)sizeof(uint64_t));
+    const uint32_t w = S.ids ? (uint32_t)sizeof(uint32_t) : (uint32_t)sizeof(uint64_t);
+    const __amdgpu_buffer_rsrc_t rs =
+        S.ids ? buf_rsrc(S.ids + g.b, g.len * w) : buf_rsrc(g.src, g.len * w);
 #pragma unroll
     for (uint32_t r = 0; r < kBmPre; ++r)
       v[r] = (uint32_t)__builtin_amdgcn_raw_buffer_load_b32(
-          rs, (int)(tid * sizeof(uint64_t)),
-          (int)((first + r * kBmThreads) * sizeof(uint64_t)), 0);
+          rs, (int)(tid * w), (int)((first + r * kBmThreads) * w), 0);
   };
   auto load_hi = [&](const BmSeg& g) {  // key 0's high word (the update)
+    if (S.ids) return g.j;
     return (uint32_t)__builtin_amdgcn_raw_buffer_load_b32(
         buf_rsrc(g.src, g.len * (uint32_t)sizeof(uint64_t)), 0, 4, 0);
   };
@@ -2190,10 +2241,17 @@ ddm_status sort_segments(const uint64_t* off, uint32_t m, uint64_t* out, uint64_
                          uint32_t* lists, uint32_t* lists_count, hipStream_t s,
                          const SegSrc& S, uint64_t max_len, Scratch* tmp_sc) {
   ProfScope ps("segsort", s);
-  segsort_small_kernel<<<(m + 255) / 256, 256, 0, s>>>(off, m, out, S, lists, lists_count);
+  if (S.ids)
+    segsort_small_kernel<true><<<(m + 255) / 256, 256, 0, s>>>(off, m, out, S, lists, lists_count);
+  else
+    segsort_small_kernel<false><<<(m + 255) / 256, 256, 0, s>>>(off, m, out, S, lists,
+                                                                lists_count);
   DDM_LAUNCHED("segsort_small_kernel");
   if (max_len <= 32) return DDM_OK;  // every segment sorted in registers
-  segsort_mid_kernel<<<4096, kSegWaves * kWave, 0, s>>>(off, out, S, lists, lists_count);
+  if (S.ids)
+    segsort_mid_kernel<true><<<4096, kSegWaves * kWave, 0, s>>>(off, out, S, lists, lists_count);
+  else
+    segsort_mid_kernel<false><<<4096, kSegWaves * kWave, 0, s>>>(off, out, S, lists, lists_count);
   DDM_LAUNCHED("segsort_mid_kernel");
   if (max_len <= kSegMid) return DDM_OK;
   ddm_status r = ensure_segsort_attr();
@@ -2432,16 +2490,19 @@ extern "C" ddm_status ddm_features(const ddm_tree* t, const float* upd_lo, const
 }
 
 // The fill of the plain two-pass form on tiles balanced by the exact
-// counts (the cut of the learned single pass): U gets the tile list; its
-// arrays live in bsc, which the caller keeps until the fill has run.
-static ddm_status balance_fill_tiles(const MatchState& st, uint32_t m, Scratch& bsc, UpdSet* U,
-                                     hipStream_t s) {
+// counts (the cut of the learned single pass): the arrays are reserved in
+// bsc first (with whatever else the caller reserves), then taken and
+// filled; U gets the tile list.  bsc must outlive the fill.
+static void balance_reserve(uint32_t m, Scratch& bsc) {
   bsc.reserve(sizeof(uint32_t) * m);                  // work, then cut flags
   bsc.reserve(sizeof(uint64_t) * ((size_t)m + 1));    // their scans
   bsc.reserve(sizeof(uint32_t) * ((size_t)m + 1));    // tile starts
   bsc.reserve(sizeof(uint32_t) * m);                  // tile buckets
   bsc.reserve(sizeof(uint64_t) * scan_tmp_words(m));  // scan scratch
-  if (!bsc.commit()) return DDM_E_NOMEM;
+}
+
+static ddm_status balance_fill_tiles(const MatchState& st, uint32_t m, Scratch& bsc, UpdSet* U,
+                                     hipStream_t s) {
   uint32_t* w = bsc.take<uint32_t>(m);
   uint64_t* cw = bsc.take<uint64_t>((size_t)m + 1);
   uint32_t* ts = bsc.take<uint32_t>((size_t)m + 1);
@@ -2482,6 +2543,8 @@ extern "C" ddm_status ddm_match_finish(ddm_pending* pd, uint64_t* out_pairs, uin
     SegOut O{};
     O.base = st.off;
     O.out = out_pairs;
+    Scratch fsc(pd->s);        // the fill's ids and tile lists (until the sort has run)
+    uint32_t* fids = nullptr;  // the fill's 4-byte ids, if it writes them
     if (st.learned) {
       // segments that fitted their slots are moved into place by the
       // segment sort; overflowed ones are filled in place here
@@ -2507,21 +2570,33 @@ extern "C" ddm_status ddm_match_finish(ddm_pending* pd, uint64_t* out_pairs, uin
         if (le != hipSuccess) r = hip_fail(le, "stash_scatter_kernel", __FILE__, __LINE__);
       }
     } else {
-      // tiles cut by the exact counts (not in the no-allocation form), when
-      // a tile of 64 of the longest segments could exceed the cut's H
+      // Not in the no-allocation form: (1) the fill writes 4-byte ids,
+      // which the segment sort expands into keys (half the bytes written by
+      // the fill and read by the sort), when the sort can read ids (every
+      // id below 2^20); (2) tiles cut by the exact counts, when a tile of 64
+      // of the longest segments could exceed the cut's H.
       UpdSet U = st.all();
-      Scratch bsc(pd->s);
       const uint64_t H = std::max<uint64_t>(
           (2ull * 64ull * st.K) / ((uint64_t)pd->m * kCutDiv), kCutMinHits);
-      if (!st.noalloc && pd->plan.traversal == DDM_TRAVERSE_TILE && U.tmap &&
-          (st.maxseg == ~0ull || 64ull * st.maxseg > H))
-        r = balance_fill_tiles(st, pd->m, bsc, &U, pd->s);
+      const bool use_ids = !st.noalloc && tree_n(pd->t) <= kMaxBitWords * 32;
+      const bool bal = !st.noalloc && pd->plan.traversal == DDM_TRAVERSE_TILE && U.tmap &&
+                       (st.maxseg == ~0ull || 64ull * st.maxseg > H);
+      if (use_ids) fsc.reserve(sizeof(uint32_t) * st.K);
+      if (bal) balance_reserve(pd->m, fsc);
+      if ((use_ids || bal) && !fsc.commit()) r = DDM_E_NOMEM;
+      if (r == DDM_OK && use_ids) {
+        fids = fsc.take<uint32_t>(st.K);
+        if (!fsc.fits()) r = scratch_overrun("fill ids");
+      }
+      if (r == DDM_OK && bal) r = balance_fill_tiles(st, pd->m, fsc, &U, pd->s);
+      O.ids = fids;
       if (r == DDM_OK)
         r = traverse_any<true>(tree_d(pd->t), pd->plan, T, pd->ulo, pd->uhi, pd->m, U, st.kstar,
                                O, pd->s);
     }
     if (r == DDM_OK) {
       SegSrc S{};
+      S.ids = fids;
       if (st.learned) {
         S.slots = st.slots;
         S.so.base = st.soff;

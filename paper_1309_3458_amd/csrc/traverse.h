@@ -143,6 +143,10 @@ struct SegOut {
   uint64_t limit;
   uint32_t* cnt;
   uint64_t* out;
+  // FILL, optional: the subscription id of each hit (4 bytes) at the same
+  // place in this array instead of the key in out (the segment sort then
+  // forms the keys as it writes them)
+  uint32_t* ids = nullptr;
   uint64_t* skey = nullptr;
   uint32_t* srank = nullptr;
   uint32_t* sused = nullptr;
@@ -348,6 +352,7 @@ __device__ __forceinline__ void tile_body(const TreeDev& T, const float* __restr
   if (FILL && qv) seg_bounds(O, gj, &mybase, &myend);
   const uint64_t mystart = mybase;
   uint64_t* __restrict__ out = O.out;
+  uint32_t* __restrict__ oids = O.ids;
   const uint64_t jhi = (uint64_t)jx << 32;
   const uint32_t nq4 = (nq + 3u) & ~3u;
   wave_sync();
@@ -463,7 +468,10 @@ __device__ __forceinline__ void tile_body(const TreeDev& T, const float* __restr
             const uint64_t e = readlane_u64(myend, qq);
             const uint64_t jq = readlane_u64(jhi, qq);
             const uint64_t dst = b + mask_rank(hm[u]);
-            if (((hm[u] >> lane) & 1ull) && dst < e) out[dst] = jq | sid;
+            if (((hm[u] >> lane) & 1ull) && dst < e) {
+              if (oids) oids[dst] = sid;
+              else out[dst] = jq | sid;
+            }
             if (lane == qq) mybase += pc;
           } else if constexpr (STASH || XP) {
             if (lane == qq) myhm = hm[u];
