@@ -265,7 +265,7 @@ ddm_status ddm_count(const ddm_tree* t, const float* upd_lo, const float* upd_hi
  *                                  (d > 1; hint = the caller's capacity, 0 =
  *                                  the default of 4 hits per update),
  *             DDM_SCRATCH_LEARNED  the single pass (d > 1) without its slot
- *                                  arena (8 bytes per predicted slot).
+ *                                  arena (4 bytes per predicted slot).
  *  bytes      host pointer, receives the size (0 for m = 0).
  * Computed on the host by the same layout code the match runs, with no GPU
  * and no memory behind it; it also checks that every piece the match takes
@@ -537,7 +537,7 @@ void ddm_batch_free(ddm_batch* b);
  * requests queued together are matched as one batch (the ddm_batch kernels,
  * sized on the device by their exact counts).  Admission is by footprint:
  * inputs + trees + match scratch when a request starts (FIFO order); with
- * learned sizing, the slot arena (8 bytes per predicted slot) plus an
+ * learned sizing, the slot arena (4 bytes per predicted slot) plus an
  * output estimate of the same size once the prediction is known and before
  * the arena is allocated; the exact output once known.  A request waits
  * until its bytes fit.  When every request in flight is waiting, the

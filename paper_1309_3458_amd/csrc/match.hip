@@ -735,28 +735,31 @@ void tile_bucket_kernel(
   }
 }
 
+// Where the segment sort finds each segment's unsorted hits: in place in
+// out as keys, or as 4-byte subscription ids (the keys then formed with the
+// update's index as the high word) in the single pass's slots (the updates
+// whose hits fitted) or, from the plain fill, at the segment's own places.
 struct SegSrc {
-  const uint64_t* slots;  // nullptr: every segment is in place
-  SegOut so;              // slot bounds (base = slot offsets, cap, limit)
-  const uint32_t* cnt;    // hits per update
-  // the fill wrote 4-byte subscription ids here (same places as out): the
-  // segments are read from it and the keys formed with the update's index
-  const uint32_t* ids = nullptr;
+  const uint32_t* slots = nullptr;  // single pass: ids in the slots
+  SegOut so{};                      // slot bounds (base = slot offsets, cap, limit)
+  const uint32_t* cnt = nullptr;    // hits per update
+  const uint32_t* ids = nullptr;    // plain fill: ids at the segments' places
 };
 
-__device__ __forceinline__ const uint64_t* seg_src(const SegSrc& S, uint32_t j,
-                                                   const uint64_t* out, uint64_t off_j,
-                                                   bool* in_place) {
+// segment j (output offset b): its ids, or else its keys (in place in out)
+struct SegAt {
+  const uint32_t* ids;
+  const uint64_t* keys;
+};
+__device__ __forceinline__ SegAt seg_at(const SegSrc& S, uint32_t j, const uint64_t* out,
+                                        uint64_t b) {
+  if (S.ids) return SegAt{S.ids + b, nullptr};
   if (S.slots) {
-    uint64_t b, e;
-    seg_bounds(S.so, j, &b, &e);
-    if ((uint64_t)S.cnt[j] <= e - b) {
-      *in_place = false;
-      return S.slots + b;
-    }
+    uint64_t sb, se;
+    seg_bounds(S.so, j, &sb, &se);
+    if ((uint64_t)S.cnt[j] <= se - sb) return SegAt{S.slots + sb, nullptr};
   }
-  *in_place = true;
-  return out + off_j;
+  return SegAt{nullptr, out + b};
 }
 
 template <int N>
@@ -786,7 +789,7 @@ __device__ __forceinline__ void sort_small_ids(const uint32_t* __restrict__ src,
     if ((uint32_t)i < len) dst[i] = v[i];
 }
 
-// IDS: the segments are the fill's 4-byte ids (S.ids), else keys
+// IDS: segments may be 4-byte ids (S.ids or S.slots); else all are keys
 template <bool IDS>
 __global__ __launch_bounds__(256) void segsort_small_kernel(const uint64_t* __restrict__ off,
                                                             uint32_t m, uint64_t* __restrict__ out,
@@ -799,8 +802,9 @@ __global__ __launch_bounds__(256) void segsort_small_kernel(const uint64_t* __re
   const uint64_t len64 = off[j + 1] - b;
   if (len64 == 0) return;
   const uint32_t len = len64 > 0xffffffffull ? 0xffffffffu : (uint32_t)len64;
-  if (IDS && len <= 32) {
-    const uint32_t* ip = S.ids + b;
+  const SegAt a = IDS ? seg_at(S, j, out, b) : SegAt{nullptr, out + b};
+  if (IDS && a.ids && len <= 32) {
+    const uint32_t* ip = a.ids;
     const uint64_t jhi = (uint64_t)j << 32;
     if (len == 1) out[b] = jhi | ip[0];
     else if (len <= 4) sort_small_ids<4>(ip, jhi, out + b, len);
@@ -809,11 +813,9 @@ __global__ __launch_bounds__(256) void segsort_small_kernel(const uint64_t* __re
     else sort_small_ids<32>(ip, jhi, out + b, len);
     return;
   }
-  bool in_place;
-  const uint64_t* src = seg_src(S, j, out, b, &in_place);
-  if (len == 1) {
-    if (!in_place) out[b] = src[0];
-  } else if (len <= 4) {
+  const uint64_t* src = a.keys;  // in place
+  if (len == 1) return;
+  if (len <= 4) {
     sort_small_segment<4>(src, out + b, len);
   } else if (len <= 8) {
     sort_small_segment<8>(src, out + b, len);
@@ -913,14 +915,13 @@ __global__ __launch_bounds__(kSegWaves * kWave) void segsort_mid_kernel(
     const uint64_t b = off[j];
     const uint32_t len = uniform_u32((uint32_t)(off[j + 1] - b));
     uint64_t* dst = out + b;
-    if constexpr (IDS) {
-      sort_wave_segment(S.ids + b, dst, len, (uint64_t)j << 32, sh, lane);
+    const SegAt a = IDS ? seg_at(S, j, out, b) : SegAt{nullptr, out + b};
+    if (IDS && a.ids) {
+      sort_wave_segment(a.ids, dst, len, (uint64_t)j << 32, sh, lane);
     } else {
-      bool in_place;
-      const uint64_t* src = seg_src(S, j, out, b, &in_place);
       // every key of the segment carries the same update id in its high word
-      const uint64_t jhi = readlane_u64(src[0], 0) & 0xffffffff00000000ull;
-      sort_wave_segment(src, dst, len, jhi, sh, lane);
+      const uint64_t jhi = readlane_u64(a.keys[0], 0) & 0xffffffff00000000ull;
+      sort_wave_segment(a.keys, dst, len, jhi, sh, lane);
     }
   }
 }
@@ -962,16 +963,15 @@ __global__ __launch_bounds__(MAXLEN / kPerThread) void segsort_bucket_kernel(
     const uint64_t len64 = off[j + 1] - b;
     if (len64 > MAXLEN || len64 <= MAXLEN / 2) continue;
     const uint32_t len = (uint32_t)len64;
-    bool in_place;
-    const uint64_t* src = seg_src(S, j, out, b, &in_place);
-    const uint64_t jhi = src[0] & 0xffffffff00000000ull;
+    const SegAt a = seg_at(S, j, out, b);
+    const uint64_t jhi = a.ids ? (uint64_t)j << 32 : a.keys[0] & 0xffffffff00000000ull;
     // this thread's keys: positions tid + r * NT (all loads in flight while
     // the counters are cleared)
     uint32_t ids[kPerThread];
 #pragma unroll
     for (uint32_t r = 0; r < kPerThread; ++r) {
       const uint32_t i = tid + r * NT;
-      ids[r] = i < len ? (uint32_t)src[i] : 0u;
+      ids[r] = i < len ? (a.ids ? a.ids[i] : (uint32_t)a.keys[i]) : 0u;
     }
 #pragma unroll
     for (uint32_t q = 0; q < kPerThread; ++q) cnt[q * NT + tid] = 0;
@@ -1057,10 +1057,9 @@ __global__ __launch_bounds__(kBigThreads) void segsort_big_kernel(
     if (j & kListDone) continue;  // sorted by the bucket kernel
     const uint64_t b = off[j];
     const uint64_t len = off[j + 1] - b;
-    bool in_place;
-    const uint64_t* src = seg_src(S, j, out, b, &in_place);
+    const SegAt a = seg_at(S, j, out, b);
     // every key of the segment carries the same update id in its high word
-    const uint64_t jhi = src[0] & 0xffffffff00000000ull;
+    const uint64_t jhi = a.ids ? (uint64_t)j << 32 : a.keys[0] & 0xffffffff00000000ull;
     __syncthreads();  // read before any in-place write of this segment
     uint64_t written = 0;
     for (uint32_t w = 0; w < nwin; ++w) {
@@ -1069,7 +1068,7 @@ __global__ __launch_bounds__(kBigThreads) void segsort_big_kernel(
       for (uint32_t i = tid; i < wwords; i += kBigThreads) bits[i] = 0;
       __syncthreads();
       for (uint64_t i = tid; i < len; i += kBigThreads) {
-        const uint32_t id = (nwin > 1 && in_place) ? tmp[b + i] : (uint32_t)src[i];
+        const uint32_t id = a.ids ? a.ids[i] : (nwin > 1 ? tmp[b + i] : (uint32_t)a.keys[i]);
         if (id >= w0 && id - w0 < span) {
           const uint32_t r = id - w0;
           atomicOr(&bits[r >> 5], 1u << (r & 31));
@@ -1197,7 +1196,8 @@ struct BmMeta {
 struct BmSeg {
   uint64_t b;
   uint32_t len;
-  const uint64_t* src;
+  const uint64_t* src;    // keys (in place), when isrc is null
+  const uint32_t* isrc;   // 4-byte ids (slots or the fill's), if any
   uint32_t j;  // the update (the keys' high word when they are formed from ids)
 };
 
@@ -1266,12 +1266,13 @@ void segsort_bitmap_kernel(const uint64_t* __restrict__ off, uint32_t m,
   };
   // a segment's keys are in its slot when every hit fits there, else in place
   auto seg_of = [&](uint32_t li, const BmMeta& q) {
-    BmSeg g{0, 0, out, 0};
+    BmSeg g{0, 0, out, nullptr, 0};
     if (li >= cntl) return g;
     g.j = uniform_v(q.j);
     g.b = uniform_v64(q.b);
     g.len = uniform_v(q.elo) - (uint32_t)g.b;
     g.src = out + g.b;
+    if (S.ids) g.isrc = S.ids + g.b;
     if (SLOTS) {
       // slot room: min(base + cap, limit) - base (cap form), else next base - base
       const uint64_t sb = uniform_v64(q.sb);
@@ -1282,7 +1283,7 @@ void segsort_bitmap_kernel(const uint64_t* __restrict__ off, uint32_t m,
       } else {
         room = (uint32_t)(uniform_v(q.selo) - (uint32_t)sb);
       }
-      if ((uint64_t)uniform_v(q.cnt) <= room) g.src = S.slots + sb;
+      if ((uint64_t)uniform_v(q.cnt) <= room) g.isrc = S.slots + sb;
     }
     return g;
   };
@@ -1292,16 +1293,16 @@ void segsort_bitmap_kernel(const uint64_t* __restrict__ off, uint32_t m,
   // (len <= n <= 2^20, so len * 8 fits)
   // (from the fill's 4-byte ids when there are: contiguous words)
   auto load_ids = [&](const BmSeg& g, uint32_t first, uint32_t (&v)[kBmPre]) {
-    const uint32_t w = S.ids ? (uint32_t)sizeof(uint32_t) : (uint32_t)sizeof(uint64_t);
+    const uint32_t w = g.isrc ? (uint32_t)sizeof(uint32_t) : (uint32_t)sizeof(uint64_t);
     const __amdgpu_buffer_rsrc_t rs =
-        S.ids ? buf_rsrc(S.ids + g.b, g.len * w) : buf_rsrc(g.src, g.len * w);
+        g.isrc ? buf_rsrc(g.isrc, g.len * w) : buf_rsrc(g.src, g.len * w);
 #pragma unroll
     for (uint32_t r = 0; r < kBmPre; ++r)
       v[r] = (uint32_t)__builtin_amdgcn_raw_buffer_load_b32(
           rs, (int)(tid * w), (int)((first + r * kBmThreads) * w), 0);
   };
   auto load_hi = [&](const BmSeg& g) {  // key 0's high word (the update)
-    if (S.ids) return g.j;
+    if (g.isrc) return g.j;
     return (uint32_t)__builtin_amdgcn_raw_buffer_load_b32(
         buf_rsrc(g.src, g.len * (uint32_t)sizeof(uint64_t)), 0, 4, 0);
   };
@@ -1646,7 +1647,7 @@ struct MatchState {
   float* X = nullptr;
   uint32_t* cap = nullptr;
   uint64_t* soff = nullptr;
-  uint64_t* slots = nullptr;
+  uint32_t* slots = nullptr;  // the single pass's 4-byte ids
   uint64_t budget = 0;
   uint64_t slots_total = 0;
   uint32_t* perm_ovf = nullptr;
@@ -2093,15 +2094,16 @@ static ddm_status front_half(const ddm_tree* t, const float* ulo, const float* u
       }
     }
     st.budget = budget;
-    st.slots_sc.reserve(sizeof(uint64_t) * (budget ? budget : 1));
+    st.slots_sc.reserve(sizeof(uint32_t) * (budget ? budget : 1));
     if (!st.slots_sc.commit()) return DDM_E_NOMEM;
-    st.slots = st.slots_sc.take<uint64_t>(budget ? budget : 1);
+    st.slots = st.slots_sc.take<uint32_t>(budget ? budget : 1);
     if (!st.slots_sc.fits()) return scratch_overrun("slot arena");
     SO.base = st.soff;
     SO.cap = st.cap;
     SO.limit = budget;
     SO.cnt = st.cnt;
-    SO.out = st.slots;
+    SO.out = nullptr;
+    SO.ids = st.slots;  // the hits' subscription ids, 4 bytes each
     r = traverse_any<true>(d, P, T, ulo, uhi, m, st.all(), st.kstar, SO, s);
     if (r != DDM_OK) return r;
     counts = st.cnt;
@@ -2241,14 +2243,14 @@ ddm_status sort_segments(const uint64_t* off, uint32_t m, uint64_t* out, uint64_
                          uint32_t* lists, uint32_t* lists_count, hipStream_t s,
                          const SegSrc& S, uint64_t max_len, Scratch* tmp_sc) {
   ProfScope ps("segsort", s);
-  if (S.ids)
+  if (S.ids || S.slots)
     segsort_small_kernel<true><<<(m + 255) / 256, 256, 0, s>>>(off, m, out, S, lists, lists_count);
   else
     segsort_small_kernel<false><<<(m + 255) / 256, 256, 0, s>>>(off, m, out, S, lists,
                                                                 lists_count);
   DDM_LAUNCHED("segsort_small_kernel");
   if (max_len <= 32) return DDM_OK;  // every segment sorted in registers
-  if (S.ids)
+  if (S.ids || S.slots)
     segsort_mid_kernel<true><<<4096, kSegWaves * kWave, 0, s>>>(off, out, S, lists, lists_count);
   else
     segsort_mid_kernel<false><<<4096, kSegWaves * kWave, 0, s>>>(off, out, S, lists, lists_count);

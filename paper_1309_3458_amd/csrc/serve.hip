@@ -387,17 +387,18 @@ ddm_status process(ddm_server* S, ddm_server_req* q, hipStream_t s, std::string*
   uint64_t held = 0;  // bytes charged for the slot arena and the output
   if (learned) {
     // Once the predicted number of slots P is known, and before the match
-    // allocates its arena, the arena (8P bytes) and an estimate of the output
-    // of the same size are charged together (waiting like any other charge),
-    // so that a request that got past this point rarely waits again.
+    // allocates its arena, the arena (4P bytes: a 4-byte id per slot) and an
+    // estimate of the output (8P bytes of keys) are charged together
+    // (waiting like any other charge), so that a request that got past this
+    // point rarely waits again.
     bool refused = false;
     const ArenaGrant grant = [&](uint64_t want) -> uint64_t {
       std::unique_lock<std::mutex> lk(S->mu);
-      if (!charge(S, lk, q, 16 * std::max<uint64_t>(want, 1), yielded != nullptr)) {
+      if (!charge(S, lk, q, 12 * std::max<uint64_t>(want, 1), yielded != nullptr)) {
         refused = true;
         return kArenaRefused;
       }
-      held = 16 * std::max<uint64_t>(want, 1);
+      held = 12 * std::max<uint64_t>(want, 1);
       return want;
     };
     st = match_learned_begin_granted(t, r.upd_lo, r.upd_hi, r.m, S->pred, &K, s, &mo, &pend,
@@ -426,7 +427,7 @@ ddm_status process(ddm_server* S, ddm_server_req* q, hipStream_t s, std::string*
   q->slots = slots;
   q->overflowed = ovf;
   const uint64_t out_bytes = 8 * std::max<uint64_t>(K, 1);
-  const uint64_t arena_bytes = learned ? 8 * std::max<uint64_t>(arena, 1) : 0;
+  const uint64_t arena_bytes = learned ? 4 * std::max<uint64_t>(arena, 1) : 0;
   {
     // the charge becomes the arena actually allocated plus the exact output
     std::unique_lock<std::mutex> lk(S->mu);
