@@ -113,9 +113,15 @@ __global__ __launch_bounds__(kProbeThreads) void b_probe_kernel(const BInst* __r
   const BInst& b = I[w.x];
   const uint32_t d = b.d;
   if (d > 1)
-    for (uint32_t k = 0; k < d; ++k)
-      for (uint32_t i = threadIdx.x; i < kQuant; i += kProbeThreads)
-        sq[k][qslot(i)] = b.T.quant[k][i];
+    for (uint32_t k = 0; k < d; ++k) {
+      // a dimension's loads are issued before its LDS stores (in flight together)
+      constexpr uint32_t Q = kQuant / kProbeThreads;
+      uint32_t v[Q];
+#pragma unroll
+      for (uint32_t r = 0; r < Q; ++r) v[r] = b.T.quant[k][r * kProbeThreads + threadIdx.x];
+#pragma unroll
+      for (uint32_t r = 0; r < Q; ++r) sq[k][qslot(r * kProbeThreads + threadIdx.x)] = v[r];
+    }
   __syncthreads();
   const uint32_t j = w.y * kProbeThreads + threadIdx.x;
   const bool act = j < b.m;

@@ -139,12 +139,47 @@ struct ProbeEst {
   bool bad;
 };
 
+// the update's extents (ua, ub: dimension k of update j), loaded before the
+// quantiles are (their loads overlap)
+template <int D>
+struct UpdExt {
+  float a[D], b[D];
+};
+template <int D>
+__device__ __forceinline__ UpdExt<D> load_ext(const float* __restrict__ ulo,
+                                              const float* __restrict__ uhi, uint32_t m,
+                                              uint32_t j) {
+  UpdExt<D> e;
+#pragma unroll
+  for (int k = 0; k < D; ++k) {
+    e.a[k] = ulo[(size_t)k * m + j];
+    e.b[k] = uhi[(size_t)k * m + j];
+  }
+  return e;
+}
+
+// the kQuant quantiles of every dimension into LDS (sq[k][qslot(i)]), by
+// THREADS threads: every load is issued before the first LDS store, so that
+// they are in flight together
+template <int D, uint32_t THREADS>
+__device__ __forceinline__ void load_quant_lds(const TreeDev& T, uint32_t (*sq)[kQuantPad]) {
+  static_assert(kQuant % THREADS == 0, "whole rounds");
+  constexpr uint32_t Q = kQuant / THREADS;
+  uint32_t v[D][Q];
+#pragma unroll
+  for (int k = 0; k < D; ++k)
+#pragma unroll
+    for (uint32_t r = 0; r < Q; ++r) v[k][r] = T.quant[k][r * THREADS + threadIdx.x];
+#pragma unroll
+  for (int k = 0; k < D; ++k)
+#pragma unroll
+    for (uint32_t r = 0; r < Q; ++r) sq[k][qslot(r * THREADS + threadIdx.x)] = v[k][r];
+}
+
 template <int D>
 __device__ __forceinline__ ProbeEst<D> probe_estimate(const TreeDev& T,
                                                       const uint32_t (*sq)[kQuantPad],
-                                                      const float* __restrict__ ulo,
-                                                      const float* __restrict__ uhi, uint32_t m,
-                                                      uint32_t j) {
+                                                      const UpdExt<D>& e) {
   ProbeEst<D> P;
   P.best = 0xffffffffu;
   P.bk = 0;
@@ -155,7 +190,7 @@ __device__ __forceinline__ ProbeEst<D> probe_estimate(const TreeDev& T,
   uint32_t xh[D], xl[D], qa[D], qb[D];
 #pragma unroll
   for (int k = 0; k < D; ++k) {
-    const float a = ulo[(size_t)k * m + j], b = uhi[(size_t)k * m + j];
+    const float a = e.a[k], b = e.b[k];
     P.bad = P.bad || !valid_extent(a, b);
     P.mid[k] = 0.5f * a + 0.5f * b;
     xh[k] = f2key(b);
@@ -204,25 +239,25 @@ __device__ __forceinline__ bool cell_mode(uint32_t best, uint32_t n) {
 // the union of far-apart ranges).
 constexpr uint32_t kShapeSamples = 256;
 
-template <int D>
+template <int D, uint32_t THREADS>
 __device__ __forceinline__ void sample_cell_shape(const TreeDev& T, const float* __restrict__ ulo,
                                                   const float* __restrict__ uhi, uint32_t m,
                                                   uint32_t* __restrict__ shape) {
+  static_assert(THREADS >= kShapeSamples, "one sample per thread");
   __shared__ uint32_t sq[D][kQuantPad];
   __shared__ uint32_t hist[D][16];
-  for (uint32_t i = threadIdx.x; i < D * 16; i += blockDim.x) hist[i / 16][i % 16] = 0;
-#pragma unroll
-  for (int k = 0; k < D; ++k)
-    for (uint32_t i = threadIdx.x; i < kQuant; i += blockDim.x) sq[k][qslot(i)] = T.quant[k][i];
-  __syncthreads();
   const uint32_t S = min(m, kShapeSamples);
+  UpdExt<D> e{};
+  if (threadIdx.x < S) e = load_ext<D>(ulo, uhi, m, (uint32_t)(((uint64_t)threadIdx.x * m) / S));
+  for (uint32_t i = threadIdx.x; i < D * 16; i += THREADS) hist[i / 16][i % 16] = 0;
+  load_quant_lds<D, THREADS>(T, sq);
+  __syncthreads();
   if (threadIdx.x < kShapeSamples) {
     // (k*, shape) of this lane's sample, or none; counted per wavefront
     // (one LDS add per distinct value, as the samples mostly agree)
     uint32_t key = ~0u;
     if (threadIdx.x < S) {
-      const uint32_t j = (uint32_t)(((uint64_t)threadIdx.x * m) / S);
-      const ProbeEst<D> P = probe_estimate<D>(T, sq, ulo, uhi, m, j);
+      const ProbeEst<D> P = probe_estimate<D>(T, sq, e);
       if (!P.bad && cell_mode<D>(P.best, T.n)) key = P.bk * 16u + cell_log2<D>(P.best);
     }
     uint64_t left = ballot(key != ~0u);
@@ -247,8 +282,9 @@ __device__ __forceinline__ void sample_cell_shape(const TreeDev& T, const float*
   }
 }
 
+constexpr uint32_t kProbeThreads = 1024;
 template <int D>
-__global__ __launch_bounds__(1024) void probe_kernel(TreeDev T, const float* __restrict__ ulo,
+__global__ __launch_bounds__(kProbeThreads) void probe_kernel(TreeDev T, const float* __restrict__ ulo,
                                                      const float* __restrict__ uhi, uint32_t m,
                                                      const uint32_t* __restrict__ shape,
                                                      uint8_t* __restrict__ kstar,
@@ -258,15 +294,15 @@ __global__ __launch_bounds__(1024) void probe_kernel(TreeDev T, const float* __r
                                                      int32_t* __restrict__ flag,
                                                      uint2* __restrict__ pb) {
   __shared__ uint32_t sq[D][kQuantPad];
-#pragma unroll
-  for (int k = 0; k < D; ++k)
-    for (uint32_t i = threadIdx.x; i < kQuant; i += blockDim.x) sq[k][qslot(i)] = T.quant[k][i];
-  __syncthreads();
-  const uint32_t j = blockIdx.x * blockDim.x + threadIdx.x;
+  const uint32_t j = blockIdx.x * kProbeThreads + threadIdx.x;
   const bool act = j < m;
+  UpdExt<D> e{};
+  if (act) e = load_ext<D>(ulo, uhi, m, j);
+  load_quant_lds<D, kProbeThreads>(T, sq);
+  __syncthreads();
   bool bad = false;
   if (act) {
-    const ProbeEst<D> P = probe_estimate<D>(T, sq, ulo, uhi, m, j);
+    const ProbeEst<D> P = probe_estimate<D>(T, sq, e);
     bad = P.bad;
     uint32_t bk = P.bk;
     const uint32_t best = P.best, bqa = P.bqa, bx = P.bx;
@@ -1714,7 +1750,7 @@ __global__ __launch_bounds__(1024) void match_init_kernel(
   if (i < 2) lists_count[i] = 0;
   if (snext && i <= kStashSlices) snext[i] = i < kStashSlices ? sfirst + i * sslice : 0u;
   if constexpr (D > 1) {
-    if (blockIdx.x == gridDim.x - 1) sample_cell_shape<D>(T, ulo, uhi, m, shape);
+    if (blockIdx.x == gridDim.x - 1) sample_cell_shape<D, 1024>(T, ulo, uhi, m, shape);
   }
 }
 
@@ -1759,9 +1795,9 @@ static ddm_status launch_probe(const TreeDev& T, const float* ulo, const float* 
     DDM_LAUNCHED("bits1_kernel");
   } else {
     ProfScope ps("probe", s);
-    probe_kernel<D><<<(m + 1023) / 1024, 1024, 0, s>>>(T, ulo, uhi, m, st.shape, st.kstar,
-                                                       st.bucket, st.rank, st.bcnt, st.flag,
-                                                       reinterpret_cast<uint2*>(st.pb));
+    probe_kernel<D><<<(m + kProbeThreads - 1) / kProbeThreads, kProbeThreads, 0, s>>>(
+        T, ulo, uhi, m, st.shape, st.kstar, st.bucket, st.rank, st.bcnt, st.flag,
+        reinterpret_cast<uint2*>(st.pb));
     DDM_LAUNCHED("probe_kernel");
   }
   return DDM_OK;
