@@ -1392,16 +1392,17 @@ void segsort_bitmap_kernel(const uint64_t* __restrict__ off, uint32_t m,
     const uint32_t ex0 = wave_scan_dpp(a0 + a1) - a0 - a1;
     // place of id among the segment's ids (its block's start from the lane
     // holding that block's prefix)
-    auto low_bits = [](uint32_t w, int t) {
-      const uint32_t tt = (uint32_t)min(max(t, 0), 32);
-      return tt >= 32u ? w : __builtin_amdgcn_ubfe(w, 0u, tt);
-    };
     auto rank = [&](uint32_t id) {
       const uint32_t e = id >> 7, blk = e >> 6;
-      const int b = (int)(id & 127u);
       const uint4 q = bm4[e];
-      const uint32_t below = __popc(low_bits(q.x, b)) + __popc(low_bits(q.y, b - 32)) +
-                             __popc(low_bits(q.z, b - 64)) + __popc(low_bits(q.w, b - 96));
+      // marks below bit b = id % 128 of the entry: in its 64-bit half below
+      // b % 64, and the whole lower half when b >= 64
+      const uint64_t lo = (uint64_t)q.x | ((uint64_t)q.y << 32);
+      const uint64_t hi = (uint64_t)q.z | ((uint64_t)q.w << 32);
+      const uint64_t mk = (1ull << (id & 63u)) - 1ull;
+      const bool up = (id & 64u) != 0;
+      const uint32_t below = (uint32_t)__popcll(lo & (up ? ~0ull : mk)) +
+                             (uint32_t)__popcll(hi & (up ? mk : 0ull));
       const uint32_t pl = blk >> 1;
       const uint32_t exl = (uint32_t)__shfl((int)ex0, (int)pl, kWave);
       const uint32_t a0l = (uint32_t)__shfl((int)a0, (int)pl, kWave);
