@@ -1152,15 +1152,14 @@ __global__ __launch_bounds__(kBigThreads) void segsort_big_kernel(
 // it in its entry.  Entry r*kBmThreads + t is counted by thread t
 // (conflict-free 16-byte LDS reads); the entries' exclusive counts within
 // their wave's block are kept as 16-bit values, the blocks' starts come
-// from a scan of the wave totals that every wave does itself.  Each thread
-// then ranks the ids it loaded (held in registers), and once every id is
-// ranked the bitmap's LDS becomes the staging array: each id is written at
-// its place there (as id + 1, 0 meaning empty), the rest of the array is
-// cleared, and consecutive threads write the staged keys out (coalesced)
-// and clear what they read.  Ids past the first kBmPre * kBmThreads of a
-// segment are loaded again when ranked and written straight to their
-// place; a segment longer than the array is staged in array-sized chunks.
-// Wave scans use DPP row shifts and row broadcasts.
+// from a scan of the wave totals that every wave does itself.  A segment
+// of at most kBmPre * kBmThreads keys has its ids in registers: each
+// thread ranks its own, and once every id is ranked the bitmap's LDS
+// becomes the staging array: each id is written at its place there (as
+// id + 1, 0 meaning empty), the rest of the array is cleared, and
+// consecutive threads write the staged keys out (coalesced) and clear what
+// they read.  A longer segment is read back from the bitmap in order,
+// chunk by chunk.  Wave scans use DPP row shifts and row broadcasts.
 //
 // Each workgroup takes every G-th listed segment, and its loads run ahead
 // (vector loads through buffer resources, so that the LDS waits of the work
