@@ -136,8 +136,8 @@ TRAFFIC_SOURCES = ("paper_1309_3458_amd/csrc/match.hip", "paper_1309_3458_amd/cs
                    "paper_1309_3458_amd/csrc/tree_dev.h", "paper_1309_3458_amd/csrc/sort_scan.hip")
 TRAFFIC = {
     ("d2_N1e6_alpha1_uniform", "plain", "traverse_tile_count_stash"): {
-        "sha": "5102703031690351", "kernel_fetch_kib": 118662.9, "kernel_write_kib": 31175.5,
-        "step_fetch_kib": 254923.9, "step_write_kib": 210890.0, "step_kernel_us": 334.1,
+        "sha": "7045801985421250", "kernel_fetch_kib": 118692.4, "kernel_write_kib": 31201.5,
+        "step_fetch_kib": 255349.1, "step_write_kib": 210557.6, "step_kernel_us": 333.8,
         "profile": "profiles/traffic_d2_N1e6_alpha1_pmc.md"},
 }
 FETCH_SCALE, WRITE_SCALE = 2.0, 1.0
