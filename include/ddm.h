@@ -649,6 +649,17 @@ const char* ddm_strerror(ddm_status s);
 /* Thread-local detail of the last error returned on this thread ("" if none).*/
 const char* ddm_last_error_detail(void);
 
+/* Test hook, for fault injection from the host: caps the device bytes the
+ * library's allocator may have handed out at once (blocks in use; freed
+ * blocks it keeps cached are not counted), process-wide; 0 lifts the cap.
+ * An allocation beyond the cap fails as a failed device allocation does:
+ * the call returns DDM_E_NOMEM and frees what it had taken (a server
+ * request fails alone with that status).  Returns the bytes in use when
+ * called, so that a test can check that a failed call left none behind.
+ * Not counted: the predictor's weights and ddm_match_noalloc's static
+ * array.                                                                     */
+uint64_t ddm_debug_alloc_cap(uint64_t bytes);
+
 /* Kernel timing with HIP events recorded on the launching stream.
  * ddm_prof_enable(1) starts recording every kernel launch of this thread;
  * ddm_prof_read() waits for the recorded events and writes a JSON object

@@ -138,6 +138,7 @@ def lib():
     _sig(L, "ddm_tree_free", None, vp)
     _sig(L, "ddm_strerror", ctypes.c_char_p, i32)
     _sig(L, "ddm_last_error_detail", ctypes.c_char_p)
+    _sig(L, "ddm_debug_alloc_cap", u64, u64)
     _sig(L, "ddm_prof_enable", None, i32)
     _sig(L, "ddm_prof_read", u64, ctypes.c_char_p, u64)
     _sig(L, "ddm_prof_focus", None, ctypes.c_char_p)

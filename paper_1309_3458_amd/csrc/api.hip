@@ -89,6 +89,10 @@ static size_t round_bytes(size_t b) {
 // an allocation that fails gives the cache back and retries
 constexpr size_t kCacheLimit = size_t(64) << 30;
 static size_t g_cached = 0;  // bytes in g_free
+// bytes handed out by dev_alloc and not yet freed, and the test hook's cap
+// on them (0: none), beyond which dev_alloc fails as the driver's would
+static size_t g_live_bytes = 0;
+static size_t g_alloc_cap = 0;
 
 // Frees cached blocks, largest first, whose last use has completed, until
 // the cache is within its limit.  Called with g_mem_mu held; returns the
@@ -120,6 +124,7 @@ char* dev_alloc(size_t bytes, hipStream_t s) {
   }
   {
     std::lock_guard<std::mutex> lk(g_mem_mu);
+    if (g_alloc_cap && g_live_bytes + bytes > g_alloc_cap) return nullptr;
     const size_t cap = bytes + bytes / 4 + (1u << 20);
     for (auto it = g_free->lower_bound(bytes); it != g_free->end() && it->first <= cap; ++it) {
       CachedBlock& b = it->second;
@@ -137,6 +142,7 @@ char* dev_alloc(size_t bytes, hipStream_t s) {
       g_cached -= sz;
       g_free->erase(it);
       (*g_live)[p] = {sz, dev};
+      g_live_bytes += sz;
       return p;
     }
   }
@@ -172,6 +178,7 @@ char* dev_alloc(size_t bytes, hipStream_t s) {
   }
   std::lock_guard<std::mutex> lk(g_mem_mu);
   (*g_live)[(char*)p] = {bytes, dev};
+  g_live_bytes += bytes;
   return (char*)p;
 }
 
@@ -186,6 +193,7 @@ void dev_free(char* p, hipStream_t s) {
     sz = it->second.first;
     dev = it->second.second;
     g_live->erase(it);
+    g_live_bytes -= sz;
   }
   hipEvent_t ev = pooled_event();
   if (ev) (void)hipEventRecord(ev, s);
@@ -327,6 +335,12 @@ extern "C" const char* ddm_strerror(ddm_status s) {
 }
 
 extern "C" const char* ddm_last_error_detail(void) { return g_detail.c_str(); }
+
+extern "C" uint64_t ddm_debug_alloc_cap(uint64_t bytes) {
+  std::lock_guard<std::mutex> lk(g_mem_mu);
+  g_alloc_cap = (size_t)bytes;
+  return g_live_bytes;
+}
 
 extern "C" void ddm_prof_enable(int on) {
   if (!on) prof_collect();
