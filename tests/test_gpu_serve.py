@@ -10,7 +10,9 @@
 * an invalid request fails alone, the others complete;
 * results kept in device memory;
 * an open-loop Poisson run: every request completes, latencies are finite
-  and sampled results equal the results alone.
+  and sampled results equal the results alone;
+* under a binding device budget, the device bytes the library has handed
+  out (sampled while the burst runs) stay within the budget.
 """
 import numpy as np
 import pytest
@@ -236,3 +238,51 @@ def test_learned_burst_stays_within_the_hbm_budget():
     for inst, r in zip(insts[:4], res[:4]):
         assert np.array_equal(r["pairs"], _alone(inst))
     pred.free()
+
+
+@pytest.mark.parametrize("learned", [False, True])
+def test_device_bytes_in_use_stay_within_the_budget(learned):
+    """The admission's accounting against the device memory the library has
+    really handed out: a thread samples the bytes in use (the allocator's
+    count of blocks handed out and not yet freed; ddm_debug_alloc_cap(0)
+    returns it without setting a cap) every half millisecond while a burst
+    is served under a binding budget; the largest sample stays within the
+    budget (the inputs are the caller's tensors and are not counted by
+    either), and every result equals the request matched alone."""
+    import threading
+    import time
+    import paper_1309_3458_amd as P
+    from paper_1309_3458_amd import _native as N
+    from paper_1309_3458_amd import learn
+    torch = _torch()
+    L = N.lib()
+    pred = learn.train_predictor(n_inst=8, per_instance=4000, epochs=6)[0] if learned else None
+    insts = [W.uniform_instance([97, k], 100_000, 100_000, 2,
+                                W.side_for_alpha(30.0, 200_000, 2)) for k in range(10)]
+    budget = 768 << 20
+    srv = P.Server(predictor=pred, workers=8, hbm_budget=budget, host_pool=2 << 30)
+    torch.cuda.synchronize()
+    base = int(L.ddm_debug_alloc_cap(0))
+    samples, stop = [], threading.Event()
+
+    def poll():
+        while not stop.is_set():
+            samples.append(int(L.ddm_debug_alloc_cap(0)) - base)
+            time.sleep(0.0005)
+
+    th = threading.Thread(target=poll)
+    th.start()
+    try:
+        res = _serve_all(srv, insts)
+    finally:
+        stop.set()
+        th.join()
+    st = srv.stats()
+    srv.close()
+    assert all(r["status"] == 0 for r in res)
+    assert len(samples) > 10 and max(samples) > 0
+    assert max(samples) <= budget, (max(samples), budget, st["hbm_peak"])
+    for inst, r in zip(insts[:3], res[:3]):
+        assert np.array_equal(r["pairs"], _alone(inst))
+    if pred is not None:
+        pred.free()
