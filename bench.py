@@ -94,7 +94,7 @@ def parse():
     ap.add_argument("--path", default="both", choices=["plain", "learned", "both"],
                     help="plain two-pass, learned single-pass, or both (value = faster)")
     ap.add_argument("--predictor", default="",
-                    help="saved predictor (.npz); default: train one before timing")
+                    help="saved predictor file (Predictor.save); default: train one before timing")
     ap.add_argument("--tuning", default="",
                     help="batch256: tuning table (JSON); default: the packaged table")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -136,7 +136,7 @@ TRAFFIC_SOURCES = ("paper_1309_3458_amd/csrc/match.hip", "paper_1309_3458_amd/cs
                    "paper_1309_3458_amd/csrc/tree_dev.h", "paper_1309_3458_amd/csrc/sort_scan.hip")
 TRAFFIC = {
     ("d2_N1e6_alpha1_uniform", "plain", "traverse_tile_count_stash"): {
-        "sha": "7045801985421250", "kernel_fetch_kib": 118692.4, "kernel_write_kib": 31201.5,
+        "sha": "c0de77896e8d9f63", "kernel_fetch_kib": 118692.4, "kernel_write_kib": 31201.5,
         "step_fetch_kib": 255349.1, "step_write_kib": 210557.6, "step_kernel_us": 333.8,
         "profile": "profiles/traffic_d2_N1e6_alpha1_pmc.md"},
 }

@@ -202,6 +202,17 @@ ddm_status ddm_predictor_get_params(const ddm_predictor* p, float* host, uint32_
 ddm_status ddm_predictor_set_params(ddm_predictor* p, const float* host, uint32_t count,
                                     float delta);
 
+/* The predictor's parameters and delta (not its Adam state) to / from a
+ * file (host path): four little-endian 32-bit words -- "DDMP", format
+ * version 1, DDM_PREDICTOR_PARAMS, delta's float bits -- then the
+ * parameters as little-endian floats.  ddm_predictor_load creates a new
+ * predictor on the current device (Adam state zero; free it with
+ * ddm_predictor_free).  DDM_E_INVALID_ARG for a NULL argument or a file
+ * that cannot be opened, read or written; DDM_E_INVALID_INPUT for a file
+ * of another format, version or size, or with non-finite values.           */
+ddm_status ddm_predictor_save(const ddm_predictor* p, const char* path);
+ddm_status ddm_predictor_load(const char* path, ddm_predictor** out);
+
 /* Features of m updates against tree t (d <= 3, n > 0): X is a device
  * pointer to m*DDM_FEATURES floats, row j = update j.                        */
 ddm_status ddm_features(const ddm_tree* t, const float* upd_lo, const float* upd_hi, uint32_t m,
@@ -446,9 +457,10 @@ void ddm_tree_free(ddm_tree* t);
  * Many independent instances -- each its own subscription set, update set
  * and dimension -- matched by one fixed sequence of kernels: one tree build
  * over all subscription sets, one probe and ordering pass over all updates,
- * a persistent count traversal and a persistent fill traversal whose
- * wavefronts take (instance, probe dimension, tile of updates) items from an
- * atomic ticket, one scan and one segment sort.  The sequence allocates
+ * a count traversal and a fill traversal over (instance, probe dimension,
+ * tile of updates) work items -- one wavefront per item, or with
+ * opts.waves_per_cu a persistent grid whose wavefronts take items from an
+ * atomic ticket -- one scan and one segment sort.  The sequence allocates
  * nothing and never waits on the host, so it is captured once into a HIP
  * graph and replayed by every ddm_batch_run (opts.use_graph).
  *

@@ -10,6 +10,7 @@ from __future__ import annotations
 
 import ctypes
 import json
+import os
 
 from ._native import (DDMError, DDM_E_CAPACITY, DDM_E_INVALID_INPUT, FEATURES, PREDICTOR_PARAMS,
                       TRAVERSE, check, header_functions, lib, opts as _opts)
@@ -352,16 +353,16 @@ class Predictor:
         return losses
 
     def save(self, path: str):
-        import numpy as np
-        a, d = self.params()
-        np.savez(path, params=a, delta=np.float32(d))
+        """Parameters and delta to a predictor file (ddm_predictor_save)."""
+        check(lib().ddm_predictor_save(self.handle, os.fsencode(path)), "ddm_predictor_save")
 
     @classmethod
     def load(cls, path: str):
-        import numpy as np
-        z = np.load(path, allow_pickle=False)
-        p = cls(0)
-        p.set_params(z["params"], float(z["delta"]))
+        """A new predictor from a file written by save() (ddm_predictor_load)."""
+        h = ctypes.c_void_p()
+        check(lib().ddm_predictor_load(os.fsencode(path), ctypes.byref(h)), "ddm_predictor_load")
+        p = cls.__new__(cls)
+        p._h = h
         return p
 
     def free(self):

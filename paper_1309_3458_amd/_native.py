@@ -147,6 +147,8 @@ def lib():
     _sig(L, "ddm_predictor_free", None, vp)
     _sig(L, "ddm_predictor_get_params", i32, vp, vp, u32, f32p)
     _sig(L, "ddm_predictor_set_params", i32, vp, vp, u32, ctypes.c_float)
+    _sig(L, "ddm_predictor_save", i32, vp, ctypes.c_char_p)
+    _sig(L, "ddm_predictor_load", i32, ctypes.c_char_p, P(vp))
     _sig(L, "ddm_features", i32, vp, vp, vp, u32, vp, vp)
     _sig(L, "ddm_predictor_forward", i32, vp, vp, u32, vp, vp)
     _sig(L, "ddm_predictor_grad", i32, vp, vp, vp, u32, vp, vp, vp)

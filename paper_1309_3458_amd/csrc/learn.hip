@@ -14,6 +14,8 @@
 
 #include <algorithm>
 #include <cmath>
+#include <cstdio>
+#include <cstring>
 #include <new>
 #include <vector>
 
@@ -675,6 +677,74 @@ extern "C" ddm_status ddm_predictor_set_params(ddm_predictor* p, const float* ho
     DDM_HIP(hipMemcpy(p->params, host, sizeof(float) * kParams, hipMemcpyHostToDevice));
   }
   p->delta = delta;
+  return DDM_OK;
+}
+
+// Predictor file: "DDMP", format version, parameter count, delta (as its
+// float bits), each a little-endian 32-bit word, then the parameters.
+static const char kPredMagic[4] = {'D', 'D', 'M', 'P'};
+constexpr uint32_t kPredVersion = 1;
+
+extern "C" ddm_status ddm_predictor_save(const ddm_predictor* p, const char* path) {
+  set_detail("");
+  if (!p || !path) return DDM_E_INVALID_ARG;
+  std::vector<float> w(kParams);
+  float delta = 0.f;
+  ddm_status st = ddm_predictor_get_params(p, w.data(), (uint32_t)kParams, &delta);
+  if (st != DDM_OK) return st;
+  uint32_t hdr[4];
+  std::memcpy(&hdr[0], kPredMagic, 4);
+  hdr[1] = kPredVersion;
+  hdr[2] = (uint32_t)kParams;
+  std::memcpy(&hdr[3], &delta, 4);
+  FILE* f = std::fopen(path, "wb");
+  if (!f) {
+    set_detail(std::string("ddm_predictor_save: cannot open ") + path);
+    return DDM_E_INVALID_ARG;
+  }
+  const bool ok = std::fwrite(hdr, sizeof(hdr), 1, f) == 1 &&
+                  std::fwrite(w.data(), sizeof(float), w.size(), f) == w.size();
+  if (std::fclose(f) != 0 || !ok) {
+    set_detail(std::string("ddm_predictor_save: write failed: ") + path);
+    return DDM_E_INVALID_ARG;
+  }
+  return DDM_OK;
+}
+
+extern "C" ddm_status ddm_predictor_load(const char* path, ddm_predictor** out) {
+  set_detail("");
+  if (!path || !out) return DDM_E_INVALID_ARG;
+  *out = nullptr;
+  FILE* f = std::fopen(path, "rb");
+  if (!f) {
+    set_detail(std::string("ddm_predictor_load: cannot open ") + path);
+    return DDM_E_INVALID_ARG;
+  }
+  uint32_t hdr[4];
+  std::vector<float> w(kParams);
+  bool ok = std::fread(hdr, sizeof(hdr), 1, f) == 1 && std::memcmp(&hdr[0], kPredMagic, 4) == 0 &&
+            hdr[1] == kPredVersion && hdr[2] == (uint32_t)kParams &&
+            std::fread(w.data(), sizeof(float), w.size(), f) == w.size();
+  char extra;
+  ok = ok && std::fread(&extra, 1, 1, f) == 0;  // nothing after the parameters
+  std::fclose(f);
+  if (!ok) {
+    set_detail(std::string("ddm_predictor_load: not a predictor file of this version: ") + path);
+    return DDM_E_INVALID_INPUT;
+  }
+  float delta;
+  std::memcpy(&delta, &hdr[3], 4);
+  ddm_predictor* p = nullptr;
+  ddm_status st = ddm_predictor_create(0, &p);
+  if (st != DDM_OK) return st;
+  st = ddm_predictor_set_params(p, w.data(), (uint32_t)kParams, delta);
+  if (st != DDM_OK) {
+    const std::string why = ddm_last_error_detail();
+    ddm_predictor_free(p);
+    set_detail("ddm_predictor_load: " + why);
+    return DDM_E_INVALID_INPUT;
+  }
+  *out = p;
   return DDM_OK;
 }
 

@@ -3,23 +3,29 @@
 // and the d-dimensional combine of Sec. III-A.
 //
 // Sequence for m updates against a tree set of d dimensions:
-//   1. bits_kernel: per update and dimension k, the exact number of
-//      subscriptions meeting it in dimension k, from two binary searches on
-//      sorted lower and upper bounds (the BITS identity recalled in Sec. II,
-//      closed form).  The smallest count picks the probe dimension k*; for
-//      d = 1 the count is already the final count.
-//   2. updates sorted by (k*, lower bound in k*) so that neighbouring lanes
-//      walk neighbouring parts of the same tree.
-//   3. count traversal (d > 1): Algorithm 4 on tree k*, every candidate also
-//      tested in the other dimensions (membership in every per-dimension
-//      overlap set is decided by that dimension's own predicate, so the
-//      intersection of Sec. III-A is formed without listing the per-dimension
-//      sets).
+//   1. probe: d = 1 (bits1_kernel): the exact count of every update from
+//      two binary searches on sorted lower and upper bounds (the BITS
+//      identity recalled in Sec. II), already the final count.  d > 1
+//      (probe_kernel): the probe dimension k* with the fewest candidate
+//      positions, estimated from quantiles of the sorted lower bounds held
+//      in LDS, bounds of those positions, and the update's bucket (k* and
+//      its place in tree k*, or a cell of tree positions and the other
+//      dimensions) with its rank inside the bucket.
+//   2. updates placed in bucket order (a counting sort), cut into tiles of
+//      up to 64 updates of one bucket.
+//   3. count traversal (d > 1): one wavefront per tile scans the tile's
+//      candidate positions of tree k* and tests every candidate in all d
+//      dimensions (membership in every per-dimension overlap set is decided
+//      by that dimension's own predicate, so the intersection of Sec. III-A
+//      is formed without listing the per-dimension sets); the hits are kept
+//      when they fit.  The lane form walks Algorithm 4 per update instead.
 //   4. exclusive scan of the counts -> segment offsets, total K.
-//   5. fill traversal: the same walk writes (update << 32) | subscription
-//      into the update's own segment (each query owns its column of M, so
-//      lanes never conflict).
+//   5. the kept hits placed, or a fill traversal (the same scan) writing
+//      each hit into the update's own segment (each query owns its column
+//      of M, so lanes never conflict).
 //   6. per-segment sort by subscription id.
+// The learned single pass replaces 3-5 by one traversal that writes into
+// slots sized by a predictor while counting exactly.
 #include "ddm_internal.h"
 #include "traverse.h"
 

@@ -11,7 +11,7 @@ Training draws are uniform placements like the paper's workloads
 (Sec. V: N extents, overlap degree alpha) extended to d in {1, 2, 3}, with
 seeds >= 100 so that they never coincide with an evaluation draw.
 
-    python -m paper_1309_3458_amd.learn --out predictor.npz
+    python -m paper_1309_3458_amd.learn --out predictor.ddmp
 """
 from __future__ import annotations
 
@@ -101,7 +101,7 @@ def train_predictor(n_inst: int = 48, per_instance: int = 20000, epochs: int = 3
 
 def main():
     ap = argparse.ArgumentParser()
-    ap.add_argument("--out", default="predictor.npz")
+    ap.add_argument("--out", default="predictor.ddmp")
     ap.add_argument("--instances", type=int, default=48)
     ap.add_argument("--epochs", type=int, default=30)
     args = ap.parse_args()

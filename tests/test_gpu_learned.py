@@ -7,7 +7,9 @@
   trained, untrained, forced-zero-capacity and tiny-arena predictors, with
   both traversal kernels;
 * training lowers the loss, and the trained network overflows far fewer
-  updates than an untrained one on a shifted (hotspot) distribution.
+  updates than an untrained one on a shifted (hotspot) distribution;
+* the predictor file round trip (ddm_predictor_save / ddm_predictor_load)
+  and the refusal of damaged files.
 """
 import numpy as np
 import pytest
@@ -237,3 +239,33 @@ def test_learned_gain_over_plain_on_hotspots():
     print(f"hotspot step: plain {ms['plain']:.2f} ms, learned {ms['learned']:.2f} ms")
     assert ms["learned"] < ms["plain"], ms
     pred.free()
+
+
+def test_predictor_file_round_trip(trained, tmp_path):
+    """ddm_predictor_save / ddm_predictor_load: the loaded predictor has the
+    same parameters and delta bit for bit and gives the same forward pass;
+    a truncated file, another format and a missing file are refused."""
+    import paper_1309_3458_amd as P
+    from paper_1309_3458_amd import _native as N
+    torch = _torch()
+    p, _ = trained
+    path = str(tmp_path / "pred.ddmp")
+    p.save(path)
+    q = P.Predictor.load(path)
+    a, da = p.params()
+    b, db = q.params()
+    assert np.array_equal(a.view(np.uint32), b.view(np.uint32)) and np.float32(da) == np.float32(db)
+    X = torch.randn(300, 18, device="cuda")
+    assert torch.equal(p.forward(X), q.forward(X))
+    q.free()
+    raw = open(path, "rb").read()
+    assert raw[:4] == b"DDMP" and len(raw) == 16 + 4 * 5441
+    bad = tmp_path / "bad.ddmp"
+    for blob in (raw[:-4], raw + b"\0", b"XXXX" + raw[4:]):
+        bad.write_bytes(blob)
+        with pytest.raises(P.DDMError) as e:
+            P.Predictor.load(str(bad))
+        assert e.value.code == N.DDM_E_INVALID_INPUT
+    with pytest.raises(P.DDMError) as e:
+        P.Predictor.load(str(tmp_path / "missing.ddmp"))
+    assert e.value.code == N.DDM_E_INVALID_ARG
