@@ -874,10 +874,19 @@ __global__ __launch_bounds__(256) void segsort_small_kernel(const uint64_t* __re
 
 // One wavefront per listed segment (33..2048 keys).  The segment's ids are
 // staged through LDS (coalesced global reads and writes) into registers in
-// blocked order, V = P2/64 per lane (P2 = the segment length rounded up to a
-// power of two, at least 64), and sorted by a bitonic network: exchanges of
-// partners less than V apart stay inside a lane's registers, the others
-// swap whole registers with the lane whose index differs in one bit.
+// blocked order (element i = lane * V + r), V = P2/64 per lane (P2 = the
+// segment length rounded up to a power of two, at least 64), and sorted by
+// a bitonic network.  From V = 4 on it is written with every comparator
+// ascending: to merge sorted blocks of k/2 into blocks of k, element i is
+// first compared with i ^ (k - 1) (the mirror image in its block of k),
+// then with i ^ j for j = k/4 .. 1; a comparator is a min and a max.
+// Partners less than V apart stay inside a lane's registers, the others
+// are in the lane whose index differs in the partner's bits (the mirror
+// pairs register r with register V - 1 - r there).  With V <= 2 nearly
+// every stage crosses lanes, and the classic form (comparators of both
+// directions, partner i ^ j for j = k/2 .. 1) is faster there: measured on
+// the 256-instance batch, segment sort 0.83 ms classic, 0.88 all-ascending,
+// 0.79 with the split; 16-hotspot workload 9.7 -> 9.1 ms.
 template <int V, typename SRC>
 __device__ __forceinline__ void wave_bitonic_segment(const SRC* __restrict__ src,
                                                      uint64_t* __restrict__ dst, uint32_t len,
@@ -889,31 +898,85 @@ __device__ __forceinline__ void wave_bitonic_segment(const SRC* __restrict__ src
   uint32_t v[V];
 #pragma unroll
   for (int r = 0; r < V; ++r) v[r] = sh[lane * V + r];
+  if constexpr (V <= 2) {
+    // classic form: the lower index keeps the smaller key when the block
+    // of k it lies in sorts up
 #pragma unroll
-  for (uint32_t k = 2; k <= P2; k <<= 1) {
+    for (uint32_t k = 2; k <= P2; k <<= 1) {
 #pragma unroll
-    for (uint32_t j = k >> 1; j > 0; j >>= 1) {
-      if (j >= (uint32_t)V) {
-        // partner: lane ^ (j / V), same register
-        const uint32_t lx = j / V;
-        const bool lower = (lane & lx) == 0;
+      for (uint32_t j = k >> 1; j > 0; j >>= 1) {
+        if (j >= (uint32_t)V) {
+          // partner: lane ^ (j / V), same register
+          const uint32_t lx = j / V;
+          const bool lower = (lane & lx) == 0;
+#pragma unroll
+          for (int r = 0; r < V; ++r) {
+            const uint32_t o = (uint32_t)__shfl_xor((int)v[r], (int)lx, kWave);
+            const bool up = ((lane * V + r) & k) == 0;
+            // the lower index keeps the smaller key when sorting up
+            v[r] = (lower == up) ? min(v[r], o) : max(v[r], o);
+          }
+        } else {
+#pragma unroll
+          for (int r = 0; r < V; ++r) {
+            if (((uint32_t)r & j) != 0) continue;
+            const int q = r + (int)j;
+            const bool up = ((lane * V + r) & k) == 0;
+            const uint32_t a = v[r], b = v[q];
+            const bool sw = up ? (a > b) : (a < b);
+            v[r] = sw ? b : a;
+            v[q] = sw ? a : b;
+          }
+        }
+      }
+    }
+  } else {
+#pragma unroll
+    for (uint32_t k = 2; k <= P2; k <<= 1) {
+      if (k <= (uint32_t)V) {
+        // the mirror inside the lane: r and r ^ (k - 1)
 #pragma unroll
         for (int r = 0; r < V; ++r) {
-          const uint32_t o = (uint32_t)__shfl_xor((int)v[r], (int)lx, kWave);
-          const bool up = ((lane * V + r) & k) == 0;
-          // the lower index keeps the smaller key when sorting up
-          v[r] = (lower == up) ? min(v[r], o) : max(v[r], o);
+          const int q = r ^ (int)(k - 1);
+          if (q <= r) continue;
+          const uint32_t a = v[r], b = v[q];
+          v[r] = min(a, b);
+          v[q] = max(a, b);
         }
       } else {
+        // the mirror across lanes: lane ^ (k/V - 1), register V - 1 - r; the
+        // lane in the lower half of the block keeps the smaller key
+        const int lm = (int)(k / V - 1);
+        const bool lower = (lane & (k / (2 * V))) == 0;
 #pragma unroll
-        for (int r = 0; r < V; ++r) {
-          if (((uint32_t)r & j) != 0) continue;
-          const int q = r + (int)j;
-          const bool up = ((lane * V + r) & k) == 0;
-          const uint32_t a = v[r], b = v[q];
-          const bool sw = up ? (a > b) : (a < b);
-          v[r] = sw ? b : a;
-          v[q] = sw ? a : b;
+        for (int r = 0; r < (V + 1) / 2; ++r) {
+          const int q = V - 1 - r;
+          const uint32_t t1 = (uint32_t)__shfl_xor((int)v[q], lm, kWave);
+          const uint32_t t2 = (uint32_t)__shfl_xor((int)v[r], lm, kWave);
+          v[r] = lower ? min(v[r], t1) : max(v[r], t1);
+          if (q != r) v[q] = lower ? min(v[q], t2) : max(v[q], t2);
+        }
+      }
+#pragma unroll
+      for (uint32_t j = k >> 2; j > 0; j >>= 1) {
+        if (j >= (uint32_t)V) {
+          // partner: lane ^ (j / V), same register
+          const uint32_t lx = j / V;
+          const bool lower = (lane & lx) == 0;
+#pragma unroll
+          for (int r = 0; r < V; ++r) {
+            const uint32_t o = (uint32_t)__shfl_xor((int)v[r], (int)lx, kWave);
+            v[r] = lower ? min(v[r], o) : max(v[r], o);
+          }
+        } else {
+#pragma unroll
+          for (int r = 0; r < V; ++r) {
+            if (((uint32_t)r & j) != 0) continue;
+            const int q = r + (int)j;
+            const uint32_t a = v[r], b = v[q];
+            v[r] = min(a, b);
+            v[q] = max(a, b);
+          }
         }
       }
     }
