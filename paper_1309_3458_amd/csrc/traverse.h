@@ -437,6 +437,7 @@ __device__ __forceinline__ void tile_body(const TreeDev& T, const float* __restr
     const uint32_t sid = s_cid[slot];
     for (uint32_t qi = 0; qi < nq4; qi += 4) {
       uint64_t hm[4];
+      bool hit[4];  // this lane's bit of hm (the fill stores under it)
 #pragma unroll
       for (uint32_t u = 0; u < 4; ++u) {
         float q[4 * RV];
@@ -450,12 +451,16 @@ __device__ __forceinline__ void tile_body(const TreeDev& T, const float* __restr
         }
         // one compare per lane mask, combined with scalar ANDs
         uint64_t h = cvm;
+        bool hl = lane < c;
 #pragma unroll
         for (int s = 0; s < D; ++s) {
-          h &= ballot(v[2 * s] <= q[2 * s + 1]);
-          h &= ballot(q[2 * s] <= v[2 * s + 1]);
+          const bool c1 = v[2 * s] <= q[2 * s + 1], c2 = q[2 * s] <= v[2 * s + 1];
+          h &= ballot(c1);
+          h &= ballot(c2);
+          hl = hl && c1 && c2;
         }
         hm[u] = h;
+        hit[u] = hl;
       }
       if ((hm[0] | hm[1] | hm[2] | hm[3]) != 0) {
 #pragma unroll
@@ -468,7 +473,7 @@ __device__ __forceinline__ void tile_body(const TreeDev& T, const float* __restr
             const uint64_t e = readlane_u64(myend, qq);
             const uint64_t jq = readlane_u64(jhi, qq);
             const uint64_t dst = b + mask_rank(hm[u]);
-            if (((hm[u] >> lane) & 1ull) && dst < e) {
+            if (hit[u] && dst < e) {
               if (oids) oids[dst] = sid;
               else out[dst] = jq | sid;
             }
