@@ -106,53 +106,65 @@ __global__ __launch_bounds__(kSortThreads) void rs_scatter_kernel(const SortArr*
                                                                   const uint32_t* __restrict__ tile_map,
                                                                   const uint32_t* __restrict__ hist,
                                                                   int pass) {
-  __shared__ uint32_t doff[256];
-  __shared__ uint32_t wc[kSortThreads / kWave][256];
+  // each wavefront ranks a contiguous run of kSortItems * 64 keys of the
+  // tile (key base + w * run + r * 64 + lane) against its own digit
+  // counters, round after round without a barrier; one scan over the
+  // wavefronts then places every run (stable: runs and rounds in key order)
+  constexpr uint32_t NW = kSortThreads / kWave;
+  constexpr uint32_t RUN = kSortItems * kWave;
+  __shared__ uint32_t wc[NW][256];
+  __shared__ uint32_t woff[NW][256];
   const uint32_t t = blockIdx.x;
   const uint32_t tid = threadIdx.x;
-  const uint32_t wave = tid / kWave;
+  const uint32_t wave = tid / kWave, lane = lane_id();
   const SortArr A = arrs[tile_map[t]];
   const uint32_t lt = t - A.tile0;
   const uint32_t* __restrict__ ks = A.k[pass & 1];
   uint32_t* __restrict__ kd = A.k[(pass & 1) ^ 1];
   const uint32_t* __restrict__ vs = A.v[pass & 1];
   uint32_t* __restrict__ vd = A.v[(pass & 1) ^ 1];
-  const uint32_t base = lt * kSortTile;
-  const uint32_t end = min(A.n, base + kSortTile);
+  const uint32_t base = lt * kSortTile + wave * RUN;
+  const uint32_t end = min(A.n, lt * kSortTile + kSortTile);
   const int shift = pass * 8;
-  doff[tid] = hist[(size_t)t * 256 + tid];
-  uint32_t key[kSortItems], val[kSortItems];
+#pragma unroll
+  for (uint32_t w = 0; w < NW; ++w) wc[w][tid] = 0;
+  uint32_t key[kSortItems], val[kSortItems], loc[kSortItems];
 #pragma unroll
   for (int r = 0; r < kSortItems; ++r) {
-    const uint32_t i = base + r * kSortThreads + tid;
+    const uint32_t i = base + r * kWave + lane;
     const bool valid = i < end;
     key[r] = valid ? ks[i] : 0u;
     val[r] = (valid && vs) ? vs[i] : 0u;
   }
+  __syncthreads();  // counters clear
 #pragma unroll
   for (int r = 0; r < kSortItems; ++r) {
-    if (base + r * kSortThreads >= end) break;
-    const uint32_t i = base + r * kSortThreads + tid;
-    const bool valid = i < end;
+    const bool valid = base + r * kWave + lane < end;
     const uint32_t dig = (key[r] >> shift) & 255u;
-#pragma unroll
-    for (int w = 0; w < kSortThreads / kWave; ++w) wc[w][tid] = 0;
-    __syncthreads();
     const uint64_t peers = match_digit8(dig, ballot(valid));
-    const uint32_t rank = mask_rank(peers);
-    if (valid && rank == 0) wc[wave][dig] = (uint32_t)__popcll(peers);
-    __syncthreads();
-    if (valid) {
-      uint32_t pos = doff[dig] + rank;
-      for (uint32_t w = 0; w < wave; ++w) pos += wc[w][dig];
-      kd[pos] = key[r];
-      if (vd) vd[pos] = val[r];
-    }
-    __syncthreads();
-    uint32_t add = 0;
+    const uint32_t rk = mask_rank(peers);
+    const uint32_t c = valid ? wc[wave][dig] : 0u;
+    loc[r] = c + rk;
+    if (valid && rk == 0) wc[wave][dig] = c + (uint32_t)__popcll(peers);
+  }
+  __syncthreads();
+  // thread tid owns digit tid: the tile's offset of the digit (from the
+  // scan of the tile histograms) plus the runs of the wavefronts before
+  {
+    uint32_t run = hist[(size_t)t * 256 + tid];
 #pragma unroll
-    for (int w = 0; w < kSortThreads / kWave; ++w) add += wc[w][tid];
-    doff[tid] += add;
+    for (uint32_t w = 0; w < NW; ++w) {
+      woff[w][tid] = run;
+      run += wc[w][tid];
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int r = 0; r < kSortItems; ++r) {
+    if (base + r * kWave + lane >= end) continue;
+    const uint32_t pos = woff[wave][(key[r] >> shift) & 255u] + loc[r];
+    kd[pos] = key[r];
+    if (vd) vd[pos] = val[r];
   }
 }
 
