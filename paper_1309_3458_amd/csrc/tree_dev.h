@@ -53,47 +53,68 @@ __device__ __forceinline__ void tree_low_chunk(const TreeJob& J, uint32_t c) {
   // to nearest, moved one float up, is >= the exact difference; lengths are
   // >= 0, so their float bits order like unsigned integers
   uint32_t lenb = 0;
-  for (uint32_t r = threadIdx.x; r < kChunk; r += kTreeThreads) {
-    const uint32_t p = c * kChunk + r;
-    float h = -INFINITY;
-    if (p >= 1 && p <= J.n) {
-      float* dst = rec + (size_t)p * 2 * D;
-      float l0;
-      if (GATHER && J.recin) {
-        // one contiguous record per subscription: one random access
-        const uint32_t i = ids[p];
-        const float* src = J.recin + (size_t)i * 2 * D;
-        l0 = src[2 * k];
-        h = src[2 * k + 1];
-        dst[0] = l0;
-        dst[1] = h;
-        uint32_t slot = 1;
-        for (uint32_t kk = 0; kk < D; ++kk) {
-          if (kk == k) continue;
-          dst[2 * slot] = src[2 * kk];
-          dst[2 * slot + 1] = src[2 * kk + 1];
-          ++slot;
-        }
-      } else if (GATHER) {
-        const uint32_t i = ids[p];
-        l0 = J.s_lo[(size_t)k * J.n + i];
-        dst[0] = l0;
-        h = J.s_hi[(size_t)k * J.n + i];
-        dst[1] = h;
-        uint32_t slot = 1;
-        for (uint32_t kk = 0; kk < D; ++kk) {
-          if (kk == k) continue;
-          dst[2 * slot] = J.s_lo[(size_t)kk * J.n + i];
-          dst[2 * slot + 1] = J.s_hi[(size_t)kk * J.n + i];
-          ++slot;
-        }
-      } else {
-        l0 = dst[0];
-        h = dst[1];
-      }
-      if (valid_extent(l0, h)) lenb = max(lenb, __float_as_uint(nextafterf(h - l0, INFINITY)));
+  if (GATHER) {
+    // every id of the thread's positions is loaded first, then every
+    // record (one contiguous record per subscription with recin, else the
+    // bounds of each dimension), so that there are two rounds of loads in
+    // flight instead of two per position; then the records are written in
+    // tree-k order (dimension k first, then the others ascending)
+    constexpr uint32_t IT = kChunk / kTreeThreads;
+    static_assert(kChunk % kTreeThreads == 0, "whole rounds");
+    const float* __restrict__ rin = J.recin;
+    uint32_t idx[IT];
+    bool ok[IT];
+#pragma unroll
+    for (uint32_t it = 0; it < IT; ++it) {
+      const uint32_t p = c * kChunk + threadIdx.x + it * kTreeThreads;
+      ok[it] = p >= 1 && p <= J.n;
+      idx[it] = ok[it] ? ids[p] : 0u;
     }
-    mx[r] = h;
+    float val[IT][2 * DDM_MAX_D];
+#pragma unroll
+    for (uint32_t it = 0; it < IT; ++it)
+#pragma unroll
+      for (uint32_t q = 0; q < 2 * DDM_MAX_D; ++q)
+        val[it][q] = !(ok[it] && q < 2 * D) ? 0.f
+                     : rin               ? rin[(size_t)idx[it] * 2 * D + q]
+                     : (q & 1u)          ? J.s_hi[(size_t)(q / 2) * J.n + idx[it]]
+                                         : J.s_lo[(size_t)(q / 2) * J.n + idx[it]];
+#pragma unroll
+    for (uint32_t it = 0; it < IT; ++it) {
+      const uint32_t r = threadIdx.x + it * kTreeThreads;
+      const uint32_t p = c * kChunk + r;
+      float h = -INFINITY;
+      if (ok[it]) {
+        float* dst = rec + (size_t)p * 2 * D;
+        float l0 = 0.f;
+#pragma unroll
+        for (uint32_t kk = 0; kk < DDM_MAX_D; ++kk) {
+          if (kk >= D) continue;
+          const uint32_t slot = kk == k ? 0u : (kk < k ? kk + 1u : kk);
+          dst[2 * slot] = val[it][2 * kk];
+          dst[2 * slot + 1] = val[it][2 * kk + 1];
+          if (kk == k) {
+            l0 = val[it][2 * kk];
+            h = val[it][2 * kk + 1];
+          }
+        }
+        if (valid_extent(l0, h)) lenb = max(lenb, __float_as_uint(nextafterf(h - l0, INFINITY)));
+      }
+      mx[r] = h;
+    }
+  } else {
+    // the records in place (extents moved): dimension k's bounds
+    for (uint32_t r = threadIdx.x; r < kChunk; r += kTreeThreads) {
+      const uint32_t p = c * kChunk + r;
+      float h = -INFINITY;
+      if (p >= 1 && p <= J.n) {
+        const float* dst = rec + (size_t)p * 2 * D;
+        const float l0 = dst[0];
+        h = dst[1];
+        if (valid_extent(l0, h)) lenb = max(lenb, __float_as_uint(nextafterf(h - l0, INFINITY)));
+      }
+      mx[r] = h;
+    }
   }
 #pragma unroll
   for (int o = 32; o > 0; o >>= 1) lenb = max(lenb, (uint32_t)__shfl_xor((int)lenb, o, kWave));
