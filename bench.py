@@ -136,8 +136,8 @@ TRAFFIC_SOURCES = ("paper_1309_3458_amd/csrc/match.hip", "paper_1309_3458_amd/cs
                    "paper_1309_3458_amd/csrc/tree_dev.h", "paper_1309_3458_amd/csrc/sort_scan.hip")
 TRAFFIC = {
     ("d2_N1e6_alpha1_uniform", "plain", "traverse_tile_count_stash"): {
-        "sha": "30e495649d34f85b", "kernel_fetch_kib": 118692.4, "kernel_write_kib": 31201.5,
-        "step_fetch_kib": 255349.1, "step_write_kib": 210557.6, "step_kernel_us": 333.8,
+        "sha": "0d9a86fc4d22feb1", "kernel_fetch_kib": 118650.9, "kernel_write_kib": 31364.4,
+        "step_fetch_kib": 238170.7, "step_write_kib": 189257.5, "step_kernel_us": 328.3,
         "profile": "profiles/traffic_d2_N1e6_alpha1_pmc.md"},
 }
 FETCH_SCALE, WRITE_SCALE = 2.0, 1.0
