@@ -1313,19 +1313,26 @@ struct BmSeg {
 #endif
 constexpr int kBmThreads = DDM_BM_THREADS;
 constexpr uint32_t kBmPre = 8192 / kBmThreads;  // ids per thread loaded ahead, per segment
-constexpr uint32_t kBmLong = 1024;               // staged positions per chunk, long segments
+// staging words past the entry starts (a long segment's chunk is those and
+// the entry starts' words: two barriers per chunk; at 2048 two workgroups
+// still fit a compute unit's 160 KiB of LDS up to about 522,000 ids)
+constexpr uint32_t kBmLong = 2048;
 // most uint4 entries per thread: ids below 2^19 (narrow), below 2^20
 constexpr uint32_t kBmRNarrow = (kMaxBitWords / 2) / 4 / kBmThreads;
 constexpr uint32_t kBmRWide = kMaxBitWords / 4 / kBmThreads;
 
 // LDS of the bitmap sort: the bitmap (uint4 entries), a 16-bit start per
-// entry (padded to 8 bytes), the long-segment staging array and its spare
-// slot (padded to 16 bytes)
+// entry (padded to 8 bytes), then kBmLong + 4 more words; a long segment is
+// staged over the entry starts and those words (the last one spare)
 constexpr size_t bitmap_lds_bytes(uint32_t words) {
   return (size_t)((words + 3) / 4) * sizeof(uint4) +
          (size_t)(((words + 3) / 4 + 3) / 4) * 4 * sizeof(uint16_t) +
          (size_t)(kBmLong + 4) * sizeof(uint32_t);
 }
+static_assert(bitmap_lds_bytes(kMaxBitWords) +
+                      (kBmRWide * (kBmThreads / kWave) + 1) * sizeof(uint32_t) <=
+                  160 * 1024,
+              "the widest bitmap sort fits one compute unit's LDS");
 
 // MAXR: most uint4 entries per thread (kBmRNarrow or kBmRWide); SLOTS:
 // segments may be read from the slots of the single-pass form
@@ -1339,7 +1346,6 @@ void segsort_bitmap_kernel(const uint64_t* __restrict__ off, uint32_t m,
   const uint32_t w4 = (words + 3) / 4;
   uint32_t* bits = reinterpret_cast<uint32_t*>(bm4);  // bitmap, then staging
   uint16_t* ep = reinterpret_cast<uint16_t*>(bm4 + w4);  // entry starts within blocks
-  uint32_t* lstage = reinterpret_cast<uint32_t*>(ep + 4 * ((w4 + 3) / 4));  // long segments
   const uint32_t cap = w4 * 4;  // staging capacity (ids)
   constexpr uint32_t NW = kBmThreads / kWave;
   __shared__ uint32_t part[MAXR * NW];
@@ -1454,10 +1460,20 @@ void segsort_bitmap_kernel(const uint64_t* __restrict__ off, uint32_t m,
     }
     __syncthreads();
     // every wave: exclusive prefix of the R * NW totals in (block, wave)
-    // order (= entry order), two per lane
-    const uint32_t e0 = 2 * lane, e1 = 2 * lane + 1;
-    const uint32_t a0 = e0 < R * NW ? part[e0] : 0u, a1 = e1 < R * NW ? part[e1] : 0u;
-    const uint32_t ex0 = wave_scan_dpp(a0 + a1) - a0 - a1;
+    // order (= entry order): one per lane when they fit a wavefront (then a
+    // rank takes its group's start with one shuffle), else two per lane
+    constexpr bool ONE = MAXR * NW <= kWave;
+    uint32_t a0, a1, ex0;
+    if constexpr (ONE) {
+      a0 = lane < R * NW ? part[lane] : 0u;
+      a1 = 0u;
+      ex0 = wave_scan_dpp(a0) - a0;
+    } else {
+      const uint32_t e0 = 2 * lane, e1 = 2 * lane + 1;
+      a0 = e0 < R * NW ? part[e0] : 0u;
+      a1 = e1 < R * NW ? part[e1] : 0u;
+      ex0 = wave_scan_dpp(a0 + a1) - a0 - a1;
+    }
     // place of id among the segment's ids (its block's start from the lane
     // holding that block's prefix)
     auto rank = [&](uint32_t id) {
@@ -1471,32 +1487,45 @@ void segsort_bitmap_kernel(const uint64_t* __restrict__ off, uint32_t m,
       const bool up = (id & 64u) != 0;
       const uint32_t below = (uint32_t)__popcll(lo & (up ? ~0ull : mk)) +
                              (uint32_t)__popcll(hi & (up ? mk : 0ull));
-      const uint32_t pl = blk >> 1;
-      const uint32_t exl = (uint32_t)__shfl((int)ex0, (int)pl, kWave);
-      const uint32_t a0l = (uint32_t)__shfl((int)a0, (int)pl, kWave);
-      return ((blk & 1u) ? exl + a0l : exl) + (uint32_t)ep[e] + below;
+      if constexpr (ONE) {
+        return (uint32_t)__shfl((int)ex0, (int)blk, kWave) + (uint32_t)ep[e] + below;
+      } else {
+        const uint32_t pl = blk >> 1;
+        const uint32_t exl = (uint32_t)__shfl((int)ex0, (int)pl, kWave);
+        const uint32_t a0l = (uint32_t)__shfl((int)a0, (int)pl, kWave);
+        return ((blk & 1u) ? exl + a0l : exl) + (uint32_t)ep[e] + below;
+      }
     };
     const uint64_t jhi = (uint64_t)s_hi << 32;
     uint64_t* dst = out + cg.b;
     if (cg.len > PRE) {
       // a segment longer than the register window: its ids are read back
       // from the bitmap in order (the keys in memory may already be
-      // overwritten), chunk by chunk of kBmLong positions through the small
-      // staging array.  Per entry block, a wave whose positions miss the
-      // chunk skips it; else the lanes take their set bits lowest first,
-      // the k-th in step k of a loop as long as the wave's fullest entry (a
-      // lane out of bits or of the chunk writes the spare slot)
-      for (uint32_t cbase = 0; cbase < cg.len; cbase += kBmLong) {
-        const uint32_t cend = min(cbase + kBmLong, cg.len);
+      // overwritten), chunk by chunk through a staging array over the entry
+      // starts (only the ranks of the register window read them) and the
+      // kBmLong words after them.  Per entry block, a wave whose positions
+      // miss the chunk skips it; else the lanes take their set bits lowest
+      // first, the k-th in step k of a loop as long as the wave's fullest
+      // entry (a lane out of bits or of the chunk writes the spare slot)
+      uint32_t* const lst = reinterpret_cast<uint32_t*>(ep);
+      const uint32_t lcap = 2u * ((w4 + 3) / 4) + kBmLong;  // spare slot lst[lcap]
+      for (uint32_t cbase = 0; cbase < cg.len; cbase += lcap) {
+        const uint32_t cend = min(cbase + lcap, cg.len);
 #pragma unroll 1
         for (uint32_t r = 0; r < R; ++r) {
           const uint32_t eidx = r * NW + wave;
-          const uint32_t pl = eidx >> 1;
-          const uint32_t exl = (uint32_t)__builtin_amdgcn_readlane((int)ex0, (int)pl);
-          const uint32_t a0l = (uint32_t)__builtin_amdgcn_readlane((int)a0, (int)pl);
-          const uint32_t a1l = (uint32_t)__builtin_amdgcn_readlane((int)a1, (int)pl);
-          const uint32_t wstart = (eidx & 1u) ? exl + a0l : exl;
-          const uint32_t wtot = (eidx & 1u) ? a1l : a0l;
+          uint32_t wstart, wtot;
+          if constexpr (ONE) {
+            wstart = (uint32_t)__builtin_amdgcn_readlane((int)ex0, (int)eidx);
+            wtot = (uint32_t)__builtin_amdgcn_readlane((int)a0, (int)eidx);
+          } else {
+            const uint32_t pl = eidx >> 1;
+            const uint32_t exl = (uint32_t)__builtin_amdgcn_readlane((int)ex0, (int)pl);
+            const uint32_t a0l = (uint32_t)__builtin_amdgcn_readlane((int)a0, (int)pl);
+            const uint32_t a1l = (uint32_t)__builtin_amdgcn_readlane((int)a1, (int)pl);
+            wstart = (eidx & 1u) ? exl + a0l : exl;
+            wtot = (eidx & 1u) ? a1l : a0l;
+          }
           if (wtot == 0 || wstart >= cend || wstart + wtot <= cbase) continue;
           const uint32_t x = r * kBmThreads + tid;
           const uint4 q = x < w4 ? bm4[x] : make_uint4(0u, 0u, 0u, 0u);
@@ -1514,11 +1543,11 @@ void segsort_bitmap_kernel(const uint64_t* __restrict__ off, uint32_t m,
             hi2 = in_lo ? hi2 : wc;
             const uint32_t p = p0 + k;
             const bool ok = k < c && p >= cbase && p < cend;
-            lstage[ok ? p - cbase : kBmLong] = x * 128u + bit;
+            lst[ok ? p - cbase : lcap] = x * 128u + bit;
           }
         }
         __syncthreads();
-        for (uint32_t i = tid; i < cend - cbase; i += kBmThreads) dst[cbase + i] = jhi | lstage[i];
+        for (uint32_t i = tid; i < cend - cbase; i += kBmThreads) dst[cbase + i] = jhi | lst[i];
         __syncthreads();  // staging free; at the end the bitmap is no longer read
       }
 #pragma unroll 1
