@@ -96,6 +96,43 @@ def test_long_segments():
         assert_keys_equal(gpu_match(inst, tr), want)
 
 
+def test_long_segment_chunk_boundaries():
+    """Segments of more than 8192 keys are read back from the bitmap sort's
+    marks in staged chunks; with 10^5 ids a chunk holds 2 * ceil(w4 / 4) +
+    2048 = 2440 positions (w4 = 782 uint4 entries).  Unit points in shuffled
+    id order and updates covering exactly L consecutive points give segments
+    of exactly L keys: L on both sides of the register window (8192), of
+    multiples of the chunk and of the whole set; plain (tile and lane forms)
+    and the learned single pass."""
+    import paper_1309_3458_amd as P
+    torch = _torch()
+    rng = np.random.default_rng(23)
+    n, chunk = 100000, 2440
+    pos = rng.permutation(n).astype(np.float32)
+    s_lo = pos[None, :].copy()
+    s_hi = pos[None, :].copy()
+    lens = [8191, 8192, 8193, 4 * chunk - 1, 4 * chunk, 4 * chunk + 1, 5 * chunk,
+            8 * chunk + 1, 30000, n]
+    starts = [int(rng.integers(0, n - L + 1)) for L in lens]
+    u_lo = np.asarray([starts], np.float32)
+    u_hi = np.asarray([[a + L - 1 for a, L in zip(starts, lens)]], np.float32)
+    inst = W.Instance(s_lo, s_hi, u_lo, u_hi)
+    want = oracle.itm(s_lo, s_hi, u_lo, u_hi, threads=8)
+    assert np.array_equal(oracle.counts_per_update(want, len(lens)), lens)
+    for tr in TRAVERSALS:
+        assert_keys_equal(gpu_match(inst, tr), want)
+    t = P.build(dev(s_lo), dev(s_hi))
+    pred = P.Predictor(seed=4)
+    # an arena of the predicted total, and one of 1000 slots that leaves
+    # most updates to the overflow fill
+    for budget in (0, 1000):
+        keys = P.match_learned(t, dev(u_lo), dev(u_hi), pred, slot_budget=budget)
+        torch.cuda.synchronize()
+        assert_keys_equal(keys.cpu().numpy().view(np.uint64), want)
+    t.free()
+    pred.free()
+
+
 @pytest.mark.parametrize("clustered", [False, True])
 def test_segment_sort_size_classes(clustered):
     """Segments of every size class of the segment sort: 1, 2..16 (one lane),
