@@ -213,6 +213,17 @@ ddm_status ddm_predictor_set_params(ddm_predictor* p, const float* host, uint32_
 ddm_status ddm_predictor_save(const ddm_predictor* p, const char* path);
 ddm_status ddm_predictor_load(const char* path, ddm_predictor** out);
 
+/* ddm_tree_prepare_learned -- enqueue on `stream` the tree's statistics
+ * that the features read (the 64-bin prefix histograms of the subscription
+ * bounds and the lower-corner grid above).  Optional: the first learned
+ * match or ddm_features on a tree computes them otherwise, on its own
+ * stream, and a plain match never needs them, so a build does not pay for
+ * them.  Call it right after ddm_build (same stream) to move that cost out
+ * of the first learned match; later users on other streams wait for it.
+ * Idempotent; an update of the tree (ddm_tree_update) discards them.
+ * DDM_E_INVALID_ARG: t NULL, d > 3, or n = 0 (no features are defined).     */
+ddm_status ddm_tree_prepare_learned(const ddm_tree* t, void* stream);
+
 /* Features of m updates against tree t (d <= 3, n > 0): X is a device
  * pointer to m*DDM_FEATURES floats, row j = update j.                        */
 ddm_status ddm_features(const ddm_tree* t, const float* upd_lo, const float* upd_hi, uint32_t m,

@@ -62,6 +62,12 @@ class Tree:
     def check(self):
         check(lib().ddm_tree_check(self.handle), "ddm_tree_check")
 
+    def prepare_learned(self, stream=None):
+        """Enqueue the statistics the learned path's features read now,
+        instead of in the first learned match (d <= 3, n > 0)."""
+        check(lib().ddm_tree_prepare_learned(self.handle, _stream_handle(stream)),
+              "ddm_tree_prepare_learned")
+
     def info(self):
         n, d, h = ctypes.c_uint32(), ctypes.c_uint32(), ctypes.c_uint32()
         check(lib().ddm_tree_info(self.handle, ctypes.byref(n), ctypes.byref(d),

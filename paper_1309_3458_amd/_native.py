@@ -128,6 +128,7 @@ def lib():
     _sig(L, "ddm_match_sets", i32, vp, vp, u32, vp, vp, u32, u32, i32, vp, u64, P(u64),
          P(ctypes.c_int), vp)
     _sig(L, "ddm_tree_check", i32, vp)
+    _sig(L, "ddm_tree_prepare_learned", i32, vp, vp)
     _sig(L, "ddm_dynamic_create", i32, vp, vp, u32, vp, vp, u32, u32, vp, P(vp))
     _sig(L, "ddm_dynamic_move", i32, vp, u32, vp, vp, vp, u32, vp, P(u64))
     _sig(L, "ddm_dynamic_result", i32, vp, P(vp), P(u64))

@@ -664,6 +664,20 @@ extern "C" ddm_status ddm_tree_check(const ddm_tree* t) {
   return DDM_OK;
 }
 
+extern "C" ddm_status ddm_tree_prepare_learned(const ddm_tree* t, void* stream) {
+  set_detail("");
+  if (!t) return DDM_E_INVALID_ARG;
+  if (t->d > 3) {
+    set_detail("features are defined for d <= 3");
+    return DDM_E_INVALID_ARG;
+  }
+  if (t->n == 0) {
+    set_detail("features need a non-empty subscription set");
+    return DDM_E_INVALID_ARG;
+  }
+  return tree_ensure_features(t, (hipStream_t)stream);
+}
+
 extern "C" ddm_status ddm_tree_info(const ddm_tree* t, uint32_t* n, uint32_t* d, uint32_t* height) {
   if (!t) return DDM_E_INVALID_ARG;
   if (n) *n = t->n;

@@ -269,3 +269,42 @@ def test_predictor_file_round_trip(trained, tmp_path):
     with pytest.raises(P.DDMError) as e:
         P.Predictor.load(str(tmp_path / "missing.ddmp"))
     assert e.value.code == N.DDM_E_INVALID_ARG
+
+
+def test_prepare_learned_moves_the_statistics_out_of_the_match():
+    """ddm_tree_prepare_learned: the first learned match on a fresh tree
+    computes the features' statistics; after prepare_learned it computes
+    none and returns the same bytes (equal to the oracle).  Calling it twice
+    is harmless; d = 4 and an empty set are refused."""
+    import paper_1309_3458_amd as P
+    from paper_1309_3458_amd import _native as N
+    torch = _torch()
+    inst = W.uniform_instance(41, 12000, 9000, 2, W.side_for_alpha(5.0, 21000, 2))
+    want = oracle.itm(inst.s_lo, inst.s_hi, inst.u_lo, inst.u_hi, threads=8)
+    s_lo, s_hi, u_lo, u_hi = dev(inst.s_lo), dev(inst.s_hi), dev(inst.u_lo), dev(inst.u_hi)
+    pred = P.Predictor(seed=6)
+    ran = {}
+    for prepared in (False, True):
+        t = P.build(s_lo, s_hi)
+        if prepared:
+            t.prepare_learned()
+            t.prepare_learned()
+        torch.cuda.synchronize()
+        P.prof_enable(True)
+        P.prof_read()
+        keys = P.match_learned(t, u_lo, u_hi, pred)
+        torch.cuda.synchronize()
+        ran[prepared] = P.prof_read()
+        P.prof_enable(False)
+        assert np.array_equal(keys.cpu().numpy().view(np.uint64), want)
+        t.free()
+    assert "feature_stats" in ran[False]
+    assert "feature_stats" not in ran[True]
+    pred.free()
+    for lo, hi in ((torch.zeros((4, 10), device="cuda"), torch.ones((4, 10), device="cuda")),
+                   (torch.zeros((2, 0), device="cuda"), torch.zeros((2, 0), device="cuda"))):
+        t = P.build(lo, hi)
+        with pytest.raises(P.DDMError) as e:
+            t.prepare_learned()
+        assert e.value.code == N.DDM_E_INVALID_ARG
+        t.free()
