@@ -1398,18 +1398,27 @@ void segsort_bitmap_kernel(const uint64_t* __restrict__ off, uint32_t m,
     return g;
   };
   // kBmPre ids per thread from key index `first` on (key first + tid + r *
-  // kBmThreads), through a buffer resource over the segment's len keys: one
-  // address register for all loads, and a load past the end returns 0
-  // (len <= n <= 2^20, so len * 8 fits)
-  // (from the fill's 4-byte ids when there are: contiguous words)
+  // kBmThreads), through a buffer resource over the segment's len keys (len
+  // <= n <= 2^20, so len * 8 fits).  The range check covers the lane's
+  // offset register, not the scalar offset: a round wholly inside the
+  // segment keeps its round offset scalar (one address register for all
+  // such loads); a round the end falls in or lies beyond puts the whole
+  // offset in the lane's register, so that a lane past the end loads 0 and
+  // touches no memory.  Every round issues one load whatever the length, so
+  // the wait counts before the ids are used do not depend on it (from the
+  // fill's 4-byte ids when there are: contiguous words)
   auto load_ids = [&](const BmSeg& g, uint32_t first, uint32_t (&v)[kBmPre]) {
     const uint32_t w = g.isrc ? (uint32_t)sizeof(uint32_t) : (uint32_t)sizeof(uint64_t);
     const __amdgpu_buffer_rsrc_t rs =
         g.isrc ? buf_rsrc(g.isrc, g.len * w) : buf_rsrc(g.src, g.len * w);
 #pragma unroll
-    for (uint32_t r = 0; r < kBmPre; ++r)
-      v[r] = (uint32_t)__builtin_amdgcn_raw_buffer_load_b32(
-          rs, (int)(tid * w), (int)((first + r * kBmThreads) * w), 0);
+    for (uint32_t r = 0; r < kBmPre; ++r) {
+      const uint32_t k0 = first + r * kBmThreads;
+      const bool whole = k0 + kBmThreads <= g.len;
+      const uint32_t vo = whole ? tid * w : (k0 + tid) * w;
+      const uint32_t so = whole ? k0 * w : 0u;
+      v[r] = (uint32_t)__builtin_amdgcn_raw_buffer_load_b32(rs, (int)vo, (int)so, 0);
+    }
   };
   auto load_hi = [&](const BmSeg& g) {  // key 0's high word (the update)
     if (g.isrc) return g.j;
