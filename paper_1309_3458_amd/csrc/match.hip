@@ -492,15 +492,17 @@ __global__ __launch_bounds__(256) void bucket_scatter_kernel(const uint32_t* __r
 // instead of one long one.
 // --------------------------------------------------------------------------
 // H = twice an average full tile's work / kCutDiv, but at least
-// kCutMinHits: with 16, an average tile of 64 updates of the hotspot
-// workload (3600 hits per update) is cut in about eight (a flush's
+// kCutMinHits: with 8, an average tile of 64 updates of the hotspot
+// workload (3600 hits per update) is cut in about four (a flush's
 // per-update work then spreads over more wavefronts; each piece scans its
 // candidate range again).  Measured on that workload's learned fill:
-// kCutDiv 1 11.1 ms, 4 8.7, 16 7.9, 64 10.3, 256 13.2.  Tiles of a few
-// thousand hits gain nothing from the cut (uniform sets at 200 hits per
-// update: fill 0.51 ms uncut, 1.04 ms cut in eight), hence the floor.
+// kCutDiv 1 11.1 ms, 4 8.7, 16 7.9, 64 10.3, 256 13.2; later, on the whole
+// learned step: 6 14.93 ms, 8 14.85, 11 14.91, 16 15.14, 32 15.87.  Tiles
+// of a few thousand hits gain nothing from the cut (uniform sets at 200
+// hits per update: fill 0.51 ms uncut, 1.04 ms cut in eight), hence the
+// floor.
 #ifndef DDM_CUT_DIV
-#define DDM_CUT_DIV 16
+#define DDM_CUT_DIV 8
 #endif
 constexpr uint32_t kCutDiv = DDM_CUT_DIV;
 constexpr uint64_t kCutMinHits = 32768;
