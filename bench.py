@@ -136,7 +136,7 @@ TRAFFIC_SOURCES = ("paper_1309_3458_amd/csrc/match.hip", "paper_1309_3458_amd/cs
                    "paper_1309_3458_amd/csrc/tree_dev.h", "paper_1309_3458_amd/csrc/sort_scan.hip")
 TRAFFIC = {
     ("d2_N1e6_alpha1_uniform", "plain", "traverse_tile_count_stash"): {
-        "sha": "24adcf27141bcca5", "kernel_fetch_kib": 118650.9, "kernel_write_kib": 31364.4,
+        "sha": "909628ee2e08fdfe", "kernel_fetch_kib": 118650.9, "kernel_write_kib": 31364.4,
         "step_fetch_kib": 238170.7, "step_write_kib": 189257.5, "step_kernel_us": 328.3,
         "profile": "profiles/traffic_d2_N1e6_alpha1_pmc.md"},
 }
