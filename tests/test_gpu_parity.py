@@ -101,9 +101,9 @@ def test_long_segment_chunk_boundaries():
     marks in staged chunks; with 10^5 ids a chunk holds 2 * ceil(w4 / 4) +
     2048 = 2440 positions (w4 = 782 uint4 entries).  Unit points in shuffled
     id order and updates covering exactly L consecutive points give segments
-    of exactly L keys: L on both sides of the register window (8192), of
-    multiples of the chunk and of the whole set; plain (tile and lane forms)
-    and the learned single pass."""
+    of exactly L keys: L at and around the register window's rounds of
+    1024 ids and its end (8192), at multiples of the chunk and the whole
+    set; plain (tile and lane forms) and the learned single pass."""
     import paper_1309_3458_amd as P
     torch = _torch()
     rng = np.random.default_rng(23)
@@ -111,7 +111,9 @@ def test_long_segment_chunk_boundaries():
     pos = rng.permutation(n).astype(np.float32)
     s_lo = pos[None, :].copy()
     s_hi = pos[None, :].copy()
-    lens = [8191, 8192, 8193, 4 * chunk - 1, 4 * chunk, 4 * chunk + 1, 5 * chunk,
+    # the register window's rounds of 1024 ids: whole, ending exactly, one past
+    lens = [2049, 3071, 3072, 3073, 4096, 5000, 7168,
+            8191, 8192, 8193, 4 * chunk - 1, 4 * chunk, 4 * chunk + 1, 5 * chunk,
             8 * chunk + 1, 30000, n]
     starts = [int(rng.integers(0, n - L + 1)) for L in lens]
     u_lo = np.asarray([starts], np.float32)
