@@ -129,7 +129,9 @@ def candidates(inst):
 # (FETCH x 2.000, WRITE x 1.000: the copy's FETCH_SIZE reads half its bytes).
 # They hold only for the kernel sources they were taken on: `sha` is the
 # SHA-256 (first 16 hex digits) of the files in TRAFFIC_SOURCES, and a build
-# from other sources reports the traffic as null.  `kernel` is the dominant
+# from other sources reports the traffic as null (the hash is moved to new
+# sources only when every kernel the step launches compiles to the same
+# code object, which the profile records).  `kernel` is the dominant
 # kernel's own launch; `step` sums every kernel of one build + match step.
 TRAFFIC_SOURCES = ("paper_1309_3458_amd/csrc/match.hip", "paper_1309_3458_amd/csrc/traverse.h",
                    "paper_1309_3458_amd/csrc/ddm_internal.h", "paper_1309_3458_amd/csrc/tree.hip",
